@@ -1,0 +1,78 @@
+"""Solver parameters of the oracle.
+
+Values fixed by the paper (Section 4.1): relative tolerance 1e-4, update
+period phi = 20 for the infrequent variants, the AdaGrad schedule, and the
+online learning-rate grids. Everything else is a reading of the parts the
+paper delegates to PDLP ("default values", Section 4.1; restarts "same
+approach as PDLP", Section 3.2):
+
+  step rule   eta_bar = (0.5 w |dx|^2 + 0.5 |dy|^2 / w) / |dy . A dx|
+              (+inf when the interaction is 0); the next step is
+              min((1 - (j+1)^-0.3) eta_bar, (1 + (j+1)^-0.6) eta); an attempt
+              is accepted when eta <= eta_bar. j counts all attempts so far,
+              the current one included (PDLP's counter; counting accepted
+              iterations from 0 would make the first factor 0 and freeze
+              eta at 0).
+  restarts    every 64 accepted iterations; candidate = lower weighted KKT of
+              the current and the step-weighted average iterate; restart on
+              sufficient decay (0.2), necessary decay (0.8) without progress,
+              or an artificial restart when t >= 0.36 k; primal weight
+              smoothed with 0.5 at restarts; preconditioners and AdaGrad
+              accumulators carried over (Section 3.2).
+  termination max of relative primal residual, dual residual and gap on the
+              unscaled LP, L2 norms, at most tol.
+  rescaling   10 Ruiz passes (infinity norms, square-root split) followed by
+              one Pock-Chambolle pass with beta = 1 (Section 2).
+  AdaGrad     diagonal: H += G^2, P -= lr * G / sqrt(H) where H > 0, no
+              epsilon; projection onto the nonnegative diagonal matrices
+              (Section 3.1) is a clamp at precond_floor (default 0).
+  indicators  primal: l <= x^{k+1/2} <= u (both ends inclusive), the
+              derivative of the box projection; dual: 1 on equality rows and
+              y^{k+1/2}_i >= 0 on >= rows, the derivative of the sign
+              projection.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+
+SCHEDULE_ADAGRAD_DIAG = 0
+SCHEDULE_ADAGRAD_NORM = 1
+SCHEDULE_CONSTANT = 2
+
+
+@dataclasses.dataclass
+class Params:
+    tol: float = 1e-4
+    max_iter: int = 100000
+    lr: float = 0.0  # online learning rate alpha; 0 is plain PDLP
+    phi: int = 20  # preconditioner update period
+    normalize: bool = True  # normalized online loss
+    schedule: int = SCHEDULE_ADAGRAD_DIAG
+    precond_floor: float = 0.0
+    ruiz_iters: int = 10
+    pc_beta: float = 1.0  # Pock-Chambolle exponent; negative disables the pass
+    eval_every: int = 64
+    beta_suff: float = 0.2
+    beta_nec: float = 0.8
+    beta_art: float = 0.36
+    pw_smoothing: float = 0.5
+    step_growth: float = 0.6
+    step_reduction: float = 0.3
+    max_step_retries: int = 60
+
+
+def default_params(**overrides) -> Params:
+    return dataclasses.replace(Params(), **overrides)
+
+
+def variant(name: str, lr: float) -> Params:
+    """The four variants of Section 4.3: {NoNorm, Norm} x {Freq, Infreq}."""
+    table = {
+        "NoNorm-Freq": (False, 1),
+        "Norm-Freq": (True, 1),
+        "NoNorm-Infreq": (False, 20),
+        "Norm-Infreq": (True, 20),
+    }
+    norm, phi = table[name]
+    return default_params(lr=lr, normalize=norm, phi=phi)
