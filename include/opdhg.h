@@ -1,0 +1,274 @@
+/*
+ * opdhg — restarted PDHG with online diagonal preconditioning for linear
+ * programs, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lu & Zhang, "Enhanced PDHG for Linear Programming with Online
+ * Preconditioning". Each iteration is the PDHG step with adaptive step size
+ * and primal weight (Section 3.2, eq. (6)); every phi-th iteration the
+ * diagonal preconditioners T and Sigma take one projected online-gradient
+ * step with the gradients of eq. (7), optionally normalized (Section 3.2,
+ * Algorithm 1), under an AdaGrad schedule (Section 4.1). Restarts keep the
+ * preconditioners (Section 3.2).
+ *
+ * Problem (the paper's standard form, Section 2 eq. (1), widened to mixed
+ * row senses and two-sided bounds):
+ *
+ *     minimize    c^T x + obj_offset
+ *     subject to  A_i x  = b_i      for rows with row_sense[i] == 0
+ *                 A_i x >= b_i      for rows with row_sense[i] == 1
+ *                 l <= x <= u       (l_j may be -INFINITY, u_j +INFINITY)
+ *
+ * Dual sign convention: the Lagrangian is c^T x - y^T (A x - b) (eq. (2)),
+ * so y_i >= 0 on >= rows.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returning int returns 0 on success or a negative
+ *     OPDHG_ERR_* code; opdhg_last_error() then describes the failure
+ *     (thread-local string, valid until the next call on that thread).
+ *   - The solver's outcome (optimal, limits, numerical failure) is a status
+ *     in opdhg_result, not an error.
+ *   - LP arrays are host pointers borrowed for the duration of the call;
+ *     the library copies, rescales and uploads them.
+ *   - Device memory is never allocated by the library. The caller passes a
+ *     workspace (device pointer + size) that must hold at least the bytes
+ *     opdhg_workspace_bytes() reports; it must stay valid and untouched
+ *     until the call (or session / server) that uses it is finished.
+ *   - Streams are hipStream_t values passed as void*; NULL is the default
+ *     stream. All device work of a call is ordered on the given stream.
+ *   - Output vectors are host arrays owned by the caller, always FP64 and
+ *     in the unscaled space, even when the solver computes in FP32.
+ *   - Calls with distinct workspaces may run concurrently from different
+ *     threads. A session or server handle is used by one thread at a time
+ *     (a server is internally synchronized).
+ */
+#ifndef OPDHG_H
+#define OPDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes (negative return values) ---- */
+#define OPDHG_OK 0
+#define OPDHG_ERR_INVALID_ARGUMENT (-1)
+#define OPDHG_ERR_WORKSPACE_TOO_SMALL (-2)
+#define OPDHG_ERR_OVER_BUDGET (-3)
+#define OPDHG_ERR_DEVICE (-4)
+#define OPDHG_ERR_NOT_READY (-5)
+#define OPDHG_ERR_CANCELLED (-6)
+#define OPDHG_ERR_UNKNOWN_TICKET (-7)
+
+/* ---- solver status (opdhg_result.status) ---- */
+#define OPDHG_STATUS_OPTIMAL 0          /* relative KKT error <= tol */
+#define OPDHG_STATUS_ITERATION_LIMIT 1  /* max_iter accepted iterations */
+#define OPDHG_STATUS_TIME_LIMIT 2       /* time_limit_s of wall time */
+#define OPDHG_STATUS_NUMERICAL_ERROR 3  /* non-finite reductions or too many step rejections */
+#define OPDHG_STATUS_RUNNING 4          /* sessions only: paused before finishing */
+
+/* ---- precision ---- */
+#define OPDHG_FP64 0 /* everything in FP64 */
+#define OPDHG_FP32 1 /* A, vectors and SpMV in FP32; reductions, step sizes, KKT in FP64 */
+
+/* ---- online learning-rate schedule (Section 4.1 names AdaGrad) ---- */
+#define OPDHG_SCHEDULE_ADAGRAD_DIAG 0 /* per coordinate: H += G^2, P -= lr G / sqrt(H) */
+#define OPDHG_SCHEDULE_ADAGRAD_NORM 1 /* scalar: H += |G|^2, P -= lr G / sqrt(H) */
+#define OPDHG_SCHEDULE_CONSTANT 2     /* plain OGD: P -= lr G */
+
+/* LP in CSR form; all pointers are host pointers. */
+typedef struct opdhg_lp {
+  int64_t m;                /* rows (>= 0) */
+  int64_t n;                /* columns (>= 1) */
+  int64_t nnz;              /* stored entries, < 2^31 */
+  const int64_t* row_ptr;   /* m + 1 offsets, row_ptr[0] = 0, nondecreasing, row_ptr[m] = nnz */
+  const int32_t* col_idx;   /* nnz column indices in [0, n); no (row, col) twice */
+  const double* val;        /* nnz finite values */
+  const double* b;          /* m finite right-hand sides */
+  const int8_t* row_sense;  /* m senses: 0 '=', 1 '>=' */
+  const double* c;          /* n finite costs */
+  const double* l;          /* n lower bounds, < +inf (may be -INFINITY) */
+  const double* u;          /* n upper bounds, > -inf, >= l (may be +INFINITY) */
+  double obj_offset;        /* constant added to both objectives */
+} opdhg_lp;
+
+/* Solver parameters. Fill with opdhg_default_params() and override. */
+typedef struct opdhg_params {
+  double tol;            /* relative KKT tolerance (Section 4.1: 1e-4) */
+  int64_t max_iter;      /* accepted-iteration limit */
+  double time_limit_s;   /* wall-clock limit of the iteration loop */
+  int32_t precision;     /* OPDHG_FP64 or OPDHG_FP32 */
+  int32_t schedule;      /* OPDHG_SCHEDULE_* */
+  double lr;             /* online learning rate alpha; 0 gives plain PDLP */
+  int32_t phi;           /* preconditioner update period (Section 3.2; 20 or 1) */
+  int32_t normalize;     /* 1: normalized online loss (Section 3.2) */
+  double precond_floor;  /* projection of T, Sigma onto diagonals >= floor */
+  int32_t ruiz_iters;    /* Ruiz infinity-norm passes (Section 2) */
+  double pc_beta;        /* Pock-Chambolle exponent (Section 2); < 0 skips the pass */
+  int32_t eval_every;    /* accepted iterations between KKT evaluations */
+  int32_t max_step_retries; /* rejections allowed per iteration */
+  double beta_suff;      /* restart on sufficient KKT decay */
+  double beta_nec;       /* restart on necessary decay without progress */
+  double beta_art;       /* artificial restart when t >= beta_art * k */
+  double pw_smoothing;   /* primal-weight smoothing at restarts */
+  double step_growth;    /* exponent of the step growth factor */
+  double step_reduction; /* exponent of the step reduction factor */
+  int32_t tile_nnz;      /* SpMV tile target in nonzeros; 0 picks automatically */
+  int32_t lanes;         /* lanes per row in SpMV row groups; 0 picks per tile */
+} opdhg_params;
+
+typedef struct opdhg_result {
+  int32_t status;        /* OPDHG_STATUS_* */
+  int32_t which;         /* 0: current iterate returned, 1: step-weighted average */
+  int64_t iterations;    /* accepted iterations */
+  int64_t attempts;      /* step attempts including rejected ones */
+  int64_t restarts;
+  double primal_obj;     /* c^T x + obj_offset */
+  double dual_obj;
+  double rel_primal;     /* |b - Ax|_violated / (1 + |b|) */
+  double rel_dual;       /* |reduced-cost residual| / (1 + |c|) */
+  double rel_gap;        /* |p - d| / (1 + |p| + |d|) */
+  double rel_kkt;        /* max of the three */
+  double solve_seconds;  /* wall time of the iteration loop */
+  double eta;            /* final step size */
+  double omega;          /* final primal weight */
+} opdhg_result;
+
+/* Scaled-space state of a session, for tracing and checkpoints. */
+typedef struct opdhg_state {
+  int64_t k;          /* accepted iterations */
+  int64_t t;          /* accepted iterations since the last restart */
+  int64_t attempts;
+  int64_t restarts;
+  int32_t status;
+  int32_t need_eval;  /* an evaluation is due before the next step */
+  double eta;
+  double omega;
+  double w;           /* sum of accepted step sizes in this restart period */
+} opdhg_state;
+
+typedef struct opdhg_session opdhg_session;
+typedef struct opdhg_server opdhg_server;
+
+/* Defaults: tol 1e-4, max_iter 100000, time limit 600 s, FP64, AdaGrad
+ * (diagonal), lr 0, phi 20, normalize 1, floor 0, 10 Ruiz passes,
+ * Pock-Chambolle beta 1, eval every 64, 60 step retries, restart constants
+ * 0.2 / 0.8 / 0.36, smoothing 0.5, step exponents 0.6 / 0.3, automatic
+ * tiling. */
+void opdhg_default_params(opdhg_params* p);
+
+/* Check an LP without touching the device. Returns OPDHG_ERR_INVALID_ARGUMENT
+ * (with a message) unless: n >= 1, m >= 0, nnz < 2^31; row_ptr starts at 0,
+ * never decreases and ends at nnz; columns in [0, n) without duplicates in a
+ * row; A, b, c finite; l < +inf, u > -inf, l <= u (no NaN); senses 0 or 1. */
+int opdhg_validate(const opdhg_lp* lp);
+
+/* Exact device bytes one LP needs under these parameters (a pure function of
+ * the LP's shape and the parameters). Host only. */
+int opdhg_workspace_bytes(const opdhg_lp* lp, const opdhg_params* p, size_t* bytes);
+
+/* Host-only rescaling, exposed for checking: the Ruiz passes and the
+ * Pock-Chambolle pass of Section 2 as applied before the iteration.
+ * Outputs (caller-allocated host arrays): scaled_val[nnz] in the order of
+ * lp->val, d_row[m], d_col[n] with A~ = diag(d_row) A diag(d_col). */
+int opdhg_rescale(const opdhg_lp* lp, const opdhg_params* p, double* scaled_val,
+                  double* d_row, double* d_col);
+
+/* Solve one LP (blocking). x_out[n], y_out[m] receive the returned iterate
+ * (unscaled); res receives status and statistics. */
+int opdhg_solve(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                size_t workspace_bytes, void* hip_stream, double* x_out, double* y_out,
+                opdhg_result* res);
+
+/* Bytes for a batch: sum of per-LP needs plus the batch tables. */
+int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_params* p,
+                                size_t* bytes);
+
+/* Solve count independent LPs packed into one set of launches: each kernel
+ * covers the tiles of every still-running LP, each LP keeps its own step
+ * size, restarts and termination, and finished LPs drop out without a new
+ * launch configuration. Each LP's arithmetic does not depend on the others,
+ * so its result equals its solo solve bit for bit. x_out[i] / y_out[i] are
+ * host arrays of lps[i].n / lps[i].m doubles. */
+int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p,
+                      void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                      double* const* x_out, double* const* y_out, opdhg_result* res);
+
+/* ---- sessions: step an LP under host control (tracing, checkpoints) ---- */
+
+int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                         size_t workspace_bytes, void* hip_stream, opdhg_session** out);
+/* Run until k >= k_target accepted iterations or the solve finishes
+ * (k_target < 0: until it finishes). An evaluation due at k_target is left
+ * for the next call, so a paused state is the state after k_target
+ * iterations and before the evaluation at the top of the next one. */
+int opdhg_session_run(opdhg_session* s, int64_t k_target);
+/* Scaled-space iterate and preconditioners (FP64 host arrays; any pointer
+ * may be NULL to skip that vector): x[n], y[m], T[n], Sigma[m]. */
+int opdhg_session_state(opdhg_session* s, double* x, double* y, double* T, double* Sigma,
+                        opdhg_state* st);
+/* Unscaled returned iterate and result of a finished (or paused) session. */
+int opdhg_session_result(opdhg_session* s, double* x_out, double* y_out, opdhg_result* res);
+/* Average device time of one launch of the primal kernel (CSR(A^T) SpMV
+ * fused with the primal step) over reps launches, timed with HIP events on
+ * the session's stream. The kernel only rewrites the candidate buffers, so
+ * the session state is unchanged. */
+int opdhg_session_time_primal_kernel(opdhg_session* s, int reps, double* avg_ms);
+void opdhg_session_destroy(opdhg_session* s);
+
+/* ---- serving: continuous batching under a device-memory budget ---- */
+
+typedef struct opdhg_server_cfg {
+  size_t budget_bytes;   /* admission budget over the arena (<= arena size) */
+  int32_t max_active;    /* at most this many LPs on the device at once */
+  int32_t attempts_per_replay; /* attempts per launch sequence between admissions */
+  double poll_interval_s; /* idle wait of the scheduler thread */
+} opdhg_server_cfg;
+
+typedef struct opdhg_server_stats {
+  int64_t submitted;
+  int64_t completed;
+  int64_t cancelled;
+  int64_t failed;
+  int64_t active;        /* LPs resident on the device */
+  int64_t queued;        /* waiting for memory or a slot */
+  int64_t replays;       /* launch sequences issued */
+  size_t bytes_in_use;   /* arena bytes held by resident LPs */
+  size_t peak_bytes;
+} opdhg_server_stats;
+
+/* Create a server over a caller-owned device arena. Three streams: compute,
+ * host-to-device uploads and device-to-host downloads (NULL uses one
+ * stream for all). Returns NULL on failure (see opdhg_last_error). */
+opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena,
+                                  size_t arena_bytes, void* compute_stream,
+                                  void* h2d_stream, void* d2h_stream);
+/* Queue an LP (copied at submit). Admitted FIFO as memory and slots free
+ * up; OPDHG_ERR_OVER_BUDGET if it can never fit the budget. */
+int opdhg_server_submit(opdhg_server* s, const opdhg_lp* lp, const opdhg_params* p,
+                        uint64_t* ticket);
+/* OPDHG_ERR_NOT_READY until the ticket's solve is done; then fills the
+ * outputs (unscaled x[n], y[m], result) and releases the ticket. */
+int opdhg_server_poll(opdhg_server* s, uint64_t ticket, double* x, double* y,
+                      opdhg_result* res);
+/* Block until the ticket is done (or timeout_s passes: OPDHG_ERR_NOT_READY). */
+int opdhg_server_wait(opdhg_server* s, uint64_t ticket, double timeout_s, double* x,
+                      double* y, opdhg_result* res);
+int opdhg_server_cancel(opdhg_server* s, uint64_t ticket);
+int opdhg_server_get_stats(opdhg_server* s, opdhg_server_stats* out);
+/* Latency of the ticket: submit time to result-on-host, in seconds (valid
+ * after poll returned the result). */
+int opdhg_server_latency(opdhg_server* s, uint64_t ticket, double* seconds);
+void opdhg_server_destroy(opdhg_server* s);
+
+const char* opdhg_last_error(void);
+const char* opdhg_status_name(int status);
+/* Library version and the GPU architecture it was built for. */
+const char* opdhg_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OPDHG_H */

@@ -25,12 +25,15 @@ import math
 
 import numpy as np
 
+from .exact import exact_dot
+
 
 def kkt_parts(slp, x: np.ndarray, y: np.ndarray, Ax: np.ndarray, ATy: np.ndarray) -> dict:
     """Squared residual norms (scaled and unscaled) and both objectives.
 
     x, y live in the scaled space; Ax = A~ x and ATy = A~^T y are passed in
-    so callers decide how they were computed.
+    so callers decide how they were computed. Every sum is correctly
+    rounded (module exact).
     """
     rp = slp.b - Ax
     rp = np.where(slp.ineq, np.maximum(rp, 0.0), rp)
@@ -43,18 +46,18 @@ def kkt_parts(slp, x: np.ndarray, y: np.ndarray, Ax: np.ndarray, ATy: np.ndarray
     rd = q - lam
     lam_pos = np.maximum(lam, 0.0)
     lam_neg = np.maximum(-lam, 0.0)
-    bound_term = float(np.sum(np.where(fl, slp.l, 0.0) * lam_pos)) - float(
-        np.sum(np.where(fu, slp.u, 0.0) * lam_neg))
-    pobj = float(slp.c @ x) + slp.c0
-    dobj = float(slp.b @ y) + bound_term + slp.c0
+    bound_term = exact_dot(np.where(fl, slp.l, 0.0), lam_pos) - exact_dot(
+        np.where(fu, slp.u, 0.0), lam_neg)
+    pobj = exact_dot(slp.c, x) + slp.c0
+    dobj = exact_dot(slp.b, y) + bound_term + slp.c0
     # unscaled residuals: b - A x = D_r^-1 (b~ - A~ x~), c - A^T y = D_c^-1 (...)
     rpu = rp / slp.Dr
     rdu = rd / slp.Dc
     return {
-        "rp2": float(rp @ rp),
-        "rd2": float(rd @ rd),
-        "rp2u": float(rpu @ rpu),
-        "rd2u": float(rdu @ rdu),
+        "rp2": exact_dot(rp, rp),
+        "rd2": exact_dot(rd, rd),
+        "rp2u": exact_dot(rpu, rpu),
+        "rd2u": exact_dot(rdu, rdu),
         "pobj": pobj,
         "dobj": dobj,
     }

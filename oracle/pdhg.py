@@ -22,6 +22,9 @@ One iteration (Algorithm 1 of the paper):
   5. and T, S take one projected online-gradient step with the AdaGrad
      schedule (Section 4.1).
 
+Every sparse product and every reduction is correctly rounded (module
+exact), so the oracle's FP64 results do not depend on summation order.
+
 Around it: evaluation every eval_every accepted iterations, restarts that
 keep T, S and the AdaGrad state (Section 3.2: the next period starts from
 the most recent preconditioners), termination on the relative KKT error.
@@ -36,6 +39,7 @@ from typing import Iterable, Optional, Union
 
 import numpy as np
 
+from .exact import exact_dot, exact_norm, exact_spmv
 from .kkt import kkt_parts, rel_kkt, weighted_kkt
 from .params import (Params, SCHEDULE_ADAGRAD_DIAG, SCHEDULE_ADAGRAD_NORM,
                      SCHEDULE_CONSTANT)
@@ -132,13 +136,23 @@ class SolveResult:
 # ---------------------------------------------------------------------------
 
 
+def A_mul(slp: ScaledLP, x: np.ndarray) -> np.ndarray:
+    """A~ x with correctly rounded rows."""
+    return exact_spmv(slp.A.indptr, slp.A.indices, slp.A.data, x)
+
+
+def AT_mul(slp: ScaledLP, y: np.ndarray) -> np.ndarray:
+    """A~^T y with correctly rounded rows."""
+    return exact_spmv(slp.AT.indptr, slp.AT.indices, slp.AT.data, y)
+
+
 def initial_state(slp: ScaledLP) -> State:
     """Start point (reading): x = proj_X(0), y = 0, T = 1, S = 1, zero AdaGrad
     state, w = |c~| / |b~| (1 when either is tiny), eta = 1 / max |A~_ij|."""
     x = np.minimum(np.maximum(np.zeros(slp.n), slp.l), slp.u)
     y = np.zeros(slp.m)
-    cn = float(np.linalg.norm(slp.c))
-    bn = float(np.linalg.norm(slp.b))
+    cn = exact_norm(slp.c)
+    bn = exact_norm(slp.b)
     omega = cn / bn if (cn > 1e-10 and bn > 1e-10) else 1.0
     amax = float(np.max(np.abs(slp.A.data))) if slp.A.nnz else 0.0
     eta = 1.0 / amax if amax > 0 else 1.0
@@ -146,7 +160,7 @@ def initial_state(slp: ScaledLP) -> State:
         x=x, y=y, T=np.ones(slp.n), S=np.ones(slp.m), Hp=np.zeros(slp.n), Hd=np.zeros(slp.m),
         Hp_norm=0.0, Hd_norm=0.0, eta=eta, omega=omega, k=0, t=0, attempts=0, restarts=0,
         x_anchor=x.copy(), y_anchor=y.copy(), anchor_parts=None,
-        x_sum=np.zeros(slp.n), y_sum=np.zeros(slp.m), w=0.0, Ax=slp.A @ x,
+        x_sum=np.zeros(slp.n), y_sum=np.zeros(slp.m), w=0.0, Ax=A_mul(slp, x),
         prev_cand_kkt=math.inf,
     )
 
@@ -161,7 +175,7 @@ def pdhg_attempt(slp: ScaledLP, x, y, Ax, g, T, S, eta: float, omega: float) -> 
     tau = eta / omega
     x_half = x - tau * T * g
     x_new = np.minimum(np.maximum(x_half, slp.l), slp.u)
-    Ax_new = slp.A @ x_new
+    Ax_new = A_mul(slp, x_new)
     Ax_bar = 2.0 * Ax_new - Ax
     r_tilde = slp.b - Ax_bar
     sig = eta * omega
@@ -209,16 +223,22 @@ def online_gradients(slp: ScaledLP, g, x_half, r, r_tilde, y_half, eta: float,
     return Gp, Gd
 
 
-def _ogd_side(G: Optional[np.ndarray], P: np.ndarray, H: np.ndarray, Hn: float,
+def _ogd_side(G: Optional[np.ndarray], scale: float, P: np.ndarray, H: np.ndarray, Hn: float,
               p: Params) -> tuple[np.ndarray, np.ndarray, float]:
-    """One projected OGD step on one diagonal preconditioner."""
+    """One projected OGD step on one diagonal preconditioner.
+
+    The gradient is G / scale (scale = 1 without normalization). The norm
+    schedule accumulates |G / scale|^2 as |G|^2 / scale^2.
+    """
     if G is None:
         return P, H, Hn
+    if p.schedule == SCHEDULE_ADAGRAD_NORM:
+        Hn = Hn + exact_dot(G, G) / (scale * scale)
+    G = G / scale
     if p.schedule == SCHEDULE_ADAGRAD_DIAG:
         H = H + G * G
         step = np.where(H > 0.0, G / np.sqrt(np.where(H > 0.0, H, 1.0)), 0.0)
     elif p.schedule == SCHEDULE_ADAGRAD_NORM:
-        Hn = Hn + float(G @ G)
         step = G / math.sqrt(Hn) if Hn > 0.0 else np.zeros_like(G)
     elif p.schedule == SCHEDULE_CONSTANT:
         step = G
@@ -235,11 +255,18 @@ def learner_update(Gp, Gd, g2: float, r2: float, st: State, p: Params) -> None:
     The projection onto nonnegative diagonal matrices is a clamp at
     precond_floor.
     """
+    sp_, sd_ = 1.0, 1.0
     if p.normalize:
-        Gp = Gp / g2 if g2 > 0.0 else None
-        Gd = Gd / r2 if r2 > 0.0 else None
-    st.T, st.Hp, st.Hp_norm = _ogd_side(Gp, st.T, st.Hp, st.Hp_norm, p)
-    st.S, st.Hd, st.Hd_norm = _ogd_side(Gd, st.S, st.Hd, st.Hd_norm, p)
+        if g2 > 0.0:
+            sp_ = g2
+        else:
+            Gp = None
+        if r2 > 0.0:
+            sd_ = r2
+        else:
+            Gd = None
+    st.T, st.Hp, st.Hp_norm = _ogd_side(Gp, sp_, st.T, st.Hp, st.Hp_norm, p)
+    st.S, st.Hd, st.Hd_norm = _ogd_side(Gd, sd_, st.S, st.Hd, st.Hd_norm, p)
 
 
 def restart_decision(kkt_cur: float, kkt_avg: float, kkt_anchor: float, prev_cand: float,
@@ -268,14 +295,14 @@ def _evaluate(slp: ScaledLP, st: State, p: Params):
     """Evaluation at the top of an iteration: termination, then restart.
 
     Returns (status or None, best (x, y), which, parts, rel tuple)."""
-    ATy = slp.AT @ st.y
+    ATy = AT_mul(slp, st.y)
     cur = kkt_parts(slp, st.x, st.y, st.Ax, ATy)
     avg = None
     if st.w > 0.0:
         xa = st.x_sum / st.w
         ya = st.y_sum / st.w
-        Axa = slp.A @ xa
-        avg = kkt_parts(slp, xa, ya, Axa, slp.AT @ ya)
+        Axa = A_mul(slp, xa)
+        avg = kkt_parts(slp, xa, ya, Axa, AT_mul(slp, ya))
     if st.anchor_parts is None:
         st.anchor_parts = cur
     rc = rel_kkt(slp, cur)
@@ -298,8 +325,8 @@ def _evaluate(slp: ScaledLP, st: State, p: Params):
                 xc, yc, Axc, pc = xa, ya, Axa, avg
             else:
                 xc, yc, Axc, pc = st.x, st.y, st.Ax, cur
-            dxn = float(np.linalg.norm(xc - st.x_anchor))
-            dyn = float(np.linalg.norm(yc - st.y_anchor))
+            dxn = exact_norm(xc - st.x_anchor)
+            dyn = exact_norm(yc - st.y_anchor)
             if dxn > 1e-10 and dyn > 1e-10:
                 th = p.pw_smoothing
                 st.omega = math.exp(th * math.log(dyn / dxn) + (1.0 - th) * math.log(st.omega))
@@ -319,16 +346,16 @@ def _evaluate(slp: ScaledLP, st: State, p: Params):
 
 def _iterate(slp: ScaledLP, st: State, p: Params) -> bool:
     """Algorithm 1 for one iteration; False on a numerical failure."""
-    g = slp.c - slp.AT @ st.y
+    g = slp.c - AT_mul(slp, st.y)
     retries = 0
     while True:
         a = pdhg_attempt(slp, st.x, st.y, st.Ax, g, st.T, st.S, st.eta, st.omega)
         st.attempts += 1
         dx = a["x_new"] - st.x
         dy = a["y_new"] - st.y
-        dx2 = float(dx @ dx)
-        dy2 = float(dy @ dy)
-        inter = abs(float(dy @ (a["Ax_new"] - st.Ax)))
+        dx2 = exact_dot(dx, dx)
+        dy2 = exact_dot(dy, dy)
+        inter = abs(exact_dot(dy, a["Ax_new"] - st.Ax))
         if not (math.isfinite(dx2) and math.isfinite(dy2) and math.isfinite(inter)):
             return False
         eta_bar, eta_next, accepted = step_size_rule(st.eta, st.omega, dx2, dy2, inter,
@@ -343,7 +370,7 @@ def _iterate(slp: ScaledLP, st: State, p: Params) -> bool:
         r = slp.b - st.Ax
         Gp, Gd = online_gradients(slp, g, a["x_half"], r, a["r_tilde"], a["y_half"],
                                   st.eta, st.omega)
-        learner_update(Gp, Gd, float(g @ g), float(r @ r), st, p)
+        learner_update(Gp, Gd, exact_dot(g, g), exact_dot(r, r), st, p)
     eta = st.eta
     st.x_sum = st.x_sum + eta * a["x_new"]
     st.y_sum = st.y_sum + eta * a["y_new"]
@@ -393,7 +420,7 @@ def solve_from_state(slp: ScaledLP, st: State, p: Params,
             if out is not None:
                 return _result(slp, st, out[0], out[1:], tr)
         if not _iterate(slp, st, p):
-            ATy = slp.AT @ st.y
+            ATy = AT_mul(slp, st.y)
             parts = kkt_parts(slp, st.x, st.y, st.Ax, ATy)
             return _result(slp, st, NUMERICAL_ERROR,
                            ((st.x, st.y), "current", parts, rel_kkt(slp, parts)), tr)

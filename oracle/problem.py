@@ -21,6 +21,8 @@ import dataclasses
 import numpy as np
 import scipy.sparse as sp
 
+from .exact import exact_norm, exact_row_sums
+
 
 class InvalidLP(ValueError):
     pass
@@ -104,12 +106,18 @@ class ScaledLP:
     c_norm: float  # ||c|| of the unscaled LP
 
 
-def _row_reduce(vals: np.ndarray, row_ptr: np.ndarray, m: int, op) -> np.ndarray:
+def _row_max(vals: np.ndarray, row_ptr: np.ndarray, m: int) -> np.ndarray:
     out = np.zeros(m)
     nonempty = np.diff(row_ptr) > 0
     if nonempty.any():
-        out[nonempty] = op.reduceat(vals, row_ptr[:-1][nonempty])
+        out[nonempty] = np.maximum.reduceat(vals, row_ptr[:-1][nonempty])
     return out
+
+
+def _col_sums(vals: np.ndarray, col: np.ndarray, row_ptr: np.ndarray, m: int, n: int):
+    """Correctly rounded sum of each column's entries."""
+    csc = sp.csr_matrix((vals, col, row_ptr), shape=(m, n)).tocsc()
+    return exact_row_sums(csc.indptr, csc.data)
 
 
 def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0) -> ScaledLP:
@@ -120,7 +128,7 @@ def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0) -> ScaledLP:
     Pock-Chambolle pass (exponent beta; skipped when beta < 0):
     r_i = sum_j |A~_ij|^beta, s_j = sum_i |A~_ij|^(2 - beta), applied the
     same way, so that with beta = 1 the scaled matrix has spectral norm at
-    most 1.
+    most 1. Sums are correctly rounded (module exact).
     """
     m, n = int(lp.m), int(lp.n)
     rp = np.asarray(lp.row_ptr, dtype=np.int64)
@@ -132,7 +140,7 @@ def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0) -> ScaledLP:
     Dc = np.ones(n)
     for _ in range(ruiz_iters):
         a = absv * Dr[rows] * Dc[col]
-        r = _row_reduce(a, rp, m, np.maximum)
+        r = _row_max(a, rp, m)
         s = np.zeros(n)
         np.maximum.at(s, col, a)
         r[r == 0] = 1.0
@@ -143,9 +151,8 @@ def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0) -> ScaledLP:
         a = absv * Dr[rows] * Dc[col]
         ar = a if pc_beta == 1.0 else a ** pc_beta
         ac = a if pc_beta == 1.0 else a ** (2.0 - pc_beta)
-        r = _row_reduce(ar, rp, m, np.add)
-        s = np.zeros(n)
-        np.add.at(s, col, ac)
+        r = exact_row_sums(rp, ar)
+        s = _col_sums(ac, col, rp, m, n)
         r[r == 0] = 1.0
         s[s == 0] = 1.0
         Dr = Dr / np.sqrt(r)
@@ -161,5 +168,5 @@ def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0) -> ScaledLP:
         m=m, n=n, A=A, AT=AT, b=Dr * b, c=Dc * c, l=l / Dc, u=u / Dc,
         ineq=np.asarray(lp.sense) == 1, Dr=Dr, Dc=Dc,
         c0=float(getattr(lp, "obj_offset", 0.0)),
-        b_norm=float(np.linalg.norm(b)), c_norm=float(np.linalg.norm(c)),
+        b_norm=exact_norm(b), c_norm=exact_norm(c),
     )

@@ -1,0 +1,24 @@
+"""opdhg: restarted PDHG with online preconditioning for LP on MI355X.
+
+The solver is libopdhg.so (HIP kernels for gfx950 behind the C-ABI of
+include/opdhg.h); this package is its Python binding. See capi.py.
+"""
+
+from .capi import (  # noqa: F401
+    OpdhgError,
+    Session,
+    load,
+    opdhg_batch_workspace_bytes,
+    opdhg_build_info,
+    opdhg_default_params,
+    opdhg_last_error,
+    opdhg_rescale,
+    opdhg_session_create,
+    opdhg_solve,
+    opdhg_solve_batch,
+    opdhg_status_name,
+    opdhg_validate,
+    opdhg_workspace_bytes,
+    OPDHG_FP32,
+    OPDHG_FP64,
+)

@@ -1,0 +1,1028 @@
+// Host side of the opdhg library: validation, rescaling, CSR transpose,
+// tiling, workspace layout, upload, graph capture and the replay loop for
+// single solves, sessions and packed batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "opdhg.h"
+#include "opdhg_host.h"
+#include "opdhg_internal.h"
+
+namespace opdhg {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return OPDHG_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return fail_hip(e_, #expr);  \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+
+int validate_lp(const opdhg_lp* lp) {
+  if (!lp) return fail(OPDHG_ERR_INVALID_ARGUMENT, "lp is NULL");
+  const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
+  if (n < 1) return fail(OPDHG_ERR_INVALID_ARGUMENT, "n must be at least 1");
+  if (m < 0) return fail(OPDHG_ERR_INVALID_ARGUMENT, "m must be nonnegative");
+  if (nnz < 0 || nnz >= (int64_t(1) << 31))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "nnz must be in [0, 2^31)");
+  if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "m and n must be below 2^31");
+  if (!lp->row_ptr || !lp->c || !lp->l || !lp->u)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "NULL array");
+  if (m > 0 && (!lp->b || !lp->row_sense))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "NULL array");
+  if (nnz > 0 && (!lp->col_idx || !lp->val))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "NULL array");
+  if (lp->row_ptr[0] != 0) return fail(OPDHG_ERR_INVALID_ARGUMENT, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < m; ++i)
+    if (lp->row_ptr[i + 1] < lp->row_ptr[i])
+      return fail(OPDHG_ERR_INVALID_ARGUMENT, "row_ptr must be nondecreasing");
+  if (lp->row_ptr[m] != nnz) return fail(OPDHG_ERR_INVALID_ARGUMENT, "row_ptr[m] must equal nnz");
+  std::vector<int64_t> seen(static_cast<size_t>(n), -1);
+  for (int64_t i = 0; i < m; ++i) {
+    for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+      const int32_t j = lp->col_idx[k];
+      if (j < 0 || j >= n) return fail(OPDHG_ERR_INVALID_ARGUMENT, "column index out of range");
+      if (seen[j] == i) return fail(OPDHG_ERR_INVALID_ARGUMENT, "duplicate (row, column) entry");
+      seen[j] = i;
+      if (!std::isfinite(lp->val[k]))
+        return fail(OPDHG_ERR_INVALID_ARGUMENT, "A has a non-finite entry");
+    }
+    if (!std::isfinite(lp->b[i])) return fail(OPDHG_ERR_INVALID_ARGUMENT, "b must be finite");
+    if (lp->row_sense[i] != 0 && lp->row_sense[i] != 1)
+      return fail(OPDHG_ERR_INVALID_ARGUMENT, "row sense must be 0 or 1");
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    if (!std::isfinite(lp->c[j])) return fail(OPDHG_ERR_INVALID_ARGUMENT, "c must be finite");
+    const double l = lp->l[j], u = lp->u[j];
+    if (std::isnan(l) || std::isnan(u))
+      return fail(OPDHG_ERR_INVALID_ARGUMENT, "bounds must not be NaN");
+    if (l == INFINITY || u == -INFINITY)
+      return fail(OPDHG_ERR_INVALID_ARGUMENT, "l must be below +inf and u above -inf");
+    if (l > u) return fail(OPDHG_ERR_INVALID_ARGUMENT, "l must not exceed u");
+  }
+  if (!std::isfinite(lp->obj_offset))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "objective offset must be finite");
+  return OPDHG_OK;
+}
+
+int validate_params(const opdhg_params* p) {
+  if (!p) return fail(OPDHG_ERR_INVALID_ARGUMENT, "params is NULL");
+  if (!(p->tol >= 0.0)) return fail(OPDHG_ERR_INVALID_ARGUMENT, "tol must be >= 0");
+  if (p->max_iter < 0) return fail(OPDHG_ERR_INVALID_ARGUMENT, "max_iter must be >= 0");
+  if (!(p->time_limit_s >= 0.0)) return fail(OPDHG_ERR_INVALID_ARGUMENT, "time limit must be >= 0");
+  if (p->precision != OPDHG_FP64 && p->precision != OPDHG_FP32)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "unknown precision");
+  if (p->schedule < 0 || p->schedule > 2) return fail(OPDHG_ERR_INVALID_ARGUMENT, "unknown schedule");
+  if (!(p->lr >= 0.0) || !std::isfinite(p->lr))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "lr must be finite and >= 0");
+  if (p->phi < 1) return fail(OPDHG_ERR_INVALID_ARGUMENT, "phi must be >= 1");
+  if (!(p->precond_floor >= 0.0) || !std::isfinite(p->precond_floor))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "precond_floor must be finite and >= 0");
+  if (p->ruiz_iters < 0) return fail(OPDHG_ERR_INVALID_ARGUMENT, "ruiz_iters must be >= 0");
+  if (!std::isfinite(p->pc_beta) || p->pc_beta > 2.0)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "pc_beta must be <= 2 (negative skips the pass)");
+  if (p->eval_every < 1) return fail(OPDHG_ERR_INVALID_ARGUMENT, "eval_every must be >= 1");
+  if (p->max_step_retries < 0)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "max_step_retries must be >= 0");
+  if (p->tile_nnz < 0) return fail(OPDHG_ERR_INVALID_ARGUMENT, "tile_nnz must be >= 0");
+  if (p->lanes < 0 || p->lanes > 64 || (p->lanes & (p->lanes - 1)) != 0)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "lanes must be 0 or a power of two <= 64");
+  return OPDHG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// double-double accumulation on the host: sums rounded once at the end,
+// so they agree with any other correctly rounded evaluation of the same sum
+// except in near-tie cases
+// ---------------------------------------------------------------------------
+
+struct HostDD {
+  double hi = 0.0, lo = 0.0;
+  void add(double x) {
+    const double s = hi + x;
+    const double bb = s - hi;
+    lo += (hi - (s - bb)) + (x - bb);
+    hi = s;
+  }
+  void add_prod(double a, double b) {
+    const double p = a * b;
+    add(p);
+    lo += std::fma(a, b, -p);
+  }
+  double value() const { return hi + lo; }
+};
+
+static double dd_norm(const double* v, int64_t n) {
+  HostDD acc;
+  for (int64_t i = 0; i < n; ++i) acc.add_prod(v[i], v[i]);
+  return std::sqrt(acc.value());
+}
+
+// ---------------------------------------------------------------------------
+// rescaling: Ruiz infinity-norm passes then one Pock-Chambolle pass
+// (Section 2 of the paper), square-root split between rows and columns
+// ---------------------------------------------------------------------------
+
+void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,
+                  std::vector<double>& dr, std::vector<double>& dc) {
+  const int64_t m = lp->m, n = lp->n;
+  dr.assign(m, 1.0);
+  dc.assign(n, 1.0);
+  std::vector<double> rs(m), cs(n);
+  auto apply = [&]() {
+    for (int64_t i = 0; i < m; ++i) dr[i] = dr[i] / std::sqrt(rs[i] == 0.0 ? 1.0 : rs[i]);
+    for (int64_t j = 0; j < n; ++j) dc[j] = dc[j] / std::sqrt(cs[j] == 0.0 ? 1.0 : cs[j]);
+  };
+  for (int it = 0; it < ruiz_iters; ++it) {
+    std::fill(rs.begin(), rs.end(), 0.0);
+    std::fill(cs.begin(), cs.end(), 0.0);
+    for (int64_t i = 0; i < m; ++i) {
+      double rmax = 0.0;
+      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+        const int32_t j = lp->col_idx[k];
+        const double a = std::fabs(lp->val[k]) * dr[i] * dc[j];
+        rmax = std::max(rmax, a);
+        cs[j] = std::max(cs[j], a);
+      }
+      rs[i] = rmax;
+    }
+    apply();
+  }
+  if (beta >= 0.0) {
+    std::vector<HostDD> csum(n);
+    for (int64_t i = 0; i < m; ++i) {
+      HostDD racc;
+      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+        const int32_t j = lp->col_idx[k];
+        const double a = std::fabs(lp->val[k]) * dr[i] * dc[j];
+        racc.add(beta == 1.0 ? a : std::pow(a, beta));
+        csum[j].add(beta == 1.0 ? a : std::pow(a, 2.0 - beta));
+      }
+      rs[i] = racc.value();
+    }
+    for (int64_t j = 0; j < n; ++j) cs[j] = csum[j].value();
+    apply();
+  }
+  sval.resize(lp->nnz);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k)
+      sval[k] = lp->val[k] * dr[i] * dc[lp->col_idx[k]];
+}
+
+// ---------------------------------------------------------------------------
+// tiling
+// ---------------------------------------------------------------------------
+
+static int lanes_for(double mean_len) {
+  int L = 1;
+  while (L < 64 && L * 1.5 < mean_len) L <<= 1;
+  return L;
+}
+
+// Rows [0, rows) of a CSR side into tiles: rows of at least `long_len`
+// nonzeros get a workgroup each; other rows are packed greedily up to
+// `target` weight (nonzeros plus a per-row charge for the epilogue).
+std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t target, int lanes_fixed) {
+  std::vector<Tile> tiles;
+  const int64_t long_len = std::max<int64_t>(1024, target);
+  const int64_t row_w = 4;
+  const int64_t max_rows = 16384;
+  int64_t i = 0;
+  while (i < rows) {
+    const int64_t len = rp[i + 1] - rp[i];
+    if (len >= long_len) {
+      tiles.push_back(Tile{(int32_t)i, (int32_t)(i + 1), 0, 0});
+      ++i;
+      continue;
+    }
+    const int64_t start = i;
+    int64_t weight = 0;
+    while (i < rows && i - start < max_rows) {
+      const int64_t l = rp[i + 1] - rp[i];
+      if (l >= long_len) break;
+      if (i > start && weight + l + row_w > target) break;
+      weight += l + row_w;
+      ++i;
+    }
+    const double mean = double(rp[i] - rp[start]) / double(i - start);
+    const int L = lanes_fixed > 0 ? lanes_fixed : lanes_for(mean);
+    tiles.push_back(Tile{(int32_t)start, (int32_t)i, L, 0});
+  }
+  if (tiles.empty()) tiles.push_back(Tile{0, 0, 1, 0});
+  return tiles;
+}
+
+int64_t auto_tile_target(int64_t nnz, int64_t rows) {
+  const int64_t weight = nnz + 4 * rows;
+  int64_t t = weight / 2048;
+  return std::min<int64_t>(std::max<int64_t>(t, 512), 32768);
+}
+
+// ---------------------------------------------------------------------------
+// preparation: everything the device needs, computed on the host in FP64
+// ---------------------------------------------------------------------------
+
+int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool structure_only) {
+  out.m = lp->m;
+  out.n = lp->n;
+  out.nnz = lp->nnz;
+  const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
+  out.rp_a.resize(m + 1);
+  for (int64_t i = 0; i <= m; ++i) out.rp_a[i] = (int32_t)lp->row_ptr[i];
+  // transpose structure: counting sort by column, rows ascending within a column
+  out.rp_t.assign(n + 1, 0);
+  for (int64_t k = 0; k < nnz; ++k) out.rp_t[lp->col_idx[k] + 1]++;
+  for (int64_t j = 0; j < n; ++j) out.rp_t[j + 1] += out.rp_t[j];
+  const int64_t target_a = p->tile_nnz > 0 ? p->tile_nnz : auto_tile_target(nnz, m);
+  const int64_t target_t = p->tile_nnz > 0 ? p->tile_nnz : auto_tile_target(nnz, n);
+  out.tiles_a = build_tiles(out.rp_a.data(), m, target_a, p->lanes);
+  out.tiles_t = build_tiles(out.rp_t.data(), n, target_t, p->lanes);
+  if (structure_only) return OPDHG_OK;
+
+  out.ci_a.assign(lp->col_idx, lp->col_idx + nnz);
+  std::vector<double> sval;
+  rescale_host(lp, p->ruiz_iters, p->pc_beta, sval, out.dr, out.dc);
+  out.va_a = sval;
+  out.ci_t.resize(nnz);
+  out.va_t.resize(nnz);
+  {
+    std::vector<int32_t> next(out.rp_t.begin(), out.rp_t.end() - 1);
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+        const int32_t pos = next[lp->col_idx[k]]++;
+        out.ci_t[pos] = (int32_t)i;
+        out.va_t[pos] = sval[k];
+      }
+  }
+  out.b.resize(m);
+  out.sense.resize(m);
+  for (int64_t i = 0; i < m; ++i) {
+    out.b[i] = out.dr[i] * lp->b[i];
+    out.sense[i] = lp->row_sense[i];
+  }
+  out.c.resize(n);
+  out.l.resize(n);
+  out.u.resize(n);
+  out.bfin.resize(n);
+  out.x0.resize(n);
+  for (int64_t j = 0; j < n; ++j) {
+    out.c[j] = out.dc[j] * lp->c[j];
+    out.l[j] = lp->l[j] / out.dc[j];
+    out.u[j] = lp->u[j] / out.dc[j];
+    out.bfin[j] = (int8_t)((std::isfinite(lp->l[j]) ? 1 : 0) | (std::isfinite(lp->u[j]) ? 2 : 0));
+    const double z = 0.0;
+    out.x0[j] = std::min(std::max(z, out.l[j]), out.u[j]);
+  }
+  double amax = 0.0;
+  for (int64_t k = 0; k < nnz; ++k) amax = std::max(amax, std::fabs(sval[k]));
+  const double bsn = dd_norm(out.b.data(), m);
+  const double csn = dd_norm(out.c.data(), n);
+  out.omega0 = (csn > 1e-10 && bsn > 1e-10) ? csn / bsn : 1.0;
+  out.eta0 = amax > 0.0 ? 1.0 / amax : 1.0;
+  DevParams& d = out.prm;
+  std::memset(&d, 0, sizeof(d));
+  d.tol = p->tol;
+  d.lr = p->lr;
+  d.floor = p->precond_floor;
+  d.beta_suff = p->beta_suff;
+  d.beta_nec = p->beta_nec;
+  d.beta_art = p->beta_art;
+  d.pw_smoothing = p->pw_smoothing;
+  d.step_growth = p->step_growth;
+  d.step_reduction = p->step_reduction;
+  d.b_norm = dd_norm(lp->b, m);
+  d.c_norm = dd_norm(lp->c, n);
+  out.pow_tab.resize(2 * kPowTab);
+  for (int j = 1; j <= kPowTab; ++j) {
+    out.pow_tab[j - 1] = std::pow((double)(j + 1), -p->step_reduction);
+    out.pow_tab[kPowTab + j - 1] = std::pow((double)(j + 1), -p->step_growth);
+  }
+  d.c0 = lp->obj_offset;
+  d.max_iter = p->max_iter;
+  d.phi = p->phi;
+  d.normalize = p->normalize ? 1 : 0;
+  d.schedule = p->schedule;
+  d.eval_every = p->eval_every;
+  d.max_retries = p->max_step_retries;
+  return OPDHG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout of one LP slot
+// ---------------------------------------------------------------------------
+
+static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int64_t ntiles_a,
+                       int prec) {
+  SlotLayout L;
+  const size_t V = prec == OPDHG_FP32 ? 4 : 8;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  L.ctl = take(sizeof(Ctl));
+  L.prm = take(sizeof(DevParams));
+  L.tiles_a = take(sizeof(Tile) * ntiles_a);
+  L.tiles_t = take(sizeof(Tile) * ntiles_t);
+  L.part_a = take(sizeof(double) * kPartStride * ntiles_a);
+  L.part_t = take(sizeof(double) * kPartStride * ntiles_t);
+  L.pow_tab = take(sizeof(double) * 2 * kPowTab);
+  L.rp_a = take(4 * (m + 1));
+  L.ci_a = take(4 * nnz);
+  L.va_a = take(V * nnz);
+  L.rp_t = take(4 * (n + 1));
+  L.ci_t = take(4 * nnz);
+  L.va_t = take(V * nnz);
+  for (int q = 0; q < SlotLayout::kNVecN; ++q) L.vn[q] = take(V * n);
+  L.dc = take(8 * n);
+  L.bfin = take(n);
+  for (int q = 0; q < SlotLayout::kNVecM; ++q) L.vm[q] = take(V * m);
+  L.dr = take(8 * m);
+  L.sense = take(m);
+  L.total = off;
+  return L;
+}
+
+// n-vector slots: c l u T Hp Gp x0 x1 xs0 xs1 xa
+// m-vector slots: b S Hd Gd y0 y1 ys0 ys1 ya Ax0 Ax1 Axa
+LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
+  LpDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.m = (int32_t)P.m;
+  d.n = (int32_t)P.n;
+  d.ntiles_t = (int32_t)P.tiles_t.size();
+  d.ntiles_a = (int32_t)P.tiles_a.size();
+  d.rp_a = reinterpret_cast<const int32_t*>(base + L.rp_a);
+  d.ci_a = reinterpret_cast<const int32_t*>(base + L.ci_a);
+  d.va_a = base + L.va_a;
+  d.rp_t = reinterpret_cast<const int32_t*>(base + L.rp_t);
+  d.ci_t = reinterpret_cast<const int32_t*>(base + L.ci_t);
+  d.va_t = base + L.va_t;
+  d.tiles_a = reinterpret_cast<const Tile*>(base + L.tiles_a);
+  d.tiles_t = reinterpret_cast<const Tile*>(base + L.tiles_t);
+  void** vn[SlotLayout::kNVecN] = {&d.c,     &d.l,     &d.u,     &d.T,      &d.Hp,  &d.Gp,
+                                   &d.x[0],  &d.x[1],  &d.xs[0], &d.xs[1],  &d.xa};
+  for (int q = 0; q < SlotLayout::kNVecN; ++q) *vn[q] = base + L.vn[q];
+  void** vm[SlotLayout::kNVecM] = {&d.b,      &d.S,      &d.Hd, &d.Gd,    &d.y[0],  &d.y[1],
+                                   &d.ys[0],  &d.ys[1],  &d.ya, &d.Ax[0], &d.Ax[1], &d.Axa};
+  for (int q = 0; q < SlotLayout::kNVecM; ++q) *vm[q] = base + L.vm[q];
+  d.dr = reinterpret_cast<const double*>(base + L.dr);
+  d.dc = reinterpret_cast<const double*>(base + L.dc);
+  d.sense = reinterpret_cast<const int8_t*>(base + L.sense);
+  d.bfin = reinterpret_cast<const int8_t*>(base + L.bfin);
+  d.part_t = reinterpret_cast<double*>(base + L.part_t);
+  d.part_a = reinterpret_cast<double*>(base + L.part_a);
+  d.pow_tab = reinterpret_cast<const double*>(base + L.pow_tab);
+  d.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
+  d.prm = reinterpret_cast<const DevParams*>(base + L.prm);
+  return d;
+}
+
+template <typename V>
+static void put_vec(std::vector<uint8_t>& img, size_t off, const std::vector<double>& v) {
+  V* dst = reinterpret_cast<V*>(img.data() + off);
+  for (size_t i = 0; i < v.size(); ++i) dst[i] = (V)v[i];
+}
+
+template <typename V>
+static void put_const(std::vector<uint8_t>& img, size_t off, size_t count, double value) {
+  V* dst = reinterpret_cast<V*>(img.data() + off);
+  for (size_t i = 0; i < count; ++i) dst[i] = (V)value;
+}
+
+Ctl initial_ctl(const Prepared& P) {
+  Ctl c;
+  std::memset(&c, 0, sizeof(c));
+  c.eta = P.eta0;
+  c.omega = P.omega0;
+  c.prev_cand = INFINITY;
+  c.k_limit = std::numeric_limits<int64_t>::max();
+  c.status = kRunning;
+  c.need_eval = 1;
+  return c;
+}
+
+// Host image of a slot: every byte the device needs at the start.
+template <typename V>
+void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& img) {
+  img.assign(L.total, 0);
+  const Ctl c = initial_ctl(P);
+  std::memcpy(img.data() + L.ctl, &c, sizeof(c));
+  std::memcpy(img.data() + L.prm, &P.prm, sizeof(DevParams));
+  std::memcpy(img.data() + L.tiles_a, P.tiles_a.data(), sizeof(Tile) * P.tiles_a.size());
+  std::memcpy(img.data() + L.tiles_t, P.tiles_t.data(), sizeof(Tile) * P.tiles_t.size());
+  std::memcpy(img.data() + L.pow_tab, P.pow_tab.data(), sizeof(double) * P.pow_tab.size());
+  std::memcpy(img.data() + L.rp_a, P.rp_a.data(), 4 * P.rp_a.size());
+  std::memcpy(img.data() + L.ci_a, P.ci_a.data(), 4 * P.ci_a.size());
+  put_vec<V>(img, L.va_a, P.va_a);
+  std::memcpy(img.data() + L.rp_t, P.rp_t.data(), 4 * P.rp_t.size());
+  std::memcpy(img.data() + L.ci_t, P.ci_t.data(), 4 * P.ci_t.size());
+  put_vec<V>(img, L.va_t, P.va_t);
+  // n-vectors: c l u T Hp Gp x0 x1 xs0 xs1 xa
+  put_vec<V>(img, L.vn[0], P.c);
+  put_vec<V>(img, L.vn[1], P.l);
+  put_vec<V>(img, L.vn[2], P.u);
+  put_const<V>(img, L.vn[3], P.n, 1.0);
+  put_vec<V>(img, L.vn[6], P.x0);
+  put_vec<V>(img, L.vn[10], P.x0);
+  std::memcpy(img.data() + L.dc, P.dc.data(), 8 * P.dc.size());
+  std::memcpy(img.data() + L.bfin, P.bfin.data(), P.bfin.size());
+  // m-vectors: b S Hd Gd y0 y1 ys0 ys1 ya Ax0 Ax1 Axa
+  put_vec<V>(img, L.vm[0], P.b);
+  put_const<V>(img, L.vm[1], P.m, 1.0);
+  std::memcpy(img.data() + L.dr, P.dr.data(), 8 * P.dr.size());
+  if (P.m) std::memcpy(img.data() + L.sense, P.sense.data(), P.sense.size());
+}
+
+template void slot_image<double>(const SlotLayout&, const Prepared&, std::vector<uint8_t>&);
+template void slot_image<float>(const SlotLayout&, const Prepared&, std::vector<uint8_t>&);
+
+// ---------------------------------------------------------------------------
+// a group of LPs launched together (one LP, a batch, or the server's mix)
+// ---------------------------------------------------------------------------
+
+int Group::capture(int attempts_per_replay) {
+  if (exec) {
+    (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = 0;
+  auto K = [&](auto tag) {
+    using V = decltype(tag);
+    rc |= Kernels<V>::eval_t(cfg, cap_stream);
+    rc |= Kernels<V>::eval_a(cfg, cap_stream);
+    rc |= Kernels<V>::apply(cfg, cap_stream);
+    for (int a = 0; a < attempts_per_replay; ++a) {
+      rc |= Kernels<V>::primal(cfg, cap_stream, 0);
+      rc |= Kernels<V>::dual(cfg, cap_stream);
+      rc |= Kernels<V>::learn(cfg, cap_stream);
+    }
+  };
+  if (prec == OPDHG_FP32) K(float{});
+  else K(double{});
+  hipError_t e = hipStreamEndCapture(cap_stream, &graph);
+  if (rc != 0) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(OPDHG_ERR_DEVICE, std::string("kernel launch failed: ") + device_error_string());
+  }
+  if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+  return OPDHG_OK;
+}
+
+int Group::init(void* stream_, int prec_) {
+  stream = (hipStream_t)stream_;
+  prec = prec_;
+  HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  return OPDHG_OK;
+}
+
+void Group::release() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  exec = nullptr;
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  cap_stream = nullptr;
+}
+
+void Group::set_grid(int64_t nwork_t, int64_t nwork_a, bool fixed) {
+  auto g = [&](int64_t w) { return (int)std::max<int64_t>(1, fixed ? kGridCap : std::min<int64_t>(w, kGridCap)); };
+  cfg.grid_t = g(nwork_t);
+  cfg.grid_a = g(nwork_a);
+  cfg.grid_ta = g(nwork_t + nwork_a);
+}
+
+int Group::launch_init() {
+  if (prec == OPDHG_FP32) return Kernels<float>::init_products(cfg, stream);
+  return Kernels<double>::init_products(cfg, stream);
+}
+
+int Group::launch_primal_forced() {
+  if (prec == OPDHG_FP32) return Kernels<float>::primal(cfg, stream, 1);
+  return Kernels<double>::primal(cfg, stream, 1);
+}
+
+int Group::replay() {
+  HIP_TRY(hipGraphLaunch(exec, stream));
+  return OPDHG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single-LP session
+// ---------------------------------------------------------------------------
+
+struct SessionImpl {
+  Prepared P;
+  SlotLayout L;
+  uint8_t* ws = nullptr;
+  LpDev lpd;
+  Group grp;
+  uint8_t* d_tables = nullptr;  // LpDev, WorkItems and BatchDev live after the slot
+  Ctl* h_ctl = nullptr;         // pinned readback
+  double time_limit = 600.0;
+  double elapsed = 0.0;
+  int replays = 0;
+};
+
+static size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a) {
+  return align_up(sizeof(LpDev) * nlps) + align_up(sizeof(WorkItem) * std::max<int64_t>(nwork_t, 1)) +
+         align_up(sizeof(WorkItem) * std::max<int64_t>(nwork_a, 1)) + align_up(sizeof(BatchDev));
+}
+
+// Write the tables for a list of LPs into device memory at `dst`.
+int write_tables(uint8_t* dst, const std::vector<LpDev>& lps, hipStream_t stream,
+                 std::vector<uint8_t>& staging, const BatchDev** bd_out, int64_t* nwt,
+                 int64_t* nwa) {
+  std::vector<WorkItem> wt, wa;
+  for (size_t i = 0; i < lps.size(); ++i) {
+    for (int t = 0; t < lps[i].ntiles_t; ++t) wt.push_back(WorkItem{(int32_t)i, t});
+    for (int t = 0; t < lps[i].ntiles_a; ++t) wa.push_back(WorkItem{(int32_t)i, t});
+  }
+  const size_t o_lps = 0;
+  const size_t o_wt = o_lps + align_up(sizeof(LpDev) * lps.size());
+  const size_t o_wa = o_wt + align_up(sizeof(WorkItem) * std::max<size_t>(wt.size(), 1));
+  const size_t o_bd = o_wa + align_up(sizeof(WorkItem) * std::max<size_t>(wa.size(), 1));
+  const size_t total = o_bd + align_up(sizeof(BatchDev));
+  staging.assign(total, 0);
+  if (!lps.empty()) std::memcpy(staging.data() + o_lps, lps.data(), sizeof(LpDev) * lps.size());
+  if (!wt.empty()) std::memcpy(staging.data() + o_wt, wt.data(), sizeof(WorkItem) * wt.size());
+  if (!wa.empty()) std::memcpy(staging.data() + o_wa, wa.data(), sizeof(WorkItem) * wa.size());
+  BatchDev bd;
+  bd.lps = reinterpret_cast<const LpDev*>(dst + o_lps);
+  bd.work_t = reinterpret_cast<const WorkItem*>(dst + o_wt);
+  bd.work_a = reinterpret_cast<const WorkItem*>(dst + o_wa);
+  bd.nwork_t = (int32_t)wt.size();
+  bd.nwork_a = (int32_t)wa.size();
+  bd.nlps = (int32_t)lps.size();
+  bd.pad = 0;
+  std::memcpy(staging.data() + o_bd, &bd, sizeof(bd));
+  HIP_TRY(hipMemcpyAsync(dst, staging.data(), total, hipMemcpyHostToDevice, stream));
+  *bd_out = reinterpret_cast<const BatchDev*>(dst + o_bd);
+  *nwt = (int64_t)wt.size();
+  *nwa = (int64_t)wa.size();
+  return OPDHG_OK;
+}
+
+int upload_slot(uint8_t* base, const SlotLayout& L, const Prepared& P, int prec,
+                hipStream_t stream, std::vector<uint8_t>& img) {
+  if (prec == OPDHG_FP32) slot_image<float>(L, P, img);
+  else slot_image<double>(L, P, img);
+  HIP_TRY(hipMemcpyAsync(base, img.data(), L.total, hipMemcpyHostToDevice, stream));
+  return OPDHG_OK;
+}
+
+template <typename V>
+static void get_vec(const uint8_t* src, size_t count, double* out) {
+  const V* s = reinterpret_cast<const V*>(src);
+  for (size_t i = 0; i < count; ++i) out[i] = (double)s[i];
+}
+
+// Download `count` elements of a V-typed device vector as doubles.
+int download_vec(const void* dptr, size_t count, int prec, hipStream_t stream, double* out) {
+  if (!out || count == 0) return OPDHG_OK;
+  const size_t V = prec == OPDHG_FP32 ? 4 : 8;
+  std::vector<uint8_t> tmp(count * V);
+  HIP_TRY(hipMemcpyAsync(tmp.data(), dptr, count * V, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (prec == OPDHG_FP32) get_vec<float>(tmp.data(), count, out);
+  else get_vec<double>(tmp.data(), count, out);
+  return OPDHG_OK;
+}
+
+void fill_result(const Ctl& c, double seconds, opdhg_result* r) {
+  std::memset(r, 0, sizeof(*r));
+  r->status = c.status;
+  r->which = c.which;
+  r->iterations = c.k;
+  r->attempts = c.attempts;
+  r->restarts = c.restarts;
+  const bool evaluated = c.status == kOptimal || c.status == kIterLimit || c.status == kTimeLimit;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  r->primal_obj = evaluated ? c.out_pobj : nan;
+  r->dual_obj = evaluated ? c.out_dobj : nan;
+  r->rel_primal = evaluated ? c.out_relp : nan;
+  r->rel_dual = evaluated ? c.out_reld : nan;
+  r->rel_gap = evaluated ? c.out_relg : nan;
+  r->rel_kkt = evaluated ? c.out_rel : nan;
+  r->solve_seconds = seconds;
+  r->eta = c.eta;
+  r->omega = c.omega;
+}
+
+static const int32_t kOne = 1;
+
+// Run a group's replays until every LP is done, k_target is reached, or
+// the time limit passes. ctls points at `count` consecutive control blocks
+// on the device only when the group is one LP; a batch passes its list.
+int run_group(Group& grp, const std::vector<Ctl*>& d_ctls, std::vector<Ctl>& h_ctls,
+              Ctl* pinned, int64_t k_target, double time_limit, double* elapsed) {
+  const size_t cnt = d_ctls.size();
+  auto t0 = std::chrono::steady_clock::now();
+  int64_t last_progress = -1;
+  int stalls = 0;
+  // pause point
+  for (size_t i = 0; i < cnt; ++i) {
+    HIP_TRY(hipMemcpyAsync(pinned + i, d_ctls[i], sizeof(Ctl), hipMemcpyDeviceToHost, grp.stream));
+  }
+  HIP_TRY(hipStreamSynchronize(grp.stream));
+  bool any_running = false;
+  for (size_t i = 0; i < cnt; ++i) {
+    h_ctls[i] = pinned[i];
+    if (h_ctls[i].status == kRunning) {
+      h_ctls[i].k_limit = k_target < 0 ? std::numeric_limits<int64_t>::max() : k_target;
+      HIP_TRY(hipMemcpyAsync(&d_ctls[i]->k_limit, &h_ctls[i].k_limit, sizeof(int64_t),
+                             hipMemcpyHostToDevice, grp.stream));
+      any_running = true;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(grp.stream));
+  bool stop_sent = false;
+  while (any_running) {
+    int rc = grp.replay();
+    if (rc) return rc;
+    for (size_t i = 0; i < cnt; ++i)
+      HIP_TRY(hipMemcpyAsync(pinned + i, d_ctls[i], sizeof(Ctl), hipMemcpyDeviceToHost, grp.stream));
+    HIP_TRY(hipStreamSynchronize(grp.stream));
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    any_running = false;
+    bool all_paused = true;
+    int64_t progress = 0;
+    for (size_t i = 0; i < cnt; ++i) {
+      h_ctls[i] = pinned[i];
+      const Ctl& c = h_ctls[i];
+      progress += c.attempts + c.restarts + c.k;
+      if (c.status == kRunning) {
+        any_running = true;
+        const bool paused = k_target >= 0 && c.k >= k_target;
+        if (!paused) all_paused = false;
+      }
+    }
+    if (!any_running || all_paused) break;
+    if (progress == last_progress) {
+      if (++stalls > 3) return fail(OPDHG_ERR_DEVICE, "device iteration made no progress");
+    } else {
+      stalls = 0;
+    }
+    last_progress = progress;
+    if (!stop_sent && el > time_limit) {
+      for (size_t i = 0; i < cnt; ++i) {
+        if (h_ctls[i].status != kRunning) continue;
+        HIP_TRY(hipMemcpyAsync(&d_ctls[i]->stop_request, &kOne, sizeof(kOne),
+                               hipMemcpyHostToDevice, grp.stream));
+        HIP_TRY(hipMemcpyAsync(&d_ctls[i]->need_eval, &kOne, sizeof(kOne),
+                               hipMemcpyHostToDevice, grp.stream));
+      }
+      stop_sent = true;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(grp.stream));
+  *elapsed += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return OPDHG_OK;
+}
+
+}  // namespace opdhg
+
+using namespace opdhg;
+
+struct opdhg_session {
+  SessionImpl impl;
+};
+
+extern "C" {
+
+void opdhg_default_params(opdhg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tol = 1e-4;
+  p->max_iter = 100000;
+  p->time_limit_s = 600.0;
+  p->precision = OPDHG_FP64;
+  p->schedule = OPDHG_SCHEDULE_ADAGRAD_DIAG;
+  p->lr = 0.0;
+  p->phi = 20;
+  p->normalize = 1;
+  p->precond_floor = 0.0;
+  p->ruiz_iters = 10;
+  p->pc_beta = 1.0;
+  p->eval_every = 64;
+  p->max_step_retries = 60;
+  p->beta_suff = 0.2;
+  p->beta_nec = 0.8;
+  p->beta_art = 0.36;
+  p->pw_smoothing = 0.5;
+  p->step_growth = 0.6;
+  p->step_reduction = 0.3;
+  p->tile_nnz = 0;
+  p->lanes = 0;
+}
+
+int opdhg_validate(const opdhg_lp* lp) { return validate_lp(lp); }
+
+int opdhg_workspace_bytes(const opdhg_lp* lp, const opdhg_params* p, size_t* bytes) {
+  int rc = validate_lp(lp);
+  if (rc) return rc;
+  if ((rc = validate_params(p))) return rc;
+  if (!bytes) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  Prepared P;
+  prepare(lp, p, P, true);
+  SlotLayout L = slot_layout(P.m, P.n, P.nnz, P.tiles_t.size(), P.tiles_a.size(), p->precision);
+  *bytes = L.total + tables_bytes(1, P.tiles_t.size(), P.tiles_a.size());
+  return OPDHG_OK;
+}
+
+int opdhg_rescale(const opdhg_lp* lp, const opdhg_params* p, double* scaled_val, double* d_row,
+                  double* d_col) {
+  int rc = validate_lp(lp);
+  if (rc) return rc;
+  if ((rc = validate_params(p))) return rc;
+  std::vector<double> sval, dr, dc;
+  rescale_host(lp, p->ruiz_iters, p->pc_beta, sval, dr, dc);
+  if (scaled_val) std::copy(sval.begin(), sval.end(), scaled_val);
+  if (d_row) std::copy(dr.begin(), dr.end(), d_row);
+  if (d_col) std::copy(dc.begin(), dc.end(), d_col);
+  return OPDHG_OK;
+}
+
+int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                         size_t workspace_bytes, void* hip_stream, opdhg_session** out) {
+  if (!out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  int rc = validate_lp(lp);
+  if (rc) return rc;
+  if ((rc = validate_params(p))) return rc;
+  if (!d_workspace) return fail(OPDHG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  auto s = std::make_unique<opdhg_session>();
+  SessionImpl& S = s->impl;
+  if ((rc = prepare(lp, p, S.P, false))) return rc;
+  S.L = slot_layout(S.P.m, S.P.n, S.P.nnz, S.P.tiles_t.size(), S.P.tiles_a.size(), p->precision);
+  const size_t need = S.L.total + tables_bytes(1, S.P.tiles_t.size(), S.P.tiles_a.size());
+  if (workspace_bytes < need)
+    return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL,
+                "workspace needs " + std::to_string(need) + " bytes");
+  S.ws = static_cast<uint8_t*>(d_workspace);
+  S.time_limit = p->time_limit_s;
+  if ((rc = S.grp.init(hip_stream, p->precision))) return rc;
+  std::vector<uint8_t> img;
+  if ((rc = upload_slot(S.ws, S.L, S.P, p->precision, S.grp.stream, img))) return rc;
+  S.lpd = slot_pointers(S.ws, S.L, S.P);
+  S.d_tables = S.ws + S.L.total;
+  std::vector<uint8_t> staging;
+  int64_t nwt = 0, nwa = 0;
+  if ((rc = write_tables(S.d_tables, {S.lpd}, S.grp.stream, staging, &S.grp.cfg.bd, &nwt, &nwa)))
+    return rc;
+  S.grp.set_grid(nwt, nwa, false);
+  if ((rc = S.grp.launch_init())) return fail(OPDHG_ERR_DEVICE, device_error_string());
+  HIP_TRY(hipStreamSynchronize(S.grp.stream));
+  if ((rc = S.grp.capture(std::max(1, p->eval_every)))) return rc;
+  HIP_TRY(hipHostMalloc((void**)&S.h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  *out = s.release();
+  return OPDHG_OK;
+}
+
+int opdhg_session_run(opdhg_session* s, int64_t k_target) {
+  if (!s) return fail(OPDHG_ERR_INVALID_ARGUMENT, "session is NULL");
+  SessionImpl& S = s->impl;
+  std::vector<Ctl*> ctls = {S.lpd.ctl};
+  std::vector<Ctl> h(1);
+  return run_group(S.grp, ctls, h, S.h_ctl, k_target, S.time_limit - S.elapsed, &S.elapsed);
+}
+
+int opdhg_session_state(opdhg_session* s, double* x, double* y, double* T, double* Sigma,
+                        opdhg_state* st) {
+  if (!s) return fail(OPDHG_ERR_INVALID_ARGUMENT, "session is NULL");
+  SessionImpl& S = s->impl;
+  Ctl c;
+  HIP_TRY(hipMemcpyAsync(S.h_ctl, S.lpd.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, S.grp.stream));
+  HIP_TRY(hipStreamSynchronize(S.grp.stream));
+  c = *S.h_ctl;
+  int rc = 0;
+  const int prec = S.grp.prec;
+  if ((rc = download_vec(S.lpd.x[c.cur], S.P.n, prec, S.grp.stream, x))) return rc;
+  if ((rc = download_vec(S.lpd.y[c.cur], S.P.m, prec, S.grp.stream, y))) return rc;
+  if ((rc = download_vec(S.lpd.T, S.P.n, prec, S.grp.stream, T))) return rc;
+  if ((rc = download_vec(S.lpd.S, S.P.m, prec, S.grp.stream, Sigma))) return rc;
+  if (st) {
+    st->k = c.k;
+    st->t = c.t;
+    st->attempts = c.attempts;
+    st->restarts = c.restarts;
+    st->status = c.status;
+    st->need_eval = c.need_eval;
+    st->eta = c.eta;
+    st->omega = c.omega;
+    st->w = c.w;
+  }
+  return OPDHG_OK;
+}
+
+int opdhg_session_result(opdhg_session* s, double* x_out, double* y_out, opdhg_result* res) {
+  if (!s) return fail(OPDHG_ERR_INVALID_ARGUMENT, "session is NULL");
+  SessionImpl& S = s->impl;
+  HIP_TRY(hipMemcpyAsync(S.h_ctl, S.lpd.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, S.grp.stream));
+  HIP_TRY(hipStreamSynchronize(S.grp.stream));
+  const Ctl c = *S.h_ctl;
+  int rc = 0;
+  const int prec = S.grp.prec;
+  if (x_out) {
+    if ((rc = download_vec(S.lpd.x[c.cur], S.P.n, prec, S.grp.stream, x_out))) return rc;
+    for (int64_t j = 0; j < S.P.n; ++j) x_out[j] *= S.P.dc[j];
+  }
+  if (y_out) {
+    if ((rc = download_vec(S.lpd.y[c.cur], S.P.m, prec, S.grp.stream, y_out))) return rc;
+    for (int64_t i = 0; i < S.P.m; ++i) y_out[i] *= S.P.dr[i];
+  }
+  if (res) fill_result(c, S.elapsed, res);
+  return OPDHG_OK;
+}
+
+int opdhg_session_time_primal_kernel(opdhg_session* s, int reps, double* avg_ms) {
+  if (!s || reps < 1 || !avg_ms) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  SessionImpl& S = s->impl;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = S.grp.launch_primal_forced();  // warm-up
+  HIP_TRY(hipEventRecord(e0, S.grp.stream));
+  for (int r = 0; r < reps && rc == 0; ++r) rc = S.grp.launch_primal_forced();
+  HIP_TRY(hipEventRecord(e1, S.grp.stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return fail(OPDHG_ERR_DEVICE, device_error_string());
+  *avg_ms = ms / reps;
+  return OPDHG_OK;
+}
+
+void opdhg_session_destroy(opdhg_session* s) {
+  if (!s) return;
+  SessionImpl& S = s->impl;
+  if (S.grp.stream || S.grp.cap_stream) (void)hipStreamSynchronize(S.grp.stream);
+  S.grp.release();
+  if (S.h_ctl) (void)hipHostFree(S.h_ctl);
+  delete s;
+}
+
+int opdhg_solve(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                size_t workspace_bytes, void* hip_stream, double* x_out, double* y_out,
+                opdhg_result* res) {
+  opdhg_session* s = nullptr;
+  int rc = opdhg_session_create(lp, p, d_workspace, workspace_bytes, hip_stream, &s);
+  if (rc) return rc;
+  rc = opdhg_session_run(s, -1);
+  if (!rc) rc = opdhg_session_result(s, x_out, y_out, res);
+  opdhg_session_destroy(s);
+  return rc;
+}
+
+int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_params* p,
+                                size_t* bytes) {
+  if (count < 0 || (count > 0 && !lps) || !bytes)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  int rc = validate_params(p);
+  if (rc) return rc;
+  size_t total = 0;
+  int64_t nwt = 0, nwa = 0;
+  for (int i = 0; i < count; ++i) {
+    if ((rc = validate_lp(&lps[i]))) return rc;
+    Prepared P;
+    prepare(&lps[i], p, P, true);
+    total += slot_layout(P.m, P.n, P.nnz, P.tiles_t.size(), P.tiles_a.size(), p->precision).total;
+    nwt += P.tiles_t.size();
+    nwa += P.tiles_a.size();
+  }
+  *bytes = total + tables_bytes(count, nwt, nwa);
+  return OPDHG_OK;
+}
+
+int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, void* d_workspace,
+                      size_t workspace_bytes, void* hip_stream, double* const* x_out,
+                      double* const* y_out, opdhg_result* res) {
+  if (count < 0 || (count > 0 && (!lps || !res)) || !d_workspace)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  int rc = validate_params(p);
+  if (rc) return rc;
+  if (count == 0) return OPDHG_OK;
+  std::vector<Prepared> P(count);
+  std::vector<SlotLayout> L(count);
+  size_t off = 0;
+  std::vector<size_t> offs(count);
+  for (int i = 0; i < count; ++i) {
+    if ((rc = validate_lp(&lps[i]))) return rc;
+    if ((rc = prepare(&lps[i], p, P[i], false))) return rc;
+    L[i] = slot_layout(P[i].m, P[i].n, P[i].nnz, P[i].tiles_t.size(), P[i].tiles_a.size(),
+                       p->precision);
+    offs[i] = off;
+    off += L[i].total;
+  }
+  int64_t nwt = 0, nwa = 0;
+  for (int i = 0; i < count; ++i) {
+    nwt += P[i].tiles_t.size();
+    nwa += P[i].tiles_a.size();
+  }
+  const size_t need = off + tables_bytes(count, nwt, nwa);
+  if (workspace_bytes < need)
+    return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(need) + " bytes");
+  uint8_t* ws = static_cast<uint8_t*>(d_workspace);
+  Group grp;
+  if ((rc = grp.init(hip_stream, p->precision))) return rc;
+  std::vector<LpDev> lpd(count);
+  std::vector<uint8_t> img;
+  for (int i = 0; i < count; ++i) {
+    if ((rc = upload_slot(ws + offs[i], L[i], P[i], p->precision, grp.stream, img))) {
+      grp.release();
+      return rc;
+    }
+    lpd[i] = slot_pointers(ws + offs[i], L[i], P[i]);
+    // the staging image is reused: wait for the copy before the next fill
+    (void)hipStreamSynchronize(grp.stream);
+  }
+  std::vector<uint8_t> staging;
+  int64_t wt = 0, wa = 0;
+  if ((rc = write_tables(ws + off, lpd, grp.stream, staging, &grp.cfg.bd, &wt, &wa))) {
+    grp.release();
+    return rc;
+  }
+  grp.set_grid(wt, wa, false);
+  if (grp.launch_init()) {
+    grp.release();
+    return fail(OPDHG_ERR_DEVICE, device_error_string());
+  }
+  (void)hipStreamSynchronize(grp.stream);
+  if ((rc = grp.capture(std::max(1, p->eval_every)))) {
+    grp.release();
+    return rc;
+  }
+  Ctl* pinned = nullptr;
+  if (hipHostMalloc((void**)&pinned, sizeof(Ctl) * count, hipHostMallocDefault) != hipSuccess) {
+    grp.release();
+    return fail(OPDHG_ERR_DEVICE, "pinned host allocation failed");
+  }
+  std::vector<Ctl*> ctls(count);
+  for (int i = 0; i < count; ++i) ctls[i] = lpd[i].ctl;
+  std::vector<Ctl> h(count);
+  double elapsed = 0.0;
+  rc = run_group(grp, ctls, h, pinned, -1, p->time_limit_s, &elapsed);
+  for (int i = 0; i < count && rc == 0; ++i) {
+    const Ctl& c = h[i];
+    if (x_out && x_out[i]) {
+      if ((rc = download_vec(lpd[i].x[c.cur], P[i].n, p->precision, grp.stream, x_out[i]))) break;
+      for (int64_t j = 0; j < P[i].n; ++j) x_out[i][j] *= P[i].dc[j];
+    }
+    if (y_out && y_out[i]) {
+      if ((rc = download_vec(lpd[i].y[c.cur], P[i].m, p->precision, grp.stream, y_out[i]))) break;
+      for (int64_t r = 0; r < P[i].m; ++r) y_out[i][r] *= P[i].dr[r];
+    }
+    fill_result(c, elapsed, &res[i]);
+  }
+  (void)hipHostFree(pinned);
+  grp.release();
+  return rc;
+}
+
+const char* opdhg_last_error(void) { return g_err.c_str(); }
+
+const char* opdhg_status_name(int status) {
+  switch (status) {
+    case OPDHG_STATUS_OPTIMAL: return "OPTIMAL";
+    case OPDHG_STATUS_ITERATION_LIMIT: return "ITERATION_LIMIT";
+    case OPDHG_STATUS_TIME_LIMIT: return "TIME_LIMIT";
+    case OPDHG_STATUS_NUMERICAL_ERROR: return "NUMERICAL_ERROR";
+    case OPDHG_STATUS_RUNNING: return "RUNNING";
+    default: return "UNKNOWN";
+  }
+}
+
+const char* opdhg_build_info(void) { return "opdhg 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Host-side structures of the opdhg library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "opdhg.h"
+#include "opdhg_internal.h"
+
+namespace opdhg {
+
+int fail(int code, const std::string& msg);
+int fail_hip(hipError_t e, const char* what);
+int validate_lp(const opdhg_lp* lp);
+int validate_params(const opdhg_params* p);
+
+// An LP after validation, rescaling and transposition, in FP64 on the host.
+struct Prepared {
+  int64_t m = 0, n = 0, nnz = 0;
+  std::vector<int32_t> rp_a, ci_a, rp_t, ci_t;
+  std::vector<double> va_a, va_t;
+  std::vector<double> b, c, l, u, dr, dc, x0;
+  std::vector<int8_t> sense, bfin;
+  std::vector<Tile> tiles_a, tiles_t;
+  std::vector<double> pow_tab;  // step-rule factors, 2 * kPowTab
+  DevParams prm;
+  double eta0 = 1.0, omega0 = 1.0;
+};
+
+// Byte offsets of every array of one LP slot in the workspace.
+struct SlotLayout {
+  static constexpr int kNVecN = 11;  // c l u T Hp Gp x0 x1 xs0 xs1 xa
+  static constexpr int kNVecM = 12;  // b S Hd Gd y0 y1 ys0 ys1 ya Ax0 Ax1 Axa
+  size_t ctl = 0, prm = 0, tiles_a = 0, tiles_t = 0, part_a = 0, part_t = 0, pow_tab = 0;
+  size_t rp_a = 0, ci_a = 0, va_a = 0, rp_t = 0, ci_t = 0, va_t = 0;
+  size_t vn[kNVecN] = {};
+  size_t vm[kNVecM] = {};
+  size_t dc = 0, bfin = 0, dr = 0, sense = 0;
+  size_t total = 0;
+};
+
+int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool structure_only);
+SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int64_t ntiles_a,
+                       int prec);
+LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P);
+int upload_slot(uint8_t* base, const SlotLayout& L, const Prepared& P, int prec,
+                hipStream_t stream, std::vector<uint8_t>& img);
+int write_tables(uint8_t* dst, const std::vector<LpDev>& lps, hipStream_t stream,
+                 std::vector<uint8_t>& staging, const BatchDev** bd_out, int64_t* nwt,
+                 int64_t* nwa);
+int download_vec(const void* dptr, size_t count, int prec, hipStream_t stream, double* out);
+void fill_result(const Ctl& c, double seconds, opdhg_result* r);
+void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,
+                  std::vector<double>& dr, std::vector<double>& dc);
+std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t target, int lanes_fixed);
+Ctl initial_ctl(const Prepared& P);
+
+// A set of LPs launched together, with its captured launch sequence:
+// one evaluation step then `attempts` step attempts.
+struct Group {
+  hipStream_t stream = nullptr;      // caller's stream (replays, copies)
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
+  hipGraphExec_t exec = nullptr;
+  LaunchCfg cfg{};
+  int prec = 0;
+  int init(void* stream, int prec);
+  void set_grid(int64_t nwork_t, int64_t nwork_a, bool fixed);
+  int capture(int attempts_per_replay);
+  int launch_init();
+  int launch_primal_forced();
+  int replay();
+  void release();
+};
+
+int run_group(Group& grp, const std::vector<Ctl*>& d_ctls, std::vector<Ctl>& h_ctls,
+              Ctl* pinned, int64_t k_target, double time_limit, double* elapsed);
+
+}  // namespace opdhg

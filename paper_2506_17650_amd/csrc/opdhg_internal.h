@@ -1,0 +1,180 @@
+// Internal structures shared by the host driver and the HIP kernels.
+//
+// Device layout of one LP ("slot"): both CSR copies (A and A^T, int32 row
+// pointers and column indices, values in the compute precision V), the
+// iteration vectors in V, the rescaling diagonals in FP64, per-tile FP64
+// reduction partials, the tile tables, a control block (Ctl) and the
+// per-LP constants (DevParams). Everything sits in the caller's workspace.
+//
+// Double buffering: x, y, A x, and the running sums of x and y have two
+// copies; Ctl::cur names the current one. An attempt writes the other copy,
+// and accepting it flips Ctl::cur, so a rejected attempt leaves no trace.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace opdhg {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kPartStride = 32;    // doubles of reduction partials per tile (16 double-doubles)
+constexpr int kPowTab = 8192;      // host-computed step-rule factors for the first attempts
+constexpr int kGridCap = 4096;     // workgroups of a persistent launch
+
+// Status values (match OPDHG_STATUS_* of the public header).
+constexpr int kOptimal = 0;
+constexpr int kIterLimit = 1;
+constexpr int kTimeLimit = 2;
+constexpr int kNumError = 3;
+constexpr int kRunning = 4;
+
+// Per-LP constants, written once at upload.
+struct DevParams {
+  double tol;
+  double lr;
+  double floor;
+  double beta_suff, beta_nec, beta_art;
+  double pw_smoothing;
+  double step_growth, step_reduction;
+  double b_norm, c_norm;  // norms of the unscaled b and c
+  double c0;              // objective offset
+  int64_t max_iter;
+  int32_t phi;
+  int32_t normalize;
+  int32_t schedule;
+  int32_t eval_every;
+  int32_t max_retries;
+  int32_t pad;
+};
+
+// Per-LP control block: the scalar state of the iteration. Written by the
+// last tile of the dual kernel (step decision), of the evaluation kernel
+// (termination / restart decision), and by the host between launches.
+struct Ctl {
+  double eta;       // step size of the next attempt
+  double omega;     // primal weight
+  double w;         // sum of accepted step sizes of this restart period
+  double eta_acc;   // step size of the last accepted attempt
+  double g2;        // |c - A^T y|^2 of the last accepted attempt
+  double r2;        // |b - A x|^2 of the last accepted attempt
+  double gp2;       // |G^p|^2 of the last accepted attempt (unnormalized)
+  double gd2;       // |G^d|^2
+  double hp_norm;   // AdaGrad accumulators of the norm schedule
+  double hd_norm;
+  double anc_rp2, anc_rd2, anc_gap;  // KKT parts of the restart anchor
+  double prev_cand;                  // candidate's weighted KKT at the last evaluation
+  double restart_w;                  // w of the period a restart closes
+  double out_pobj, out_dobj, out_relp, out_reld, out_relg, out_rel;
+  double last_eta_bar;
+  int64_t k;         // accepted iterations
+  int64_t t;         // accepted iterations since the last restart
+  int64_t attempts;  // all attempts
+  int64_t restarts;
+  int64_t retries;   // rejections of the current iteration
+  int64_t k_limit;   // attempts pause when k reaches it (host-controlled)
+  int32_t status;
+  int32_t cur;           // current buffer (0 or 1)
+  int32_t need_eval;     // an evaluation is due before the next attempt
+  int32_t learn_pending; // the learner must apply the accepted gradients
+  int32_t restart_pending;
+  int32_t restart_avg;   // the restart point is the average
+  int32_t finalize_avg;  // terminal with the average: copy it into the current buffers
+  int32_t anchor_set;
+  int32_t which;         // 0 current, 1 average (returned iterate)
+  int32_t stop_request;  // host asks for a final evaluation (time limit)
+  int32_t cnt_dual;      // completion counters of the per-LP last-tile steps
+  int32_t cnt_eval;
+  int32_t cnt_learn;
+  int32_t cnt_apply;
+  int32_t pad0, pad1;
+};
+
+// Tile: rows [rb, re) of one CSR side. lanes > 0: row groups of `lanes`
+// threads; lanes == 0: one long row reduced by the whole workgroup.
+struct Tile {
+  int32_t rb, re, lanes, pad;
+};
+
+// One LP slot as the kernels see it (device pointers into the workspace).
+struct LpDev {
+  int32_t m, n;
+  int32_t ntiles_t, ntiles_a;  // tiles over A^T rows (n) and A rows (m)
+  const int32_t* rp_a;
+  const int32_t* ci_a;
+  const void* va_a;
+  const int32_t* rp_t;
+  const int32_t* ci_t;
+  const void* va_t;
+  const Tile* tiles_a;
+  const Tile* tiles_t;
+  // n-vectors (type V)
+  void* c;
+  void* l;
+  void* u;
+  void* T;
+  void* Hp;
+  void* Gp;
+  void* x[2];
+  void* xs[2];
+  void* xa;
+  // m-vectors (type V)
+  void* b;
+  void* S;
+  void* Hd;
+  void* Gd;
+  void* y[2];
+  void* ys[2];
+  void* ya;
+  void* Ax[2];
+  void* Axa;
+  // FP64 scaling diagonals and per-variable / per-row flags
+  const double* dr;
+  const double* dc;
+  const int8_t* sense;  // m: 0 '=', 1 '>='
+  const int8_t* bfin;   // n: bit 0 l finite, bit 1 u finite
+  double* part_t;       // ntiles_t * kPartStride
+  double* part_a;       // ntiles_a * kPartStride
+  const double* pow_tab;  // 2 * kPowTab: (j+1)^-reduction, then (j+1)^-growth, j = 1..kPowTab
+  Ctl* ctl;
+  const DevParams* prm;
+};
+
+// A set of LPs launched together. Work items are (lp, tile) pairs; the
+// kernels loop over them with a fixed grid so the set can change between
+// launches without new launch parameters.
+struct WorkItem {
+  int32_t lp, tile;
+};
+
+struct BatchDev {
+  const LpDev* lps;
+  const WorkItem* work_t;  // all A^T-side tiles of all LPs
+  const WorkItem* work_a;  // all A-side tiles
+  int32_t nwork_t;
+  int32_t nwork_a;
+  int32_t nlps;
+  int32_t pad;
+};
+
+// Host-side launch wrappers (kernels.hip). V is float or double.
+struct LaunchCfg {
+  const BatchDev* bd;  // device pointer
+  int grid_t;          // workgroups over work_t
+  int grid_a;          // workgroups over work_a
+  int grid_ta;         // workgroups over work_t + work_a
+};
+
+template <typename V>
+struct Kernels {
+  static int init_products(const LaunchCfg& c, void* stream);
+  static int primal(const LaunchCfg& c, void* stream, int force);
+  static int dual(const LaunchCfg& c, void* stream);
+  static int learn(const LaunchCfg& c, void* stream);
+  static int eval_t(const LaunchCfg& c, void* stream);
+  static int eval_a(const LaunchCfg& c, void* stream);
+  static int apply(const LaunchCfg& c, void* stream);
+};
+
+const char* device_error_string();
+
+}  // namespace opdhg

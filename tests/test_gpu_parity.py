@@ -1,0 +1,202 @@
+"""GPU path vs the FP64 oracle, through the C-ABI.
+
+Trace parity: in FP64 the GPU's iterates, preconditioners, step sizes and
+primal weights after each of the first 200 accepted iterations match the
+oracle's to 1e-10 relative (|a-b| / |b|, 0 when both are 0), with the same
+attempt and restart counts at every k. Final parity: the returned
+objective, x and y match to 1e-6 relative, with the same status and
+iteration count.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.params import default_params
+from lpgen import LP, config_lp, tiny_lp
+
+pytestmark = pytest.mark.gpu
+
+TRACE_TOL = 1e-10
+FINAL_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_17650_amd as P
+    P.load()
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    nb = np.linalg.norm(b)
+    d = np.linalg.norm(a - b)
+    if nb == 0.0:
+        return 0.0 if d == 0.0 else math.inf
+    return d / nb
+
+
+def lib_params(P, op, **kw):
+    """Library parameters equal to oracle parameters op."""
+    return P.opdhg_default_params(
+        tol=op.tol, max_iter=op.max_iter, lr=op.lr, phi=op.phi, normalize=int(op.normalize),
+        schedule=op.schedule, precond_floor=op.precond_floor, ruiz_iters=op.ruiz_iters,
+        pc_beta=op.pc_beta, eval_every=op.eval_every, beta_suff=op.beta_suff,
+        beta_nec=op.beta_nec, beta_art=op.beta_art, pw_smoothing=op.pw_smoothing,
+        step_growth=op.step_growth, step_reduction=op.step_reduction,
+        max_step_retries=op.max_step_retries, **kw)
+
+
+def check_trace(P, lp, op, K=200, **kw):
+    ref = oracle.solve(lp, op, trace=K, stop_k=K)
+    tr = {e.k: e for e in ref.trace}
+    worst = 0.0
+    with P.Session(lp, lib_params(P, op, **kw)) as s:
+        for k in range(0, K + 1):
+            if k not in tr:
+                break  # the oracle finished earlier
+            s.run(k)
+            x, y, T, S, st = s.state()
+            e = tr[k]
+            assert st.k == k, (k, st.k)
+            assert st.attempts == e.attempts, ("attempts", k, st.attempts, e.attempts)
+            assert st.restarts == e.restarts, ("restarts", k, st.restarts, e.restarts)
+            errs = {"x": rel(x, e.x), "y": rel(y, e.y), "T": rel(T, e.T), "S": rel(S, e.S),
+                    "eta": abs(st.eta - e.eta) / abs(e.eta),
+                    "omega": abs(st.omega - e.omega) / abs(e.omega)}
+            for name, v in errs.items():
+                assert v <= TRACE_TOL, (k, name, v)
+            worst = max(worst, max(errs.values()))
+    return worst
+
+
+def check_final(P, lp, op, **kw):
+    ref = oracle.solve(lp, op)
+    x, y, r = P.opdhg_solve(lp, lib_params(P, op, **kw))
+    assert r.status == ref.status, (r.status, ref.status)
+    assert r.iterations == ref.iterations and r.attempts == ref.attempts
+    assert r.restarts == ref.restarts
+    assert abs(r.primal_obj - ref.primal_obj) <= FINAL_TOL * abs(ref.primal_obj)
+    assert rel(x, ref.x) <= FINAL_TOL and rel(y, ref.y) <= FINAL_TOL
+    assert abs(r.rel_kkt - ref.rel_kkt) <= 1e-6 * max(ref.rel_kkt, 1e-12) + 1e-14
+    return ref, r
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_cfg0_final_parity_fp64(P, seed):
+    lp = config_lp("cfg0", seed=seed)
+    _say(f"[cfg0 final] seed={seed}")
+    ref, r = check_final(P, lp, default_params(max_iter=20000))
+    assert r.status == 0 and r.rel_kkt <= 1e-4
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cfg0_trace_parity_plain(P, seed):
+    _say(f"[cfg0 trace lr=0] seed={seed}")
+    check_trace(P, config_lp("cfg0", seed=seed), default_params(max_iter=20000))
+
+
+@pytest.mark.parametrize("lr,phi,norm", [(1e-2, 1, True), (1e-2, 20, True), (5e-2, 1, False),
+                                         (5e-2, 20, False)])
+def test_cfg0_trace_parity_online(P, lr, phi, norm):
+    _say(f"[cfg0 trace] lr={lr} phi={phi} normalize={norm}")
+    check_trace(P, config_lp("cfg0", seed=4), default_params(lr=lr, phi=phi, normalize=norm))
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_trace_parity_other_schedules(P, schedule):
+    _say(f"[cfg0 trace] schedule={schedule}")
+    check_trace(P, config_lp("cfg0", seed=6),
+                default_params(lr=1e-3, phi=5, schedule=schedule), K=120)
+
+
+def test_cfg1_small_trace_parity(P):
+    # power-law columns (long rows in A^T), free and one-sided bounds, row scales
+    lp = config_lp("cfg1", scale=0.05)
+    _say(f"[cfg1x0.05 trace] m={lp.m} n={lp.n} nnz={lp.nnz}")
+    check_trace(P, lp, default_params(lr=1e-2, phi=20), K=200)
+
+
+def test_cfg1_small_final_parity(P):
+    lp = config_lp("cfg1", scale=0.02)
+    _say(f"[cfg1x0.02 final] m={lp.m} n={lp.n}")
+    check_final(P, lp, default_params(max_iter=40000))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tiny_lps(P, seed):
+    lp = tiny_lp(seed, 3, 5, m_eq=1)
+    _say(f"[tiny] seed={seed}")
+    check_final(P, lp, default_params(tol=1e-8, max_iter=50000))
+
+
+def test_no_rows(P):
+    lp = LP(m=0, n=3, row_ptr=np.zeros(1, np.int64), col_idx=np.zeros(0, np.int32),
+            val=np.zeros(0), b=np.zeros(0), sense=np.zeros(0, np.int8),
+            c=np.array([1.0, -2.0, 0.5]), l=np.array([0.0, -1.0, 2.0]),
+            u=np.array([4.0, 3.0, 5.0]), obj_offset=1.5)
+    _say("[m=0]")
+    ref, r = check_final(P, lp, default_params(tol=1e-9))
+    assert r.status == 0
+
+
+def test_iteration_limit_and_retries(P):
+    lp = config_lp("cfg0", seed=1)
+    _say("[limits]")
+    ref, r = check_final(P, lp, default_params(max_iter=100))
+    assert r.status == 1 and r.iterations == 100
+
+
+def test_long_rows_whole_workgroup(P):
+    # tile_nnz small enough that the dense-ish columns go to whole-workgroup tiles
+    lp = config_lp("cfg1", scale=0.05)
+    _say("[long-row tiles]")
+    op = default_params(lr=1e-2)
+    check_trace(P, lp, op, K=80, tile_nnz=512)
+    check_trace(P, lp, op, K=80, tile_nnz=64, lanes=4)
+
+
+def test_run_twice_bit_identical(P):
+    lp = config_lp("cfg1", scale=0.03)
+    _say("[determinism]")
+    p = P.opdhg_default_params(max_iter=3000, lr=1e-2)
+    a = P.opdhg_solve(lp, p)
+    b = P.opdhg_solve(lp, p)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2].iterations == b[2].iterations
+
+
+def test_batch_equals_solo(P):
+    lps = [config_lp("cfg0", seed=s) for s in range(4)] + [config_lp("cfg3", index=i, scale=0.3)
+                                                          for i in range(4)]
+    _say(f"[batch] {len(lps)} LPs")
+    p = P.opdhg_default_params(max_iter=5000, lr=1e-2)
+    out = P.opdhg_solve_batch(lps, p)
+    for lp, (x, y, r) in zip(lps, out):
+        xs, ys, rs = P.opdhg_solve(lp, p)
+        assert r.status == rs.status and r.iterations == rs.iterations
+        assert np.array_equal(x, xs) and np.array_equal(y, ys)
+
+
+def test_fp32_mode_error_reported(P):
+    lp = config_lp("cfg0", seed=3)
+    _say("[fp32]")
+    ref = oracle.solve(lp, default_params(max_iter=20000))
+    x, y, r = P.opdhg_solve(lp, P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=20000))
+    assert r.status == 0 and r.rel_kkt <= 1e-4
+    err_obj = abs(r.primal_obj - ref.primal_obj) / abs(ref.primal_obj)
+    _say(f"  fp32 objective rel err {err_obj:.3e}, y rel err {rel(y, ref.y):.3e}")
+    assert err_obj <= 1e-3
