@@ -115,7 +115,8 @@ typedef struct opdhg_params {
   double step_growth;    /* exponent of the step growth factor */
   double step_reduction; /* exponent of the step reduction factor */
   int32_t tile_nnz;      /* SpMV tile target in nonzeros; 0 picks automatically */
-  int32_t lanes;         /* lanes per row in SpMV row groups; 0 picks per tile */
+  int32_t lanes;         /* lanes per row in SpMV tiles; 0 picks per tile */
+  int32_t workgroups;    /* workgroups per sparse-product launch; 0 picks automatically */
 } opdhg_params;
 
 typedef struct opdhg_result {
@@ -204,6 +205,12 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
  * for the next call, so a paused state is the state after k_target
  * iterations and before the evaluation at the top of the next one. */
 int opdhg_session_run(opdhg_session* s, int64_t k_target);
+/* Enqueue exactly `replays` launch sequences (one evaluation step plus
+ * eval_every attempts each) on the session's stream and wait for them,
+ * without reading the state in between; limits and termination still
+ * apply on the device (finished LPs make the remaining launches no-ops).
+ * For timing the iteration at a fixed amount of work. */
+int opdhg_session_replay(opdhg_session* s, int replays);
 /* Scaled-space iterate and preconditioners (FP64 host arrays; any pointer
  * may be NULL to skip that vector): x[n], y[m], T[n], Sigma[m]. */
 int opdhg_session_state(opdhg_session* s, double* x, double* y, double* T, double* Sigma,

@@ -62,7 +62,7 @@ class opdhg_params(ctypes.Structure):
         ("pc_beta", c_dbl), ("eval_every", c_i32), ("max_step_retries", c_i32),
         ("beta_suff", c_dbl), ("beta_nec", c_dbl), ("beta_art", c_dbl),
         ("pw_smoothing", c_dbl), ("step_growth", c_dbl), ("step_reduction", c_dbl),
-        ("tile_nnz", c_i32), ("lanes", c_i32),
+        ("tile_nnz", c_i32), ("lanes", c_i32), ("workgroups", c_i32),
     ]
 
 
@@ -116,6 +116,7 @@ SIGNATURES = {
     "opdhg_session_create": (c_i32, [_p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                                      ctypes.c_void_p, _p(ctypes.c_void_p)]),
     "opdhg_session_run": (c_i32, [ctypes.c_void_p, c_i64]),
+    "opdhg_session_replay": (c_i32, [ctypes.c_void_p, c_i32]),
     "opdhg_session_state": (c_i32, [ctypes.c_void_p, _p(c_dbl), _p(c_dbl), _p(c_dbl),
                                     _p(c_dbl), _p(opdhg_state)]),
     "opdhg_session_result": (c_i32, [ctypes.c_void_p, _p(c_dbl), _p(c_dbl),
@@ -150,13 +151,20 @@ class OpdhgError(RuntimeError):
 
 
 def load() -> ctypes.CDLL:
-    """Load libopdhg.so (built in-tree); raise if it is missing."""
+    """Load libopdhg.so (built in-tree); raise if it is missing.
+
+    torch is imported first: it ships its own HIP runtime under the same
+    soname, and the library must resolve to that copy so that torch's
+    device pointers and stream handles are valid in the library's runtime
+    (two HIP runtimes in one process do not share devices).
+    """
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2506_17650_amd.build`")
+    import torch  # noqa: F401  (binds the process to torch's HIP runtime)
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name, None)
@@ -339,6 +347,9 @@ class Session:
 
     def run(self, k_target: int = -1) -> None:
         _check(load().opdhg_session_run(self._h, int(k_target)))
+
+    def replay(self, replays: int) -> None:
+        _check(load().opdhg_session_replay(self._h, int(replays)))
 
     def state(self):
         n, m = self._a.n, self._a.m

@@ -110,6 +110,8 @@ int validate_params(const opdhg_params* p) {
   if (p->tile_nnz < 0) return fail(OPDHG_ERR_INVALID_ARGUMENT, "tile_nnz must be >= 0");
   if (p->lanes < 0 || p->lanes > 64 || (p->lanes & (p->lanes - 1)) != 0)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "lanes must be 0 or a power of two <= 64");
+  if (p->workgroups < 0 || p->workgroups > kMaxGrid)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "workgroups must be in [0, 65536]");
   return OPDHG_OK;
 }
 
@@ -193,52 +195,73 @@ void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<d
 }
 
 // ---------------------------------------------------------------------------
-// tiling
+// row classes and tiling
+//
+// On the device the rows of each side are relabelled so that rows of like
+// length sit together: long rows (more than 256 nonzeros) first, then
+// medium (33 to 256), then short, keeping the original order inside each
+// class. Variables follow the order of the A^T rows and constraints the
+// order of the A rows. The relabelling is a permutation of the LP, and
+// every FP64 sum is rounded once from its exact value, so results do not
+// depend on it; it only keeps one long row from holding up a workgroup of
+// short ones.
 // ---------------------------------------------------------------------------
 
-static int lanes_for(double mean_len) {
+static int row_class(int64_t len) { return len > 256 ? 0 : (len > 32 ? 1 : 2); }
+
+// perm[new] = old, stable within each class; class_end[c] = end of class c.
+static void class_order(const std::vector<int64_t>& len, std::vector<int32_t>& perm,
+                        int64_t class_end[3]) {
+  const int64_t rows = (int64_t)len.size();
+  int64_t cnt[3] = {0, 0, 0};
+  for (int64_t i = 0; i < rows; ++i) cnt[row_class(len[i])]++;
+  int64_t start[3] = {0, cnt[0], cnt[0] + cnt[1]};
+  class_end[0] = cnt[0];
+  class_end[1] = cnt[0] + cnt[1];
+  class_end[2] = rows;
+  perm.resize(rows);
+  for (int64_t i = 0; i < rows; ++i) perm[start[row_class(len[i])]++] = (int32_t)i;
+}
+
+// Lanes per row for a stream tile whose longest row has max_len nonzeros:
+// enough that each lane sums at most 16 products, at most 64.
+static int lanes_for(int64_t max_len) {
   int L = 1;
-  while (L < 64 && L * 1.5 < mean_len) L <<= 1;
+  while (L < 64 && max_len > 16 * L) L <<= 1;
   return L;
 }
 
-// Rows [0, rows) of a CSR side into tiles: rows of at least `long_len`
-// nonzeros get a workgroup each; other rows are packed greedily up to
-// `target` weight (nonzeros plus a per-row charge for the epilogue).
-std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t target, int lanes_fixed) {
+// Rows of one CSR side into tiles. A row with more than `cap` nonzeros is a
+// tile of its own (lanes 0); other rows are packed greedily into stream
+// tiles of at most `cap` nonzeros and kBlock / lanes rows.
+std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t cap, int lanes_fixed) {
   std::vector<Tile> tiles;
-  const int64_t long_len = std::max<int64_t>(1024, target);
-  const int64_t row_w = 4;
-  const int64_t max_rows = 16384;
   int64_t i = 0;
   while (i < rows) {
     const int64_t len = rp[i + 1] - rp[i];
-    if (len >= long_len) {
-      tiles.push_back(Tile{(int32_t)i, (int32_t)(i + 1), 0, 0});
+    if (len > cap) {
+      tiles.push_back(Tile{(int32_t)i, (int32_t)(i + 1), rp[i], rp[i + 1], 0, 0});
       ++i;
       continue;
     }
     const int64_t start = i;
-    int64_t weight = 0;
-    while (i < rows && i - start < max_rows) {
+    int64_t nz = 0, max_len = 0;
+    int L = 1;
+    while (i < rows) {
       const int64_t l = rp[i + 1] - rp[i];
-      if (l >= long_len) break;
-      if (i > start && weight + l + row_w > target) break;
-      weight += l + row_w;
+      if (l > cap) break;
+      const int64_t ml = std::max(max_len, l);
+      const int Ln = lanes_fixed > 0 ? lanes_fixed : lanes_for(ml);
+      if (i > start && (nz + l > cap || i - start + 1 > kBlock / Ln)) break;
+      nz += l;
+      max_len = ml;
+      L = Ln;
       ++i;
     }
-    const double mean = double(rp[i] - rp[start]) / double(i - start);
-    const int L = lanes_fixed > 0 ? lanes_fixed : lanes_for(mean);
-    tiles.push_back(Tile{(int32_t)start, (int32_t)i, L, 0});
+    tiles.push_back(Tile{(int32_t)start, (int32_t)i, rp[start], rp[i], L, 0});
   }
-  if (tiles.empty()) tiles.push_back(Tile{0, 0, 1, 0});
+  if (tiles.empty()) tiles.push_back(Tile{0, 0, 0, 0, 1, 0});
   return tiles;
-}
-
-int64_t auto_tile_target(int64_t nnz, int64_t rows) {
-  const int64_t weight = nnz + 4 * rows;
-  int64_t t = weight / 2048;
-  return std::min<int64_t>(std::max<int64_t>(t, 512), 32768);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,51 +273,79 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.n = lp->n;
   out.nnz = lp->nnz;
   const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
-  out.rp_a.resize(m + 1);
-  for (int64_t i = 0; i <= m; ++i) out.rp_a[i] = (int32_t)lp->row_ptr[i];
-  // transpose structure: counting sort by column, rows ascending within a column
+  // row lengths of A and of A^T (= column counts), device order by class
+  std::vector<int64_t> len_a(m), len_t(n, 0);
+  for (int64_t i = 0; i < m; ++i) len_a[i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
+  for (int64_t k = 0; k < nnz; ++k) len_t[lp->col_idx[k]]++;
+  int64_t cend_a[3], cend_t[3];
+  class_order(len_a, out.perm_a, cend_a);
+  class_order(len_t, out.perm_t, cend_t);
+  (void)cend_a;
+  (void)cend_t;
+  out.rp_a.assign(m + 1, 0);
+  for (int64_t i = 0; i < m; ++i) out.rp_a[i + 1] = out.rp_a[i] + (int32_t)len_a[out.perm_a[i]];
   out.rp_t.assign(n + 1, 0);
-  for (int64_t k = 0; k < nnz; ++k) out.rp_t[lp->col_idx[k] + 1]++;
-  for (int64_t j = 0; j < n; ++j) out.rp_t[j + 1] += out.rp_t[j];
-  const int64_t target_a = p->tile_nnz > 0 ? p->tile_nnz : auto_tile_target(nnz, m);
-  const int64_t target_t = p->tile_nnz > 0 ? p->tile_nnz : auto_tile_target(nnz, n);
-  out.tiles_a = build_tiles(out.rp_a.data(), m, target_a, p->lanes);
-  out.tiles_t = build_tiles(out.rp_t.data(), n, target_t, p->lanes);
+  for (int64_t j = 0; j < n; ++j) out.rp_t[j + 1] = out.rp_t[j] + (int32_t)len_t[out.perm_t[j]];
+  const int64_t cap = p->tile_nnz > 0 ? std::min<int64_t>(p->tile_nnz, kTileCap) : kTileCap;
+  out.tiles_a = build_tiles(out.rp_a.data(), m, cap, p->lanes);
+  out.tiles_t = build_tiles(out.rp_t.data(), n, cap, p->lanes);
   if (structure_only) return OPDHG_OK;
 
-  out.ci_a.assign(lp->col_idx, lp->col_idx + nnz);
+  std::vector<int32_t> inv_a(m), inv_t(n);
+  for (int64_t i = 0; i < m; ++i) inv_a[out.perm_a[i]] = (int32_t)i;
+  for (int64_t j = 0; j < n; ++j) inv_t[out.perm_t[j]] = (int32_t)j;
   std::vector<double> sval;
   rescale_host(lp, p->ruiz_iters, p->pc_beta, sval, out.dr, out.dc);
-  out.va_a = sval;
+  // A in device order: row i' is original row perm_a[i'], columns relabelled
+  out.ci_a.resize(nnz);
+  out.va_a.resize(nnz);
+  for (int64_t i2 = 0; i2 < m; ++i2) {
+    const int64_t i = out.perm_a[i2];
+    int64_t pos = out.rp_a[i2];
+    for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k, ++pos) {
+      out.ci_a[pos] = inv_t[lp->col_idx[k]];
+      out.va_a[pos] = sval[k];
+    }
+  }
+  // A^T in device order: row j' is original column perm_t[j']; entries in
+  // ascending original row, labelled with device row indices
   out.ci_t.resize(nnz);
   out.va_t.resize(nnz);
   {
-    std::vector<int32_t> next(out.rp_t.begin(), out.rp_t.end() - 1);
+    std::vector<int32_t> next(n);
+    for (int64_t j = 0; j < n; ++j) next[j] = out.rp_t[inv_t[j]];
     for (int64_t i = 0; i < m; ++i)
       for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
         const int32_t pos = next[lp->col_idx[k]]++;
-        out.ci_t[pos] = (int32_t)i;
+        out.ci_t[pos] = inv_a[i];
         out.va_t[pos] = sval[k];
       }
   }
   out.b.resize(m);
   out.sense.resize(m);
-  for (int64_t i = 0; i < m; ++i) {
-    out.b[i] = out.dr[i] * lp->b[i];
-    out.sense[i] = lp->row_sense[i];
+  out.dr_dev.resize(m);
+
+  for (int64_t i2 = 0; i2 < m; ++i2) {
+    const int64_t i = out.perm_a[i2];
+    out.b[i2] = out.dr[i] * lp->b[i];
+    out.sense[i2] = lp->row_sense[i];
+    out.dr_dev[i2] = out.dr[i];
   }
   out.c.resize(n);
   out.l.resize(n);
   out.u.resize(n);
   out.bfin.resize(n);
   out.x0.resize(n);
-  for (int64_t j = 0; j < n; ++j) {
-    out.c[j] = out.dc[j] * lp->c[j];
-    out.l[j] = lp->l[j] / out.dc[j];
-    out.u[j] = lp->u[j] / out.dc[j];
-    out.bfin[j] = (int8_t)((std::isfinite(lp->l[j]) ? 1 : 0) | (std::isfinite(lp->u[j]) ? 2 : 0));
+  out.dc_dev.resize(n);
+  for (int64_t j2 = 0; j2 < n; ++j2) {
+    const int64_t j = out.perm_t[j2];
+    out.c[j2] = out.dc[j] * lp->c[j];
+    out.l[j2] = lp->l[j] / out.dc[j];
+    out.u[j2] = lp->u[j] / out.dc[j];
+    out.bfin[j2] = (int8_t)((std::isfinite(lp->l[j]) ? 1 : 0) | (std::isfinite(lp->u[j]) ? 2 : 0));
     const double z = 0.0;
-    out.x0[j] = std::min(std::max(z, out.l[j]), out.u[j]);
+    out.x0[j2] = std::min(std::max(z, out.l[j2]), out.u[j2]);
+    out.dc_dev[j2] = out.dc[j];
   }
   double amax = 0.0;
   for (int64_t k = 0; k < nnz; ++k) amax = std::max(amax, std::fabs(sval[k]));
@@ -328,6 +379,17 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   d.eval_every = p->eval_every;
   d.max_retries = p->max_step_retries;
   return OPDHG_OK;
+}
+
+// Device-order vector back to the caller's order, scaled by `scale`
+// (the unscaling diagonal) when given.
+void unpermute(const double* dev, const std::vector<int32_t>& perm, const double* scale,
+               double* out) {
+  const size_t n = perm.size();
+  for (size_t i = 0; i < n; ++i) {
+    const int32_t o = perm[i];
+    out[o] = scale ? dev[i] * scale[o] : dev[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -425,6 +487,7 @@ Ctl initial_ctl(const Prepared& P) {
   c.k_limit = std::numeric_limits<int64_t>::max();
   c.status = kRunning;
   c.need_eval = 1;
+  c.learn_now = P.prm.lr > 0.0 ? 1 : 0;
   return c;
 }
 
@@ -451,12 +514,12 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
   put_const<V>(img, L.vn[3], P.n, 1.0);
   put_vec<V>(img, L.vn[6], P.x0);
   put_vec<V>(img, L.vn[10], P.x0);
-  std::memcpy(img.data() + L.dc, P.dc.data(), 8 * P.dc.size());
+  std::memcpy(img.data() + L.dc, P.dc_dev.data(), 8 * P.dc_dev.size());
   std::memcpy(img.data() + L.bfin, P.bfin.data(), P.bfin.size());
   // m-vectors: b S Hd Gd y0 y1 ys0 ys1 ya Ax0 Ax1 Axa
   put_vec<V>(img, L.vm[0], P.b);
   put_const<V>(img, L.vm[1], P.m, 1.0);
-  std::memcpy(img.data() + L.dr, P.dr.data(), 8 * P.dr.size());
+  std::memcpy(img.data() + L.dr, P.dr_dev.data(), 8 * P.dr_dev.size());
   if (P.m) std::memcpy(img.data() + L.sense, P.sense.data(), P.sense.size());
 }
 
@@ -479,11 +542,12 @@ int Group::capture(int attempts_per_replay) {
     using V = decltype(tag);
     rc |= Kernels<V>::eval_t(cfg, cap_stream);
     rc |= Kernels<V>::eval_a(cfg, cap_stream);
+    rc |= Kernels<V>::eval_decide(cfg, cap_stream);
     rc |= Kernels<V>::apply(cfg, cap_stream);
     for (int a = 0; a < attempts_per_replay; ++a) {
       rc |= Kernels<V>::primal(cfg, cap_stream, 0);
       rc |= Kernels<V>::dual(cfg, cap_stream);
-      rc |= Kernels<V>::learn(cfg, cap_stream);
+      rc |= Kernels<V>::decide(cfg, cap_stream);
     }
   };
   if (prec == OPDHG_FP32) K(float{});
@@ -514,11 +578,9 @@ void Group::release() {
   cap_stream = nullptr;
 }
 
-void Group::set_grid(int64_t nwork_t, int64_t nwork_a, bool fixed) {
-  auto g = [&](int64_t w) { return (int)std::max<int64_t>(1, fixed ? kGridCap : std::min<int64_t>(w, kGridCap)); };
-  cfg.grid_t = g(nwork_t);
-  cfg.grid_a = g(nwork_a);
-  cfg.grid_ta = g(nwork_t + nwork_a);
+int Group::launch_learn_flush() {
+  if (prec == OPDHG_FP32) return Kernels<float>::learn_flush(cfg, stream);
+  return Kernels<double>::learn_flush(cfg, stream);
 }
 
 int Group::launch_init() {
@@ -553,42 +615,96 @@ struct SessionImpl {
   int replays = 0;
 };
 
-static size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a) {
-  return align_up(sizeof(LpDev) * nlps) + align_up(sizeof(WorkItem) * std::max<int64_t>(nwork_t, 1)) +
-         align_up(sizeof(WorkItem) * std::max<int64_t>(nwork_a, 1)) + align_up(sizeof(BatchDev));
+// Chunking of a work list of n items over at most `cap` workgroups.
+static void chunking(int64_t n, int64_t cap, int* grid, int* chunk) {
+  const int64_t g0 = std::max<int64_t>(1, std::min<int64_t>(n, cap));
+  const int64_t c = std::max<int64_t>(1, (n + g0 - 1) / g0);
+  *chunk = (int)c;
+  *grid = (int)std::max<int64_t>(1, (n + c - 1) / c);
 }
 
-// Write the tables for a list of LPs into device memory at `dst`.
-int write_tables(uint8_t* dst, const std::vector<LpDev>& lps, hipStream_t stream,
-                 std::vector<uint8_t>& staging, const BatchDev** bd_out, int64_t* nwt,
-                 int64_t* nwa) {
-  std::vector<WorkItem> wt, wa;
+static int64_t grid_cap(const opdhg_params* p) {
+  return p->workgroups > 0 ? p->workgroups : kGridCap;
+}
+
+static size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64_t cap) {
+  int gt, ct, ga, ca;
+  chunking(nwork_t, cap, &gt, &ct);
+  chunking(nwork_a, cap, &ga, &ca);
+  return align_up(sizeof(LpDev) * std::max<int64_t>(nlps, 1)) +
+         align_up(sizeof(WorkItem) * (size_t)gt * ct) +
+         align_up(sizeof(WorkItem) * (size_t)ga * ca) + align_up(sizeof(Counts));
+}
+
+// Items of one side for all LPs, chunked: fills slot / last and each LP's
+// slot count.
+static void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps,
+                       bool tside, int64_t cap, int* grid, int* chunk,
+                       std::vector<WorkItem>& out) {
+  out.clear();
+  std::vector<std::pair<int64_t, int64_t>> range(lps.size());
   for (size_t i = 0; i < lps.size(); ++i) {
-    for (int t = 0; t < lps[i].ntiles_t; ++t) wt.push_back(WorkItem{(int32_t)i, t});
-    for (int t = 0; t < lps[i].ntiles_a; ++t) wa.push_back(WorkItem{(int32_t)i, t});
+    const std::vector<Tile>& tiles = tside ? preps[i]->tiles_t : preps[i]->tiles_a;
+    range[i].first = (int64_t)out.size();
+    for (size_t t = 0; t < tiles.size(); ++t) {
+      const Tile& tl = tiles[t];
+      out.push_back(WorkItem{lps[i].ctl, (int32_t)i, (int32_t)t, tl.rb, tl.re, tl.s, tl.e,
+                             tl.lanes, 0, 0, 0});
+    }
+    range[i].second = (int64_t)out.size();
+  }
+  const int64_t n = (int64_t)out.size();
+  chunking(n, cap, grid, chunk);
+  const int64_t C = *chunk;
+  for (size_t i = 0; i < lps.size(); ++i) {
+    const int64_t s = range[i].first, e = range[i].second;
+    const int64_t first_wg = s / C;
+    for (int64_t q = s; q < e; ++q) {
+      out[q].slot = (int32_t)(q / C - first_wg);
+      out[q].last = (q == e - 1 || (q + 1) % C == 0) ? 1 : 0;
+    }
+    const int32_t nslot = e > s ? (int32_t)((e - 1) / C - first_wg + 1) : 0;
+    if (tside) lps[i].nslot_t = nslot;
+    else lps[i].nslot_a = nslot;
+  }
+  const WorkItem pad{nullptr, -1, 0, 0, 0, 0, 0, 1, 0, 0, 0};
+  out.resize((size_t)(*grid) * (*chunk), pad);
+}
+
+// Write the tables for a list of LPs into device memory at `dst` and point
+// cfg at them.
+int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
+                 const std::vector<const Prepared*>& preps, int64_t cap, hipStream_t stream,
+                 std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa) {
+  std::vector<LpDev> lps(lps_in);
+  std::vector<WorkItem> wt, wa;
+  side_items(lps, preps, true, cap, &cfg->grid_t, &cfg->chunk_t, wt);
+  side_items(lps, preps, false, cap, &cfg->grid_a, &cfg->chunk_a, wa);
+  int64_t n_t = 0, n_a = 0;
+  for (const Prepared* P : preps) {
+    n_t += (int64_t)P->tiles_t.size();
+    n_a += (int64_t)P->tiles_a.size();
   }
   const size_t o_lps = 0;
-  const size_t o_wt = o_lps + align_up(sizeof(LpDev) * lps.size());
-  const size_t o_wa = o_wt + align_up(sizeof(WorkItem) * std::max<size_t>(wt.size(), 1));
-  const size_t o_bd = o_wa + align_up(sizeof(WorkItem) * std::max<size_t>(wa.size(), 1));
-  const size_t total = o_bd + align_up(sizeof(BatchDev));
+  const size_t o_wt = o_lps + align_up(sizeof(LpDev) * std::max<size_t>(lps.size(), 1));
+  const size_t o_wa = o_wt + align_up(sizeof(WorkItem) * wt.size());
+  const size_t o_cn = o_wa + align_up(sizeof(WorkItem) * wa.size());
+  const size_t total = o_cn + align_up(sizeof(Counts));
   staging.assign(total, 0);
   if (!lps.empty()) std::memcpy(staging.data() + o_lps, lps.data(), sizeof(LpDev) * lps.size());
-  if (!wt.empty()) std::memcpy(staging.data() + o_wt, wt.data(), sizeof(WorkItem) * wt.size());
-  if (!wa.empty()) std::memcpy(staging.data() + o_wa, wa.data(), sizeof(WorkItem) * wa.size());
-  BatchDev bd;
-  bd.lps = reinterpret_cast<const LpDev*>(dst + o_lps);
-  bd.work_t = reinterpret_cast<const WorkItem*>(dst + o_wt);
-  bd.work_a = reinterpret_cast<const WorkItem*>(dst + o_wa);
-  bd.nwork_t = (int32_t)wt.size();
-  bd.nwork_a = (int32_t)wa.size();
-  bd.nlps = (int32_t)lps.size();
-  bd.pad = 0;
-  std::memcpy(staging.data() + o_bd, &bd, sizeof(bd));
+  std::memcpy(staging.data() + o_wt, wt.data(), sizeof(WorkItem) * wt.size());
+  std::memcpy(staging.data() + o_wa, wa.data(), sizeof(WorkItem) * wa.size());
+  Counts cn{(int32_t)n_t, (int32_t)n_a, (int32_t)lps.size(), 0};
+  std::memcpy(staging.data() + o_cn, &cn, sizeof(cn));
   HIP_TRY(hipMemcpyAsync(dst, staging.data(), total, hipMemcpyHostToDevice, stream));
-  *bd_out = reinterpret_cast<const BatchDev*>(dst + o_bd);
-  *nwt = (int64_t)wt.size();
-  *nwa = (int64_t)wa.size();
+  cfg->lps = reinterpret_cast<const LpDev*>(dst + o_lps);
+  cfg->work_t = reinterpret_cast<const WorkItem*>(dst + o_wt);
+  cfg->work_a = reinterpret_cast<const WorkItem*>(dst + o_wa);
+  cfg->counts = reinterpret_cast<const Counts*>(dst + o_cn);
+  cfg->grid_ta = std::max(cfg->grid_t, cfg->grid_a);
+  cfg->grid_lp = (int)std::max<size_t>(1, std::min<size_t>(lps.size(), kGridCap));
+  *nwt = n_t;
+  *nwa = n_a;
   return OPDHG_OK;
 }
 
@@ -743,6 +859,7 @@ void opdhg_default_params(opdhg_params* p) {
   p->step_reduction = 0.3;
   p->tile_nnz = 0;
   p->lanes = 0;
+  p->workgroups = 0;
 }
 
 int opdhg_validate(const opdhg_lp* lp) { return validate_lp(lp); }
@@ -755,7 +872,7 @@ int opdhg_workspace_bytes(const opdhg_lp* lp, const opdhg_params* p, size_t* byt
   Prepared P;
   prepare(lp, p, P, true);
   SlotLayout L = slot_layout(P.m, P.n, P.nnz, P.tiles_t.size(), P.tiles_a.size(), p->precision);
-  *bytes = L.total + tables_bytes(1, P.tiles_t.size(), P.tiles_a.size());
+  *bytes = L.total + tables_bytes(1, P.tiles_t.size(), P.tiles_a.size(), grid_cap(p));
   return OPDHG_OK;
 }
 
@@ -784,7 +901,8 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
   SessionImpl& S = s->impl;
   if ((rc = prepare(lp, p, S.P, false))) return rc;
   S.L = slot_layout(S.P.m, S.P.n, S.P.nnz, S.P.tiles_t.size(), S.P.tiles_a.size(), p->precision);
-  const size_t need = S.L.total + tables_bytes(1, S.P.tiles_t.size(), S.P.tiles_a.size());
+  const size_t need =
+      S.L.total + tables_bytes(1, S.P.tiles_t.size(), S.P.tiles_a.size(), grid_cap(p));
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL,
                 "workspace needs " + std::to_string(need) + " bytes");
@@ -797,9 +915,9 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
   S.d_tables = S.ws + S.L.total;
   std::vector<uint8_t> staging;
   int64_t nwt = 0, nwa = 0;
-  if ((rc = write_tables(S.d_tables, {S.lpd}, S.grp.stream, staging, &S.grp.cfg.bd, &nwt, &nwa)))
+  if ((rc = write_tables(S.d_tables, {S.lpd}, {&S.P}, grid_cap(p), S.grp.stream, staging,
+                         &S.grp.cfg, &nwt, &nwa)))
     return rc;
-  S.grp.set_grid(nwt, nwa, false);
   if ((rc = S.grp.launch_init())) return fail(OPDHG_ERR_DEVICE, device_error_string());
   HIP_TRY(hipStreamSynchronize(S.grp.stream));
   if ((rc = S.grp.capture(std::max(1, p->eval_every)))) return rc;
@@ -816,6 +934,23 @@ int opdhg_session_run(opdhg_session* s, int64_t k_target) {
   return run_group(S.grp, ctls, h, S.h_ctl, k_target, S.time_limit - S.elapsed, &S.elapsed);
 }
 
+int opdhg_session_replay(opdhg_session* s, int replays) {
+  if (!s || replays < 0) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  SessionImpl& S = s->impl;
+  const int64_t unlimited = std::numeric_limits<int64_t>::max();
+  HIP_TRY(hipMemcpyAsync(&S.lpd.ctl->k_limit, &unlimited, sizeof(unlimited),
+                         hipMemcpyHostToDevice, S.grp.stream));
+  HIP_TRY(hipStreamSynchronize(S.grp.stream));
+  auto t0 = std::chrono::steady_clock::now();
+  for (int r = 0; r < replays; ++r) {
+    int rc = S.grp.replay();
+    if (rc) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(S.grp.stream));
+  S.elapsed += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return OPDHG_OK;
+}
+
 int opdhg_session_state(opdhg_session* s, double* x, double* y, double* T, double* Sigma,
                         opdhg_state* st) {
   if (!s) return fail(OPDHG_ERR_INVALID_ARGUMENT, "session is NULL");
@@ -824,12 +959,30 @@ int opdhg_session_state(opdhg_session* s, double* x, double* y, double* T, doubl
   HIP_TRY(hipMemcpyAsync(S.h_ctl, S.lpd.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, S.grp.stream));
   HIP_TRY(hipStreamSynchronize(S.grp.stream));
   c = *S.h_ctl;
+  if (c.learn_pending) {
+    // apply the accepted learner step now (the next attempt would have)
+    if (S.grp.launch_learn_flush()) return fail(OPDHG_ERR_DEVICE, device_error_string());
+    static const int32_t zero = 0;
+    HIP_TRY(hipMemcpyAsync(&S.lpd.ctl->learn_pending, &zero, sizeof(zero),
+                           hipMemcpyHostToDevice, S.grp.stream));
+    HIP_TRY(hipStreamSynchronize(S.grp.stream));
+    c.learn_pending = 0;
+  }
   int rc = 0;
   const int prec = S.grp.prec;
-  if ((rc = download_vec(S.lpd.x[c.cur], S.P.n, prec, S.grp.stream, x))) return rc;
-  if ((rc = download_vec(S.lpd.y[c.cur], S.P.m, prec, S.grp.stream, y))) return rc;
-  if ((rc = download_vec(S.lpd.T, S.P.n, prec, S.grp.stream, T))) return rc;
-  if ((rc = download_vec(S.lpd.S, S.P.m, prec, S.grp.stream, Sigma))) return rc;
+  std::vector<double> tn(S.P.n), tm(S.P.m);
+  struct {
+    const void* src;
+    double* dst;
+    bool primal;
+  } outs[4] = {{S.lpd.x[c.cur], x, true}, {S.lpd.y[c.cur], y, false},
+               {S.lpd.T, T, true}, {S.lpd.S, Sigma, false}};
+  for (auto& o : outs) {
+    if (!o.dst) continue;
+    std::vector<double>& tmp = o.primal ? tn : tm;
+    if ((rc = download_vec(o.src, tmp.size(), prec, S.grp.stream, tmp.data()))) return rc;
+    unpermute(tmp.data(), o.primal ? S.P.perm_t : S.P.perm_a, nullptr, o.dst);
+  }
   if (st) {
     st->k = c.k;
     st->t = c.t;
@@ -853,12 +1006,14 @@ int opdhg_session_result(opdhg_session* s, double* x_out, double* y_out, opdhg_r
   int rc = 0;
   const int prec = S.grp.prec;
   if (x_out) {
-    if ((rc = download_vec(S.lpd.x[c.cur], S.P.n, prec, S.grp.stream, x_out))) return rc;
-    for (int64_t j = 0; j < S.P.n; ++j) x_out[j] *= S.P.dc[j];
+    std::vector<double> tmp(S.P.n);
+    if ((rc = download_vec(S.lpd.x[c.cur], S.P.n, prec, S.grp.stream, tmp.data()))) return rc;
+    unpermute(tmp.data(), S.P.perm_t, S.P.dc.data(), x_out);
   }
-  if (y_out) {
-    if ((rc = download_vec(S.lpd.y[c.cur], S.P.m, prec, S.grp.stream, y_out))) return rc;
-    for (int64_t i = 0; i < S.P.m; ++i) y_out[i] *= S.P.dr[i];
+  if (y_out && S.P.m) {
+    std::vector<double> tmp(S.P.m);
+    if ((rc = download_vec(S.lpd.y[c.cur], S.P.m, prec, S.grp.stream, tmp.data()))) return rc;
+    unpermute(tmp.data(), S.P.perm_a, S.P.dr.data(), y_out);
   }
   if (res) fill_result(c, S.elapsed, res);
   return OPDHG_OK;
@@ -921,7 +1076,7 @@ int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_para
     nwt += P.tiles_t.size();
     nwa += P.tiles_a.size();
   }
-  *bytes = total + tables_bytes(count, nwt, nwa);
+  *bytes = total + tables_bytes(count, nwt, nwa, grid_cap(p));
   return OPDHG_OK;
 }
 
@@ -950,7 +1105,7 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, voi
     nwt += P[i].tiles_t.size();
     nwa += P[i].tiles_a.size();
   }
-  const size_t need = off + tables_bytes(count, nwt, nwa);
+  const size_t need = off + tables_bytes(count, nwt, nwa, grid_cap(p));
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(need) + " bytes");
   uint8_t* ws = static_cast<uint8_t*>(d_workspace);
@@ -969,11 +1124,13 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, voi
   }
   std::vector<uint8_t> staging;
   int64_t wt = 0, wa = 0;
-  if ((rc = write_tables(ws + off, lpd, grp.stream, staging, &grp.cfg.bd, &wt, &wa))) {
+  std::vector<const Prepared*> preps(count);
+  for (int i = 0; i < count; ++i) preps[i] = &P[i];
+  if ((rc = write_tables(ws + off, lpd, preps, grid_cap(p), grp.stream, staging, &grp.cfg, &wt,
+                         &wa))) {
     grp.release();
     return rc;
   }
-  grp.set_grid(wt, wa, false);
   if (grp.launch_init()) {
     grp.release();
     return fail(OPDHG_ERR_DEVICE, device_error_string());
@@ -996,12 +1153,16 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, voi
   for (int i = 0; i < count && rc == 0; ++i) {
     const Ctl& c = h[i];
     if (x_out && x_out[i]) {
-      if ((rc = download_vec(lpd[i].x[c.cur], P[i].n, p->precision, grp.stream, x_out[i]))) break;
-      for (int64_t j = 0; j < P[i].n; ++j) x_out[i][j] *= P[i].dc[j];
+      std::vector<double> tmp(P[i].n);
+      if ((rc = download_vec(lpd[i].x[c.cur], P[i].n, p->precision, grp.stream, tmp.data())))
+        break;
+      unpermute(tmp.data(), P[i].perm_t, P[i].dc.data(), x_out[i]);
     }
-    if (y_out && y_out[i]) {
-      if ((rc = download_vec(lpd[i].y[c.cur], P[i].m, p->precision, grp.stream, y_out[i]))) break;
-      for (int64_t r = 0; r < P[i].m; ++r) y_out[i][r] *= P[i].dr[r];
+    if (y_out && y_out[i] && P[i].m) {
+      std::vector<double> tmp(P[i].m);
+      if ((rc = download_vec(lpd[i].y[c.cur], P[i].m, p->precision, grp.stream, tmp.data())))
+        break;
+      unpermute(tmp.data(), P[i].perm_a, P[i].dr.data(), y_out[i]);
     }
     fill_result(c, elapsed, &res[i]);
   }

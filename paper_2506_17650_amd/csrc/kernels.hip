@@ -1,15 +1,25 @@
 // HIP kernels of restarted PDHG with online preconditioning (gfx950).
 //
-// Every kernel covers a set of LPs: it loops with a fixed grid over
-// (lp, tile) work items, so one launch serves one LP, a packed batch or the
-// server's changing mix. A tile is a range of CSR rows of one side (A or
-// A^T) handled by one 256-thread workgroup, either as row groups of
-// `lanes` threads (consecutive lanes read consecutive nonzeros, then an
-// xor-shuffle tree sums the group) or, for one long row, by the whole
-// workgroup. Per-row epilogues fuse the vector work of the method into the
-// sparse product, and per-tile FP64 partial sums feed deterministic
-// reductions: the last tile of an LP to finish (completion counter) sums
-// all tiles' partials in a fixed order and takes the LP's scalar decision.
+// Every kernel covers a set of LPs, so one launch serves one LP, a packed
+// batch or the server's changing mix. The rows of each CSR side (A or A^T)
+// are cut into tiles; a work item is one tile of one LP. Each workgroup of
+// 256 threads (4 wave64) takes a fixed, contiguous chunk of the work list.
+//
+// A stream tile holds up to kTileCap nonzeros of consecutive rows. Its
+// workgroup first streams the tile's column indices and values with
+// coalesced loads, gathers the vector entries and writes the products to
+// LDS, all loads of the tile in flight together; then each row is reduced
+// from LDS by a group of `lanes` threads and finished by a per-row epilogue
+// whose vector loads were issued before the stream. A row longer than
+// kTileCap is a tile of its own, reduced by the whole workgroup.
+//
+// The epilogues fuse the method's vector work into the sparse products and
+// accumulate FP64 partial sums per thread; at the end of an LP's part of a
+// chunk the workgroup reduces them and stores one partial per (workgroup,
+// LP). A one-workgroup-per-LP decision kernel sums an LP's partials in a
+// fixed order and takes its scalar decision. Workgroups never wait for or
+// signal each other inside a launch; kernel boundaries carry every result
+// to the next step.
 //
 // Per attempt (Algorithm 1, line 1, eq. (6)):
 //   k_primal  CSR(A^T) SpMV of y, g = c - A^T y, x' = proj_[l,u](x - (eta/w) T g),
@@ -17,16 +27,19 @@
 //             (eq. (7)), partials |x'-x|^2, |g|^2, |G^p|^2
 //   k_dual    CSR(A) SpMV of x', A x_bar = 2 A x' - A x, dual step and sign
 //             projection, running sum of y, dual online gradient, partials
-//             |y'-y|^2, (y'-y).(A x'-A x), |b-Ax|^2, |G^d|^2; the last tile
-//             applies the adaptive step rule: accept (flip buffers) or retry
-//   k_learn   normalized online-gradient step with AdaGrad on T and Sigma
-//             (Algorithm 1, lines 4-8), every phi-th accepted iteration
+//             |y'-y|^2, (y'-y).(A x'-A x), |b-Ax|^2, |G^d|^2
+//   k_decide  adaptive step rule: accept (flip buffers) or retry
+// The normalized online-gradient step with AdaGrad on T and Sigma
+// (Algorithm 1, lines 4-8) after an accepted update iteration is applied by
+// the next attempt's k_primal (T) and k_dual (Sigma) to the rows they
+// visit, before those rows use the preconditioner.
 // Every eval_every accepted iterations:
-//   k_eval_t  CSR(A^T) SpMV of y and of the running sum of y: reduced costs,
+//   k_eval_t  CSR(A^T) SpMV of y and of the average of y: reduced costs,
 //             dual residuals, bound terms of the dual objective, c^T x, and
 //             distances to the restart anchor, for current and average
-//   k_eval_a  CSR(A) SpMV of the running sum of x: primal residuals, b^T y,
-//             distances; the last tile decides termination and restarts
+//   k_eval_a  CSR(A) SpMV of the average of x: primal residuals, b^T y,
+//             distances
+//   k_eval_decide  termination and restart decision
 //   k_apply   moves the iterate to the restart point, resets the sums and the
 //             anchor (preconditioners kept), or copies a returned average out
 //
@@ -36,8 +49,8 @@
 // is gathered in a second double, which is folded in once at the end. The
 // result is the correctly rounded sum except when the exact value lies
 // within about n * 2^-106 (relative) of a rounding boundary, so it does not
-// depend on the tile size, the lane count, the grid, or what else shares
-// the launch. In FP32 mode the SpMV accumulates in FP32 with FMA.
+// depend on the tiling, the lane count, the grid, or what else shares the
+// launch. In FP32 mode the SpMV products and row sums are FP32.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -109,107 +122,155 @@ __device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
   __syncthreads();
 }
 
-// Store the workgroup totals of a tile (thread 0).
+// Store workgroup totals in partial slot `slot` (thread 0). Partials are
+// laid out quantity-major (hi and lo of quantity q at 2q * stride + slot and
+// (2q + 1) * stride + slot) so the decision kernel reads them coalesced.
 template <int NV>
-__device__ __forceinline__ void store_partials(double* out, const DD (&v)[NV]) {
+__device__ __forceinline__ void store_partials(double* part, int stride, int slot,
+                                               const DD (&v)[NV]) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      out[2 * q] = v[q].hi;
-      out[2 * q + 1] = v[q].lo;
+      part[(size_t)(2 * q) * stride + slot] = v[q].hi;
+      part[(size_t)(2 * q + 1) * stride + slot] = v[q].lo;
     }
   }
 }
 
-__device__ __forceinline__ double load_agent(const double* p) {
-  unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double(static_cast<long long>(v));
-}
-
-// Fixed-order merge of NV double-double partials over ntiles tiles (whole
-// workgroup); thread 0 gets the rounded totals. Partials were written by
-// other workgroups of this launch or of earlier launches.
+// Fixed-order merge of NV double-double partials over `count` slots (whole
+// workgroup; quantity-major with the given stride); thread 0 gets the
+// rounded totals. Partials were written by
+// earlier launches. Each thread loads B tiles' partials before merging
+// them, so the loads of a batch are in flight together.
 template <int NV>
-__device__ __forceinline__ void sum_partials(const double* part, int ntiles, double (&out)[NV],
-                                             DD* s_red) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int stride,
+                                             int count, double (&out)[NV], DD* s_red) {
+  constexpr int B = NV <= 4 ? 8 : 2;
   DD v[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = dd_zero();
-  for (int t = threadIdx.x; t < ntiles; t += kBlock) {
-    const double* src = part + (size_t)t * kPartStride;
+  for (int base = threadIdx.x; base < count; base += kBlock * B) {
+    double h[B][NV], l[B][NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = dd_merge(v[q], DD{load_agent(src + 2 * q),
-                                                           load_agent(src + 2 * q + 1)});
+    for (int k = 0; k < B; ++k) {
+      const int t = base + k * kBlock;
+      const bool ok = t < count;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        h[k][q] = ok ? part[(size_t)(2 * q) * stride + t] : 0.0;
+        l[k][q] = ok ? part[(size_t)(2 * q + 1) * stride + t] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] = dd_merge(v[q], DD{h[k][q], l[k][q]});
+    }
   }
   block_sum<NV>(v, s_red);
 #pragma unroll
   for (int q = 0; q < NV; ++q) out[q] = dd_value(v[q]);
 }
 
-// ---- SpMV row accumulators: double-double in FP64, FMA in FP32 ----
+// ---- numbers of the sparse products: exact products and double-double
+// row sums in FP64, plain FP32 products and sums in FP32 ----
 template <typename V>
-struct RowAcc;
+struct Num;
 
 template <>
-struct RowAcc<double> {
-  DD v;
-  __device__ __forceinline__ void zero() { v = dd_zero(); }
-  __device__ __forceinline__ void add(double a, double x) { dd_add_prod(v, a, x); }
-  __device__ __forceinline__ void merge_xor(int off) { v = dd_merge(v, dd_shfl_xor(v, off)); }
-  __device__ __forceinline__ void merge(const RowAcc& o) { v = dd_merge(v, o.v); }
-  __device__ __forceinline__ double value() const { return dd_value(v); }
-};
-
-template <>
-struct RowAcc<float> {
-  float v;
-  __device__ __forceinline__ void zero() { v = 0.f; }
-  __device__ __forceinline__ void add(float a, float x) { v = fmaf(a, x, v); }
-  __device__ __forceinline__ void merge_xor(int off) { v += __shfl_xor(v, off, 64); }
-  __device__ __forceinline__ void merge(const RowAcc& o) { v += o.v; }
-  __device__ __forceinline__ float value() const { return v; }
-};
-
-// Completion counting: true in every thread of the workgroup that finished
-// the last tile of its LP for this counter. The counter is reset by the
-// caller of the final step.
-__device__ __forceinline__ bool last_tile(int32_t* counter, int ntiles, int* s_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int prev = atomicAdd(counter, 1);
-    *s_flag = (prev == ntiles - 1);
+struct Num<double> {
+  struct Prod {
+    double p, e;  // p + e is the exact product
+  };
+  static __device__ __forceinline__ Prod mul(double a, double x) {
+    const double p = a * x;
+    return Prod{p, fma(a, x, -p)};
   }
-  __syncthreads();
-  const bool last = *s_flag != 0;
-  if (last) __threadfence();
-  return last;
+  struct Acc {
+    DD v;
+    __device__ __forceinline__ void zero() { v = dd_zero(); }
+    __device__ __forceinline__ void add(const Prod& q) {
+      dd_add(v, q.p);
+      v.lo += q.e;
+    }
+    __device__ __forceinline__ void merge_xor(int off) { v = dd_merge(v, dd_shfl_xor(v, off)); }
+    __device__ __forceinline__ void merge(const Acc& o) { v = dd_merge(v, o.v); }
+    __device__ __forceinline__ double value() const { return dd_value(v); }
+  };
+};
+
+template <>
+struct Num<float> {
+  using Prod = float;
+  static __device__ __forceinline__ float mul(float a, float x) { return a * x; }
+  struct Acc {
+    float v;
+    __device__ __forceinline__ void zero() { v = 0.f; }
+    __device__ __forceinline__ void add(float q) { v += q; }
+    __device__ __forceinline__ void merge_xor(int off) { v += __shfl_xor(v, off, 64); }
+    __device__ __forceinline__ void merge(const Acc& o) { v += o.v; }
+    __device__ __forceinline__ float value() const { return v; }
+  };
+};
+
+template <typename V>
+using Prod = typename Num<V>::Prod;
+template <typename V>
+using Acc = typename Num<V>::Acc;
+
+// Vector q at column c: vec[q][c], or vec[q][c] / div[q] for the average.
+template <typename V>
+__device__ __forceinline__ V vec_at(const V* const* vec, const double* div, int q, int c) {
+  const V v = vec[q][c];
+  return div[q] > 0.0 ? (V)((double)v / div[q]) : v;
 }
 
-// Sparse dot products of the rows of one tile with NA vectors, then a
-// per-row epilogue epi(row, val[NA]) run by one thread per row. Vector q is
-// read as vec[q][col] / div[q] when div[q] > 0 (the average iterate).
-template <typename V, int NA, typename Epi>
-__device__ __forceinline__ void tile_spmv(const Tile& tile, const int32_t* __restrict__ rp,
+// LDS of a workgroup for the sparse products: kTileCap products per
+// vector, and room for the cross-wave sums of a long row.
+template <typename V, int NA>
+struct SpmvShared {
+  Prod<V> prod[NA][kTileCap];
+  Acc<V> wave[4][NA];
+};
+
+// One tile: sparse dot products of its rows with NA vectors and the row
+// epilogues. pre = load(row) runs in the thread that finishes the row,
+// before the tile's nonzeros are read; finish(row, val[NA], pre) runs once
+// the row's sums are known. Called by the whole workgroup.
+template <typename V, int NA, typename Load, typename Finish>
+__device__ __forceinline__ void spmv_tile(const WorkItem& it, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const V* __restrict__ va, const V* const* vec,
-                                          const double* div, Epi&& epi,
-                                          RowAcc<V>* s_long) {
+                                          const double* div, Load&& load, Finish&& finish,
+                                          SpmvShared<V, NA>& sh) {
   const int tid = threadIdx.x;
-  if (tile.lanes == 0) {
-    const int r = tile.rb;
-    const int s = rp[r], e = rp[r + 1];
-    RowAcc<V> acc[NA];
+  if (it.lanes == 0) {
+    // one long row: every thread takes every kBlock-th nonzero, four at a
+    // time so their loads overlap; waves combine through LDS
+    const int r = it.rb;
+    decltype(load(r)) pre{};
+    if (tid == 0) pre = load(r);
+    Acc<V> acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q].zero();
-    for (int i = s + tid; i < e; i += kBlock) {
-      const V a = va[i];
-      const int cc = ci[i];
+    constexpr int U = 4;
+    for (int k = it.s + tid; k < it.e; k += U * kBlock) {
+      V a[U];
+      int c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int kk = k + u * kBlock;
+        a[u] = kk < it.e ? va[kk] : V(0);
+        c[u] = kk < it.e ? ci[kk] : 0;
+      }
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
-        const V xv = div[q] > 0.0 ? (V)((double)vec[q][cc] / div[q]) : vec[q][cc];
-        acc[q].add(a, xv);
+        V x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = k + u * kBlock < it.e ? vec_at(vec, div, q, c[u]) : V(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (k + u * kBlock < it.e) acc[q].add(Num<V>::mul(a[u], x[u]));
       }
     }
 #pragma unroll
@@ -219,52 +280,79 @@ __device__ __forceinline__ void tile_spmv(const Tile& tile, const int32_t* __res
     }
     if ((tid & 63) == 0) {
 #pragma unroll
-      for (int q = 0; q < NA; ++q) s_long[(tid >> 6) * NA + q] = acc[q];
+      for (int q = 0; q < NA; ++q) sh.wave[tid >> 6][q] = acc[q];
     }
     __syncthreads();
     if (tid == 0) {
       V out[NA];
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
-        RowAcc<V> t = s_long[q];
-        t.merge(s_long[NA + q]);
-        t.merge(s_long[2 * NA + q]);
-        t.merge(s_long[3 * NA + q]);
+        Acc<V> t = sh.wave[0][q];
+        t.merge(sh.wave[1][q]);
+        t.merge(sh.wave[2][q]);
+        t.merge(sh.wave[3][q]);
         out[q] = t.value();
       }
-      epi(r, out);
+      finish(r, out, pre);
     }
     __syncthreads();
-  } else {
-    const int L = tile.lanes;
-    const int lane = tid & (L - 1);
-    const int ng = kBlock / L;
-    for (int r = tile.rb + tid / L; r < tile.re; r += ng) {
-      const int s = rp[r], e = rp[r + 1];
-      RowAcc<V> acc[NA];
+    return;
+  }
+  // stream tile: group g of `lanes` threads owns row rb + g (at most one)
+  const int L = it.lanes;
+  const int g = tid / L;
+  const int lane = tid & (L - 1);
+  const int r = it.rb + g;
+  const bool has_row = r < it.re;
+  decltype(load(r)) pre{};
+  int r0 = 0, r1 = 0;
+  if (has_row) {
+    if (lane == 0) pre = load(r);
+    r0 = rp[r] - it.s;
+    r1 = rp[r + 1] - it.s;
+  }
+  const int n = it.e - it.s;
+  constexpr int K = kTileCap / kBlock;
+  V a[K];
+  int c[K];
 #pragma unroll
-      for (int q = 0; q < NA; ++q) acc[q].zero();
-      for (int i = s + lane; i < e; i += L) {
-        const V a = va[i];
-        const int cc = ci[i];
+  for (int u = 0; u < K; ++u) {
+    const int k = tid + u * kBlock;
+    a[u] = k < n ? va[it.s + k] : V(0);
+    c[u] = k < n ? ci[it.s + k] : 0;
+  }
 #pragma unroll
-        for (int q = 0; q < NA; ++q) {
-          const V xv = div[q] > 0.0 ? (V)((double)vec[q][cc] / div[q]) : vec[q][cc];
-          acc[q].add(a, xv);
-        }
-      }
-      for (int off = L >> 1; off > 0; off >>= 1) {
+  for (int q = 0; q < NA; ++q) {
+    V x[K];
 #pragma unroll
-        for (int q = 0; q < NA; ++q) acc[q].merge_xor(off);
-      }
-      if (lane == 0) {
-        V out[NA];
+    for (int u = 0; u < K; ++u) x[u] = tid + u * kBlock < n ? vec_at(vec, div, q, c[u]) : V(0);
 #pragma unroll
-        for (int q = 0; q < NA; ++q) out[q] = acc[q].value();
-        epi(r, out);
-      }
+    for (int u = 0; u < K; ++u) {
+      const int k = tid + u * kBlock;
+      if (k < n) sh.prod[q][k] = Num<V>::mul(a[u], x[u]);
     }
   }
+  __syncthreads();
+  if (has_row) {
+    Acc<V> acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q].zero();
+    for (int k = r0 + lane; k < r1; k += L) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) acc[q].add(sh.prod[q][k]);
+    }
+    for (int off = L >> 1; off > 0; off >>= 1) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) acc[q].merge_xor(off);
+    }
+    if (lane == 0) {
+      V out[NA];
+#pragma unroll
+      for (int q = 0; q < NA; ++q) out[q] = acc[q].value();
+      finish(r, out, pre);
+    }
+  }
+  __syncthreads();
 }
 
 template <typename V>
@@ -274,11 +362,28 @@ __device__ __forceinline__ V clampv(V v, V lo, V hi) {
 }
 
 __device__ __forceinline__ bool attempt_guard(const Ctl* c) {
+  // running, no evaluation due, below the pause point
   return c->status == kRunning && c->need_eval == 0 && c->k < c->k_limit;
 }
 
 __device__ __forceinline__ bool eval_guard(const Ctl* c) {
   return c->status == kRunning && c->need_eval != 0;
+}
+
+template <int NV>
+__device__ __forceinline__ void dd_reset(DD (&v)[NV]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = dd_zero();
+}
+
+// End of an LP's part of this workgroup's chunk: reduce the thread sums and
+// store them in the LP's partial slot.
+template <int NV>
+__device__ __forceinline__ void flush_partials(DD (&p)[NV], DD* s_red, double* part, int stride,
+                                               int slot) {
+  block_sum<NV>(p, s_red);
+  store_partials<NV>(part, stride, slot, p);
+  dd_reset(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,6 +415,8 @@ __device__ void decide_step(Ctl* c, const DevParams* p, const double* tab, const
   const double second = (1.0 + step_factor(tab, 1, c->attempts, p->step_growth)) * eta;
   const double eta_next = second < first ? second : first;
   c->last_eta_bar = eta_bar;
+  // a pending learner update was applied by this attempt's kernels
+  c->learn_pending = 0;
   if (eta <= eta_bar) {
     const bool learn = p->lr > 0.0 && (c->k % p->phi) == 0;
     c->eta_acc = eta;
@@ -334,6 +441,7 @@ __device__ void decide_step(Ctl* c, const DevParams* p, const double* tab, const
         if (!nd) c->hd_norm = c->hd_norm + gd2 / (sd * sd);
       }
     }
+    c->learn_now = (p->lr > 0.0 && (c->k % p->phi) == 0) ? 1 : 0;
     if (c->k % p->eval_every == 0 || c->k >= p->max_iter) c->need_eval = 1;
   } else {
     c->eta = eta_next;
@@ -431,212 +539,335 @@ __device__ void decide_eval(Ctl* c, const DevParams* p, const double* st, const 
   }
 }
 
+// Drives a workgroup over its chunk of a side's work list. The next item is
+// read while the current one runs; when the LP changes, begin(item) loads
+// the LP's pointers and scalars into registers and returns whether the LP
+// takes part; tile(item) processes a tile of a running LP; end(item, run)
+// closes the LP's part of the chunk.
+template <typename Begin, typename TileFn, typename End>
+__device__ __forceinline__ void run_chunk(const WorkItem* __restrict__ work, int chunk,
+                                          Begin&& begin, TileFn&& tile, End&& end) {
+  const int w0 = blockIdx.x * chunk;
+  WorkItem it = work[w0];
+  int lp = -1;
+  bool run = false;
+  for (int k = 0; k < chunk; ++k) {
+    const WorkItem nx = work[w0 + (k + 1 < chunk ? k + 1 : k)];
+    if (it.lp >= 0) {
+      if (it.lp != lp) {
+        lp = it.lp;
+        run = begin(it);
+      }
+      if (run) tile(it);
+      if (it.last) end(it, run);
+    }
+    it = nx;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 
+// One projected online-gradient step on one preconditioner entry
+// (Algorithm 1, lines 4-8): G / scale (scale = |g|^2 or |b - Ax|^2 when
+// normalizing, else 1), then AdaGrad (diagonal or on the norm) or a
+// constant rate, then the clamp at the floor.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_init_products(const BatchDev* __restrict__ bd) {
-  __shared__ RowAcc<V> s_long[4];
-  const int nwork = bd->nwork_a;
+__device__ __forceinline__ V learn_elem(V Pv, V& Hv, V Graw, double scale, const DevParams* p,
+                                        double hnorm) {
+  const V gv = (V)((double)Graw / scale);
+  V step;
+  if (p->schedule == 0) {
+    Hv = Hv + gv * gv;
+    step = Hv > V(0) ? gv / sqrt(Hv) : V(0);
+  } else if (p->schedule == 1) {
+    step = hnorm > 0.0 ? (V)((double)gv / sqrt(hnorm)) : V(0);
+  } else {
+    step = gv;
+  }
+  const V pv = Pv - (V)p->lr * step;
+  const V fl = (V)p->floor;
+  return pv < fl ? fl : pv;
+}
+
+// Whether the pending learner update touches this side, and its scale.
+__device__ __forceinline__ bool learn_side(const Ctl* c, const DevParams* p, bool primal,
+                                           double* scale) {
+  if (!c->learn_pending) return false;
+  const double nrm = primal ? c->g2 : c->r2;
+  if (p->normalize && !(nrm > 0.0)) return false;
+  *scale = p->normalize ? nrm : 1.0;
+  return true;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_init_products(LaunchCfg cfg) {
+  __shared__ SpmvShared<V, 1> sh;
   const double nodiv[1] = {0.0};
-  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-    const WorkItem it = bd->work_a[wi];
-    const LpDev& lp = bd->lps[it.lp];
-    const int cur = lp.ctl->cur;
-    const Tile tile = lp.tiles_a[it.tile];
+  const int i0 = blockIdx.x * cfg.chunk_a;
+  for (int wi = i0; wi < i0 + cfg.chunk_a; ++wi) {
+    const WorkItem it = cfg.work_a[wi];
+    if (it.lp < 0) continue;
+    const LpDev& lp = cfg.lps[it.lp];
+    const int cur = it.ctl->cur;
     V* Ax = static_cast<V*>(lp.Ax[cur]);
     const V* vecs[1] = {static_cast<const V*>(lp.x[cur])};
-    tile_spmv<V, 1>(tile, lp.rp_a, lp.ci_a, static_cast<const V*>(lp.va_a), vecs, nodiv,
-                    [&](int i, V (&acc)[1]) { Ax[i] = acc[0]; }, s_long);
+    spmv_tile<V, 1>(
+        it, lp.rp_a, lp.ci_a, static_cast<const V*>(lp.va_a), vecs, nodiv,
+        [&](int) { return 0; }, [&](int i, V (&acc)[1], int) { Ax[i] = acc[0]; }, sh);
   }
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_primal(const BatchDev* __restrict__ bd, int force) {
+struct PrimalPre {
+  V c, x, T, l, u, xs, H, G;
+};
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
+  __shared__ SpmvShared<V, 1> sh;
   __shared__ DD s_red[4 * 3];
-  __shared__ RowAcc<V> s_long[4];
-  const int nwork = bd->nwork_t;
   const double nodiv[1] = {0.0};
-  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-    const WorkItem it = bd->work_t[wi];
-    const LpDev& lp = bd->lps[it.lp];
-    const Ctl* c = lp.ctl;
-    if (!force && !attempt_guard(c)) continue;
-    const int cur = c->cur, nxt = cur ^ 1;
-    const double eta = c->eta, om = c->omega;
-    const V tau = (V)(eta / om);
-    const V etav = (V)eta;
-    const bool learn = lp.prm->lr > 0.0 && (c->k % lp.prm->phi) == 0;
-    const V* __restrict__ cc = static_cast<const V*>(lp.c);
-    const V* __restrict__ lo = static_cast<const V*>(lp.l);
-    const V* __restrict__ hi = static_cast<const V*>(lp.u);
-    const V* __restrict__ T = static_cast<const V*>(lp.T);
-    const V* __restrict__ x = static_cast<const V*>(lp.x[cur]);
-    const V* __restrict__ xs = static_cast<const V*>(lp.xs[cur]);
-    V* __restrict__ xn = static_cast<V*>(lp.x[nxt]);
-    V* __restrict__ xsn = static_cast<V*>(lp.xs[nxt]);
-    V* __restrict__ Gp = static_cast<V*>(lp.Gp);
-    const V* vecs[1] = {static_cast<const V*>(lp.y[cur])};
-    DD p[3] = {dd_zero(), dd_zero(), dd_zero()};
-    const Tile tile = lp.tiles_t[it.tile];
-    tile_spmv<V, 1>(
-        tile, lp.rp_t, lp.ci_t, static_cast<const V*>(lp.va_t), vecs, nodiv,
-        [&](int j, V (&acc)[1]) {
-          const V g = cc[j] - acc[0];
-          const V xj = x[j];
-          const V xh = xj - (tau * T[j]) * g;
-          const V lj = lo[j], uj = hi[j];
-          const V xv = clampv(xh, lj, uj);
-          xn[j] = xv;
-          xsn[j] = xs[j] + etav * xv;
-          const double dx = (double)xv - (double)xj;
-          dd_add_prod(p[0], dx, dx);
-          dd_add_prod(p[1], (double)g, (double)g);
-          if (learn) {
-            const bool ind = (xh >= lj) && (xh <= uj);
-            const V gp = ind ? -((tau * g) * g) : V(0);
-            Gp[j] = gp;
-            dd_add_prod(p[2], (double)gp, (double)gp);
-          }
-        },
-        s_long);
-    block_sum<3>(p, s_red);
-    store_partials<3>(lp.part_t + (size_t)it.tile * kPartStride, p);
-  }
+  DD p[3];
+  dd_reset(p);
+  // per-LP context, loaded when the LP changes
+  const LpDev* lp = nullptr;
+  Ctl* c = nullptr;
+  const V *cc = nullptr, *lo = nullptr, *hi = nullptr, *x = nullptr, *xs = nullptr;
+  V *T = nullptr, *Hp = nullptr, *xn = nullptr, *xsn = nullptr, *Gp = nullptr;
+  const V* vecs[1] = {nullptr};
+  V tau = V(0), etav = V(0);
+  bool learn = false, upd = false;
+  double lscale = 1.0, hnorm = 0.0;
+  run_chunk(
+      cfg.work_t, cfg.chunk_t,
+      [&](const WorkItem& it) {
+        c = it.ctl;
+        // the restart / final copy of the evaluation step ran before this launch
+        if (it.tile == 0 && threadIdx.x == 0 && (c->restart_pending | c->finalize_avg)) {
+          c->restart_pending = 0;
+          c->finalize_avg = 0;
+        }
+        if (!force && !attempt_guard(c)) return false;
+        lp = &cfg.lps[it.lp];
+        const int cur = c->cur, nxt = cur ^ 1;
+        const double eta = c->eta, om = c->omega;
+        tau = (V)(eta / om);
+        etav = (V)eta;
+        learn = c->learn_now != 0;
+        lscale = 1.0;
+        upd = !force && c->learn_pending && learn_side(c, lp->prm, true, &lscale);
+        hnorm = c->hp_norm;
+        cc = static_cast<const V*>(lp->c);
+        lo = static_cast<const V*>(lp->l);
+        hi = static_cast<const V*>(lp->u);
+        T = static_cast<V*>(lp->T);
+        Hp = static_cast<V*>(lp->Hp);
+        x = static_cast<const V*>(lp->x[cur]);
+        xs = static_cast<const V*>(lp->xs[cur]);
+        xn = static_cast<V*>(lp->x[nxt]);
+        xsn = static_cast<V*>(lp->xs[nxt]);
+        Gp = static_cast<V*>(lp->Gp);
+        vecs[0] = static_cast<const V*>(lp->y[cur]);
+        return true;
+      },
+      [&](const WorkItem& it) {
+        spmv_tile<V, 1>(
+            it, lp->rp_t, lp->ci_t, static_cast<const V*>(lp->va_t), vecs, nodiv,
+            [&](int j) {
+              PrimalPre<V> q;
+              q.c = cc[j];
+              q.x = x[j];
+              q.T = T[j];
+              q.l = lo[j];
+              q.u = hi[j];
+              q.xs = xs[j];
+              if (upd) {
+                q.H = Hp[j];
+                q.G = Gp[j];
+              }
+              return q;
+            },
+            [&](int j, V (&acc)[1], PrimalPre<V>& q) {
+              V Tj = q.T;
+              if (upd) {
+                V h = q.H;
+                Tj = learn_elem<V>(Tj, h, q.G, lscale, lp->prm, hnorm);
+                T[j] = Tj;
+                Hp[j] = h;
+              }
+              const V g = q.c - acc[0];
+              const V xh = q.x - (tau * Tj) * g;
+              const V xv = clampv(xh, q.l, q.u);
+              xn[j] = xv;
+              xsn[j] = q.xs + etav * xv;
+              const double dx = (double)xv - (double)q.x;
+              dd_add_prod(p[0], dx, dx);
+              dd_add_prod(p[1], (double)g, (double)g);
+              if (learn) {
+                const bool ind = (xh >= q.l) && (xh <= q.u);
+                const V gp = ind ? -((tau * g) * g) : V(0);
+                Gp[j] = gp;
+                dd_add_prod(p[2], (double)gp, (double)gp);
+              }
+            },
+            sh);
+      },
+      [&](const WorkItem& it, bool run) {
+        if (run) flush_partials<3>(p, s_red, lp->part_t, lp->ntiles_t, it.slot);
+        else dd_reset(p);
+      });
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_dual(const BatchDev* __restrict__ bd) {
+struct DualPre {
+  V ax, b, y, ys, S, H, G;
+  int8_t ineq;
+};
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg) {
+  __shared__ SpmvShared<V, 1> sh;
   __shared__ DD s_red[4 * 4];
-  __shared__ RowAcc<V> s_long[4];
-  __shared__ int s_flag;
-  const int nwork = bd->nwork_a;
   const double nodiv[1] = {0.0};
-  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-    const WorkItem it = bd->work_a[wi];
-    const LpDev& lp = bd->lps[it.lp];
+  DD p[4];
+  dd_reset(p);
+  const LpDev* lp = nullptr;
+  const Ctl* c = nullptr;
+  const V *b = nullptr, *y = nullptr, *ys = nullptr, *Ax = nullptr;
+  V *S = nullptr, *Hd = nullptr, *yn = nullptr, *ysn = nullptr, *Axn = nullptr, *Gd = nullptr;
+  const int8_t* sense = nullptr;
+  const V* vecs[1] = {nullptr};
+  V sig = V(0), etav = V(0);
+  bool learn = false, upd = false;
+  double lscale = 1.0, hnorm = 0.0;
+  run_chunk(
+      cfg.work_a, cfg.chunk_a,
+      [&](const WorkItem& it) {
+        c = it.ctl;
+        if (!attempt_guard(c)) return false;
+        lp = &cfg.lps[it.lp];
+        const int cur = c->cur, nxt = cur ^ 1;
+        const double eta = c->eta, om = c->omega;
+        sig = (V)(eta * om);
+        etav = (V)eta;
+        learn = c->learn_now != 0;
+        lscale = 1.0;
+        upd = c->learn_pending && learn_side(c, lp->prm, false, &lscale);
+        hnorm = c->hd_norm;
+        b = static_cast<const V*>(lp->b);
+        S = static_cast<V*>(lp->S);
+        Hd = static_cast<V*>(lp->Hd);
+        y = static_cast<const V*>(lp->y[cur]);
+        ys = static_cast<const V*>(lp->ys[cur]);
+        Ax = static_cast<const V*>(lp->Ax[cur]);
+        yn = static_cast<V*>(lp->y[nxt]);
+        ysn = static_cast<V*>(lp->ys[nxt]);
+        Axn = static_cast<V*>(lp->Ax[nxt]);
+        Gd = static_cast<V*>(lp->Gd);
+        sense = lp->sense;
+        vecs[0] = static_cast<const V*>(lp->x[nxt]);
+        return true;
+      },
+      [&](const WorkItem& it) {
+        spmv_tile<V, 1>(
+            it, lp->rp_a, lp->ci_a, static_cast<const V*>(lp->va_a), vecs, nodiv,
+            [&](int i) {
+              DualPre<V> q;
+              q.ax = Ax[i];
+              q.b = b[i];
+              q.y = y[i];
+              q.ys = ys[i];
+              q.S = S[i];
+              q.ineq = sense[i];
+              if (upd) {
+                q.H = Hd[i];
+                q.G = Gd[i];
+              }
+              return q;
+            },
+            [&](int i, V (&acc)[1], DualPre<V>& q) {
+              V Si = q.S;
+              if (upd) {
+                V h = q.H;
+                Si = learn_elem<V>(Si, h, q.G, lscale, lp->prm, hnorm);
+                S[i] = Si;
+                Hd[i] = h;
+              }
+              const V axn = acc[0];
+              const V axbar = V(2) * axn - q.ax;
+              const V rt = q.b - axbar;
+              const V yh = q.y + (sig * Si) * rt;
+              const bool ineq = q.ineq != 0;
+              const V yv = (ineq && yh < V(0)) ? V(0) : yh;
+              yn[i] = yv;
+              Axn[i] = axn;
+              ysn[i] = q.ys + etav * yv;
+              const double dy = (double)yv - (double)q.y;
+              dd_add_prod(p[0], dy, dy);
+              dd_add_prod(p[1], dy, (double)axn - (double)q.ax);
+              const V r = q.b - q.ax;
+              dd_add_prod(p[2], (double)r, (double)r);
+              if (learn) {
+                const bool ind = !ineq || yh >= V(0);
+                const V gd = ind ? -((sig * r) * rt) : V(0);
+                Gd[i] = gd;
+                dd_add_prod(p[3], (double)gd, (double)gd);
+              }
+            },
+            sh);
+      },
+      [&](const WorkItem& it, bool run) {
+        if (run) flush_partials<4>(p, s_red, lp->part_a, lp->ntiles_a, it.slot);
+        else dd_reset(p);
+      });
+}
+
+// One workgroup per LP: the step decision of the attempt that just ran.
+__global__ __launch_bounds__(kBlock) void k_decide(LaunchCfg cfg) {
+  __shared__ DD s_red[4 * 4];
+  const int nlps = cfg.counts->nlps;
+  for (int li = blockIdx.x; li < nlps; li += gridDim.x) {
+    const LpDev& lp = cfg.lps[li];
     Ctl* c = lp.ctl;
     if (!attempt_guard(c)) continue;
-    const int cur = c->cur, nxt = cur ^ 1;
-    const double eta = c->eta, om = c->omega;
-    const V sig = (V)(eta * om);
-    const V etav = (V)eta;
-    const bool learn = lp.prm->lr > 0.0 && (c->k % lp.prm->phi) == 0;
-    const V* __restrict__ b = static_cast<const V*>(lp.b);
-    const V* __restrict__ S = static_cast<const V*>(lp.S);
-    const V* __restrict__ y = static_cast<const V*>(lp.y[cur]);
-    const V* __restrict__ ys = static_cast<const V*>(lp.ys[cur]);
-    const V* __restrict__ Ax = static_cast<const V*>(lp.Ax[cur]);
-    V* __restrict__ yn = static_cast<V*>(lp.y[nxt]);
-    V* __restrict__ ysn = static_cast<V*>(lp.ys[nxt]);
-    V* __restrict__ Axn = static_cast<V*>(lp.Ax[nxt]);
-    V* __restrict__ Gd = static_cast<V*>(lp.Gd);
-    const int8_t* __restrict__ sense = lp.sense;
-    const V* vecs[1] = {static_cast<const V*>(lp.x[nxt])};
-    DD p[4] = {dd_zero(), dd_zero(), dd_zero(), dd_zero()};
-    const Tile tile = lp.tiles_a[it.tile];
-    tile_spmv<V, 1>(
-        tile, lp.rp_a, lp.ci_a, static_cast<const V*>(lp.va_a), vecs, nodiv,
-        [&](int i, V (&acc)[1]) {
-          const V axn = acc[0];
-          const V ax = Ax[i];
-          const V axbar = V(2) * axn - ax;
-          const V bi = b[i];
-          const V rt = bi - axbar;
-          const V yi = y[i];
-          const V yh = yi + (sig * S[i]) * rt;
-          const bool ineq = sense[i] != 0;
-          const V yv = (ineq && yh < V(0)) ? V(0) : yh;
-          yn[i] = yv;
-          Axn[i] = axn;
-          ysn[i] = ys[i] + etav * yv;
-          const double dy = (double)yv - (double)yi;
-          dd_add_prod(p[0], dy, dy);
-          dd_add_prod(p[1], dy, (double)axn - (double)ax);
-          const V r = bi - ax;
-          dd_add_prod(p[2], (double)r, (double)r);
-          if (learn) {
-            const bool ind = !ineq || yh >= V(0);
-            const V gd = ind ? -((sig * r) * rt) : V(0);
-            Gd[i] = gd;
-            dd_add_prod(p[3], (double)gd, (double)gd);
-          }
-        },
-        s_long);
-    block_sum<4>(p, s_red);
-    store_partials<4>(lp.part_a + (size_t)it.tile * kPartStride, p);
-    if (last_tile(&c->cnt_dual, lp.ntiles_a, &s_flag)) {
-      double st[3], sa[4];
-      sum_partials<3>(lp.part_t, lp.ntiles_t, st, s_red);
-      sum_partials<4>(lp.part_a, lp.ntiles_a, sa, s_red);
-      if (threadIdx.x == 0) {
-        const double s[7] = {st[0], st[1], st[2], sa[0], sa[1], sa[2], sa[3]};
-        decide_step(c, lp.prm, lp.pow_tab, s);
-        c->cnt_dual = 0;
-        __threadfence();
-      }
-      __syncthreads();
+    double st[3], sa[4];
+    sum_partials<3>(lp.part_t, lp.ntiles_t, lp.nslot_t, st, s_red);
+    sum_partials<4>(lp.part_a, lp.ntiles_a, lp.nslot_a, sa, s_red);
+    if (threadIdx.x == 0) {
+      const double sv[7] = {st[0], st[1], st[2], sa[0], sa[1], sa[2], sa[3]};
+      decide_step(c, lp.prm, lp.pow_tab, sv);
     }
+    __syncthreads();
   }
 }
 
+// Applies a pending learner update to every entry of T and Sigma without
+// taking a step (used before the state of a paused solve is read).
 template <typename V>
-__device__ __forceinline__ void ogd_update(V* __restrict__ P, V* __restrict__ H,
-                                           const V* __restrict__ G, int r0, int r1,
-                                           double scale, const DevParams* p, double hnorm) {
-  const V lr = (V)p->lr;
-  const V fl = (V)p->floor;
-  for (int r = r0 + threadIdx.x; r < r1; r += kBlock) {
-    const V gv = (V)((double)G[r] / scale);
-    V step;
-    if (p->schedule == 0) {
-      const V h = H[r] + gv * gv;
+__global__ __launch_bounds__(kBlock) void k_learn_flush(LaunchCfg cfg) {
+  auto body = [&](const WorkItem& it, bool tside) {
+    const LpDev& lp = cfg.lps[it.lp];
+    const Ctl* c = it.ctl;
+    double scale = 1.0;
+    if (!learn_side(c, lp.prm, tside, &scale)) return;
+    V* P = static_cast<V*>(tside ? lp.T : lp.S);
+    V* H = static_cast<V*>(tside ? lp.Hp : lp.Hd);
+    const V* G = static_cast<const V*>(tside ? lp.Gp : lp.Gd);
+    const double hnorm = tside ? c->hp_norm : c->hd_norm;
+    for (int r = it.rb + threadIdx.x; r < it.re; r += kBlock) {
+      V h = H[r];
+      P[r] = learn_elem<V>(P[r], h, G[r], scale, lp.prm, hnorm);
       H[r] = h;
-      step = h > V(0) ? gv / sqrt(h) : V(0);
-    } else if (p->schedule == 1) {
-      step = hnorm > 0.0 ? (V)((double)gv / sqrt(hnorm)) : V(0);
-    } else {
-      step = gv;
     }
-    const V pv = P[r] - lr * step;
-    P[r] = pv < fl ? fl : pv;
-  }
-}
-
-template <typename V>
-__global__ __launch_bounds__(kBlock) void k_learn(const BatchDev* __restrict__ bd) {
-  __shared__ int s_flag;
-  const int nt = bd->nwork_t;
-  const int nwork = nt + bd->nwork_a;
-  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-    const bool tside = wi < nt;
-    const WorkItem it = tside ? bd->work_t[wi] : bd->work_a[wi - nt];
-    const LpDev& lp = bd->lps[it.lp];
-    Ctl* c = lp.ctl;
-    if (!c->learn_pending) continue;
-    const DevParams* p = lp.prm;
-    const Tile tile = tside ? lp.tiles_t[it.tile] : lp.tiles_a[it.tile];
-    const double nrm = tside ? c->g2 : c->r2;
-    const bool skip = p->normalize && !(nrm > 0.0);
-    const double scale = p->normalize ? nrm : 1.0;
-    if (!skip) {
-      if (tside)
-        ogd_update<V>(static_cast<V*>(lp.T), static_cast<V*>(lp.Hp),
-                      static_cast<const V*>(lp.Gp), tile.rb, tile.re, scale, p, c->hp_norm);
-      else
-        ogd_update<V>(static_cast<V*>(lp.S), static_cast<V*>(lp.Hd),
-                      static_cast<const V*>(lp.Gd), tile.rb, tile.re, scale, p, c->hd_norm);
-    }
-    if (last_tile(&c->cnt_learn, lp.ntiles_t + lp.ntiles_a, &s_flag)) {
-      if (threadIdx.x == 0) {
-        c->learn_pending = 0;
-        c->cnt_learn = 0;
-        __threadfence();
-      }
-      __syncthreads();
-    }
-  }
+  };
+  if ((int)blockIdx.x < cfg.grid_t)
+    for (int wi = blockIdx.x * cfg.chunk_t; wi < (int)(blockIdx.x + 1) * cfg.chunk_t; ++wi)
+      if (cfg.work_t[wi].lp >= 0) body(cfg.work_t[wi], true);
+  if ((int)blockIdx.x < cfg.grid_a)
+    for (int wi = blockIdx.x * cfg.chunk_a; wi < (int)(blockIdx.x + 1) * cfg.chunk_a; ++wi)
+      if (cfg.work_a[wi].lp >= 0) body(cfg.work_a[wi], false);
 }
 
 // Reduced cost q = c - A^T y split by the variable's bound type into
@@ -651,15 +882,21 @@ __device__ __forceinline__ void reduced_cost(double q, int8_t bf, double& lam, d
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_eval_t(const BatchDev* __restrict__ bd) {
+__global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
+  __shared__ SpmvShared<V, 2> sh;
   __shared__ DD s_red[4 * 2 * kEvT];
-  __shared__ RowAcc<V> s_long[4 * 2];
-  const int nwork = bd->nwork_t;
-  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-    const WorkItem it = bd->work_t[wi];
-    const LpDev& lp = bd->lps[it.lp];
-    const Ctl* c = lp.ctl;
-    if (!eval_guard(c)) continue;
+  DD p[2 * kEvT];
+  dd_reset(p);
+  const int i0 = blockIdx.x * cfg.chunk_t;
+  for (int wi = i0; wi < i0 + cfg.chunk_t; ++wi) {
+    const WorkItem it = cfg.work_t[wi];
+    if (it.lp < 0) continue;
+    const Ctl* c = it.ctl;
+    if (!eval_guard(c)) {
+      if (it.last) dd_reset(p);
+      continue;
+    }
+    const LpDev& lp = cfg.lps[it.lp];
     const int cur = c->cur;
     const double w = c->w;
     const bool has_avg = w > 0.0;
@@ -672,14 +909,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(const BatchDev* __restrict__ 
     const double* __restrict__ dc = lp.dc;
     const int8_t* __restrict__ bfin = lp.bfin;
     const V* vecs[2] = {static_cast<const V*>(lp.y[cur]), static_cast<const V*>(lp.ys[cur])};
-    const double divs[2] = {0.0, has_avg ? w : 0.0};
-    DD p[2 * kEvT];
-#pragma unroll
-    for (int q = 0; q < 2 * kEvT; ++q) p[q] = dd_zero();
-    const Tile tile = lp.tiles_t[it.tile];
-    tile_spmv<V, 2>(
-        tile, lp.rp_t, lp.ci_t, static_cast<const V*>(lp.va_t), vecs, divs,
-        [&](int j, V (&acc)[2]) {
+    const double divs[2] = {0.0, has_avg ? w : -1.0};
+    spmv_tile<V, 2>(
+        it, lp.rp_t, lp.ci_t, static_cast<const V*>(lp.va_t), vecs, divs,
+        [&](int) { return 0; },
+        [&](int j, V (&acc)[2], int) {
           const double cj = (double)cc[j];
           const int8_t bf = bfin[j];
           const double lj = (double)lo[j], uj = (double)hi[j];
@@ -699,23 +933,27 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(const BatchDev* __restrict__ 
             dd_add_prod(q[5], d, d);
           }
         },
-        s_long);
-    block_sum<2 * kEvT>(p, s_red);
-    store_partials<2 * kEvT>(lp.part_t + (size_t)it.tile * kPartStride, p);
+        sh);
+    if (it.last) flush_partials<2 * kEvT>(p, s_red, lp.part_t, lp.ntiles_t, it.slot);
   }
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_eval_a(const BatchDev* __restrict__ bd) {
-  __shared__ DD s_red[4 * 2 * kEvT];
-  __shared__ RowAcc<V> s_long[4];
-  __shared__ int s_flag;
-  const int nwork = bd->nwork_a;
-  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-    const WorkItem it = bd->work_a[wi];
-    const LpDev& lp = bd->lps[it.lp];
-    Ctl* c = lp.ctl;
-    if (!eval_guard(c)) continue;
+__global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
+  __shared__ SpmvShared<V, 1> sh;
+  __shared__ DD s_red[4 * 2 * kEvA];
+  DD p[2 * kEvA];
+  dd_reset(p);
+  const int i0 = blockIdx.x * cfg.chunk_a;
+  for (int wi = i0; wi < i0 + cfg.chunk_a; ++wi) {
+    const WorkItem it = cfg.work_a[wi];
+    if (it.lp < 0) continue;
+    const Ctl* c = it.ctl;
+    if (!eval_guard(c)) {
+      if (it.last) dd_reset(p);
+      continue;
+    }
+    const LpDev& lp = cfg.lps[it.lp];
     const int cur = c->cur;
     const double w = c->w;
     const bool has_avg = w > 0.0;
@@ -728,14 +966,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(const BatchDev* __restrict__ 
     const double* __restrict__ dr = lp.dr;
     const int8_t* __restrict__ sense = lp.sense;
     const V* vecs[1] = {static_cast<const V*>(lp.xs[cur])};
-    const double divs[1] = {has_avg ? w : 0.0};
-    DD p[2 * kEvA];
-#pragma unroll
-    for (int q = 0; q < 2 * kEvA; ++q) p[q] = dd_zero();
-    const Tile tile = lp.tiles_a[it.tile];
-    tile_spmv<V, 1>(
-        tile, lp.rp_a, lp.ci_a, static_cast<const V*>(lp.va_a), vecs, divs,
-        [&](int i, V (&acc)[1]) {
+    const double divs[1] = {has_avg ? w : -1.0};
+    spmv_tile<V, 1>(
+        it, lp.rp_a, lp.ci_a, static_cast<const V*>(lp.va_a), vecs, divs,
+        [&](int) { return 0; },
+        [&](int i, V (&acc)[1], int) {
           const double bi = (double)b[i];
           const bool ineq = sense[i] != 0;
           const double yai = (double)ya[i];
@@ -754,45 +989,47 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(const BatchDev* __restrict__ 
             dd_add_prod(q[3], d, d);
           }
         },
-        s_long);
-    block_sum<2 * kEvA>(p, s_red);
-    store_partials<2 * kEvA>(lp.part_a + (size_t)it.tile * kPartStride, p);
-    if (last_tile(&c->cnt_eval, lp.ntiles_a, &s_flag)) {
-      double st[2 * kEvT], sa[2 * kEvA];
-      sum_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, st, s_red);
-      sum_partials<2 * kEvA>(lp.part_a, lp.ntiles_a, sa, s_red);
-      if (threadIdx.x == 0) {
-        decide_eval(c, lp.prm, st, sa);
-        c->cnt_eval = 0;
-        __threadfence();
-      }
-      __syncthreads();
-    }
+        sh);
+    if (it.last) flush_partials<2 * kEvA>(p, s_red, lp.part_a, lp.ntiles_a, it.slot);
   }
 }
 
-template <typename V>
-__global__ __launch_bounds__(kBlock) void k_apply(const BatchDev* __restrict__ bd) {
-  __shared__ int s_flag;
-  const int nt = bd->nwork_t;
-  const int nwork = nt + bd->nwork_a;
-  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-    const bool tside = wi < nt;
-    const WorkItem it = tside ? bd->work_t[wi] : bd->work_a[wi - nt];
-    const LpDev& lp = bd->lps[it.lp];
+// One workgroup per LP: termination and restart decision of an evaluation.
+__global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg) {
+  __shared__ DD s_red[4 * 2 * kEvT];
+  const int nlps = cfg.counts->nlps;
+  for (int li = blockIdx.x; li < nlps; li += gridDim.x) {
+    const LpDev& lp = cfg.lps[li];
     Ctl* c = lp.ctl;
+    if (!eval_guard(c)) continue;
+    double st[2 * kEvT], sa[2 * kEvA];
+    sum_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, lp.nslot_t, st, s_red);
+    sum_partials<2 * kEvA>(lp.part_a, lp.ntiles_a, lp.nslot_a, sa, s_red);
+    if (threadIdx.x == 0) decide_eval(c, lp.prm, st, sa);
+    __syncthreads();
+  }
+}
+
+// Restart application or the final copy of the returned average. The
+// flags stay set until the next k_primal clears them, and restarting to the
+// average reads the sums it then clears, so this kernel runs exactly once
+// per evaluation step, right before the attempts.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_apply(LaunchCfg cfg) {
+  auto body = [&](const WorkItem& it, bool tside) {
+    const Ctl* c = it.ctl;
     const bool restart = c->restart_pending != 0;
     const bool fin = c->finalize_avg != 0;
-    if (!restart && !fin) continue;
+    if (!restart && !fin) return;
+    const LpDev& lp = cfg.lps[it.lp];
     const int cur = c->cur;
     const bool to_avg = restart ? (c->restart_avg != 0) : true;
     const double w = c->restart_w;
-    const Tile tile = tside ? lp.tiles_t[it.tile] : lp.tiles_a[it.tile];
     if (tside) {
       V* x = static_cast<V*>(lp.x[cur]);
       V* xs = static_cast<V*>(lp.xs[cur]);
       V* xa = static_cast<V*>(lp.xa);
-      for (int j = tile.rb + threadIdx.x; j < tile.re; j += kBlock) {
+      for (int j = it.rb + threadIdx.x; j < it.re; j += kBlock) {
         V xv = x[j];
         if (to_avg) {
           xv = (V)((double)xs[j] / w);
@@ -809,7 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BatchDev* __restrict__ b
       V* ya = static_cast<V*>(lp.ya);
       V* Ax = static_cast<V*>(lp.Ax[cur]);
       const V* Axa = static_cast<const V*>(lp.Axa);
-      for (int i = tile.rb + threadIdx.x; i < tile.re; i += kBlock) {
+      for (int i = it.rb + threadIdx.x; i < it.re; i += kBlock) {
         V yv = y[i];
         if (to_avg) {
           yv = (V)((double)ys[i] / w);
@@ -822,16 +1059,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BatchDev* __restrict__ b
         }
       }
     }
-    if (last_tile(&c->cnt_apply, lp.ntiles_t + lp.ntiles_a, &s_flag)) {
-      if (threadIdx.x == 0) {
-        c->restart_pending = 0;
-        c->finalize_avg = 0;
-        c->cnt_apply = 0;
-        __threadfence();
-      }
-      __syncthreads();
-    }
-  }
+  };
+  if ((int)blockIdx.x < cfg.grid_t)
+    for (int wi = blockIdx.x * cfg.chunk_t; wi < (int)(blockIdx.x + 1) * cfg.chunk_t; ++wi)
+      if (cfg.work_t[wi].lp >= 0) body(cfg.work_t[wi], true);
+  if ((int)blockIdx.x < cfg.grid_a)
+    for (int wi = blockIdx.x * cfg.chunk_a; wi < (int)(blockIdx.x + 1) * cfg.chunk_a; ++wi)
+      if (cfg.work_a[wi].lp >= 0) body(cfg.work_a[wi], false);
 }
 
 }  // namespace
@@ -849,48 +1083,47 @@ static int launched() {
   return 0;
 }
 
+#define OPDHG_LAUNCH(kernel, grid, ...)                                                   \
+  do {                                                                                    \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, __VA_ARGS__); \
+    return launched();                                                                    \
+  } while (0)
+
 template <typename V>
 int Kernels<V>::init_products(const LaunchCfg& c, void* stream) {
-  hipLaunchKernelGGL(k_init_products<V>, dim3(c.grid_a), dim3(kBlock), 0,
-                     (hipStream_t)stream, c.bd);
-  return launched();
+  OPDHG_LAUNCH(k_init_products<V>, c.grid_a, c);
 }
-
 template <typename V>
 int Kernels<V>::primal(const LaunchCfg& c, void* stream, int force) {
-  hipLaunchKernelGGL(k_primal<V>, dim3(c.grid_t), dim3(kBlock), 0, (hipStream_t)stream, c.bd,
-                     force);
-  return launched();
+  OPDHG_LAUNCH(k_primal<V>, c.grid_t, c, force);
 }
-
 template <typename V>
 int Kernels<V>::dual(const LaunchCfg& c, void* stream) {
-  hipLaunchKernelGGL(k_dual<V>, dim3(c.grid_a), dim3(kBlock), 0, (hipStream_t)stream, c.bd);
-  return launched();
+  OPDHG_LAUNCH(k_dual<V>, c.grid_a, c);
 }
-
 template <typename V>
-int Kernels<V>::learn(const LaunchCfg& c, void* stream) {
-  hipLaunchKernelGGL(k_learn<V>, dim3(c.grid_ta), dim3(kBlock), 0, (hipStream_t)stream, c.bd);
-  return launched();
+int Kernels<V>::decide(const LaunchCfg& c, void* stream) {
+  OPDHG_LAUNCH(k_decide, c.grid_lp, c);
 }
-
+template <typename V>
+int Kernels<V>::learn_flush(const LaunchCfg& c, void* stream) {
+  OPDHG_LAUNCH(k_learn_flush<V>, c.grid_ta, c);
+}
 template <typename V>
 int Kernels<V>::eval_t(const LaunchCfg& c, void* stream) {
-  hipLaunchKernelGGL(k_eval_t<V>, dim3(c.grid_t), dim3(kBlock), 0, (hipStream_t)stream, c.bd);
-  return launched();
+  OPDHG_LAUNCH(k_eval_t<V>, c.grid_t, c);
 }
-
 template <typename V>
 int Kernels<V>::eval_a(const LaunchCfg& c, void* stream) {
-  hipLaunchKernelGGL(k_eval_a<V>, dim3(c.grid_a), dim3(kBlock), 0, (hipStream_t)stream, c.bd);
-  return launched();
+  OPDHG_LAUNCH(k_eval_a<V>, c.grid_a, c);
 }
-
+template <typename V>
+int Kernels<V>::eval_decide(const LaunchCfg& c, void* stream) {
+  OPDHG_LAUNCH(k_eval_decide, c.grid_lp, c);
+}
 template <typename V>
 int Kernels<V>::apply(const LaunchCfg& c, void* stream) {
-  hipLaunchKernelGGL(k_apply<V>, dim3(c.grid_ta), dim3(kBlock), 0, (hipStream_t)stream, c.bd);
-  return launched();
+  OPDHG_LAUNCH(k_apply<V>, c.grid_ta, c);
 }
 
 template struct Kernels<double>;

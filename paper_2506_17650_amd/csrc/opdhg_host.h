@@ -17,12 +17,18 @@ int validate_lp(const opdhg_lp* lp);
 int validate_params(const opdhg_params* p);
 
 // An LP after validation, rescaling and transposition, in FP64 on the host.
+// Arrays marked "device order" follow the relabelling by row class:
+// device row i of A is original row perm_a[i], device variable j is
+// original variable perm_t[j].
 struct Prepared {
   int64_t m = 0, n = 0, nnz = 0;
-  std::vector<int32_t> rp_a, ci_a, rp_t, ci_t;
-  std::vector<double> va_a, va_t;
-  std::vector<double> b, c, l, u, dr, dc, x0;
-  std::vector<int8_t> sense, bfin;
+  std::vector<int32_t> perm_a, perm_t;
+  std::vector<int32_t> rp_a, ci_a, rp_t, ci_t;  // device order
+  std::vector<double> va_a, va_t;               // device order
+  std::vector<double> b, c, l, u, x0;           // device order
+  std::vector<double> dr_dev, dc_dev;           // device order
+  std::vector<double> dr, dc;                   // original order (unscaling)
+  std::vector<int8_t> sense, bfin;              // device order
   std::vector<Tile> tiles_a, tiles_t;
   std::vector<double> pow_tab;  // step-rule factors, 2 * kPowTab
   DevParams prm;
@@ -47,14 +53,16 @@ SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int6
 LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P);
 int upload_slot(uint8_t* base, const SlotLayout& L, const Prepared& P, int prec,
                 hipStream_t stream, std::vector<uint8_t>& img);
-int write_tables(uint8_t* dst, const std::vector<LpDev>& lps, hipStream_t stream,
-                 std::vector<uint8_t>& staging, const BatchDev** bd_out, int64_t* nwt,
-                 int64_t* nwa);
+int write_tables(uint8_t* dst, const std::vector<LpDev>& lps,
+                 const std::vector<const Prepared*>& preps, int64_t cap, hipStream_t stream,
+                 std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa);
 int download_vec(const void* dptr, size_t count, int prec, hipStream_t stream, double* out);
 void fill_result(const Ctl& c, double seconds, opdhg_result* r);
 void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,
                   std::vector<double>& dr, std::vector<double>& dc);
-std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t target, int lanes_fixed);
+std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t cap, int lanes_fixed);
+void unpermute(const double* dev, const std::vector<int32_t>& perm, const double* scale,
+               double* out);
 Ctl initial_ctl(const Prepared& P);
 
 // A set of LPs launched together, with its captured launch sequence:
@@ -66,10 +74,10 @@ struct Group {
   LaunchCfg cfg{};
   int prec = 0;
   int init(void* stream, int prec);
-  void set_grid(int64_t nwork_t, int64_t nwork_a, bool fixed);
   int capture(int attempts_per_replay);
   int launch_init();
   int launch_primal_forced();
+  int launch_learn_flush();
   int replay();
   void release();
 };

@@ -19,7 +19,9 @@ namespace opdhg {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kPartStride = 32;    // doubles of reduction partials per tile (16 double-doubles)
 constexpr int kPowTab = 8192;      // host-computed step-rule factors for the first attempts
-constexpr int kGridCap = 4096;     // workgroups of a persistent launch
+constexpr int kGridCap = 2048;     // default workgroups of a launch (chunks of the work list)
+constexpr int kMaxGrid = 65536;    // largest workgroup count a caller may ask for
+constexpr int kTileCap = 1024;     // nonzeros of a stream tile (staged in LDS)
 
 // Status values (match OPDHG_STATUS_* of the public header).
 constexpr int kOptimal = 0;
@@ -48,8 +50,8 @@ struct DevParams {
 };
 
 // Per-LP control block: the scalar state of the iteration. Written by the
-// last tile of the dual kernel (step decision), of the evaluation kernel
-// (termination / restart decision), and by the host between launches.
+// decision kernels (step, termination / restart), the first tile of the
+// primal kernel (clears the restart flags), and the host between launches.
 struct Ctl {
   double eta;       // step size of the next attempt
   double omega;     // primal weight
@@ -82,23 +84,23 @@ struct Ctl {
   int32_t anchor_set;
   int32_t which;         // 0 current, 1 average (returned iterate)
   int32_t stop_request;  // host asks for a final evaluation (time limit)
-  int32_t cnt_dual;      // completion counters of the per-LP last-tile steps
-  int32_t cnt_eval;
-  int32_t cnt_learn;
-  int32_t cnt_apply;
-  int32_t pad0, pad1;
+  int32_t learn_now;     // the next attempt is an update iteration (k mod phi == 0)
+  int32_t pad1, pad2, pad3, pad4, pad5;
 };
 
-// Tile: rows [rb, re) of one CSR side. lanes > 0: row groups of `lanes`
-// threads; lanes == 0: one long row reduced by the whole workgroup.
+// Tile: rows [rb, re) of one CSR side with nonzeros [s, e).
+// lanes > 0: stream tile (e - s <= kTileCap, re - rb <= kBlock / lanes),
+// each row reduced from LDS by `lanes` threads; lanes == 0: one row longer
+// than kTileCap, reduced by the whole workgroup.
 struct Tile {
-  int32_t rb, re, lanes, pad;
+  int32_t rb, re, s, e, lanes, pad;
 };
 
 // One LP slot as the kernels see it (device pointers into the workspace).
 struct LpDev {
   int32_t m, n;
-  int32_t ntiles_t, ntiles_a;  // tiles over A^T rows (n) and A rows (m)
+  int32_t ntiles_t, ntiles_a;  // tiles over A^T rows (n) and A rows (m); partial stride
+  int32_t nslot_t, nslot_a;    // partial slots in use (workgroups touching the LP)
   const int32_t* rp_a;
   const int32_t* ci_a;
   const void* va_a;
@@ -139,29 +141,40 @@ struct LpDev {
   const DevParams* prm;
 };
 
-// A set of LPs launched together. Work items are (lp, tile) pairs; the
-// kernels loop over them with a fixed grid so the set can change between
-// launches without new launch parameters.
+// A set of LPs launched together. A work item is one tile of one LP, with
+// the tile's rows and the LP's control block inline so a workgroup reaches
+// everything it needs in one dependent load. The kernels loop over the
+// items with a fixed grid, so the set can change between launches without
+// new launch parameters; lp < 0 marks padding.
 struct WorkItem {
-  int32_t lp, tile;
-};
-
-struct BatchDev {
-  const LpDev* lps;
-  const WorkItem* work_t;  // all A^T-side tiles of all LPs
-  const WorkItem* work_a;  // all A-side tiles
-  int32_t nwork_t;
-  int32_t nwork_a;
-  int32_t nlps;
+  Ctl* ctl;
+  int32_t lp;     // index into the LP table
+  int32_t tile;   // index of the tile within its side of the LP
+  int32_t rb, re; // rows [rb, re)
+  int32_t s, e;   // nonzeros [s, e)
+  int32_t lanes;  // see Tile
+  int32_t slot;   // partial slot of this item's workgroup for its LP
+  int32_t last;   // last item of its LP in this workgroup's chunk
   int32_t pad;
 };
 
+// Item counts of a set, in device memory: {nwork_t, nwork_a, nlps}.
+struct Counts {
+  int32_t nwork_t, nwork_a, nlps, pad;
+};
+
 // Host-side launch wrappers (kernels.hip). V is float or double.
+// Workgroup b of a side takes items [b * chunk, (b + 1) * chunk) of that
+// side's list, which is padded to grid * chunk items.
 struct LaunchCfg {
-  const BatchDev* bd;  // device pointer
-  int grid_t;          // workgroups over work_t
-  int grid_a;          // workgroups over work_a
-  int grid_ta;         // workgroups over work_t + work_a
+  const LpDev* lps;        // device pointers
+  const WorkItem* work_t;  // A^T-side tiles of all LPs
+  const WorkItem* work_a;  // A-side tiles
+  const Counts* counts;
+  int grid_t, chunk_t;     // workgroups and items per workgroup over work_t
+  int grid_a, chunk_a;     // same over work_a
+  int grid_ta;             // max(grid_t, grid_a): kernels that visit both sides
+  int grid_lp;             // workgroups over LPs (decision kernels)
 };
 
 template <typename V>
@@ -169,9 +182,11 @@ struct Kernels {
   static int init_products(const LaunchCfg& c, void* stream);
   static int primal(const LaunchCfg& c, void* stream, int force);
   static int dual(const LaunchCfg& c, void* stream);
-  static int learn(const LaunchCfg& c, void* stream);
+  static int decide(const LaunchCfg& c, void* stream);
+  static int learn_flush(const LaunchCfg& c, void* stream);
   static int eval_t(const LaunchCfg& c, void* stream);
   static int eval_a(const LaunchCfg& c, void* stream);
+  static int eval_decide(const LaunchCfg& c, void* stream);
   static int apply(const LaunchCfg& c, void* stream);
 };
 
