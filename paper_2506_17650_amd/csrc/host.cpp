@@ -615,12 +615,16 @@ struct SessionImpl {
   int replays = 0;
 };
 
-// Chunking of a work list of n items over at most `cap` workgroups.
+// Chunking of a work list of n items over at most `cap` workgroups. A grid
+// of more than 8 workgroups is rounded up to a multiple of 8 (with empty
+// chunks) so the kernels can give each XCD a contiguous range of chunks.
 static void chunking(int64_t n, int64_t cap, int* grid, int* chunk) {
   const int64_t g0 = std::max<int64_t>(1, std::min<int64_t>(n, cap));
   const int64_t c = std::max<int64_t>(1, (n + g0 - 1) / g0);
+  int64_t g = std::max<int64_t>(1, (n + c - 1) / c);
+  if (g > 8) g = (g + 7) / 8 * 8;
   *chunk = (int)c;
-  *grid = (int)std::max<int64_t>(1, (n + c - 1) / c);
+  *grid = (int)g;
 }
 
 static int64_t grid_cap(const opdhg_params* p) {
@@ -636,6 +640,26 @@ static size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64
          align_up(sizeof(WorkItem) * (size_t)ga * ca) + align_up(sizeof(Counts));
 }
 
+// Order in which an LP's tiles enter the work list. Long rows (tiles of
+// one row, relabelled to the front of the side) are spread evenly among the
+// stream tiles, which keep their row order so consecutive chunks (one XCD)
+// gather from nearby rows. Every row is finished inside its tile and all
+// reductions are exact, so the order does not change any result.
+static std::vector<int64_t> spread_long_tiles(const std::vector<Tile>& tiles) {
+  std::vector<int64_t> longs, stream, order;
+  for (size_t t = 0; t < tiles.size(); ++t) (tiles[t].lanes == 0 ? longs : stream).push_back(t);
+  order.reserve(tiles.size());
+  const int64_t nl = (int64_t)longs.size(), ns = (int64_t)stream.size();
+  int64_t il = 0;
+  for (int64_t j = 0; j < ns; ++j) {
+    // long tile il goes before stream tile floor(il * ns / nl)
+    while (il < nl && il * ns <= j * nl) order.push_back(longs[il++]);
+    order.push_back(stream[j]);
+  }
+  while (il < nl) order.push_back(longs[il++]);
+  return order;
+}
+
 // Items of one side for all LPs, chunked: fills slot / last and each LP's
 // slot count.
 static void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps,
@@ -646,7 +670,7 @@ static void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared
   for (size_t i = 0; i < lps.size(); ++i) {
     const std::vector<Tile>& tiles = tside ? preps[i]->tiles_t : preps[i]->tiles_a;
     range[i].first = (int64_t)out.size();
-    for (size_t t = 0; t < tiles.size(); ++t) {
+    for (int64_t t : spread_long_tiles(tiles)) {
       const Tile& tl = tiles[t];
       out.push_back(WorkItem{lps[i].ctl, (int32_t)i, (int32_t)t, tl.rb, tl.re, tl.s, tl.e,
                              tl.lanes, 0, 0, 0});

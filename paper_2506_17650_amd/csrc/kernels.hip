@@ -93,6 +93,41 @@ __device__ __forceinline__ DD dd_merge(DD a, const DD& b) {
 
 __device__ __forceinline__ double dd_value(const DD& a) { return a.hi + a.lo; }
 
+// ---- memory access ----
+// Pointers into the workspace reach the kernels through tables, so the
+// compiler sees generic pointers and emits flat accesses, which count
+// toward both the vector-memory and the LDS counters: every wait for an LDS
+// result then also waits for outstanding HBM loads and stores. Global views
+// of the same addresses compile to global_* accesses that only count toward
+// the vector-memory counter.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T* p) {
+  return (gptr<T>)p;
+}
+
+// Barrier for data exchanged through LDS only: waits for this wave's LDS
+// accesses, not for its global loads and stores, which stay in flight
+// across the barrier. (__syncthreads also drains every global access.)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Chunk of the work list taken by this workgroup. Workgroups are handed to
+// the 8 XCDs round-robin (workgroup b to XCD b mod 8), so with a grid that
+// is a multiple of 8, XCD x takes the contiguous chunks
+// [x * grid/8, (x + 1) * grid/8): the rows an XCD's tiles gather from stay
+// in that XCD's L2 instead of being spread over all eight.
+__device__ __forceinline__ int chunk_index() {
+  const int g = gridDim.x, b = blockIdx.x;
+  if (g & 7) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ DD dd_shfl_xor(const DD& a, int off) {
   return DD{__shfl_xor(a.hi, off, 64), __shfl_xor(a.lo, off, 64)};
 }
@@ -112,14 +147,14 @@ __device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) s_red[wave * NV + q] = v[q];
   }
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q)
       v[q] = dd_merge(dd_merge(dd_merge(s_red[q], s_red[NV + q]), s_red[2 * NV + q]),
                       s_red[3 * NV + q]);
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Store workgroup totals in partial slot `slot` (thread 0). Partials are
@@ -129,10 +164,11 @@ template <int NV>
 __device__ __forceinline__ void store_partials(double* part, int stride, int slot,
                                                const DD (&v)[NV]) {
   if (threadIdx.x == 0) {
+    gptr<double> g = gp(part);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      part[(size_t)(2 * q) * stride + slot] = v[q].hi;
-      part[(size_t)(2 * q + 1) * stride + slot] = v[q].lo;
+      g[(size_t)(2 * q) * stride + slot] = v[q].hi;
+      g[(size_t)(2 * q + 1) * stride + slot] = v[q].lo;
     }
   }
 }
@@ -149,16 +185,21 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   DD v[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = dd_zero();
+  const gptr<const double> g = gp(part);
   for (int base = threadIdx.x; base < count; base += kBlock * B) {
     double h[B][NV], l[B][NV];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
+      // out-of-range slots re-read slot `base` (valid) and are zeroed
       const int t = base + k * kBlock;
       const bool ok = t < count;
+      const int tc = ok ? t : base;
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        h[k][q] = ok ? part[(size_t)(2 * q) * stride + t] : 0.0;
-        l[k][q] = ok ? part[(size_t)(2 * q + 1) * stride + t] : 0.0;
+        const double hv = g[(size_t)(2 * q) * stride + tc];
+        const double lv = g[(size_t)(2 * q + 1) * stride + tc];
+        h[k][q] = ok ? hv : 0.0;
+        l[k][q] = ok ? lv : 0.0;
       }
     }
 #pragma unroll
@@ -186,6 +227,13 @@ struct Num<double> {
     const double p = a * x;
     return Prod{p, fma(a, x, -p)};
   }
+  // q, or zero, by a bit mask (a select of a loaded value can be turned
+  // into a branch with the load inside)
+  static __device__ __forceinline__ Prod mask(bool keep, const Prod& q) {
+    const unsigned long long m = -(unsigned long long)keep;
+    return Prod{__longlong_as_double(__double_as_longlong(q.p) & m),
+                __longlong_as_double(__double_as_longlong(q.e) & m)};
+  }
   struct Acc {
     DD v;
     __device__ __forceinline__ void zero() { v = dd_zero(); }
@@ -203,6 +251,9 @@ template <>
 struct Num<float> {
   using Prod = float;
   static __device__ __forceinline__ float mul(float a, float x) { return a * x; }
+  static __device__ __forceinline__ float mask(bool keep, float q) {
+    return __uint_as_float(__float_as_uint(q) & -(unsigned)keep);
+  }
   struct Acc {
     float v;
     __device__ __forceinline__ void zero() { v = 0.f; }
@@ -220,7 +271,7 @@ using Acc = typename Num<V>::Acc;
 
 // Vector q at column c: vec[q][c], or vec[q][c] / div[q] for the average.
 template <typename V>
-__device__ __forceinline__ V vec_at(const V* const* vec, const double* div, int q, int c) {
+__device__ __forceinline__ V vec_at(const gptr<const V>* vec, const double* div, int q, int c) {
   const V v = vec[q][c];
   return div[q] > 0.0 ? (V)((double)v / div[q]) : v;
 }
@@ -234,22 +285,26 @@ struct SpmvShared {
 };
 
 // One tile: sparse dot products of its rows with NA vectors and the row
-// epilogues. pre = load(row) runs in the thread that finishes the row,
-// before the tile's nonzeros are read; finish(row, val[NA], pre) runs once
-// the row's sums are known. Called by the whole workgroup.
+// epilogues. pre = load(row) is issued together with the tile's index and
+// value loads (every thread of a row's group loads it, for a clamped valid
+// row, so no load sits behind a branch); finish(row, val[NA], pre) runs in
+// the first thread of the row's group once the row's sums are known.
+// Loads past the end of the tile re-read its last nonzero and are masked,
+// so all of a thread's loads issue back to back. Called by the whole
+// workgroup (every branch below is uniform over it).
 template <typename V, int NA, typename Load, typename Finish>
-__device__ __forceinline__ void spmv_tile(const WorkItem& it, const int32_t* __restrict__ rp,
-                                          const int32_t* __restrict__ ci,
-                                          const V* __restrict__ va, const V* const* vec,
-                                          const double* div, Load&& load, Finish&& finish,
-                                          SpmvShared<V, NA>& sh) {
+__device__ __forceinline__ void spmv_tile(const WorkItem& it, gptr<const int32_t> rp,
+                                          gptr<const int32_t> ci, gptr<const V> va,
+                                          const gptr<const V>* vec, const double* div,
+                                          Load&& load, Finish&& finish, SpmvShared<V, NA>& sh) {
   const int tid = threadIdx.x;
+  if (it.re <= it.rb) return;  // the placeholder tile of a side without rows
+  const int last = it.e - 1;
   if (it.lanes == 0) {
-    // one long row: every thread takes every kBlock-th nonzero, four at a
+    // one long row: every thread takes every kBlock-th nonzero, U at a
     // time so their loads overlap; waves combine through LDS
     const int r = it.rb;
-    decltype(load(r)) pre{};
-    if (tid == 0) pre = load(r);
+    auto pre = load(r);
     Acc<V> acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q].zero();
@@ -259,18 +314,20 @@ __device__ __forceinline__ void spmv_tile(const WorkItem& it, const int32_t* __r
       int c[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int kk = k + u * kBlock;
-        a[u] = kk < it.e ? va[kk] : V(0);
-        c[u] = kk < it.e ? ci[kk] : 0;
+        const int kk = min(k + u * kBlock, last);
+        a[u] = va[kk];
+        c[u] = ci[kk];
       }
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         V x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = k + u * kBlock < it.e ? vec_at(vec, div, q, c[u]) : V(0);
+        for (int u = 0; u < U; ++u) x[u] = vec_at(vec, div, q, c[u]);
+        // a select, not a branch: a branch would let the compiler sink the
+        // loads into it, one wait each
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (k + u * kBlock < it.e) acc[q].add(Num<V>::mul(a[u], x[u]));
+          acc[q].add(Num<V>::mask(k + u * kBlock < it.e, Num<V>::mul(a[u], x[u])));
       }
     }
 #pragma unroll
@@ -282,7 +339,7 @@ __device__ __forceinline__ void spmv_tile(const WorkItem& it, const int32_t* __r
 #pragma unroll
       for (int q = 0; q < NA; ++q) sh.wave[tid >> 6][q] = acc[q];
     }
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) {
       V out[NA];
 #pragma unroll
@@ -295,49 +352,67 @@ __device__ __forceinline__ void spmv_tile(const WorkItem& it, const int32_t* __r
       }
       finish(r, out, pre);
     }
-    __syncthreads();
+    lds_barrier();
     return;
   }
   // stream tile: group g of `lanes` threads owns row rb + g (at most one)
-  const int L = it.lanes;
-  const int g = tid / L;
+  const int L = it.lanes;  // a power of two
+  const int g = tid >> __builtin_ctz(L);
   const int lane = tid & (L - 1);
   const int r = it.rb + g;
   const bool has_row = r < it.re;
-  decltype(load(r)) pre{};
-  int r0 = 0, r1 = 0;
-  if (has_row) {
-    if (lane == 0) pre = load(r);
-    r0 = rp[r] - it.s;
-    r1 = rp[r + 1] - it.s;
-  }
+  const int rc = has_row ? r : it.re - 1;
   const int n = it.e - it.s;
   constexpr int K = kTileCap / kBlock;
   V a[K];
   int c[K];
-#pragma unroll
-  for (int u = 0; u < K; ++u) {
-    const int k = tid + u * kBlock;
-    a[u] = k < n ? va[it.s + k] : V(0);
-    c[u] = k < n ? ci[it.s + k] : 0;
-  }
-#pragma unroll
-  for (int q = 0; q < NA; ++q) {
-    V x[K];
-#pragma unroll
-    for (int u = 0; u < K; ++u) x[u] = tid + u * kBlock < n ? vec_at(vec, div, q, c[u]) : V(0);
+  // every load of the tile that does not depend on another is issued here,
+  // before any of them is used
+  auto pre = load(rc);
+  const int rp0 = rp[rc], rp1 = rp[rc + 1];
+  if (n > 0) {  // a tile of empty rows has no nonzeros to read
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-      const int k = tid + u * kBlock;
-      if (k < n) sh.prod[q][k] = Num<V>::mul(a[u], x[u]);
+      const int k = min(it.s + tid + u * kBlock, last);
+      a[u] = va[k];
+      c[u] = ci[k];
     }
   }
-  __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
+  const int r0 = rp0 - it.s;
+  const int r1 = r0 + ((rp1 - rp0) & -(int)has_row);  // empty range without a row
+  if (n > 0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      V x[K];
+#pragma unroll
+      for (int u = 0; u < K; ++u) x[u] = vec_at(vec, div, q, c[u]);
+      // slots past the tile's end get products of the repeated last
+      // nonzero; no row reads them
+#pragma unroll
+      for (int u = 0; u < K; ++u) sh.prod[q][tid + u * kBlock] = Num<V>::mul(a[u], x[u]);
+    }
+  }
+  lds_barrier();
   if (has_row) {
     Acc<V> acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q].zero();
-    for (int k = r0 + lane; k < r1; k += L) {
+    int k = r0 + lane;
+    // four products per pass so their LDS reads are in flight together;
+    // they are added in the same order as one at a time
+    for (; k + 3 * L < r1; k += 4 * L) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const Prod<V> p0 = sh.prod[q][k], p1 = sh.prod[q][k + L];
+        const Prod<V> p2 = sh.prod[q][k + 2 * L], p3 = sh.prod[q][k + 3 * L];
+        acc[q].add(p0);
+        acc[q].add(p1);
+        acc[q].add(p2);
+        acc[q].add(p3);
+      }
+    }
+    for (; k < r1; k += L) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) acc[q].add(sh.prod[q][k]);
     }
@@ -352,7 +427,7 @@ __device__ __forceinline__ void spmv_tile(const WorkItem& it, const int32_t* __r
       finish(r, out, pre);
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 template <typename V>
@@ -539,29 +614,82 @@ __device__ void decide_eval(Ctl* c, const DevParams* p, const double* st, const 
   }
 }
 
-// Drives a workgroup over its chunk of a side's work list. The next item is
-// read while the current one runs; when the LP changes, begin(item) loads
-// the LP's pointers and scalars into registers and returns whether the LP
-// takes part; tile(item) processes a tile of a running LP; end(item, run)
-// closes the LP's part of the chunk.
+// Work items of a chunk are staged in LDS, kItemWin at a time, so that a
+// tile's start waits on LDS only: a work item loaded through the vector
+// memory path would make the tile's first wait also wait for the previous
+// tile's stores.
+constexpr int kItemWin = 32;
+constexpr int kItemWords = sizeof(WorkItem) / 4;
+static_assert(sizeof(WorkItem) % 4 == 0, "work items are copied as 32-bit words");
+
+// A value that is the same in every thread, moved to scalar registers. A
+// pointer loaded once per LP then needs no wait where the tiles use it.
+template <typename T>
+__device__ __forceinline__ T uni(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
+// The same work item in every thread, moved to scalar registers: the
+// compiler then branches on its fields and divides by its lane count with
+// scalar instructions.
+__device__ __forceinline__ WorkItem uniform_item(const WorkItem& w) {
+  WorkItem u;
+  const uint64_t cp = reinterpret_cast<uint64_t>(w.ctl);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)cp);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(cp >> 32));
+  u.ctl = reinterpret_cast<Ctl*>(((uint64_t)hi << 32) | lo);
+  u.lp = __builtin_amdgcn_readfirstlane(w.lp);
+  u.tile = __builtin_amdgcn_readfirstlane(w.tile);
+  u.rb = __builtin_amdgcn_readfirstlane(w.rb);
+  u.re = __builtin_amdgcn_readfirstlane(w.re);
+  u.s = __builtin_amdgcn_readfirstlane(w.s);
+  u.e = __builtin_amdgcn_readfirstlane(w.e);
+  u.lanes = __builtin_amdgcn_readfirstlane(w.lanes);
+  u.slot = __builtin_amdgcn_readfirstlane(w.slot);
+  u.last = __builtin_amdgcn_readfirstlane(w.last);
+  u.pad = 0;
+  return u;
+}
+
+// Drives a workgroup over its chunk of a side's work list. When the LP
+// changes, begin(item) loads the LP's pointers and scalars into registers
+// and returns whether the LP takes part; tile(item) processes a tile of a
+// running LP; end(item, run) closes the LP's part of the chunk.
 template <typename Begin, typename TileFn, typename End>
 __device__ __forceinline__ void run_chunk(const WorkItem* __restrict__ work, int chunk,
-                                          Begin&& begin, TileFn&& tile, End&& end) {
-  const int w0 = blockIdx.x * chunk;
-  WorkItem it = work[w0];
+                                          WorkItem* s_items, Begin&& begin, TileFn&& tile,
+                                          End&& end) {
+  const int w0 = chunk_index() * chunk;
   int lp = -1;
   bool run = false;
-  for (int k = 0; k < chunk; ++k) {
-    const WorkItem nx = work[w0 + (k + 1 < chunk ? k + 1 : k)];
-    if (it.lp >= 0) {
-      if (it.lp != lp) {
-        lp = it.lp;
-        run = begin(it);
-      }
-      if (run) tile(it);
-      if (it.last) end(it, run);
+  for (int k0 = 0; k0 < chunk; k0 += kItemWin) {
+    const int cnt = min(kItemWin, chunk - k0);
+    {
+      const gptr<const int32_t> src = gp(reinterpret_cast<const int32_t*>(work + w0 + k0));
+      int32_t* dst = reinterpret_cast<int32_t*>(s_items);
+      for (int q = threadIdx.x; q < cnt * kItemWords; q += kBlock) dst[q] = src[q];
     }
-    it = nx;
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+      const WorkItem it = uniform_item(s_items[k]);
+      if (it.lp >= 0) {
+        if (it.lp != lp) {
+          lp = it.lp;
+          run = begin(it);
+        }
+        if (run) tile(it);
+        if (it.last) end(it, run);
+      }
+    }
+    lds_barrier();  // the window is rewritten next
   }
 }
 
@@ -605,16 +733,16 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_init_products(LaunchCfg cfg) {
   __shared__ SpmvShared<V, 1> sh;
   const double nodiv[1] = {0.0};
-  const int i0 = blockIdx.x * cfg.chunk_a;
+  const int i0 = chunk_index() * cfg.chunk_a;
   for (int wi = i0; wi < i0 + cfg.chunk_a; ++wi) {
     const WorkItem it = cfg.work_a[wi];
     if (it.lp < 0) continue;
     const LpDev& lp = cfg.lps[it.lp];
     const int cur = it.ctl->cur;
-    V* Ax = static_cast<V*>(lp.Ax[cur]);
-    const V* vecs[1] = {static_cast<const V*>(lp.x[cur])};
+    const gptr<V> Ax = gp(static_cast<V*>(lp.Ax[cur]));
+    const gptr<const V> vecs[1] = {gp(static_cast<const V*>(lp.x[cur]))};
     spmv_tile<V, 1>(
-        it, lp.rp_a, lp.ci_a, static_cast<const V*>(lp.va_a), vecs, nodiv,
+        it, gp(lp.rp_a), gp(lp.ci_a), gp(static_cast<const V*>(lp.va_a)), vecs, nodiv,
         [&](int) { return 0; }, [&](int i, V (&acc)[1], int) { Ax[i] = acc[0]; }, sh);
   }
 }
@@ -634,18 +762,26 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
   // per-LP context, loaded when the LP changes
   const LpDev* lp = nullptr;
   Ctl* c = nullptr;
-  const V *cc = nullptr, *lo = nullptr, *hi = nullptr, *x = nullptr, *xs = nullptr;
-  V *T = nullptr, *Hp = nullptr, *xn = nullptr, *xsn = nullptr, *Gp = nullptr;
-  const V* vecs[1] = {nullptr};
+  gptr<const V> cc = nullptr, lo = nullptr, hi = nullptr, x = nullptr, xs = nullptr;
+  gptr<V> T = nullptr, Hp = nullptr, xn = nullptr, xsn = nullptr, Gp = nullptr;
+  // sources of the AdaGrad state read with the row: H and G on update
+  // attempts, else a vector the row reads anyway (values unused), so the
+  // loads need no branch
+  gptr<const V> Hsrc = nullptr, Gsrc = nullptr;
+  gptr<const V> vecs[1] = {nullptr};
+  gptr<const int32_t> rp = nullptr, ci = nullptr;
+  gptr<const V> va = nullptr;
   V tau = V(0), etav = V(0);
   bool learn = false, upd = false;
   double lscale = 1.0, hnorm = 0.0;
+  __shared__ WorkItem s_items[kItemWin];
   run_chunk(
-      cfg.work_t, cfg.chunk_t,
+      cfg.work_t, cfg.chunk_t, s_items,
       [&](const WorkItem& it) {
         c = it.ctl;
-        // the restart / final copy of the evaluation step ran before this launch
-        if (it.tile == 0 && threadIdx.x == 0 && (c->restart_pending | c->finalize_avg)) {
+        // the restart / final copy of the evaluation step ran before this
+        // launch; the LP's first chunk (partial slot 0) clears the flags
+        if (it.slot == 0 && threadIdx.x == 0 && (c->restart_pending | c->finalize_avg)) {
           c->restart_pending = 0;
           c->finalize_avg = 0;
         }
@@ -659,22 +795,32 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
         lscale = 1.0;
         upd = !force && c->learn_pending && learn_side(c, lp->prm, true, &lscale);
         hnorm = c->hp_norm;
-        cc = static_cast<const V*>(lp->c);
-        lo = static_cast<const V*>(lp->l);
-        hi = static_cast<const V*>(lp->u);
-        T = static_cast<V*>(lp->T);
-        Hp = static_cast<V*>(lp->Hp);
-        x = static_cast<const V*>(lp->x[cur]);
-        xs = static_cast<const V*>(lp->xs[cur]);
-        xn = static_cast<V*>(lp->x[nxt]);
-        xsn = static_cast<V*>(lp->xs[nxt]);
-        Gp = static_cast<V*>(lp->Gp);
-        vecs[0] = static_cast<const V*>(lp->y[cur]);
+        cc = gp(static_cast<const V*>(lp->c));
+        lo = gp(static_cast<const V*>(lp->l));
+        hi = gp(static_cast<const V*>(lp->u));
+        T = gp(static_cast<V*>(lp->T));
+        Hp = gp(static_cast<V*>(lp->Hp));
+        x = gp(static_cast<const V*>(lp->x[cur]));
+        xs = gp(static_cast<const V*>(lp->xs[cur]));
+        xn = gp(static_cast<V*>(lp->x[nxt]));
+        xsn = gp(static_cast<V*>(lp->xs[nxt]));
+        Gp = gp(static_cast<V*>(lp->Gp));
+        Hsrc = upd ? Hp : x;
+        Gsrc = upd ? Gp : x;
+        vecs[0] = gp(static_cast<const V*>(lp->y[cur]));
+        rp = gp(lp->rp_t);
+        ci = gp(lp->ci_t);
+        va = gp(static_cast<const V*>(lp->va_t));
+        cc = uni(cc), lo = uni(lo), hi = uni(hi), x = uni(x), xs = uni(xs);
+        T = uni(T), Hp = uni(Hp), xn = uni(xn), xsn = uni(xsn), Gp = uni(Gp);
+        Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
+        rp = uni(rp), ci = uni(ci), va = uni(va);
+        tau = uni(tau), etav = uni(etav);
         return true;
       },
       [&](const WorkItem& it) {
         spmv_tile<V, 1>(
-            it, lp->rp_t, lp->ci_t, static_cast<const V*>(lp->va_t), vecs, nodiv,
+            it, rp, ci, va, vecs, nodiv,
             [&](int j) {
               PrimalPre<V> q;
               q.c = cc[j];
@@ -683,10 +829,8 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
               q.l = lo[j];
               q.u = hi[j];
               q.xs = xs[j];
-              if (upd) {
-                q.H = Hp[j];
-                q.G = Gp[j];
-              }
+              q.H = Hsrc[j];
+              q.G = Gsrc[j];
               return q;
             },
             [&](int j, V (&acc)[1], PrimalPre<V>& q) {
@@ -707,9 +851,9 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
               dd_add_prod(p[1], (double)g, (double)g);
               if (learn) {
                 const bool ind = (xh >= q.l) && (xh <= q.u);
-                const V gp = ind ? -((tau * g) * g) : V(0);
-                Gp[j] = gp;
-                dd_add_prod(p[2], (double)gp, (double)gp);
+                const V gp_ = ind ? -((tau * g) * g) : V(0);
+                Gp[j] = gp_;
+                dd_add_prod(p[2], (double)gp_, (double)gp_);
               }
             },
             sh);
@@ -735,15 +879,19 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg) {
   dd_reset(p);
   const LpDev* lp = nullptr;
   const Ctl* c = nullptr;
-  const V *b = nullptr, *y = nullptr, *ys = nullptr, *Ax = nullptr;
-  V *S = nullptr, *Hd = nullptr, *yn = nullptr, *ysn = nullptr, *Axn = nullptr, *Gd = nullptr;
-  const int8_t* sense = nullptr;
-  const V* vecs[1] = {nullptr};
+  gptr<const V> b = nullptr, y = nullptr, ys = nullptr, Ax = nullptr;
+  gptr<V> S = nullptr, Hd = nullptr, yn = nullptr, ysn = nullptr, Axn = nullptr, Gd = nullptr;
+  gptr<const V> Hsrc = nullptr, Gsrc = nullptr;  // as in k_primal
+  gptr<const int8_t> sense = nullptr;
+  gptr<const int32_t> rp = nullptr, ci = nullptr;
+  gptr<const V> va = nullptr;
+  gptr<const V> vecs[1] = {nullptr};
   V sig = V(0), etav = V(0);
   bool learn = false, upd = false;
   double lscale = 1.0, hnorm = 0.0;
+  __shared__ WorkItem s_items[kItemWin];
   run_chunk(
-      cfg.work_a, cfg.chunk_a,
+      cfg.work_a, cfg.chunk_a, s_items,
       [&](const WorkItem& it) {
         c = it.ctl;
         if (!attempt_guard(c)) return false;
@@ -756,23 +904,33 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg) {
         lscale = 1.0;
         upd = c->learn_pending && learn_side(c, lp->prm, false, &lscale);
         hnorm = c->hd_norm;
-        b = static_cast<const V*>(lp->b);
-        S = static_cast<V*>(lp->S);
-        Hd = static_cast<V*>(lp->Hd);
-        y = static_cast<const V*>(lp->y[cur]);
-        ys = static_cast<const V*>(lp->ys[cur]);
-        Ax = static_cast<const V*>(lp->Ax[cur]);
-        yn = static_cast<V*>(lp->y[nxt]);
-        ysn = static_cast<V*>(lp->ys[nxt]);
-        Axn = static_cast<V*>(lp->Ax[nxt]);
-        Gd = static_cast<V*>(lp->Gd);
-        sense = lp->sense;
-        vecs[0] = static_cast<const V*>(lp->x[nxt]);
+        b = gp(static_cast<const V*>(lp->b));
+        S = gp(static_cast<V*>(lp->S));
+        Hd = gp(static_cast<V*>(lp->Hd));
+        y = gp(static_cast<const V*>(lp->y[cur]));
+        ys = gp(static_cast<const V*>(lp->ys[cur]));
+        Ax = gp(static_cast<const V*>(lp->Ax[cur]));
+        yn = gp(static_cast<V*>(lp->y[nxt]));
+        ysn = gp(static_cast<V*>(lp->ys[nxt]));
+        Axn = gp(static_cast<V*>(lp->Ax[nxt]));
+        Gd = gp(static_cast<V*>(lp->Gd));
+        sense = gp(lp->sense);
+        Hsrc = upd ? Hd : y;
+        Gsrc = upd ? Gd : y;
+        vecs[0] = gp(static_cast<const V*>(lp->x[nxt]));
+        rp = gp(lp->rp_a);
+        ci = gp(lp->ci_a);
+        va = gp(static_cast<const V*>(lp->va_a));
+        b = uni(b), S = uni(S), Hd = uni(Hd), y = uni(y), ys = uni(ys), Ax = uni(Ax);
+        yn = uni(yn), ysn = uni(ysn), Axn = uni(Axn), Gd = uni(Gd), sense = uni(sense);
+        Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
+        rp = uni(rp), ci = uni(ci), va = uni(va);
+        sig = uni(sig), etav = uni(etav);
         return true;
       },
       [&](const WorkItem& it) {
         spmv_tile<V, 1>(
-            it, lp->rp_a, lp->ci_a, static_cast<const V*>(lp->va_a), vecs, nodiv,
+            it, rp, ci, va, vecs, nodiv,
             [&](int i) {
               DualPre<V> q;
               q.ax = Ax[i];
@@ -781,10 +939,8 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg) {
               q.ys = ys[i];
               q.S = S[i];
               q.ineq = sense[i];
-              if (upd) {
-                q.H = Hd[i];
-                q.G = Gd[i];
-              }
+              q.H = Hsrc[i];
+              q.G = Gsrc[i];
               return q;
             },
             [&](int i, V (&acc)[1], DualPre<V>& q) {
@@ -887,7 +1043,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
   __shared__ DD s_red[4 * 2 * kEvT];
   DD p[2 * kEvT];
   dd_reset(p);
-  const int i0 = blockIdx.x * cfg.chunk_t;
+  const int i0 = chunk_index() * cfg.chunk_t;
   for (int wi = i0; wi < i0 + cfg.chunk_t; ++wi) {
     const WorkItem it = cfg.work_t[wi];
     if (it.lp < 0) continue;
@@ -900,18 +1056,19 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
     const int cur = c->cur;
     const double w = c->w;
     const bool has_avg = w > 0.0;
-    const V* __restrict__ cc = static_cast<const V*>(lp.c);
-    const V* __restrict__ lo = static_cast<const V*>(lp.l);
-    const V* __restrict__ hi = static_cast<const V*>(lp.u);
-    const V* __restrict__ x = static_cast<const V*>(lp.x[cur]);
-    const V* __restrict__ xs = static_cast<const V*>(lp.xs[cur]);
-    const V* __restrict__ xa = static_cast<const V*>(lp.xa);
-    const double* __restrict__ dc = lp.dc;
-    const int8_t* __restrict__ bfin = lp.bfin;
-    const V* vecs[2] = {static_cast<const V*>(lp.y[cur]), static_cast<const V*>(lp.ys[cur])};
+    const gptr<const V> cc = gp(static_cast<const V*>(lp.c));
+    const gptr<const V> lo = gp(static_cast<const V*>(lp.l));
+    const gptr<const V> hi = gp(static_cast<const V*>(lp.u));
+    const gptr<const V> x = gp(static_cast<const V*>(lp.x[cur]));
+    const gptr<const V> xs = gp(static_cast<const V*>(lp.xs[cur]));
+    const gptr<const V> xa = gp(static_cast<const V*>(lp.xa));
+    const gptr<const double> dc = gp(lp.dc);
+    const gptr<const int8_t> bfin = gp(lp.bfin);
+    const gptr<const V> vecs[2] = {gp(static_cast<const V*>(lp.y[cur])),
+                                   gp(static_cast<const V*>(lp.ys[cur]))};
     const double divs[2] = {0.0, has_avg ? w : -1.0};
     spmv_tile<V, 2>(
-        it, lp.rp_t, lp.ci_t, static_cast<const V*>(lp.va_t), vecs, divs,
+        it, gp(lp.rp_t), gp(lp.ci_t), gp(static_cast<const V*>(lp.va_t)), vecs, divs,
         [&](int) { return 0; },
         [&](int j, V (&acc)[2], int) {
           const double cj = (double)cc[j];
@@ -944,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
   __shared__ DD s_red[4 * 2 * kEvA];
   DD p[2 * kEvA];
   dd_reset(p);
-  const int i0 = blockIdx.x * cfg.chunk_a;
+  const int i0 = chunk_index() * cfg.chunk_a;
   for (int wi = i0; wi < i0 + cfg.chunk_a; ++wi) {
     const WorkItem it = cfg.work_a[wi];
     if (it.lp < 0) continue;
@@ -957,18 +1114,18 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
     const int cur = c->cur;
     const double w = c->w;
     const bool has_avg = w > 0.0;
-    const V* __restrict__ b = static_cast<const V*>(lp.b);
-    const V* __restrict__ y = static_cast<const V*>(lp.y[cur]);
-    const V* __restrict__ ys = static_cast<const V*>(lp.ys[cur]);
-    const V* __restrict__ ya = static_cast<const V*>(lp.ya);
-    const V* __restrict__ Ax = static_cast<const V*>(lp.Ax[cur]);
-    V* __restrict__ Axa = static_cast<V*>(lp.Axa);
-    const double* __restrict__ dr = lp.dr;
-    const int8_t* __restrict__ sense = lp.sense;
-    const V* vecs[1] = {static_cast<const V*>(lp.xs[cur])};
+    const gptr<const V> b = gp(static_cast<const V*>(lp.b));
+    const gptr<const V> y = gp(static_cast<const V*>(lp.y[cur]));
+    const gptr<const V> ys = gp(static_cast<const V*>(lp.ys[cur]));
+    const gptr<const V> ya = gp(static_cast<const V*>(lp.ya));
+    const gptr<const V> Ax = gp(static_cast<const V*>(lp.Ax[cur]));
+    const gptr<V> Axa = gp(static_cast<V*>(lp.Axa));
+    const gptr<const double> dr = gp(lp.dr);
+    const gptr<const int8_t> sense = gp(lp.sense);
+    const gptr<const V> vecs[1] = {gp(static_cast<const V*>(lp.xs[cur]))};
     const double divs[1] = {has_avg ? w : -1.0};
     spmv_tile<V, 1>(
-        it, lp.rp_a, lp.ci_a, static_cast<const V*>(lp.va_a), vecs, divs,
+        it, gp(lp.rp_a), gp(lp.ci_a), gp(static_cast<const V*>(lp.va_a)), vecs, divs,
         [&](int) { return 0; },
         [&](int i, V (&acc)[1], int) {
           const double bi = (double)b[i];
