@@ -227,11 +227,20 @@ void opdhg_session_destroy(opdhg_session* s);
 /* ---- serving: continuous batching under a device-memory budget ---- */
 
 typedef struct opdhg_server_cfg {
-  size_t budget_bytes;   /* admission budget over the arena (<= arena size) */
-  int32_t max_active;    /* at most this many LPs on the device at once */
-  int32_t attempts_per_replay; /* attempts per launch sequence between admissions */
+  size_t budget_bytes;   /* admission budget for resident LPs; capped at what the arena
+                            holds after the launch tables */
+  int32_t max_active;    /* at most this many LPs on the device at once (1..65535) */
+  int32_t attempts_per_replay; /* step attempts per launch sequence; each sequence starts
+                                  with the due KKT evaluations, admissions and retirements
+                                  happen between sequences */
+  int32_t precision;     /* OPDHG_FP64 or OPDHG_FP32; every request must use it */
+  int32_t workgroups;    /* workgroups of the sparse-product launches; 0: automatic */
   double poll_interval_s; /* idle wait of the scheduler thread */
 } opdhg_server_cfg;
+
+/* Defaults: budget = whole arena, 256 active LPs, 64 attempts per sequence,
+ * FP32, automatic workgroups, 1 ms idle wait. */
+void opdhg_server_default_cfg(opdhg_server_cfg* cfg);
 
 typedef struct opdhg_server_stats {
   int64_t submitted;
@@ -245,9 +254,18 @@ typedef struct opdhg_server_stats {
   size_t peak_bytes;
 } opdhg_server_stats;
 
-/* Create a server over a caller-owned device arena. Three streams: compute,
- * host-to-device uploads and device-to-host downloads (NULL uses one
- * stream for all). Returns NULL on failure (see opdhg_last_error). */
+/* Create a server over a caller-owned device arena (the launch tables take
+ * the first arena_bytes / 64 bytes, clamped to [4 MiB, 1 GiB]; the LPs share
+ * the rest up to budget_bytes). Three streams: compute, host-to-device
+ * uploads and device-to-host downloads; a NULL upload or download stream
+ * uses the compute stream. The server runs two host threads: one prepares
+ * submitted LPs (validation, rescaling, tiling) in submission order, one
+ * admits prepared LPs in submission order as memory and slots free up,
+ * uploads them while the resident LPs iterate, launches the shared launch
+ * sequence, and retires finished LPs. An LP's arithmetic does not depend
+ * on what else is resident, so each result equals its solo solve with the
+ * same parameters bit for bit. Returns NULL on failure (see
+ * opdhg_last_error). */
 opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena,
                                   size_t arena_bytes, void* compute_stream,
                                   void* h2d_stream, void* d2h_stream);

@@ -6,6 +6,7 @@ include/opdhg.h); this package is its Python binding. See capi.py.
 
 from .capi import (  # noqa: F401
     OpdhgError,
+    Server,
     Session,
     load,
     opdhg_batch_workspace_bytes,
@@ -13,6 +14,7 @@ from .capi import (  # noqa: F401
     opdhg_default_params,
     opdhg_last_error,
     opdhg_rescale,
+    opdhg_server_default_cfg,
     opdhg_session_create,
     opdhg_solve,
     opdhg_solve_batch,

@@ -89,7 +89,7 @@ class opdhg_state(ctypes.Structure):
 class opdhg_server_cfg(ctypes.Structure):
     _fields_ = [
         ("budget_bytes", c_sz), ("max_active", c_i32), ("attempts_per_replay", c_i32),
-        ("poll_interval_s", c_dbl),
+        ("precision", c_i32), ("workgroups", c_i32), ("poll_interval_s", c_dbl),
     ]
 
 
@@ -123,6 +123,7 @@ SIGNATURES = {
                                      _p(opdhg_result)]),
     "opdhg_session_time_primal_kernel": (c_i32, [ctypes.c_void_p, c_i32, _p(c_dbl)]),
     "opdhg_session_destroy": (None, [ctypes.c_void_p]),
+    "opdhg_server_default_cfg": (None, [_p(opdhg_server_cfg)]),
     "opdhg_server_create": (ctypes.c_void_p, [_p(opdhg_server_cfg), ctypes.c_void_p, c_sz,
                                               ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
@@ -198,8 +199,18 @@ class _LPArrays:
         self.l = np.ascontiguousarray(lp.l, dtype=np.float64)
         self.u = np.ascontiguousarray(lp.u, dtype=np.float64)
         self.m, self.n = int(lp.m), int(lp.n)
+        nnz = self.col_idx.size
+        # the C-ABI trusts these lengths; a mismatch would read past an array
+        sizes = {"row_ptr": (self.row_ptr.size, self.m + 1), "val": (self.val.size, nnz),
+                 "b": (self.b.size, self.m), "sense": (self.sense.size, self.m),
+                 "c": (self.c.size, self.n), "l": (self.l.size, self.n),
+                 "u": (self.u.size, self.n)}
+        bad = {k: v for k, v in sizes.items() if v[0] != v[1]}
+        if bad or self.m < 0 or self.n < 0:
+            raise ValueError(f"LP array lengths do not match m={self.m}, n={self.n}, "
+                             f"nnz={nnz}: {bad}")
         self.struct = opdhg_lp(
-            m=self.m, n=self.n, nnz=int(self.row_ptr[-1]) if self.row_ptr.size else 0,
+            m=self.m, n=self.n, nnz=nnz,
             row_ptr=_dptr(self.row_ptr, c_i64), col_idx=_dptr(self.col_idx, c_i32),
             val=_dptr(self.val, c_dbl), b=_dptr(self.b, c_dbl),
             row_sense=_dptr(self.sense, ctypes.c_int8), c=_dptr(self.c, c_dbl),
@@ -391,3 +402,101 @@ class Session:
 
 def opdhg_session_create(lp, params=None, stream=None) -> Session:
     return Session(lp, params, stream)
+
+
+def opdhg_server_default_cfg(**overrides) -> opdhg_server_cfg:
+    cfg = opdhg_server_cfg()
+    load().opdhg_server_default_cfg(ctypes.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Server:
+    """opdhg_server_*: continuous batching of LP solves over a device arena.
+
+    The arena is one torch uint8 device tensor of arena_bytes; the server's
+    compute, upload and download streams are torch streams at default
+    priority. submit() copies the LP; wait() / poll() return
+    (x, y, opdhg_result) or raise OpdhgError (NOT_READY from poll while the
+    solve runs).
+    """
+
+    NOT_READY = OPDHG_ERR_NOT_READY
+
+    def __init__(self, arena_bytes: int, cfg: Optional[opdhg_server_cfg] = None, **overrides):
+        torch = _torch()
+        self.cfg = cfg or opdhg_server_default_cfg(**overrides)
+        self._arena = device_workspace(int(arena_bytes))
+        ptr, size = _ws_ptr(self._arena)
+        self._streams = [torch.cuda.Stream() for _ in range(3)]
+        h = load().opdhg_server_create(ctypes.byref(self.cfg), ctypes.c_void_p(ptr), size,
+                                       *[ctypes.c_void_p(int(st.cuda_stream))
+                                         for st in self._streams])
+        if not h:
+            raise OpdhgError(OPDHG_ERR_DEVICE, load().opdhg_last_error().decode())
+        self._h = ctypes.c_void_p(h)
+        self._shapes = {}
+
+    def submit(self, lp, params: Optional[opdhg_params] = None) -> int:
+        params = params or opdhg_default_params(precision=self.cfg.precision)
+        a = _LPArrays(lp)
+        t = ctypes.c_uint64(0)
+        _check(load().opdhg_server_submit(self._h, ctypes.byref(a.struct), ctypes.byref(params),
+                                          ctypes.byref(t)))
+        self._shapes[t.value] = (a.n, a.m)
+        return t.value
+
+    def _outputs(self, ticket):
+        n, m = self._shapes[ticket]
+        return np.empty(n), np.empty(max(m, 1)), opdhg_result(), m
+
+    def poll(self, ticket: int):
+        x, y, res, m = self._outputs(ticket)
+        rc = load().opdhg_server_poll(self._h, ctypes.c_uint64(ticket), _dptr(x, c_dbl),
+                                      _dptr(y, c_dbl), ctypes.byref(res))
+        if rc != OPDHG_ERR_NOT_READY:
+            self._shapes.pop(ticket, None)
+        _check(rc)
+        return x, y[:m], res
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        x, y, res, m = self._outputs(ticket)
+        rc = load().opdhg_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s),
+                                      _dptr(x, c_dbl), _dptr(y, c_dbl), ctypes.byref(res))
+        if rc != OPDHG_ERR_NOT_READY:
+            self._shapes.pop(ticket, None)
+        _check(rc)
+        return x, y[:m], res
+
+    def cancel(self, ticket: int) -> None:
+        _check(load().opdhg_server_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def stats(self) -> opdhg_server_stats:
+        st = opdhg_server_stats()
+        _check(load().opdhg_server_get_stats(self._h, ctypes.byref(st)))
+        return st
+
+    def latency(self, ticket: int) -> float:
+        out = c_dbl(0.0)
+        _check(load().opdhg_server_latency(self._h, ctypes.c_uint64(ticket), ctypes.byref(out)))
+        return float(out.value)
+
+    def close(self) -> None:
+        if self._h:
+            load().opdhg_server_destroy(self._h)
+            self._h = None
+            torch = _torch()
+            torch.cuda.synchronize()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -30,12 +30,6 @@ int fail_hip(hipError_t e, const char* what) {
   return OPDHG_ERR_DEVICE;
 }
 
-#define HIP_TRY(expr)                                  \
-  do {                                                 \
-    hipError_t e_ = (expr);                            \
-    if (e_ != hipSuccess) return fail_hip(e_, #expr);  \
-  } while (0)
-
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
@@ -549,6 +543,7 @@ int Group::capture(int attempts_per_replay) {
       rc |= Kernels<V>::dual(cfg, cap_stream);
       rc |= Kernels<V>::decide(cfg, cap_stream);
     }
+    rc |= launch_board(cfg, cap_stream);
   };
   if (prec == OPDHG_FP32) K(float{});
   else K(double{});
@@ -618,7 +613,7 @@ struct SessionImpl {
 // Chunking of a work list of n items over at most `cap` workgroups. A grid
 // of more than 8 workgroups is rounded up to a multiple of 8 (with empty
 // chunks) so the kernels can give each XCD a contiguous range of chunks.
-static void chunking(int64_t n, int64_t cap, int* grid, int* chunk) {
+void chunking(int64_t n, int64_t cap, int* grid, int* chunk) {
   const int64_t g0 = std::max<int64_t>(1, std::min<int64_t>(n, cap));
   const int64_t c = std::max<int64_t>(1, (n + g0 - 1) / g0);
   int64_t g = std::max<int64_t>(1, (n + c - 1) / c);
@@ -627,17 +622,18 @@ static void chunking(int64_t n, int64_t cap, int* grid, int* chunk) {
   *grid = (int)g;
 }
 
-static int64_t grid_cap(const opdhg_params* p) {
+int64_t grid_cap(const opdhg_params* p) {
   return p->workgroups > 0 ? p->workgroups : kGridCap;
 }
 
-static size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64_t cap) {
+size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64_t cap) {
   int gt, ct, ga, ca;
   chunking(nwork_t, cap, &gt, &ct);
   chunking(nwork_a, cap, &ga, &ca);
-  return align_up(sizeof(LpDev) * std::max<int64_t>(nlps, 1)) +
-         align_up(sizeof(WorkItem) * (size_t)gt * ct) +
-         align_up(sizeof(WorkItem) * (size_t)ga * ca) + align_up(sizeof(Counts));
+  const size_t nl = (size_t)std::max<int64_t>(nlps, 1);
+  return align_up(sizeof(LpDev) * nl) + align_up(sizeof(WorkItem) * (size_t)gt * ct) +
+         align_up(sizeof(WorkItem) * (size_t)ga * ca) + align_up(sizeof(Counts)) +
+         align_up(sizeof(Ctl) * nl);
 }
 
 // Order in which an LP's tiles enter the work list. Long rows (tiles of
@@ -662,9 +658,8 @@ static std::vector<int64_t> spread_long_tiles(const std::vector<Tile>& tiles) {
 
 // Items of one side for all LPs, chunked: fills slot / last and each LP's
 // slot count.
-static void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps,
-                       bool tside, int64_t cap, int* grid, int* chunk,
-                       std::vector<WorkItem>& out) {
+void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps, bool tside,
+                int64_t cap, int* grid, int* chunk, std::vector<WorkItem>& out) {
   out.clear();
   std::vector<std::pair<int64_t, int64_t>> range(lps.size());
   for (size_t i = 0; i < lps.size(); ++i) {
@@ -699,7 +694,8 @@ static void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared
 // cfg at them.
 int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
                  const std::vector<const Prepared*>& preps, int64_t cap, hipStream_t stream,
-                 std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa) {
+                 std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa,
+                 size_t capacity, bool fixed_launch) {
   std::vector<LpDev> lps(lps_in);
   std::vector<WorkItem> wt, wa;
   side_items(lps, preps, true, cap, &cfg->grid_t, &cfg->chunk_t, wt);
@@ -709,24 +705,35 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
     n_t += (int64_t)P->tiles_t.size();
     n_a += (int64_t)P->tiles_a.size();
   }
+  const size_t nl = std::max<size_t>(lps.size(), 1);
   const size_t o_lps = 0;
-  const size_t o_wt = o_lps + align_up(sizeof(LpDev) * std::max<size_t>(lps.size(), 1));
+  const size_t o_wt = o_lps + align_up(sizeof(LpDev) * nl);
   const size_t o_wa = o_wt + align_up(sizeof(WorkItem) * wt.size());
   const size_t o_cn = o_wa + align_up(sizeof(WorkItem) * wa.size());
-  const size_t total = o_cn + align_up(sizeof(Counts));
-  staging.assign(total, 0);
+  const size_t o_bd = o_cn + align_up(sizeof(Counts));
+  const size_t total = o_bd + align_up(sizeof(Ctl) * nl);
+  if (capacity && total > capacity)
+    return fail(OPDHG_ERR_OVER_BUDGET, "launch tables need " + std::to_string(total) + " bytes");
+  const size_t upload = o_bd;  // the board is written by the device
+  staging.assign(upload, 0);
   if (!lps.empty()) std::memcpy(staging.data() + o_lps, lps.data(), sizeof(LpDev) * lps.size());
   std::memcpy(staging.data() + o_wt, wt.data(), sizeof(WorkItem) * wt.size());
   std::memcpy(staging.data() + o_wa, wa.data(), sizeof(WorkItem) * wa.size());
-  Counts cn{(int32_t)n_t, (int32_t)n_a, (int32_t)lps.size(), 0};
+  Counts cn{(int32_t)n_t, (int32_t)n_a, (int32_t)lps.size(), 0,
+            cfg->grid_t, cfg->chunk_t, cfg->grid_a, cfg->chunk_a};
   std::memcpy(staging.data() + o_cn, &cn, sizeof(cn));
-  HIP_TRY(hipMemcpyAsync(dst, staging.data(), total, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(dst, staging.data(), upload, hipMemcpyHostToDevice, stream));
   cfg->lps = reinterpret_cast<const LpDev*>(dst + o_lps);
   cfg->work_t = reinterpret_cast<const WorkItem*>(dst + o_wt);
   cfg->work_a = reinterpret_cast<const WorkItem*>(dst + o_wa);
   cfg->counts = reinterpret_cast<const Counts*>(dst + o_cn);
-  cfg->grid_ta = std::max(cfg->grid_t, cfg->grid_a);
-  cfg->grid_lp = (int)std::max<size_t>(1, std::min<size_t>(lps.size(), kGridCap));
+  cfg->board = reinterpret_cast<Ctl*>(dst + o_bd);
+  if (!fixed_launch) {
+    cfg->launch_t = cfg->grid_t;
+    cfg->launch_a = cfg->grid_a;
+    cfg->launch_ta = std::max(cfg->grid_t, cfg->grid_a);
+    cfg->launch_lp = (int)std::max<size_t>(1, std::min<size_t>(lps.size(), kGridCap));
+  }
   *nwt = n_t;
   *nwa = n_a;
   return OPDHG_OK;
@@ -809,8 +816,8 @@ int run_group(Group& grp, const std::vector<Ctl*>& d_ctls, std::vector<Ctl>& h_c
   while (any_running) {
     int rc = grp.replay();
     if (rc) return rc;
-    for (size_t i = 0; i < cnt; ++i)
-      HIP_TRY(hipMemcpyAsync(pinned + i, d_ctls[i], sizeof(Ctl), hipMemcpyDeviceToHost, grp.stream));
+    HIP_TRY(hipMemcpyAsync(pinned, grp.cfg.board, sizeof(Ctl) * cnt, hipMemcpyDeviceToHost,
+                           grp.stream));
     HIP_TRY(hipStreamSynchronize(grp.stream));
     const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     any_running = false;

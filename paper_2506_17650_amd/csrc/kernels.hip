@@ -122,8 +122,11 @@ __device__ __forceinline__ void lds_barrier() {
 // is a multiple of 8, XCD x takes the contiguous chunks
 // [x * grid/8, (x + 1) * grid/8): the rows an XCD's tiles gather from stay
 // in that XCD's L2 instead of being spread over all eight.
-__device__ __forceinline__ int chunk_index() {
-  const int g = gridDim.x, b = blockIdx.x;
+// g is the side's chunk count (read from the device-side counts); the
+// launch grid may be larger, and workgroups b >= g get -1 (no chunk).
+__device__ __forceinline__ int chunk_index(int g) {
+  const int b = blockIdx.x;
+  if (b >= g) return -1;
   if (g & 7) return b;
   return (b & 7) * (g >> 3) + (b >> 3);
 }
@@ -659,15 +662,28 @@ __device__ __forceinline__ WorkItem uniform_item(const WorkItem& w) {
   return u;
 }
 
+// A side's chunking as the launch sees it, in scalar registers.
+struct SideChunks {
+  int grid, chunk;
+};
+
+__device__ __forceinline__ SideChunks side_chunks(const Counts* counts, bool tside) {
+  const gptr<const Counts> c = gp(counts);
+  return SideChunks{uni(tside ? c->grid_t : c->grid_a), uni(tside ? c->chunk_t : c->chunk_a)};
+}
+
 // Drives a workgroup over its chunk of a side's work list. When the LP
 // changes, begin(item) loads the LP's pointers and scalars into registers
 // and returns whether the LP takes part; tile(item) processes a tile of a
 // running LP; end(item, run) closes the LP's part of the chunk.
 template <typename Begin, typename TileFn, typename End>
-__device__ __forceinline__ void run_chunk(const WorkItem* __restrict__ work, int chunk,
+__device__ __forceinline__ void run_chunk(const WorkItem* __restrict__ work, SideChunks sc,
                                           WorkItem* s_items, Begin&& begin, TileFn&& tile,
                                           End&& end) {
-  const int w0 = chunk_index() * chunk;
+  const int ci = chunk_index(sc.grid);
+  if (ci < 0) return;
+  const int chunk = sc.chunk;
+  const int w0 = ci * chunk;
   int lp = -1;
   bool run = false;
   for (int k0 = 0; k0 < chunk; k0 += kItemWin) {
@@ -733,8 +749,11 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_init_products(LaunchCfg cfg) {
   __shared__ SpmvShared<V, 1> sh;
   const double nodiv[1] = {0.0};
-  const int i0 = chunk_index() * cfg.chunk_a;
-  for (int wi = i0; wi < i0 + cfg.chunk_a; ++wi) {
+  const SideChunks sc = side_chunks(cfg.counts, false);
+  const int ch = chunk_index(sc.grid);
+  if (ch < 0) return;
+  const int i0 = ch * sc.chunk;
+  for (int wi = i0; wi < i0 + sc.chunk; ++wi) {
     const WorkItem it = cfg.work_a[wi];
     if (it.lp < 0) continue;
     const LpDev& lp = cfg.lps[it.lp];
@@ -776,7 +795,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
   double lscale = 1.0, hnorm = 0.0;
   __shared__ WorkItem s_items[kItemWin];
   run_chunk(
-      cfg.work_t, cfg.chunk_t, s_items,
+      cfg.work_t, side_chunks(cfg.counts, true), s_items,
       [&](const WorkItem& it) {
         c = it.ctl;
         // the restart / final copy of the evaluation step ran before this
@@ -891,7 +910,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg) {
   double lscale = 1.0, hnorm = 0.0;
   __shared__ WorkItem s_items[kItemWin];
   run_chunk(
-      cfg.work_a, cfg.chunk_a, s_items,
+      cfg.work_a, side_chunks(cfg.counts, false), s_items,
       [&](const WorkItem& it) {
         c = it.ctl;
         if (!attempt_guard(c)) return false;
@@ -1018,11 +1037,13 @@ __global__ __launch_bounds__(kBlock) void k_learn_flush(LaunchCfg cfg) {
       H[r] = h;
     }
   };
-  if ((int)blockIdx.x < cfg.grid_t)
-    for (int wi = blockIdx.x * cfg.chunk_t; wi < (int)(blockIdx.x + 1) * cfg.chunk_t; ++wi)
+  const SideChunks st = side_chunks(cfg.counts, true), sa = side_chunks(cfg.counts, false);
+  const int b = blockIdx.x;
+  if (b < st.grid)
+    for (int wi = b * st.chunk; wi < (b + 1) * st.chunk; ++wi)
       if (cfg.work_t[wi].lp >= 0) body(cfg.work_t[wi], true);
-  if ((int)blockIdx.x < cfg.grid_a)
-    for (int wi = blockIdx.x * cfg.chunk_a; wi < (int)(blockIdx.x + 1) * cfg.chunk_a; ++wi)
+  if (b < sa.grid)
+    for (int wi = b * sa.chunk; wi < (b + 1) * sa.chunk; ++wi)
       if (cfg.work_a[wi].lp >= 0) body(cfg.work_a[wi], false);
 }
 
@@ -1043,8 +1064,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
   __shared__ DD s_red[4 * 2 * kEvT];
   DD p[2 * kEvT];
   dd_reset(p);
-  const int i0 = chunk_index() * cfg.chunk_t;
-  for (int wi = i0; wi < i0 + cfg.chunk_t; ++wi) {
+  const SideChunks sc = side_chunks(cfg.counts, true);
+  const int ch = chunk_index(sc.grid);
+  if (ch < 0) return;
+  const int i0 = ch * sc.chunk;
+  for (int wi = i0; wi < i0 + sc.chunk; ++wi) {
     const WorkItem it = cfg.work_t[wi];
     if (it.lp < 0) continue;
     const Ctl* c = it.ctl;
@@ -1101,8 +1125,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
   __shared__ DD s_red[4 * 2 * kEvA];
   DD p[2 * kEvA];
   dd_reset(p);
-  const int i0 = chunk_index() * cfg.chunk_a;
-  for (int wi = i0; wi < i0 + cfg.chunk_a; ++wi) {
+  const SideChunks sc = side_chunks(cfg.counts, false);
+  const int ch = chunk_index(sc.grid);
+  if (ch < 0) return;
+  const int i0 = ch * sc.chunk;
+  for (int wi = i0; wi < i0 + sc.chunk; ++wi) {
     const WorkItem it = cfg.work_a[wi];
     if (it.lp < 0) continue;
     const Ctl* c = it.ctl;
@@ -1217,12 +1244,27 @@ __global__ __launch_bounds__(kBlock) void k_apply(LaunchCfg cfg) {
       }
     }
   };
-  if ((int)blockIdx.x < cfg.grid_t)
-    for (int wi = blockIdx.x * cfg.chunk_t; wi < (int)(blockIdx.x + 1) * cfg.chunk_t; ++wi)
+  const SideChunks st = side_chunks(cfg.counts, true), sa = side_chunks(cfg.counts, false);
+  const int b = blockIdx.x;
+  if (b < st.grid)
+    for (int wi = b * st.chunk; wi < (b + 1) * st.chunk; ++wi)
       if (cfg.work_t[wi].lp >= 0) body(cfg.work_t[wi], true);
-  if ((int)blockIdx.x < cfg.grid_a)
-    for (int wi = blockIdx.x * cfg.chunk_a; wi < (int)(blockIdx.x + 1) * cfg.chunk_a; ++wi)
+  if (b < sa.grid)
+    for (int wi = b * sa.chunk; wi < (b + 1) * sa.chunk; ++wi)
       if (cfg.work_a[wi].lp >= 0) body(cfg.work_a[wi], false);
+}
+
+// Gathers every LP's control block into one array, so the host reads the
+// state of a whole set with one copy.
+__global__ __launch_bounds__(kBlock) void k_board(LaunchCfg cfg) {
+  constexpr int kWords = sizeof(Ctl) / 8;
+  static_assert(sizeof(Ctl) % 8 == 0, "Ctl is copied as 64-bit words");
+  const int nlps = uni(gp(cfg.counts)->nlps);
+  for (int li = blockIdx.x; li < nlps; li += gridDim.x) {
+    const gptr<const uint64_t> src = gp(reinterpret_cast<const uint64_t*>(cfg.lps[li].ctl));
+    const gptr<uint64_t> dst = gp(reinterpret_cast<uint64_t*>(cfg.board + li));
+    for (int w = threadIdx.x; w < kWords; w += kBlock) dst[w] = src[w];
+  }
 }
 
 }  // namespace
@@ -1248,40 +1290,42 @@ static int launched() {
 
 template <typename V>
 int Kernels<V>::init_products(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_init_products<V>, c.grid_a, c);
+  OPDHG_LAUNCH(k_init_products<V>, c.launch_a, c);
 }
 template <typename V>
 int Kernels<V>::primal(const LaunchCfg& c, void* stream, int force) {
-  OPDHG_LAUNCH(k_primal<V>, c.grid_t, c, force);
+  OPDHG_LAUNCH(k_primal<V>, c.launch_t, c, force);
 }
 template <typename V>
 int Kernels<V>::dual(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_dual<V>, c.grid_a, c);
+  OPDHG_LAUNCH(k_dual<V>, c.launch_a, c);
 }
 template <typename V>
 int Kernels<V>::decide(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_decide, c.grid_lp, c);
+  OPDHG_LAUNCH(k_decide, c.launch_lp, c);
 }
 template <typename V>
 int Kernels<V>::learn_flush(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_learn_flush<V>, c.grid_ta, c);
+  OPDHG_LAUNCH(k_learn_flush<V>, c.launch_ta, c);
 }
 template <typename V>
 int Kernels<V>::eval_t(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_eval_t<V>, c.grid_t, c);
+  OPDHG_LAUNCH(k_eval_t<V>, c.launch_t, c);
 }
 template <typename V>
 int Kernels<V>::eval_a(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_eval_a<V>, c.grid_a, c);
+  OPDHG_LAUNCH(k_eval_a<V>, c.launch_a, c);
 }
 template <typename V>
 int Kernels<V>::eval_decide(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_eval_decide, c.grid_lp, c);
+  OPDHG_LAUNCH(k_eval_decide, c.launch_lp, c);
 }
 template <typename V>
 int Kernels<V>::apply(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_apply<V>, c.grid_ta, c);
+  OPDHG_LAUNCH(k_apply<V>, c.launch_ta, c);
 }
+
+int launch_board(const LaunchCfg& c, void* stream) { OPDHG_LAUNCH(k_board, c.launch_lp, c); }
 
 template struct Kernels<double>;
 template struct Kernels<float>;

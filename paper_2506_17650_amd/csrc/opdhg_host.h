@@ -13,6 +13,13 @@ namespace opdhg {
 
 int fail(int code, const std::string& msg);
 int fail_hip(hipError_t e, const char* what);
+
+// Return the HIP error of expr as OPDHG_ERR_DEVICE (with a message).
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return fail_hip(e_, #expr);  \
+  } while (0)
 int validate_lp(const opdhg_lp* lp);
 int validate_params(const opdhg_params* p);
 
@@ -53,9 +60,23 @@ SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int6
 LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P);
 int upload_slot(uint8_t* base, const SlotLayout& L, const Prepared& P, int prec,
                 hipStream_t stream, std::vector<uint8_t>& img);
+// Launch tables of a set of LPs at dst: LP table, both work lists (chunked
+// over at most cap workgroups), counts and the Ctl board. With capacity > 0,
+// OPDHG_ERR_OVER_BUDGET when they need more bytes. With fixed_launch the
+// launch grids in cfg are kept (they must cover the new grids).
 int write_tables(uint8_t* dst, const std::vector<LpDev>& lps,
                  const std::vector<const Prepared*>& preps, int64_t cap, hipStream_t stream,
-                 std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa);
+                 std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa,
+                 size_t capacity = 0, bool fixed_launch = false);
+size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64_t cap);
+// Work list of one side for a set of LPs (tiles of LP 0, then LP 1, ...),
+// chunked over at most cap workgroups and padded to grid * chunk items;
+// fills each item's slot / last flags and each LP's slot count.
+void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps, bool tside,
+                int64_t cap, int* grid, int* chunk, std::vector<WorkItem>& out);
+// Workgroup cap of the sparse-product launches under these parameters.
+int64_t grid_cap(const opdhg_params* p);
+void chunking(int64_t n, int64_t cap, int* grid, int* chunk);
 int download_vec(const void* dptr, size_t count, int prec, hipStream_t stream, double* out);
 void fill_result(const Ctl& c, double seconds, opdhg_result* r);
 void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,

@@ -158,23 +158,31 @@ struct WorkItem {
   int32_t pad;
 };
 
-// Item counts of a set, in device memory: {nwork_t, nwork_a, nlps}.
+// Item counts and chunking of a set, in device memory. Chunk c of a side
+// holds items [c * chunk, (c + 1) * chunk) of that side's list, which is
+// padded to grid * chunk items. The kernels read these at run time, so a
+// captured launch sequence serves any set whose grids fit its launch grids
+// (the server rewrites the tables between replays).
 struct Counts {
   int32_t nwork_t, nwork_a, nlps, pad;
+  int32_t grid_t, chunk_t;  // chunks (a multiple of 8 when above 8) and items per chunk
+  int32_t grid_a, chunk_a;
 };
 
 // Host-side launch wrappers (kernels.hip). V is float or double.
-// Workgroup b of a side takes items [b * chunk, (b + 1) * chunk) of that
-// side's list, which is padded to grid * chunk items.
 struct LaunchCfg {
   const LpDev* lps;        // device pointers
   const WorkItem* work_t;  // A^T-side tiles of all LPs
   const WorkItem* work_a;  // A-side tiles
   const Counts* counts;
-  int grid_t, chunk_t;     // workgroups and items per workgroup over work_t
-  int grid_a, chunk_a;     // same over work_a
-  int grid_ta;             // max(grid_t, grid_a): kernels that visit both sides
-  int grid_lp;             // workgroups over LPs (decision kernels)
+  Ctl* board;              // after each launch sequence: copy of every LP's Ctl, in LP order
+  // launch grids; each covers the device-side grid it serves (workgroups
+  // past the device grid exit at once)
+  int launch_t, launch_a;  // sparse-product kernels of each side
+  int launch_ta;           // kernels that visit both sides
+  int launch_lp;           // one workgroup per LP (decision kernels, board)
+  // host copy of the device-side chunking
+  int grid_t, chunk_t, grid_a, chunk_a;
 };
 
 template <typename V>
@@ -189,6 +197,9 @@ struct Kernels {
   static int eval_decide(const LaunchCfg& c, void* stream);
   static int apply(const LaunchCfg& c, void* stream);
 };
+
+// Copies every LP's Ctl into c.board (precision independent).
+int launch_board(const LaunchCfg& c, void* stream);
 
 const char* device_error_string();
 

@@ -1,0 +1,138 @@
+"""Serving loop on the GPU (opdhg_server_* through the C-ABI).
+
+An LP's arithmetic depends only on its own data (rows reduced inside one
+tile, exact cross-tile sums), so each result from the server must equal the
+solo opdhg_solve of the same LP with the same parameters bit for bit, in
+whatever mix it ran: submitted together, under a budget that admits only a
+few at a time, or arriving while others iterate.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from lpgen import config_lp
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_2506_17650_amd as P
+    P.load()
+    return P
+
+
+def _mix():
+    lps = [config_lp("cfg0", seed=s) for s in range(3)]
+    lps += [config_lp("cfg3", index=i, scale=0.02) for i in range(4)]
+    lps += [config_lp("cfg4", index=i, scale=0.002) for i in range(3)]
+    return lps
+
+
+def _params(P, prec, **kw):
+    base = dict(precision=prec, tol=1e-4, max_iter=20000, lr=1e-3, phi=20)
+    base.update(kw)
+    return P.opdhg_default_params(**base)
+
+
+def _same(a, b):
+    xa, ya, ra = a
+    xb, yb, rb = b
+    assert ra.status == rb.status
+    assert ra.iterations == rb.iterations and ra.attempts == rb.attempts
+    assert ra.restarts == rb.restarts
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    assert ra.primal_obj == rb.primal_obj and ra.rel_kkt == rb.rel_kkt
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
+def test_mix_equals_solo(prec_name):
+    P = _P()
+    prec = P.OPDHG_FP32 if prec_name == "fp32" else P.OPDHG_FP64
+    lps = _mix()
+    solo = [P.opdhg_solve(lp, _params(P, prec)) for lp in lps]
+    with P.Server(512 << 20, precision=prec) as srv:
+        tickets = [srv.submit(lp, _params(P, prec)) for lp in lps]
+        got = [srv.wait(t, 120.0) for t in tickets]
+        st = srv.stats()
+        assert st.completed == len(lps) and st.failed == 0 and st.active == 0
+        lat = [srv.latency(t) for t in tickets]
+    for a, b in zip(got, solo):
+        _same(a, b)
+    assert all(r.status == P.capi.OPDHG_STATUS_OPTIMAL for _, _, r in got)
+    assert all(v > 0 for v in lat)
+
+
+def test_tight_budget_admits_in_turn():
+    P = _P()
+    prec = P.OPDHG_FP32
+    lps = [config_lp("cfg3", index=i, scale=0.03) for i in range(6)]
+    params = _params(P, prec)
+    need = [P.opdhg_workspace_bytes(lp, params) for lp in lps]
+    budget = int(2.2 * max(need))  # two at a time at most
+    solo = [P.opdhg_solve(lp, params) for lp in lps]
+    with P.Server(64 << 20, precision=prec, budget_bytes=budget) as srv:
+        tickets = [srv.submit(lp, params) for lp in lps]
+        got = [srv.wait(t, 120.0) for t in tickets]
+        st = srv.stats()
+    assert st.peak_bytes <= budget
+    assert st.completed == len(lps)
+    for a, b in zip(got, solo):
+        _same(a, b)
+
+
+def test_over_budget_request_fails_alone():
+    P = _P()
+    prec = P.OPDHG_FP32
+    small = config_lp("cfg0", seed=1)
+    big = config_lp("cfg4", index=0, scale=0.01)
+    params = _params(P, prec)
+    budget = P.opdhg_workspace_bytes(small, params) * 2
+    with P.Server(64 << 20, precision=prec, budget_bytes=budget) as srv:
+        tb = srv.submit(big, params)
+        ts = srv.submit(small, params)
+        with pytest.raises(P.OpdhgError) as e:
+            srv.wait(tb, 60.0)
+        assert e.value.code == P.capi.OPDHG_ERR_OVER_BUDGET
+        x, y, r = srv.wait(ts, 60.0)
+    assert r.status == P.capi.OPDHG_STATUS_OPTIMAL
+
+
+def test_cancel_running_and_queued():
+    P = _P()
+    prec = P.OPDHG_FP32
+    lp = config_lp("cfg3", index=1, scale=0.05)
+    endless = _params(P, prec, tol=0.0, max_iter=10**9, time_limit_s=1e9)
+    with P.Server(64 << 20, precision=prec, max_active=1) as srv:
+        t_run = srv.submit(lp, endless)
+        t_queued = srv.submit(lp, endless)
+        time.sleep(0.5)
+        srv.cancel(t_queued)
+        srv.cancel(t_run)
+        for t in (t_run, t_queued):
+            with pytest.raises(P.OpdhgError) as e:
+                srv.wait(t, 60.0)
+            assert e.value.code == P.capi.OPDHG_ERR_CANCELLED
+        st = srv.stats()
+        assert st.cancelled == 2 and st.active == 0 and st.bytes_in_use == 0
+        # the server keeps serving after cancellations
+        x, y, r = srv.wait(srv.submit(config_lp("cfg0", seed=2), _params(P, prec)), 60.0)
+    assert r.status == P.capi.OPDHG_STATUS_OPTIMAL
+
+
+def test_arrivals_while_others_iterate():
+    P = _P()
+    prec = P.OPDHG_FP32
+    lps = [config_lp("cfg4", index=i, scale=0.003) for i in range(6)]
+    params = _params(P, prec)
+    solo = [P.opdhg_solve(lp, params) for lp in lps]
+    with P.Server(256 << 20, precision=prec) as srv:
+        tickets = []
+        for lp in lps:
+            tickets.append(srv.submit(lp, params))
+            time.sleep(0.02)
+        got = [srv.wait(t, 120.0) for t in tickets]
+        assert srv.stats().replays > 0
+    for a, b in zip(got, solo):
+        _same(a, b)

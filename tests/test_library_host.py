@@ -1,0 +1,131 @@
+"""Host-side checks of libopdhg.so that need no GPU.
+
+- The library exports every function include/opdhg.h declares, and the
+  Python binding names only exported functions.
+- opdhg_validate applies the same rules as the oracle's validation.
+- opdhg_rescale (host C++) gives the oracle's rescaling bit for bit: both
+  compute correctly rounded sums, so no tolerance is needed.
+- opdhg_workspace_bytes grows with the LP and is smaller in FP32.
+No test here launches a kernel.
+"""
+
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2506_17650_amd as P
+from paper_2506_17650_amd import capi
+from lpgen import config_lp, tiny_lp
+from oracle.problem import InvalidLP, rescale, validate
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "opdhg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(opdhg_[a-z_0-9]+)\s*\(", text)))
+
+
+def exported_symbols():
+    out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], check=True,
+                         capture_output=True, text=True).stdout
+    return {line.split()[-1] for line in out.splitlines() if line.strip()}
+
+
+def test_library_exports_every_declared_function():
+    assert os.path.exists(capi.LIB_PATH), "build the library first"
+    decl = declared_functions()
+    assert len(decl) >= 25, decl
+    missing = [f for f in decl if f not in exported_symbols()]
+    assert not missing, missing
+
+
+def test_binding_names_only_declared_functions():
+    decl = set(declared_functions())
+    assert set(capi.SIGNATURES) <= decl, set(capi.SIGNATURES) - decl
+    lib = P.load()
+    for name in capi.SIGNATURES:
+        assert getattr(lib, name) is not None
+
+
+def _broken_lps():
+    """One invalid LP per validation rule, from a valid tiny LP."""
+    base = tiny_lp(seed=3)
+
+    def mutate(**kw):
+        import copy
+        lp = copy.deepcopy(base)
+        for k, v in kw.items():
+            setattr(lp, k, v)
+        return lp
+
+    rp = base.row_ptr.copy()
+    ci = base.col_idx.copy()
+    cases = {
+        "n zero": mutate(n=0, c=np.zeros(0), l=np.zeros(0), u=np.zeros(0),
+                         col_idx=np.zeros(0, np.int32), val=np.zeros(0),
+                         row_ptr=np.zeros(base.m + 1, np.int64)),
+        "row_ptr start": mutate(row_ptr=np.r_[1, rp[1:]]),
+        "row_ptr end": mutate(row_ptr=np.r_[rp[:-1], rp[-1] - 1]),
+        "column range": mutate(col_idx=np.r_[ci[:-1], base.n]),
+        "nan value": mutate(val=np.r_[np.nan, base.val[1:]]),
+        "inf b": mutate(b=np.r_[np.inf, base.b[1:]]),
+        "inf c": mutate(c=np.r_[base.c[:-1], -np.inf]),
+        "l = +inf": mutate(l=np.r_[np.inf, base.l[1:]]),
+        "u = -inf": mutate(u=np.r_[-np.inf, base.u[1:]]),
+        "l > u": mutate(l=np.r_[base.u[0] + 1.0, base.l[1:]]),
+        "sense": mutate(sense=np.r_[2, base.sense[1:]].astype(np.int8)),
+    }
+    # a duplicate (row, col): repeat the first column of row 0
+    if rp[1] - rp[0] >= 2:
+        ci2 = ci.copy()
+        ci2[rp[0] + 1] = ci2[rp[0]]
+        cases["duplicate"] = mutate(col_idx=ci2)
+    return base, cases
+
+
+def test_validate_agrees_with_oracle():
+    base, cases = _broken_lps()
+    assert P.opdhg_validate(base) == 0
+    validate(base)
+    for name, lp in cases.items():
+        with pytest.raises(InvalidLP):
+            validate(lp)
+        assert P.opdhg_validate(lp) == capi.OPDHG_ERR_INVALID_ARGUMENT, name
+
+
+@pytest.mark.parametrize("name,seed", [("cfg0", 0), ("cfg0", 5), ("cfg1", 1)])
+def test_rescale_bitwise_equal_to_oracle(name, seed):
+    lp = config_lp(name, seed=seed, scale=0.05 if name == "cfg1" else 1.0)
+    sval, dr, dc = P.opdhg_rescale(lp, P.opdhg_default_params())
+    ref = rescale(lp, 10, 1.0)
+    assert np.array_equal(dr, ref.Dr)
+    assert np.array_equal(dc, ref.Dc)
+    assert np.array_equal(sval, ref.A.data)
+
+
+def test_workspace_bytes_monotone_and_precision():
+    small = config_lp("cfg0", seed=0)
+    big = config_lp("cfg1", seed=1, scale=0.05)
+    p64 = P.opdhg_default_params()
+    p32 = P.opdhg_default_params(precision=P.OPDHG_FP32)
+    b_small = P.opdhg_workspace_bytes(small, p64)
+    b_big = P.opdhg_workspace_bytes(big, p64)
+    assert 0 < b_small < b_big
+    assert P.opdhg_workspace_bytes(big, p32) < b_big
+    # a batch needs at least the sum of its members' slots
+    assert P.opdhg_batch_workspace_bytes([small, small], p64) >= b_small
+
+
+def test_binding_refuses_mismatched_lengths():
+    base, _ = _broken_lps()
+    import copy
+    lp = copy.deepcopy(base)
+    lp.c = lp.c[:-1]
+    with pytest.raises(ValueError):
+        P.opdhg_validate(lp)
