@@ -1,43 +1,62 @@
 """Benchmark of restarted PDHG with online preconditioning on one MI355X.
 
-One step is one launch sequence of the hot path: the KKT evaluation with
-its restart / termination decision, then 64 step attempts, each the
-CSR(A^T) SpMV fused with the primal step, the CSR(A) SpMV fused with the
-dual step and the adaptive step decision, and the AdaGrad learner on update
-iterations (every 20th). The LP never terminates during timing (tol 0), so
-every step does the full work.
+One step is one launch sequence of the hot path on the resident LP: the KKT
+evaluation with its restart / termination decision, then 64 step attempts,
+each the CSR(A^T) SpMV fused with the primal step, the CSR(A) SpMV fused
+with the dual step, and the adaptive step decision, with the AdaGrad
+learner on update iterations (every 20th). The LP never terminates during
+timing (tol 0), so every step does the full work.
 
-Default workload: the badly scaled LP (m = 50k rows, 40% equality, n = 100k
-columns, power-law column degree on 2..2000 with exponent 2.2, ~0.7M
-nonzeros, row scales log-uniform in [1e-3, 1e3]), synthetic and seeded.
+Headline: accepted PDHG iterations per second on the badly scaled LP
+(m = 50k rows, 40% equality, n = 100k columns, power-law column degree on
+2..2000 with exponent 2.2, ~0.7M nonzeros, row scales log-uniform in
+[1e-3, 1e3]; synthetic, seeded), FP32 storage and SpMV with FP64
+reductions, data resident in HBM. The same JSON line carries:
+  roofline      the dominant sparse-product kernel: algorithmic bytes per
+                launch / average launch time (HIP events on the solver's
+                stream) against 8 TB/s; HBM traffic from rocprofv3 counters
+                when a counter summary for the current kernel source exists
+  cpu_baseline  the FP64 oracle on a bounded sample of the same LP
+  fp64          the same LP in FP64
+  hbm           the block-angular LP (1.92M x 5.12M, 35M nonzeros), FP32
+  batch         256 LPs solved to relative KKT 1e-4 in one packed launch
+                set (FP32), against plain FP64 PDHG (lr 0) one at a time,
+                with the FP32 error against FP64 per result
+  serving       a Poisson stream of serving requests through the
+                continuous-batching server (FP32), against plain FP64 PDHG
+                served first-in first-out one at a time; p50 / p99 latency
 
-The printed JSON line reports accepted PDHG iterations per second
-(whole-job throughput, data resident in HBM), the achieved bandwidth of
-the dominant kernel against the HBM roofline (algorithmic bytes / kernel
-time measured with HIP events on the solver's stream), and the FP64 CPU
-oracle timed on a bounded sample of the same LP on the host.
-
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--sections main,fp64,hbm,batch,serving]
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "PDHG iters/s + SpMV HBM GB/s; LP solves/s and p99 latency at rel KKT 1e-4"
+SECTIONS = ("main", "fp64", "hbm", "batch", "serving")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_17650_amd", "csrc", "kernels.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes
+# ---------------------------------------------------------------------------
 
 def primal_kernel_bytes(lp, vbytes: int) -> float:
     """Algorithmic bytes of one launch of the primal kernel.
@@ -51,6 +70,18 @@ def primal_kernel_bytes(lp, vbytes: int) -> float:
     return nnz * (vbytes + 4) + 4.0 * (n + 1) + vbytes * m + 8.0 * vbytes * n
 
 
+def dual_kernel_bytes(lp, vbytes: int) -> float:
+    """Algorithmic bytes of one launch of the dual kernel.
+
+    CSR(A): nnz values + indices + (m+1) row pointers; the gathered x' read
+    once (n values); the dual vectors: read y, b, Sigma, A x and the running
+    sum, write y', A x' and the new sum (8 m values), and the row senses
+    (m bytes).
+    """
+    nnz, m, n = lp.nnz, lp.m, lp.n
+    return nnz * (vbytes + 4) + 4.0 * (m + 1) + vbytes * n + 8.0 * vbytes * m + m
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -62,12 +93,256 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def counter_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary.
+
+    profiles/<kernel>_<workload>_<precision>_counters.txt holds the
+    FETCH_SIZE and WRITE_SIZE readings of the kernel and of a device copy
+    of known size, and the SHA-256 of the kernel source they were taken
+    with. Returns None when the file is absent or the source has changed.
+    """
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else None
+
+
+# ---------------------------------------------------------------------------
+# sections
+# ---------------------------------------------------------------------------
+
+def iterate_section(P, lp, prec, args, steps, warmup, reps):
+    """Replays of the resident LP: iterations/s and kernel times."""
+    params = P.opdhg_default_params(precision=prec, tol=0.0, max_iter=10**12, lr=args.lr,
+                                    phi=args.phi, normalize=1, time_limit_s=1e9,
+                                    tile_nnz=args.tile_nnz, lanes=args.lanes,
+                                    workgroups=args.workgroups)
+    import torch
+    t = time.perf_counter()
+    sess = P.Session(lp, params)
+    log(f"[bench]   session ready in {time.perf_counter() - t:.1f}s")
+    sess.replay(warmup)
+    _, _, _, _, st0 = sess.state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sess.replay(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, _, _, _, st1 = sess.state()
+    if st1.status != P.capi.OPDHG_STATUS_RUNNING:
+        raise SystemExit(f"solver stopped during timing (status {st1.status})")
+    primal_ms, dual_ms = sess.time_kernels(reps)
+    sess.close()
+    vb = 4 if prec == P.OPDHG_FP32 else 8
+    kb = {"primal": primal_kernel_bytes(lp, vb), "dual": dual_kernel_bytes(lp, vb)}
+    km = {"primal": primal_ms, "dual": dual_ms}
+    return {
+        "iters": st1.k - st0.k, "attempts": st1.attempts - st0.attempts, "seconds": dt,
+        "kernels": {k: {"avg_launch_ms": km[k], "bytes_per_launch": kb[k],
+                        "achieved_GBs": kb[k] / (km[k] * 1e-3) / 1e9,
+                        "frac": kb[k] / (km[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                    for k in km},
+    }
+
+
+def section_main(P, args):
+    from lpgen import config_lp
+    from lpgen.generators import summary
+    t = time.perf_counter()
+    lp = config_lp("cfg1")
+    log(f"[bench] main: cfg1 m={lp.m} n={lp.n} nnz={lp.nnz} "
+        f"(generated in {time.perf_counter() - t:.1f}s)")
+    r = iterate_section(P, lp, P.OPDHG_FP32, args, args.steps, args.warmup, args.kernel_reps)
+    log(f"[bench] main: {r['iters'] / r['seconds']:.0f} iters/s")
+    return lp, summary(lp), r
+
+
+def section_fp64(P, args, lp):
+    log("[bench] fp64: cfg1 in FP64")
+    r = iterate_section(P, lp, P.OPDHG_FP64, args, args.steps, args.warmup, args.kernel_reps)
+    log(f"[bench] fp64: {r['iters'] / r['seconds']:.0f} iters/s")
+    return {"workload": "cfg1", "dtype": "f64", "value": r["iters"] / r["seconds"],
+            "unit": "PDHG iters/s", "attempts_per_s": r["attempts"] / r["seconds"],
+            "kernels": r["kernels"]}
+
+
+def section_hbm(P, args):
+    from lpgen import config_lp
+    t = time.perf_counter()
+    lp = config_lp("cfg2")
+    log(f"[bench] hbm: cfg2 m={lp.m} n={lp.n} nnz={lp.nnz} "
+        f"(generated in {time.perf_counter() - t:.1f}s)")
+    r = iterate_section(P, lp, P.OPDHG_FP32, args, args.hbm_steps, 1, 10)
+    log(f"[bench] hbm: {r['iters'] / r['seconds']:.0f} iters/s, primal "
+        f"{r['kernels']['primal']['achieved_GBs']:.0f} GB/s, dual "
+        f"{r['kernels']['dual']['achieved_GBs']:.0f} GB/s")
+    return {"workload": "cfg2: block-angular LP, 64 blocks of 30k x 80k + 2k linking rows",
+            "m": lp.m, "n": lp.n, "nnz": lp.nnz, "dtype": "f32",
+            "value": r["iters"] / r["seconds"], "unit": "PDHG iters/s",
+            "attempts_per_s": r["attempts"] / r["seconds"], "steps": args.hbm_steps,
+            "kernels": r["kernels"]}
+
+
+def section_batch(P, args):
+    import numpy as np
+    from lpgen import batch_lps
+    t = time.perf_counter()
+    lps = batch_lps(args.batch_size)
+    nnz = sum(lp.nnz for lp in lps)
+    log(f"[bench] batch: {len(lps)} cfg3 LPs, {nnz} nonzeros "
+        f"(generated in {time.perf_counter() - t:.1f}s)")
+    p32 = P.opdhg_default_params(precision=P.OPDHG_FP32, tol=1e-4, max_iter=200000,
+                                 lr=args.lr, phi=args.phi, time_limit_s=600)
+    p64 = P.opdhg_default_params(precision=P.OPDHG_FP64, tol=1e-4, max_iter=200000, lr=0.0,
+                                 time_limit_s=600)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res32 = P.opdhg_solve_batch(lps, p32)
+    wall32 = time.perf_counter() - t0
+    loop32 = max(r.solve_seconds for _, _, r in res32)
+    opt32 = sum(r.status == P.capi.OPDHG_STATUS_OPTIMAL for _, _, r in res32)
+    log(f"[bench] batch: FP32 packed: {opt32}/{len(lps)} optimal in {wall32:.1f}s "
+        f"(loop {loop32:.1f}s)")
+    # plain FP64 PDHG one at a time on an evenly spaced sample of the batch
+    idx = list(range(0, len(lps), max(1, len(lps) // args.batch_baseline)))[: args.batch_baseline]
+    wall64, loop64, opt64, errs = 0.0, 0.0, 0, []
+    for i in idx:
+        t0 = time.perf_counter()
+        x, y, r = P.opdhg_solve(lps[i], p64)
+        wall64 += time.perf_counter() - t0
+        loop64 += r.solve_seconds
+        opt64 += r.status == P.capi.OPDHG_STATUS_OPTIMAL
+        r32 = res32[i][2]
+        errs.append(abs(r32.primal_obj - r.primal_obj) / (1.0 + abs(r.primal_obj)))
+    log(f"[bench] batch: FP64 one at a time: {opt64}/{len(idx)} optimal in {wall64:.1f}s")
+    kkt32 = [r.rel_kkt for _, _, r in res32]
+    return {
+        "workload": f"cfg3: {len(lps)} LPs, m log-uniform in [1k, 50k], n=2m, 3..8 per column",
+        "lps": len(lps), "nnz_total": nnz, "dtype": "f32",
+        "solves_per_s": opt32 / wall32, "solves_per_s_loop": opt32 / loop32,
+        "optimal": opt32, "wall_s": wall32, "loop_s": loop32,
+        "fp32_rel_kkt_max": max(kkt32),
+        "baseline": {
+            "kind": "plain FP64 PDHG (lr 0), one LP at a time, same GPU",
+            "sample": f"{len(idx)} LPs evenly spaced in the batch", "optimal": opt64,
+            "solves_per_s": opt64 / wall64, "solves_per_s_loop": opt64 / loop64,
+        },
+        "speedup_solves_per_s": (opt32 / wall32) / (opt64 / wall64) if opt64 else None,
+        "fp32_vs_fp64_rel_objective_error": {
+            "per_result": errs, "max": max(errs), "median": pct(errs, 50),
+            "note": "|p32 - p64| / (1 + |p64|) on the sampled LPs; both at rel KKT <= 1e-4"},
+    }
+
+
+def section_serving(P, args):
+    import numpy as np
+    from lpgen import config_lp
+    from lpgen.generators import serving_requests
+    n = args.serve_requests
+    t = time.perf_counter()
+    reqs = [config_lp("cfg4", index=i) for i in range(n)]
+    log(f"[bench] serving: {n} cfg4 requests, nnz "
+        f"{min(r.nnz for r in reqs)}..{max(r.nnz for r in reqs)} "
+        f"(generated in {time.perf_counter() - t:.1f}s)")
+    p32 = P.opdhg_default_params(precision=P.OPDHG_FP32, tol=1e-4, max_iter=200000,
+                                 lr=args.lr, phi=args.phi, time_limit_s=600)
+    p64 = P.opdhg_default_params(precision=P.OPDHG_FP64, tol=1e-4, max_iter=200000, lr=0.0,
+                                 time_limit_s=600)
+    # plain FP64 one at a time: measured service time of each request
+    service, ok64 = [], 0
+    for i, lp in enumerate(reqs):
+        t0 = time.perf_counter()
+        _, _, r = P.opdhg_solve(lp, p64)
+        service.append(time.perf_counter() - t0)
+        ok64 += r.status == P.capi.OPDHG_STATUS_OPTIMAL
+    mu_plain = n / sum(service)
+    log(f"[bench] serving: FP64 one at a time: {ok64}/{n} optimal, mu {mu_plain:.2f}/s")
+    rate = 0.7 * mu_plain
+    arrivals, _ = serving_requests(n, rate)
+    arrivals = np.asarray(arrivals) - arrivals[0]
+    # first-in first-out single server with the measured service times
+    fin, lat64 = 0.0, []
+    for a, s in zip(arrivals, service):
+        fin = max(fin, a) + s
+        lat64.append(fin - a)
+    span64 = fin - arrivals[0]
+    # the continuous-batching server, open loop at the same arrival times
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    arena = int(min(args.serve_budget_gb * 1e9, 0.8 * free))
+    lat32, ok32 = [], 0
+    with P.Server(arena, precision=P.OPDHG_FP32, max_active=256) as srv:
+        # closed loop: everything at once
+        t0 = time.perf_counter()
+        tk = [srv.submit(lp, p32) for lp in reqs]
+        for x in tk:
+            srv.wait(x)
+        mu_srv = n / (time.perf_counter() - t0)
+        log(f"[bench] serving: server closed loop mu {mu_srv:.2f}/s")
+        # open loop
+        tickets = [None] * n
+        t0 = time.perf_counter()
+
+        def feed():
+            for i, lp in enumerate(reqs):
+                d = arrivals[i] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(lp, p32)
+
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        for x in tickets:
+            _, _, r = srv.wait(x)
+            ok32 += r.status == P.capi.OPDHG_STATUS_OPTIMAL
+            lat32.append(srv.latency(x))
+        span32 = time.perf_counter() - t0
+        st = srv.stats()
+    log(f"[bench] serving: server open loop p50 {pct(lat32, 50):.3f}s p99 {pct(lat32, 99):.3f}s; "
+        f"FIFO FP64 p50 {pct(lat64, 50):.3f}s p99 {pct(lat64, 99):.3f}s")
+    return {
+        "workload": f"cfg4: {n} requests, m log-uniform in [500, 500k], n=2.5m, "
+                    "power-law degree 4..10, Poisson arrivals",
+        "requests": n, "rate_per_s": rate, "rate_rule": "0.7 x plain FP64 throughput",
+        "arena_bytes": arena, "peak_bytes": st.peak_bytes, "dtype": "f32",
+        "optimal": ok32, "solves_per_s": ok32 / span32, "closed_loop_solves_per_s": mu_srv,
+        "latency_p50_s": pct(lat32, 50), "latency_p99_s": pct(lat32, 99),
+        "baseline": {
+            "kind": "plain FP64 PDHG (lr 0) served first-in first-out one at a time, same GPU "
+                    "and arrivals; latencies from the measured per-request solve times",
+            "optimal": ok64, "solves_per_s": ok64 / span64, "closed_loop_solves_per_s": mu_plain,
+            "latency_p50_s": pct(lat64, 50), "latency_p99_s": pct(lat64, 99)},
+    }
+
+
 def oracle_baseline(lp, lr: float, phi: int, seconds: float) -> dict:
     """The FP64 oracle as it stands, single-threaded, on a bounded sample:
     as many accepted iterations of the same LP as fit in ~`seconds`."""
     import oracle
     from oracle.params import default_params
-    # calibrate with a short run, then time a run sized to the budget
     t0 = time.perf_counter()
     r = oracle.solve(lp, default_params(tol=0.0, max_iter=4, lr=lr, phi=phi))
     per_it = max((time.perf_counter() - t0) / max(r.iterations, 1), 1e-4)
@@ -89,85 +364,58 @@ def oracle_baseline(lp, lr: float, phi: int, seconds: float) -> dict:
 def run(args) -> dict:
     import torch
     import paper_2506_17650_amd as P
-    from lpgen import config_lp
-    from lpgen.generators import summary
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     P.load()
-    t = time.perf_counter()
-    lp = config_lp(args.workload, scale=args.scale)
-    shape = summary(lp)
-    log(f"[bench] workload {args.workload} m={lp.m} n={lp.n} nnz={lp.nnz} "
-        f"generated in {time.perf_counter() - t:.1f}s")
-    prec = P.OPDHG_FP32 if args.precision == "fp32" else P.OPDHG_FP64
-    vbytes = 4 if prec == P.OPDHG_FP32 else 8
-    params = P.opdhg_default_params(precision=prec, tol=0.0, max_iter=10**12, lr=args.lr,
-                                    phi=args.phi, normalize=1, time_limit_s=1e9,
-                                    tile_nnz=args.tile_nnz, lanes=args.lanes,
-                                    workgroups=args.workgroups)
-    t = time.perf_counter()
-    sess = P.Session(lp, params)
-    log(f"[bench] session ready in {time.perf_counter() - t:.1f}s")
-    sess.replay(args.warmup)
-    torch.cuda.synchronize()
-    _, _, _, _, st0 = sess.state()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sess.replay(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    _, _, _, _, st1 = sess.state()
-    iters = st1.k - st0.k
-    attempts = st1.attempts - st0.attempts
-    log(f"[bench] {args.steps} steps, {iters} iterations, {attempts} attempts in {dt:.3f}s; "
-        f"status {st1.status}")
-    if st1.status != P.capi.OPDHG_STATUS_RUNNING:
-        raise SystemExit(f"solver stopped during timing (status {st1.status})")
-    # dominant kernel: CSR(A^T) SpMV fused with the primal step
-    reps = max(20, args.kernel_reps)
-    ms = sess.time_primal_kernel(reps)
-    kbytes = primal_kernel_bytes(lp, vbytes)
-    achieved = kbytes / (ms * 1e-3) / 1e9
-    sess.close()
+    sections = [s for s in args.sections.split(",") if s]
+    lp, shape, main = section_main(P, args)
+    ker = main["kernels"]
+    dom = max(ker, key=lambda k: ker[k]["avg_launch_ms"])
+    kname = {"primal": "k_primal", "dual": "k_dual"}[dom]
     out = {
-        "metric": "PDHG iters/s + SpMV HBM GB/s; LP solves/s and p99 latency at rel KKT 1e-4",
-        "value": iters / dt,
+        "metric": METRIC,
+        "value": main["iters"] / main["seconds"],
         "unit": "PDHG iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": main["seconds"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == P.OPDHG_FP32 else "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: badly scaled random LP, power-law column degree"
-                        if args.workload == "cfg1" else args.workload,
+            "workload": "cfg1: badly scaled random LP, power-law column degree",
             "m": lp.m, "n": lp.n, "nnz": lp.nnz,
-            "row_len_mean": round(shape["row_len_mean"], 2),
-            "col_len_max": shape["col_len_max"],
-            "precision": args.precision + (" (reductions, steps, KKT in f64)"
-                                           if prec == P.OPDHG_FP32 else ""),
-            "attempts_per_step": 64,
+            "row_len_mean": round(shape["row_len_mean"], 2), "col_len_max": shape["col_len_max"],
+            "precision": "f32 A, vectors and SpMV; f64 reductions, steps and KKT",
+            "attempts_per_step": 64, "attempts_per_s": main["attempts"] / main["seconds"],
             "tile_nnz": args.tile_nnz, "lanes": args.lanes, "workgroups": args.workgroups,
             "lr": args.lr, "phi": args.phi, "normalize": True,
-            "attempts_per_s": attempts / dt,
         },
         "roofline": {
             "bound": "hbm",
-            "achieved": achieved,
+            "achieved": ker[dom]["achieved_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_primal (CSR(A^T) SpMV + primal step)",
-            "bytes_per_launch": kbytes,
-            "avg_launch_ms": ms,
+            "frac": ker[dom]["frac"],
+            "traffic": counter_traffic(kname, "cfg1", "fp32"),
+            "kernel": kname,
+            "bytes_per_launch": ker[dom]["bytes_per_launch"],
+            "avg_launch_ms": ker[dom]["avg_launch_ms"],
+            "kernels": ker,
         },
     }
+    if "fp64" in sections:
+        out["fp64"] = section_fp64(P, args, lp)
+    if "hbm" in sections:
+        out["hbm"] = section_hbm(P, args)
+    if "batch" in sections:
+        out["batch"] = section_batch(P, args)
+    if "serving" in sections:
+        out["serving"] = section_serving(P, args)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = oracle_baseline(lp, args.lr, args.phi, args.cpu_seconds)
@@ -179,15 +427,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cfg1")
-    ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--sections", default=",".join(SECTIONS))
     ap.add_argument("--lr", type=float, default=1e-5)
     ap.add_argument("--phi", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--tile-nnz", type=int, default=0, help="SpMV tile target (0: automatic)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per row (0: per tile)")
     ap.add_argument("--workgroups", type=int, default=0, help="workgroups per launch (0: auto)")
+    ap.add_argument("--hbm-steps", type=int, default=5)
+    ap.add_argument("--batch-size", type=int, default=256)
+    ap.add_argument("--batch-baseline", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

@@ -222,6 +222,12 @@ int opdhg_session_result(opdhg_session* s, double* x_out, double* y_out, opdhg_r
  * the session's stream. The kernel only rewrites the candidate buffers, so
  * the session state is unchanged. */
 int opdhg_session_time_primal_kernel(opdhg_session* s, int reps, double* avg_ms);
+/* Average device times of one launch of the primal kernel and of the dual
+ * kernel (CSR(A) SpMV of the candidate x fused with the dual step), each
+ * over reps back-to-back launches timed with HIP events on the session's
+ * stream. Timing launches write only the candidate buffers (no
+ * preconditioner update, no online gradient), so the state is unchanged. */
+int opdhg_session_time_kernels(opdhg_session* s, int reps, double* primal_ms, double* dual_ms);
 void opdhg_session_destroy(opdhg_session* s);
 
 /* ---- serving: continuous batching under a device-memory budget ---- */
@@ -235,11 +241,12 @@ typedef struct opdhg_server_cfg {
                                   happen between sequences */
   int32_t precision;     /* OPDHG_FP64 or OPDHG_FP32; every request must use it */
   int32_t workgroups;    /* workgroups of the sparse-product launches; 0: automatic */
+  int32_t prep_threads;  /* host threads preparing submitted LPs; 0: automatic */
   double poll_interval_s; /* idle wait of the scheduler thread */
 } opdhg_server_cfg;
 
 /* Defaults: budget = whole arena, 256 active LPs, 64 attempts per sequence,
- * FP32, automatic workgroups, 1 ms idle wait. */
+ * FP32, automatic workgroups and preparation threads, 1 ms idle wait. */
 void opdhg_server_default_cfg(opdhg_server_cfg* cfg);
 
 typedef struct opdhg_server_stats {
@@ -258,9 +265,10 @@ typedef struct opdhg_server_stats {
  * the first arena_bytes / 64 bytes, clamped to [4 MiB, 1 GiB]; the LPs share
  * the rest up to budget_bytes). Three streams: compute, host-to-device
  * uploads and device-to-host downloads; a NULL upload or download stream
- * uses the compute stream. The server runs two host threads: one prepares
- * submitted LPs (validation, rescaling, tiling) in submission order, one
- * admits prepared LPs in submission order as memory and slots free up,
+ * uses the compute stream. The server runs host threads of its own:
+ * workers prepare submitted LPs (validation, rescaling, tiling), taking
+ * them in submission order, and a scheduler admits prepared LPs in
+ * submission order as memory and slots free up,
  * uploads them while the resident LPs iterate, launches the shared launch
  * sequence, and retires finished LPs. An LP's arithmetic does not depend
  * on what else is resident, so each result equals its solo solve with the

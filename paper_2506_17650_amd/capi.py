@@ -89,7 +89,8 @@ class opdhg_state(ctypes.Structure):
 class opdhg_server_cfg(ctypes.Structure):
     _fields_ = [
         ("budget_bytes", c_sz), ("max_active", c_i32), ("attempts_per_replay", c_i32),
-        ("precision", c_i32), ("workgroups", c_i32), ("poll_interval_s", c_dbl),
+        ("precision", c_i32), ("workgroups", c_i32), ("prep_threads", c_i32),
+        ("poll_interval_s", c_dbl),
     ]
 
 
@@ -122,6 +123,7 @@ SIGNATURES = {
     "opdhg_session_result": (c_i32, [ctypes.c_void_p, _p(c_dbl), _p(c_dbl),
                                      _p(opdhg_result)]),
     "opdhg_session_time_primal_kernel": (c_i32, [ctypes.c_void_p, c_i32, _p(c_dbl)]),
+    "opdhg_session_time_kernels": (c_i32, [ctypes.c_void_p, c_i32, _p(c_dbl), _p(c_dbl)]),
     "opdhg_session_destroy": (None, [ctypes.c_void_p]),
     "opdhg_server_default_cfg": (None, [_p(opdhg_server_cfg)]),
     "opdhg_server_create": (ctypes.c_void_p, [_p(opdhg_server_cfg), ctypes.c_void_p, c_sz,
@@ -381,6 +383,13 @@ class Session:
         out = c_dbl(0.0)
         _check(load().opdhg_session_time_primal_kernel(self._h, int(reps), ctypes.byref(out)))
         return float(out.value)
+
+    def time_kernels(self, reps: int) -> tuple[float, float]:
+        """(primal_ms, dual_ms): average device time of one launch of each."""
+        a, b = c_dbl(0.0), c_dbl(0.0)
+        _check(load().opdhg_session_time_kernels(self._h, int(reps), ctypes.byref(a),
+                                                 ctypes.byref(b)))
+        return float(a.value), float(b.value)
 
     def close(self) -> None:
         if self._h:

@@ -4,12 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "opdhg.h"
@@ -23,6 +25,11 @@ thread_local std::string g_err;
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
+}
+
+int host_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return hw ? (int)hw : 1;
 }
 
 int fail_hip(hipError_t e, const char* what) {
@@ -588,6 +595,11 @@ int Group::launch_primal_forced() {
   return Kernels<double>::primal(cfg, stream, 1);
 }
 
+int Group::launch_dual_forced() {
+  if (prec == OPDHG_FP32) return Kernels<float>::dual(cfg, stream, 1);
+  return Kernels<double>::dual(cfg, stream, 1);
+}
+
 int Group::replay() {
   HIP_TRY(hipGraphLaunch(exec, stream));
   return OPDHG_OK;
@@ -1050,15 +1062,15 @@ int opdhg_session_result(opdhg_session* s, double* x_out, double* y_out, opdhg_r
   return OPDHG_OK;
 }
 
-int opdhg_session_time_primal_kernel(opdhg_session* s, int reps, double* avg_ms) {
-  if (!s || reps < 1 || !avg_ms) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
-  SessionImpl& S = s->impl;
+// Average time of reps back-to-back launches of one forced kernel.
+static int time_forced(SessionImpl& S, int reps, bool primal, double* avg_ms) {
+  auto launch = [&] { return primal ? S.grp.launch_primal_forced() : S.grp.launch_dual_forced(); };
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  int rc = S.grp.launch_primal_forced();  // warm-up
+  int rc = launch();  // warm-up
   HIP_TRY(hipEventRecord(e0, S.grp.stream));
-  for (int r = 0; r < reps && rc == 0; ++r) rc = S.grp.launch_primal_forced();
+  for (int r = 0; r < reps && rc == 0; ++r) rc = launch();
   HIP_TRY(hipEventRecord(e1, S.grp.stream));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -1068,6 +1080,19 @@ int opdhg_session_time_primal_kernel(opdhg_session* s, int reps, double* avg_ms)
   if (rc) return fail(OPDHG_ERR_DEVICE, device_error_string());
   *avg_ms = ms / reps;
   return OPDHG_OK;
+}
+
+int opdhg_session_time_primal_kernel(opdhg_session* s, int reps, double* avg_ms) {
+  if (!s || reps < 1 || !avg_ms) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  return time_forced(s->impl, reps, true, avg_ms);
+}
+
+int opdhg_session_time_kernels(opdhg_session* s, int reps, double* primal_ms, double* dual_ms) {
+  if (!s || reps < 1 || !primal_ms || !dual_ms)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  int rc = time_forced(s->impl, reps, true, primal_ms);
+  if (!rc) rc = time_forced(s->impl, reps, false, dual_ms);
+  return rc;
 }
 
 void opdhg_session_destroy(opdhg_session* s) {
@@ -1123,9 +1148,27 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, voi
   std::vector<SlotLayout> L(count);
   size_t off = 0;
   std::vector<size_t> offs(count);
+  // validation, rescaling, transposes and tiling of each LP are independent
+  std::vector<int> rcs(count, OPDHG_OK);
+  std::vector<std::string> msgs(count);
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (int i = next++; i < count; i = next++) {
+      int r = validate_lp(&lps[i]);
+      if (!r) r = prepare(&lps[i], p, P[i], false);
+      if (r) {
+        rcs[i] = r;
+        msgs[i] = opdhg_last_error();
+      }
+    }
+  };
+  const int nth = std::max(1, std::min({count, host_threads(), 16}));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
   for (int i = 0; i < count; ++i) {
-    if ((rc = validate_lp(&lps[i]))) return rc;
-    if ((rc = prepare(&lps[i], p, P[i], false))) return rc;
+    if (rcs[i]) return fail(rcs[i], "LP " + std::to_string(i) + ": " + msgs[i]);
     L[i] = slot_layout(P[i].m, P[i].n, P[i].nnz, P[i].tiles_t.size(), P[i].tiles_a.size(),
                        p->precision);
     offs[i] = off;

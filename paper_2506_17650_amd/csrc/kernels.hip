@@ -810,7 +810,8 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
         const double eta = c->eta, om = c->omega;
         tau = (V)(eta / om);
         etav = (V)eta;
-        learn = c->learn_now != 0;
+        // a forced (timing) launch writes only the candidate buffers
+        learn = !force && c->learn_now != 0;
         lscale = 1.0;
         upd = !force && c->learn_pending && learn_side(c, lp->prm, true, &lscale);
         hnorm = c->hp_norm;
@@ -890,7 +891,7 @@ struct DualPre {
 };
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg) {
+__global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
   __shared__ SpmvShared<V, 1> sh;
   __shared__ DD s_red[4 * 4];
   const double nodiv[1] = {0.0};
@@ -913,15 +914,15 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg) {
       cfg.work_a, side_chunks(cfg.counts, false), s_items,
       [&](const WorkItem& it) {
         c = it.ctl;
-        if (!attempt_guard(c)) return false;
+        if (!force && !attempt_guard(c)) return false;
         lp = &cfg.lps[it.lp];
         const int cur = c->cur, nxt = cur ^ 1;
         const double eta = c->eta, om = c->omega;
         sig = (V)(eta * om);
         etav = (V)eta;
-        learn = c->learn_now != 0;
+        learn = !force && c->learn_now != 0;  // as in k_primal
         lscale = 1.0;
-        upd = c->learn_pending && learn_side(c, lp->prm, false, &lscale);
+        upd = !force && c->learn_pending && learn_side(c, lp->prm, false, &lscale);
         hnorm = c->hd_norm;
         b = gp(static_cast<const V*>(lp->b));
         S = gp(static_cast<V*>(lp->S));
@@ -1297,8 +1298,8 @@ int Kernels<V>::primal(const LaunchCfg& c, void* stream, int force) {
   OPDHG_LAUNCH(k_primal<V>, c.launch_t, c, force);
 }
 template <typename V>
-int Kernels<V>::dual(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_dual<V>, c.launch_a, c);
+int Kernels<V>::dual(const LaunchCfg& c, void* stream, int force) {
+  OPDHG_LAUNCH(k_dual<V>, c.launch_a, c, force);
 }
 template <typename V>
 int Kernels<V>::decide(const LaunchCfg& c, void* stream) {

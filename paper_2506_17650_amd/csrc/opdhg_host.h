@@ -13,6 +13,7 @@ namespace opdhg {
 
 int fail(int code, const std::string& msg);
 int fail_hip(hipError_t e, const char* what);
+int host_threads();  // hardware threads of the host (at least 1)
 
 // Return the HIP error of expr as OPDHG_ERR_DEVICE (with a message).
 #define HIP_TRY(expr)                                  \
@@ -98,6 +99,7 @@ struct Group {
   int capture(int attempts_per_replay);
   int launch_init();
   int launch_primal_forced();
+  int launch_dual_forced();
   int launch_learn_flush();
   int replay();
   void release();

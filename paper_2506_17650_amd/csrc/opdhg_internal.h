@@ -189,7 +189,7 @@ template <typename V>
 struct Kernels {
   static int init_products(const LaunchCfg& c, void* stream);
   static int primal(const LaunchCfg& c, void* stream, int force);
-  static int dual(const LaunchCfg& c, void* stream);
+  static int dual(const LaunchCfg& c, void* stream, int force = 0);
   static int decide(const LaunchCfg& c, void* stream);
   static int learn_flush(const LaunchCfg& c, void* stream);
   static int eval_t(const LaunchCfg& c, void* stream);

@@ -2,7 +2,7 @@
 // budget.
 //
 // Submitted LPs are copied, then prepared (validation, rescaling, CSR
-// transpose, tiling) by a worker thread in submission order. The scheduler
+// transpose, tiling) by worker threads that take them in submission order. The scheduler
 // thread admits prepared LPs in submission order while the budget, the
 // launch-table capacity and the slot limit allow; it uploads each into its
 // own block of the arena and computes its initial A x on the upload stream
@@ -181,7 +181,8 @@ struct ServerImpl {
   std::vector<std::shared_ptr<Job>> active;  // resident, in table order
   int64_t items_t = 0, items_a = 0;          // tiles of the resident LPs
 
-  std::thread th_prep, th_sched;
+  std::vector<std::thread> th_prep;
+  std::thread th_sched;
 
   void prep_loop();
   void sched_loop();
@@ -254,7 +255,8 @@ void ServerImpl::fail_all(const std::string& msg) {
   cv_done.notify_all();
 }
 
-// Worker: prepares submitted LPs in submission order.
+// Worker (one of several): takes submitted LPs in submission order and
+// prepares them; admission still follows submission order.
 void ServerImpl::prep_loop() {
   for (;;) {
     std::shared_ptr<Job> j;
@@ -547,6 +549,7 @@ void opdhg_server_default_cfg(opdhg_server_cfg* cfg) {
   cfg->attempts_per_replay = 64;
   cfg->precision = OPDHG_FP32;
   cfg->workgroups = 0;
+  cfg->prep_threads = 0;
   cfg->poll_interval_s = 1e-3;
 }
 
@@ -558,6 +561,7 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
   }
   if (cfg->max_active < 1 || cfg->max_active > 65535 || cfg->attempts_per_replay < 1 ||
       (cfg->precision != OPDHG_FP32 && cfg->precision != OPDHG_FP64) || cfg->workgroups < 0 ||
+      cfg->prep_threads < 0 || cfg->prep_threads > 64 ||
       cfg->workgroups > kMaxGrid || !(cfg->poll_interval_s >= 0.0)) {
     fail(OPDHG_ERR_INVALID_ARGUMENT, "bad server configuration");
     return nullptr;
@@ -616,7 +620,9 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
     S.grp.release();
     return nullptr;
   }
-  S.th_prep = std::thread([&S] { S.prep_loop(); });
+  const int nprep = cfg->prep_threads > 0 ? cfg->prep_threads
+                                          : std::max(1, std::min(host_threads() / 2, 8));
+  for (int t = 0; t < nprep; ++t) S.th_prep.emplace_back([&S] { S.prep_loop(); });
   S.th_sched = std::thread([&S] { S.sched_loop(); });
   return s.release();
 }
@@ -749,7 +755,8 @@ void opdhg_server_destroy(opdhg_server* s) {
   }
   S.cv_prep.notify_all();
   S.cv_sched.notify_all();
-  if (S.th_prep.joinable()) S.th_prep.join();
+  for (auto& t : S.th_prep)
+    if (t.joinable()) t.join();
   if (S.th_sched.joinable()) S.th_sched.join();
   if (S.pinned_board) (void)hipHostFree(S.pinned_board);
   S.grp.release();
