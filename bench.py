@@ -368,6 +368,16 @@ def run(args) -> dict:
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     P.load()
+    if args.copy_probe_mb > 0:
+        # a device-to-device copy of known size, outside every timed region:
+        # profiler counter runs scale the solver kernels' byte counters by it
+        nb = int(args.copy_probe_mb * 2**20)
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] copy probe: {nb} bytes device to device")
     sections = [s for s in args.sections.split(",") if s]
     lp, shape, main = section_main(P, args)
     ker = main["kernels"]
@@ -441,6 +451,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=float, default=0.0,
+                    help="copy this many MiB device to device first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every LP here is solved on a single device "
