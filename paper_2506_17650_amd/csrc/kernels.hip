@@ -108,6 +108,27 @@ __device__ __forceinline__ gptr<T> gp(T* p) {
   return (gptr<T>)p;
 }
 
+// Element idx of a global array with a 32-bit byte offset: with the base
+// in scalar registers this is one global load with a 32-bit vector offset
+// (a 64-bit address would take two registers per load in flight). Every
+// array of a slot is below 4 GiB (checked on the host).
+template <typename T>
+__device__ __forceinline__ T ldg(gptr<const T> base, uint32_t idx) {
+  const uint32_t off = idx * (uint32_t)sizeof(T);
+  return *reinterpret_cast<gptr<const T>>(reinterpret_cast<gptr<const char>>(base) + off);
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg(gptr<T> base, uint32_t idx) {
+  return ldg<T>((gptr<const T>)base, idx);
+}
+
+template <typename T>
+__device__ __forceinline__ void stg(gptr<T> base, uint32_t idx, T v) {
+  const uint32_t off = idx * (uint32_t)sizeof(T);
+  *reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) + off) = v;
+}
+
 // Barrier for data exchanged through LDS only: waits for this wave's LDS
 // accesses, not for its global loads and stores, which stay in flight
 // across the barrier. (__syncthreads also drains every global access.)
@@ -275,7 +296,7 @@ using Acc = typename Num<V>::Acc;
 // Vector q at column c: vec[q][c], or vec[q][c] / div[q] for the average.
 template <typename V>
 __device__ __forceinline__ V vec_at(const gptr<const V>* vec, const double* div, int q, int c) {
-  const V v = vec[q][c];
+  const V v = ldg(vec[q], (uint32_t)c);
   return div[q] > 0.0 ? (V)((double)v / div[q]) : v;
 }
 
@@ -287,113 +308,78 @@ struct SpmvShared {
   Acc<V> wave[4][NA];
 };
 
-// One tile: sparse dot products of its rows with NA vectors and the row
-// epilogues. pre = load(row) is issued together with the tile's index and
-// value loads (every thread of a row's group loads it, for a clamped valid
-// row, so no load sits behind a branch); finish(row, val[NA], pre) runs in
-// the first thread of the row's group once the row's sums are known.
-// Loads past the end of the tile re-read its last nonzero and are masked,
-// so all of a thread's loads issue back to back. Called by the whole
-// workgroup (every branch below is uniform over it).
-template <typename V, int NA, typename Load, typename Finish>
-__device__ __forceinline__ void spmv_tile(const WorkItem& it, gptr<const int32_t> rp,
-                                          gptr<const int32_t> ci, gptr<const V> va,
-                                          const gptr<const V>* vec, const double* div,
-                                          Load&& load, Finish&& finish, SpmvShared<V, NA>& sh) {
+constexpr int kK = kTileCap / kBlock;  // nonzeros per thread of a stream tile
+
+// Registers of one stream tile between its load stage and its finish.
+template <typename V, typename Pre>
+struct StreamTile {
+  V a[kK];
+  int c[kK];
+  int rp0, rp1;
+  Pre pre;
+};
+
+// Stream tile, stage 1: every load of the tile that depends on no other
+// load: the epilogue's vector loads (pre = load(row), issued by every
+// thread of a row's group for a clamped valid row so that no load sits
+// behind a branch), the row's pointers, and the tile's values and column
+// indices (clamped to the tile's last nonzero, so the loads issue back to
+// back). Stream tiles group `lanes` threads per row: group g owns row rb+g.
+template <typename V, typename Pre, typename Load>
+__device__ __forceinline__ void stream_load(const WorkItem& it, gptr<const int32_t> rp,
+                                            gptr<const int32_t> ci, gptr<const V> va,
+                                            Load&& load, StreamTile<V, Pre>& T) {
   const int tid = threadIdx.x;
-  if (it.re <= it.rb) return;  // the placeholder tile of a side without rows
-  const int last = it.e - 1;
-  if (it.lanes == 0) {
-    // one long row: every thread takes every kBlock-th nonzero, U at a
-    // time so their loads overlap; waves combine through LDS
-    const int r = it.rb;
-    auto pre = load(r);
-    Acc<V> acc[NA];
+  const int r = it.rb + (tid >> __builtin_ctz(it.lanes));
+  const int rc = r < it.re ? r : it.re - 1;
+  T.pre = load(rc);
+  T.rp0 = ldg(rp, (uint32_t)rc);
+  T.rp1 = ldg(rp, (uint32_t)rc + 1u);
+  if (it.e > it.s) {  // a tile of empty rows has no nonzeros to read
+    const int last = it.e - 1;
 #pragma unroll
-    for (int q = 0; q < NA; ++q) acc[q].zero();
-    constexpr int U = 4;
-    for (int k = it.s + tid; k < it.e; k += U * kBlock) {
-      V a[U];
-      int c[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int kk = min(k + u * kBlock, last);
-        a[u] = va[kk];
-        c[u] = ci[kk];
-      }
-#pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        V x[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = vec_at(vec, div, q, c[u]);
-        // a select, not a branch: a branch would let the compiler sink the
-        // loads into it, one wait each
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          acc[q].add(Num<V>::mask(k + u * kBlock < it.e, Num<V>::mul(a[u], x[u])));
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-      for (int q = 0; q < NA; ++q) acc[q].merge_xor(off);
-    }
-    if ((tid & 63) == 0) {
-#pragma unroll
-      for (int q = 0; q < NA; ++q) sh.wave[tid >> 6][q] = acc[q];
-    }
-    lds_barrier();
-    if (tid == 0) {
-      V out[NA];
-#pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        Acc<V> t = sh.wave[0][q];
-        t.merge(sh.wave[1][q]);
-        t.merge(sh.wave[2][q]);
-        t.merge(sh.wave[3][q]);
-        out[q] = t.value();
-      }
-      finish(r, out, pre);
-    }
-    lds_barrier();
-    return;
-  }
-  // stream tile: group g of `lanes` threads owns row rb + g (at most one)
-  const int L = it.lanes;  // a power of two
-  const int g = tid >> __builtin_ctz(L);
-  const int lane = tid & (L - 1);
-  const int r = it.rb + g;
-  const bool has_row = r < it.re;
-  const int rc = has_row ? r : it.re - 1;
-  const int n = it.e - it.s;
-  constexpr int K = kTileCap / kBlock;
-  V a[K];
-  int c[K];
-  // every load of the tile that does not depend on another is issued here,
-  // before any of them is used
-  auto pre = load(rc);
-  const int rp0 = rp[rc], rp1 = rp[rc + 1];
-  if (n > 0) {  // a tile of empty rows has no nonzeros to read
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      const int k = min(it.s + tid + u * kBlock, last);
-      a[u] = va[k];
-      c[u] = ci[k];
+    for (int u = 0; u < kK; ++u) {
+      const uint32_t k = (uint32_t)min(it.s + tid + u * kBlock, last);
+      T.a[u] = ldg(va, k);
+      T.c[u] = ldg(ci, k);
     }
   }
-  __builtin_amdgcn_sched_barrier(0);
-  const int r0 = rp0 - it.s;
-  const int r1 = r0 + ((rp1 - rp0) & -(int)has_row);  // empty range without a row
-  if (n > 0) {
+}
+
+// Stage 2: the gathers of the NA vectors at the tile's columns.
+template <typename V, int NA, typename Pre>
+__device__ __forceinline__ void stream_gather(const WorkItem& it, const StreamTile<V, Pre>& T,
+                                              const gptr<const V>* vec, const double* div,
+                                              V (&x)[NA][kK]) {
+  if (it.e > it.s) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      V x[K];
 #pragma unroll
-      for (int u = 0; u < K; ++u) x[u] = vec_at(vec, div, q, c[u]);
-      // slots past the tile's end get products of the repeated last
-      // nonzero; no row reads them
+      for (int u = 0; u < kK; ++u) x[q][u] = vec_at(vec, div, q, T.c[u]);
+    }
+  }
+}
+
+// Stage 3: products into LDS (slots past the tile's end hold products of
+// the repeated last nonzero; no row reads them), each row reduced by its
+// group of lanes, and finish(row, sums[NA], pre) in the group's first lane.
+// Called by the whole workgroup.
+template <typename V, int NA, typename Pre, typename Finish>
+__device__ __forceinline__ void stream_finish(const WorkItem& it, StreamTile<V, Pre>& T,
+                                              const V (&x)[NA][kK], Finish&& finish,
+                                              SpmvShared<V, NA>& sh) {
+  const int tid = threadIdx.x;
+  const int L = it.lanes;  // a power of two
+  const int lane = tid & (L - 1);
+  const int r = it.rb + (tid >> __builtin_ctz(L));
+  const bool has_row = r < it.re;
+  const int r0 = T.rp0 - it.s;
+  const int r1 = r0 + ((T.rp1 - T.rp0) & -(int)has_row);  // empty range without a row
+  if (it.e > it.s) {
 #pragma unroll
-      for (int u = 0; u < K; ++u) sh.prod[q][tid + u * kBlock] = Num<V>::mul(a[u], x[u]);
+    for (int q = 0; q < NA; ++q) {
+#pragma unroll
+      for (int u = 0; u < kK; ++u) sh.prod[q][tid + u * kBlock] = Num<V>::mul(T.a[u], x[q][u]);
     }
   }
   lds_barrier();
@@ -427,10 +413,94 @@ __device__ __forceinline__ void spmv_tile(const WorkItem& it, gptr<const int32_t
       V out[NA];
 #pragma unroll
       for (int q = 0; q < NA; ++q) out[q] = acc[q].value();
-      finish(r, out, pre);
+      finish(r, out, T.pre);
     }
   }
   lds_barrier();
+}
+
+// A row longer than kTileCap (lanes == 0): every thread takes every
+// kBlock-th nonzero, U at a time so their loads overlap; waves combine
+// through LDS; thread 0 finishes the row.
+template <typename V, int NA, typename Load, typename Finish>
+__device__ __forceinline__ void long_row_tile(const WorkItem& it, gptr<const int32_t> ci,
+                                              gptr<const V> va, const gptr<const V>* vec,
+                                              const double* div, Load&& load, Finish&& finish,
+                                              SpmvShared<V, NA>& sh) {
+  const int tid = threadIdx.x;
+  const int last = it.e - 1;
+  const int r = it.rb;
+  auto pre = load(r);
+  Acc<V> acc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q].zero();
+  constexpr int U = 4;
+  for (int k = it.s + tid; k < it.e; k += U * kBlock) {
+    V a[U];
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t kk = (uint32_t)min(k + u * kBlock, last);
+      a[u] = ldg(va, kk);
+      c[u] = ldg(ci, kk);
+    }
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      V x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = vec_at(vec, div, q, c[u]);
+      // a select, not a branch: a branch would let the compiler sink the
+      // loads into it, one wait each
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        acc[q].add(Num<V>::mask(k + u * kBlock < it.e, Num<V>::mul(a[u], x[u])));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q].merge_xor(off);
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) sh.wave[tid >> 6][q] = acc[q];
+  }
+  lds_barrier();
+  if (tid == 0) {
+    V out[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      Acc<V> t = sh.wave[0][q];
+      t.merge(sh.wave[1][q]);
+      t.merge(sh.wave[2][q]);
+      t.merge(sh.wave[3][q]);
+      out[q] = t.value();
+    }
+    finish(r, out, pre);
+  }
+  lds_barrier();
+}
+
+// One tile on its own (no overlap with neighbours): sparse dot products of
+// its rows with NA vectors and the row epilogues. Called by the whole
+// workgroup (every branch below is uniform over it).
+template <typename V, int NA, typename Load, typename Finish>
+__device__ __forceinline__ void spmv_tile(const WorkItem& it, gptr<const int32_t> rp,
+                                          gptr<const int32_t> ci, gptr<const V> va,
+                                          const gptr<const V>* vec, const double* div,
+                                          Load&& load, Finish&& finish, SpmvShared<V, NA>& sh) {
+  if (it.re <= it.rb) return;  // the placeholder tile of a side without rows
+  if (it.lanes == 0) {
+    long_row_tile<V, NA>(it, ci, va, vec, div, load, finish, sh);
+    return;
+  }
+  using Pre = decltype(load(0));
+  StreamTile<V, Pre> T;
+  stream_load<V, Pre>(it, rp, ci, va, load, T);
+  __builtin_amdgcn_sched_barrier(0);
+  V x[NA][kK];
+  stream_gather<V, NA, Pre>(it, T, vec, div, x);
+  stream_finish<V, NA, Pre>(it, T, x, finish, sh);
 }
 
 template <typename V>
@@ -672,18 +742,23 @@ __device__ __forceinline__ SideChunks side_chunks(const Counts* counts, bool tsi
   return SideChunks{uni(tside ? c->grid_t : c->grid_a), uni(tside ? c->chunk_t : c->chunk_a)};
 }
 
-// Drives a workgroup over its chunk of a side's work list. When the LP
-// changes, begin(item) loads the LP's pointers and scalars into registers
-// and returns whether the LP takes part; tile(item) processes a tile of a
-// running LP; end(item, run) closes the LP's part of the chunk.
-template <typename Begin, typename TileFn, typename End>
-__device__ __forceinline__ void run_chunk(const WorkItem* __restrict__ work, SideChunks sc,
-                                          WorkItem* s_items, Begin&& begin, TileFn&& tile,
-                                          End&& end) {
-  const int ci = chunk_index(sc.grid);
-  if (ci < 0) return;
+// Drives a workgroup over its chunk of a side's work list, running the
+// sparse product of each tile with the row epilogues load / finish. When
+// the LP changes, begin(item) loads the LP's context (the pointers rp, ci,
+// va, vec refer to variables it sets) and returns whether the LP takes
+// part; end(item, run) closes the LP's part of the chunk.
+template <typename V, int NA, typename Begin, typename Load, typename Finish, typename End>
+__device__ __forceinline__ void run_chunk_spmv(const WorkItem* __restrict__ work, SideChunks sc,
+                                               WorkItem* s_items, const gptr<const int32_t>& rp,
+                                               const gptr<const int32_t>& ci,
+                                               const gptr<const V>& va, const gptr<const V>* vec,
+                                               const double* div, Begin&& begin, Load&& load,
+                                               Finish&& finish, End&& end,
+                                               SpmvShared<V, NA>& sh) {
+  const int chi = chunk_index(sc.grid);
+  if (chi < 0) return;
   const int chunk = sc.chunk;
-  const int w0 = ci * chunk;
+  const int w0 = chi * chunk;
   int lp = -1;
   bool run = false;
   for (int k0 = 0; k0 < chunk; k0 += kItemWin) {
@@ -696,14 +771,13 @@ __device__ __forceinline__ void run_chunk(const WorkItem* __restrict__ work, Sid
     __syncthreads();
     for (int k = 0; k < cnt; ++k) {
       const WorkItem it = uniform_item(s_items[k]);
-      if (it.lp >= 0) {
-        if (it.lp != lp) {
-          lp = it.lp;
-          run = begin(it);
-        }
-        if (run) tile(it);
-        if (it.last) end(it, run);
+      if (it.lp < 0) continue;
+      if (it.lp != lp) {
+        lp = it.lp;
+        run = begin(it);
       }
+      if (run) spmv_tile<V, NA>(it, rp, ci, va, vec, div, load, finish, sh);
+      if (it.last) end(it, run);
     }
     lds_barrier();  // the window is rewritten next
   }
@@ -794,8 +868,8 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
   bool learn = false, upd = false;
   double lscale = 1.0, hnorm = 0.0;
   __shared__ WorkItem s_items[kItemWin];
-  run_chunk(
-      cfg.work_t, side_chunks(cfg.counts, true), s_items,
+  run_chunk_spmv<V, 1>(
+      cfg.work_t, side_chunks(cfg.counts, true), s_items, rp, ci, va, vecs, nodiv,
       [&](const WorkItem& it) {
         c = it.ctl;
         // the restart / final copy of the evaluation step ran before this
@@ -804,17 +878,21 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
           c->restart_pending = 0;
           c->finalize_avg = 0;
         }
-        if (!force && !attempt_guard(c)) return false;
+        // every value read here is the same in all threads: moved to scalar
+        // registers (uni) so the branches on them are uniform and the
+        // pointers stay out of vector registers
+        if (!uni((int)(force || attempt_guard(c)))) return false;
         lp = &cfg.lps[it.lp];
-        const int cur = c->cur, nxt = cur ^ 1;
-        const double eta = c->eta, om = c->omega;
+        const int cur = uni(c->cur), nxt = cur ^ 1;
+        const double eta = uni(c->eta), om = uni(c->omega);
         tau = (V)(eta / om);
         etav = (V)eta;
         // a forced (timing) launch writes only the candidate buffers
-        learn = !force && c->learn_now != 0;
+        learn = uni((int)(!force && c->learn_now != 0)) != 0;
         lscale = 1.0;
-        upd = !force && c->learn_pending && learn_side(c, lp->prm, true, &lscale);
-        hnorm = c->hp_norm;
+        upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, true, &lscale))) != 0;
+        lscale = uni(lscale);
+        hnorm = uni(c->hp_norm);
         cc = gp(static_cast<const V*>(lp->c));
         lo = gp(static_cast<const V*>(lp->l));
         hi = gp(static_cast<const V*>(lp->u));
@@ -838,19 +916,16 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
         tau = uni(tau), etav = uni(etav);
         return true;
       },
-      [&](const WorkItem& it) {
-        spmv_tile<V, 1>(
-            it, rp, ci, va, vecs, nodiv,
             [&](int j) {
               PrimalPre<V> q;
-              q.c = cc[j];
-              q.x = x[j];
-              q.T = T[j];
-              q.l = lo[j];
-              q.u = hi[j];
-              q.xs = xs[j];
-              q.H = Hsrc[j];
-              q.G = Gsrc[j];
+              q.c = ldg(cc, (uint32_t)j);
+              q.x = ldg(x, (uint32_t)j);
+              q.T = ldg(T, (uint32_t)j);
+              q.l = ldg(lo, (uint32_t)j);
+              q.u = ldg(hi, (uint32_t)j);
+              q.xs = ldg(xs, (uint32_t)j);
+              q.H = ldg(Hsrc, (uint32_t)j);
+              q.G = ldg(Gsrc, (uint32_t)j);
               return q;
             },
             [&](int j, V (&acc)[1], PrimalPre<V>& q) {
@@ -858,30 +933,29 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
               if (upd) {
                 V h = q.H;
                 Tj = learn_elem<V>(Tj, h, q.G, lscale, lp->prm, hnorm);
-                T[j] = Tj;
-                Hp[j] = h;
+                stg(T, (uint32_t)j, Tj);
+                stg(Hp, (uint32_t)j, h);
               }
               const V g = q.c - acc[0];
               const V xh = q.x - (tau * Tj) * g;
               const V xv = clampv(xh, q.l, q.u);
-              xn[j] = xv;
-              xsn[j] = q.xs + etav * xv;
+              stg(xn, (uint32_t)j, xv);
+              stg(xsn, (uint32_t)j, q.xs + etav * xv);
               const double dx = (double)xv - (double)q.x;
               dd_add_prod(p[0], dx, dx);
               dd_add_prod(p[1], (double)g, (double)g);
               if (learn) {
                 const bool ind = (xh >= q.l) && (xh <= q.u);
                 const V gp_ = ind ? -((tau * g) * g) : V(0);
-                Gp[j] = gp_;
+                stg(Gp, (uint32_t)j, gp_);
                 dd_add_prod(p[2], (double)gp_, (double)gp_);
               }
             },
-            sh);
-      },
       [&](const WorkItem& it, bool run) {
         if (run) flush_partials<3>(p, s_red, lp->part_t, lp->ntiles_t, it.slot);
         else dd_reset(p);
-      });
+      },
+      sh);
 }
 
 template <typename V>
@@ -910,20 +984,22 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
   bool learn = false, upd = false;
   double lscale = 1.0, hnorm = 0.0;
   __shared__ WorkItem s_items[kItemWin];
-  run_chunk(
-      cfg.work_a, side_chunks(cfg.counts, false), s_items,
+  run_chunk_spmv<V, 1>(
+      cfg.work_a, side_chunks(cfg.counts, false), s_items, rp, ci, va, vecs, nodiv,
       [&](const WorkItem& it) {
         c = it.ctl;
-        if (!force && !attempt_guard(c)) return false;
+        // as in k_primal: uniform values in scalar registers
+        if (!uni((int)(force || attempt_guard(c)))) return false;
         lp = &cfg.lps[it.lp];
-        const int cur = c->cur, nxt = cur ^ 1;
-        const double eta = c->eta, om = c->omega;
+        const int cur = uni(c->cur), nxt = cur ^ 1;
+        const double eta = uni(c->eta), om = uni(c->omega);
         sig = (V)(eta * om);
         etav = (V)eta;
-        learn = !force && c->learn_now != 0;  // as in k_primal
+        learn = uni((int)(!force && c->learn_now != 0)) != 0;
         lscale = 1.0;
-        upd = !force && c->learn_pending && learn_side(c, lp->prm, false, &lscale);
-        hnorm = c->hd_norm;
+        upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, false, &lscale))) != 0;
+        lscale = uni(lscale);
+        hnorm = uni(c->hd_norm);
         b = gp(static_cast<const V*>(lp->b));
         S = gp(static_cast<V*>(lp->S));
         Hd = gp(static_cast<V*>(lp->Hd));
@@ -948,19 +1024,16 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
         sig = uni(sig), etav = uni(etav);
         return true;
       },
-      [&](const WorkItem& it) {
-        spmv_tile<V, 1>(
-            it, rp, ci, va, vecs, nodiv,
             [&](int i) {
               DualPre<V> q;
-              q.ax = Ax[i];
-              q.b = b[i];
-              q.y = y[i];
-              q.ys = ys[i];
-              q.S = S[i];
-              q.ineq = sense[i];
-              q.H = Hsrc[i];
-              q.G = Gsrc[i];
+              q.ax = ldg(Ax, (uint32_t)i);
+              q.b = ldg(b, (uint32_t)i);
+              q.y = ldg(y, (uint32_t)i);
+              q.ys = ldg(ys, (uint32_t)i);
+              q.S = ldg(S, (uint32_t)i);
+              q.ineq = ldg(sense, (uint32_t)i);
+              q.H = ldg(Hsrc, (uint32_t)i);
+              q.G = ldg(Gsrc, (uint32_t)i);
               return q;
             },
             [&](int i, V (&acc)[1], DualPre<V>& q) {
@@ -968,8 +1041,8 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
               if (upd) {
                 V h = q.H;
                 Si = learn_elem<V>(Si, h, q.G, lscale, lp->prm, hnorm);
-                S[i] = Si;
-                Hd[i] = h;
+                stg(S, (uint32_t)i, Si);
+                stg(Hd, (uint32_t)i, h);
               }
               const V axn = acc[0];
               const V axbar = V(2) * axn - q.ax;
@@ -977,9 +1050,9 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
               const V yh = q.y + (sig * Si) * rt;
               const bool ineq = q.ineq != 0;
               const V yv = (ineq && yh < V(0)) ? V(0) : yh;
-              yn[i] = yv;
-              Axn[i] = axn;
-              ysn[i] = q.ys + etav * yv;
+              stg(yn, (uint32_t)i, yv);
+              stg(Axn, (uint32_t)i, axn);
+              stg(ysn, (uint32_t)i, q.ys + etav * yv);
               const double dy = (double)yv - (double)q.y;
               dd_add_prod(p[0], dy, dy);
               dd_add_prod(p[1], dy, (double)axn - (double)q.ax);
@@ -988,16 +1061,15 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
               if (learn) {
                 const bool ind = !ineq || yh >= V(0);
                 const V gd = ind ? -((sig * r) * rt) : V(0);
-                Gd[i] = gd;
+                stg(Gd, (uint32_t)i, gd);
                 dd_add_prod(p[3], (double)gd, (double)gd);
               }
             },
-            sh);
-      },
       [&](const WorkItem& it, bool run) {
         if (run) flush_partials<4>(p, s_red, lp->part_a, lp->ntiles_a, it.slot);
         else dd_reset(p);
-      });
+      },
+      sh);
 }
 
 // One workgroup per LP: the step decision of the attempt that just ran.

@@ -200,3 +200,44 @@ def test_fp32_mode_error_reported(P):
     err_obj = abs(r.primal_obj - ref.primal_obj) / abs(ref.primal_obj)
     _say(f"  fp32 objective rel err {err_obj:.3e}, y rel err {rel(y, ref.y):.3e}")
     assert err_obj <= 1e-3
+
+
+# FP32 trace tolerance. One FP32 step perturbs the iterate by about
+# (row length) x 2^-24 relative to the row sums; after rescaling the rows
+# are O(1), so 30 steps stay below ~30 x 1e-6. 2e-4 leaves a 5x margin.
+# The step size is a ratio of differences of iterates (|dx|^2 over
+# dy . A dx), so the iterates' rounding reaches it amplified by
+# |x| / |dx| (~10-100 here): it gets 2e-3.
+FP32_TRACE_TOL = 2e-4
+FP32_ETA_TOL = 2e-3
+
+
+@pytest.mark.parametrize("name,scale,tile,wg", [
+    ("cfg1", 0.02, 256, 8),    # many stream tiles per workgroup: tiles overlap
+    ("cfg1", 0.1, 512, 16),    # plus rows longer than a tile
+    ("cfg0", 1.0, 64, 4),      # four lanes per row, ragged tails
+])
+def test_fp32_trace_close_to_oracle(P, name, scale, tile, wg):
+    """FP32 iterates stay within FP32 rounding of the FP64 oracle's."""
+    lp = config_lp(name, scale=scale)
+    op = default_params(max_iter=100000, lr=1e-3, phi=5)
+    K = 30
+    ref = oracle.solve(lp, op, trace=K, stop_k=K)
+    tr = {e.k: e for e in ref.trace}
+    _say(f"[fp32-trace] {name} x{scale} tile {tile} wg {wg}: m={lp.m} n={lp.n} nnz={lp.nnz}")
+    worst = 0.0
+    with P.Session(lp, lib_params(P, op, precision=P.OPDHG_FP32, tile_nnz=tile,
+                                  workgroups=wg)) as s:
+        for k in (1, 2, 5, 10, 20, 30):
+            if k not in tr:
+                break
+            s.run(k)
+            x, y, T, S, st = s.state()
+            e = tr[k]
+            assert st.k == k and st.attempts == e.attempts, (k, st.attempts, e.attempts)
+            errs = {"x": rel(x, e.x), "y": rel(y, e.y), "T": rel(T, e.T), "S": rel(S, e.S),
+                    "eta": abs(st.eta - e.eta) / abs(e.eta)}
+            worst = max(worst, max(v for nm, v in errs.items() if nm != "eta"))
+            for nm, v in errs.items():
+                assert v <= (FP32_ETA_TOL if nm == "eta" else FP32_TRACE_TOL), (k, nm, v)
+    _say(f"  worst FP32 relative deviation {worst:.2e}")
