@@ -217,6 +217,11 @@ def section_batch(P, args):
     p64 = P.opdhg_default_params(precision=P.OPDHG_FP64, tol=1e-4, max_iter=200000, lr=0.0,
                                  time_limit_s=600)
     import torch
+    t0 = time.perf_counter()
+    tun, p32 = P.opdhg_autotune(lps, p32, replays=2)
+    log(f"[bench] batch: autotuned tile {tun.tile_nnz}, workgroups {tun.workgroups}: "
+        f"{tun.attempts_per_s:.0f} attempts/s (automatic tiling {tun.default_attempts_per_s:.0f}); "
+        f"{time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res32 = P.opdhg_solve_batch(lps, p32)
@@ -243,6 +248,9 @@ def section_batch(P, args):
         "lps": len(lps), "nnz_total": nnz, "dtype": "f32",
         "solves_per_s": opt32 / wall32, "solves_per_s_loop": opt32 / loop32,
         "optimal": opt32, "wall_s": wall32, "loop_s": loop32,
+        "autotune": {"tile_nnz": tun.tile_nnz, "lanes": tun.lanes, "workgroups": tun.workgroups,
+                     "candidates": tun.candidates, "attempts_per_s": tun.attempts_per_s,
+                     "automatic_tiling_attempts_per_s": tun.default_attempts_per_s},
         "fp32_rel_kkt_max": max(kkt32),
         "baseline": {
             "kind": "plain FP64 PDHG (lr 0), one LP at a time, same GPU",

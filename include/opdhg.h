@@ -196,6 +196,31 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p,
                       void* d_workspace, size_t workspace_bytes, void* hip_stream,
                       double* const* x_out, double* const* y_out, opdhg_result* res);
 
+/* ---- autotuning of the sparse-product tiling ----
+ * Not part of the method: a performance helper. The LPs are prepared once;
+ * each candidate tiling (tile size in nonzeros x workgroups per launch,
+ * lanes per row picked per tile) is uploaded, captured and timed over
+ * `replays` launch sequences (64 step attempts each) with the LPs kept
+ * running. The fastest candidate by step attempts per second, summed over
+ * the set, is returned; pass its fields as tile_nnz, lanes and workgroups
+ * of opdhg_params. In FP64 every tiling gives identical results; in FP32
+ * results move only by rounding. The workspace is overwritten. */
+typedef struct opdhg_tuning {
+  int32_t tile_nnz;       /* chosen tile size (nonzeros) */
+  int32_t lanes;          /* chosen lanes per row (0: per tile) */
+  int32_t workgroups;     /* chosen workgroups per launch */
+  int32_t candidates;     /* candidates timed */
+  double attempts_per_s;  /* measured for the chosen tiling */
+  double default_attempts_per_s; /* measured for the automatic tiling */
+} opdhg_tuning;
+
+/* Workspace bytes opdhg_autotune needs for these LPs (the largest
+ * candidate's). Host only. */
+int opdhg_autotune_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_params* p,
+                                   size_t* bytes);
+int opdhg_autotune(int count, const opdhg_lp* lps, const opdhg_params* p, void* d_workspace,
+                   size_t workspace_bytes, void* hip_stream, int replays, opdhg_tuning* out);
+
 /* ---- sessions: step an LP under host control (tracing, checkpoints) ---- */
 
 int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,

@@ -9,6 +9,7 @@ from .capi import (  # noqa: F401
     Server,
     Session,
     load,
+    opdhg_autotune,
     opdhg_batch_workspace_bytes,
     opdhg_build_info,
     opdhg_default_params,

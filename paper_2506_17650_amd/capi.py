@@ -102,6 +102,13 @@ class opdhg_server_stats(ctypes.Structure):
     ]
 
 
+class opdhg_tuning(ctypes.Structure):
+    _fields_ = [
+        ("tile_nnz", c_i32), ("lanes", c_i32), ("workgroups", c_i32), ("candidates", c_i32),
+        ("attempts_per_s", c_dbl), ("default_attempts_per_s", c_dbl),
+    ]
+
+
 # exported symbols and their signatures (restype, argtypes)
 SIGNATURES = {
     "opdhg_default_params": (None, [_p(opdhg_params)]),
@@ -114,6 +121,9 @@ SIGNATURES = {
     "opdhg_solve_batch": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                                   ctypes.c_void_p, _p(_p(c_dbl)), _p(_p(c_dbl)),
                                   _p(opdhg_result)]),
+    "opdhg_autotune_workspace_bytes": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), _p(c_sz)]),
+    "opdhg_autotune": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
+                               ctypes.c_void_p, c_i32, _p(opdhg_tuning)]),
     "opdhg_session_create": (c_i32, [_p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                                      ctypes.c_void_p, _p(ctypes.c_void_p)]),
     "opdhg_session_run": (c_i32, [ctypes.c_void_p, c_i64]),
@@ -340,6 +350,28 @@ def opdhg_solve_batch(lps: Sequence, params: Optional[opdhg_params] = None, work
     _check(load().opdhg_solve_batch(count, structs, ctypes.byref(params), ctypes.c_void_p(ptr),
                                     size, ctypes.c_void_p(_stream_handle(stream)), xp, yp, res))
     return [(xs[i], ys[i][: arrs[i].m], res[i]) for i in range(count)]
+
+
+def opdhg_autotune(lps: Sequence, params: Optional[opdhg_params] = None, replays: int = 3,
+                   stream=None):
+    """Time the candidate tilings on these LPs: (opdhg_tuning, tuned params)."""
+    import copy
+    params = params or opdhg_default_params()
+    arrs = [_LPArrays(lp) for lp in lps]
+    count = len(arrs)
+    structs = (opdhg_lp * count)(*[a.struct for a in arrs])
+    need = c_sz(0)
+    _check(load().opdhg_autotune_workspace_bytes(count, structs, ctypes.byref(params),
+                                                 ctypes.byref(need)))
+    ws = device_workspace(int(need.value))
+    ptr, size = _ws_ptr(ws)
+    out = opdhg_tuning()
+    _check(load().opdhg_autotune(count, structs, ctypes.byref(params), ctypes.c_void_p(ptr),
+                                 size, ctypes.c_void_p(_stream_handle(stream)), int(replays),
+                                 ctypes.byref(out)))
+    tuned = copy.copy(params)
+    tuned.tile_nnz, tuned.lanes, tuned.workgroups = out.tile_nnz, out.lanes, out.workgroups
+    return out, tuned
 
 
 class Session:

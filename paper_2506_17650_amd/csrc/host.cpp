@@ -416,6 +416,7 @@ SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int6
   L.part_a = take(sizeof(double) * kPartStride * ntiles_a);
   L.part_t = take(sizeof(double) * kPartStride * ntiles_t);
   L.pow_tab = take(sizeof(double) * 2 * kPowTab);
+  L.pow_ring = take(sizeof(double) * 2 * kPowRing);
   L.rp_a = take(4 * (m + 1));
   L.ci_a = take(4 * nnz);
   L.va_a = take(V * nnz);
@@ -462,6 +463,7 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
   d.part_t = reinterpret_cast<double*>(base + L.part_t);
   d.part_a = reinterpret_cast<double*>(base + L.part_a);
   d.pow_tab = reinterpret_cast<const double*>(base + L.pow_tab);
+  d.pow_ring = reinterpret_cast<double*>(base + L.pow_ring);
   d.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   d.prm = reinterpret_cast<const DevParams*>(base + L.prm);
   return d;

@@ -21,7 +21,7 @@
 // signal each other inside a launch; kernel boundaries carry every result
 // to the next step.
 //
-// Per attempt (Algorithm 1, line 1, eq. (6)):
+// Per attempt (the PDHG step of Algorithm 1, eq. (6)):
 //   k_primal  CSR(A^T) SpMV of y, g = c - A^T y, x' = proj_[l,u](x - (eta/w) T g),
 //             running sum of x, primal online gradient on update iterations
 //             (eq. (7)), partials |x'-x|^2, |g|^2, |G^p|^2
@@ -30,7 +30,7 @@
 //             |y'-y|^2, (y'-y).(A x'-A x), |b-Ax|^2, |G^d|^2
 //   k_decide  adaptive step rule: accept (flip buffers) or retry
 // The normalized online-gradient step with AdaGrad on T and Sigma
-// (Algorithm 1, lines 4-8) after an accepted update iteration is applied by
+// (the learner of Algorithm 1) after an accepted update iteration is applied by
 // the next attempt's k_primal (T) and k_dual (Sigma) to the rows they
 // visit, before those rows use the preconditioner.
 // Every eval_every accepted iterations:
@@ -235,6 +235,50 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   block_sum<NV>(v, s_red);
 #pragma unroll
   for (int q = 0; q < NV; ++q) out[q] = dd_value(v[q]);
+}
+
+// The same for two partial arrays at once (NA quantities over ca slots of
+// pa, then NB over cb slots of pb): one pass, so the loads of both arrays
+// are in flight together.
+template <int NA, int NB>
+__device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, const double* pb,
+                                              int sb, int cb, double (&out)[NA + NB],
+                                              DD* s_red) {
+  constexpr int B = 4;
+  DD v[NA + NB];
+#pragma unroll
+  for (int q = 0; q < NA + NB; ++q) v[q] = dd_zero();
+  const gptr<const double> ga = gp(pa), gb = gp(pb);
+  const int count = ca > cb ? ca : cb;
+  for (int base = threadIdx.x; base < count; base += kBlock * B) {
+    double h[B][NA + NB], l[B][NA + NB];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int t = base + k * kBlock;
+      const bool oka = t < ca, okb = t < cb;
+      const int ta = oka ? t : 0, tb = okb ? t : 0;  // slot 0 exists on both sides
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const double hv = ga[(size_t)(2 * q) * sa + ta], lv = ga[(size_t)(2 * q + 1) * sa + ta];
+        h[k][q] = oka ? hv : 0.0;
+        l[k][q] = oka ? lv : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const double hv = gb[(size_t)(2 * q) * sb + tb], lv = gb[(size_t)(2 * q + 1) * sb + tb];
+        h[k][NA + q] = okb ? hv : 0.0;
+        l[k][NA + q] = okb ? lv : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+#pragma unroll
+      for (int q = 0; q < NA + NB; ++q) v[q] = dd_merge(v[q], DD{h[k][q], l[k][q]});
+    }
+  }
+  block_sum<NA + NB>(v, s_red);
+#pragma unroll
+  for (int q = 0; q < NA + NB; ++q) out[q] = dd_value(v[q]);
 }
 
 // ---- numbers of the sparse products: exact products and double-double
@@ -539,63 +583,69 @@ __device__ __forceinline__ void flush_partials(DD (&p)[NV], DD* s_red, double* p
 // ---------------------------------------------------------------------------
 
 // Factor (j+1)^-e of the step rule for attempt j: from the host-computed
-// table for the first kPowTab attempts, else computed here.
-__device__ __forceinline__ double step_factor(const double* tab, int which, int64_t j,
-                                              double e) {
-  if (j >= 1 && j <= kPowTab) return tab[which * kPowTab + (j - 1)];
-  return pow((double)(j + 1), -e);
+// table for the first kPowTab attempts, else from the ring the evaluation
+// kernel fills at the start of each launch sequence (which holds at most
+// kPowRing attempts, so the ring covers every attempt j of it).
+__device__ __forceinline__ double step_factor(const LpDev& lp, int64_t ring_base, int which,
+                                              int64_t j) {
+  if (j >= 1 && j <= kPowTab) return lp.pow_tab[which * kPowTab + (j - 1)];
+  int64_t r = j - ring_base - 1;
+  r = r < 0 ? 0 : (r >= kPowRing ? kPowRing - 1 : r);
+  return lp.pow_ring[which * kPowRing + r];
 }
 
 // Adaptive step rule (PDLP's): accept when eta <= eta_bar; the next step is
 // min((1 - (j+1)^-red) eta_bar, (1 + (j+1)^-gro) eta), j counting attempts.
-__device__ void decide_step(Ctl* c, const DevParams* p, const double* tab, const double* s) {
+// c is the LP's control block; s holds the attempt's sums
+// |x'-x|^2, |g|^2, |G^p|^2, |y'-y|^2, (y'-y).(A x'-A x), |b-Ax|^2, |G^d|^2.
+__device__ void decide_step(Ctl& c, const DevParams& p, const LpDev& lp, const double* s) {
   const double dx2 = s[0], g2 = s[1], gp2 = s[2];
   const double dy2 = s[3], inter = fabs(s[4]), r2 = s[5], gd2 = s[6];
-  c->attempts += 1;
+  c.attempts += 1;
   if (!(isfinite(dx2) && isfinite(dy2) && isfinite(inter))) {
-    c->status = kNumError;
+    c.status = kNumError;
     return;
   }
-  const double eta = c->eta, om = c->omega;
+  const double eta = c.eta, om = c.omega;
   const double movement = 0.5 * om * dx2 + 0.5 * dy2 / om;
   const double eta_bar = inter > 0.0 ? movement / inter : INFINITY;
-  const double first = (1.0 - step_factor(tab, 0, c->attempts, p->step_reduction)) * eta_bar;
-  const double second = (1.0 + step_factor(tab, 1, c->attempts, p->step_growth)) * eta;
+  const double first = (1.0 - step_factor(lp, c.ring_base, 0, c.attempts)) * eta_bar;
+  const double second = (1.0 + step_factor(lp, c.ring_base, 1, c.attempts)) * eta;
   const double eta_next = second < first ? second : first;
-  c->last_eta_bar = eta_bar;
+  c.last_eta_bar = eta_bar;
   // a pending learner update was applied by this attempt's kernels
-  c->learn_pending = 0;
+  c.learn_pending = 0;
   if (eta <= eta_bar) {
-    const bool learn = p->lr > 0.0 && (c->k % p->phi) == 0;
-    c->eta_acc = eta;
-    c->w += eta;
-    c->k += 1;
-    c->t += 1;
-    c->cur ^= 1;
-    c->eta = eta_next;
-    c->retries = 0;
+    const bool learn = p.lr > 0.0 && (c.k % p.phi) == 0;
+    c.eta_acc = eta;
+    c.w += eta;
+    c.k += 1;
+    c.t += 1;
+    c.cur ^= 1;
+    c.eta = eta_next;
+    c.retries = 0;
     if (learn) {
-      c->learn_pending = 1;
-      c->g2 = g2;
-      c->r2 = r2;
-      c->gp2 = gp2;
-      c->gd2 = gd2;
-      if (p->schedule == 1) {  // AdaGrad on the norm: H += |G / scale|^2 = |G|^2 / scale^2
-        const bool np = p->normalize && !(g2 > 0.0);
-        const bool nd = p->normalize && !(r2 > 0.0);
-        const double sp = p->normalize ? g2 : 1.0;
-        const double sd = p->normalize ? r2 : 1.0;
-        if (!np) c->hp_norm = c->hp_norm + gp2 / (sp * sp);
-        if (!nd) c->hd_norm = c->hd_norm + gd2 / (sd * sd);
+      c.learn_pending = 1;
+      c.g2 = g2;
+      c.r2 = r2;
+      c.gp2 = gp2;
+      c.gd2 = gd2;
+      if (p.schedule == 1) {  // AdaGrad on the norm: H += |G / scale|^2 = |G|^2 / scale^2
+        const bool np = p.normalize && !(g2 > 0.0);
+        const bool nd = p.normalize && !(r2 > 0.0);
+        const double sp = p.normalize ? g2 : 1.0;
+        const double sd = p.normalize ? r2 : 1.0;
+        if (!np) c.hp_norm = c.hp_norm + gp2 / (sp * sp);
+        if (!nd) c.hd_norm = c.hd_norm + gd2 / (sd * sd);
       }
     }
-    c->learn_now = (p->lr > 0.0 && (c->k % p->phi) == 0) ? 1 : 0;
-    if (c->k % p->eval_every == 0 || c->k >= p->max_iter) c->need_eval = 1;
+    c.learn_now = (p.lr > 0.0 && (c.k % p.phi) == 0) ? 1 : 0;
+    if (c.k % p.eval_every == 0 || c.k >= p.max_iter) c.need_eval = 1;
   } else {
-    c->eta = eta_next;
-    c->retries += 1;
-    if (c->retries > p->max_retries || !(eta_next > 0.0 && isfinite(eta_next)))
-      c->status = kNumError;
+    c.eta = eta_next;
+    c.retries += 1;
+    if (c.retries > p.max_retries || !(eta_next > 0.0 && isfinite(eta_next)))
+      c.status = kNumError;
   }
 }
 
@@ -788,7 +838,7 @@ __device__ __forceinline__ void run_chunk_spmv(const WorkItem* __restrict__ work
 // ---------------------------------------------------------------------------
 
 // One projected online-gradient step on one preconditioner entry
-// (Algorithm 1, lines 4-8): G / scale (scale = |g|^2 or |b - Ax|^2 when
+// (the learner of Algorithm 1): G / scale (scale = |g|^2 or |b - Ax|^2 when
 // normalizing, else 1), then AdaGrad (diagonal or on the norm) or a
 // constant rate, then the clamp at the floor.
 template <typename V>
@@ -1073,21 +1123,27 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
 }
 
 // One workgroup per LP: the step decision of the attempt that just ran.
+// The loads are arranged so that few wait for another: the LP's record
+// first (the LP table holds at least one record per workgroup of this
+// launch, so it is read before the LP count arrives), then the control
+// block and both partial arrays together.
 __global__ __launch_bounds__(kBlock) void k_decide(LaunchCfg cfg) {
-  __shared__ DD s_red[4 * 4];
-  const int nlps = cfg.counts->nlps;
-  for (int li = blockIdx.x; li < nlps; li += gridDim.x) {
-    const LpDev& lp = cfg.lps[li];
-    Ctl* c = lp.ctl;
-    if (!attempt_guard(c)) continue;
-    double st[3], sa[4];
-    sum_partials<3>(lp.part_t, lp.ntiles_t, lp.nslot_t, st, s_red);
-    sum_partials<4>(lp.part_a, lp.ntiles_a, lp.nslot_a, sa, s_red);
-    if (threadIdx.x == 0) {
-      const double sv[7] = {st[0], st[1], st[2], sa[0], sa[1], sa[2], sa[3]};
-      decide_step(c, lp.prm, lp.pow_tab, sv);
-    }
+  __shared__ DD s_red[4 * 7];
+  int li = blockIdx.x;
+  LpDev lp = cfg.lps[li];
+  const int nlps = uni(gp(cfg.counts)->nlps);
+  while (li < nlps) {
+    Ctl* cp = lp.ctl;
+    const int status = uni(cp->status), need = uni(cp->need_eval);
+    const int64_t k = uni(cp->k), k_limit = uni(cp->k_limit);
+    double sv[7];
+    sum_partials2<3, 4>(lp.part_t, lp.ntiles_t, lp.nslot_t, lp.part_a, lp.ntiles_a, lp.nslot_a,
+                        sv, s_red);
+    if (status == kRunning && need == 0 && k < k_limit && threadIdx.x == 0)
+      decide_step(*cp, *lp.prm, lp, sv);
     __syncthreads();
+    li += gridDim.x;
+    if (li < nlps) lp = cfg.lps[li];
   }
 }
 
@@ -1258,6 +1314,20 @@ __global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg) {
   for (int li = blockIdx.x; li < nlps; li += gridDim.x) {
     const LpDev& lp = cfg.lps[li];
     Ctl* c = lp.ctl;
+    if (c->status != kRunning) continue;
+    // step-rule factors for the attempts of this launch sequence that the
+    // host table does not cover (the step decision, fused into the dual
+    // kernel, reads them instead of computing powers there)
+    const int64_t a0 = c->attempts;
+    if (a0 + kPowRing > kPowTab) {
+      const DevParams* p = lp.prm;
+      for (int t = threadIdx.x; t < kPowRing; t += kBlock) {
+        const double j1 = (double)(a0 + 1 + t) + 1.0;
+        lp.pow_ring[t] = pow(j1, -p->step_reduction);
+        lp.pow_ring[kPowRing + t] = pow(j1, -p->step_growth);
+      }
+      if (threadIdx.x == 0) c->ring_base = a0;
+    }
     if (!eval_guard(c)) continue;
     double st[2 * kEvT], sa[2 * kEvA];
     sum_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, lp.nslot_t, st, s_red);

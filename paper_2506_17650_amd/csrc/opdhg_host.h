@@ -48,6 +48,7 @@ struct SlotLayout {
   static constexpr int kNVecN = 11;  // c l u T Hp Gp x0 x1 xs0 xs1 xa
   static constexpr int kNVecM = 12;  // b S Hd Gd y0 y1 ys0 ys1 ya Ax0 Ax1 Axa
   size_t ctl = 0, prm = 0, tiles_a = 0, tiles_t = 0, part_a = 0, part_t = 0, pow_tab = 0;
+  size_t pow_ring = 0;
   size_t rp_a = 0, ci_a = 0, va_a = 0, rp_t = 0, ci_t = 0, va_t = 0;
   size_t vn[kNVecN] = {};
   size_t vm[kNVecM] = {};

@@ -19,6 +19,7 @@ namespace opdhg {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kPartStride = 32;    // doubles of reduction partials per tile (16 double-doubles)
 constexpr int kPowTab = 8192;      // host-computed step-rule factors for the first attempts
+constexpr int kPowRing = 64;       // factors for the attempts of one launch sequence beyond
 constexpr int kGridCap = 2048;     // default workgroups of a launch (chunks of the work list)
 constexpr int kMaxGrid = 65536;    // largest workgroup count a caller may ask for
 constexpr int kTileCap = 1024;     // nonzeros of a stream tile (staged in LDS)
@@ -74,6 +75,7 @@ struct Ctl {
   int64_t restarts;
   int64_t retries;   // rejections of the current iteration
   int64_t k_limit;   // attempts pause when k reaches it (host-controlled)
+  int64_t ring_base; // the step-rule factor ring holds attempts ring_base+1 .. +kPowRing
   int32_t status;
   int32_t cur;           // current buffer (0 or 1)
   int32_t need_eval;     // an evaluation is due before the next attempt
@@ -137,6 +139,7 @@ struct LpDev {
   double* part_t;       // ntiles_t * kPartStride
   double* part_a;       // ntiles_a * kPartStride
   const double* pow_tab;  // 2 * kPowTab: (j+1)^-reduction, then (j+1)^-growth, j = 1..kPowTab
+  double* pow_ring;       // 2 * kPowRing: the same factors for j = ring_base+1 .. +kPowRing
   Ctl* ctl;
   const DevParams* prm;
 };

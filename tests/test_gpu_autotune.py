@@ -1,0 +1,54 @@
+"""Autotuner of the sparse-product tiling (opdhg_autotune through the C-ABI).
+
+The tuner must time every candidate and return one of them; in FP64 the
+chosen tiling must give the same results as the automatic one bit for bit
+(every sum is exact), and in FP32 results within FP32 rounding.
+"""
+
+import numpy as np
+import pytest
+
+from lpgen import config_lp
+
+pytestmark = pytest.mark.gpu
+
+CANDIDATES = {(t, w) for t in (256, 512, 1024) for w in (256, 512, 1024, 2048)}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_17650_amd as P
+    P.load()
+    return P
+
+
+def test_autotune_fp64_results_unchanged(P):
+    lps = [config_lp("cfg3", index=i, scale=0.05) for i in range(6)] + [config_lp("cfg0", seed=4)]
+    p = P.opdhg_default_params(max_iter=5000, lr=1e-2)
+    tun, tuned = P.opdhg_autotune(lps, p, replays=2)
+    print(f"tuned tile {tun.tile_nnz} workgroups {tun.workgroups}: "
+          f"{tun.attempts_per_s:.0f} vs {tun.default_attempts_per_s:.0f} attempts/s", flush=True)
+    assert tun.candidates == len(CANDIDATES)
+    assert (tun.tile_nnz, tun.workgroups) in CANDIDATES and tun.lanes == 0
+    assert tun.attempts_per_s > 0 and tun.default_attempts_per_s > 0
+    assert tun.attempts_per_s >= tun.default_attempts_per_s
+    a = P.opdhg_solve_batch(lps, p)
+    b = P.opdhg_solve_batch(lps, tuned)
+    for (xa, ya, ra), (xb, yb, rb) in zip(a, b):
+        assert ra.status == rb.status and ra.iterations == rb.iterations
+        assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+
+
+def test_autotune_fp32_results_close(P):
+    lps = [config_lp("cfg3", index=i, scale=0.05) for i in range(4)]
+    p = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=20000, lr=1e-3)
+    tun, tuned = P.opdhg_autotune(lps, p, replays=2)
+    a = P.opdhg_solve_batch(lps, p)
+    b = P.opdhg_solve_batch(lps, tuned)
+    for (_, _, ra), (_, _, rb) in zip(a, b):
+        assert ra.status == rb.status == P.capi.OPDHG_STATUS_OPTIMAL
+        # both are 1e-4-optimal: objectives agree to the tolerance scale
+        assert abs(ra.primal_obj - rb.primal_obj) <= 1e-3 * (1.0 + abs(rb.primal_obj))
