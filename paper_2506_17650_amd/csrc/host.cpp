@@ -149,8 +149,117 @@ static double dd_norm(const double* v, int64_t n) {
 // (Section 2 of the paper), square-root split between rows and columns
 // ---------------------------------------------------------------------------
 
-void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,
-                  std::vector<double>& dr, std::vector<double>& dc) {
+// ---- host parallelism for the preparation (results do not depend on it) ----
+
+// Runs f(begin, end) over [0, rows) cut into pieces of about equal nonzero
+// counts (ptr: rows + 1 offsets), one host thread per piece.
+template <typename F>
+static void parallel_rows(const int64_t* ptr, int64_t rows, F&& f) {
+  const int64_t total = rows ? ptr[rows] : 0;
+  const int nth = (int)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)std::min(host_threads(), 16), rows, total / 65536 + 1}));
+  if (nth == 1) {
+    f((int64_t)0, rows);
+    return;
+  }
+  std::vector<int64_t> cut(nth + 1, rows);
+  cut[0] = 0;
+  for (int t = 1; t < nth; ++t) {
+    const int64_t target = total * t / nth;
+    cut[t] = std::lower_bound(ptr, ptr + rows + 1, target) - ptr;
+    cut[t] = std::max(cut[t], cut[t - 1]);
+  }
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back([&, t] { f(cut[t], cut[t + 1]); });
+  f(cut[0], cut[1]);
+  for (auto& th : pool) th.join();
+}
+
+// Column-major index of a CSR matrix: for column j, entries
+// cstart[j] .. cstart[j+1]-1 of cpos hold the CSR positions of its
+// nonzeros in ascending row order, and crow their rows.
+// An array left uninitialised on allocation, so that the threads that fill
+// it are the first to touch its pages.
+template <typename T>
+struct RawArray {
+  std::unique_ptr<T[]> p;
+  void reset(int64_t count) { p.reset(new T[std::max<int64_t>(count, 1)]); }
+  T& operator[](int64_t i) { return p[i]; }
+  const T& operator[](int64_t i) const { return p[i]; }
+};
+
+struct ColIndex {
+  std::vector<int64_t> cstart;
+  RawArray<int64_t> cpos;
+  RawArray<int32_t> crow;
+  RawArray<double> cabs;  // |value| in the same order, read sequentially by column passes
+};
+
+static void build_col_index(const opdhg_lp* lp, ColIndex& C) {
+  const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
+  C.cstart.assign(n + 1, 0);
+  C.cpos.reset(nnz);
+  C.crow.reset(nnz);
+  C.cabs.reset(nnz);
+  // a counting sort by column in parallel: thread t takes a range of rows
+  // (in row order), counts its columns, and scatters its entries to the
+  // positions after those of threads t' < t, so rows stay ascending within
+  // every column exactly as a serial pass would leave them
+  int nth = (int)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)std::min(host_threads(), 16), m, nnz / 262144 + 1}));
+  nth = (int)std::max<int64_t>(1, std::min<int64_t>(nth, (int64_t)(1ll << 29) / (4 * (n + 1))));
+  std::vector<int64_t> cut(nth + 1, m);
+  cut[0] = 0;
+  for (int t = 1; t < nth; ++t)
+    cut[t] = std::max(cut[t - 1],
+                      (int64_t)(std::lower_bound(lp->row_ptr, lp->row_ptr + m + 1, nnz * t / nth) -
+                                lp->row_ptr));
+  std::vector<std::vector<int32_t>> cnt(nth, std::vector<int32_t>(n, 0));
+  auto run = [&](auto&& f) {
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back([&, t] { f(t); });
+    f(0);
+    for (auto& th : pool) th.join();
+  };
+  run([&](int t) {
+    for (int64_t k = lp->row_ptr[cut[t]]; k < lp->row_ptr[cut[t + 1]]; ++k) cnt[t][lp->col_idx[k]]++;
+  });
+  // column starts, then each thread's first position in every column
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t c = 0;
+    for (int t = 0; t < nth; ++t) c += cnt[t][j];
+    C.cstart[j + 1] = C.cstart[j] + c;
+  }
+  run([&](int t) {
+    // this thread's columns in [n * t / nth, n * (t + 1) / nth): turn counts into positions
+    for (int64_t j = n * t / nth; j < n * (t + 1) / nth; ++j) {
+      int64_t pos = C.cstart[j];
+      for (int u = 0; u < nth; ++u) {
+        const int32_t c = cnt[u][j];
+        cnt[u][j] = (int32_t)(pos - C.cstart[j]);  // offset of thread u inside column j
+        pos += c;
+      }
+    }
+  });
+  run([&](int t) {
+    std::vector<int32_t>& off = cnt[t];
+    for (int64_t i = cut[t]; i < cut[t + 1]; ++i)
+      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+        const int32_t j = lp->col_idx[k];
+        const int64_t q = C.cstart[j] + off[j]++;
+        C.cpos[q] = k;
+        C.crow[q] = (int32_t)i;
+        C.cabs[q] = std::fabs(lp->val[k]);
+      }
+  });
+}
+
+// Ruiz passes then one Pock-Chambolle pass (Section 2); see the oracle's
+// rescaling for the definition. Maxima do not depend on order and the sums
+// are double-double, so the threads change no bit of the result.
+static void rescale_with(const opdhg_lp* lp, const ColIndex& C, int ruiz_iters, double beta,
+                         std::vector<double>& sval, std::vector<double>& dr,
+                         std::vector<double>& dc) {
   const int64_t m = lp->m, n = lp->n;
   dr.assign(m, 1.0);
   dc.assign(n, 1.0);
@@ -160,39 +269,60 @@ void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<d
     for (int64_t j = 0; j < n; ++j) dc[j] = dc[j] / std::sqrt(cs[j] == 0.0 ? 1.0 : cs[j]);
   };
   for (int it = 0; it < ruiz_iters; ++it) {
-    std::fill(rs.begin(), rs.end(), 0.0);
-    std::fill(cs.begin(), cs.end(), 0.0);
-    for (int64_t i = 0; i < m; ++i) {
-      double rmax = 0.0;
-      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
-        const int32_t j = lp->col_idx[k];
-        const double a = std::fabs(lp->val[k]) * dr[i] * dc[j];
-        rmax = std::max(rmax, a);
-        cs[j] = std::max(cs[j], a);
+    parallel_rows(lp->row_ptr, m, [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        double rmax = 0.0;
+        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k)
+          rmax = std::max(rmax, std::fabs(lp->val[k]) * dr[i] * dc[lp->col_idx[k]]);
+        rs[i] = rmax;
       }
-      rs[i] = rmax;
-    }
+    });
+    parallel_rows(C.cstart.data(), n, [&](int64_t j0, int64_t j1) {
+      for (int64_t j = j0; j < j1; ++j) {
+        double cmax = 0.0;
+        for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q)
+          cmax = std::max(cmax, C.cabs[q] * dr[C.crow[q]] * dc[j]);
+        cs[j] = cmax;
+      }
+    });
     apply();
   }
   if (beta >= 0.0) {
-    std::vector<HostDD> csum(n);
-    for (int64_t i = 0; i < m; ++i) {
-      HostDD racc;
-      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
-        const int32_t j = lp->col_idx[k];
-        const double a = std::fabs(lp->val[k]) * dr[i] * dc[j];
-        racc.add(beta == 1.0 ? a : std::pow(a, beta));
-        csum[j].add(beta == 1.0 ? a : std::pow(a, 2.0 - beta));
+    parallel_rows(lp->row_ptr, m, [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        HostDD racc;
+        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+          const double a = std::fabs(lp->val[k]) * dr[i] * dc[lp->col_idx[k]];
+          racc.add(beta == 1.0 ? a : std::pow(a, beta));
+        }
+        rs[i] = racc.value();
       }
-      rs[i] = racc.value();
-    }
-    for (int64_t j = 0; j < n; ++j) cs[j] = csum[j].value();
+    });
+    parallel_rows(C.cstart.data(), n, [&](int64_t j0, int64_t j1) {
+      for (int64_t j = j0; j < j1; ++j) {
+        HostDD cacc;
+        for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q) {
+          const double a = C.cabs[q] * dr[C.crow[q]] * dc[j];
+          cacc.add(beta == 1.0 ? a : std::pow(a, 2.0 - beta));
+        }
+        cs[j] = cacc.value();
+      }
+    });
     apply();
   }
   sval.resize(lp->nnz);
-  for (int64_t i = 0; i < m; ++i)
-    for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k)
-      sval[k] = lp->val[k] * dr[i] * dc[lp->col_idx[k]];
+  parallel_rows(lp->row_ptr, m, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i)
+      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k)
+        sval[k] = lp->val[k] * dr[i] * dc[lp->col_idx[k]];
+  });
+}
+
+void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,
+                  std::vector<double>& dr, std::vector<double>& dc) {
+  ColIndex C;
+  build_col_index(lp, C);
+  rescale_with(lp, C, ruiz_iters, beta, sval, dr, dc);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,31 +426,43 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   for (int64_t i = 0; i < m; ++i) inv_a[out.perm_a[i]] = (int32_t)i;
   for (int64_t j = 0; j < n; ++j) inv_t[out.perm_t[j]] = (int32_t)j;
   std::vector<double> sval;
-  rescale_host(lp, p->ruiz_iters, p->pc_beta, sval, out.dr, out.dc);
+  ColIndex C;
+  build_col_index(lp, C);
+  rescale_with(lp, C, p->ruiz_iters, p->pc_beta, sval, out.dr, out.dc);
   // A in device order: row i' is original row perm_a[i'], columns relabelled
   out.ci_a.resize(nnz);
   out.va_a.resize(nnz);
-  for (int64_t i2 = 0; i2 < m; ++i2) {
-    const int64_t i = out.perm_a[i2];
-    int64_t pos = out.rp_a[i2];
-    for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k, ++pos) {
-      out.ci_a[pos] = inv_t[lp->col_idx[k]];
-      out.va_a[pos] = sval[k];
-    }
+  {
+    std::vector<int64_t> dptr(m + 1);  // nonzero offsets in device order, for balancing
+    for (int64_t i2 = 0; i2 <= m; ++i2) dptr[i2] = out.rp_a[i2];
+    parallel_rows(dptr.data(), m, [&](int64_t r0, int64_t r1) {
+      for (int64_t i2 = r0; i2 < r1; ++i2) {
+        const int64_t i = out.perm_a[i2];
+        int64_t pos = out.rp_a[i2];
+        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k, ++pos) {
+          out.ci_a[pos] = inv_t[lp->col_idx[k]];
+          out.va_a[pos] = sval[k];
+        }
+      }
+    });
   }
   // A^T in device order: row j' is original column perm_t[j']; entries in
   // ascending original row, labelled with device row indices
   out.ci_t.resize(nnz);
   out.va_t.resize(nnz);
   {
-    std::vector<int32_t> next(n);
-    for (int64_t j = 0; j < n; ++j) next[j] = out.rp_t[inv_t[j]];
-    for (int64_t i = 0; i < m; ++i)
-      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
-        const int32_t pos = next[lp->col_idx[k]]++;
-        out.ci_t[pos] = inv_a[i];
-        out.va_t[pos] = sval[k];
+    std::vector<int64_t> dptr(n + 1);
+    for (int64_t j2 = 0; j2 <= n; ++j2) dptr[j2] = out.rp_t[j2];
+    parallel_rows(dptr.data(), n, [&](int64_t r0, int64_t r1) {
+      for (int64_t j2 = r0; j2 < r1; ++j2) {
+        const int64_t j = out.perm_t[j2];
+        int64_t pos = out.rp_t[j2];
+        for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q, ++pos) {
+          out.ci_t[pos] = inv_a[C.crow[q]];
+          out.va_t[pos] = sval[C.cpos[q]];
+        }
       }
+    });
   }
   out.b.resize(m);
   out.sense.resize(m);

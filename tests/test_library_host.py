@@ -99,9 +99,13 @@ def test_validate_agrees_with_oracle():
         assert P.opdhg_validate(lp) == capi.OPDHG_ERR_INVALID_ARGUMENT, name
 
 
-@pytest.mark.parametrize("name,seed", [("cfg0", 0), ("cfg0", 5), ("cfg1", 1)])
-def test_rescale_bitwise_equal_to_oracle(name, seed):
-    lp = config_lp(name, seed=seed, scale=0.05 if name == "cfg1" else 1.0)
+@pytest.mark.parametrize("name,seed,scale", [("cfg0", 0, 1.0), ("cfg0", 5, 1.0), ("cfg1", 1, 0.05),
+                                             ("cfg4", 0, 0.06)])
+def test_rescale_bitwise_equal_to_oracle(name, seed, scale):
+    # the last case has enough nonzeros (about 370k) that the library splits
+    # its column index and its row and column passes over several host threads
+    lp = config_lp(name, seed=seed, scale=scale) if name != "cfg4" else \
+        config_lp(name, index=seed, scale=scale)
     sval, dr, dc = P.opdhg_rescale(lp, P.opdhg_default_params())
     ref = rescale(lp, 10, 1.0)
     assert np.array_equal(dr, ref.Dr)
