@@ -16,7 +16,7 @@ termination test to PDLP; those parts implement the readings listed in
 
 Modules:
   params    solver parameters and their defaults
-  problem   input validation and diagonal rescaling (Ruiz, Pock-Chambolle)
+  problem   input validation and diagonal rescaling (Ruiz, L2, Pock-Chambolle)
   kkt       residuals, objectives, duality gap, relative KKT error
   pdhg      the iteration, the learner, restarts, the solve loop and traces
 
@@ -27,7 +27,7 @@ definitions). The constants of the PDLP step-size rule and restart scheme
 are pinned only by hand-worked examples of the readings, not by the paper.
 """
 
-from .params import Params, default_params  # noqa: F401
+from .params import Params, default_params, vanilla_params, variant  # noqa: F401
 from .problem import validate, rescale, ScaledLP  # noqa: F401
 from .kkt import kkt_parts, rel_kkt, weighted_kkt  # noqa: F401
 from .pdhg import (  # noqa: F401
@@ -41,4 +41,5 @@ from .pdhg import (  # noqa: F401
     solve,
     solve_from_state,
     initial_state,
+    spectral_norm_estimate,
 )

@@ -30,6 +30,22 @@ approach as PDLP", Section 3.2):
               derivative of the box projection; dual: 1 on equality rows and
               y^{k+1/2}_i >= 0 on >= rows, the derivative of the sign
               projection.
+
+The vanilla PDHG of Section 4.2 (constant step sizes with tau sigma
+|A|_2^2 < 1, Section 2; Ruiz then L2-norm rescaling; no restarts) is the
+second configuration (readings):
+
+  constant step  eta = step_scale / nu, nu the power-iteration estimate of
+              |A~|_2 (module pdhg), so tau sigma |A~|^2 = eta^2 |A~|^2 <
+              1 whenever nu > step_scale |A~|; every attempt is accepted
+              and eta never changes. nu = 0 (no nonzeros) gives
+              eta = step_scale.
+  no restarts the evaluation every eval_every iterations only tests
+              termination; the primal weight keeps its initial value and the
+              average runs over all iterations.
+  L2 pass     after the Ruiz passes and before the Pock-Chambolle pass:
+              rows and columns divided by the square roots of their L2
+              norms (0 read as 1).
 """
 
 from __future__ import annotations
@@ -39,6 +55,12 @@ import dataclasses
 SCHEDULE_ADAGRAD_DIAG = 0
 SCHEDULE_ADAGRAD_NORM = 1
 SCHEDULE_CONSTANT = 2
+
+STEP_ADAPTIVE = 0
+STEP_CONSTANT = 1
+
+RESTART_ADAPTIVE = 0
+RESTART_NONE = 1
 
 
 @dataclasses.dataclass
@@ -60,6 +82,12 @@ class Params:
     step_growth: float = 0.6
     step_reduction: float = 0.3
     max_step_retries: int = 60
+    step_rule: int = STEP_ADAPTIVE
+    restart_scheme: int = RESTART_ADAPTIVE
+    l2_rescale: bool = False
+    step_scale: float = 0.9  # constant step: eta = step_scale / |A~|_2 estimate
+    power_iters: int = 200  # power-iteration limit
+    power_tol: float = 1e-7  # stop when the estimate of |A~|_2^2 moves less than this, relatively
 
 
 def default_params(**overrides) -> Params:
@@ -76,3 +104,14 @@ def variant(name: str, lr: float) -> Params:
     }
     norm, phi = table[name]
     return default_params(lr=lr, normalize=norm, phi=phi)
+
+
+def vanilla_params(lr: float, **overrides) -> Params:
+    """Section 4.2: vanilla PDHG (constant steps, no restarts) after 10 Ruiz
+    passes and one L2-norm pass, with the normalized online loss updated every
+    iteration; iteration limit 5e4 and tolerance 1e-4."""
+    base = dict(lr=lr, normalize=True, phi=1, step_rule=STEP_CONSTANT,
+                restart_scheme=RESTART_NONE, l2_rescale=True, pc_beta=-1.0,
+                ruiz_iters=10, max_iter=50000, tol=1e-4)
+    base.update(overrides)
+    return default_params(**base)

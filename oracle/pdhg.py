@@ -2,7 +2,7 @@
 
 One iteration (Algorithm 1 of the paper):
 
-  1. PDHG step with adaptive step size eta and primal weight w, eq. (6):
+  1. PDHG step with step size eta and primal weight w, eq. (6):
         x^{k+1/2} = x^k - (eta / w) T_k (c - A^T y^k)
         x^{k+1}   = proj_X(x^{k+1/2})                 X = [l, u]
         y^{k+1/2} = y^k + eta w S_k (b - A(2 x^{k+1} - x^k))
@@ -10,7 +10,8 @@ One iteration (Algorithm 1 of the paper):
      The paper writes the standard form (X = R^n_+, Y = R^m); the box and
      the sign constraint on >= rows are the general form this solver takes.
      A step is tried with eta, judged by the step-size rule and retried with
-     a smaller eta when rejected (reading of PDLP's rule, params.py).
+     a smaller eta when rejected (reading of PDLP's rule, params.py); with
+     the constant step of vanilla PDHG every attempt is accepted.
   2. If k mod phi != 0 the preconditioners stay.
   3. Otherwise the online gradients of eq. (7) are formed,
         G^p = -(eta / w) (g o 1[l <= x^{k+1/2} <= u]) o g,   g = c - A^T y^k
@@ -41,8 +42,8 @@ import numpy as np
 
 from .exact import exact_dot, exact_norm, exact_spmv
 from .kkt import kkt_parts, rel_kkt, weighted_kkt
-from .params import (Params, SCHEDULE_ADAGRAD_DIAG, SCHEDULE_ADAGRAD_NORM,
-                     SCHEDULE_CONSTANT)
+from .params import (Params, RESTART_NONE, SCHEDULE_ADAGRAD_DIAG, SCHEDULE_ADAGRAD_NORM,
+                     SCHEDULE_CONSTANT, STEP_CONSTANT)
 from .problem import ScaledLP, rescale, validate
 
 OPTIMAL = 0
@@ -146,16 +147,47 @@ def AT_mul(slp: ScaledLP, y: np.ndarray) -> np.ndarray:
     return exact_spmv(slp.AT.indptr, slp.AT.indices, slp.AT.data, y)
 
 
-def initial_state(slp: ScaledLP) -> State:
+def spectral_norm_estimate(slp: ScaledLP, iters: int, tol: float) -> float:
+    """Power iteration on A~^T A~ for |A~|_2 (the constant step of vanilla
+    PDHG needs tau sigma |A~|_2^2 < 1, Section 2).
+
+    v_0 = 1 / |1|; each round forms w = A~^T (A~ v), takes lam = |w| (for a
+    unit v, |A~ v|^2 <= |w| <= |A~|_2^2, so lam never overshoots) and
+    v = w / lam. It stops after `iters` rounds, when lam stops changing by
+    more than tol relative to itself, or when w = 0. Returns sqrt(lam).
+    """
+    ones = np.ones(slp.n)
+    v = ones / exact_norm(ones)
+    lam = 0.0
+    for _ in range(iters):
+        w = AT_mul(slp, A_mul(slp, v))
+        lam_new = exact_norm(w)
+        if lam_new == 0.0:
+            return 0.0
+        v = w / lam_new
+        done = abs(lam_new - lam) <= tol * lam_new
+        lam = lam_new
+        if done:
+            break
+    return math.sqrt(lam)
+
+
+def initial_state(slp: ScaledLP, p: Optional[Params] = None) -> State:
     """Start point (reading): x = proj_X(0), y = 0, T = 1, S = 1, zero AdaGrad
-    state, w = |c~| / |b~| (1 when either is tiny), eta = 1 / max |A~_ij|."""
+    state, w = |c~| / |b~| (1 when either is tiny), eta = 1 / max |A~_ij|
+    for the adaptive rule, eta = step_scale / |A~|_2 (estimate) for the
+    constant step."""
     x = np.minimum(np.maximum(np.zeros(slp.n), slp.l), slp.u)
     y = np.zeros(slp.m)
     cn = exact_norm(slp.c)
     bn = exact_norm(slp.b)
     omega = cn / bn if (cn > 1e-10 and bn > 1e-10) else 1.0
-    amax = float(np.max(np.abs(slp.A.data))) if slp.A.nnz else 0.0
-    eta = 1.0 / amax if amax > 0 else 1.0
+    if p is not None and p.step_rule == STEP_CONSTANT:
+        nu = spectral_norm_estimate(slp, p.power_iters, p.power_tol)
+        eta = p.step_scale / nu if nu > 0.0 else p.step_scale
+    else:
+        amax = float(np.max(np.abs(slp.A.data))) if slp.A.nnz else 0.0
+        eta = 1.0 / amax if amax > 0 else 1.0
     return State(
         x=x, y=y, T=np.ones(slp.n), S=np.ones(slp.m), Hp=np.zeros(slp.n), Hd=np.zeros(slp.m),
         Hp_norm=0.0, Hd_norm=0.0, eta=eta, omega=omega, k=0, t=0, attempts=0, restarts=0,
@@ -315,7 +347,7 @@ def _evaluate(slp: ScaledLP, st: State, p: Params):
         return (OPTIMAL,) + best
     if st.k >= p.max_iter:
         return (ITERATION_LIMIT,) + best
-    if st.t > 0:
+    if st.t > 0 and p.restart_scheme != RESTART_NONE:
         kc = weighted_kkt(cur, st.omega)
         ka = weighted_kkt(avg, st.omega) if avg is not None else math.inf
         kanc = weighted_kkt(st.anchor_parts, st.omega)
@@ -358,8 +390,11 @@ def _iterate(slp: ScaledLP, st: State, p: Params) -> bool:
         inter = abs(exact_dot(dy, a["Ax_new"] - st.Ax))
         if not (math.isfinite(dx2) and math.isfinite(dy2) and math.isfinite(inter)):
             return False
-        eta_bar, eta_next, accepted = step_size_rule(st.eta, st.omega, dx2, dy2, inter,
-                                                     st.attempts, p)
+        if p.step_rule == STEP_CONSTANT:
+            eta_next, accepted = st.eta, True
+        else:
+            _, eta_next, accepted = step_size_rule(st.eta, st.omega, dx2, dy2, inter,
+                                                   st.attempts, p)
         if accepted:
             break
         st.eta = eta_next
@@ -432,6 +467,6 @@ def solve(lp, params: Optional[Params] = None,
     """Validate, rescale, initialize and run; x and y come back unscaled."""
     p = params or Params()
     validate(lp)
-    slp = rescale(lp, p.ruiz_iters, p.pc_beta)
-    st = initial_state(slp)
+    slp = rescale(lp, p.ruiz_iters, p.pc_beta, p.l2_rescale)
+    st = initial_state(slp, p)
     return solve_from_state(slp, st, p, trace=trace, stop_k=stop_k)

@@ -120,11 +120,14 @@ def _col_sums(vals: np.ndarray, col: np.ndarray, row_ptr: np.ndarray, m: int, n:
     return exact_row_sums(csc.indptr, csc.data)
 
 
-def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0) -> ScaledLP:
-    """Ruiz infinity-norm passes, then one Pock-Chambolle pass.
+def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0, l2: bool = False) -> ScaledLP:
+    """Ruiz infinity-norm passes, an optional L2-norm pass, then one
+    Pock-Chambolle pass.
 
     Ruiz pass: r_i = max_j |A~_ij|, s_j = max_i |A~_ij| (0 read as 1), then
     D_r /= sqrt(r), D_c /= sqrt(s), with A~_ij = A_ij D_r,i D_c,j.
+    L2 pass (l2=True; the preprocessing of the vanilla PDHG runs, Section
+    4.2): r_i = |A~_i,:|_2, s_j = |A~_:,j|_2, applied the same way.
     Pock-Chambolle pass (exponent beta; skipped when beta < 0):
     r_i = sum_j |A~_ij|^beta, s_j = sum_i |A~_ij|^(2 - beta), applied the
     same way, so that with beta = 1 the scaled matrix has spectral norm at
@@ -143,6 +146,15 @@ def rescale(lp, ruiz_iters: int = 10, pc_beta: float = 1.0) -> ScaledLP:
         r = _row_max(a, rp, m)
         s = np.zeros(n)
         np.maximum.at(s, col, a)
+        r[r == 0] = 1.0
+        s[s == 0] = 1.0
+        Dr = Dr / np.sqrt(r)
+        Dc = Dc / np.sqrt(s)
+    if l2:
+        a = absv * Dr[rows] * Dc[col]
+        a2 = a * a
+        r = np.sqrt(exact_row_sums(rp, a2))
+        s = np.sqrt(_col_sums(a2, col, rp, m, n))
         r[r == 0] = 1.0
         s[s == 0] = 1.0
         Dr = Dr / np.sqrt(r)

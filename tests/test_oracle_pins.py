@@ -605,3 +605,117 @@ def test_restart_primal_weight_update():
     dx = np.linalg.norm(xa - st0.x)
     dy = np.linalg.norm(ya - st0.y)
     assert math.isclose(tr[65].omega, math.sqrt(dy / dx * tr[64].omega), rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# vanilla PDHG of Section 4.2: L2 pass, power iteration, constant steps,
+# no restarts
+# ---------------------------------------------------------------------------
+
+
+def _rank_one_lp(seed, m=6, n=9):
+    rng = np.random.default_rng(seed)
+    uu = rng.uniform(0.1, 10.0, m) * rng.choice([-1, 1], m)
+    vv = rng.uniform(0.1, 10.0, n) * rng.choice([-1, 1], n)
+    A = np.outer(uu, vv)
+    lp = _lp_from_dense(A, np.ones(m), np.zeros(m), np.ones(n), np.zeros(n), np.full(n, 5.0))
+    return lp, uu, vv
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_l2_pass_rank_one_closed_form(seed):
+    # A = u v^T: |A_i,:| = |u_i| |v|, |A_:,j| = |v_j| |u|, so one L2 pass gives
+    # A~_ij = sign(u_i v_j) sqrt(|u_i v_j|) / sqrt(|u| |v|)
+    lp, uu, vv = _rank_one_lp(seed)
+    s = rescale(lp, ruiz_iters=0, pc_beta=-1, l2=True)
+    want = np.sign(np.outer(uu, vv)) * np.sqrt(np.abs(np.outer(uu, vv))) / math.sqrt(
+        np.linalg.norm(uu) * np.linalg.norm(vv))
+    assert np.allclose(s.A.toarray(), want, rtol=1e-14, atol=0)
+    assert np.allclose(s.Dr, 1.0 / np.sqrt(np.abs(uu) * np.linalg.norm(vv)), rtol=1e-14, atol=0)
+
+
+def test_l2_pass_exact_on_scaled_permutation():
+    rng = np.random.default_rng(4)
+    n = 8
+    A = np.zeros((n, n))
+    A[np.arange(n), rng.permutation(n)] = rng.uniform(0.01, 100, n) * rng.choice([-1, 1], n)
+    lp = _lp_from_dense(A, np.ones(n), np.zeros(n), np.ones(n), np.zeros(n), np.ones(n))
+    s = rescale(lp, ruiz_iters=0, pc_beta=-1, l2=True)
+    assert np.allclose(np.abs(s.A.data), 1.0, rtol=1e-15, atol=0)
+
+
+def test_l2_pass_sits_between_ruiz_and_pock_chambolle():
+    # with all three passes the Pock-Chambolle bound still holds, and the L2
+    # pass changes the result (it runs, and before the last pass)
+    lp = random_lp(5, 50, 90, degree=("uniform", 1, 6))
+    s1 = rescale(lp, 10, 1.0, l2=True)
+    s0 = rescale(lp, 10, 1.0, l2=False)
+    assert np.linalg.norm(s1.A.toarray(), 2) <= 1.0 + 1e-12
+    assert not np.array_equal(s1.Dr, s0.Dr)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_power_iteration_rank_one_exact(seed):
+    lp, uu, vv = _rank_one_lp(seed)
+    s = rescale(lp, ruiz_iters=0, pc_beta=-1)
+    nu = P.spectral_norm_estimate(s, 50, 1e-12)
+    assert math.isclose(nu, np.linalg.norm(uu) * np.linalg.norm(vv), rel_tol=1e-14)
+
+
+def test_power_iteration_known_spectrum():
+    # A = Q1 diag(sv) Q2^T with a clear gap: the estimate converges to max(sv)
+    rng = np.random.default_rng(7)
+    q1, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    q2, _ = np.linalg.qr(rng.standard_normal((20, 20)))
+    sv = np.array([3.0, 2.0, 1.5, 1.0, 0.9, 0.5, 0.4, 0.3, 0.2, 0.1, 0.05, 0.01])
+    A = q1 @ np.hstack([np.diag(sv), np.zeros((12, 8))]) @ q2.T
+    lp = _lp_from_dense(A, np.ones(12), np.zeros(12), np.ones(20), np.zeros(20), np.ones(20))
+    s = rescale(lp, ruiz_iters=0, pc_beta=-1)
+    assert math.isclose(P.spectral_norm_estimate(s, 500, 1e-15), 3.0, rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_power_iteration_never_overshoots(seed):
+    lp = random_lp(seed, 40, 70, degree=("uniform", 1, 6))
+    s = rescale(lp, 10, -1.0, l2=True)
+    true = np.linalg.norm(s.A.toarray(), 2)
+    for iters in (1, 3, 10, 200):
+        nu = P.spectral_norm_estimate(s, iters, 1e-7)
+        assert nu <= true * (1 + 1e-12)
+    assert nu >= 0.99 * true
+
+
+def test_vanilla_constant_step_no_restarts():
+    lp = config_lp("cfg0", seed=1)
+    p = oracle.vanilla_params(0.0, max_iter=3000)
+    r = oracle.solve(lp, p, trace=range(0, 3000, 250))
+    s = rescale(lp, 10, -1.0, l2=True)
+    eta0 = 0.9 / P.spectral_norm_estimate(s, p.power_iters, p.power_tol)
+    st0 = P.initial_state(s, p)
+    assert r.eta == eta0 == st0.eta
+    assert r.omega == st0.omega
+    assert r.restarts == 0 and r.attempts == r.iterations
+    for e in r.trace:
+        assert e.eta == eta0 and e.omega == st0.omega and e.attempts == e.k
+    # the step-weighted average runs over every iteration
+    assert math.isclose(r.state.w, r.iterations * eta0, rel_tol=1e-12)
+    # tau sigma |A~|^2 = eta^2 |A~|^2 < 1 (Section 2)
+    assert eta0 * np.linalg.norm(s.A.toarray(), 2) < 1.0
+
+
+@pytest.mark.parametrize("lr", [0.0, 1e-1])
+def test_vanilla_reaches_planted_objective(lr):
+    lp = config_lp("cfg0", seed=0)
+    r = oracle.solve(lp, oracle.vanilla_params(lr, max_iter=20000))
+    assert r.status == P.OPTIMAL and r.restarts == 0
+    obj = lp.planted_obj
+    assert abs(r.primal_obj - obj) <= 2e-4 * (1 + abs(obj))
+
+
+def test_vanilla_tiny_matches_vertex_enumeration():
+    lp = tiny_lp(2, 3, 5, m_eq=1)
+    best, xv, _ = brute_force(lp)
+    assert xv is not None
+    r = oracle.solve(lp, oracle.vanilla_params(1e-2, tol=1e-8, max_iter=200000))
+    assert r.status == P.OPTIMAL
+    assert math.isclose(r.primal_obj, best, rel_tol=1e-6, abs_tol=1e-6)
