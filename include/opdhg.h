@@ -77,6 +77,16 @@ extern "C" {
 #define OPDHG_SCHEDULE_ADAGRAD_NORM 1 /* scalar: H += |G|^2, P -= lr G / sqrt(H) */
 #define OPDHG_SCHEDULE_CONSTANT 2     /* plain OGD: P -= lr G */
 
+/* ---- step-size rule ---- */
+#define OPDHG_STEP_ADAPTIVE 0 /* PDLP's adaptive rule (the paper runs on top of cuPDLP.jl, Section 4.3) */
+#define OPDHG_STEP_CONSTANT 1 /* vanilla PDHG (Sections 2 and 4.2): eta = step_scale / |A~|_2 estimate,
+                                 every attempt accepted */
+
+/* ---- restart scheme ---- */
+#define OPDHG_RESTART_ADAPTIVE 0 /* PDLP's KKT-based restarts, preconditioners kept (Section 3.2) */
+#define OPDHG_RESTART_NONE 1     /* vanilla PDHG (Section 4.2): evaluations test termination only;
+                                    the primal weight keeps its initial value */
+
 /* LP in CSR form; all pointers are host pointers. */
 typedef struct opdhg_lp {
   int64_t m;                /* rows (>= 0) */
@@ -117,6 +127,12 @@ typedef struct opdhg_params {
   int32_t tile_nnz;      /* SpMV tile target in nonzeros; 0 picks automatically */
   int32_t lanes;         /* lanes per row in SpMV tiles; 0 picks per tile */
   int32_t workgroups;    /* workgroups per sparse-product launch; 0 picks automatically */
+  int32_t step_rule;     /* OPDHG_STEP_* */
+  int32_t restart_scheme; /* OPDHG_RESTART_* */
+  int32_t l2_rescale;    /* 1: one L2-norm pass after the Ruiz passes (Section 4.2) */
+  int32_t power_iters;   /* constant step: power-iteration rounds at most (>= 1) */
+  double step_scale;     /* constant step: eta = step_scale / estimate of |A~|_2 (> 0) */
+  double power_tol;      /* power iteration stops when |A~|_2^2 moves less than this, relatively */
 } opdhg_params;
 
 typedef struct opdhg_result {
@@ -153,10 +169,15 @@ typedef struct opdhg_session opdhg_session;
 typedef struct opdhg_server opdhg_server;
 
 /* Defaults: tol 1e-4, max_iter 100000, time limit 600 s, FP64, AdaGrad
- * (diagonal), lr 0, phi 20, normalize 1, floor 0, 10 Ruiz passes,
- * Pock-Chambolle beta 1, eval every 64, 60 step retries, restart constants
- * 0.2 / 0.8 / 0.36, smoothing 0.5, step exponents 0.6 / 0.3, automatic
- * tiling. */
+ * (diagonal), lr 0, phi 20, normalize 1, floor 0, 10 Ruiz passes, no L2
+ * pass, Pock-Chambolle beta 1, eval every 64, 60 step retries, adaptive
+ * steps and restarts, restart constants 0.2 / 0.8 / 0.36, smoothing 0.5,
+ * step exponents 0.6 / 0.3, automatic tiling; for the constant step:
+ * step_scale 0.9, at most 200 power-iteration rounds, power_tol 1e-7.
+ *
+ * The vanilla PDHG runs of Section 4.2 take OPDHG_STEP_CONSTANT,
+ * OPDHG_RESTART_NONE, l2_rescale 1, pc_beta -1, normalize 1, phi 1 and
+ * max_iter 50000. */
 void opdhg_default_params(opdhg_params* p);
 
 /* Check an LP without touching the device. Returns OPDHG_ERR_INVALID_ARGUMENT
@@ -175,6 +196,16 @@ int opdhg_workspace_bytes(const opdhg_lp* lp, const opdhg_params* p, size_t* byt
  * lp->val, d_row[m], d_col[n] with A~ = diag(d_row) A diag(d_col). */
 int opdhg_rescale(const opdhg_lp* lp, const opdhg_params* p, double* scaled_val,
                   double* d_row, double* d_col);
+
+/* Host-only estimate of |A~|_2 for the rescaled matrix A~ (rescaling as in
+ * opdhg_rescale, with the parameters' passes), exposed for checking: power
+ * iteration on A~^T A~ from the normalized all-ones vector, lam = |A~^T A~ v|
+ * and v = A~^T A~ v / lam per round, stopping after p->power_iters rounds or
+ * when lam changes by at most p->power_tol * lam; *norm_out = sqrt(lam), 0
+ * when A~ v vanishes. The constant step (Section 2: tau sigma |A|_2^2 < 1)
+ * is eta = p->step_scale / *norm_out. Sums are double-double, so the result
+ * does not depend on the thread count. */
+int opdhg_spectral_norm(const opdhg_lp* lp, const opdhg_params* p, double* norm_out);
 
 /* Solve one LP (blocking). x_out[n], y_out[m] receive the returned iterate
  * (unscaled); res receives status and statistics. */

@@ -15,6 +15,8 @@ from .capi import (  # noqa: F401
     opdhg_default_params,
     opdhg_last_error,
     opdhg_rescale,
+    opdhg_spectral_norm,
+    opdhg_vanilla_params,
     opdhg_server_default_cfg,
     opdhg_session_create,
     opdhg_solve,
@@ -24,4 +26,8 @@ from .capi import (  # noqa: F401
     opdhg_workspace_bytes,
     OPDHG_FP32,
     OPDHG_FP64,
+    OPDHG_RESTART_ADAPTIVE,
+    OPDHG_RESTART_NONE,
+    OPDHG_STEP_ADAPTIVE,
+    OPDHG_STEP_CONSTANT,
 )

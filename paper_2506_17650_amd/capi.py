@@ -40,6 +40,10 @@ OPDHG_FP32 = 1
 OPDHG_SCHEDULE_ADAGRAD_DIAG = 0
 OPDHG_SCHEDULE_ADAGRAD_NORM = 1
 OPDHG_SCHEDULE_CONSTANT = 2
+OPDHG_STEP_ADAPTIVE = 0
+OPDHG_STEP_CONSTANT = 1
+OPDHG_RESTART_ADAPTIVE = 0
+OPDHG_RESTART_NONE = 1
 
 _p = ctypes.POINTER
 c_i64, c_i32, c_dbl, c_sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
@@ -63,6 +67,8 @@ class opdhg_params(ctypes.Structure):
         ("beta_suff", c_dbl), ("beta_nec", c_dbl), ("beta_art", c_dbl),
         ("pw_smoothing", c_dbl), ("step_growth", c_dbl), ("step_reduction", c_dbl),
         ("tile_nnz", c_i32), ("lanes", c_i32), ("workgroups", c_i32),
+        ("step_rule", c_i32), ("restart_scheme", c_i32), ("l2_rescale", c_i32),
+        ("power_iters", c_i32), ("step_scale", c_dbl), ("power_tol", c_dbl),
     ]
 
 
@@ -115,6 +121,7 @@ SIGNATURES = {
     "opdhg_validate": (c_i32, [_p(opdhg_lp)]),
     "opdhg_workspace_bytes": (c_i32, [_p(opdhg_lp), _p(opdhg_params), _p(c_sz)]),
     "opdhg_rescale": (c_i32, [_p(opdhg_lp), _p(opdhg_params), _p(c_dbl), _p(c_dbl), _p(c_dbl)]),
+    "opdhg_spectral_norm": (c_i32, [_p(opdhg_lp), _p(opdhg_params), _p(c_dbl)]),
     "opdhg_solve": (c_i32, [_p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                             ctypes.c_void_p, _p(c_dbl), _p(c_dbl), _p(opdhg_result)]),
     "opdhg_batch_workspace_bytes": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), _p(c_sz)]),
@@ -240,6 +247,17 @@ def opdhg_default_params(**overrides) -> opdhg_params:
     return p
 
 
+def opdhg_vanilla_params(lr: float = 0.0, **overrides) -> opdhg_params:
+    """Vanilla PDHG as run in Section 4.2: constant steps from a power
+    iteration, no restarts, 10 Ruiz passes then one L2-norm pass, normalized
+    online loss updated every iteration, 5e4 iterations at most."""
+    base = dict(lr=lr, normalize=1, phi=1, step_rule=OPDHG_STEP_CONSTANT,
+                restart_scheme=OPDHG_RESTART_NONE, l2_rescale=1, pc_beta=-1.0,
+                ruiz_iters=10, max_iter=50000, tol=1e-4)
+    base.update(overrides)
+    return opdhg_default_params(**base)
+
+
 def opdhg_validate(lp) -> int:
     a = _LPArrays(lp)
     return load().opdhg_validate(ctypes.byref(a.struct))
@@ -272,6 +290,15 @@ def opdhg_batch_workspace_bytes(lps: Sequence, params: opdhg_params) -> int:
     _check(load().opdhg_batch_workspace_bytes(len(arrs), structs, ctypes.byref(params),
                                               ctypes.byref(out)))
     return int(out.value)
+
+
+def opdhg_spectral_norm(lp, params: opdhg_params) -> float:
+    """Host-only power-iteration estimate of |A~|_2 after rescaling."""
+    a = _LPArrays(lp)
+    out = c_dbl(0.0)
+    _check(load().opdhg_spectral_norm(ctypes.byref(a.struct), ctypes.byref(params),
+                                      ctypes.byref(out)))
+    return out.value
 
 
 def opdhg_rescale(lp, params: opdhg_params):

@@ -113,6 +113,17 @@ int validate_params(const opdhg_params* p) {
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "lanes must be 0 or a power of two <= 64");
   if (p->workgroups < 0 || p->workgroups > kMaxGrid)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "workgroups must be in [0, 65536]");
+  if (p->step_rule != OPDHG_STEP_ADAPTIVE && p->step_rule != OPDHG_STEP_CONSTANT)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "unknown step rule");
+  if (p->restart_scheme != OPDHG_RESTART_ADAPTIVE && p->restart_scheme != OPDHG_RESTART_NONE)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "unknown restart scheme");
+  if (p->l2_rescale != 0 && p->l2_rescale != 1)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "l2_rescale must be 0 or 1");
+  if (p->power_iters < 1) return fail(OPDHG_ERR_INVALID_ARGUMENT, "power_iters must be >= 1");
+  if (!(p->step_scale > 0.0) || !std::isfinite(p->step_scale))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "step_scale must be finite and > 0");
+  if (!(p->power_tol >= 0.0) || !std::isfinite(p->power_tol))
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "power_tol must be finite and >= 0");
   return OPDHG_OK;
 }
 
@@ -257,8 +268,8 @@ static void build_col_index(const opdhg_lp* lp, ColIndex& C) {
 // Ruiz passes then one Pock-Chambolle pass (Section 2); see the oracle's
 // rescaling for the definition. Maxima do not depend on order and the sums
 // are double-double, so the threads change no bit of the result.
-static void rescale_with(const opdhg_lp* lp, const ColIndex& C, int ruiz_iters, double beta,
-                         std::vector<double>& sval, std::vector<double>& dr,
+static void rescale_with(const opdhg_lp* lp, const ColIndex& C, int ruiz_iters, bool l2,
+                         double beta, std::vector<double>& sval, std::vector<double>& dr,
                          std::vector<double>& dc) {
   const int64_t m = lp->m, n = lp->n;
   dr.assign(m, 1.0);
@@ -283,6 +294,29 @@ static void rescale_with(const opdhg_lp* lp, const ColIndex& C, int ruiz_iters, 
         for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q)
           cmax = std::max(cmax, C.cabs[q] * dr[C.crow[q]] * dc[j]);
         cs[j] = cmax;
+      }
+    });
+    apply();
+  }
+  if (l2) {  // divide by the square roots of the rows' and columns' L2 norms
+    parallel_rows(lp->row_ptr, m, [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        HostDD racc;
+        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+          const double a = std::fabs(lp->val[k]) * dr[i] * dc[lp->col_idx[k]];
+          racc.add(a * a);
+        }
+        rs[i] = std::sqrt(racc.value());
+      }
+    });
+    parallel_rows(C.cstart.data(), n, [&](int64_t j0, int64_t j1) {
+      for (int64_t j = j0; j < j1; ++j) {
+        HostDD cacc;
+        for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q) {
+          const double a = C.cabs[q] * dr[C.crow[q]] * dc[j];
+          cacc.add(a * a);
+        }
+        cs[j] = std::sqrt(cacc.value());
       }
     });
     apply();
@@ -318,11 +352,49 @@ static void rescale_with(const opdhg_lp* lp, const ColIndex& C, int ruiz_iters, 
   });
 }
 
-void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,
+void rescale_host(const opdhg_lp* lp, const opdhg_params* p, std::vector<double>& sval,
                   std::vector<double>& dr, std::vector<double>& dc) {
   ColIndex C;
   build_col_index(lp, C);
-  rescale_with(lp, C, ruiz_iters, beta, sval, dr, dc);
+  rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, dr, dc);
+}
+
+// Power iteration on A~^T A~ for |A~|_2 (the constant step of vanilla PDHG,
+// Section 2): v = 1 / |1|, then per round w = A~^T (A~ v), lam = |w|,
+// v = w / lam; stop after `iters` rounds, when lam moves by at most
+// tol * lam, or when w = 0 (returns 0). For a unit v, lam <= |A~|_2^2.
+static double spectral_norm_with(const opdhg_lp* lp, const ColIndex& C,
+                                 const std::vector<double>& sval, int iters, double tol) {
+  const int64_t m = lp->m, n = lp->n;
+  std::vector<double> v(n, 1.0), av(m), w(n);
+  const double n1 = dd_norm(v.data(), n);
+  for (int64_t j = 0; j < n; ++j) v[j] = v[j] / n1;
+  double lam = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    parallel_rows(lp->row_ptr, m, [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        HostDD acc;
+        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k)
+          acc.add_prod(sval[k], v[lp->col_idx[k]]);
+        av[i] = acc.value();
+      }
+    });
+    parallel_rows(C.cstart.data(), n, [&](int64_t j0, int64_t j1) {
+      for (int64_t j = j0; j < j1; ++j) {
+        HostDD acc;
+        for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q)
+          acc.add_prod(sval[C.cpos[q]], av[C.crow[q]]);
+        w[j] = acc.value();
+      }
+    });
+    const double lam_new = dd_norm(w.data(), n);
+    if (lam_new == 0.0) return 0.0;
+    for (int64_t j = 0; j < n; ++j) v[j] = w[j] / lam_new;
+    const bool done = std::fabs(lam_new - lam) <= tol * lam_new;
+    lam = lam_new;
+    if (done) break;
+  }
+  return std::sqrt(lam);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +500,10 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   std::vector<double> sval;
   ColIndex C;
   build_col_index(lp, C);
-  rescale_with(lp, C, p->ruiz_iters, p->pc_beta, sval, out.dr, out.dc);
+  rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, out.dr, out.dc);
+  double spec = -1.0;
+  if (p->step_rule == OPDHG_STEP_CONSTANT)
+    spec = spectral_norm_with(lp, C, sval, p->power_iters, p->power_tol);
   // A in device order: row i' is original row perm_a[i'], columns relabelled
   out.ci_a.resize(nnz);
   out.va_a.resize(nnz);
@@ -495,7 +570,10 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   const double bsn = dd_norm(out.b.data(), m);
   const double csn = dd_norm(out.c.data(), n);
   out.omega0 = (csn > 1e-10 && bsn > 1e-10) ? csn / bsn : 1.0;
-  out.eta0 = amax > 0.0 ? 1.0 / amax : 1.0;
+  if (p->step_rule == OPDHG_STEP_CONSTANT)
+    out.eta0 = spec > 0.0 ? p->step_scale / spec : p->step_scale;
+  else
+    out.eta0 = amax > 0.0 ? 1.0 / amax : 1.0;
   DevParams& d = out.prm;
   std::memset(&d, 0, sizeof(d));
   d.tol = p->tol;
@@ -521,6 +599,8 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   d.schedule = p->schedule;
   d.eval_every = p->eval_every;
   d.max_retries = p->max_step_retries;
+  d.flags = (p->step_rule == OPDHG_STEP_CONSTANT ? kConstantStep : 0) |
+            (p->restart_scheme == OPDHG_RESTART_NONE ? kNoRestart : 0);
   return OPDHG_OK;
 }
 
@@ -1047,6 +1127,12 @@ void opdhg_default_params(opdhg_params* p) {
   p->tile_nnz = 0;
   p->lanes = 0;
   p->workgroups = 0;
+  p->step_rule = OPDHG_STEP_ADAPTIVE;
+  p->restart_scheme = OPDHG_RESTART_ADAPTIVE;
+  p->l2_rescale = 0;
+  p->power_iters = 200;
+  p->step_scale = 0.9;
+  p->power_tol = 1e-7;
 }
 
 int opdhg_validate(const opdhg_lp* lp) { return validate_lp(lp); }
@@ -1069,10 +1155,23 @@ int opdhg_rescale(const opdhg_lp* lp, const opdhg_params* p, double* scaled_val,
   if (rc) return rc;
   if ((rc = validate_params(p))) return rc;
   std::vector<double> sval, dr, dc;
-  rescale_host(lp, p->ruiz_iters, p->pc_beta, sval, dr, dc);
+  rescale_host(lp, p, sval, dr, dc);
   if (scaled_val) std::copy(sval.begin(), sval.end(), scaled_val);
   if (d_row) std::copy(dr.begin(), dr.end(), d_row);
   if (d_col) std::copy(dc.begin(), dc.end(), d_col);
+  return OPDHG_OK;
+}
+
+int opdhg_spectral_norm(const opdhg_lp* lp, const opdhg_params* p, double* norm_out) {
+  int rc = validate_lp(lp);
+  if (rc) return rc;
+  if ((rc = validate_params(p))) return rc;
+  if (!norm_out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "norm_out is NULL");
+  ColIndex C;
+  build_col_index(lp, C);
+  std::vector<double> sval, dr, dc;
+  rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, dr, dc);
+  *norm_out = spectral_norm_with(lp, C, sval, p->power_iters, p->power_tol);
   return OPDHG_OK;
 }
 

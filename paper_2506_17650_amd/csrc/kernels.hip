@@ -609,13 +609,18 @@ __device__ void decide_step(Ctl& c, const DevParams& p, const LpDev& lp, const d
   const double eta = c.eta, om = c.omega;
   const double movement = 0.5 * om * dx2 + 0.5 * dy2 / om;
   const double eta_bar = inter > 0.0 ? movement / inter : INFINITY;
-  const double first = (1.0 - step_factor(lp, c.ring_base, 0, c.attempts)) * eta_bar;
-  const double second = (1.0 + step_factor(lp, c.ring_base, 1, c.attempts)) * eta;
-  const double eta_next = second < first ? second : first;
+  // the constant step (vanilla PDHG) accepts every attempt and keeps eta
+  const bool constant = (p.flags & kConstantStep) != 0;
+  double eta_next = eta;
+  if (!constant) {
+    const double first = (1.0 - step_factor(lp, c.ring_base, 0, c.attempts)) * eta_bar;
+    const double second = (1.0 + step_factor(lp, c.ring_base, 1, c.attempts)) * eta;
+    eta_next = second < first ? second : first;
+  }
   c.last_eta_bar = eta_bar;
   // a pending learner update was applied by this attempt's kernels
   c.learn_pending = 0;
-  if (eta <= eta_bar) {
+  if (constant || eta <= eta_bar) {
     const bool learn = p.lr > 0.0 && (c.k % p.phi) == 0;
     c.eta_acc = eta;
     c.w += eta;
@@ -704,7 +709,7 @@ __device__ void decide_eval(Ctl* c, const DevParams* p, const double* st, const 
     c->restart_w = c->w;
     return;
   }
-  if (c->t > 0) {
+  if (c->t > 0 && !(p->flags & kNoRestart)) {
     const double om = c->omega;
     const double kc = wkkt(rp2[0], rd2[0], pobj[0] - dobj[0], om);
     const double ka = has_avg ? wkkt(rp2[1], rd2[1], pobj[1] - dobj[1], om) : INFINITY;

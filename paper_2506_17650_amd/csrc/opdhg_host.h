@@ -81,7 +81,7 @@ int64_t grid_cap(const opdhg_params* p);
 void chunking(int64_t n, int64_t cap, int* grid, int* chunk);
 int download_vec(const void* dptr, size_t count, int prec, hipStream_t stream, double* out);
 void fill_result(const Ctl& c, double seconds, opdhg_result* r);
-void rescale_host(const opdhg_lp* lp, int ruiz_iters, double beta, std::vector<double>& sval,
+void rescale_host(const opdhg_lp* lp, const opdhg_params* p, std::vector<double>& sval,
                   std::vector<double>& dr, std::vector<double>& dc);
 std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t cap, int lanes_fixed);
 void unpermute(const double* dev, const std::vector<int32_t>& perm, const double* scale,

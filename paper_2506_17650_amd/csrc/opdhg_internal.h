@@ -47,8 +47,11 @@ struct DevParams {
   int32_t schedule;
   int32_t eval_every;
   int32_t max_retries;
-  int32_t pad;
+  int32_t flags;  // kConstantStep | kNoRestart
 };
+
+constexpr int32_t kConstantStep = 1;  // every attempt accepted, eta unchanged (vanilla PDHG)
+constexpr int32_t kNoRestart = 2;     // evaluations test termination only
 
 // Per-LP control block: the scalar state of the iteration. Written by the
 // decision kernels (step, termination / restart), the first tile of the

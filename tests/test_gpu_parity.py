@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.params import default_params
+from oracle.params import default_params, vanilla_params
 from lpgen import LP, config_lp, tiny_lp
 
 pytestmark = pytest.mark.gpu
@@ -57,7 +57,9 @@ def lib_params(P, op, **kw):
         pc_beta=op.pc_beta, eval_every=op.eval_every, beta_suff=op.beta_suff,
         beta_nec=op.beta_nec, beta_art=op.beta_art, pw_smoothing=op.pw_smoothing,
         step_growth=op.step_growth, step_reduction=op.step_reduction,
-        max_step_retries=op.max_step_retries, **kw)
+        max_step_retries=op.max_step_retries, step_rule=op.step_rule,
+        restart_scheme=op.restart_scheme, l2_rescale=int(op.l2_rescale),
+        step_scale=op.step_scale, power_iters=op.power_iters, power_tol=op.power_tol, **kw)
 
 
 def check_trace(P, lp, op, K=200, **kw):
@@ -241,3 +243,45 @@ def test_fp32_trace_close_to_oracle(P, name, scale, tile, wg):
             for nm, v in errs.items():
                 assert v <= (FP32_ETA_TOL if nm == "eta" else FP32_TRACE_TOL), (k, nm, v)
     _say(f"  worst FP32 relative deviation {worst:.2e}")
+
+
+# ---- vanilla PDHG of Section 4.2: constant steps, no restarts, Ruiz + L2 ----
+
+
+@pytest.mark.parametrize("seed,lr", [(0, 0.0), (1, 1e-1), (2, 1e-2)])
+def test_vanilla_trace_parity(P, seed, lr):
+    _say(f"[vanilla trace] cfg0 seed={seed} lr={lr}")
+    check_trace(P, config_lp("cfg0", seed=seed), vanilla_params(lr))
+
+
+def test_vanilla_cfg1_small_trace_parity(P):
+    lp = config_lp("cfg1", scale=0.05)
+    _say(f"[vanilla trace] cfg1x0.05 m={lp.m} n={lp.n}")
+    check_trace(P, lp, vanilla_params(1e-2), K=150)
+
+
+@pytest.mark.parametrize("lr", [0.0, 1e-1])
+def test_vanilla_final_parity(P, lr):
+    lp = config_lp("cfg0", seed=0)
+    _say(f"[vanilla final] cfg0 lr={lr}")
+    ref, r = check_final(P, lp, vanilla_params(lr, max_iter=20000))
+    assert r.status == 0 and r.restarts == 0 and r.attempts == r.iterations
+
+
+def test_vanilla_iteration_limit(P):
+    lp = config_lp("cfg1", scale=0.02)
+    _say("[vanilla limit]")
+    ref, r = check_final(P, lp, vanilla_params(1e-1, max_iter=300))
+    assert r.status == 1 and r.iterations == 300 and r.restarts == 0
+
+
+def test_vanilla_batch_equals_solo(P):
+    lps = [config_lp("cfg0", seed=s) for s in range(3)] + [config_lp("cfg3", index=i, scale=0.2)
+                                                          for i in range(3)]
+    _say(f"[vanilla batch] {len(lps)} LPs")
+    p = P.opdhg_vanilla_params(1e-2, max_iter=4000)
+    out = P.opdhg_solve_batch(lps, p)
+    for lp, (x, y, r) in zip(lps, out):
+        xs, ys, rs = P.opdhg_solve(lp, p)
+        assert r.status == rs.status and r.iterations == rs.iterations and r.restarts == 0
+        assert np.array_equal(x, xs) and np.array_equal(y, ys)

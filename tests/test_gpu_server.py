@@ -136,3 +136,20 @@ def test_arrivals_while_others_iterate():
         assert srv.stats().replays > 0
     for a, b in zip(got, solo):
         _same(a, b)
+
+
+def test_vanilla_and_adaptive_requests_mixed():
+    # the step rule and restart scheme are per request: vanilla PDHG and
+    # restarted PDHG LPs iterate side by side and each equals its solo solve
+    P = _P()
+    prec = P.OPDHG_FP32
+    lps = [config_lp("cfg0", seed=s) for s in range(4)]
+    plist = [P.opdhg_vanilla_params(lr, precision=prec, max_iter=20000) for lr in (0.0, 1e-1)]
+    plist += [_params(P, prec), _params(P, prec, lr=0.0)]
+    solo = [P.opdhg_solve(lp, q) for lp, q in zip(lps, plist)]
+    with P.Server(64 << 20, precision=prec) as srv:
+        tickets = [srv.submit(lp, q) for lp, q in zip(lps, plist)]
+        got = [srv.wait(t, 120.0) for t in tickets]
+    for a, b in zip(got, solo):
+        _same(a, b)
+    assert got[0][2].restarts == 0 and got[1][2].restarts == 0

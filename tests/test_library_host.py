@@ -133,3 +133,35 @@ def test_binding_refuses_mismatched_lengths():
     lp.c = lp.c[:-1]
     with pytest.raises(ValueError):
         P.opdhg_validate(lp)
+
+
+@pytest.mark.parametrize("name,seed,scale", [("cfg0", 2, 1.0), ("cfg1", 1, 0.05),
+                                             ("cfg4", 1, 0.06)])
+def test_l2_rescale_and_spectral_norm_bitwise_equal_to_oracle(name, seed, scale):
+    # the vanilla PDHG preprocessing (Ruiz, then the L2 pass) and the
+    # power-iteration estimate behind its constant step
+    from oracle.pdhg import spectral_norm_estimate
+    lp = config_lp(name, seed=seed, scale=scale) if name != "cfg4" else \
+        config_lp(name, index=seed, scale=scale)
+    params = P.opdhg_vanilla_params(0.0)
+    sval, dr, dc = P.opdhg_rescale(lp, params)
+    ref = rescale(lp, 10, -1.0, l2=True)
+    assert np.array_equal(dr, ref.Dr) and np.array_equal(dc, ref.Dc)
+    assert np.array_equal(sval, ref.A.data)
+    nu = P.opdhg_spectral_norm(lp, params)
+    assert nu == spectral_norm_estimate(ref, params.power_iters, params.power_tol)
+    # with the Pock-Chambolle pass too (order: Ruiz, L2, Pock-Chambolle)
+    both = P.opdhg_default_params(l2_rescale=1)
+    sval2, dr2, dc2 = P.opdhg_rescale(lp, both)
+    ref2 = rescale(lp, 10, 1.0, l2=True)
+    assert np.array_equal(dr2, ref2.Dr) and np.array_equal(sval2, ref2.A.data)
+
+
+def test_new_parameters_validated():
+    lp = tiny_lp(seed=3)
+    for k, v in [("step_rule", 2), ("restart_scheme", -1), ("l2_rescale", 2),
+                 ("power_iters", 0), ("step_scale", 0.0), ("step_scale", float("inf")),
+                 ("power_tol", -1.0)]:
+        with pytest.raises(P.OpdhgError) as e:
+            P.opdhg_spectral_norm(lp, P.opdhg_default_params(**{k: v}))
+        assert e.value.code == capi.OPDHG_ERR_INVALID_ARGUMENT, k
