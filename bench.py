@@ -25,9 +25,13 @@ reductions, data resident in HBM. The same JSON line carries:
   serving       a Poisson stream of serving requests through the
                 continuous-batching server (FP32), against plain FP64 PDHG
                 served first-in first-out one at a time; p50 / p99 latency
+  variants      (on request: --sections ...,variants) the paper's variant
+                matrix with #Opt, SGM10 / mean iterations, GM / mean time
+                and #Imp / #Wors on a mixed synthetic set, for restarted
+                adaptive PDHG and for vanilla PDHG
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--sections main,fp64,hbm,batch,serving]
+                       [--sections main,fp64,hbm,batch,serving[,variants]]
 """
 
 from __future__ import annotations
@@ -346,6 +350,77 @@ def section_serving(P, args):
     }
 
 
+def section_variants(P, args):
+    """The paper's variant matrix on a seeded synthetic instance set.
+
+    Restarted adaptive PDHG (the cuPDLP.jl-style runs of Section 4.3): lr 0
+    against NoNorm/Norm x Freq/Infreq, the rate chosen per instance from
+    {1e-5, 1e-6, 1e-7}. Vanilla PDHG (Section 4.2): lr 0 against the
+    normalized, every-iteration variant with the rate chosen per instance
+    from {1e-1, 1e-2, 1e-3}, 5e4 iterations at most. Iteration counts come
+    from packed batch solves (bit-identical to solo solves); times are the
+    iteration-loop seconds of solo solves of the baseline and of each
+    variant at its chosen rates. FP64 throughout.
+    """
+    from lpgen import study_lps
+    from paper_2506_17650_amd.metrics import best_over_grid, compare
+    t = time.perf_counter()
+    lps = study_lps(args.study_size)
+    log(f"[bench] variants: {len(lps)} instances, {sum(lp.nnz for lp in lps)} nonzeros "
+        f"(generated in {time.perf_counter() - t:.1f}s)")
+    OPT = P.capi.OPDHG_STATUS_OPTIMAL
+
+    def rec(r, timed):
+        return {"optimal": r.status == OPT, "iterations": int(r.iterations),
+                "seconds": r.solve_seconds if timed else None}
+
+    def batch(params):
+        return [rec(r, False) for _, _, r in P.opdhg_solve_batch(lps, params)]
+
+    def solo(plist):
+        return [rec(P.opdhg_solve(lp, q)[2], True) for lp, q in zip(lps, plist)]
+
+    def study(make, grid, variants, base):
+        t0 = time.perf_counter()
+        methods = {"lr=0": solo([make(0.0, *base)] * len(lps))}
+        fixed, chosen, mismatch = {}, {}, 0
+        for name, kw in variants.items():
+            by_rate = {lr: batch(make(lr, *kw)) for lr in grid}
+            runs, rates = best_over_grid(by_rate)
+            timed = solo([make(r if r is not None else grid[0], *kw) for r in rates])
+            mismatch += sum(a["iterations"] != b["iterations"] for a, b in zip(runs, timed))
+            methods[name] = timed
+            chosen[name] = [r for r in rates]
+            for lr in grid:
+                fixed[f"{name} lr={lr:g}"] = compare(
+                    {"lr=0": methods["lr=0"], "v": by_rate[lr]}, "lr=0")["rows"]["v"]
+        table = compare(methods, "lr=0")
+        for name, row in table["rows"].items():
+            log(f"[bench]   {name:14s} opt {row['optimal']:3d}  SGM10 {row['iter_sgm10']:9.1f}  "
+                f"mean {row['iter_mean']:9.1f}  imp {row['improved']:3d}  wors {row['worsened']:3d}")
+        return {"table": table, "fixed_rate_rows": fixed, "chosen_rates": chosen,
+                "batch_vs_solo_iteration_mismatches": mismatch,
+                "seconds": time.perf_counter() - t0}
+
+    def pdlp(lr, norm, phi):
+        return P.opdhg_default_params(precision=P.OPDHG_FP64, tol=1e-4, lr=lr, normalize=norm,
+                                      phi=phi, max_iter=args.study_max_iter, time_limit_s=600)
+
+    def vanilla(lr, norm, phi):
+        return P.opdhg_vanilla_params(lr, precision=P.OPDHG_FP64, normalize=norm, phi=phi)
+
+    log("[bench] variants: restarted adaptive PDHG, rates {1e-5, 1e-6, 1e-7}")
+    restarted = study(pdlp, (1e-5, 1e-6, 1e-7),
+                      {"NoNorm-Freq": (0, 1), "Norm-Freq": (1, 1), "NoNorm-Infreq": (0, 20),
+                       "Norm-Infreq": (1, 20)}, (1, 20))
+    log("[bench] variants: vanilla PDHG, rates {1e-1, 1e-2, 1e-3}")
+    van = study(vanilla, (1e-1, 1e-2, 1e-3), {"Norm-Freq": (1, 1)}, (1, 1))
+    return {"workload": "mixed synthetic set: cfg0-, cfg1-, cfg3- and cfg4-shaped LPs "
+                        "(stand-in for the paper's benchmark collections)",
+            "instances": len(lps), "dtype": "f64", "max_iter_restarted": args.study_max_iter,
+            "restarted": restarted, "vanilla": van}
+
+
 def oracle_baseline(lp, lr: float, phi: int, seconds: float) -> dict:
     """The FP64 oracle as it stands, single-threaded, on a bounded sample:
     as many accepted iterations of the same LP as fit in ~`seconds`."""
@@ -434,6 +509,8 @@ def run(args) -> dict:
         out["batch"] = section_batch(P, args)
     if "serving" in sections:
         out["serving"] = section_serving(P, args)
+    if "variants" in sections:
+        out["variants"] = section_variants(P, args)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = oracle_baseline(lp, args.lr, args.phi, args.cpu_seconds)
@@ -457,6 +534,8 @@ def main():
     ap.add_argument("--batch-baseline", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--study-size", type=int, default=24)
+    ap.add_argument("--study-max-iter", type=int, default=100000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,

@@ -26,4 +26,5 @@ from .generators import (  # noqa: F401
     block_angular_lp,
     batch_lps,
     serving_requests,
+    study_lps,
 )

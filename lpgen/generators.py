@@ -431,6 +431,31 @@ def batch_lps(count: int = 256, scale: float = 1.0) -> list[LP]:
     return [config_lp("cfg3", index=i, scale=scale) for i in range(count)]
 
 
+def study_lps(count: int = 24) -> list[LP]:
+    """A mixed instance set for the variant study (it stands in for the
+    paper's benchmark collections, which are not used here).
+
+    Instance i comes from family i mod 4, member j = i // 4:
+      0  the random sparse box LP (cfg0 shape), seed 100 + j;
+      1  the badly scaled LP with power-law columns and free variables
+         (cfg1 shape) at 1%..2% of full size, seed 200 + j;
+      2  the batch LP family (cfg3) at 10% size, index j;
+      3  the serving family (cfg4) at 1% size, index j.
+    """
+    out = []
+    for i in range(count):
+        fam, j = i % 4, i // 4
+        if fam == 0:
+            out.append(config_lp("cfg0", seed=100 + j))
+        elif fam == 1:
+            out.append(config_lp("cfg1", seed=200 + j, scale=(0.01, 0.015, 0.02)[j % 3]))
+        elif fam == 2:
+            out.append(config_lp("cfg3", index=j, scale=0.1))
+        else:
+            out.append(config_lp("cfg4", index=j, scale=0.01))
+    return out
+
+
 def serving_requests(count: int, rate_per_s: float, scale: float = 1.0,
                      first_index: int = 0) -> tuple[np.ndarray, Iterator[LP]]:
     """Poisson arrivals (seed (4, 0)) and a lazy stream of cfg4 requests.

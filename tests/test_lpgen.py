@@ -123,3 +123,15 @@ def test_tiny_is_feasible():
     for s in range(10):
         lp = tiny_lp(s, 3, 5)
         assert lp.m == 3 and lp.n == 5 and np.all(np.isfinite(lp.u))
+
+
+def test_study_set_families_and_determinism():
+    from lpgen import study_lps
+    a = study_lps(8)
+    b = study_lps(8)
+    assert [lp.m for lp in a] == [lp.m for lp in b]
+    assert all(np.array_equal(x.val, y.val) for x, y in zip(a, b))
+    # families cycle: cfg0 shape first (200 x 500), then the badly scaled one
+    assert (a[0].m, a[0].n) == (200, 500) and (a[4].m, a[4].n) == (200, 500)
+    assert a[1].n == 2 * a[1].m and np.isinf(a[1].u).any() and np.isinf(a[1].l).any()
+    assert a[2].n == 2 * a[2].m and a[3].n == int(2.5 * a[3].m)
