@@ -46,6 +46,13 @@ second configuration (readings):
   L2 pass     after the Ruiz passes and before the Pock-Chambolle pass:
               rows and columns divided by the square roots of their L2
               norms (0 read as 1).
+
+A preconditioner-weighted step rule is an option (step_norm =
+STEP_NORM_PRECOND): the movement of the adaptive rule measures dx and dy in
+the norms of the preconditioned step, |dx|^2_{T^-1} = sum_j dx_j (dx_j / T_j)
+and |dy|^2_{S^-1} likewise (a coordinate with T_j = 0 or S_i = 0 adds 0: its
+step is 0), with the T and S the attempt used. With T = S = I it is the plain
+rule.
 """
 
 from __future__ import annotations
@@ -61,6 +68,9 @@ STEP_CONSTANT = 1
 
 RESTART_ADAPTIVE = 0
 RESTART_NONE = 1
+
+STEP_NORM_PLAIN = 0
+STEP_NORM_PRECOND = 1
 
 
 @dataclasses.dataclass
@@ -88,6 +98,7 @@ class Params:
     step_scale: float = 0.9  # constant step: eta = step_scale / |A~|_2 estimate
     power_iters: int = 200  # power-iteration limit
     power_tol: float = 1e-7  # stop when the estimate of |A~|_2^2 moves less than this, relatively
+    step_norm: int = STEP_NORM_PLAIN  # movement in plain or preconditioner-weighted norms
 
 
 def default_params(**overrides) -> Params:

@@ -43,7 +43,7 @@ import numpy as np
 from .exact import exact_dot, exact_norm, exact_spmv
 from .kkt import kkt_parts, rel_kkt, weighted_kkt
 from .params import (Params, RESTART_NONE, SCHEDULE_ADAGRAD_DIAG, SCHEDULE_ADAGRAD_NORM,
-                     SCHEDULE_CONSTANT, STEP_CONSTANT)
+                     SCHEDULE_CONSTANT, STEP_CONSTANT, STEP_NORM_PRECOND)
 from .problem import ScaledLP, rescale, validate
 
 OPTIMAL = 0
@@ -376,6 +376,13 @@ def _evaluate(slp: ScaledLP, st: State, p: Params):
     return None
 
 
+def _over(d: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """d / P per coordinate, 0 where P = 0 (a zero preconditioner entry
+    makes that coordinate's step 0)."""
+    pos = P > 0.0
+    return np.where(pos, d / np.where(pos, P, 1.0), 0.0)
+
+
 def _iterate(slp: ScaledLP, st: State, p: Params) -> bool:
     """Algorithm 1 for one iteration; False on a numerical failure."""
     g = slp.c - AT_mul(slp, st.y)
@@ -385,8 +392,12 @@ def _iterate(slp: ScaledLP, st: State, p: Params) -> bool:
         st.attempts += 1
         dx = a["x_new"] - st.x
         dy = a["y_new"] - st.y
-        dx2 = exact_dot(dx, dx)
-        dy2 = exact_dot(dy, dy)
+        if p.step_norm == STEP_NORM_PRECOND:
+            dx2 = exact_dot(dx, _over(dx, st.T))
+            dy2 = exact_dot(dy, _over(dy, st.S))
+        else:
+            dx2 = exact_dot(dx, dx)
+            dy2 = exact_dot(dy, dy)
         inter = abs(exact_dot(dy, a["Ax_new"] - st.Ax))
         if not (math.isfinite(dx2) and math.isfinite(dy2) and math.isfinite(inter)):
             return False

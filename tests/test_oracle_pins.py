@@ -719,3 +719,47 @@ def test_vanilla_tiny_matches_vertex_enumeration():
     r = oracle.solve(lp, oracle.vanilla_params(1e-2, tol=1e-8, max_iter=200000))
     assert r.status == P.OPTIMAL
     assert math.isclose(r.primal_obj, best, rel_tol=1e-6, abs_tol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# preconditioner-weighted step rule
+# ---------------------------------------------------------------------------
+
+
+def test_weighted_step_rule_hand_example():
+    from oracle.params import STEP_NORM_PRECOND, STEP_NORM_PLAIN
+    with open(os.path.join(HERE, "golden", "weighted_step_1var.json")) as f:
+        g = json.load(f)
+    d = g["lp"]
+    lp = _lp_from_dense(d["A"], d["b"], d["sense"], d["c"], d["l"], d["u"])
+    want = {STEP_NORM_PRECOND: (1 - 2 ** -0.3) * 65 / 56,
+            STEP_NORM_PLAIN: (1 - 2 ** -0.3) * 305 / 224}
+    for norm, eta1 in want.items():
+        p = default_params(step_norm=norm)
+        s = rescale(lp, p.ruiz_iters, p.pc_beta)
+        st = P.initial_state(s, p)
+        st.T = np.array(g["start"]["T"])
+        st.S = np.array(g["start"]["S"])
+        r = P.solve_from_state(s, st, p, trace=1, stop_k=1)
+        e = r.trace[-1]
+        assert e.k == 1 and e.attempts == 1
+        assert e.x[0] == 4.0 and e.y[0] == -1.75
+        assert math.isclose(e.eta, eta1, rel_tol=1e-15), (norm, e.eta, eta1)
+
+
+def test_weighted_step_rule_reduces_to_plain_at_identity():
+    # lr = 0 keeps T = S = 1, where dividing by them changes nothing
+    lp = config_lp("cfg0", seed=3)
+    a = oracle.solve(lp, default_params(step_norm=1, max_iter=2000), trace=range(0, 2001, 100))
+    b = oracle.solve(lp, default_params(step_norm=0, max_iter=2000), trace=range(0, 2001, 100))
+    assert a.iterations == b.iterations and a.attempts == b.attempts
+    for ea, eb in zip(a.trace, b.trace):
+        assert np.array_equal(ea.x, eb.x) and ea.eta == eb.eta
+
+
+@pytest.mark.parametrize("lr,phi", [(1e-2, 1), (1e-1, 1)])
+def test_weighted_step_rule_converges(lr, phi):
+    lp = config_lp("cfg0", seed=7)
+    r = oracle.solve(lp, default_params(step_norm=1, lr=lr, phi=phi, max_iter=20000))
+    assert r.status == P.OPTIMAL
+    assert abs(r.primal_obj - lp.planted_obj) <= 2e-4 * (1 + abs(lp.planted_obj))
