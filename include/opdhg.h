@@ -82,6 +82,11 @@ extern "C" {
 #define OPDHG_STEP_CONSTANT 1 /* vanilla PDHG (Sections 2 and 4.2): eta = step_scale / |A~|_2 estimate,
                                  every attempt accepted */
 
+/* ---- norms of the adaptive step rule's movement term ---- */
+#define OPDHG_STEP_NORM_PLAIN 0   /* 0.5 omega |dx|^2 + 0.5 |dy|^2 / omega */
+#define OPDHG_STEP_NORM_PRECOND 1 /* |dx|^2_{T^-1} and |dy|^2_{Sigma^-1}: the norms of the
+                                     preconditioned step (eq. (6)); equal to PLAIN at T = Sigma = I */
+
 /* ---- restart scheme ---- */
 #define OPDHG_RESTART_ADAPTIVE 0 /* PDLP's KKT-based restarts, preconditioners kept (Section 3.2) */
 #define OPDHG_RESTART_NONE 1     /* vanilla PDHG (Section 4.2): evaluations test termination only;
@@ -133,6 +138,7 @@ typedef struct opdhg_params {
   int32_t power_iters;   /* constant step: power-iteration rounds at most (>= 1) */
   double step_scale;     /* constant step: eta = step_scale / estimate of |A~|_2 (> 0) */
   double power_tol;      /* power iteration stops when |A~|_2^2 moves less than this, relatively */
+  int32_t step_norm;     /* OPDHG_STEP_NORM_*: norms of the adaptive rule's movement term */
 } opdhg_params;
 
 typedef struct opdhg_result {
@@ -172,7 +178,8 @@ typedef struct opdhg_server opdhg_server;
  * (diagonal), lr 0, phi 20, normalize 1, floor 0, 10 Ruiz passes, no L2
  * pass, Pock-Chambolle beta 1, eval every 64, 60 step retries, adaptive
  * steps and restarts, restart constants 0.2 / 0.8 / 0.36, smoothing 0.5,
- * step exponents 0.6 / 0.3, automatic tiling; for the constant step:
+ * step exponents 0.6 / 0.3, plain step norms, automatic tiling; for the
+ * constant step:
  * step_scale 0.9, at most 200 power-iteration rounds, power_tol 1e-7.
  *
  * The vanilla PDHG runs of Section 4.2 take OPDHG_STEP_CONSTANT,

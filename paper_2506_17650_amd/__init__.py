@@ -30,4 +30,6 @@ from .capi import (  # noqa: F401
     OPDHG_RESTART_NONE,
     OPDHG_STEP_ADAPTIVE,
     OPDHG_STEP_CONSTANT,
+    OPDHG_STEP_NORM_PLAIN,
+    OPDHG_STEP_NORM_PRECOND,
 )

@@ -124,6 +124,8 @@ int validate_params(const opdhg_params* p) {
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "step_scale must be finite and > 0");
   if (!(p->power_tol >= 0.0) || !std::isfinite(p->power_tol))
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "power_tol must be finite and >= 0");
+  if (p->step_norm != OPDHG_STEP_NORM_PLAIN && p->step_norm != OPDHG_STEP_NORM_PRECOND)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "unknown step norm");
   return OPDHG_OK;
 }
 
@@ -600,7 +602,8 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   d.eval_every = p->eval_every;
   d.max_retries = p->max_step_retries;
   d.flags = (p->step_rule == OPDHG_STEP_CONSTANT ? kConstantStep : 0) |
-            (p->restart_scheme == OPDHG_RESTART_NONE ? kNoRestart : 0);
+            (p->restart_scheme == OPDHG_RESTART_NONE ? kNoRestart : 0) |
+            (p->step_norm == OPDHG_STEP_NORM_PRECOND ? kWeightedStep : 0);
   return OPDHG_OK;
 }
 
@@ -713,6 +716,7 @@ Ctl initial_ctl(const Prepared& P) {
   c.status = kRunning;
   c.need_eval = 1;
   c.learn_now = P.prm.lr > 0.0 ? 1 : 0;
+  c.weighted_step = (P.prm.flags & kWeightedStep) ? 1 : 0;
   return c;
 }
 
@@ -1133,6 +1137,7 @@ void opdhg_default_params(opdhg_params* p) {
   p->power_iters = 200;
   p->step_scale = 0.9;
   p->power_tol = 1e-7;
+  p->step_norm = OPDHG_STEP_NORM_PLAIN;
 }
 
 int opdhg_validate(const opdhg_lp* lp) { return validate_lp(lp); }

@@ -920,7 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
   gptr<const int32_t> rp = nullptr, ci = nullptr;
   gptr<const V> va = nullptr;
   V tau = V(0), etav = V(0);
-  bool learn = false, upd = false;
+  bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
   __shared__ WorkItem s_items[kItemWin];
   run_chunk_spmv<V, 1>(
@@ -944,6 +944,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
         etav = (V)eta;
         // a forced (timing) launch writes only the candidate buffers
         learn = uni((int)(!force && c->learn_now != 0)) != 0;
+        wstep = uni(c->weighted_step) != 0;
         lscale = 1.0;
         upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, true, &lscale))) != 0;
         lscale = uni(lscale);
@@ -997,7 +998,10 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
               stg(xn, (uint32_t)j, xv);
               stg(xsn, (uint32_t)j, q.xs + etav * xv);
               const double dx = (double)xv - (double)q.x;
-              dd_add_prod(p[0], dx, dx);
+              // the movement of the step rule, optionally in the T^-1 norm
+              const double tj = (double)Tj;
+              const double wdx = !wstep ? dx : (tj > 0.0 ? dx / tj : 0.0);
+              dd_add_prod(p[0], dx, wdx);
               dd_add_prod(p[1], (double)g, (double)g);
               if (learn) {
                 const bool ind = (xh >= q.l) && (xh <= q.u);
@@ -1036,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
   gptr<const V> va = nullptr;
   gptr<const V> vecs[1] = {nullptr};
   V sig = V(0), etav = V(0);
-  bool learn = false, upd = false;
+  bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
   __shared__ WorkItem s_items[kItemWin];
   run_chunk_spmv<V, 1>(
@@ -1051,6 +1055,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
         sig = (V)(eta * om);
         etav = (V)eta;
         learn = uni((int)(!force && c->learn_now != 0)) != 0;
+        wstep = uni(c->weighted_step) != 0;
         lscale = 1.0;
         upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, false, &lscale))) != 0;
         lscale = uni(lscale);
@@ -1109,7 +1114,9 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
               stg(Axn, (uint32_t)i, axn);
               stg(ysn, (uint32_t)i, q.ys + etav * yv);
               const double dy = (double)yv - (double)q.y;
-              dd_add_prod(p[0], dy, dy);
+              const double si = (double)Si;
+              const double wdy = !wstep ? dy : (si > 0.0 ? dy / si : 0.0);
+              dd_add_prod(p[0], dy, wdy);
               dd_add_prod(p[1], dy, (double)axn - (double)q.ax);
               const V r = q.b - q.ax;
               dd_add_prod(p[2], (double)r, (double)r);

@@ -47,11 +47,12 @@ struct DevParams {
   int32_t schedule;
   int32_t eval_every;
   int32_t max_retries;
-  int32_t flags;  // kConstantStep | kNoRestart
+  int32_t flags;  // kConstantStep | kNoRestart | kWeightedStep
 };
 
 constexpr int32_t kConstantStep = 1;  // every attempt accepted, eta unchanged (vanilla PDHG)
 constexpr int32_t kNoRestart = 2;     // evaluations test termination only
+constexpr int32_t kWeightedStep = 4;  // step-rule movement in the T^-1 and Sigma^-1 norms
 
 // Per-LP control block: the scalar state of the iteration. Written by the
 // decision kernels (step, termination / restart), the first tile of the
@@ -90,7 +91,8 @@ struct Ctl {
   int32_t which;         // 0 current, 1 average (returned iterate)
   int32_t stop_request;  // host asks for a final evaluation (time limit)
   int32_t learn_now;     // the next attempt is an update iteration (k mod phi == 0)
-  int32_t pad1, pad2, pad3, pad4, pad5;
+  int32_t weighted_step; // movement partials divided by T and Sigma (read with the other fields)
+  int32_t pad2, pad3, pad4, pad5;
 };
 
 // Tile: rows [rb, re) of one CSR side with nonzeros [s, e).

@@ -59,7 +59,8 @@ def lib_params(P, op, **kw):
         step_growth=op.step_growth, step_reduction=op.step_reduction,
         max_step_retries=op.max_step_retries, step_rule=op.step_rule,
         restart_scheme=op.restart_scheme, l2_rescale=int(op.l2_rescale),
-        step_scale=op.step_scale, power_iters=op.power_iters, power_tol=op.power_tol, **kw)
+        step_scale=op.step_scale, power_iters=op.power_iters, power_tol=op.power_tol,
+        step_norm=op.step_norm, **kw)
 
 
 def check_trace(P, lp, op, K=200, **kw):
@@ -285,3 +286,27 @@ def test_vanilla_batch_equals_solo(P):
         xs, ys, rs = P.opdhg_solve(lp, p)
         assert r.status == rs.status and r.iterations == rs.iterations and r.restarts == 0
         assert np.array_equal(x, xs) and np.array_equal(y, ys)
+
+
+# ---- preconditioner-weighted step rule (movement in the T^-1, Sigma^-1 norms) ----
+
+
+@pytest.mark.parametrize("lr,phi,norm", [(1e-2, 1, True), (1e-1, 20, False)])
+def test_weighted_step_trace_parity(P, lr, phi, norm):
+    _say(f"[weighted step trace] cfg0 lr={lr} phi={phi} normalize={norm}")
+    check_trace(P, config_lp("cfg0", seed=4),
+                default_params(step_norm=1, lr=lr, phi=phi, normalize=norm))
+
+
+def test_weighted_step_cfg1_small_trace_and_final(P):
+    lp = config_lp("cfg1", scale=0.05)
+    _say(f"[weighted step] cfg1x0.05 m={lp.m} n={lp.n}")
+    check_trace(P, lp, default_params(step_norm=1, lr=1e-2, phi=5), K=150)
+    small = config_lp("cfg1", scale=0.02)
+    check_final(P, small, default_params(step_norm=1, lr=1e-3, phi=1, max_iter=40000))
+
+
+def test_weighted_step_vanilla_trace_parity(P):
+    # the constant step ignores the movement: weighting must change nothing there
+    _say("[weighted step + vanilla]")
+    check_trace(P, config_lp("cfg0", seed=5), vanilla_params(1e-1, step_norm=1), K=120)

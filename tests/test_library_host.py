@@ -165,3 +165,32 @@ def test_new_parameters_validated():
         with pytest.raises(P.OpdhgError) as e:
             P.opdhg_spectral_norm(lp, P.opdhg_default_params(**{k: v}))
         assert e.value.code == capi.OPDHG_ERR_INVALID_ARGUMENT, k
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror has the C compiler's size and field offsets."""
+    import ctypes
+    import shutil
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [getattr(capi, n) for n in dir(capi)
+               if isinstance(getattr(capi, n), type) and issubclass(getattr(capi, n), ctypes.Structure)
+               and n.startswith("opdhg_")]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "opdhg.h"', "int main(void) {"]
+    want = []
+    for st in structs:
+        lines.append(f'  printf("%zu\\n", sizeof({st.__name__}));')
+        want.append(ctypes.sizeof(st))
+        for f, _ in st._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({st.__name__}, {f}));')
+            want.append(getattr(st, f).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "abi"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert len(structs) >= 6
+    assert got == want
