@@ -360,7 +360,11 @@ def section_variants(P, args):
     from {1e-1, 1e-2, 1e-3}, 5e4 iterations at most. Iteration counts come
     from packed batch solves (bit-identical to solo solves); times are the
     iteration-loop seconds of solo solves of the baseline and of each
-    variant at its chosen rates. FP64 throughout.
+    variant at its chosen rates. FP64 throughout. A third table compares the
+    learning-rate schedules (AdaGrad per coordinate, AdaGrad on the norm,
+    constant) and the preconditioner-weighted step rule on the restarted
+    solver; its fixed-rate rows show each schedule with one rate for every
+    instance (no per-instance tuning).
     """
     from lpgen import study_lps
     from paper_2506_17650_amd.metrics import best_over_grid, compare
@@ -400,7 +404,7 @@ def section_variants(P, args):
                 f"mean {row['iter_mean']:9.1f}  imp {row['improved']:3d}  wors {row['worsened']:3d}")
         return {"table": table, "fixed_rate_rows": fixed, "chosen_rates": chosen,
                 "batch_vs_solo_iteration_mismatches": mismatch,
-                "seconds": time.perf_counter() - t0}
+                "seconds": time.perf_counter() - t0}, methods["lr=0"]
 
     def pdlp(lr, norm, phi):
         return P.opdhg_default_params(precision=P.OPDHG_FP64, tol=1e-4, lr=lr, normalize=norm,
@@ -410,15 +414,32 @@ def section_variants(P, args):
         return P.opdhg_vanilla_params(lr, precision=P.OPDHG_FP64, normalize=norm, phi=phi)
 
     log("[bench] variants: restarted adaptive PDHG, rates {1e-5, 1e-6, 1e-7}")
-    restarted = study(pdlp, (1e-5, 1e-6, 1e-7),
-                      {"NoNorm-Freq": (0, 1), "Norm-Freq": (1, 1), "NoNorm-Infreq": (0, 20),
-                       "Norm-Infreq": (1, 20)}, (1, 20))
+    restarted, _ = study(pdlp, (1e-5, 1e-6, 1e-7),
+                         {"NoNorm-Freq": (0, 1), "Norm-Freq": (1, 1), "NoNorm-Infreq": (0, 20),
+                          "Norm-Infreq": (1, 20)}, (1, 20))
     log("[bench] variants: vanilla PDHG, rates {1e-1, 1e-2, 1e-3}")
-    van = study(vanilla, (1e-1, 1e-2, 1e-3), {"Norm-Freq": (1, 1)}, (1, 1))
+    van, _ = study(vanilla, (1e-1, 1e-2, 1e-3), {"Norm-Freq": (1, 1)}, (1, 1))
+
+    # step-rule norms and learning-rate schedules on the restarted solver
+    # (Norm-Infreq): per-instance rates, and one rate for every instance
+    def sched(lr, schedule, step_norm):
+        return P.opdhg_default_params(precision=P.OPDHG_FP64, tol=1e-4, lr=lr, normalize=1,
+                                      phi=20, schedule=schedule, step_norm=step_norm,
+                                      max_iter=args.study_max_iter, time_limit_s=600)
+
+    log("[bench] variants: schedules and step norms (restarted, Norm-Infreq)")
+    schedules, base_runs = study(sched, (1e-5, 1e-6, 1e-7),
+                                 {"AdaGrad-diag": (0, 0), "AdaGrad-norm": (1, 0),
+                                  "constant": (2, 0), "AdaGrad-diag weighted-step": (0, 1)},
+                                 (0, 0))
+    # the weighted rule alone (lr 0 keeps T = S = I: it must equal the plain rule)
+    weighted_lr0 = solo([sched(0.0, 0, 1)] * len(lps))
+    schedules["weighted_step_lr0"] = compare({"lr=0": base_runs, "w": weighted_lr0},
+                                             "lr=0")["rows"]["w"]
     return {"workload": "mixed synthetic set: cfg0-, cfg1-, cfg3- and cfg4-shaped LPs "
                         "(stand-in for the paper's benchmark collections)",
             "instances": len(lps), "dtype": "f64", "max_iter_restarted": args.study_max_iter,
-            "restarted": restarted, "vanilla": van}
+            "restarted": restarted, "vanilla": van, "schedules": schedules}
 
 
 def oracle_baseline(lp, lr: float, phi: int, seconds: float) -> dict:
