@@ -87,6 +87,11 @@ extern "C" {
 #define OPDHG_STEP_NORM_PRECOND 1 /* |dx|^2_{T^-1} and |dy|^2_{Sigma^-1}: the norms of the
                                      preconditioned step (eq. (6)); equal to PLAIN at T = Sigma = I */
 
+/* ---- windowed sparse products (FP32) ---- */
+#define OPDHG_WINDOWS_AUTO 0   /* a side whose rows give at least 128 windowed chunks uses them */
+#define OPDHG_WINDOWS_OFF 1    /* every row in tiles that gather from global memory */
+#define OPDHG_WINDOWS_ALWAYS 2 /* every windowable chunk, however few (small LPs, checks) */
+
 /* ---- restart scheme ---- */
 #define OPDHG_RESTART_ADAPTIVE 0 /* PDLP's KKT-based restarts, preconditioners kept (Section 3.2) */
 #define OPDHG_RESTART_NONE 1     /* vanilla PDHG (Section 4.2): evaluations test termination only;
@@ -139,6 +144,9 @@ typedef struct opdhg_params {
   double step_scale;     /* constant step: eta = step_scale / estimate of |A~|_2 (> 0) */
   double power_tol;      /* power iteration stops when |A~|_2^2 moves less than this, relatively */
   int32_t step_norm;     /* OPDHG_STEP_NORM_*: norms of the adaptive rule's movement term */
+  int32_t windows;       /* OPDHG_WINDOWS_*: FP32 only; FP64 and the server never use windows */
+  int32_t window_buckets; /* LDS window per pass in buckets of 1024 entries, 1..26; 0: 26 */
+  int32_t window_rows;   /* rows per windowed chunk, 1..8192; 0: picked from the side's size */
 } opdhg_params;
 
 typedef struct opdhg_result {
@@ -178,8 +186,8 @@ typedef struct opdhg_server opdhg_server;
  * (diagonal), lr 0, phi 20, normalize 1, floor 0, 10 Ruiz passes, no L2
  * pass, Pock-Chambolle beta 1, eval every 64, 60 step retries, adaptive
  * steps and restarts, restart constants 0.2 / 0.8 / 0.36, smoothing 0.5,
- * step exponents 0.6 / 0.3, plain step norms, automatic tiling; for the
- * constant step:
+ * step exponents 0.6 / 0.3, plain step norms, automatic tiling and
+ * windows; for the constant step:
  * step_scale 0.9, at most 200 power-iteration rounds, power_tol 1e-7.
  *
  * The vanilla PDHG runs of Section 4.2 take OPDHG_STEP_CONSTANT,

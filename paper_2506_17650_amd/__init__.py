@@ -32,4 +32,7 @@ from .capi import (  # noqa: F401
     OPDHG_STEP_CONSTANT,
     OPDHG_STEP_NORM_PLAIN,
     OPDHG_STEP_NORM_PRECOND,
+    OPDHG_WINDOWS_AUTO,
+    OPDHG_WINDOWS_OFF,
+    OPDHG_WINDOWS_ALWAYS,
 )

@@ -37,18 +37,18 @@ constexpr Candidate kCandidates[] = {
 void retile(Prepared& P, int64_t cap, int lanes) {
   P.tiles_a = build_tiles(P.rp_a.data(), P.m, cap, lanes);
   P.tiles_t = build_tiles(P.rp_t.data(), P.n, cap, lanes);
+  step_tiles(P, cap, lanes);  // windowed chunks do not depend on the tiling
 }
 
 // Workspace bytes of the set under one candidate (tiles already built).
 size_t set_bytes(const std::vector<Prepared>& P, int prec, int64_t wg_cap) {
   size_t total = 0;
-  int64_t nwt = 0, nwa = 0;
+  std::vector<const Prepared*> preps;
   for (const Prepared& q : P) {
-    total += slot_layout(q.m, q.n, q.nnz, q.tiles_t.size(), q.tiles_a.size(), prec).total;
-    nwt += q.tiles_t.size();
-    nwa += q.tiles_a.size();
+    total += slot_layout(q, prec).total;
+    preps.push_back(&q);
   }
-  return total + tables_bytes((int64_t)P.size(), nwt, nwa, wg_cap);
+  return total + tables_bytes(preps, wg_cap);
 }
 
 // Prepares every LP with parameters that keep it running while timed.
@@ -89,8 +89,7 @@ int time_candidate(std::vector<Prepared>& P, int prec, const Candidate& cand, ui
   std::vector<uint8_t> img, staging;
   size_t off = 0;
   for (int i = 0; i < count; ++i) {
-    const SlotLayout L =
-        slot_layout(P[i].m, P[i].n, P[i].nnz, P[i].tiles_t.size(), P[i].tiles_a.size(), prec);
+    const SlotLayout L = slot_layout(P[i], prec);
     if ((rc = upload_slot(ws + off, L, P[i], prec, grp.stream, img))) break;
     lpd[i] = slot_pointers(ws + off, L, P[i]);
     preps[i] = &P[i];

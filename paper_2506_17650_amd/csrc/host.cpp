@@ -126,6 +126,12 @@ int validate_params(const opdhg_params* p) {
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "power_tol must be finite and >= 0");
   if (p->step_norm != OPDHG_STEP_NORM_PLAIN && p->step_norm != OPDHG_STEP_NORM_PRECOND)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "unknown step norm");
+  if (p->windows < OPDHG_WINDOWS_AUTO || p->windows > OPDHG_WINDOWS_ALWAYS)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "windows must be OPDHG_WINDOWS_AUTO, _OFF or _ALWAYS");
+  if (p->window_buckets < 0 || p->window_buckets > kWinBuckets)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_buckets must be in [0, 26]");
+  if (p->window_rows < 0 || p->window_rows > kWinRows)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_rows must be in [0, 8192]");
   return OPDHG_OK;
 }
 
@@ -470,6 +476,182 @@ std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t cap, int 
 }
 
 // ---------------------------------------------------------------------------
+// windowed chunks (FP32 step kernels)
+//
+// Rows [lo, hi) of one side are cut into chunks of `chunk_rows` rows. A
+// chunk is windowed when the vector entries its nonzeros gather lie in a few
+// runs of 1024-entry buckets: the runs are packed into at most kWinMaxPass
+// passes of `per_pass` buckets, and the staged entries (4 bytes each) must
+// cost at most half the chunk's matrix bytes (8 per nonzero), so the window
+// copies stay small against the stream of the matrix. Other chunks stay
+// in tiles.
+// ---------------------------------------------------------------------------
+
+constexpr int64_t kWinMinNnz = 8192;  // smaller chunks are not worth a workgroup of kWinBlock
+
+static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+                         int64_t ncols, int64_t lo, int64_t hi, int64_t chunk_rows, int per_pass,
+                         WinPlan& W) {
+  if (hi <= lo || ncols <= 0) return;
+  const int64_t nb = (ncols + kWinBucket - 1) / kWinBucket;
+  const int64_t max_buckets = (int64_t)per_pass * kWinMaxPass;
+  std::vector<int32_t> stamp(nb, -1), rstamp(nb, -1), bpass(nb, -1), boff(nb, 0);
+  std::vector<int64_t> touched;
+  int32_t id = 0;
+  for (int64_t a = lo, b = lo; a < hi; a = b, ++id) {
+    // grow the chunk row by row. It ends at chunk_rows rows, before a row
+    // that would need more than kWinMaxPass passes, or (past a quarter of
+    // chunk_rows) before a row most of whose buckets are new: a new block
+    // of columns begins there, and a chunk that crossed into it would stage
+    // both blocks.
+    touched.clear();
+    for (b = a; b < hi && b - a < chunk_rows; ++b) {
+      int64_t row_b = 0, row_new = 0;
+      for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
+        const int64_t bk = ci[k] / kWinBucket;
+        if (rstamp[bk] == (int32_t)b) continue;
+        rstamp[bk] = (int32_t)b;
+        ++row_b;
+        if (stamp[bk] != id) ++row_new;
+      }
+      if (b > a && ((int64_t)touched.size() + row_new > max_buckets ||
+                    (4 * (b - a) >= chunk_rows && 2 * row_new > row_b)))
+        break;
+      for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
+        const int64_t bk = ci[k] / kWinBucket;
+        if (stamp[bk] != id) {
+          stamp[bk] = id;
+          touched.push_back(bk);
+        }
+      }
+    }
+    const int64_t nz = (int64_t)rp[b] - rp[a];
+    if (nz < kWinMinNnz) continue;
+    const int64_t nbk = (int64_t)touched.size();
+    if ((nbk + per_pass - 1) / per_pass > kWinMaxPass) continue;
+    if (nbk * kWinBucket * 4 > nz * 4) continue;  // staged bytes <= half the matrix bytes
+    std::sort(touched.begin(), touched.end());
+    // buckets to passes in order; runs of consecutive buckets become one range
+    const int32_t pass0 = (int32_t)W.passes.size();
+    int npass = 0;
+    for (int64_t q = 0; q < nbk; q += per_pass) {
+      WinPass ps{0, 0, (int32_t)W.ranges.size(), 0};
+      int32_t off = 0;
+      for (int64_t u = q; u < std::min(nbk, q + per_pass); ++u) {
+        const int64_t bk = touched[u];
+        const int32_t src = (int32_t)(bk * kWinBucket);
+        const int32_t len = (int32_t)std::min<int64_t>(kWinBucket, ncols - src);
+        if (ps.nrange > 0 && u > q && touched[u - 1] == bk - 1) {
+          W.ranges.back().len += len;  // extends the previous range
+        } else {
+          W.ranges.push_back(WinRange{src, len});
+          ps.nrange++;
+        }
+        bpass[bk] = npass;
+        boff[bk] = off;
+        off += len;
+      }
+      W.passes.push_back(ps);
+      ++npass;
+    }
+    // entries of each pass, rows in order; padded to whole kWinNpt groups
+    for (int q = 0; q < npass; ++q) {
+      WinPass& ps = W.passes[pass0 + q];
+      ps.e0 = (int32_t)W.col.size();
+      uint16_t last_col = 0, last_row = 0;
+      for (int64_t r = a; r < b; ++r)
+        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+          const int64_t bk = ci[k] / kWinBucket;
+          if (bpass[bk] != q) continue;
+          last_col = (uint16_t)(boff[bk] + (ci[k] - bk * kWinBucket));
+          last_row = (uint16_t)(r - a);
+          W.col.push_back(last_col);
+          W.row.push_back(last_row);
+          W.src.push_back(k);
+        }
+      while ((W.col.size() - ps.e0) % kWinNpt) {
+        W.col.push_back(last_col);
+        W.row.push_back(last_row);
+        W.src.push_back(-1);
+      }
+      ps.e1 = (int32_t)W.col.size();
+    }
+    W.r0.push_back((int32_t)a);
+    W.r1.push_back((int32_t)b);
+    W.pass0.push_back(pass0);
+    W.npass.push_back(npass);
+  }
+}
+
+// Every index a windowed kernel derives from the plan stays in its
+// buffers: LDS columns inside their pass's staged length, chunk rows below
+// kWinRows, entry groups whole, staged ranges inside the vector.
+static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
+  for (size_t c = 0; c < W.chunks(); ++c) {
+    const int64_t nrow = (int64_t)W.r1[c] - W.r0[c];
+    if (W.r0[c] < 0 || W.r1[c] > rows || nrow <= 0 || nrow > kWinRows) return false;
+    if (W.npass[c] < 1 || W.npass[c] > kWinMaxPass) return false;
+    for (int32_t q = W.pass0[c]; q < W.pass0[c] + W.npass[c]; ++q) {
+      if (q < 0 || (size_t)q >= W.passes.size()) return false;
+      const WinPass& ps = W.passes[q];
+      if (ps.e0 % kWinNpt || ps.e1 % kWinNpt || ps.e1 <= ps.e0) return false;
+      if ((size_t)ps.e1 > W.col.size() || ps.range0 < 0 || ps.nrange < 1 ||
+          (size_t)(ps.range0 + ps.nrange) > W.ranges.size())
+        return false;
+      int64_t len = 0;
+      for (int32_t g = ps.range0; g < ps.range0 + ps.nrange; ++g) {
+        const WinRange& rg = W.ranges[g];
+        if (rg.src < 0 || rg.len <= 0 || (int64_t)rg.src + rg.len > ncols) return false;
+        len += rg.len;
+      }
+      if (len > kWinCap) return false;
+      for (int32_t e = ps.e0; e < ps.e1; ++e)
+        if (W.col[e] >= len || W.row[e] >= nrow) return false;
+    }
+  }
+  return W.col.size() == W.row.size() && W.col.size() == W.src.size();
+}
+
+// Tiles over the rows of a side that no windowed chunk takes.
+static std::vector<Tile> tiles_outside(const std::vector<int32_t>& rp, int64_t rows,
+                                       const WinPlan& W, int64_t cap, int lanes) {
+  std::vector<Tile> out;
+  auto add = [&](int64_t a, int64_t b) {
+    if (b <= a) return;
+    for (Tile t : build_tiles(rp.data() + a, b - a, cap, lanes)) {
+      t.rb += (int32_t)a;
+      t.re += (int32_t)a;
+      out.push_back(t);
+    }
+  };
+  int64_t cur = 0;
+  for (size_t c = 0; c < W.chunks(); ++c) {
+    add(cur, W.r0[c]);
+    cur = W.r1[c];
+  }
+  add(cur, rows);
+  return out;
+}
+
+void step_tiles(Prepared& P, int64_t cap, int lanes) {
+  P.stiles_t = P.win_t.chunks() ? tiles_outside(P.rp_t, P.n, P.win_t, cap, lanes) : P.tiles_t;
+  P.stiles_a = P.win_a.chunks() ? tiles_outside(P.rp_a, P.m, P.win_a, cap, lanes) : P.tiles_a;
+}
+
+// Chunk rows of a windowed side: the parameter, or the side's windowable
+// rows spread evenly over whole rounds of kWinRound chunks (one chunk per
+// compute unit at a time, so no round is left half empty), at least 1024.
+constexpr int64_t kWinRound = 256;
+constexpr int64_t kWinMinChunks = 128;  // fewer chunks than this leave most CUs idle
+
+static int64_t window_chunk_rows(const opdhg_params* p, int64_t rows) {
+  if (p->window_rows > 0) return p->window_rows;
+  const int64_t rounds = std::max<int64_t>(1, (rows + kWinRound * kWinRows - 1) / (kWinRound * kWinRows));
+  const int64_t per = (rows + rounds * kWinRound - 1) / (rounds * kWinRound);
+  return std::min<int64_t>(kWinRows, std::max<int64_t>(1024, per));
+}
+
+// ---------------------------------------------------------------------------
 // preparation: everything the device needs, computed on the host in FP64
 // ---------------------------------------------------------------------------
 
@@ -482,11 +664,8 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   std::vector<int64_t> len_a(m), len_t(n, 0);
   for (int64_t i = 0; i < m; ++i) len_a[i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
   for (int64_t k = 0; k < nnz; ++k) len_t[lp->col_idx[k]]++;
-  int64_t cend_a[3], cend_t[3];
-  class_order(len_a, out.perm_a, cend_a);
-  class_order(len_t, out.perm_t, cend_t);
-  (void)cend_a;
-  (void)cend_t;
+  class_order(len_a, out.perm_a, out.cend_a);
+  class_order(len_t, out.perm_t, out.cend_t);
   out.rp_a.assign(m + 1, 0);
   for (int64_t i = 0; i < m; ++i) out.rp_a[i + 1] = out.rp_a[i] + (int32_t)len_a[out.perm_a[i]];
   out.rp_t.assign(n + 1, 0);
@@ -494,7 +673,13 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   const int64_t cap = p->tile_nnz > 0 ? std::min<int64_t>(p->tile_nnz, kTileCap) : kTileCap;
   out.tiles_a = build_tiles(out.rp_a.data(), m, cap, p->lanes);
   out.tiles_t = build_tiles(out.rp_t.data(), n, cap, p->lanes);
-  if (structure_only) return OPDHG_OK;
+  // windowed chunks need the device-order column indices, also for sizing
+  const bool windows = p->precision == OPDHG_FP32 && p->windows != OPDHG_WINDOWS_OFF;
+  if (structure_only && !windows) {
+    out.stiles_a = out.tiles_a;
+    out.stiles_t = out.tiles_t;
+    return OPDHG_OK;
+  }
 
   std::vector<int32_t> inv_a(m), inv_t(n);
   for (int64_t i = 0; i < m; ++i) inv_a[out.perm_a[i]] = (int32_t)i;
@@ -502,13 +687,16 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   std::vector<double> sval;
   ColIndex C;
   build_col_index(lp, C);
-  rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, out.dr, out.dc);
   double spec = -1.0;
-  if (p->step_rule == OPDHG_STEP_CONSTANT)
-    spec = spectral_norm_with(lp, C, sval, p->power_iters, p->power_tol);
+  if (!structure_only) {
+    rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, out.dr, out.dc);
+    if (p->step_rule == OPDHG_STEP_CONSTANT)
+      spec = spectral_norm_with(lp, C, sval, p->power_iters, p->power_tol);
+  }
+  const bool vals = !structure_only;
   // A in device order: row i' is original row perm_a[i'], columns relabelled
   out.ci_a.resize(nnz);
-  out.va_a.resize(nnz);
+  if (vals) out.va_a.resize(nnz);
   {
     std::vector<int64_t> dptr(m + 1);  // nonzero offsets in device order, for balancing
     for (int64_t i2 = 0; i2 <= m; ++i2) dptr[i2] = out.rp_a[i2];
@@ -518,7 +706,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
         int64_t pos = out.rp_a[i2];
         for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k, ++pos) {
           out.ci_a[pos] = inv_t[lp->col_idx[k]];
-          out.va_a[pos] = sval[k];
+          if (vals) out.va_a[pos] = sval[k];
         }
       }
     });
@@ -526,7 +714,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   // A^T in device order: row j' is original column perm_t[j']; entries in
   // ascending original row, labelled with device row indices
   out.ci_t.resize(nnz);
-  out.va_t.resize(nnz);
+  if (vals) out.va_t.resize(nnz);
   {
     std::vector<int64_t> dptr(n + 1);
     for (int64_t j2 = 0; j2 <= n; ++j2) dptr[j2] = out.rp_t[j2];
@@ -536,11 +724,30 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
         int64_t pos = out.rp_t[j2];
         for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q, ++pos) {
           out.ci_t[pos] = inv_a[C.crow[q]];
-          out.va_t[pos] = sval[C.cpos[q]];
+          if (vals) out.va_t[pos] = sval[C.cpos[q]];
         }
       }
     });
   }
+  // windowed chunks of both sides (rows of the long class stay in tiles):
+  // A^T rows gather y (m entries), A rows gather x' (n entries)
+  out.win_t = WinPlan();
+  out.win_a = WinPlan();
+  if (windows) {
+    const int per_pass = p->window_buckets > 0 ? p->window_buckets : kWinBuckets;
+    plan_windows(out.rp_t, out.ci_t, m, out.cend_t[0], n,
+                 window_chunk_rows(p, n - out.cend_t[0]), per_pass, out.win_t);
+    plan_windows(out.rp_a, out.ci_a, n, out.cend_a[0], m,
+                 window_chunk_rows(p, m - out.cend_a[0]), per_pass, out.win_a);
+    if (!plan_ok(out.win_t, n, m) || !plan_ok(out.win_a, m, n))
+      return fail(OPDHG_ERR_DEVICE, "internal error: inconsistent window plan");
+    if (p->windows == OPDHG_WINDOWS_AUTO) {
+      if ((int64_t)out.win_t.chunks() < kWinMinChunks) out.win_t = WinPlan();
+      if ((int64_t)out.win_a.chunks() < kWinMinChunks) out.win_a = WinPlan();
+    }
+  }
+  step_tiles(out, cap, p->lanes);
+  if (structure_only) return OPDHG_OK;
   out.b.resize(m);
   out.sense.resize(m);
   out.dr_dev.resize(m);
@@ -624,8 +831,9 @@ void unpermute(const double* dev, const std::vector<int32_t>& perm, const double
 
 static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int64_t ntiles_a,
-                       int prec) {
+SlotLayout slot_layout(const Prepared& P, int prec) {
+  const int64_t m = P.m, n = P.n, nnz = P.nnz;
+  const int64_t ntiles_t = (int64_t)P.tiles_t.size(), ntiles_a = (int64_t)P.tiles_a.size();
   SlotLayout L;
   const size_t V = prec == OPDHG_FP32 ? 4 : 8;
   size_t off = 0;
@@ -638,8 +846,8 @@ SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int6
   L.prm = take(sizeof(DevParams));
   L.tiles_a = take(sizeof(Tile) * ntiles_a);
   L.tiles_t = take(sizeof(Tile) * ntiles_t);
-  L.part_a = take(sizeof(double) * kPartStride * ntiles_a);
-  L.part_t = take(sizeof(double) * kPartStride * ntiles_t);
+  L.part_a = take(sizeof(double) * kPartStride * P.part_stride_a());
+  L.part_t = take(sizeof(double) * kPartStride * P.part_stride_t());
   L.pow_tab = take(sizeof(double) * 2 * kPowTab);
   L.pow_ring = take(sizeof(double) * 2 * kPowRing);
   L.rp_a = take(4 * (m + 1));
@@ -654,6 +862,22 @@ SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int6
   for (int q = 0; q < SlotLayout::kNVecM; ++q) L.vm[q] = take(V * m);
   L.dr = take(8 * m);
   L.sense = take(m);
+  if (P.win_t.chunks()) {
+    const size_t e = P.win_t.col.size();
+    L.wcol_t = take(2 * e);
+    L.wrow_t = take(2 * e);
+    L.wval_t = take(V * e);
+    L.wpass_t = take(sizeof(WinPass) * P.win_t.passes.size());
+    L.wrange_t = take(sizeof(WinRange) * P.win_t.ranges.size());
+  }
+  if (P.win_a.chunks()) {
+    const size_t e = P.win_a.col.size();
+    L.wcol_a = take(2 * e);
+    L.wrow_a = take(2 * e);
+    L.wval_a = take(V * e);
+    L.wpass_a = take(sizeof(WinPass) * P.win_a.passes.size());
+    L.wrange_a = take(sizeof(WinRange) * P.win_a.ranges.size());
+  }
   L.total = off;
   return L;
 }
@@ -665,8 +889,8 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
   std::memset(&d, 0, sizeof(d));
   d.m = (int32_t)P.m;
   d.n = (int32_t)P.n;
-  d.ntiles_t = (int32_t)P.tiles_t.size();
-  d.ntiles_a = (int32_t)P.tiles_a.size();
+  d.ntiles_t = (int32_t)P.part_stride_t();
+  d.ntiles_a = (int32_t)P.part_stride_a();
   d.rp_a = reinterpret_cast<const int32_t*>(base + L.rp_a);
   d.ci_a = reinterpret_cast<const int32_t*>(base + L.ci_a);
   d.va_a = base + L.va_a;
@@ -691,6 +915,20 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
   d.pow_ring = reinterpret_cast<double*>(base + L.pow_ring);
   d.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   d.prm = reinterpret_cast<const DevParams*>(base + L.prm);
+  if (P.win_t.chunks()) {
+    d.wcol_t = reinterpret_cast<const uint16_t*>(base + L.wcol_t);
+    d.wrow_t = reinterpret_cast<const uint16_t*>(base + L.wrow_t);
+    d.wval_t = base + L.wval_t;
+    d.wpass_t = reinterpret_cast<const WinPass*>(base + L.wpass_t);
+    d.wrange_t = reinterpret_cast<const WinRange*>(base + L.wrange_t);
+  }
+  if (P.win_a.chunks()) {
+    d.wcol_a = reinterpret_cast<const uint16_t*>(base + L.wcol_a);
+    d.wrow_a = reinterpret_cast<const uint16_t*>(base + L.wrow_a);
+    d.wval_a = base + L.wval_a;
+    d.wpass_a = reinterpret_cast<const WinPass*>(base + L.wpass_a);
+    d.wrange_a = reinterpret_cast<const WinRange*>(base + L.wrange_a);
+  }
   return d;
 }
 
@@ -736,6 +974,18 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
   std::memcpy(img.data() + L.rp_t, P.rp_t.data(), 4 * P.rp_t.size());
   std::memcpy(img.data() + L.ci_t, P.ci_t.data(), 4 * P.ci_t.size());
   put_vec<V>(img, L.va_t, P.va_t);
+  auto put_win = [&](const WinPlan& W, const std::vector<double>& va, size_t oc, size_t orow,
+                     size_t ov, size_t opass, size_t orange) {
+    if (!W.chunks()) return;
+    std::memcpy(img.data() + oc, W.col.data(), 2 * W.col.size());
+    std::memcpy(img.data() + orow, W.row.data(), 2 * W.row.size());
+    V* dst = reinterpret_cast<V*>(img.data() + ov);
+    for (size_t e = 0; e < W.src.size(); ++e) dst[e] = W.src[e] < 0 ? V(0) : (V)va[W.src[e]];
+    std::memcpy(img.data() + opass, W.passes.data(), sizeof(WinPass) * W.passes.size());
+    std::memcpy(img.data() + orange, W.ranges.data(), sizeof(WinRange) * W.ranges.size());
+  };
+  put_win(P.win_t, P.va_t, L.wcol_t, L.wrow_t, L.wval_t, L.wpass_t, L.wrange_t);
+  put_win(P.win_a, P.va_a, L.wcol_a, L.wrow_a, L.wval_a, L.wpass_a, L.wrange_a);
   // n-vectors: c l u T Hp Gp x0 x1 xs0 xs1 xa
   put_vec<V>(img, L.vn[0], P.c);
   put_vec<V>(img, L.vn[1], P.l);
@@ -774,8 +1024,8 @@ int Group::capture(int attempts_per_replay) {
     rc |= Kernels<V>::eval_decide(cfg, cap_stream);
     rc |= Kernels<V>::apply(cfg, cap_stream);
     for (int a = 0; a < attempts_per_replay; ++a) {
-      rc |= Kernels<V>::primal(cfg, cap_stream, 0);
-      rc |= Kernels<V>::dual(cfg, cap_stream);
+      rc |= launch_side(true, 0, cap_stream);
+      rc |= launch_side(false, 0, cap_stream);
       rc |= Kernels<V>::decide(cfg, cap_stream);
     }
     rc |= launch_board(cfg, cap_stream);
@@ -794,9 +1044,46 @@ int Group::capture(int attempts_per_replay) {
   return OPDHG_OK;
 }
 
+// One side of an attempt (primal: A^T, dual: A): the tile kernel for the
+// rows in tiles, the windowed kernel for the windowed chunks. They take
+// disjoint rows and partial slots, so when both run, the tile kernel goes
+// to side_stream (forked from and joined back into s by events) and the
+// two overlap on the device.
+int Group::launch_side(bool primal, int force, hipStream_t s) {
+  const bool tiles = !cfg.step_fixed || (primal ? cfg.sgrid_t : cfg.sgrid_a) > 0;
+  const bool wins = (primal ? cfg.nwin_t : cfg.nwin_a) > 0;
+  auto tile = [&](hipStream_t q) {
+    if (prec == OPDHG_FP32)
+      return primal ? Kernels<float>::primal(cfg, q, force) : Kernels<float>::dual(cfg, q, force);
+    return primal ? Kernels<double>::primal(cfg, q, force) : Kernels<double>::dual(cfg, q, force);
+  };
+  auto win = [&](hipStream_t q) {
+    if (prec == OPDHG_FP32)
+      return primal ? Kernels<float>::primal_win(cfg, q, force)
+                    : Kernels<float>::dual_win(cfg, q, force);
+    return primal ? Kernels<double>::primal_win(cfg, q, force)
+                  : Kernels<double>::dual_win(cfg, q, force);
+  };
+  if (!(tiles && wins)) return (tiles ? tile(s) : 0) | (wins ? win(s) : 0);
+  if (hipEventRecord(ev_fork, s) != hipSuccess ||
+      hipStreamWaitEvent(side_stream, ev_fork, 0) != hipSuccess)
+    return -1;
+  int rc = tile(side_stream);
+  if (hipEventRecord(ev_join, side_stream) != hipSuccess) return -1;
+  rc |= win(s);
+  if (hipStreamWaitEvent(s, ev_join, 0) != hipSuccess) return -1;
+  return rc;
+}
+
 int Group::init(void* stream_, int prec_) {
   stream = (hipStream_t)stream_;
   prec = prec_;
+  HIP_TRY(hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  // outside any capture: the windowed kernels' LDS attribute
+  if (prec == OPDHG_FP32 && window_kernels_ready())
+    return fail(OPDHG_ERR_DEVICE, device_error_string());
   HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
   return OPDHG_OK;
 }
@@ -806,6 +1093,11 @@ void Group::release() {
   exec = nullptr;
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   cap_stream = nullptr;
+  if (side_stream) (void)hipStreamDestroy(side_stream);
+  side_stream = nullptr;
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  ev_fork = ev_join = nullptr;
 }
 
 int Group::launch_learn_flush() {
@@ -818,15 +1110,10 @@ int Group::launch_init() {
   return Kernels<double>::init_products(cfg, stream);
 }
 
-int Group::launch_primal_forced() {
-  if (prec == OPDHG_FP32) return Kernels<float>::primal(cfg, stream, 1);
-  return Kernels<double>::primal(cfg, stream, 1);
-}
+// A forced launch of a side, as in the captured sequence.
+int Group::launch_primal_forced() { return launch_side(true, 1, stream); }
 
-int Group::launch_dual_forced() {
-  if (prec == OPDHG_FP32) return Kernels<float>::dual(cfg, stream, 1);
-  return Kernels<double>::dual(cfg, stream, 1);
-}
+int Group::launch_dual_forced() { return launch_side(false, 1, stream); }
 
 int Group::replay() {
   HIP_TRY(hipGraphLaunch(exec, stream));
@@ -866,6 +1153,41 @@ int64_t grid_cap(const opdhg_params* p) {
   return p->workgroups > 0 ? p->workgroups : kGridCap;
 }
 
+// Work-list sizes of a fixed set: evaluation tiles, step tiles, windowed chunks.
+struct ListSizes {
+  int64_t nlps = 0, nt = 0, na = 0, st = 0, sa = 0, vt = 0, va = 0;
+  void add(const Prepared& P) {
+    ++nlps;
+    nt += (int64_t)P.tiles_t.size();
+    na += (int64_t)P.tiles_a.size();
+    st += (int64_t)P.stiles_t.size();
+    sa += (int64_t)P.stiles_a.size();
+    vt += (int64_t)P.win_t.chunks();
+    va += (int64_t)P.win_a.chunks();
+  }
+};
+
+static size_t tables_bytes(const ListSizes& z, int64_t cap);
+
+size_t tables_bytes(const std::vector<const Prepared*>& preps, int64_t cap) {
+  ListSizes z;
+  for (const Prepared* P : preps) z.add(*P);
+  return tables_bytes(z, cap);
+}
+
+static size_t tables_bytes(const ListSizes& z, int64_t cap) {
+  const int64_t nt = z.nt, na = z.na, st = z.st, sa = z.sa, vt = z.vt, va = z.va;
+  int g, c;
+  size_t extra = 0;
+  chunking(st, cap, &g, &c);
+  extra += align_up(sizeof(WorkItem) * (size_t)g * c);
+  chunking(sa, cap, &g, &c);
+  extra += align_up(sizeof(WorkItem) * (size_t)g * c);
+  auto padded = [](int64_t v) { return (size_t)(v > 8 ? (v + 7) / 8 * 8 : v); };
+  extra += align_up(sizeof(WinItem) * padded(vt)) + align_up(sizeof(WinItem) * padded(va));
+  return tables_bytes(z.nlps, nt, na, cap) + extra;
+}
+
 size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64_t cap) {
   int gt, ct, ga, ca;
   chunking(nwork_t, cap, &gt, &ct);
@@ -899,11 +1221,13 @@ static std::vector<int64_t> spread_long_tiles(const std::vector<Tile>& tiles) {
 // Items of one side for all LPs, chunked: fills slot / last and each LP's
 // slot count.
 void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps, bool tside,
-                int64_t cap, int* grid, int* chunk, std::vector<WorkItem>& out) {
+                int64_t cap, int* grid, int* chunk, std::vector<WorkItem>& out, bool step) {
   out.clear();
   std::vector<std::pair<int64_t, int64_t>> range(lps.size());
   for (size_t i = 0; i < lps.size(); ++i) {
-    const std::vector<Tile>& tiles = tside ? preps[i]->tiles_t : preps[i]->tiles_a;
+    const Prepared& P = *preps[i];
+    const std::vector<Tile>& tiles =
+        step ? (tside ? P.stiles_t : P.stiles_a) : (tside ? P.tiles_t : P.tiles_a);
     range[i].first = (int64_t)out.size();
     for (int64_t t : spread_long_tiles(tiles)) {
       const Tile& tl = tiles[t];
@@ -923,8 +1247,8 @@ void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& pre
       out[q].last = (q == e - 1 || (q + 1) % C == 0) ? 1 : 0;
     }
     const int32_t nslot = e > s ? (int32_t)((e - 1) / C - first_wg + 1) : 0;
-    if (tside) lps[i].nslot_t = nslot;
-    else lps[i].nslot_a = nslot;
+    if (step) (tside ? lps[i].nslot_st : lps[i].nslot_sa) = nslot;
+    else (tside ? lps[i].nslot_t : lps[i].nslot_a) = nslot;
   }
   const WorkItem pad{nullptr, -1, 0, 0, 0, 0, 0, 1, 0, 0, 0};
   out.resize((size_t)(*grid) * (*chunk), pad);
@@ -937,9 +1261,52 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
                  std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa,
                  size_t capacity, bool fixed_launch) {
   std::vector<LpDev> lps(lps_in);
-  std::vector<WorkItem> wt, wa;
+  std::vector<WorkItem> wt, wa, st, sa;
+  std::vector<WinItem> vt, va;
   side_items(lps, preps, true, cap, &cfg->grid_t, &cfg->chunk_t, wt);
   side_items(lps, preps, false, cap, &cfg->grid_a, &cfg->chunk_a, wa);
+  if (fixed_launch) {
+    // the server's changing set: its step kernels run the evaluation lists
+    // with the device-side chunking (no LP there has windowed chunks)
+    for (size_t i = 0; i < lps.size(); ++i) {
+      if (preps[i]->win_t.chunks() || preps[i]->win_a.chunks())
+        return fail(OPDHG_ERR_INVALID_ARGUMENT, "windowed chunks in a shared launch set");
+      lps[i].nslot_st = lps[i].nslot_t;
+      lps[i].nslot_sa = lps[i].nslot_a;
+    }
+    cfg->sgrid_t = cfg->schunk_t = cfg->sgrid_a = cfg->schunk_a = 0;
+    cfg->step_fixed = 0;
+  } else {
+    side_items(lps, preps, true, cap, &cfg->sgrid_t, &cfg->schunk_t, st, true);
+    side_items(lps, preps, false, cap, &cfg->sgrid_a, &cfg->schunk_a, sa, true);
+    cfg->step_fixed = 1;
+    int64_t nst = 0, nsa = 0;
+    for (const Prepared* P : preps) {
+      nst += (int64_t)P->stiles_t.size();
+      nsa += (int64_t)P->stiles_a.size();
+    }
+    if (nst == 0) cfg->sgrid_t = 0;  // every row windowed: no tile launch
+    if (nsa == 0) cfg->sgrid_a = 0;
+    // windowed chunks take the partial slots after the LP's step tiles
+    auto wins = [&](bool tside, std::vector<WinItem>& out) {
+      for (size_t i = 0; i < lps.size(); ++i) {
+        const WinPlan& W = tside ? preps[i]->win_t : preps[i]->win_a;
+        int32_t& ns = tside ? lps[i].nslot_st : lps[i].nslot_sa;
+        for (size_t c = 0; c < W.chunks(); ++c)
+          out.push_back(WinItem{lps[i].ctl, (int32_t)i, ns + (int32_t)c, W.r0[c], W.r1[c],
+                                W.pass0[c], W.npass[c]});
+        ns += (int32_t)W.chunks();
+      }
+      // a multiple of 8 workgroups (above 8) spreads consecutive chunks of
+      // one LP over one XCD at a time
+      if (out.size() > 8)
+        while (out.size() % 8) out.push_back(WinItem{nullptr, -1, 0, 0, 0, 0, 0});
+    };
+    wins(true, vt);
+    wins(false, va);
+  }
+  cfg->nwin_t = (int)vt.size();
+  cfg->nwin_a = (int)va.size();
   int64_t n_t = 0, n_a = 0;
   for (const Prepared* P : preps) {
     n_t += (int64_t)P->tiles_t.size();
@@ -949,7 +1316,11 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   const size_t o_lps = 0;
   const size_t o_wt = o_lps + align_up(sizeof(LpDev) * nl);
   const size_t o_wa = o_wt + align_up(sizeof(WorkItem) * wt.size());
-  const size_t o_cn = o_wa + align_up(sizeof(WorkItem) * wa.size());
+  const size_t o_st = o_wa + align_up(sizeof(WorkItem) * wa.size());
+  const size_t o_sa = o_st + align_up(sizeof(WorkItem) * st.size());
+  const size_t o_vt = o_sa + align_up(sizeof(WorkItem) * sa.size());
+  const size_t o_va = o_vt + align_up(sizeof(WinItem) * vt.size());
+  const size_t o_cn = o_va + align_up(sizeof(WinItem) * va.size());
   const size_t o_bd = o_cn + align_up(sizeof(Counts));
   const size_t total = o_bd + align_up(sizeof(Ctl) * nl);
   if (capacity && total > capacity)
@@ -959,6 +1330,10 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   if (!lps.empty()) std::memcpy(staging.data() + o_lps, lps.data(), sizeof(LpDev) * lps.size());
   std::memcpy(staging.data() + o_wt, wt.data(), sizeof(WorkItem) * wt.size());
   std::memcpy(staging.data() + o_wa, wa.data(), sizeof(WorkItem) * wa.size());
+  if (!st.empty()) std::memcpy(staging.data() + o_st, st.data(), sizeof(WorkItem) * st.size());
+  if (!sa.empty()) std::memcpy(staging.data() + o_sa, sa.data(), sizeof(WorkItem) * sa.size());
+  if (!vt.empty()) std::memcpy(staging.data() + o_vt, vt.data(), sizeof(WinItem) * vt.size());
+  if (!va.empty()) std::memcpy(staging.data() + o_va, va.data(), sizeof(WinItem) * va.size());
   Counts cn{(int32_t)n_t, (int32_t)n_a, (int32_t)lps.size(), 0,
             cfg->grid_t, cfg->chunk_t, cfg->grid_a, cfg->chunk_a};
   std::memcpy(staging.data() + o_cn, &cn, sizeof(cn));
@@ -967,6 +1342,10 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   cfg->work_t = reinterpret_cast<const WorkItem*>(dst + o_wt);
   cfg->work_a = reinterpret_cast<const WorkItem*>(dst + o_wa);
   cfg->counts = reinterpret_cast<const Counts*>(dst + o_cn);
+  cfg->step_t = fixed_launch ? cfg->work_t : reinterpret_cast<const WorkItem*>(dst + o_st);
+  cfg->step_a = fixed_launch ? cfg->work_a : reinterpret_cast<const WorkItem*>(dst + o_sa);
+  cfg->win_t = reinterpret_cast<const WinItem*>(dst + o_vt);
+  cfg->win_a = reinterpret_cast<const WinItem*>(dst + o_va);
   cfg->board = reinterpret_cast<Ctl*>(dst + o_bd);
   if (!fixed_launch) {
     cfg->launch_t = cfg->grid_t;
@@ -1138,6 +1517,9 @@ void opdhg_default_params(opdhg_params* p) {
   p->step_scale = 0.9;
   p->power_tol = 1e-7;
   p->step_norm = OPDHG_STEP_NORM_PLAIN;
+  p->windows = OPDHG_WINDOWS_AUTO;
+  p->window_buckets = 0;
+  p->window_rows = 0;
 }
 
 int opdhg_validate(const opdhg_lp* lp) { return validate_lp(lp); }
@@ -1149,8 +1531,8 @@ int opdhg_workspace_bytes(const opdhg_lp* lp, const opdhg_params* p, size_t* byt
   if (!bytes) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bytes is NULL");
   Prepared P;
   prepare(lp, p, P, true);
-  SlotLayout L = slot_layout(P.m, P.n, P.nnz, P.tiles_t.size(), P.tiles_a.size(), p->precision);
-  *bytes = L.total + tables_bytes(1, P.tiles_t.size(), P.tiles_a.size(), grid_cap(p));
+  SlotLayout L = slot_layout(P, p->precision);
+  *bytes = L.total + tables_bytes({&P}, grid_cap(p));
   return OPDHG_OK;
 }
 
@@ -1191,9 +1573,9 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
   auto s = std::make_unique<opdhg_session>();
   SessionImpl& S = s->impl;
   if ((rc = prepare(lp, p, S.P, false))) return rc;
-  S.L = slot_layout(S.P.m, S.P.n, S.P.nnz, S.P.tiles_t.size(), S.P.tiles_a.size(), p->precision);
+  S.L = slot_layout(S.P, p->precision);
   const size_t need =
-      S.L.total + tables_bytes(1, S.P.tiles_t.size(), S.P.tiles_a.size(), grid_cap(p));
+      S.L.total + tables_bytes({&S.P}, grid_cap(p));
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL,
                 "workspace needs " + std::to_string(need) + " bytes");
@@ -1371,16 +1753,15 @@ int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_para
   int rc = validate_params(p);
   if (rc) return rc;
   size_t total = 0;
-  int64_t nwt = 0, nwa = 0;
+  ListSizes z;
   for (int i = 0; i < count; ++i) {
     if ((rc = validate_lp(&lps[i]))) return rc;
     Prepared P;
     prepare(&lps[i], p, P, true);
-    total += slot_layout(P.m, P.n, P.nnz, P.tiles_t.size(), P.tiles_a.size(), p->precision).total;
-    nwt += P.tiles_t.size();
-    nwa += P.tiles_a.size();
+    total += slot_layout(P, p->precision).total;
+    z.add(P);
   }
-  *bytes = total + tables_bytes(count, nwt, nwa, grid_cap(p));
+  *bytes = total + tables_bytes(z, grid_cap(p));
   return OPDHG_OK;
 }
 
@@ -1417,17 +1798,13 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, voi
   for (auto& t : pool) t.join();
   for (int i = 0; i < count; ++i) {
     if (rcs[i]) return fail(rcs[i], "LP " + std::to_string(i) + ": " + msgs[i]);
-    L[i] = slot_layout(P[i].m, P[i].n, P[i].nnz, P[i].tiles_t.size(), P[i].tiles_a.size(),
-                       p->precision);
+    L[i] = slot_layout(P[i], p->precision);
     offs[i] = off;
     off += L[i].total;
   }
-  int64_t nwt = 0, nwa = 0;
-  for (int i = 0; i < count; ++i) {
-    nwt += P[i].tiles_t.size();
-    nwa += P[i].tiles_a.size();
-  }
-  const size_t need = off + tables_bytes(count, nwt, nwa, grid_cap(p));
+  ListSizes z;
+  for (int i = 0; i < count; ++i) z.add(P[i]);
+  const size_t need = off + tables_bytes(z, grid_cap(p));
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(need) + " bytes");
   uint8_t* ws = static_cast<uint8_t*>(d_workspace);

@@ -55,6 +55,9 @@
 
 #include <math.h>
 
+#include <mutex>
+#include <type_traits>
+
 #include "opdhg_internal.h"
 
 namespace opdhg {
@@ -156,9 +159,9 @@ __device__ __forceinline__ DD dd_shfl_xor(const DD& a, int off) {
   return DD{__shfl_xor(a.hi, off, 64), __shfl_xor(a.lo, off, 64)};
 }
 
-// Merge NV double-doubles over the workgroup in a fixed tree; thread 0
-// gets the totals. s_red holds 4 * NV DD.
-template <int NV>
+// Merge NV double-doubles over the workgroup (NW waves) in a fixed tree;
+// thread 0 gets the totals. s_red holds NW * NV DD.
+template <int NV, int NW = kBlock / 64>
 __device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -174,9 +177,12 @@ __device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
   lds_barrier();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-      v[q] = dd_merge(dd_merge(dd_merge(s_red[q], s_red[NV + q]), s_red[2 * NV + q]),
-                      s_red[3 * NV + q]);
+    for (int q = 0; q < NV; ++q) {
+      DD t = s_red[q];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) t = dd_merge(t, s_red[w * NV + q]);
+      v[q] = t;
+    }
   }
   lds_barrier();
 }
@@ -900,14 +906,14 @@ struct PrimalPre {
   V c, x, T, l, u, xs, H, G;
 };
 
+// Context of the primal step for one LP (A^T y, eq. (6)'s primal update and
+// projection, the running sum, the primal online gradient of eq. (7) and
+// the deferred learner update of T), loaded once per LP by begin(). Every
+// value begin() reads is the same in all threads: it is moved to scalar
+// registers (uni) so the branches on it are uniform and the pointers stay
+// out of vector registers.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
-  __shared__ SpmvShared<V, 1> sh;
-  __shared__ DD s_red[4 * 3];
-  const double nodiv[1] = {0.0};
-  DD p[3];
-  dd_reset(p);
-  // per-LP context, loaded when the LP changes
+struct PrimalStep {
   const LpDev* lp = nullptr;
   Ctl* c = nullptr;
   gptr<const V> cc = nullptr, lo = nullptr, hi = nullptr, x = nullptr, xs = nullptr;
@@ -916,112 +922,250 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
   // attempts, else a vector the row reads anyway (values unused), so the
   // loads need no branch
   gptr<const V> Hsrc = nullptr, Gsrc = nullptr;
-  gptr<const V> vecs[1] = {nullptr};
+  gptr<const V> vecs[1] = {nullptr};  // the gathered vector, y
   gptr<const int32_t> rp = nullptr, ci = nullptr;
   gptr<const V> va = nullptr;
   V tau = V(0), etav = V(0);
   bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
-  __shared__ WorkItem s_items[kItemWin];
-  run_chunk_spmv<V, 1>(
-      cfg.work_t, side_chunks(cfg.counts, true), s_items, rp, ci, va, vecs, nodiv,
-      [&](const WorkItem& it) {
-        c = it.ctl;
-        // the restart / final copy of the evaluation step ran before this
-        // launch; the LP's first chunk (partial slot 0) clears the flags
-        if (it.slot == 0 && threadIdx.x == 0 && (c->restart_pending | c->finalize_avg)) {
-          c->restart_pending = 0;
-          c->finalize_avg = 0;
-        }
-        // every value read here is the same in all threads: moved to scalar
-        // registers (uni) so the branches on them are uniform and the
-        // pointers stay out of vector registers
-        if (!uni((int)(force || attempt_guard(c)))) return false;
-        lp = &cfg.lps[it.lp];
-        const int cur = uni(c->cur), nxt = cur ^ 1;
-        const double eta = uni(c->eta), om = uni(c->omega);
-        tau = (V)(eta / om);
-        etav = (V)eta;
-        // a forced (timing) launch writes only the candidate buffers
-        learn = uni((int)(!force && c->learn_now != 0)) != 0;
-        wstep = uni(c->weighted_step) != 0;
-        lscale = 1.0;
-        upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, true, &lscale))) != 0;
-        lscale = uni(lscale);
-        hnorm = uni(c->hp_norm);
-        cc = gp(static_cast<const V*>(lp->c));
-        lo = gp(static_cast<const V*>(lp->l));
-        hi = gp(static_cast<const V*>(lp->u));
-        T = gp(static_cast<V*>(lp->T));
-        Hp = gp(static_cast<V*>(lp->Hp));
-        x = gp(static_cast<const V*>(lp->x[cur]));
-        xs = gp(static_cast<const V*>(lp->xs[cur]));
-        xn = gp(static_cast<V*>(lp->x[nxt]));
-        xsn = gp(static_cast<V*>(lp->xs[nxt]));
-        Gp = gp(static_cast<V*>(lp->Gp));
-        Hsrc = upd ? Hp : x;
-        Gsrc = upd ? Gp : x;
-        vecs[0] = gp(static_cast<const V*>(lp->y[cur]));
-        rp = gp(lp->rp_t);
-        ci = gp(lp->ci_t);
-        va = gp(static_cast<const V*>(lp->va_t));
-        cc = uni(cc), lo = uni(lo), hi = uni(hi), x = uni(x), xs = uni(xs);
-        T = uni(T), Hp = uni(Hp), xn = uni(xn), xsn = uni(xsn), Gp = uni(Gp);
-        Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
-        rp = uni(rp), ci = uni(ci), va = uni(va);
-        tau = uni(tau), etav = uni(etav);
-        return true;
-      },
-            [&](int j) {
-              PrimalPre<V> q;
-              q.c = ldg(cc, (uint32_t)j);
-              q.x = ldg(x, (uint32_t)j);
-              q.T = ldg(T, (uint32_t)j);
-              q.l = ldg(lo, (uint32_t)j);
-              q.u = ldg(hi, (uint32_t)j);
-              q.xs = ldg(xs, (uint32_t)j);
-              q.H = ldg(Hsrc, (uint32_t)j);
-              q.G = ldg(Gsrc, (uint32_t)j);
-              return q;
-            },
-            [&](int j, V (&acc)[1], PrimalPre<V>& q) {
-              V Tj = q.T;
-              if (upd) {
-                V h = q.H;
-                Tj = learn_elem<V>(Tj, h, q.G, lscale, lp->prm, hnorm);
-                stg(T, (uint32_t)j, Tj);
-                stg(Hp, (uint32_t)j, h);
-              }
-              const V g = q.c - acc[0];
-              const V xh = q.x - (tau * Tj) * g;
-              const V xv = clampv(xh, q.l, q.u);
-              stg(xn, (uint32_t)j, xv);
-              stg(xsn, (uint32_t)j, q.xs + etav * xv);
-              const double dx = (double)xv - (double)q.x;
-              // the movement of the step rule, optionally in the T^-1 norm
-              const double tj = (double)Tj;
-              const double wdx = !wstep ? dx : (tj > 0.0 ? dx / tj : 0.0);
-              dd_add_prod(p[0], dx, wdx);
-              dd_add_prod(p[1], (double)g, (double)g);
-              if (learn) {
-                const bool ind = (xh >= q.l) && (xh <= q.u);
-                const V gp_ = ind ? -((tau * g) * g) : V(0);
-                stg(Gp, (uint32_t)j, gp_);
-                dd_add_prod(p[2], (double)gp_, (double)gp_);
-              }
-            },
-      [&](const WorkItem& it, bool run) {
-        if (run) flush_partials<3>(p, s_red, lp->part_t, lp->ntiles_t, it.slot);
-        else dd_reset(p);
-      },
-      sh);
-}
+
+  __device__ __forceinline__ bool begin(const LaunchCfg& cfg, Ctl* ctl, int lpi, int slot,
+                                        int force) {
+    c = ctl;
+    // the restart / final copy of the evaluation step ran before this
+    // launch; the LP's first chunk (partial slot 0) clears the flags
+    if (slot == 0 && threadIdx.x == 0 && (c->restart_pending | c->finalize_avg)) {
+      c->restart_pending = 0;
+      c->finalize_avg = 0;
+    }
+    if (!uni((int)(force || attempt_guard(c)))) return false;
+    lp = &cfg.lps[lpi];
+    const int cur = uni(c->cur), nxt = cur ^ 1;
+    const double eta = uni(c->eta), om = uni(c->omega);
+    tau = (V)(eta / om);
+    etav = (V)eta;
+    // a forced (timing) launch writes only the candidate buffers
+    learn = uni((int)(!force && c->learn_now != 0)) != 0;
+    wstep = uni(c->weighted_step) != 0;
+    lscale = 1.0;
+    upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, true, &lscale))) != 0;
+    lscale = uni(lscale);
+    hnorm = uni(c->hp_norm);
+    cc = gp(static_cast<const V*>(lp->c));
+    lo = gp(static_cast<const V*>(lp->l));
+    hi = gp(static_cast<const V*>(lp->u));
+    T = gp(static_cast<V*>(lp->T));
+    Hp = gp(static_cast<V*>(lp->Hp));
+    x = gp(static_cast<const V*>(lp->x[cur]));
+    xs = gp(static_cast<const V*>(lp->xs[cur]));
+    xn = gp(static_cast<V*>(lp->x[nxt]));
+    xsn = gp(static_cast<V*>(lp->xs[nxt]));
+    Gp = gp(static_cast<V*>(lp->Gp));
+    Hsrc = upd ? Hp : x;
+    Gsrc = upd ? Gp : x;
+    vecs[0] = gp(static_cast<const V*>(lp->y[cur]));
+    rp = gp(lp->rp_t);
+    ci = gp(lp->ci_t);
+    va = gp(static_cast<const V*>(lp->va_t));
+    cc = uni(cc), lo = uni(lo), hi = uni(hi), x = uni(x), xs = uni(xs);
+    T = uni(T), Hp = uni(Hp), xn = uni(xn), xsn = uni(xsn), Gp = uni(Gp);
+    Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
+    rp = uni(rp), ci = uni(ci), va = uni(va);
+    tau = uni(tau), etav = uni(etav);
+    return true;
+  }
+
+  __device__ __forceinline__ PrimalPre<V> load(int j) const {
+    PrimalPre<V> q;
+    q.c = ldg(cc, (uint32_t)j);
+    q.x = ldg(x, (uint32_t)j);
+    q.T = ldg(T, (uint32_t)j);
+    q.l = ldg(lo, (uint32_t)j);
+    q.u = ldg(hi, (uint32_t)j);
+    q.xs = ldg(xs, (uint32_t)j);
+    q.H = ldg(Hsrc, (uint32_t)j);
+    q.G = ldg(Gsrc, (uint32_t)j);
+    return q;
+  }
+
+  // Row j with (A^T y)_j = aty: partials |x'-x|^2 (or its T^-1 norm),
+  // |g|^2, |G^p|^2 into p.
+  __device__ __forceinline__ void finish(int j, V aty, PrimalPre<V>& q, DD (&p)[3]) const {
+    V Tj = q.T;
+    if (upd) {
+      V h = q.H;
+      Tj = learn_elem<V>(Tj, h, q.G, lscale, lp->prm, hnorm);
+      stg(T, (uint32_t)j, Tj);
+      stg(Hp, (uint32_t)j, h);
+    }
+    const V g = q.c - aty;
+    const V xh = q.x - (tau * Tj) * g;
+    const V xv = clampv(xh, q.l, q.u);
+    stg(xn, (uint32_t)j, xv);
+    stg(xsn, (uint32_t)j, q.xs + etav * xv);
+    const double dx = (double)xv - (double)q.x;
+    // the movement of the step rule, optionally in the T^-1 norm
+    const double tj = (double)Tj;
+    const double wdx = !wstep ? dx : (tj > 0.0 ? dx / tj : 0.0);
+    dd_add_prod(p[0], dx, wdx);
+    dd_add_prod(p[1], (double)g, (double)g);
+    if (learn) {
+      const bool ind = (xh >= q.l) && (xh <= q.u);
+      const V gp_ = ind ? -((tau * g) * g) : V(0);
+      stg(Gp, (uint32_t)j, gp_);
+      dd_add_prod(p[2], (double)gp_, (double)gp_);
+    }
+  }
+
+  __device__ __forceinline__ double* part() const { return lp->part_t; }
+  __device__ __forceinline__ int stride() const { return lp->ntiles_t; }
+};
 
 template <typename V>
 struct DualPre {
   V ax, b, y, ys, S, H, G;
   int8_t ineq;
 };
+
+// Context of the dual step for one LP (A x', the extrapolation, eq. (6)'s
+// dual update and sign projection, the running sum, the dual online
+// gradient of eq. (7) and the deferred learner update of Sigma).
+template <typename V>
+struct DualStep {
+  const LpDev* lp = nullptr;
+  const Ctl* c = nullptr;
+  gptr<const V> b = nullptr, y = nullptr, ys = nullptr, Ax = nullptr;
+  gptr<V> S = nullptr, Hd = nullptr, yn = nullptr, ysn = nullptr, Axn = nullptr, Gd = nullptr;
+  gptr<const V> Hsrc = nullptr, Gsrc = nullptr;  // as in PrimalStep
+  gptr<const int8_t> sense = nullptr;
+  gptr<const int32_t> rp = nullptr, ci = nullptr;
+  gptr<const V> va = nullptr;
+  gptr<const V> vecs[1] = {nullptr};  // the gathered vector, x'
+  V sig = V(0), etav = V(0);
+  bool learn = false, upd = false, wstep = false;
+  double lscale = 1.0, hnorm = 0.0;
+
+  __device__ __forceinline__ bool begin(const LaunchCfg& cfg, const Ctl* ctl, int lpi, int,
+                                        int force) {
+    c = ctl;
+    // as in PrimalStep: uniform values in scalar registers
+    if (!uni((int)(force || attempt_guard(c)))) return false;
+    lp = &cfg.lps[lpi];
+    const int cur = uni(c->cur), nxt = cur ^ 1;
+    const double eta = uni(c->eta), om = uni(c->omega);
+    sig = (V)(eta * om);
+    etav = (V)eta;
+    learn = uni((int)(!force && c->learn_now != 0)) != 0;
+    wstep = uni(c->weighted_step) != 0;
+    lscale = 1.0;
+    upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, false, &lscale))) != 0;
+    lscale = uni(lscale);
+    hnorm = uni(c->hd_norm);
+    b = gp(static_cast<const V*>(lp->b));
+    S = gp(static_cast<V*>(lp->S));
+    Hd = gp(static_cast<V*>(lp->Hd));
+    y = gp(static_cast<const V*>(lp->y[cur]));
+    ys = gp(static_cast<const V*>(lp->ys[cur]));
+    Ax = gp(static_cast<const V*>(lp->Ax[cur]));
+    yn = gp(static_cast<V*>(lp->y[nxt]));
+    ysn = gp(static_cast<V*>(lp->ys[nxt]));
+    Axn = gp(static_cast<V*>(lp->Ax[nxt]));
+    Gd = gp(static_cast<V*>(lp->Gd));
+    sense = gp(lp->sense);
+    Hsrc = upd ? Hd : y;
+    Gsrc = upd ? Gd : y;
+    vecs[0] = gp(static_cast<const V*>(lp->x[nxt]));
+    rp = gp(lp->rp_a);
+    ci = gp(lp->ci_a);
+    va = gp(static_cast<const V*>(lp->va_a));
+    b = uni(b), S = uni(S), Hd = uni(Hd), y = uni(y), ys = uni(ys), Ax = uni(Ax);
+    yn = uni(yn), ysn = uni(ysn), Axn = uni(Axn), Gd = uni(Gd), sense = uni(sense);
+    Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
+    rp = uni(rp), ci = uni(ci), va = uni(va);
+    sig = uni(sig), etav = uni(etav);
+    return true;
+  }
+
+  __device__ __forceinline__ DualPre<V> load(int i) const {
+    DualPre<V> q;
+    q.ax = ldg(Ax, (uint32_t)i);
+    q.b = ldg(b, (uint32_t)i);
+    q.y = ldg(y, (uint32_t)i);
+    q.ys = ldg(ys, (uint32_t)i);
+    q.S = ldg(S, (uint32_t)i);
+    q.ineq = ldg(sense, (uint32_t)i);
+    q.H = ldg(Hsrc, (uint32_t)i);
+    q.G = ldg(Gsrc, (uint32_t)i);
+    return q;
+  }
+
+  // Row i with (A x')_i = axn: partials |y'-y|^2 (or its Sigma^-1 norm),
+  // (y'-y).(Ax'-Ax), |b-Ax|^2, |G^d|^2 into p.
+  __device__ __forceinline__ void finish(int i, V axn, DualPre<V>& q, DD (&p)[4]) const {
+    V Si = q.S;
+    if (upd) {
+      V h = q.H;
+      Si = learn_elem<V>(Si, h, q.G, lscale, lp->prm, hnorm);
+      stg(S, (uint32_t)i, Si);
+      stg(Hd, (uint32_t)i, h);
+    }
+    const V axbar = V(2) * axn - q.ax;
+    const V rt = q.b - axbar;
+    const V yh = q.y + (sig * Si) * rt;
+    const bool ineq = q.ineq != 0;
+    const V yv = (ineq && yh < V(0)) ? V(0) : yh;
+    stg(yn, (uint32_t)i, yv);
+    stg(Axn, (uint32_t)i, axn);
+    stg(ysn, (uint32_t)i, q.ys + etav * yv);
+    const double dy = (double)yv - (double)q.y;
+    const double si = (double)Si;
+    const double wdy = !wstep ? dy : (si > 0.0 ? dy / si : 0.0);
+    dd_add_prod(p[0], dy, wdy);
+    dd_add_prod(p[1], dy, (double)axn - (double)q.ax);
+    const V r = q.b - q.ax;
+    dd_add_prod(p[2], (double)r, (double)r);
+    if (learn) {
+      const bool ind = !ineq || yh >= V(0);
+      const V gd = ind ? -((sig * r) * rt) : V(0);
+      stg(Gd, (uint32_t)i, gd);
+      dd_add_prod(p[3], (double)gd, (double)gd);
+    }
+  }
+
+  __device__ __forceinline__ double* part() const { return lp->part_a; }
+  __device__ __forceinline__ int stride() const { return lp->ntiles_a; }
+};
+
+// Chunking of a step kernel's tile list: fixed sets carry it in the launch
+// arguments (no dependent load before the work items); the server's
+// changing set reads the device-side counts.
+__device__ __forceinline__ SideChunks step_chunks(const LaunchCfg& cfg, bool tside) {
+  if (cfg.step_fixed)
+    return SideChunks{tside ? cfg.sgrid_t : cfg.sgrid_a, tside ? cfg.schunk_t : cfg.schunk_a};
+  return side_chunks(cfg.counts, tside);
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
+  __shared__ SpmvShared<V, 1> sh;
+  __shared__ DD s_red[4 * 3];
+  const double nodiv[1] = {0.0};
+  DD p[3];
+  dd_reset(p);
+  PrimalStep<V> st;
+  __shared__ WorkItem s_items[kItemWin];
+  run_chunk_spmv<V, 1>(
+      cfg.step_fixed ? cfg.step_t : cfg.work_t, step_chunks(cfg, true), s_items, st.rp, st.ci,
+      st.va, st.vecs, nodiv,
+      [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.slot, force); },
+      [&](int j) { return st.load(j); },
+      [&](int j, V (&acc)[1], PrimalPre<V>& q) { st.finish(j, acc[0], q, p); },
+      [&](const WorkItem& it, bool run) {
+        if (run) flush_partials<3>(p, s_red, st.part(), st.stride(), it.slot);
+        else dd_reset(p);
+      },
+      sh);
+}
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
@@ -1030,108 +1174,166 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
   const double nodiv[1] = {0.0};
   DD p[4];
   dd_reset(p);
-  const LpDev* lp = nullptr;
-  const Ctl* c = nullptr;
-  gptr<const V> b = nullptr, y = nullptr, ys = nullptr, Ax = nullptr;
-  gptr<V> S = nullptr, Hd = nullptr, yn = nullptr, ysn = nullptr, Axn = nullptr, Gd = nullptr;
-  gptr<const V> Hsrc = nullptr, Gsrc = nullptr;  // as in k_primal
-  gptr<const int8_t> sense = nullptr;
-  gptr<const int32_t> rp = nullptr, ci = nullptr;
-  gptr<const V> va = nullptr;
-  gptr<const V> vecs[1] = {nullptr};
-  V sig = V(0), etav = V(0);
-  bool learn = false, upd = false, wstep = false;
-  double lscale = 1.0, hnorm = 0.0;
+  DualStep<V> st;
   __shared__ WorkItem s_items[kItemWin];
   run_chunk_spmv<V, 1>(
-      cfg.work_a, side_chunks(cfg.counts, false), s_items, rp, ci, va, vecs, nodiv,
-      [&](const WorkItem& it) {
-        c = it.ctl;
-        // as in k_primal: uniform values in scalar registers
-        if (!uni((int)(force || attempt_guard(c)))) return false;
-        lp = &cfg.lps[it.lp];
-        const int cur = uni(c->cur), nxt = cur ^ 1;
-        const double eta = uni(c->eta), om = uni(c->omega);
-        sig = (V)(eta * om);
-        etav = (V)eta;
-        learn = uni((int)(!force && c->learn_now != 0)) != 0;
-        wstep = uni(c->weighted_step) != 0;
-        lscale = 1.0;
-        upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, false, &lscale))) != 0;
-        lscale = uni(lscale);
-        hnorm = uni(c->hd_norm);
-        b = gp(static_cast<const V*>(lp->b));
-        S = gp(static_cast<V*>(lp->S));
-        Hd = gp(static_cast<V*>(lp->Hd));
-        y = gp(static_cast<const V*>(lp->y[cur]));
-        ys = gp(static_cast<const V*>(lp->ys[cur]));
-        Ax = gp(static_cast<const V*>(lp->Ax[cur]));
-        yn = gp(static_cast<V*>(lp->y[nxt]));
-        ysn = gp(static_cast<V*>(lp->ys[nxt]));
-        Axn = gp(static_cast<V*>(lp->Ax[nxt]));
-        Gd = gp(static_cast<V*>(lp->Gd));
-        sense = gp(lp->sense);
-        Hsrc = upd ? Hd : y;
-        Gsrc = upd ? Gd : y;
-        vecs[0] = gp(static_cast<const V*>(lp->x[nxt]));
-        rp = gp(lp->rp_a);
-        ci = gp(lp->ci_a);
-        va = gp(static_cast<const V*>(lp->va_a));
-        b = uni(b), S = uni(S), Hd = uni(Hd), y = uni(y), ys = uni(ys), Ax = uni(Ax);
-        yn = uni(yn), ysn = uni(ysn), Axn = uni(Axn), Gd = uni(Gd), sense = uni(sense);
-        Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
-        rp = uni(rp), ci = uni(ci), va = uni(va);
-        sig = uni(sig), etav = uni(etav);
-        return true;
-      },
-            [&](int i) {
-              DualPre<V> q;
-              q.ax = ldg(Ax, (uint32_t)i);
-              q.b = ldg(b, (uint32_t)i);
-              q.y = ldg(y, (uint32_t)i);
-              q.ys = ldg(ys, (uint32_t)i);
-              q.S = ldg(S, (uint32_t)i);
-              q.ineq = ldg(sense, (uint32_t)i);
-              q.H = ldg(Hsrc, (uint32_t)i);
-              q.G = ldg(Gsrc, (uint32_t)i);
-              return q;
-            },
-            [&](int i, V (&acc)[1], DualPre<V>& q) {
-              V Si = q.S;
-              if (upd) {
-                V h = q.H;
-                Si = learn_elem<V>(Si, h, q.G, lscale, lp->prm, hnorm);
-                stg(S, (uint32_t)i, Si);
-                stg(Hd, (uint32_t)i, h);
-              }
-              const V axn = acc[0];
-              const V axbar = V(2) * axn - q.ax;
-              const V rt = q.b - axbar;
-              const V yh = q.y + (sig * Si) * rt;
-              const bool ineq = q.ineq != 0;
-              const V yv = (ineq && yh < V(0)) ? V(0) : yh;
-              stg(yn, (uint32_t)i, yv);
-              stg(Axn, (uint32_t)i, axn);
-              stg(ysn, (uint32_t)i, q.ys + etav * yv);
-              const double dy = (double)yv - (double)q.y;
-              const double si = (double)Si;
-              const double wdy = !wstep ? dy : (si > 0.0 ? dy / si : 0.0);
-              dd_add_prod(p[0], dy, wdy);
-              dd_add_prod(p[1], dy, (double)axn - (double)q.ax);
-              const V r = q.b - q.ax;
-              dd_add_prod(p[2], (double)r, (double)r);
-              if (learn) {
-                const bool ind = !ineq || yh >= V(0);
-                const V gd = ind ? -((sig * r) * rt) : V(0);
-                stg(Gd, (uint32_t)i, gd);
-                dd_add_prod(p[3], (double)gd, (double)gd);
-              }
-            },
+      cfg.step_fixed ? cfg.step_a : cfg.work_a, step_chunks(cfg, false), s_items, st.rp, st.ci,
+      st.va, st.vecs, nodiv,
+      [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.slot, force); },
+      [&](int i) { return st.load(i); },
+      [&](int i, V (&acc)[1], DualPre<V>& q) { st.finish(i, acc[0], q, p); },
       [&](const WorkItem& it, bool run) {
-        if (run) flush_partials<4>(p, s_red, lp->part_a, lp->ntiles_a, it.slot);
+        if (run) flush_partials<4>(p, s_red, st.part(), st.stride(), it.slot);
         else dd_reset(p);
       },
       sh);
+}
+
+// Windowed step kernel (FP32): one workgroup of kWinBlock threads per
+// windowed chunk. Each pass stages its vector ranges in LDS, then every
+// thread takes kWinNpt consecutive entries at a time (16-byte loads of
+// columns, rows and values) and adds up its runs of equal rows, gathering
+// from LDS. A run that lies inside one thread's entries is added to the
+// row's sum at once; a run that crosses threads is added by the thread
+// where it starts, which collects the pieces of the threads after it in
+// thread order, so every row sum is formed in one fixed order (the same
+// for every grid and every co-resident LP). The first thread of each step
+// of kWinBlock * kWinNpt entries owns its first run: the earlier pieces
+// were added at the previous step. After the passes each thread runs the
+// row epilogue for rows r0 + t, r0 + t + kWinBlock, ...
+template <typename Step, typename Pre, int NV>
+__device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* list, int nwin,
+                                          bool tside, int force) {
+  extern __shared__ float wlds[];
+  float* win = wlds;
+  float* part = win + kWinCap;
+  float* hs = part + kWinRows;
+  int* hspan = reinterpret_cast<int*>(hs + kWinBlock);
+  DD* s_red = reinterpret_cast<DD*>(hspan + kWinBlock);
+  const int chi = chunk_index(nwin);
+  if (chi < 0) return;
+  const WinItem it = list[chi];
+  if (it.lp < 0) return;  // padding of the list to a multiple of 8
+  Step st;
+  if (!st.begin(cfg, it.ctl, it.lp, it.slot, force)) return;
+  const LpDev* lp = st.lp;
+  const gptr<const uint16_t> wc = uni(gp(tside ? lp->wcol_t : lp->wcol_a));
+  const gptr<const uint16_t> wr = uni(gp(tside ? lp->wrow_t : lp->wrow_a));
+  const gptr<const float> wv = uni(gp(static_cast<const float*>(tside ? lp->wval_t : lp->wval_a)));
+  const gptr<const WinPass> passes = uni(gp(tside ? lp->wpass_t : lp->wpass_a));
+  const gptr<const WinRange> ranges = uni(gp(tside ? lp->wrange_t : lp->wrange_a));
+  const gptr<const float> vec = st.vecs[0];
+  const int t = threadIdx.x;
+  const int r0 = uni(it.r0), nrow = uni(it.r1 - it.r0);
+  for (int r = t; r < nrow; r += kWinBlock) part[r] = 0.f;
+  for (int ps = it.pass0; ps < it.pass0 + it.npass; ++ps) {
+    const int pe0 = passes[ps].e0, pe1 = passes[ps].e1;
+    const int pr0 = passes[ps].range0, prn = passes[ps].nrange;
+    __syncthreads();  // the previous pass is done with the window (and part is zeroed)
+    // ranges start on bucket boundaries (multiples of 4 entries, here and
+    // in the window), so they are copied 16 bytes at a time; only the
+    // vector's last bucket can end on a partial group
+    int off = 0;
+    for (int g = pr0; g < pr0 + prn; ++g) {
+      const int src = ranges[g].src, len = ranges[g].len;
+      using f32x4 = float __attribute__((ext_vector_type(4)));
+      const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src);
+      f32x4* w4 = reinterpret_cast<f32x4*>(win + off);
+      for (int q = t; q < (len >> 2); q += kWinBlock) w4[q] = v4[q];
+      for (int q = (len & ~3) + t; q < len; q += kWinBlock) win[off + q] = ldg(vec, (uint32_t)(src + q));
+      off += len;
+    }
+    __syncthreads();
+    for (int base = pe0; base < pe1; base += kWinBlock * kWinNpt) {
+      const int p0 = base + t * kWinNpt;
+      const bool active = p0 < pe1;
+      float s_run = 0.f, head_sum = 0.f;
+      int cur_row = -1;
+      bool in_head = false, spans = false, owner = false;
+      if (active) {
+        uint16_t cs[kWinNpt], rs[kWinNpt];
+        float vs[kWinNpt];
+        {
+          using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+          using f32x4 = float __attribute__((ext_vector_type(4)));
+          const u32x4 c0 = *reinterpret_cast<gptr<const u32x4>>(wc + p0);
+          const u32x4 c1 = *reinterpret_cast<gptr<const u32x4>>(wc + p0 + 8);
+          const u32x4 q0 = *reinterpret_cast<gptr<const u32x4>>(wr + p0);
+          const u32x4 q1 = *reinterpret_cast<gptr<const u32x4>>(wr + p0 + 8);
+          f32x4 v4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v4[u] = *reinterpret_cast<gptr<const f32x4>>(wv + p0 + 4 * u);
+          __builtin_memcpy(cs, &c0, 16);
+          __builtin_memcpy(cs + 8, &c1, 16);
+          __builtin_memcpy(rs, &q0, 16);
+          __builtin_memcpy(rs + 8, &q1, 16);
+          __builtin_memcpy(vs, v4, 64);
+        }
+        const int prev_row = t > 0 ? (int)wr[p0 - 1] : -1;
+        const int next_row = p0 + kWinNpt < pe1 ? (int)wr[p0 + kWinNpt] : -1;
+        cur_row = rs[0];
+        in_head = (int)rs[0] == prev_row;
+#pragma unroll
+        for (int i = 0; i < kWinNpt; ++i) {
+          const int r = rs[i];
+          if (r != cur_row) {
+            if (in_head) {
+              head_sum = s_run;
+              in_head = false;
+            } else {
+              part[cur_row] += s_run;
+            }
+            s_run = 0.f;
+            cur_row = r;
+          }
+          s_run += vs[i] * win[cs[i]];
+        }
+        const bool tail_cont = cur_row == next_row;
+        if (in_head) {
+          head_sum = s_run;
+          spans = tail_cont;
+        } else if (tail_cont) {
+          owner = true;
+        } else {
+          part[cur_row] += s_run;
+        }
+      }
+      hs[t] = head_sum;
+      hspan[t] = spans ? 1 : 0;
+      __syncthreads();
+      if (owner) {
+        float tot = s_run;
+        for (int u = t + 1; u < kWinBlock; ++u) {
+          tot += hs[u];
+          if (!hspan[u]) break;
+        }
+        part[cur_row] += tot;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  DD p[NV];
+  dd_reset(p);
+  // two rows per thread in flight: their vector loads are issued together
+  for (int r = t; r < nrow; r += 2 * kWinBlock) {
+    const int r2 = r + kWinBlock;
+    const bool two = r2 < nrow;
+    Pre q0 = st.load(r0 + r);
+    Pre q1 = st.load(r0 + (two ? r2 : r));
+    st.finish(r0 + r, part[r], q0, p);
+    if (two) st.finish(r0 + r2, part[r2], q1, p);
+  }
+  block_sum<NV, kWinWaves>(p, s_red);
+  store_partials<NV>(st.part(), st.stride(), it.slot, p);
+}
+
+__global__ __launch_bounds__(kWinBlock) void k_primal_win(LaunchCfg cfg, int force) {
+  win_chunk<PrimalStep<float>, PrimalPre<float>, 3>(cfg, cfg.win_t, cfg.nwin_t, true, force);
+}
+
+__global__ __launch_bounds__(kWinBlock) void k_dual_win(LaunchCfg cfg, int force) {
+  win_chunk<DualStep<float>, DualPre<float>, 4>(cfg, cfg.win_a, cfg.nwin_a, false, force);
 }
 
 // One workgroup per LP: the step decision of the attempt that just ran.
@@ -1149,7 +1351,11 @@ __global__ __launch_bounds__(kBlock) void k_decide(LaunchCfg cfg) {
     const int status = uni(cp->status), need = uni(cp->need_eval);
     const int64_t k = uni(cp->k), k_limit = uni(cp->k_limit);
     double sv[7];
-    sum_partials2<3, 4>(lp.part_t, lp.ntiles_t, lp.nslot_t, lp.part_a, lp.ntiles_a, lp.nslot_a,
+    // slots of the step kernels: their own lists in fixed sets, else the
+    // evaluation lists
+    const int ns_t = cfg.step_fixed ? lp.nslot_st : lp.nslot_t;
+    const int ns_a = cfg.step_fixed ? lp.nslot_sa : lp.nslot_a;
+    sum_partials2<3, 4>(lp.part_t, lp.ntiles_t, ns_t, lp.part_a, lp.ntiles_a, ns_a,
                         sv, s_red);
     if (status == kRunning && need == 0 && k < k_limit && threadIdx.x == 0)
       decide_step(*cp, *lp.prm, lp, sv);
@@ -1449,11 +1655,53 @@ int Kernels<V>::init_products(const LaunchCfg& c, void* stream) {
 }
 template <typename V>
 int Kernels<V>::primal(const LaunchCfg& c, void* stream, int force) {
-  OPDHG_LAUNCH(k_primal<V>, c.launch_t, c, force);
+  OPDHG_LAUNCH(k_primal<V>, c.step_fixed ? c.sgrid_t : c.launch_t, c, force);
 }
 template <typename V>
 int Kernels<V>::dual(const LaunchCfg& c, void* stream, int force) {
-  OPDHG_LAUNCH(k_dual<V>, c.launch_a, c, force);
+  OPDHG_LAUNCH(k_dual<V>, c.step_fixed ? c.sgrid_a : c.launch_a, c, force);
+}
+// The windowed kernels take more than the default 64 KiB of LDS; the
+// attribute is set once per process, before the first launch.
+static int win_attributes() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] {
+    err = hipFuncSetAttribute((const void*)k_primal_win,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLds);
+    if (err == hipSuccess)
+      err = hipFuncSetAttribute((const void*)k_dual_win,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLds);
+  });
+  if (err != hipSuccess) g_last_device_error = err;
+  return err == hipSuccess ? 0 : -1;
+}
+
+int window_kernels_ready() { return win_attributes(); }
+
+template <typename V>
+int Kernels<V>::primal_win(const LaunchCfg& c, void* stream, int force) {
+  if (c.nwin_t <= 0) return 0;
+  if constexpr (!std::is_same<V, float>::value) {
+    return -1;  // windowed chunks are planned for FP32 only
+  } else {
+    if (win_attributes()) return -1;
+    hipLaunchKernelGGL(k_primal_win, dim3(c.nwin_t), dim3(kWinBlock), kWinLds,
+                       (hipStream_t)stream, c, force);
+    return launched();
+  }
+}
+template <typename V>
+int Kernels<V>::dual_win(const LaunchCfg& c, void* stream, int force) {
+  if (c.nwin_a <= 0) return 0;
+  if constexpr (!std::is_same<V, float>::value) {
+    return -1;
+  } else {
+    if (win_attributes()) return -1;
+    hipLaunchKernelGGL(k_dual_win, dim3(c.nwin_a), dim3(kWinBlock), kWinLds,
+                       (hipStream_t)stream, c, force);
+    return launched();
+  }
 }
 template <typename V>
 int Kernels<V>::decide(const LaunchCfg& c, void* stream) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,19 @@ int host_threads();  // hardware threads of the host (at least 1)
 int validate_lp(const opdhg_lp* lp);
 int validate_params(const opdhg_params* p);
 
+// Windowed chunks of one CSR side (see WinItem): rows and passes of each
+// chunk, the passes' entry ranges and LDS ranges, and the entries in
+// window-major order (window-local column, chunk-local row) with the
+// device-order CSR position of each (-1 for padding).
+struct WinPlan {
+  std::vector<int32_t> r0, r1, pass0, npass;
+  std::vector<WinPass> passes;
+  std::vector<WinRange> ranges;
+  std::vector<uint16_t> col, row;
+  std::vector<int64_t> src;
+  size_t chunks() const { return r0.size(); }
+};
+
 // An LP after validation, rescaling and transposition, in FP64 on the host.
 // Arrays marked "device order" follow the relabelling by row class:
 // device row i of A is original row perm_a[i], device variable j is
@@ -37,10 +51,20 @@ struct Prepared {
   std::vector<double> dr_dev, dc_dev;           // device order
   std::vector<double> dr, dc;                   // original order (unscaling)
   std::vector<int8_t> sense, bfin;              // device order
-  std::vector<Tile> tiles_a, tiles_t;
+  std::vector<Tile> tiles_a, tiles_t;    // every row (evaluations, initial products)
+  std::vector<Tile> stiles_a, stiles_t;  // rows the step kernels take in tiles (not windowed)
+  WinPlan win_a, win_t;                  // windowed rows of the step kernels (FP32)
+  int64_t cend_a[3] = {0, 0, 0}, cend_t[3] = {0, 0, 0};  // ends of the row classes
   std::vector<double> pow_tab;  // step-rule factors, 2 * kPowTab
   DevParams prm;
   double eta0 = 1.0, omega0 = 1.0;
+  // partial slots per side: evaluation tiles, or step tiles plus windowed chunks
+  int64_t part_stride_t() const {
+    return (int64_t)std::max(tiles_t.size(), stiles_t.size() + win_t.chunks());
+  }
+  int64_t part_stride_a() const {
+    return (int64_t)std::max(tiles_a.size(), stiles_a.size() + win_a.chunks());
+  }
 };
 
 // Byte offsets of every array of one LP slot in the workspace.
@@ -53,12 +77,14 @@ struct SlotLayout {
   size_t vn[kNVecN] = {};
   size_t vm[kNVecM] = {};
   size_t dc = 0, bfin = 0, dr = 0, sense = 0;
+  // windowed entries of each side (0 when none)
+  size_t wcol_t = 0, wrow_t = 0, wval_t = 0, wpass_t = 0, wrange_t = 0;
+  size_t wcol_a = 0, wrow_a = 0, wval_a = 0, wpass_a = 0, wrange_a = 0;
   size_t total = 0;
 };
 
 int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool structure_only);
-SlotLayout slot_layout(int64_t m, int64_t n, int64_t nnz, int64_t ntiles_t, int64_t ntiles_a,
-                       int prec);
+SlotLayout slot_layout(const Prepared& P, int prec);
 LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P);
 int upload_slot(uint8_t* base, const SlotLayout& L, const Prepared& P, int prec,
                 hipStream_t stream, std::vector<uint8_t>& img);
@@ -70,12 +96,19 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps,
                  const std::vector<const Prepared*>& preps, int64_t cap, hipStream_t stream,
                  std::vector<uint8_t>& staging, LaunchCfg* cfg, int64_t* nwt, int64_t* nwa,
                  size_t capacity = 0, bool fixed_launch = false);
+// Bytes of the launch tables of a fixed set (evaluation and step lists,
+// windowed chunks), or of the server's shared tables (evaluation lists,
+// which its step kernels also run).
+size_t tables_bytes(const std::vector<const Prepared*>& preps, int64_t cap);
 size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64_t cap);
+// The step tiles of an LP: its rows outside windowed chunks, tiled.
+void step_tiles(Prepared& P, int64_t cap, int lanes);
 // Work list of one side for a set of LPs (tiles of LP 0, then LP 1, ...),
 // chunked over at most cap workgroups and padded to grid * chunk items;
 // fills each item's slot / last flags and each LP's slot count.
+// step: the step kernels' tiles (stiles) and slot counts (nslot_st / nslot_sa).
 void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps, bool tside,
-                int64_t cap, int* grid, int* chunk, std::vector<WorkItem>& out);
+                int64_t cap, int* grid, int* chunk, std::vector<WorkItem>& out, bool step = false);
 // Workgroup cap of the sparse-product launches under these parameters.
 int64_t grid_cap(const opdhg_params* p);
 void chunking(int64_t n, int64_t cap, int* grid, int* chunk);
@@ -94,9 +127,13 @@ struct Group {
   hipStream_t stream = nullptr;      // caller's stream (replays, copies)
   hipStream_t cap_stream = nullptr;  // private stream used only for capture
   hipGraphExec_t exec = nullptr;
+  // a side's tile kernel runs on side_stream beside its windowed kernel
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   LaunchCfg cfg{};
   int prec = 0;
   int init(void* stream, int prec);
+  int launch_side(bool primal, int force, hipStream_t s);
   int capture(int attempts_per_replay);
   int launch_init();
   int launch_primal_forced();

@@ -103,11 +103,47 @@ struct Tile {
   int32_t rb, re, s, e, lanes, pad;
 };
 
+// Windowed sparse products (FP32). Rows of one side whose gathered vector
+// entries fall into a few column ranges are taken in chunks of up to
+// kWinRows consecutive rows by workgroups of kWinBlock threads. For each
+// pass the workgroup copies up to kWinCap vector entries (whole buckets of
+// kWinBucket columns) into LDS, then streams the pass's entries
+// (window-local column, chunk-local row, value; padded to kWinNpt) and
+// gathers from LDS; row sums of the passes add up in LDS and feed the same
+// row epilogues as the tile kernels.
+constexpr int kWinBlock = 1024;
+constexpr int kWinNpt = 16;
+constexpr int kWinBucket = 1024;
+constexpr int kWinBuckets = 26;
+constexpr int kWinCap = kWinBuckets * kWinBucket;
+constexpr int kWinRows = 8192;
+constexpr int kWinMaxPass = 4;
+constexpr int kWinWaves = kWinBlock / 64;
+// LDS of a windowed workgroup: window, row sums, per-thread carries, reduction
+constexpr size_t kWinLds = (size_t)(kWinCap + kWinRows + 2 * kWinBlock) * 4 + kWinWaves * 4 * 16;
+
+// Entries [e0, e1) of a pass (both multiples of kWinNpt) and the vector
+// ranges [range0, range0 + nrange) it stages, in window order.
+struct WinPass {
+  int32_t e0, e1, range0, nrange;
+};
+struct WinRange {
+  int32_t src, len;  // vector entries [src, src + len), device order
+};
+// A windowed chunk: rows [r0, r1) of one LP side, passes [pass0, pass0 + npass).
+struct WinItem {
+  Ctl* ctl;
+  int32_t lp, slot;
+  int32_t r0, r1;
+  int32_t pass0, npass;
+};
+
 // One LP slot as the kernels see it (device pointers into the workspace).
 struct LpDev {
   int32_t m, n;
   int32_t ntiles_t, ntiles_a;  // tiles over A^T rows (n) and A rows (m); partial stride
-  int32_t nslot_t, nslot_a;    // partial slots in use (workgroups touching the LP)
+  int32_t nslot_t, nslot_a;    // partial slots of the evaluation kernels (workgroups touching the LP)
+  int32_t nslot_st, nslot_sa;  // partial slots of the step kernels (tile chunks, then windowed chunks)
   const int32_t* rp_a;
   const int32_t* ci_a;
   const void* va_a;
@@ -147,6 +183,17 @@ struct LpDev {
   double* pow_ring;       // 2 * kPowRing: the same factors for j = ring_base+1 .. +kPowRing
   Ctl* ctl;
   const DevParams* prm;
+  // windowed rows of each side (FP32; empty when the side has none)
+  const uint16_t* wcol_t;  // window-local column of each entry
+  const uint16_t* wrow_t;  // chunk-local row of each entry
+  const void* wval_t;      // value of each entry (type V)
+  const WinPass* wpass_t;
+  const WinRange* wrange_t;
+  const uint16_t* wcol_a;
+  const uint16_t* wrow_a;
+  const void* wval_a;
+  const WinPass* wpass_a;
+  const WinRange* wrange_a;
 };
 
 // A set of LPs launched together. A work item is one tile of one LP, with
@@ -191,6 +238,18 @@ struct LaunchCfg {
   int launch_lp;           // one workgroup per LP (decision kernels, board)
   // host copy of the device-side chunking
   int grid_t, chunk_t, grid_a, chunk_a;
+  // the step kernels' work: tile lists (rows not taken by windowed chunks)
+  // and windowed chunks. With step_fixed the tile lists' chunking is the
+  // one below (a fixed set of LPs); else the step kernels run the
+  // evaluation lists with the device-side chunking.
+  const WorkItem* step_t;
+  const WorkItem* step_a;
+  const WinItem* win_t;
+  const WinItem* win_a;
+  int sgrid_t, schunk_t, sgrid_a, schunk_a;
+  int nwin_t, nwin_a;  // windowed chunks per side (launch grid rounded up to 8)
+  int step_fixed;
+  int pad_;
 };
 
 template <typename V>
@@ -198,6 +257,9 @@ struct Kernels {
   static int init_products(const LaunchCfg& c, void* stream);
   static int primal(const LaunchCfg& c, void* stream, int force);
   static int dual(const LaunchCfg& c, void* stream, int force = 0);
+  // windowed chunks of each side (FP32 only; nothing to launch when the set has none)
+  static int primal_win(const LaunchCfg& c, void* stream, int force);
+  static int dual_win(const LaunchCfg& c, void* stream, int force = 0);
   static int decide(const LaunchCfg& c, void* stream);
   static int learn_flush(const LaunchCfg& c, void* stream);
   static int eval_t(const LaunchCfg& c, void* stream);
@@ -208,6 +270,8 @@ struct Kernels {
 
 // Copies every LP's Ctl into c.board (precision independent).
 int launch_board(const LaunchCfg& c, void* stream);
+// Sets the windowed kernels' LDS attribute (once per process); 0 on success.
+int window_kernels_ready();
 
 const char* device_error_string();
 

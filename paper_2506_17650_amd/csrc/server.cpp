@@ -272,9 +272,8 @@ void ServerImpl::prep_loop() {
     int rc = prepare(&v, &j->p, j->P, false);
     std::string msg = rc ? std::string(opdhg_last_error()) : std::string();
     if (!rc) {
-      j->L = slot_layout(j->P.m, j->P.n, j->P.nnz, j->P.tiles_t.size(), j->P.tiles_a.size(),
-                         cfg.precision);
-      j->own_tables = tables_bytes(1, j->P.tiles_t.size(), j->P.tiles_a.size(), wg_cap);
+      j->L = slot_layout(j->P, cfg.precision);
+      j->own_tables = tables_bytes({&j->P}, wg_cap);
       j->need = align256(j->L.total) + align256(j->own_tables);
       if (j->need > budget) {
         rc = OPDHG_ERR_OVER_BUDGET;
@@ -345,6 +344,10 @@ int ServerImpl::write_shared() {
   int gt = 1, ct = 1, ga = 1, ca = 1;
   side_items(lps, preps, true, wg_cap, &gt, &ct, wt);
   side_items(lps, preps, false, wg_cap, &ga, &ca, wa);
+  for (LpDev& l : lps) {  // the step kernels write the same slots as the evaluation kernels
+    l.nslot_st = l.nslot_t;
+    l.nslot_sa = l.nslot_a;
+  }
   if ((int64_t)wt.size() > tab.cap_wt || (int64_t)wa.size() > tab.cap_wa ||
       (int64_t)lps.size() > tab.cap_lps)
     return fail(OPDHG_ERR_OVER_BUDGET, "launch tables overflow");
@@ -598,6 +601,13 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
   L.work_a = reinterpret_cast<const WorkItem*>(S.tab.base + S.tab.o_wa);
   L.counts = reinterpret_cast<const Counts*>(S.tab.base + S.tab.o_cn);
   L.board = reinterpret_cast<Ctl*>(S.tab.base + S.tab.o_board);
+  // the step kernels run the same lists with the device-side chunking; no
+  // request has windowed chunks (windows are off for every submission)
+  L.step_t = L.work_t;
+  L.step_a = L.work_a;
+  L.step_fixed = 0;
+  L.win_t = L.win_a = nullptr;
+  L.nwin_t = L.nwin_a = 0;
   const int g8 = (int)((S.wg_cap + 7) / 8 * 8);
   L.launch_t = L.launch_a = L.launch_ta = g8;
   L.launch_lp = std::min(cfg->max_active, kGridCap);
@@ -638,6 +648,8 @@ int opdhg_server_submit(opdhg_server* s, const opdhg_lp* lp, const opdhg_params*
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "request precision differs from the server's");
   auto j = std::make_shared<Job>();
   j->p = *p;
+  // one captured launch sequence serves every mix of requests: tiles only
+  j->p.windows = OPDHG_WINDOWS_OFF;
   j->m = lp->m;
   j->n = lp->n;
   j->nnz = lp->nnz;

@@ -3,7 +3,8 @@
 An LP's arithmetic depends only on its own data (rows reduced inside one
 tile, exact cross-tile sums), so each result from the server must equal the
 solo opdhg_solve of the same LP with the same parameters bit for bit, in
-whatever mix it ran: submitted together, under a budget that admits only a
+whatever mix it ran (the server runs tiles only, so the solo solves turn
+windows off): submitted together, under a budget that admits only a
 few at a time, or arriving while others iterate.
 """
 
@@ -31,7 +32,10 @@ def _mix():
 
 
 def _params(P, prec, **kw):
-    base = dict(precision=prec, tol=1e-4, max_iter=20000, lr=1e-3, phi=20)
+    # the server runs every request in tiles (one captured sequence serves
+    # every mix), so the solo solves it is compared with use tiles too
+    base = dict(precision=prec, tol=1e-4, max_iter=20000, lr=1e-3, phi=20,
+                windows=P.OPDHG_WINDOWS_OFF)
     base.update(kw)
     return P.opdhg_default_params(**base)
 
@@ -144,7 +148,8 @@ def test_vanilla_and_adaptive_requests_mixed():
     P = _P()
     prec = P.OPDHG_FP32
     lps = [config_lp("cfg0", seed=s) for s in range(4)]
-    plist = [P.opdhg_vanilla_params(lr, precision=prec, max_iter=20000) for lr in (0.0, 1e-1)]
+    plist = [P.opdhg_vanilla_params(lr, precision=prec, max_iter=20000,
+                                    windows=P.OPDHG_WINDOWS_OFF) for lr in (0.0, 1e-1)]
     plist += [_params(P, prec), _params(P, prec, lr=0.0)]
     solo = [P.opdhg_solve(lp, q) for lp, q in zip(lps, plist)]
     with P.Server(64 << 20, precision=prec) as srv:

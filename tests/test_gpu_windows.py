@@ -1,0 +1,170 @@
+"""Windowed sparse products (FP32) against the oracle, through the C-ABI.
+
+Rows whose gathered vector entries fall into a few column ranges (the
+block rows of a block-angular LP) run in windowed chunks: the ranges are
+staged in LDS and each row sum is formed in a fixed order of its own. The
+results are FP32 results, so they are held to the FP32 bounds of the tile
+path: traces within the FP32 trace tolerances of the FP64 oracle, final
+objectives within 1e-3 at rel KKT 1e-4, bit-identical reruns, batch = solo.
+At the full block-angular size one step from the GPU's own iterate is
+checked against one oracle step from the same point.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pdhg as OP
+from oracle.params import default_params
+from lpgen import config_lp
+
+pytestmark = pytest.mark.gpu
+
+# as in test_gpu_parity: FP32 rounding of O(1) row sums over 30 steps, 5x margin
+FP32_TRACE_TOL = 2e-4
+FP32_ETA_TOL = 2e-3
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_17650_amd as P
+    P.load()
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    nb = np.linalg.norm(b)
+    d = np.linalg.norm(a - b)
+    return 0.0 if (nb == 0.0 and d == 0.0) else d / nb
+
+
+def _lib(P, op, **kw):
+    # these LPs are too small for the automatic choice (fewer than 128
+    # chunks): windows are asked for explicitly
+    return P.opdhg_default_params(
+        precision=P.OPDHG_FP32, tol=op.tol, max_iter=op.max_iter, lr=op.lr, phi=op.phi,
+        normalize=int(op.normalize), ruiz_iters=op.ruiz_iters, pc_beta=op.pc_beta,
+        windows=P.OPDHG_WINDOWS_ALWAYS, **kw)
+
+
+# block-angular LPs small enough for the oracle: 6 blocks of 3000 x 8000,
+# 6 nonzeros per column, plus linking rows; the A side (block rows, 16 per
+# row) is windowed. window_buckets / window_rows force more passes and other
+# chunkings.
+CASES = [
+    dict(window_buckets=0, window_rows=0),     # automatic: 2 passes per chunk
+    dict(window_buckets=2, window_rows=0),     # 4 passes of 2048 entries
+    dict(window_buckets=3, window_rows=2500),  # 3 passes, chunks ending mid-block
+    dict(window_buckets=8, window_rows=3000),  # 1 pass, one chunk per block
+]
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_windowed_trace_close_to_oracle(P, kw):
+    lp = config_lp("cfg2", scale=0.1)
+    op = default_params(max_iter=100000, lr=1e-3, phi=5)
+    K = 30
+    ref = oracle.solve(lp, op, trace=K, stop_k=K)
+    tr = {e.k: e for e in ref.trace}
+    _say(f"[windows trace] cfg2x0.1 m={lp.m} n={lp.n} nnz={lp.nnz} {kw}")
+    worst = 0.0
+    with P.Session(lp, _lib(P, op, **kw)) as s:
+        for k in (1, 2, 5, 10, 20, 30):
+            s.run(k)
+            x, y, T, S, st = s.state()
+            e = tr[k]
+            assert st.k == k and st.attempts == e.attempts, (k, st.attempts, e.attempts)
+            errs = {"x": rel(x, e.x), "y": rel(y, e.y), "T": rel(T, e.T), "S": rel(S, e.S),
+                    "eta": abs(st.eta - e.eta) / abs(e.eta)}
+            worst = max(worst, max(v for nm, v in errs.items() if nm != "eta"))
+            for nm, v in errs.items():
+                assert v <= (FP32_ETA_TOL if nm == "eta" else FP32_TRACE_TOL), (k, nm, v)
+    _say(f"  worst FP32 relative deviation {worst:.2e}")
+
+
+def test_windowed_solve_matches_tiles_and_oracle(P):
+    lp = config_lp("cfg2", scale=0.1)
+    _say("[windows solve]")
+    ref = oracle.solve(lp, default_params(max_iter=40000))
+    p = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=40000,
+                               windows=P.OPDHG_WINDOWS_ALWAYS)
+    xw, yw, rw = P.opdhg_solve(lp, p)
+    xt, yt, rt = P.opdhg_solve(lp, P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=40000,
+                                                         windows=P.OPDHG_WINDOWS_OFF))
+    assert rw.status == 0 and rt.status == 0 and ref.status == 0
+    for r in (rw, rt):
+        assert abs(r.primal_obj - ref.primal_obj) <= 1e-3 * abs(ref.primal_obj)
+        assert r.rel_kkt <= 1e-4
+    _say(f"  iterations windows {rw.iterations}, tiles {rt.iterations}, oracle {ref.iterations}")
+
+
+def test_windowed_rerun_bit_identical_and_batch_equals_solo(P):
+    lps = [config_lp("cfg2", scale=0.1), config_lp("cfg1", scale=0.05),
+           config_lp("cfg2", scale=0.1, seed=5)]
+    _say("[windows determinism]")
+    p = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=3000, lr=1e-3, window_buckets=3,
+                               windows=P.OPDHG_WINDOWS_ALWAYS)
+    a = P.opdhg_solve(lps[0], p)
+    b = P.opdhg_solve(lps[0], p)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2].iterations == b[2].iterations
+    out = P.opdhg_solve_batch(lps, p)
+    for lp, (x, y, r) in zip(lps, out):
+        xs, ys, rs = P.opdhg_solve(lp, p)
+        assert r.status == rs.status and r.iterations == rs.iterations
+        assert np.array_equal(x, xs) and np.array_equal(y, ys)
+
+
+def test_server_ignores_windows(P):
+    # one captured sequence serves every mix: requests run in tiles, and
+    # equal the solo solve with windows off
+    lp = config_lp("cfg2", scale=0.1)
+    p = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=20000,
+                               windows=P.OPDHG_WINDOWS_ALWAYS)
+    off = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=20000,
+                                 windows=P.OPDHG_WINDOWS_OFF)
+    solo = P.opdhg_solve(lp, off)
+    with P.Server(64 << 20, precision=P.OPDHG_FP32) as srv:
+        x, y, r = srv.wait(srv.submit(lp, p), 120.0)
+    assert np.array_equal(x, solo[0]) and r.iterations == solo[2].iterations
+
+
+def _one_step_check(P, lp, params, k):
+    """Run k iterations on the GPU, then compare the GPU's next accepted
+    attempt with one oracle attempt from the GPU's own iterate (FP64)."""
+    slp = oracle.rescale(lp, params.ruiz_iters, params.pc_beta)
+    with P.Session(lp, params) as s:
+        s.run(k)
+        x, y, T, S, st = s.state()
+        s.run(k + 1)
+        x1, y1, T1, S1, st1 = s.state()
+    if st1.attempts != st.attempts + 1:
+        pytest.skip("the next attempt was rejected; nothing to compare")
+    g = slp.c - OP.AT_mul(slp, y)
+    Ax = OP.A_mul(slp, x)
+    a = OP.pdhg_attempt(slp, x, y, Ax, g, T, S, st.eta, st.omega)
+    ex, ey = rel(x1, a["x_new"]), rel(y1, a["y_new"])
+    _say(f"  one step from k={k}: x rel {ex:.2e}, y rel {ey:.2e}")
+    assert ex <= FP32_TRACE_TOL and ey <= FP32_TRACE_TOL
+
+
+def test_windowed_full_size_one_step(P):
+    """The full block-angular LP (1.92M x 5.12M, 35M nonzeros): every A^T row
+    and every block row of A is windowed."""
+    lp = config_lp("cfg2")
+    _say(f"[windows full size] m={lp.m} n={lp.n} nnz={lp.nnz}")
+    _one_step_check(P, lp, P.opdhg_default_params(precision=P.OPDHG_FP32, lr=1e-5, tol=0.0,
+                                                  max_iter=10**6), 12)
