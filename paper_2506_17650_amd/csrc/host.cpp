@@ -131,7 +131,7 @@ int validate_params(const opdhg_params* p) {
   if (p->window_buckets < 0 || p->window_buckets > kWinBuckets)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_buckets must be in [0, 26]");
   if (p->window_rows < 0 || p->window_rows > kWinRows)
-    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_rows must be in [0, 8192]");
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_rows must be in [0, 10240]");
   return OPDHG_OK;
 }
 
@@ -490,13 +490,19 @@ std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t cap, int 
 constexpr int64_t kWinMinNnz = 8192;  // smaller chunks are not worth a workgroup of kWinBlock
 
 static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
-                         int64_t ncols, int64_t lo, int64_t hi, int64_t chunk_rows, int per_pass,
-                         WinPlan& W) {
+                         int64_t ncols, int64_t lo, int64_t hi, int64_t long_end,
+                         int64_t chunk_rows, int per_pass, WinPlan& W) {
   if (hi <= lo || ncols <= 0) return;
   const int64_t nb = (ncols + kWinBucket - 1) / kWinBucket;
   const int64_t max_buckets = (int64_t)per_pass * kWinMaxPass;
-  std::vector<int32_t> stamp(nb, -1), rstamp(nb, -1), bpass(nb, -1), boff(nb, 0);
+  std::vector<int32_t> stamp(nb, -1), rstamp(nb, -1);
   std::vector<int64_t> touched;
+  // a chunk's staged buckets: (bucket, pass, offset in the pass's window)
+  struct Slot {
+    int64_t bucket;
+    int32_t pass, off;
+  };
+  std::vector<std::vector<Slot>> slots;
   int32_t id = 0;
   for (int64_t a = lo, b = lo; a < hi; a = b, ++id) {
     // grow the chunk row by row. It ends at chunk_rows rows, before a row
@@ -534,6 +540,7 @@ static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32
     // buckets to passes in order; runs of consecutive buckets become one range
     const int32_t pass0 = (int32_t)W.passes.size();
     int npass = 0;
+    std::vector<Slot> sl;
     for (int64_t q = 0; q < nbk; q += per_pass) {
       WinPass ps{0, 0, (int32_t)W.ranges.size(), 0};
       int32_t off = 0;
@@ -547,28 +554,133 @@ static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32
           W.ranges.push_back(WinRange{src, len});
           ps.nrange++;
         }
-        bpass[bk] = npass;
-        boff[bk] = off;
+        sl.push_back(Slot{bk, npass, off});
         off += len;
       }
       W.passes.push_back(ps);
       ++npass;
     }
-    // entries of each pass, rows in order; padded to whole kWinNpt groups
-    for (int q = 0; q < npass; ++q) {
-      WinPass& ps = W.passes[pass0 + q];
+    W.r0.push_back((int32_t)a);
+    W.r1.push_back((int32_t)b);
+    W.pass0.push_back(pass0);
+    W.npass.push_back(npass);
+    slots.push_back(std::move(sl));
+  }
+  const int64_t nch = (int64_t)W.chunks();
+  W.nseg.assign(nch, 0);
+  W.seg0.assign(nch, 0);
+  if (nch == 0) return;
+
+  // Row segments. A long row (rows [0, long_end)) whose every entry falls
+  // in some chunk's window is split by chunk: the entries of a bucket go to
+  // one of the chunks that stage it (chosen by the row, so that the long
+  // rows spread over those chunks), and each (row, chunk) pair becomes an
+  // extra row of that chunk, after its own rows. Its pass sums go to a
+  // partial of its own; a finishing kernel adds a row's partials in chunk
+  // order. The row then leaves the tiles.
+  std::vector<std::vector<int32_t>> cover(nb);  // chunks staging each bucket
+  for (int64_t c = 0; c < nch; ++c)
+    for (const Slot& x : slots[c]) cover[x.bucket].push_back((int32_t)c);
+  auto chunk_of = [&](int64_t r, int64_t bk) -> int32_t {
+    const std::vector<int32_t>& cv = cover[bk];
+    return cv.empty() ? -1 : cv[(size_t)(r % (int64_t)cv.size())];
+  };
+  std::vector<std::vector<int64_t>> seg_rows(nch);  // per chunk: its segment rows, in order
+  std::vector<int32_t> used;
+  std::vector<int32_t> cstamp(nch, -1);
+  for (int64_t r = 0; r < std::min(long_end, hi); ++r) {
+    if (rp[r + 1] == rp[r]) continue;
+    used.clear();
+    bool ok = true;
+    for (int64_t k = rp[r]; k < rp[r + 1] && ok; ++k) {
+      const int32_t c = chunk_of(r, ci[k] / kWinBucket);
+      if (c < 0) ok = false;
+      else if (cstamp[c] != (int32_t)r) {
+        cstamp[c] = (int32_t)r;
+        used.push_back(c);
+      }
+    }
+    if (!ok) continue;
+    for (int32_t c : used)
+      if ((int64_t)W.r1[c] - W.r0[c] + W.nseg[c] + 1 > kWinRows) ok = false;
+    if (!ok) continue;
+    std::sort(used.begin(), used.end());
+    W.srow.push_back((int32_t)r);
+    for (int32_t c : used) {
+      seg_rows[c].push_back(r);
+      W.nseg[c]++;
+    }
+  }
+  // global segment ids: chunk by chunk
+  int32_t sid = 0;
+  for (int64_t c = 0; c < nch; ++c) {
+    W.seg0[c] = sid;
+    sid += W.nseg[c];
+  }
+  W.nsegs = sid;
+  // each segmented row's partials, in chunk order
+  {
+    std::vector<int32_t> next(nch, 0);
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> per_row(W.srow.size());
+    std::vector<int32_t> row_index((size_t)std::min(long_end, hi), -1);
+    for (size_t q = 0; q < W.srow.size(); ++q) row_index[W.srow[q]] = (int32_t)q;
+    for (int64_t c = 0; c < nch; ++c)
+      for (int64_t r : seg_rows[c]) per_row[row_index[r]].push_back({(int32_t)c, W.seg0[c] + next[c]++});
+    W.sptr.assign(1, 0);
+    for (auto& v : per_row) {
+      std::sort(v.begin(), v.end());
+      for (auto& pr : v) W.sids.push_back(pr.second);
+      W.sptr.push_back((int32_t)W.sids.size());
+    }
+  }
+
+  // each chunk's segment entries (CSR position, chunk-local row), in
+  // segment order: one pass over the segmented rows (ascending, the order in
+  // which the chunks took them)
+  std::vector<std::vector<std::pair<int64_t, int32_t>>> seg_entries(nch);
+  {
+    std::vector<int32_t> taken(nch, 0), local(nch, -1), at(nch, -1);
+    for (int32_t r : W.srow)
+      for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+        const int32_t c = chunk_of(r, ci[k] / kWinBucket);
+        if (at[c] != r) {
+          at[c] = r;
+          local[c] = (W.r1[c] - W.r0[c]) + taken[c]++;
+        }
+        seg_entries[c].push_back({k, local[c]});
+      }
+  }
+  // entries of each pass of each chunk: its own rows in order, then its
+  // segments in order; padded to whole kWinNpt groups
+  std::vector<int32_t> bpass(nb, -1), boff(nb, 0);
+  for (int64_t c = 0; c < nch; ++c) {
+    for (const Slot& x : slots[c]) {
+      bpass[x.bucket] = x.pass;
+      boff[x.bucket] = x.off;
+    }
+    const int64_t a = W.r0[c], b = W.r1[c];
+    for (int q = 0; q < W.npass[c]; ++q) {
+      WinPass& ps = W.passes[W.pass0[c] + q];
       ps.e0 = (int32_t)W.col.size();
       uint16_t last_col = 0, last_row = 0;
+      auto emit = [&](int64_t k, int64_t local) {
+        const int64_t bk = ci[k] / kWinBucket;
+        last_col = (uint16_t)(boff[bk] + (ci[k] - bk * kWinBucket));
+        last_row = (uint16_t)local;
+        W.col.push_back(last_col);
+        W.row.push_back(last_row);
+        W.src.push_back(k);
+      };
       for (int64_t r = a; r < b; ++r)
-        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
-          const int64_t bk = ci[k] / kWinBucket;
-          if (bpass[bk] != q) continue;
-          last_col = (uint16_t)(boff[bk] + (ci[k] - bk * kWinBucket));
-          last_row = (uint16_t)(r - a);
-          W.col.push_back(last_col);
-          W.row.push_back(last_row);
-          W.src.push_back(k);
-        }
+        for (int64_t k = rp[r]; k < rp[r + 1]; ++k)
+          if (bpass[ci[k] / kWinBucket] == q) emit(k, r - a);
+      for (const auto& e : seg_entries[c])
+        if (bpass[ci[e.first] / kWinBucket] == q) emit(e.first, e.second);
+      if (W.col.size() == (size_t)ps.e0) {  // a pass with no entry keeps one zero entry
+        W.col.push_back(0);
+        W.row.push_back(0);
+        W.src.push_back(-1);
+      }
       while ((W.col.size() - ps.e0) % kWinNpt) {
         W.col.push_back(last_col);
         W.row.push_back(last_row);
@@ -576,10 +688,7 @@ static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32
       }
       ps.e1 = (int32_t)W.col.size();
     }
-    W.r0.push_back((int32_t)a);
-    W.r1.push_back((int32_t)b);
-    W.pass0.push_back(pass0);
-    W.npass.push_back(npass);
+    for (const Slot& x : slots[c]) bpass[x.bucket] = -1;
   }
 }
 
@@ -588,8 +697,9 @@ static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32
 // kWinRows, entry groups whole, staged ranges inside the vector.
 static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
   for (size_t c = 0; c < W.chunks(); ++c) {
-    const int64_t nrow = (int64_t)W.r1[c] - W.r0[c];
-    if (W.r0[c] < 0 || W.r1[c] > rows || nrow <= 0 || nrow > kWinRows) return false;
+    const int64_t nrow = (int64_t)W.r1[c] - W.r0[c] + W.nseg[c];
+    if (W.r0[c] < 0 || W.r1[c] > rows || W.r1[c] <= W.r0[c] || nrow > kWinRows) return false;
+    if (W.seg0[c] < 0 || W.seg0[c] + W.nseg[c] > W.nsegs) return false;
     if (W.npass[c] < 1 || W.npass[c] > kWinMaxPass) return false;
     for (int32_t q = W.pass0[c]; q < W.pass0[c] + W.npass[c]; ++q) {
       if (q < 0 || (size_t)q >= W.passes.size()) return false;
@@ -609,6 +719,13 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
         if (W.col[e] >= len || W.row[e] >= nrow) return false;
     }
   }
+  if (!W.srow.empty() &&
+      (W.sptr.size() != W.srow.size() + 1 || (size_t)W.sptr.back() != W.sids.size()))
+    return false;
+  for (int32_t r : W.srow)
+    if (r < 0 || r >= rows) return false;
+  for (int32_t q : W.sids)
+    if (q < 0 || q >= W.nsegs) return false;
   return W.col.size() == W.row.size() && W.col.size() == W.src.size();
 }
 
@@ -624,10 +741,15 @@ static std::vector<Tile> tiles_outside(const std::vector<int32_t>& rp, int64_t r
       out.push_back(t);
     }
   };
+  // rows taken elsewhere: the chunks' ranges and the segmented rows
+  std::vector<std::pair<int64_t, int64_t>> taken;
+  for (size_t c = 0; c < W.chunks(); ++c) taken.push_back({W.r0[c], W.r1[c]});
+  for (int32_t r : W.srow) taken.push_back({r, r + 1});
+  std::sort(taken.begin(), taken.end());
   int64_t cur = 0;
-  for (size_t c = 0; c < W.chunks(); ++c) {
-    add(cur, W.r0[c]);
-    cur = W.r1[c];
+  for (auto& t : taken) {
+    add(cur, t.first);
+    cur = std::max(cur, t.second);
   }
   add(cur, rows);
   return out;
@@ -735,9 +857,9 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.win_a = WinPlan();
   if (windows) {
     const int per_pass = p->window_buckets > 0 ? p->window_buckets : kWinBuckets;
-    plan_windows(out.rp_t, out.ci_t, m, out.cend_t[0], n,
+    plan_windows(out.rp_t, out.ci_t, m, out.cend_t[0], n, out.cend_t[0],
                  window_chunk_rows(p, n - out.cend_t[0]), per_pass, out.win_t);
-    plan_windows(out.rp_a, out.ci_a, n, out.cend_a[0], m,
+    plan_windows(out.rp_a, out.ci_a, n, out.cend_a[0], m, out.cend_a[0],
                  window_chunk_rows(p, m - out.cend_a[0]), per_pass, out.win_a);
     if (!plan_ok(out.win_t, n, m) || !plan_ok(out.win_a, m, n))
       return fail(OPDHG_ERR_DEVICE, "internal error: inconsistent window plan");
@@ -869,6 +991,12 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
     L.wval_t = take(V * e);
     L.wpass_t = take(sizeof(WinPass) * P.win_t.passes.size());
     L.wrange_t = take(sizeof(WinRange) * P.win_t.ranges.size());
+    if (!P.win_t.srow.empty()) {
+      L.segp_t = take(V * P.win_t.nsegs);
+      L.srow_t = take(4 * P.win_t.srow.size());
+      L.sptr_t = take(4 * P.win_t.sptr.size());
+      L.sids_t = take(4 * P.win_t.sids.size());
+    }
   }
   if (P.win_a.chunks()) {
     const size_t e = P.win_a.col.size();
@@ -877,6 +1005,12 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
     L.wval_a = take(V * e);
     L.wpass_a = take(sizeof(WinPass) * P.win_a.passes.size());
     L.wrange_a = take(sizeof(WinRange) * P.win_a.ranges.size());
+    if (!P.win_a.srow.empty()) {
+      L.segp_a = take(V * P.win_a.nsegs);
+      L.srow_a = take(4 * P.win_a.srow.size());
+      L.sptr_a = take(4 * P.win_a.sptr.size());
+      L.sids_a = take(4 * P.win_a.sids.size());
+    }
   }
   L.total = off;
   return L;
@@ -921,6 +1055,12 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
     d.wval_t = base + L.wval_t;
     d.wpass_t = reinterpret_cast<const WinPass*>(base + L.wpass_t);
     d.wrange_t = reinterpret_cast<const WinRange*>(base + L.wrange_t);
+    if (!P.win_t.srow.empty()) {
+      d.segp_t = base + L.segp_t;
+      d.srow_t = reinterpret_cast<const int32_t*>(base + L.srow_t);
+      d.sptr_t = reinterpret_cast<const int32_t*>(base + L.sptr_t);
+      d.sids_t = reinterpret_cast<const int32_t*>(base + L.sids_t);
+    }
   }
   if (P.win_a.chunks()) {
     d.wcol_a = reinterpret_cast<const uint16_t*>(base + L.wcol_a);
@@ -928,6 +1068,12 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
     d.wval_a = base + L.wval_a;
     d.wpass_a = reinterpret_cast<const WinPass*>(base + L.wpass_a);
     d.wrange_a = reinterpret_cast<const WinRange*>(base + L.wrange_a);
+    if (!P.win_a.srow.empty()) {
+      d.segp_a = base + L.segp_a;
+      d.srow_a = reinterpret_cast<const int32_t*>(base + L.srow_a);
+      d.sptr_a = reinterpret_cast<const int32_t*>(base + L.sptr_a);
+      d.sids_a = reinterpret_cast<const int32_t*>(base + L.sids_a);
+    }
   }
   return d;
 }
@@ -975,8 +1121,14 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
   std::memcpy(img.data() + L.ci_t, P.ci_t.data(), 4 * P.ci_t.size());
   put_vec<V>(img, L.va_t, P.va_t);
   auto put_win = [&](const WinPlan& W, const std::vector<double>& va, size_t oc, size_t orow,
-                     size_t ov, size_t opass, size_t orange) {
+                     size_t ov, size_t opass, size_t orange, size_t osrow, size_t osptr,
+                     size_t osids) {
     if (!W.chunks()) return;
+    if (!W.srow.empty()) {
+      std::memcpy(img.data() + osrow, W.srow.data(), 4 * W.srow.size());
+      std::memcpy(img.data() + osptr, W.sptr.data(), 4 * W.sptr.size());
+      std::memcpy(img.data() + osids, W.sids.data(), 4 * W.sids.size());
+    }
     std::memcpy(img.data() + oc, W.col.data(), 2 * W.col.size());
     std::memcpy(img.data() + orow, W.row.data(), 2 * W.row.size());
     V* dst = reinterpret_cast<V*>(img.data() + ov);
@@ -984,8 +1136,10 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
     std::memcpy(img.data() + opass, W.passes.data(), sizeof(WinPass) * W.passes.size());
     std::memcpy(img.data() + orange, W.ranges.data(), sizeof(WinRange) * W.ranges.size());
   };
-  put_win(P.win_t, P.va_t, L.wcol_t, L.wrow_t, L.wval_t, L.wpass_t, L.wrange_t);
-  put_win(P.win_a, P.va_a, L.wcol_a, L.wrow_a, L.wval_a, L.wpass_a, L.wrange_a);
+  put_win(P.win_t, P.va_t, L.wcol_t, L.wrow_t, L.wval_t, L.wpass_t, L.wrange_t, L.srow_t,
+          L.sptr_t, L.sids_t);
+  put_win(P.win_a, P.va_a, L.wcol_a, L.wrow_a, L.wval_a, L.wpass_a, L.wrange_a, L.srow_a,
+          L.sptr_a, L.sids_a);
   // n-vectors: c l u T Hp Gp x0 x1 xs0 xs1 xa
   put_vec<V>(img, L.vn[0], P.c);
   put_vec<V>(img, L.vn[1], P.l);
@@ -1064,13 +1218,23 @@ int Group::launch_side(bool primal, int force, hipStream_t s) {
     return primal ? Kernels<double>::primal_win(cfg, q, force)
                   : Kernels<double>::dual_win(cfg, q, force);
   };
-  if (!(tiles && wins)) return (tiles ? tile(s) : 0) | (wins ? win(s) : 0);
+  // segmented long rows finish after the windowed chunks wrote their partials
+  auto seg = [&](hipStream_t q) {
+    if ((primal ? cfg.nseg_t : cfg.nseg_a) <= 0) return 0;
+    if (prec == OPDHG_FP32)
+      return primal ? Kernels<float>::primal_seg(cfg, q, force)
+                    : Kernels<float>::dual_seg(cfg, q, force);
+    return primal ? Kernels<double>::primal_seg(cfg, q, force)
+                  : Kernels<double>::dual_seg(cfg, q, force);
+  };
+  if (!(tiles && wins)) return (tiles ? tile(s) : 0) | (wins ? win(s) | seg(s) : 0);
   if (hipEventRecord(ev_fork, s) != hipSuccess ||
       hipStreamWaitEvent(side_stream, ev_fork, 0) != hipSuccess)
     return -1;
   int rc = tile(side_stream);
   if (hipEventRecord(ev_join, side_stream) != hipSuccess) return -1;
   rc |= win(s);
+  rc |= seg(s);
   if (hipStreamWaitEvent(s, ev_join, 0) != hipSuccess) return -1;
   return rc;
 }
@@ -1155,8 +1319,10 @@ int64_t grid_cap(const opdhg_params* p) {
 
 // Work-list sizes of a fixed set: evaluation tiles, step tiles, windowed chunks.
 struct ListSizes {
-  int64_t nlps = 0, nt = 0, na = 0, st = 0, sa = 0, vt = 0, va = 0;
+  int64_t nlps = 0, nt = 0, na = 0, st = 0, sa = 0, vt = 0, va = 0, gt = 0, ga = 0;
   void add(const Prepared& P) {
+    gt += (int64_t)P.win_t.seg_items();
+    ga += (int64_t)P.win_a.seg_items();
     ++nlps;
     nt += (int64_t)P.tiles_t.size();
     na += (int64_t)P.tiles_a.size();
@@ -1185,6 +1351,7 @@ static size_t tables_bytes(const ListSizes& z, int64_t cap) {
   extra += align_up(sizeof(WorkItem) * (size_t)g * c);
   auto padded = [](int64_t v) { return (size_t)(v > 8 ? (v + 7) / 8 * 8 : v); };
   extra += align_up(sizeof(WinItem) * padded(vt)) + align_up(sizeof(WinItem) * padded(va));
+  extra += align_up(sizeof(SegItem) * padded(z.gt)) + align_up(sizeof(SegItem) * padded(z.ga));
   return tables_bytes(z.nlps, nt, na, cap) + extra;
 }
 
@@ -1263,6 +1430,7 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   std::vector<LpDev> lps(lps_in);
   std::vector<WorkItem> wt, wa, st, sa;
   std::vector<WinItem> vt, va;
+  std::vector<SegItem> gt, ga;
   side_items(lps, preps, true, cap, &cfg->grid_t, &cfg->chunk_t, wt);
   side_items(lps, preps, false, cap, &cfg->grid_a, &cfg->chunk_a, wa);
   if (fixed_launch) {
@@ -1294,19 +1462,36 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
         int32_t& ns = tside ? lps[i].nslot_st : lps[i].nslot_sa;
         for (size_t c = 0; c < W.chunks(); ++c)
           out.push_back(WinItem{lps[i].ctl, (int32_t)i, ns + (int32_t)c, W.r0[c], W.r1[c],
-                                W.pass0[c], W.npass[c]});
+                                W.pass0[c], W.npass[c], W.nseg[c], W.seg0[c]});
         ns += (int32_t)W.chunks();
       }
       // a multiple of 8 workgroups (above 8) spreads consecutive chunks of
       // one LP over one XCD at a time
       if (out.size() > 8)
-        while (out.size() % 8) out.push_back(WinItem{nullptr, -1, 0, 0, 0, 0, 0});
+        while (out.size() % 8) out.push_back(WinItem{nullptr, -1, 0, 0, 0, 0, 0, 0, 0});
     };
     wins(true, vt);
     wins(false, va);
+    // segmented long rows, kSegRows per workgroup, take the slots after the chunks
+    auto segs = [&](bool tside, std::vector<SegItem>& out) {
+      for (size_t i = 0; i < lps.size(); ++i) {
+        const WinPlan& W = tside ? preps[i]->win_t : preps[i]->win_a;
+        int32_t& ns = tside ? lps[i].nslot_st : lps[i].nslot_sa;
+        const int32_t nrows = (int32_t)W.srow.size();
+        for (int32_t s0 = 0, g = 0; s0 < nrows; s0 += kSegRows, ++g)
+          out.push_back(SegItem{lps[i].ctl, (int32_t)i, ns + g, s0, std::min(nrows, s0 + kSegRows)});
+        ns += (int32_t)W.seg_items();
+      }
+      if (out.size() > 8)
+        while (out.size() % 8) out.push_back(SegItem{nullptr, -1, 0, 0, 0});
+    };
+    segs(true, gt);
+    segs(false, ga);
   }
   cfg->nwin_t = (int)vt.size();
   cfg->nwin_a = (int)va.size();
+  cfg->nseg_t = (int)gt.size();
+  cfg->nseg_a = (int)ga.size();
   int64_t n_t = 0, n_a = 0;
   for (const Prepared* P : preps) {
     n_t += (int64_t)P->tiles_t.size();
@@ -1320,7 +1505,9 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   const size_t o_sa = o_st + align_up(sizeof(WorkItem) * st.size());
   const size_t o_vt = o_sa + align_up(sizeof(WorkItem) * sa.size());
   const size_t o_va = o_vt + align_up(sizeof(WinItem) * vt.size());
-  const size_t o_cn = o_va + align_up(sizeof(WinItem) * va.size());
+  const size_t o_gt = o_va + align_up(sizeof(WinItem) * va.size());
+  const size_t o_ga = o_gt + align_up(sizeof(SegItem) * gt.size());
+  const size_t o_cn = o_ga + align_up(sizeof(SegItem) * ga.size());
   const size_t o_bd = o_cn + align_up(sizeof(Counts));
   const size_t total = o_bd + align_up(sizeof(Ctl) * nl);
   if (capacity && total > capacity)
@@ -1334,6 +1521,8 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   if (!sa.empty()) std::memcpy(staging.data() + o_sa, sa.data(), sizeof(WorkItem) * sa.size());
   if (!vt.empty()) std::memcpy(staging.data() + o_vt, vt.data(), sizeof(WinItem) * vt.size());
   if (!va.empty()) std::memcpy(staging.data() + o_va, va.data(), sizeof(WinItem) * va.size());
+  if (!gt.empty()) std::memcpy(staging.data() + o_gt, gt.data(), sizeof(SegItem) * gt.size());
+  if (!ga.empty()) std::memcpy(staging.data() + o_ga, ga.data(), sizeof(SegItem) * ga.size());
   Counts cn{(int32_t)n_t, (int32_t)n_a, (int32_t)lps.size(), 0,
             cfg->grid_t, cfg->chunk_t, cfg->grid_a, cfg->chunk_a};
   std::memcpy(staging.data() + o_cn, &cn, sizeof(cn));
@@ -1346,6 +1535,8 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   cfg->step_a = fixed_launch ? cfg->work_a : reinterpret_cast<const WorkItem*>(dst + o_sa);
   cfg->win_t = reinterpret_cast<const WinItem*>(dst + o_vt);
   cfg->win_a = reinterpret_cast<const WinItem*>(dst + o_va);
+  cfg->seg_t = reinterpret_cast<const SegItem*>(dst + o_gt);
+  cfg->seg_a = reinterpret_cast<const SegItem*>(dst + o_ga);
   cfg->board = reinterpret_cast<Ctl*>(dst + o_bd);
   if (!fixed_launch) {
     cfg->launch_t = cfg->grid_t;

@@ -250,7 +250,7 @@ template <int NA, int NB>
 __device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, const double* pb,
                                               int sb, int cb, double (&out)[NA + NB],
                                               DD* s_red) {
-  constexpr int B = 4;
+  constexpr int B = 8;  // 2048 slots per round: one round of loads for most launch sets
   DD v[NA + NB];
 #pragma unroll
   for (int q = 0; q < NA + NB; ++q) v[q] = dd_zero();
@@ -1224,8 +1224,8 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   const gptr<const WinRange> ranges = uni(gp(tside ? lp->wrange_t : lp->wrange_a));
   const gptr<const float> vec = st.vecs[0];
   const int t = threadIdx.x;
-  const int r0 = uni(it.r0), nrow = uni(it.r1 - it.r0);
-  for (int r = t; r < nrow; r += kWinBlock) part[r] = 0.f;
+  const int r0 = uni(it.r0), nrow = uni(it.r1 - it.r0), nseg = uni(it.nseg);
+  for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;
   for (int ps = it.pass0; ps < it.pass0 + it.npass; ++ps) {
     const int pe0 = passes[ps].e0, pe1 = passes[ps].e1;
     const int pr0 = passes[ps].range0, prn = passes[ps].nrange;
@@ -1315,6 +1315,11 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   __syncthreads();
   DD p[NV];
   dd_reset(p);
+  // the segments' partial row sums go out for the finishing kernel
+  if (nseg > 0) {
+    const gptr<float> sp = gp(static_cast<float*>(tside ? lp->segp_t : lp->segp_a));
+    for (int q = t; q < nseg; q += kWinBlock) stg(sp, (uint32_t)(it.seg0 + q), part[nrow + q]);
+  }
   // two rows per thread in flight: their vector loads are issued together
   for (int r = t; r < nrow; r += 2 * kWinBlock) {
     const int r2 = r + kWinBlock;
@@ -1326,6 +1331,50 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   }
   block_sum<NV, kWinWaves>(p, s_red);
   store_partials<NV>(st.part(), st.stride(), it.slot, p);
+}
+
+// Segmented long rows (FP32): kSegLanes lanes per row. Lane l adds the
+// row's partials l, l + kSegLanes, ... in order, the lanes combine in a
+// fixed shuffle tree, and the row's first lane runs the row epilogue.
+template <typename Step, typename Pre, int NV>
+__device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* list, int nitems,
+                                         bool tside, int force) {
+  __shared__ DD s_red[4 * NV];
+  const int chi = chunk_index(nitems);
+  if (chi < 0) return;
+  const SegItem it = list[chi];
+  if (it.lp < 0) return;
+  Step st;
+  if (!st.begin(cfg, it.ctl, it.lp, it.slot, force)) return;
+  const LpDev* lp = st.lp;
+  const gptr<const float> sp = uni(gp(static_cast<const float*>(tside ? lp->segp_t : lp->segp_a)));
+  const gptr<const int32_t> srow = uni(gp(tside ? lp->srow_t : lp->srow_a));
+  const gptr<const int32_t> sptr = uni(gp(tside ? lp->sptr_t : lp->sptr_a));
+  const gptr<const int32_t> sids = uni(gp(tside ? lp->sids_t : lp->sids_a));
+  DD p[NV];
+  dd_reset(p);
+  const int lane = (int)threadIdx.x % kSegLanes;
+  const int q = it.s0 + (int)threadIdx.x / kSegLanes;
+  const bool on = q < it.s1;
+  const int qq = on ? q : it.s0;  // idle groups read row s0 and drop it
+  const int row = ldg(srow, (uint32_t)qq);
+  Pre pre = st.load(row);
+  const int k0 = ldg(sptr, (uint32_t)qq), k1 = ldg(sptr, (uint32_t)(qq + 1));
+  float acc = 0.f;
+  for (int k = k0 + lane; k < k1; k += kSegLanes) acc += ldg(sp, (uint32_t)ldg(sids, (uint32_t)k));
+#pragma unroll
+  for (int off = kSegLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSegLanes);
+  if (on && lane == 0) st.finish(row, acc, pre, p);
+  block_sum<NV>(p, s_red);
+  store_partials<NV>(st.part(), st.stride(), it.slot, p);
+}
+
+__global__ __launch_bounds__(kBlock) void k_primal_seg(LaunchCfg cfg, int force) {
+  seg_rows<PrimalStep<float>, PrimalPre<float>, 3>(cfg, cfg.seg_t, cfg.nseg_t, true, force);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dual_seg(LaunchCfg cfg, int force) {
+  seg_rows<DualStep<float>, DualPre<float>, 4>(cfg, cfg.seg_a, cfg.nseg_a, false, force);
 }
 
 __global__ __launch_bounds__(kWinBlock) void k_primal_win(LaunchCfg cfg, int force) {
@@ -1701,6 +1750,24 @@ int Kernels<V>::dual_win(const LaunchCfg& c, void* stream, int force) {
     hipLaunchKernelGGL(k_dual_win, dim3(c.nwin_a), dim3(kWinBlock), kWinLds,
                        (hipStream_t)stream, c, force);
     return launched();
+  }
+}
+template <typename V>
+int Kernels<V>::primal_seg(const LaunchCfg& c, void* stream, int force) {
+  if (c.nseg_t <= 0) return 0;
+  if constexpr (!std::is_same<V, float>::value) {
+    return -1;
+  } else {
+    OPDHG_LAUNCH(k_primal_seg, c.nseg_t, c, force);
+  }
+}
+template <typename V>
+int Kernels<V>::dual_seg(const LaunchCfg& c, void* stream, int force) {
+  if (c.nseg_a <= 0) return 0;
+  if constexpr (!std::is_same<V, float>::value) {
+    return -1;
+  } else {
+    OPDHG_LAUNCH(k_dual_seg, c.nseg_a, c, force);
   }
 }
 template <typename V>

@@ -31,11 +31,18 @@ int validate_params(const opdhg_params* p);
 // device-order CSR position of each (-1 for padding).
 struct WinPlan {
   std::vector<int32_t> r0, r1, pass0, npass;
+  std::vector<int32_t> nseg, seg0;  // per chunk: segments after its rows, first segment id
   std::vector<WinPass> passes;
   std::vector<WinRange> ranges;
   std::vector<uint16_t> col, row;
   std::vector<int64_t> src;
+  // long rows split into segments: the rows (device order), and per row the
+  // ids of its segments' partials in chunk order (CSR over srow)
+  std::vector<int32_t> srow, sptr, sids;
+  int32_t nsegs = 0;
   size_t chunks() const { return r0.size(); }
+  // workgroups of the finishing kernel (kSegRows segmented rows each)
+  size_t seg_items() const { return (srow.size() + kSegRows - 1) / kSegRows; }
 };
 
 // An LP after validation, rescaling and transposition, in FP64 on the host.
@@ -60,10 +67,12 @@ struct Prepared {
   double eta0 = 1.0, omega0 = 1.0;
   // partial slots per side: evaluation tiles, or step tiles plus windowed chunks
   int64_t part_stride_t() const {
-    return (int64_t)std::max(tiles_t.size(), stiles_t.size() + win_t.chunks());
+    return (int64_t)std::max(tiles_t.size(),
+                             stiles_t.size() + win_t.chunks() + win_t.seg_items());
   }
   int64_t part_stride_a() const {
-    return (int64_t)std::max(tiles_a.size(), stiles_a.size() + win_a.chunks());
+    return (int64_t)std::max(tiles_a.size(),
+                             stiles_a.size() + win_a.chunks() + win_a.seg_items());
   }
 };
 
@@ -80,6 +89,8 @@ struct SlotLayout {
   // windowed entries of each side (0 when none)
   size_t wcol_t = 0, wrow_t = 0, wval_t = 0, wpass_t = 0, wrange_t = 0;
   size_t wcol_a = 0, wrow_a = 0, wval_a = 0, wpass_a = 0, wrange_a = 0;
+  size_t segp_t = 0, srow_t = 0, sptr_t = 0, sids_t = 0;  // segmented rows (0 when none)
+  size_t segp_a = 0, srow_a = 0, sptr_a = 0, sids_a = 0;
   size_t total = 0;
 };
 

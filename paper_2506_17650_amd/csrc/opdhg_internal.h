@@ -116,7 +116,7 @@ constexpr int kWinNpt = 16;
 constexpr int kWinBucket = 1024;
 constexpr int kWinBuckets = 26;
 constexpr int kWinCap = kWinBuckets * kWinBucket;
-constexpr int kWinRows = 8192;
+constexpr int kWinRows = 10240;
 constexpr int kWinMaxPass = 4;
 constexpr int kWinWaves = kWinBlock / 64;
 // LDS of a windowed workgroup: window, row sums, per-thread carries, reduction
@@ -130,12 +130,23 @@ struct WinPass {
 struct WinRange {
   int32_t src, len;  // vector entries [src, src + len), device order
 };
-// A windowed chunk: rows [r0, r1) of one LP side, passes [pass0, pass0 + npass).
+// A windowed chunk: rows [r0, r1) of one LP side, passes [pass0, pass0 + npass),
+// then nseg segments of long rows (partials seg0 .. seg0 + nseg - 1).
 struct WinItem {
   Ctl* ctl;
   int32_t lp, slot;
   int32_t r0, r1;
   int32_t pass0, npass;
+  int32_t nseg, seg0;
+};
+// Segmented long rows [s0, s1) of one LP side's list, finished by one
+// workgroup: kSegLanes lanes per row add its partials.
+constexpr int kSegLanes = 16;
+constexpr int kSegRows = 256 / kSegLanes;
+struct SegItem {
+  Ctl* ctl;
+  int32_t lp, slot;
+  int32_t s0, s1;
 };
 
 // One LP slot as the kernels see it (device pointers into the workspace).
@@ -194,6 +205,16 @@ struct LpDev {
   const void* wval_a;
   const WinPass* wpass_a;
   const WinRange* wrange_a;
+  // long rows split into segments over windowed chunks: the segments'
+  // partial row sums (type V), the rows and their partials' ids (CSR)
+  void* segp_t;
+  const int32_t* srow_t;
+  const int32_t* sptr_t;
+  const int32_t* sids_t;
+  void* segp_a;
+  const int32_t* srow_a;
+  const int32_t* sptr_a;
+  const int32_t* sids_a;
 };
 
 // A set of LPs launched together. A work item is one tile of one LP, with
@@ -250,6 +271,9 @@ struct LaunchCfg {
   int nwin_t, nwin_a;  // windowed chunks per side (launch grid rounded up to 8)
   int step_fixed;
   int pad_;
+  const SegItem* seg_t;  // segmented long rows, finished after the windowed chunks
+  const SegItem* seg_a;
+  int nseg_t, nseg_a;
 };
 
 template <typename V>
@@ -260,6 +284,9 @@ struct Kernels {
   // windowed chunks of each side (FP32 only; nothing to launch when the set has none)
   static int primal_win(const LaunchCfg& c, void* stream, int force);
   static int dual_win(const LaunchCfg& c, void* stream, int force = 0);
+  // segmented long rows: adds each row's segment partials and runs its epilogue
+  static int primal_seg(const LaunchCfg& c, void* stream, int force);
+  static int dual_seg(const LaunchCfg& c, void* stream, int force = 0);
   static int decide(const LaunchCfg& c, void* stream);
   static int learn_flush(const LaunchCfg& c, void* stream);
   static int eval_t(const LaunchCfg& c, void* stream);

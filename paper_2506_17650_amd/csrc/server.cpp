@@ -608,6 +608,8 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
   L.step_fixed = 0;
   L.win_t = L.win_a = nullptr;
   L.nwin_t = L.nwin_a = 0;
+  L.seg_t = L.seg_a = nullptr;
+  L.nseg_t = L.nseg_a = 0;
   const int g8 = (int)((S.wg_cap + 7) / 8 * 8);
   L.launch_t = L.launch_a = L.launch_ta = g8;
   L.launch_lp = std::min(cfg->max_active, kGridCap);

@@ -72,14 +72,36 @@ CASES = [
 ]
 
 
+def _block_long():
+    """6 blocks of 3000 x 8000 and 40 linking rows of 600 nonzeros: the
+    linking rows are long, so they run as segments of the block chunks."""
+    from lpgen import block_angular_lp
+    return block_angular_lp(7, blocks=6, block_rows=3000, block_cols=8000, col_degree=6,
+                            link_rows=40, link_nnz_per_row=600)
+
+
+CASES_LONG = [
+    dict(window_buckets=0, window_rows=0),     # A rows windowed, linking rows as segments
+    dict(window_buckets=2, window_rows=1500),  # A^T rows windowed in up to 3 passes
+]
+
+
+@pytest.mark.parametrize("kw", CASES_LONG)
+def test_segmented_rows_trace_close_to_oracle(P, kw):
+    _trace_case(P, _block_long(), kw, "block LP with long linking rows")
+
+
 @pytest.mark.parametrize("kw", CASES)
 def test_windowed_trace_close_to_oracle(P, kw):
-    lp = config_lp("cfg2", scale=0.1)
+    _trace_case(P, config_lp("cfg2", scale=0.1), kw, "cfg2x0.1")
+
+
+def _trace_case(P, lp, kw, label):
     op = default_params(max_iter=100000, lr=1e-3, phi=5)
     K = 30
     ref = oracle.solve(lp, op, trace=K, stop_k=K)
     tr = {e.k: e for e in ref.trace}
-    _say(f"[windows trace] cfg2x0.1 m={lp.m} n={lp.n} nnz={lp.nnz} {kw}")
+    _say(f"[windows trace] {label} m={lp.m} n={lp.n} nnz={lp.nnz} {kw}")
     worst = 0.0
     with P.Session(lp, _lib(P, op, **kw)) as s:
         for k in (1, 2, 5, 10, 20, 30):
@@ -113,7 +135,7 @@ def test_windowed_solve_matches_tiles_and_oracle(P):
 
 def test_windowed_rerun_bit_identical_and_batch_equals_solo(P):
     lps = [config_lp("cfg2", scale=0.1), config_lp("cfg1", scale=0.05),
-           config_lp("cfg2", scale=0.1, seed=5)]
+           config_lp("cfg2", scale=0.1, seed=5), _block_long()]
     _say("[windows determinism]")
     p = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=3000, lr=1e-3, window_buckets=3,
                                windows=P.OPDHG_WINDOWS_ALWAYS)
