@@ -201,6 +201,18 @@ def section_hbm(P, args):
     log(f"[bench] hbm: {r['iters'] / r['seconds']:.0f} iters/s, primal "
         f"{r['kernels']['primal']['achieved_GBs']:.0f} GB/s, dual "
         f"{r['kernels']['dual']['achieved_GBs']:.0f} GB/s")
+    # HBM traffic of each step from the committed counter summaries: the
+    # primal step is the windowed kernel; the dual step is the windowed
+    # kernel, the tile kernel of the rows left in tiles (beside it) and the
+    # segmented linking rows' finish
+    parts = {"primal": ["k_primal_win"], "dual": ["k_dual_win", "k_dual", "k_dual_seg"]}
+    for side, names in parts.items():
+        vals = [counter_traffic(nm, "cfg2", "fp32") for nm in names]
+        k = r["kernels"][side]
+        k["kernels"] = names
+        k["traffic"] = None if any(v is None for v in vals) else sum(vals)
+        if k["traffic"] is not None:
+            k["traffic_GBs"] = k["traffic"] / (k["avg_launch_ms"] * 1e-3) / 1e9
     return {"workload": "cfg2: block-angular LP, 64 blocks of 30k x 80k + 2k linking rows",
             "m": lp.m, "n": lp.n, "nnz": lp.nnz, "dtype": "f32",
             "value": r["iters"] / r["seconds"], "unit": "PDHG iters/s",
