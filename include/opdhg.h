@@ -92,6 +92,12 @@ extern "C" {
 #define OPDHG_WINDOWS_OFF 1    /* every row in tiles that gather from global memory */
 #define OPDHG_WINDOWS_ALWAYS 2 /* every windowable chunk, however few (small LPs, checks) */
 
+/* ---- where the rescaling and the scaled data are computed ---- */
+#define OPDHG_PREP_AUTO 0   /* on the device for LPs of 2^20 nonzeros or more, else on the host */
+#define OPDHG_PREP_HOST 1   /* host threads (FP64) */
+#define OPDHG_PREP_DEVICE 2 /* device kernels (FP64), same results; not with OPDHG_STEP_CONSTANT,
+                               whose power iteration runs on the host */
+
 /* ---- restart scheme ---- */
 #define OPDHG_RESTART_ADAPTIVE 0 /* PDLP's KKT-based restarts, preconditioners kept (Section 3.2) */
 #define OPDHG_RESTART_NONE 1     /* vanilla PDHG (Section 4.2): evaluations test termination only;
@@ -147,6 +153,7 @@ typedef struct opdhg_params {
   int32_t windows;       /* OPDHG_WINDOWS_*: FP32 only; FP64 and the server never use windows */
   int32_t window_buckets; /* LDS window per pass in buckets of 1024 entries, 1..26; 0: 26 */
   int32_t window_rows;   /* rows per windowed chunk, 1..10240; 0: picked from the side's size */
+  int32_t prep;          /* OPDHG_PREP_*: rescaling passes and scaled data on the host or device */
 } opdhg_params;
 
 typedef struct opdhg_result {

@@ -35,4 +35,7 @@ from .capi import (  # noqa: F401
     OPDHG_WINDOWS_AUTO,
     OPDHG_WINDOWS_OFF,
     OPDHG_WINDOWS_ALWAYS,
+    OPDHG_PREP_AUTO,
+    OPDHG_PREP_HOST,
+    OPDHG_PREP_DEVICE,
 )

@@ -49,6 +49,9 @@ OPDHG_STEP_NORM_PRECOND = 1
 OPDHG_WINDOWS_AUTO = 0
 OPDHG_WINDOWS_OFF = 1
 OPDHG_WINDOWS_ALWAYS = 2
+OPDHG_PREP_AUTO = 0
+OPDHG_PREP_HOST = 1
+OPDHG_PREP_DEVICE = 2
 
 _p = ctypes.POINTER
 c_i64, c_i32, c_dbl, c_sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
@@ -75,7 +78,7 @@ class opdhg_params(ctypes.Structure):
         ("step_rule", c_i32), ("restart_scheme", c_i32), ("l2_rescale", c_i32),
         ("power_iters", c_i32), ("step_scale", c_dbl), ("power_tol", c_dbl),
         ("step_norm", c_i32), ("windows", c_i32), ("window_buckets", c_i32),
-        ("window_rows", c_i32),
+        ("window_rows", c_i32), ("prep", c_i32),
     ]
 
 

@@ -132,6 +132,11 @@ int validate_params(const opdhg_params* p) {
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_buckets must be in [0, 26]");
   if (p->window_rows < 0 || p->window_rows > kWinRows)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_rows must be in [0, 10240]");
+  if (p->prep < OPDHG_PREP_AUTO || p->prep > OPDHG_PREP_DEVICE)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "prep must be OPDHG_PREP_AUTO, _HOST or _DEVICE");
+  if (p->prep == OPDHG_PREP_DEVICE && p->step_rule == OPDHG_STEP_CONSTANT)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT,
+                "the constant step's power iteration needs host preparation");
   return OPDHG_OK;
 }
 
@@ -214,12 +219,12 @@ struct ColIndex {
   RawArray<double> cabs;  // |value| in the same order, read sequentially by column passes
 };
 
-static void build_col_index(const opdhg_lp* lp, ColIndex& C) {
+static void build_col_index(const opdhg_lp* lp, ColIndex& C, bool with_abs = true) {
   const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
   C.cstart.assign(n + 1, 0);
   C.cpos.reset(nnz);
   C.crow.reset(nnz);
-  C.cabs.reset(nnz);
+  if (with_abs) C.cabs.reset(nnz);
   // a counting sort by column in parallel: thread t takes a range of rows
   // (in row order), counts its columns, and scatters its entries to the
   // positions after those of threads t' < t, so rows stay ascending within
@@ -268,7 +273,7 @@ static void build_col_index(const opdhg_lp* lp, ColIndex& C) {
         const int64_t q = C.cstart[j] + off[j]++;
         C.cpos[q] = k;
         C.crow[q] = (int32_t)i;
-        C.cabs[q] = std::fabs(lp->val[k]);
+        if (with_abs) C.cabs[q] = std::fabs(lp->val[k]);
       }
   });
 }
@@ -797,6 +802,12 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.tiles_t = build_tiles(out.rp_t.data(), n, cap, p->lanes);
   // windowed chunks need the device-order column indices, also for sizing
   const bool windows = p->precision == OPDHG_FP32 && p->windows != OPDHG_WINDOWS_OFF;
+  // device-side preparation: the rescaling and the scaled data on the GPU
+  out.dprep = p->step_rule != OPDHG_STEP_CONSTANT &&
+              (p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz));
+  out.prep_ruiz = p->ruiz_iters;
+  out.prep_l2 = p->l2_rescale != 0;
+  out.prep_beta = p->pc_beta;
   if (structure_only && !windows) {
     out.stiles_a = out.tiles_a;
     out.stiles_t = out.tiles_t;
@@ -808,17 +819,22 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   for (int64_t j = 0; j < n; ++j) inv_t[out.perm_t[j]] = (int32_t)j;
   std::vector<double> sval;
   ColIndex C;
-  build_col_index(lp, C);
+  build_col_index(lp, C, !out.dprep);
   double spec = -1.0;
-  if (!structure_only) {
+  if (!structure_only && !out.dprep) {
     rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, out.dr, out.dc);
     if (p->step_rule == OPDHG_STEP_CONSTANT)
       spec = spectral_norm_with(lp, C, sval, p->power_iters, p->power_tol);
   }
+  // values go to the device order: scaled on the host, or unscaled (raw)
+  // for the device-side preparation
   const bool vals = !structure_only;
+  const double* vsrc = out.dprep ? lp->val : sval.data();
   // A in device order: row i' is original row perm_a[i'], columns relabelled
   out.ci_a.resize(nnz);
-  if (vals) out.va_a.resize(nnz);
+  std::vector<double>& dst_a = out.dprep ? out.raw_a : out.va_a;
+  std::vector<double>& dst_t = out.dprep ? out.raw_t : out.va_t;
+  if (vals) dst_a.resize(nnz);
   {
     std::vector<int64_t> dptr(m + 1);  // nonzero offsets in device order, for balancing
     for (int64_t i2 = 0; i2 <= m; ++i2) dptr[i2] = out.rp_a[i2];
@@ -828,7 +844,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
         int64_t pos = out.rp_a[i2];
         for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k, ++pos) {
           out.ci_a[pos] = inv_t[lp->col_idx[k]];
-          if (vals) out.va_a[pos] = sval[k];
+          if (vals) dst_a[pos] = vsrc[k];
         }
       }
     });
@@ -836,7 +852,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   // A^T in device order: row j' is original column perm_t[j']; entries in
   // ascending original row, labelled with device row indices
   out.ci_t.resize(nnz);
-  if (vals) out.va_t.resize(nnz);
+  if (vals) dst_t.resize(nnz);
   {
     std::vector<int64_t> dptr(n + 1);
     for (int64_t j2 = 0; j2 <= n; ++j2) dptr[j2] = out.rp_t[j2];
@@ -846,7 +862,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
         int64_t pos = out.rp_t[j2];
         for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q, ++pos) {
           out.ci_t[pos] = inv_a[C.crow[q]];
-          if (vals) out.va_t[pos] = sval[C.cpos[q]];
+          if (vals) dst_t[pos] = vsrc[C.cpos[q]];
         }
       }
     });
@@ -870,23 +886,46 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   }
   step_tiles(out, cap, p->lanes);
   if (structure_only) return OPDHG_OK;
-  out.b.resize(m);
+  if (out.dprep) {
+    // unscaled vectors in device order; the device scales them
+    out.raw_b.resize(m);
+    out.sense.resize(m);
+    for (int64_t i2 = 0; i2 < m; ++i2) {
+      const int64_t i = out.perm_a[i2];
+      out.raw_b[i2] = lp->b[i];
+      out.sense[i2] = lp->row_sense[i];
+    }
+    out.raw_c.resize(n);
+    out.raw_l.resize(n);
+    out.raw_u.resize(n);
+    out.bfin.resize(n);
+    for (int64_t j2 = 0; j2 < n; ++j2) {
+      const int64_t j = out.perm_t[j2];
+      out.raw_c[j2] = lp->c[j];
+      out.raw_l[j2] = lp->l[j];
+      out.raw_u[j2] = lp->u[j];
+      out.bfin[j2] =
+          (int8_t)((std::isfinite(lp->l[j]) ? 1 : 0) | (std::isfinite(lp->u[j]) ? 2 : 0));
+    }
+  }
+  out.b.resize(out.dprep ? 0 : m);
   out.sense.resize(m);
-  out.dr_dev.resize(m);
+  out.dr_dev.resize(out.dprep ? 0 : m);
 
-  for (int64_t i2 = 0; i2 < m; ++i2) {
+  for (int64_t i2 = 0; i2 < m && !out.dprep; ++i2) {
     const int64_t i = out.perm_a[i2];
     out.b[i2] = out.dr[i] * lp->b[i];
     out.sense[i2] = lp->row_sense[i];
     out.dr_dev[i2] = out.dr[i];
   }
-  out.c.resize(n);
-  out.l.resize(n);
-  out.u.resize(n);
-  out.bfin.resize(n);
-  out.x0.resize(n);
-  out.dc_dev.resize(n);
-  for (int64_t j2 = 0; j2 < n; ++j2) {
+  const int64_t nh = out.dprep ? 0 : n;
+  out.c.resize(nh);
+  out.l.resize(nh);
+  out.u.resize(nh);
+  if (!out.dprep) out.bfin.resize(n);
+  out.x0.resize(nh);
+  out.dc_dev.resize(nh);
+  for (int64_t j2 = 0; j2 < nh; ++j2) {
     const int64_t j = out.perm_t[j2];
     out.c[j2] = out.dc[j] * lp->c[j];
     out.l[j2] = lp->l[j] / out.dc[j];
@@ -896,15 +935,17 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
     out.x0[j2] = std::min(std::max(z, out.l[j2]), out.u[j2]);
     out.dc_dev[j2] = out.dc[j];
   }
-  double amax = 0.0;
-  for (int64_t k = 0; k < nnz; ++k) amax = std::max(amax, std::fabs(sval[k]));
-  const double bsn = dd_norm(out.b.data(), m);
-  const double csn = dd_norm(out.c.data(), n);
-  out.omega0 = (csn > 1e-10 && bsn > 1e-10) ? csn / bsn : 1.0;
-  if (p->step_rule == OPDHG_STEP_CONSTANT)
-    out.eta0 = spec > 0.0 ? p->step_scale / spec : p->step_scale;
-  else
-    out.eta0 = amax > 0.0 ? 1.0 / amax : 1.0;
+  if (!out.dprep) {
+    double amax = 0.0;
+    for (int64_t k = 0; k < nnz; ++k) amax = std::max(amax, std::fabs(sval[k]));
+    const double bsn = dd_norm(out.b.data(), m);
+    const double csn = dd_norm(out.c.data(), n);
+    out.omega0 = (csn > 1e-10 && bsn > 1e-10) ? csn / bsn : 1.0;
+    if (p->step_rule == OPDHG_STEP_CONSTANT)
+      out.eta0 = spec > 0.0 ? p->step_scale / spec : p->step_scale;
+    else
+      out.eta0 = amax > 0.0 ? 1.0 / amax : 1.0;
+  }
   DevParams& d = out.prm;
   std::memset(&d, 0, sizeof(d));
   d.tol = p->tol;
@@ -1011,6 +1052,19 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
       L.sptr_a = take(4 * P.win_a.sptr.size());
       L.sids_a = take(4 * P.win_a.sids.size());
     }
+  }
+  if (P.dprep) {
+    L.raw_a = take(8 * nnz);
+    L.raw_t = take(8 * nnz);
+    L.raw_b = take(8 * m);
+    L.raw_c = take(8 * n);
+    L.raw_l = take(8 * n);
+    L.raw_u = take(8 * n);
+    L.sr = take(8 * m);
+    L.sc = take(8 * n);
+    L.pscr = take(8 * (4 * kPrepGrid + 3));
+    if (P.win_t.chunks()) L.wsrc_t = take(4 * P.win_t.src.size());
+    if (P.win_a.chunks()) L.wsrc_a = take(4 * P.win_a.src.size());
   }
   L.total = off;
   return L;
@@ -1122,8 +1176,12 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
   put_vec<V>(img, L.va_t, P.va_t);
   auto put_win = [&](const WinPlan& W, const std::vector<double>& va, size_t oc, size_t orow,
                      size_t ov, size_t opass, size_t orange, size_t osrow, size_t osptr,
-                     size_t osids) {
+                     size_t osids, size_t owsrc) {
     if (!W.chunks()) return;
+    if (P.dprep) {  // the device fills the values from the scaled entries they stand for
+      int32_t* ws = reinterpret_cast<int32_t*>(img.data() + owsrc);
+      for (size_t e = 0; e < W.src.size(); ++e) ws[e] = (int32_t)W.src[e];
+    }
     if (!W.srow.empty()) {
       std::memcpy(img.data() + osrow, W.srow.data(), 4 * W.srow.size());
       std::memcpy(img.data() + osptr, W.sptr.data(), 4 * W.sptr.size());
@@ -1132,14 +1190,31 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
     std::memcpy(img.data() + oc, W.col.data(), 2 * W.col.size());
     std::memcpy(img.data() + orow, W.row.data(), 2 * W.row.size());
     V* dst = reinterpret_cast<V*>(img.data() + ov);
-    for (size_t e = 0; e < W.src.size(); ++e) dst[e] = W.src[e] < 0 ? V(0) : (V)va[W.src[e]];
+    if (!P.dprep)
+      for (size_t e = 0; e < W.src.size(); ++e) dst[e] = W.src[e] < 0 ? V(0) : (V)va[W.src[e]];
     std::memcpy(img.data() + opass, W.passes.data(), sizeof(WinPass) * W.passes.size());
     std::memcpy(img.data() + orange, W.ranges.data(), sizeof(WinRange) * W.ranges.size());
   };
   put_win(P.win_t, P.va_t, L.wcol_t, L.wrow_t, L.wval_t, L.wpass_t, L.wrange_t, L.srow_t,
-          L.sptr_t, L.sids_t);
+          L.sptr_t, L.sids_t, L.wsrc_t);
   put_win(P.win_a, P.va_a, L.wcol_a, L.wrow_a, L.wval_a, L.wpass_a, L.wrange_a, L.srow_a,
-          L.sptr_a, L.sids_a);
+          L.sptr_a, L.sids_a, L.wsrc_a);
+  if (P.dprep) {
+    auto put64 = [&](size_t o, const std::vector<double>& v) {
+      if (!v.empty()) std::memcpy(img.data() + o, v.data(), 8 * v.size());
+    };
+    put64(L.raw_a, P.raw_a);
+    put64(L.raw_t, P.raw_t);
+    put64(L.raw_b, P.raw_b);
+    put64(L.raw_c, P.raw_c);
+    put64(L.raw_l, P.raw_l);
+    put64(L.raw_u, P.raw_u);
+    // the diagonals start at 1; the device rescales them
+    double* dr = reinterpret_cast<double*>(img.data() + L.dr);
+    for (int64_t i = 0; i < P.m; ++i) dr[i] = 1.0;
+    double* dc = reinterpret_cast<double*>(img.data() + L.dc);
+    for (int64_t j = 0; j < P.n; ++j) dc[j] = 1.0;
+  }
   // n-vectors: c l u T Hp Gp x0 x1 xs0 xs1 xa
   put_vec<V>(img, L.vn[0], P.c);
   put_vec<V>(img, L.vn[1], P.l);
@@ -1549,11 +1624,78 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   return OPDHG_OK;
 }
 
-int upload_slot(uint8_t* base, const SlotLayout& L, const Prepared& P, int prec,
-                hipStream_t stream, std::vector<uint8_t>& img) {
+// The preparation kernels of a slot prepared on the device, then the
+// diagonals (for unscaling results) and the first step size and primal
+// weight back to the host.
+static int device_prepare(uint8_t* base, const SlotLayout& L, Prepared& P, int prec,
+                          hipStream_t stream) {
+  const LpDev d = slot_pointers(base, L, P);
+  PrepCfg c{};
+  c.rp_a = d.rp_a;
+  c.ci_a = d.ci_a;
+  c.rp_t = d.rp_t;
+  c.ci_t = d.ci_t;
+  c.raw_a = reinterpret_cast<const double*>(base + L.raw_a);
+  c.raw_t = reinterpret_cast<const double*>(base + L.raw_t);
+  c.raw_b = reinterpret_cast<const double*>(base + L.raw_b);
+  c.raw_c = reinterpret_cast<const double*>(base + L.raw_c);
+  c.raw_l = reinterpret_cast<const double*>(base + L.raw_l);
+  c.raw_u = reinterpret_cast<const double*>(base + L.raw_u);
+  c.dr = reinterpret_cast<double*>(base + L.dr);
+  c.dc = reinterpret_cast<double*>(base + L.dc);
+  c.sr = reinterpret_cast<double*>(base + L.sr);
+  c.sc = reinterpret_cast<double*>(base + L.sc);
+  c.scr = reinterpret_cast<double*>(base + L.pscr);
+  c.va_a = const_cast<void*>(d.va_a);
+  c.va_t = const_cast<void*>(d.va_t);
+  c.b = d.b;
+  c.c = d.c;
+  c.l = d.l;
+  c.u = d.u;
+  c.x0 = d.x[0];
+  c.xa = d.xa;
+  c.wval_t = const_cast<void*>(d.wval_t);
+  c.wval_a = const_cast<void*>(d.wval_a);
+  c.wsrc_t = P.win_t.chunks() ? reinterpret_cast<const int32_t*>(base + L.wsrc_t) : nullptr;
+  c.wsrc_a = P.win_a.chunks() ? reinterpret_cast<const int32_t*>(base + L.wsrc_a) : nullptr;
+  c.went_t = P.win_t.chunks() ? (int64_t)P.win_t.src.size() : 0;
+  c.went_a = P.win_a.chunks() ? (int64_t)P.win_a.src.size() : 0;
+  c.ctl = d.ctl;
+  c.m = (int32_t)P.m;
+  c.n = (int32_t)P.n;
+  int rc = 0;
+  // Ruiz passes, the L2 pass, the Pock-Chambolle pass (Section 2), as on the host
+  for (int it = 0; it < P.prep_ruiz && !rc; ++it)
+    rc = prep_stats(c, stream, false, 0, 0.0) | prep_stats(c, stream, true, 0, 0.0) |
+         prep_apply(c, stream);
+  if (!rc && P.prep_l2)
+    rc = prep_stats(c, stream, false, 2, 0.0) | prep_stats(c, stream, true, 2, 0.0) |
+         prep_apply(c, stream);
+  if (!rc && P.prep_beta >= 0.0)
+    rc = prep_stats(c, stream, false, 1, P.prep_beta) |
+         prep_stats(c, stream, true, 1, 2.0 - P.prep_beta) | prep_apply(c, stream);
+  if (!rc) rc = prec == OPDHG_FP32 ? prep_finish<float>(c, stream) : prep_finish<double>(c, stream);
+  if (rc) return fail(OPDHG_ERR_DEVICE, std::string("preparation kernels: ") + device_error_string());
+  std::vector<double> dr(P.m), dc(P.n), sc(2);
+  if (P.m) HIP_TRY(hipMemcpyAsync(dr.data(), c.dr, 8 * P.m, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(dc.data(), c.dc, 8 * P.n, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(sc.data(), c.scr + 4 * kPrepGrid + 1, 16, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  P.dr.assign(P.m, 1.0);
+  P.dc.assign(P.n, 1.0);
+  for (int64_t i2 = 0; i2 < P.m; ++i2) P.dr[P.perm_a[i2]] = dr[i2];
+  for (int64_t j2 = 0; j2 < P.n; ++j2) P.dc[P.perm_t[j2]] = dc[j2];
+  P.eta0 = sc[0];
+  P.omega0 = sc[1];
+  return OPDHG_OK;
+}
+
+int upload_slot(uint8_t* base, const SlotLayout& L, Prepared& P, int prec, hipStream_t stream,
+                std::vector<uint8_t>& img) {
   if (prec == OPDHG_FP32) slot_image<float>(L, P, img);
   else slot_image<double>(L, P, img);
   HIP_TRY(hipMemcpyAsync(base, img.data(), L.total, hipMemcpyHostToDevice, stream));
+  if (P.dprep) return device_prepare(base, L, P, prec, stream);
   return OPDHG_OK;
 }
 
@@ -1711,6 +1853,7 @@ void opdhg_default_params(opdhg_params* p) {
   p->windows = OPDHG_WINDOWS_AUTO;
   p->window_buckets = 0;
   p->window_rows = 0;
+  p->prep = OPDHG_PREP_AUTO;
 }
 
 int opdhg_validate(const opdhg_lp* lp) { return validate_lp(lp); }

@@ -55,6 +55,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -1710,6 +1711,166 @@ template <typename V>
 int Kernels<V>::dual(const LaunchCfg& c, void* stream, int force) {
   OPDHG_LAUNCH(k_dual<V>, c.step_fixed ? c.sgrid_a : c.launch_a, c, force);
 }
+// ---------------------------------------------------------------------------
+// device-side preparation (FP64)
+// ---------------------------------------------------------------------------
+
+// The host's double-double accumulator, operation for operation (the
+// preparation on either side gives the same bits).
+struct SeqDD {
+  double hi = 0.0, lo = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    const double s = hi + x;
+    const double bb = s - hi;
+    lo += (hi - (s - bb)) + (x - bb);
+    hi = s;
+  }
+  __device__ __forceinline__ void add_prod(double a, double b) {
+    const double p = a * b;
+    add(p);
+    lo += fma(a, b, -p);
+  }
+  __device__ __forceinline__ double value() const { return hi + lo; }
+};
+
+// Row statistics of |a~_ij| = |a_ij| d_r,i d_c,j over the rows of A
+// (tside 0) or of A^T (tside 1, a row per column of A), one thread per row,
+// entries in stored order.
+__global__ __launch_bounds__(kBlock) void k_prep_stats(PrepCfg a, int tside, int kind, double e) {
+  const int rows = tside ? a.n : a.m;
+  const int32_t* rp = tside ? a.rp_t : a.rp_a;
+  const int32_t* ci = tside ? a.ci_t : a.ci_a;
+  const double* raw = tside ? a.raw_t : a.raw_a;
+  double* out = tside ? a.sc : a.sr;
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < rows; r += gridDim.x * kBlock) {
+    double mx = 0.0;
+    SeqDD acc;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) {
+      const double v = fabs(raw[k]);
+      const double x = tside ? (v * a.dr[ci[k]]) * a.dc[r] : (v * a.dr[r]) * a.dc[ci[k]];
+      if (kind == 0) mx = mx < x ? x : mx;
+      else if (kind == 1) acc.add(e == 1.0 ? x : pow(x, e));
+      else acc.add(x * x);
+    }
+    out[r] = kind == 0 ? mx : (kind == 1 ? acc.value() : sqrt(acc.value()));
+  }
+}
+
+// d_r /= sqrt(s_r), d_c /= sqrt(s_c), a zero statistic read as 1.
+__global__ __launch_bounds__(kBlock) void k_prep_apply(PrepCfg a) {
+  const int tot = a.m + a.n;
+  for (int q = blockIdx.x * kBlock + threadIdx.x; q < tot; q += gridDim.x * kBlock) {
+    if (q < a.m) a.dr[q] = a.dr[q] / sqrt(a.sr[q] == 0.0 ? 1.0 : a.sr[q]);
+    else {
+      const int j = q - a.m;
+      a.dc[j] = a.dc[j] / sqrt(a.sc[j] == 0.0 ? 1.0 : a.sc[j]);
+    }
+  }
+}
+
+// Scaled values of both CSR copies, (a_ij d_r,i) d_c,j as the host forms
+// them, and the largest |a~_ij| (order free: the maximum of the bit
+// patterns of positive doubles).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_prep_values(PrepCfg a) {
+  __shared__ unsigned long long s_max;
+  if (threadIdx.x == 0) s_max = 0ull;
+  __syncthreads();
+  unsigned long long mx = 0ull;
+  V* va = static_cast<V*>(a.va_a);
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.m; r += gridDim.x * kBlock)
+    for (int k = a.rp_a[r]; k < a.rp_a[r + 1]; ++k) {
+      const double v = (a.raw_a[k] * a.dr[r]) * a.dc[a.ci_a[k]];
+      va[k] = (V)v;
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
+      mx = mx < bits ? bits : mx;
+    }
+  V* vt = static_cast<V*>(a.va_t);
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.n; r += gridDim.x * kBlock)
+    for (int k = a.rp_t[r]; k < a.rp_t[r + 1]; ++k) vt[k] = (V)((a.raw_t[k] * a.dr[a.ci_t[k]]) * a.dc[r]);
+  atomicMax(&s_max, mx);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(a.scr + 4 * kPrepGrid), s_max);
+}
+
+// Scaled vectors in V (b~ = d_r b, c~ = d_c c, l~ = l / d_c, u~ = u / d_c),
+// the start point x = clamp(0, l~, u~), and per-workgroup double-double
+// partials of |b~|^2 and |c~|^2 in FP64.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_prep_vectors(PrepCfg a) {
+  __shared__ DD s_red[4 * 2];
+  DD p[2];
+  p[0] = dd_zero();
+  p[1] = dd_zero();
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.m; i += gridDim.x * kBlock) {
+    const double bi = a.dr[i] * a.raw_b[i];
+    static_cast<V*>(a.b)[i] = (V)bi;
+    dd_add_prod(p[0], bi, bi);
+  }
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+    const double cj = a.dc[j] * a.raw_c[j];
+    const double lj = a.raw_l[j] / a.dc[j];
+    const double uj = a.raw_u[j] / a.dc[j];
+    const double t = 0.0 < lj ? lj : 0.0;
+    const double x0 = uj < t ? uj : t;
+    static_cast<V*>(a.c)[j] = (V)cj;
+    static_cast<V*>(a.l)[j] = (V)lj;
+    static_cast<V*>(a.u)[j] = (V)uj;
+    static_cast<V*>(a.x0)[j] = (V)x0;
+    static_cast<V*>(a.xa)[j] = (V)x0;
+    dd_add_prod(p[1], cj, cj);
+  }
+  block_sum<2>(p, s_red);
+  if (threadIdx.x == 0) {
+    a.scr[4 * blockIdx.x + 0] = p[0].hi;
+    a.scr[4 * blockIdx.x + 1] = p[0].lo;
+    a.scr[4 * blockIdx.x + 2] = p[1].hi;
+    a.scr[4 * blockIdx.x + 3] = p[1].lo;
+  }
+}
+
+// Windowed entries' values: copies of the scaled values they stand for.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_prep_windows(PrepCfg a) {
+  const int64_t tot = a.went_t + a.went_a;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < tot; e += (int64_t)gridDim.x * kBlock) {
+    if (e < a.went_t) {
+      const int32_t s = a.wsrc_t[e];
+      static_cast<V*>(a.wval_t)[e] = s < 0 ? V(0) : static_cast<const V*>(a.va_t)[s];
+    } else {
+      const int64_t f = e - a.went_t;
+      const int32_t s = a.wsrc_a[f];
+      static_cast<V*>(a.wval_a)[f] = s < 0 ? V(0) : static_cast<const V*>(a.va_a)[s];
+    }
+  }
+}
+
+// The first step size 1 / max |a~_ij| and primal weight |c~| / |b~| (1
+// when either is below 1e-10): into the control block and scr.
+__global__ __launch_bounds__(kBlock) void k_prep_scalars(PrepCfg a) {
+  __shared__ DD s_red[4 * 2];
+  DD p[2];
+  p[0] = dd_zero();
+  p[1] = dd_zero();
+  if (threadIdx.x == 0) {
+    for (int g = 0; g < kPrepGrid; ++g) {
+      p[0] = dd_merge(p[0], DD{a.scr[4 * g + 0], a.scr[4 * g + 1]});
+      p[1] = dd_merge(p[1], DD{a.scr[4 * g + 2], a.scr[4 * g + 3]});
+    }
+    const double bsn = sqrt(dd_value(p[0])), csn = sqrt(dd_value(p[1]));
+    const double amax = __longlong_as_double(
+        (long long)*reinterpret_cast<const unsigned long long*>(a.scr + 4 * kPrepGrid));
+    const double eta0 = amax > 0.0 ? 1.0 / amax : 1.0;
+    const double om0 = (csn > 1e-10 && bsn > 1e-10) ? csn / bsn : 1.0;
+    a.ctl->eta = eta0;
+    a.ctl->omega = om0;
+    a.scr[4 * kPrepGrid + 1] = eta0;
+    a.scr[4 * kPrepGrid + 2] = om0;
+  }
+  (void)s_red;
+}
+
 // The windowed kernels take more than the default 64 KiB of LDS; the
 // attribute is set once per process, before the first launch.
 static int win_attributes() {
@@ -1796,6 +1957,40 @@ int Kernels<V>::apply(const LaunchCfg& c, void* stream) {
 }
 
 int launch_board(const LaunchCfg& c, void* stream) { OPDHG_LAUNCH(k_board, c.launch_lp, c); }
+
+int prep_stats(const PrepCfg& c, void* stream, bool tside, int kind, double e) {
+  const int rows = tside ? c.n : c.m;
+  const int grid = std::max(1, std::min(4096, (rows + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_prep_stats, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, c,
+                     tside ? 1 : 0, kind, e);
+  return launched();
+}
+
+int prep_apply(const PrepCfg& c, void* stream) {
+  const int grid = std::max(1, std::min(4096, (c.m + c.n + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_prep_apply, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, c);
+  return launched();
+}
+
+template <typename V>
+int prep_finish(const PrepCfg& c, void* stream) {
+  const int rows = std::max(c.m, c.n);
+  const int grid = std::max(1, std::min(4096, (rows + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_prep_values<V>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, c);
+  if (launched()) return -1;
+  hipLaunchKernelGGL(k_prep_vectors<V>, dim3(kPrepGrid), dim3(kBlock), 0, (hipStream_t)stream, c);
+  if (launched()) return -1;
+  if (c.went_t + c.went_a > 0) {
+    const int64_t tot = c.went_t + c.went_a;
+    const int wg = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (tot + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_prep_windows<V>, dim3(wg), dim3(kBlock), 0, (hipStream_t)stream, c);
+    if (launched()) return -1;
+  }
+  hipLaunchKernelGGL(k_prep_scalars, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, c);
+  return launched();
+}
+template int prep_finish<double>(const PrepCfg&, void*);
+template int prep_finish<float>(const PrepCfg&, void*);
 
 template struct Kernels<double>;
 template struct Kernels<float>;

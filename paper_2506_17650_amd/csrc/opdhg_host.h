@@ -45,6 +45,10 @@ struct WinPlan {
   size_t seg_items() const { return (srow.size() + kSegRows - 1) / kSegRows; }
 };
 
+// LPs of at least this many nonzeros are prepared on the device under
+// OPDHG_PREP_AUTO.
+constexpr int64_t kDevicePrepNnz = int64_t(1) << 20;
+
 // An LP after validation, rescaling and transposition, in FP64 on the host.
 // Arrays marked "device order" follow the relabelling by row class:
 // device row i of A is original row perm_a[i], device variable j is
@@ -65,6 +69,14 @@ struct Prepared {
   std::vector<double> pow_tab;  // step-rule factors, 2 * kPowTab
   DevParams prm;
   double eta0 = 1.0, omega0 = 1.0;
+  // device-side preparation: the host keeps the structure and sends the
+  // unscaled values in device order; dr, dc, eta0 and omega0 come back
+  // after the preparation kernels
+  bool dprep = false;
+  int prep_ruiz = 0;
+  bool prep_l2 = false;
+  double prep_beta = -1.0;
+  std::vector<double> raw_a, raw_t, raw_b, raw_c, raw_l, raw_u;
   // partial slots per side: evaluation tiles, or step tiles plus windowed chunks
   int64_t part_stride_t() const {
     return (int64_t)std::max(tiles_t.size(),
@@ -91,14 +103,20 @@ struct SlotLayout {
   size_t wcol_a = 0, wrow_a = 0, wval_a = 0, wpass_a = 0, wrange_a = 0;
   size_t segp_t = 0, srow_t = 0, sptr_t = 0, sids_t = 0;  // segmented rows (0 when none)
   size_t segp_a = 0, srow_a = 0, sptr_a = 0, sids_a = 0;
+  // device-side preparation (0 when the host prepares)
+  size_t raw_a = 0, raw_t = 0, raw_b = 0, raw_c = 0, raw_l = 0, raw_u = 0, sr = 0, sc = 0;
+  size_t pscr = 0, wsrc_t = 0, wsrc_a = 0;
   size_t total = 0;
 };
 
 int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool structure_only);
 SlotLayout slot_layout(const Prepared& P, int prec);
 LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P);
-int upload_slot(uint8_t* base, const SlotLayout& L, const Prepared& P, int prec,
-                hipStream_t stream, std::vector<uint8_t>& img);
+// Writes the slot's image; with device-side preparation also runs the
+// preparation kernels and fills P.dr, P.dc, P.eta0 and P.omega0 from the
+// device (synchronizes the stream then).
+int upload_slot(uint8_t* base, const SlotLayout& L, Prepared& P, int prec, hipStream_t stream,
+                std::vector<uint8_t>& img);
 // Launch tables of a set of LPs at dst: LP table, both work lists (chunked
 // over at most cap workgroups), counts and the Ctl board. With capacity > 0,
 // OPDHG_ERR_OVER_BUDGET when they need more bytes. With fixed_launch the

@@ -297,6 +297,50 @@ struct Kernels {
 
 // Copies every LP's Ctl into c.board (precision independent).
 int launch_board(const LaunchCfg& c, void* stream);
+
+// Device-side preparation of one slot (FP64 arithmetic, results in V):
+// the rescaling passes over the two stored CSR copies in device order,
+// then the scaled values, vectors, windowed values and the first step size
+// and primal weight. Every row statistic follows the host's expression and
+// order (maxima; double-double sums added one entry at a time).
+constexpr int kPrepGrid = 256;  // workgroups of the vector kernel (norm partials)
+struct PrepCfg {
+  const int32_t* rp_a;
+  const int32_t* ci_a;
+  const int32_t* rp_t;
+  const int32_t* ci_t;
+  const double* raw_a;  // unscaled values, device order of each CSR copy
+  const double* raw_t;
+  const double* raw_b;  // unscaled b (m), c, l, u (n), device order
+  const double* raw_c;
+  const double* raw_l;
+  const double* raw_u;
+  double* dr;  // diagonals, device order (start at 1)
+  double* dc;
+  double* sr;  // row / column statistics of a pass
+  double* sc;
+  double* scr;  // 4 * kPrepGrid norm partials, then amax bits, then eta0, omega0
+  void* va_a;
+  void* va_t;
+  void* b;
+  void* c;
+  void* l;
+  void* u;
+  void* x0;
+  void* xa;
+  void* wval_t;
+  void* wval_a;
+  const int32_t* wsrc_t;
+  const int32_t* wsrc_a;
+  int64_t went_t, went_a;
+  Ctl* ctl;
+  int32_t m, n;
+};
+// kind 0: maxima of |a~|, 1: sums of |a~|^e, 2: L2 norms
+int prep_stats(const PrepCfg& c, void* stream, bool tside, int kind, double e);
+int prep_apply(const PrepCfg& c, void* stream);  // dr /= sqrt(sr), dc /= sqrt(sc)
+template <typename V>
+int prep_finish(const PrepCfg& c, void* stream);
 // Sets the windowed kernels' LDS attribute (once per process); 0 on success.
 int window_kernels_ready();
 

@@ -1,0 +1,109 @@
+"""Device-side preparation against host preparation, through the C-ABI.
+
+With OPDHG_PREP_DEVICE the Ruiz, L2 and Pock-Chambolle passes, the scaled
+values and vectors, and the first step size and primal weight are computed
+by device kernels in the device order of the rows. Each row statistic
+follows the host's expression and order, so the whole solve must equal the
+host-prepared solve bit for bit; the host's rescaling is in turn bitwise
+equal to the oracle's (test_library_host.py), so these solves are tied to
+the oracle's rescaling.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from lpgen import block_angular_lp, config_lp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_17650_amd as P
+    P.load()
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _lps():
+    return {
+        "cfg0": config_lp("cfg0", seed=3),
+        "cfg1x0.05": config_lp("cfg1", scale=0.05),  # row scales over 6 decades, free variables
+        "cfg4-2x0.01": config_lp("cfg4", index=2, scale=0.01),
+        "cfg3-1x0.2": config_lp("cfg3", index=1, scale=0.2),
+    }
+
+
+def _same(a, b):
+    (xa, ya, ra), (xb, yb, rb) = a, b
+    assert ra.status == rb.status and ra.iterations == rb.iterations
+    assert ra.attempts == rb.attempts and ra.restarts == rb.restarts
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    assert ra.primal_obj == rb.primal_obj and ra.eta == rb.eta and ra.omega == rb.omega
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+@pytest.mark.parametrize("extra", [{}, {"l2_rescale": 1, "pc_beta": -1.0}])
+def test_device_prep_equals_host_prep(P, prec_name, extra):
+    prec = P.OPDHG_FP64 if prec_name == "fp64" else P.OPDHG_FP32
+    for name, lp in _lps().items():
+        _say(f"[prep] {name} {prec_name} {extra}")
+        kw = dict(precision=prec, max_iter=3000, lr=1e-3, tol=1e-4, **extra)
+        host = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw))
+        dev = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw))
+        _same(dev, host)
+
+
+def test_device_prep_other_exponent_to_rounding(P):
+    """A Pock-Chambolle exponent other than 1 takes powers: the device's pow
+    and the host's may differ in the last bit, so the two preparations agree
+    to rounding. Over 20 iterations the iterates stay within 1e-12."""
+    lp = config_lp("cfg1", scale=0.05)
+    kw = dict(precision=P.OPDHG_FP64, lr=1e-3, ruiz_iters=3, pc_beta=0.5, tol=0.0,
+              max_iter=10**6)
+    with P.Session(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw)) as a, \
+            P.Session(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw)) as b:
+        for k in (1, 5, 20):
+            a.run(k)
+            b.run(k)
+            xa, ya, Ta, Sa, sa = a.state()
+            xb, yb, Tb, Sb, sb = b.state()
+            assert sa.attempts == sb.attempts
+            for u, v in ((xa, xb), (ya, yb), (Ta, Tb), (Sa, Sb)):
+                assert np.linalg.norm(u - v) <= 1e-12 * max(np.linalg.norm(u), 1e-300)
+            assert abs(sa.eta - sb.eta) <= 1e-12 * abs(sa.eta)
+
+
+def test_device_prep_windows_and_segments(P):
+    # FP32 block LPs with windowed chunks, and long linking rows as segments
+    lps = [config_lp("cfg2", scale=0.1),
+           block_angular_lp(7, blocks=6, block_rows=3000, block_cols=8000, col_degree=6,
+                            link_rows=40, link_nnz_per_row=600)]
+    for lp in lps:
+        _say(f"[prep windows] m={lp.m} n={lp.n}")
+        kw = dict(precision=P.OPDHG_FP32, max_iter=2000, lr=1e-3, windows=P.OPDHG_WINDOWS_ALWAYS)
+        host = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw))
+        dev = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw))
+        _same(dev, host)
+
+
+def test_device_prep_batch_and_server(P):
+    lps = list(_lps().values())
+    kw = dict(precision=P.OPDHG_FP32, max_iter=3000, lr=1e-3, windows=P.OPDHG_WINDOWS_OFF)
+    dev = P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw)
+    solo = [P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw)) for lp in lps]
+    for got, ref in zip(P.opdhg_solve_batch(lps, dev), solo):
+        _same(got, ref)
+    with P.Server(64 << 20, precision=P.OPDHG_FP32) as srv:
+        got = [srv.wait(srv.submit(lp, dev), 120.0) for lp in lps]
+    for g, ref in zip(got, solo):
+        _same(g, ref)

@@ -161,7 +161,8 @@ def test_new_parameters_validated():
     lp = tiny_lp(seed=3)
     for k, v in [("step_rule", 2), ("restart_scheme", -1), ("l2_rescale", 2),
                  ("power_iters", 0), ("step_scale", 0.0), ("step_scale", float("inf")),
-                 ("power_tol", -1.0)]:
+                 ("power_tol", -1.0), ("windows", 3), ("window_buckets", 27),
+                 ("window_rows", 10241), ("prep", 3)]:
         with pytest.raises(P.OpdhgError) as e:
             P.opdhg_spectral_norm(lp, P.opdhg_default_params(**{k: v}))
         assert e.value.code == capi.OPDHG_ERR_INVALID_ARGUMENT, k
@@ -194,3 +195,12 @@ def test_binding_structs_match_the_header_layout(tmp_path):
                                           text=True).stdout.split()]
     assert len(structs) >= 6
     assert got == want
+
+
+def test_constant_step_needs_host_preparation():
+    # the power iteration behind the constant step runs on the host
+    lp = tiny_lp(seed=3)
+    p = P.opdhg_vanilla_params(0.0, prep=capi.OPDHG_PREP_DEVICE)
+    with pytest.raises(P.OpdhgError) as e:
+        P.opdhg_workspace_bytes(lp, p)
+    assert e.value.code == capi.OPDHG_ERR_INVALID_ARGUMENT
