@@ -494,6 +494,19 @@ std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t cap, int 
 
 constexpr int64_t kWinMinNnz = 8192;  // smaller chunks are not worth a workgroup of kWinBlock
 
+// Chunk rows of a windowed side: the parameter, or the side's windowable
+// rows spread evenly over whole rounds of kWinRound chunks (one chunk per
+// compute unit at a time, so no round is left half empty), at least 1024.
+constexpr int64_t kWinRound = 256;
+constexpr int64_t kWinMinChunks = 128;  // fewer chunks than this leave most CUs idle
+
+static int64_t window_chunk_rows(const opdhg_params* p, int64_t rows) {
+  if (p->window_rows > 0) return p->window_rows;
+  const int64_t rounds = std::max<int64_t>(1, (rows + kWinRound * kWinRows - 1) / (kWinRound * kWinRows));
+  const int64_t per = (rows + rounds * kWinRound - 1) / (rounds * kWinRound);
+  return std::min<int64_t>(kWinRows, std::max<int64_t>(1024, per));
+}
+
 static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
                          int64_t ncols, int64_t lo, int64_t hi, int64_t long_end,
                          int64_t chunk_rows, int per_pass, WinPlan& W) {
@@ -734,6 +747,39 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
   return W.col.size() == W.row.size() && W.col.size() == W.src.size();
 }
 
+// Whether automatic windows are worth planning: enough nonzeros for
+// kWinMinChunks chunks, and at least half of 8 chunks sampled evenly over
+// the windowable rows of A (device order, columns relabelled through inv_t)
+// would be windowed. A cheap test on the original CSR, so LPs without
+// column locality skip the device-order indices and the planning.
+static bool windows_worth_planning(const opdhg_lp* lp, const Prepared& out,
+                                   const std::vector<int32_t>& inv_t, int64_t chunk_rows,
+                                   int per_pass) {
+  if (lp->nnz < kWinMinChunks * kWinMinNnz) return false;
+  const int64_t lo = out.cend_a[0], hi = lp->m;
+  if (hi - lo < 8 * chunk_rows) return false;
+  const int64_t nb = (lp->n + kWinBucket - 1) / kWinBucket;
+  std::vector<int32_t> stamp(nb, -1);
+  int ok = 0;
+  for (int s = 0; s < 8; ++s) {
+    const int64_t a = lo + (hi - lo - chunk_rows) * s / 7, b = a + chunk_rows;
+    int64_t nz = 0, nbk = 0;
+    for (int64_t r = a; r < b; ++r) {
+      const int64_t i = out.perm_a[r];
+      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+        const int64_t bk = inv_t[lp->col_idx[k]] / kWinBucket;
+        ++nz;
+        if (stamp[bk] != s) {
+          stamp[bk] = s;
+          ++nbk;
+        }
+      }
+    }
+    if ((nbk + per_pass - 1) / per_pass <= kWinMaxPass && nbk * kWinBucket <= nz) ++ok;
+  }
+  return ok >= 4;
+}
+
 // Tiles over the rows of a side that no windowed chunk takes.
 static std::vector<Tile> tiles_outside(const std::vector<int32_t>& rp, int64_t rows,
                                        const WinPlan& W, int64_t cap, int lanes) {
@@ -765,18 +811,6 @@ void step_tiles(Prepared& P, int64_t cap, int lanes) {
   P.stiles_a = P.win_a.chunks() ? tiles_outside(P.rp_a, P.m, P.win_a, cap, lanes) : P.tiles_a;
 }
 
-// Chunk rows of a windowed side: the parameter, or the side's windowable
-// rows spread evenly over whole rounds of kWinRound chunks (one chunk per
-// compute unit at a time, so no round is left half empty), at least 1024.
-constexpr int64_t kWinRound = 256;
-constexpr int64_t kWinMinChunks = 128;  // fewer chunks than this leave most CUs idle
-
-static int64_t window_chunk_rows(const opdhg_params* p, int64_t rows) {
-  if (p->window_rows > 0) return p->window_rows;
-  const int64_t rounds = std::max<int64_t>(1, (rows + kWinRound * kWinRows - 1) / (kWinRound * kWinRows));
-  const int64_t per = (rows + rounds * kWinRound - 1) / (rounds * kWinRound);
-  return std::min<int64_t>(kWinRows, std::max<int64_t>(1024, per));
-}
 
 // ---------------------------------------------------------------------------
 // preparation: everything the device needs, computed on the host in FP64
@@ -800,8 +834,16 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   const int64_t cap = p->tile_nnz > 0 ? std::min<int64_t>(p->tile_nnz, kTileCap) : kTileCap;
   out.tiles_a = build_tiles(out.rp_a.data(), m, cap, p->lanes);
   out.tiles_t = build_tiles(out.rp_t.data(), n, cap, p->lanes);
-  // windowed chunks need the device-order column indices, also for sizing
-  const bool windows = p->precision == OPDHG_FP32 && p->windows != OPDHG_WINDOWS_OFF;
+  // windowed chunks need the device-order column indices, also for sizing;
+  // automatic windows only where a sample of chunks shows column locality
+  bool windows = p->precision == OPDHG_FP32 && p->windows != OPDHG_WINDOWS_OFF;
+  const int per_pass = p->window_buckets > 0 ? p->window_buckets : kWinBuckets;
+  if (windows && p->windows == OPDHG_WINDOWS_AUTO) {
+    std::vector<int32_t> inv(n);
+    for (int64_t j = 0; j < n; ++j) inv[out.perm_t[j]] = (int32_t)j;
+    windows = windows_worth_planning(lp, out, inv, window_chunk_rows(p, m - out.cend_a[0]),
+                                     per_pass);
+  }
   // device-side preparation: the rescaling and the scaled data on the GPU
   out.dprep = p->step_rule != OPDHG_STEP_CONSTANT &&
               (p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz));
@@ -872,7 +914,6 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.win_t = WinPlan();
   out.win_a = WinPlan();
   if (windows) {
-    const int per_pass = p->window_buckets > 0 ? p->window_buckets : kWinBuckets;
     plan_windows(out.rp_t, out.ci_t, m, out.cend_t[0], n, out.cend_t[0],
                  window_chunk_rows(p, n - out.cend_t[0]), per_pass, out.win_t);
     plan_windows(out.rp_a, out.ci_a, n, out.cend_a[0], m, out.cend_a[0],
