@@ -209,11 +209,15 @@ void opdhg_default_params(opdhg_params* p);
 int opdhg_validate(const opdhg_lp* lp);
 
 /* Exact device bytes one LP needs under these parameters (a pure function of
- * the LP's shape and the parameters). Host only. */
+ * the LP's sparsity pattern and the parameters: the tiling, the windowed
+ * chunks planned from the pattern in FP32, and, with device-side
+ * preparation, the unscaled values' staging). Host only. */
 int opdhg_workspace_bytes(const opdhg_lp* lp, const opdhg_params* p, size_t* bytes);
 
-/* Host-only rescaling, exposed for checking: the Ruiz passes and the
- * Pock-Chambolle pass of Section 2 as applied before the iteration.
+/* Host-only rescaling, exposed for checking: the Ruiz passes, the optional
+ * L2 pass and the Pock-Chambolle pass of Section 2 as applied before the
+ * iteration (the device-side preparation gives the same bits for
+ * pc_beta 1 or < 0; for other exponents it agrees to rounding).
  * Outputs (caller-allocated host arrays): scaled_val[nnz] in the order of
  * lp->val, d_row[m], d_col[n] with A~ = diag(d_row) A diag(d_col). */
 int opdhg_rescale(const opdhg_lp* lp, const opdhg_params* p, double* scaled_val,
@@ -230,7 +234,11 @@ int opdhg_rescale(const opdhg_lp* lp, const opdhg_params* p, double* scaled_val,
 int opdhg_spectral_norm(const opdhg_lp* lp, const opdhg_params* p, double* norm_out);
 
 /* Solve one LP (blocking). x_out[n], y_out[m] receive the returned iterate
- * (unscaled); res receives status and statistics. */
+ * (unscaled); res receives status and statistics. In FP64 the result does
+ * not depend on the tiling, the windows or the preparation side (exact
+ * sums); in FP32 the row sums of windowed chunks and of tiles are formed in
+ * different orders, so the FP32 result moves with those choices by
+ * rounding only, and is the same on every run. */
 int opdhg_solve(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
                 size_t workspace_bytes, void* hip_stream, double* x_out, double* y_out,
                 opdhg_result* res);
