@@ -476,10 +476,17 @@ def oracle_baseline(lp, lr: float, phi: int, seconds: float) -> dict:
     as many accepted iterations of the same LP as fit in ~`seconds`."""
     import oracle
     from oracle.params import default_params
-    t0 = time.perf_counter()
-    r = oracle.solve(lp, default_params(tol=0.0, max_iter=4, lr=lr, phi=phi))
-    per_it = max((time.perf_counter() - t0) / max(r.iterations, 1), 1e-4)
-    iters = int(max(8, min(2000, seconds / per_it)))
+    # per-iteration cost from the difference of two short runs, so that the
+    # setup (rescaling, transposition) does not shorten the sample
+    runs = []
+    for k in (4, 16):
+        t0 = time.perf_counter()
+        r = oracle.solve(lp, default_params(tol=0.0, max_iter=k, lr=lr, phi=phi))
+        runs.append((r.iterations, time.perf_counter() - t0))
+    (k0, t0_), (k1, t1_) = runs
+    per_it = max((t1_ - t0_) / max(k1 - k0, 1), 1e-4)
+    setup = max(t0_ - k0 * per_it, 0.0)
+    iters = int(max(8, min(5000, (seconds - setup) / per_it)))
     t0 = time.perf_counter()
     r = oracle.solve(lp, default_params(tol=0.0, max_iter=iters, lr=lr, phi=phi))
     dt = time.perf_counter() - t0

@@ -292,7 +292,7 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
  * iterations and before the evaluation at the top of the next one. */
 int opdhg_session_run(opdhg_session* s, int64_t k_target);
 /* Enqueue exactly `replays` launch sequences (one evaluation step plus
- * eval_every attempts each) on the session's stream and wait for them,
+ * min(eval_every, 64) attempts each) on the session's stream and wait for them,
  * without reading the state in between; limits and termination still
  * apply on the device (finished LPs make the remaining launches no-ops).
  * For timing the iteration at a fixed amount of work. */
@@ -322,9 +322,9 @@ typedef struct opdhg_server_cfg {
   size_t budget_bytes;   /* admission budget for resident LPs; capped at what the arena
                             holds after the launch tables */
   int32_t max_active;    /* at most this many LPs on the device at once (1..65535) */
-  int32_t attempts_per_replay; /* step attempts per launch sequence; each sequence starts
-                                  with the due KKT evaluations, admissions and retirements
-                                  happen between sequences */
+  int32_t attempts_per_replay; /* step attempts per launch sequence (1..64); each sequence
+                                  starts with the due KKT evaluations, admissions and
+                                  retirements happen between sequences */
   int32_t precision;     /* OPDHG_FP64 or OPDHG_FP32; every request must use it */
   int32_t workgroups;    /* workgroups of the sparse-product launches; 0: automatic */
   int32_t prep_threads;  /* host threads preparing submitted LPs; 0: automatic */

@@ -1144,6 +1144,14 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
   d.pow_ring = reinterpret_cast<double*>(base + L.pow_ring);
   d.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   d.prm = reinterpret_cast<const DevParams*>(base + L.prm);
+  d.s_lr = P.prm.lr;
+  d.s_max_iter = P.prm.max_iter;
+  d.s_phi = P.prm.phi;
+  d.s_schedule = P.prm.schedule;
+  d.s_normalize = P.prm.normalize;
+  d.s_eval_every = P.prm.eval_every;
+  d.s_max_retries = P.prm.max_retries;
+  d.s_flags = P.prm.flags;
   if (P.win_t.chunks()) {
     d.wcol_t = reinterpret_cast<const uint16_t*>(base + L.wcol_t);
     d.wrow_t = reinterpret_cast<const uint16_t*>(base + L.wrow_t);
@@ -1280,6 +1288,8 @@ template void slot_image<float>(const SlotLayout&, const Prepared&, std::vector<
 // ---------------------------------------------------------------------------
 
 int Group::capture(int attempts_per_replay) {
+  // the step-rule factor ring covers kPowRing attempts per launch sequence
+  attempts_per_replay = std::min(std::max(1, attempts_per_replay), kPowRing);
   if (exec) {
     (void)hipGraphExecDestroy(exec);
     exec = nullptr;

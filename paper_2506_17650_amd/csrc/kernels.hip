@@ -247,42 +247,61 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 // The same for two partial arrays at once (NA quantities over ca slots of
 // pa, then NB over cb slots of pb): one pass, so the loads of both arrays
 // are in flight together.
-template <int NA, int NB>
+template <int NA, int NB, typename Mid>
 __device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, const double* pb,
                                               int sb, int cb, double (&out)[NA + NB],
-                                              DD* s_red) {
+                                              DD* s_red, Mid&& mid) {
   constexpr int B = 8;  // 2048 slots per round: one round of loads for most launch sets
   DD v[NA + NB];
 #pragma unroll
   for (int q = 0; q < NA + NB; ++q) v[q] = dd_zero();
   const gptr<const double> ga = gp(pa), gb = gp(pb);
   const int count = ca > cb ? ca : cb;
-  for (int base = threadIdx.x; base < count; base += kBlock * B) {
+  // Every thread runs the first round; mid() runs between its loads and
+  // its merges, so that loads the caller issues there overlap them. Groups
+  // of kBlock slots that lie past a side's count are skipped (a uniform
+  // test); inside a group, slots past the count read slot 0 and add zero.
+  auto round = [&](int r0, bool first) {
+    const int t0 = r0 + (int)threadIdx.x;
     double h[B][NA + NB], l[B][NA + NB];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      const int t = base + k * kBlock;
-      const bool oka = t < ca, okb = t < cb;
-      const int ta = oka ? t : 0, tb = okb ? t : 0;  // slot 0 exists on both sides
+      const int t = t0 + k * kBlock;
+      const int ta = t < ca ? t : 0, tb = t < cb ? t : 0;
+      // only loads behind the uniform tests: the masks apply at the merge
 #pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const double hv = ga[(size_t)(2 * q) * sa + ta], lv = ga[(size_t)(2 * q + 1) * sa + ta];
-        h[k][q] = oka ? hv : 0.0;
-        l[k][q] = oka ? lv : 0.0;
+      for (int q = 0; q < NA + NB; ++q) h[k][q] = l[k][q] = 0.0;
+      if (r0 + k * kBlock < ca) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+          h[k][q] = ga[(size_t)(2 * q) * sa + ta];
+          l[k][q] = ga[(size_t)(2 * q + 1) * sa + ta];
+        }
       }
+      if (r0 + k * kBlock < cb) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const double hv = gb[(size_t)(2 * q) * sb + tb], lv = gb[(size_t)(2 * q + 1) * sb + tb];
-        h[k][NA + q] = okb ? hv : 0.0;
-        l[k][NA + q] = okb ? lv : 0.0;
+        for (int q = 0; q < NB; ++q) {
+          h[k][NA + q] = gb[(size_t)(2 * q) * sb + tb];
+          l[k][NA + q] = gb[(size_t)(2 * q + 1) * sb + tb];
+        }
       }
     }
+    if (first) mid();
 #pragma unroll
     for (int k = 0; k < B; ++k) {
+      if (r0 + k * kBlock < count) {
+        const int t = t0 + k * kBlock;
+        const bool oka = t < ca, okb = t < cb;
 #pragma unroll
-      for (int q = 0; q < NA + NB; ++q) v[q] = dd_merge(v[q], DD{h[k][q], l[k][q]});
+        for (int q = 0; q < NA + NB; ++q) {
+          const bool ok = q < NA ? oka : okb;
+          v[q] = dd_merge(v[q], DD{ok ? h[k][q] : 0.0, ok ? l[k][q] : 0.0});
+        }
+      }
     }
-  }
+  };
+  round(0, true);
+  for (int r0 = kBlock * B; r0 < count; r0 += kBlock * B) round(r0, false);
   block_sum<NA + NB>(v, s_red);
 #pragma unroll
   for (int q = 0; q < NA + NB; ++q) out[q] = dd_value(v[q]);
@@ -560,11 +579,6 @@ __device__ __forceinline__ V clampv(V v, V lo, V hi) {
   return t > hi ? hi : t;
 }
 
-__device__ __forceinline__ bool attempt_guard(const Ctl* c) {
-  // running, no evaluation due, below the pause point
-  return c->status == kRunning && c->need_eval == 0 && c->k < c->k_limit;
-}
-
 __device__ __forceinline__ bool eval_guard(const Ctl* c) {
   return c->status == kRunning && c->need_eval != 0;
 }
@@ -586,54 +600,58 @@ __device__ __forceinline__ void flush_partials(DD (&p)[NV], DD* s_red, double* p
 }
 
 // ---------------------------------------------------------------------------
-// scalar decisions (thread 0 of the last workgroup of an LP)
+// scalar decisions (one workgroup per LP)
 // ---------------------------------------------------------------------------
 
-// Factor (j+1)^-e of the step rule for attempt j: from the host-computed
-// table for the first kPowTab attempts, else from the ring the evaluation
-// kernel fills at the start of each launch sequence (which holds at most
-// kPowRing attempts, so the ring covers every attempt j of it).
-__device__ __forceinline__ double step_factor(const LpDev& lp, int64_t ring_base, int which,
-                                              int64_t j) {
-  if (j >= 1 && j <= kPowTab) return lp.pow_tab[which * kPowTab + (j - 1)];
-  int64_t r = j - ring_base - 1;
-  r = r < 0 ? 0 : (r >= kPowRing ? kPowRing - 1 : r);
-  return lp.pow_ring[which * kPowRing + r];
-}
+// Inputs of the step decision, read before the partial sums are merged so
+// that their loads overlap those of the partials: the control-block fields
+// it reads, the parameters it uses, and the step-rule factors
+// (j+1)^-reduction and (j+1)^-growth of the attempt j it decides.
+struct StepIn {
+  double eta, omega, w, hp_norm, hd_norm;
+  int64_t k, t, attempts, retries;
+  int32_t cur;
+  double lr;
+  int64_t max_iter;
+  int32_t phi, schedule, normalize, eval_every, max_retries, flags;
+  double f_red, f_gro;
+};
 
 // Adaptive step rule (PDLP's): accept when eta <= eta_bar; the next step is
 // min((1 - (j+1)^-red) eta_bar, (1 + (j+1)^-gro) eta), j counting attempts.
-// c is the LP's control block; s holds the attempt's sums
+// c is the LP's control block (written here), in its fields as read before
+// the decision; s holds the attempt's sums
 // |x'-x|^2, |g|^2, |G^p|^2, |y'-y|^2, (y'-y).(A x'-A x), |b-Ax|^2, |G^d|^2.
-__device__ void decide_step(Ctl& c, const DevParams& p, const LpDev& lp, const double* s) {
+__device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
   const double dx2 = s[0], g2 = s[1], gp2 = s[2];
   const double dy2 = s[3], inter = fabs(s[4]), r2 = s[5], gd2 = s[6];
-  c.attempts += 1;
+  c.attempts = in.attempts + 1;
   if (!(isfinite(dx2) && isfinite(dy2) && isfinite(inter))) {
     c.status = kNumError;
     return;
   }
-  const double eta = c.eta, om = c.omega;
+  const double eta = in.eta, om = in.omega;
   const double movement = 0.5 * om * dx2 + 0.5 * dy2 / om;
   const double eta_bar = inter > 0.0 ? movement / inter : INFINITY;
   // the constant step (vanilla PDHG) accepts every attempt and keeps eta
-  const bool constant = (p.flags & kConstantStep) != 0;
+  const bool constant = (in.flags & kConstantStep) != 0;
   double eta_next = eta;
   if (!constant) {
-    const double first = (1.0 - step_factor(lp, c.ring_base, 0, c.attempts)) * eta_bar;
-    const double second = (1.0 + step_factor(lp, c.ring_base, 1, c.attempts)) * eta;
+    const double first = (1.0 - in.f_red) * eta_bar;
+    const double second = (1.0 + in.f_gro) * eta;
     eta_next = second < first ? second : first;
   }
   c.last_eta_bar = eta_bar;
   // a pending learner update was applied by this attempt's kernels
   c.learn_pending = 0;
   if (constant || eta <= eta_bar) {
-    const bool learn = p.lr > 0.0 && (c.k % p.phi) == 0;
+    const bool learn = in.lr > 0.0 && (in.k % in.phi) == 0;
+    const int64_t k1 = in.k + 1;
     c.eta_acc = eta;
-    c.w += eta;
-    c.k += 1;
-    c.t += 1;
-    c.cur ^= 1;
+    c.w = in.w + eta;
+    c.k = k1;
+    c.t = in.t + 1;
+    c.cur = in.cur ^ 1;
     c.eta = eta_next;
     c.retries = 0;
     if (learn) {
@@ -642,22 +660,22 @@ __device__ void decide_step(Ctl& c, const DevParams& p, const LpDev& lp, const d
       c.r2 = r2;
       c.gp2 = gp2;
       c.gd2 = gd2;
-      if (p.schedule == 1) {  // AdaGrad on the norm: H += |G / scale|^2 = |G|^2 / scale^2
-        const bool np = p.normalize && !(g2 > 0.0);
-        const bool nd = p.normalize && !(r2 > 0.0);
-        const double sp = p.normalize ? g2 : 1.0;
-        const double sd = p.normalize ? r2 : 1.0;
-        if (!np) c.hp_norm = c.hp_norm + gp2 / (sp * sp);
-        if (!nd) c.hd_norm = c.hd_norm + gd2 / (sd * sd);
+      if (in.schedule == 1) {  // AdaGrad on the norm: H += |G / scale|^2 = |G|^2 / scale^2
+        const bool np = in.normalize && !(g2 > 0.0);
+        const bool nd = in.normalize && !(r2 > 0.0);
+        const double sp = in.normalize ? g2 : 1.0;
+        const double sd = in.normalize ? r2 : 1.0;
+        if (!np) c.hp_norm = in.hp_norm + gp2 / (sp * sp);
+        if (!nd) c.hd_norm = in.hd_norm + gd2 / (sd * sd);
       }
     }
-    c.learn_now = (p.lr > 0.0 && (c.k % p.phi) == 0) ? 1 : 0;
-    if (c.k % p.eval_every == 0 || c.k >= p.max_iter) c.need_eval = 1;
+    c.learn_now = (in.lr > 0.0 && (k1 % in.phi) == 0) ? 1 : 0;
+    if (k1 % in.eval_every == 0 || k1 >= in.max_iter) c.need_eval = 1;
   } else {
+    const int64_t r1 = in.retries + 1;
     c.eta = eta_next;
-    c.retries += 1;
-    if (c.retries > p.max_retries || !(eta_next > 0.0 && isfinite(eta_next)))
-      c.status = kNumError;
+    c.retries = r1;
+    if (r1 > in.max_retries || !(eta_next > 0.0 && isfinite(eta_next))) c.status = kNumError;
   }
 }
 
@@ -772,6 +790,43 @@ __device__ __forceinline__ T uni(T v) {
   }
 }
 
+// The control-block fields a step kernel reads, fetched together through
+// the global address space into scalar registers: every load is issued
+// before the first branch on any of them, so they cost one round trip
+// instead of one per branch.
+struct CtlView {
+  double eta, omega, g2, r2, hp_norm, hd_norm;
+  int64_t k, k_limit;
+  int32_t status, cur, need_eval, learn_pending, restart_pending, finalize_avg, learn_now,
+      weighted_step;
+  // running, no evaluation due, below the pause point
+  __device__ __forceinline__ bool attempt() const {
+    return (status == kRunning) & (need_eval == 0) & (k < k_limit);
+  }
+};
+
+__device__ __forceinline__ CtlView ctl_view(const Ctl* c) {
+  const gptr<const Ctl> g = gp(c);
+  CtlView v;
+  v.eta = uni(g->eta);
+  v.omega = uni(g->omega);
+  v.g2 = uni(g->g2);
+  v.r2 = uni(g->r2);
+  v.hp_norm = uni(g->hp_norm);
+  v.hd_norm = uni(g->hd_norm);
+  v.k = uni(g->k);
+  v.k_limit = uni(g->k_limit);
+  v.status = uni(g->status);
+  v.cur = uni(g->cur);
+  v.need_eval = uni(g->need_eval);
+  v.learn_pending = uni(g->learn_pending);
+  v.restart_pending = uni(g->restart_pending);
+  v.finalize_avg = uni(g->finalize_avg);
+  v.learn_now = uni(g->learn_now);
+  v.weighted_step = uni(g->weighted_step);
+  return v;
+}
+
 // The same work item in every thread, moved to scalar registers: the
 // compiler then branches on its fields and divides by its lane count with
 // scalar instructions.
@@ -871,11 +926,12 @@ __device__ __forceinline__ V learn_elem(V Pv, V& Hv, V Graw, double scale, const
   return pv < fl ? fl : pv;
 }
 
-// Whether the pending learner update touches this side, and its scale.
-__device__ __forceinline__ bool learn_side(const Ctl* c, const DevParams* p, bool primal,
+// Whether a pending learner update (pending != 0) touches a side whose
+// loss norm is nrm (|g|^2 on the primal side, |b - Ax|^2 on the dual side),
+// and its scale.
+__device__ __forceinline__ bool learn_side(int pending, double nrm, const DevParams* p,
                                            double* scale) {
-  if (!c->learn_pending) return false;
-  const double nrm = primal ? c->g2 : c->r2;
+  if (!pending) return false;
   if (p->normalize && !(nrm > 0.0)) return false;
   *scale = p->normalize ? nrm : 1.0;
   return true;
@@ -916,6 +972,7 @@ struct PrimalPre {
 template <typename V>
 struct PrimalStep {
   const LpDev* lp = nullptr;
+  const DevParams* prm = nullptr;
   Ctl* c = nullptr;
   gptr<const V> cc = nullptr, lo = nullptr, hi = nullptr, x = nullptr, xs = nullptr;
   gptr<V> T = nullptr, Hp = nullptr, xn = nullptr, xsn = nullptr, Gp = nullptr;
@@ -926,6 +983,8 @@ struct PrimalStep {
   gptr<const V> vecs[1] = {nullptr};  // the gathered vector, y
   gptr<const int32_t> rp = nullptr, ci = nullptr;
   gptr<const V> va = nullptr;
+  double* part_ = nullptr;
+  int stride_ = 0;
   V tau = V(0), etav = V(0);
   bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
@@ -933,45 +992,67 @@ struct PrimalStep {
   __device__ __forceinline__ bool begin(const LaunchCfg& cfg, Ctl* ctl, int lpi, int slot,
                                         int force) {
     c = ctl;
+    lp = &cfg.lps[lpi];
+    // The LP's record and its control block do not depend on each other:
+    // both are read before the first wait.
+    const CtlView v = ctl_view(ctl);
+    const gptr<const LpDev> L = gp(lp);
+    const void* const pc = uni(L->c);
+    const void* const pl = uni(L->l);
+    const void* const pu = uni(L->u);
+    void* const pT = uni(L->T);
+    void* const pH = uni(L->Hp);
+    void* const pG = uni(L->Gp);
+    void* const px0 = uni(L->x[0]);
+    void* const px1 = uni(L->x[1]);
+    void* const ps0 = uni(L->xs[0]);
+    void* const ps1 = uni(L->xs[1]);
+    const void* const py0 = uni(L->y[0]);
+    const void* const py1 = uni(L->y[1]);
+    const int32_t* const prp = uni(L->rp_t);
+    const int32_t* const pci = uni(L->ci_t);
+    const void* const pva = uni(L->va_t);
+    const DevParams* const pprm = uni(L->prm);
+    double* const ppart = uni(L->part_t);
+    const int pstride = uni(L->ntiles_t);
     // the restart / final copy of the evaluation step ran before this
     // launch; the LP's first chunk (partial slot 0) clears the flags
-    if (slot == 0 && threadIdx.x == 0 && (c->restart_pending | c->finalize_avg)) {
+    if (slot == 0 && threadIdx.x == 0 && (v.restart_pending | v.finalize_avg)) {
       c->restart_pending = 0;
       c->finalize_avg = 0;
     }
-    if (!uni((int)(force || attempt_guard(c)))) return false;
-    lp = &cfg.lps[lpi];
-    const int cur = uni(c->cur), nxt = cur ^ 1;
-    const double eta = uni(c->eta), om = uni(c->omega);
+    if (!uni((int)(force || v.attempt()))) return false;
+    const int cur = uni(v.cur);
+    const double eta = uni(v.eta), om = uni(v.omega);
     tau = (V)(eta / om);
     etav = (V)eta;
+    prm = uni(pprm);
     // a forced (timing) launch writes only the candidate buffers
-    learn = uni((int)(!force && c->learn_now != 0)) != 0;
-    wstep = uni(c->weighted_step) != 0;
+    learn = uni((int)(!force && v.learn_now != 0)) != 0;
+    wstep = uni(v.weighted_step) != 0;
     lscale = 1.0;
-    upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, true, &lscale))) != 0;
+    upd = uni((int)(!force && v.learn_pending &&
+                    learn_side(v.learn_pending, v.g2, prm, &lscale))) != 0;
     lscale = uni(lscale);
-    hnorm = uni(c->hp_norm);
-    cc = gp(static_cast<const V*>(lp->c));
-    lo = gp(static_cast<const V*>(lp->l));
-    hi = gp(static_cast<const V*>(lp->u));
-    T = gp(static_cast<V*>(lp->T));
-    Hp = gp(static_cast<V*>(lp->Hp));
-    x = gp(static_cast<const V*>(lp->x[cur]));
-    xs = gp(static_cast<const V*>(lp->xs[cur]));
-    xn = gp(static_cast<V*>(lp->x[nxt]));
-    xsn = gp(static_cast<V*>(lp->xs[nxt]));
-    Gp = gp(static_cast<V*>(lp->Gp));
+    hnorm = uni(v.hp_norm);
+    cc = uni(gp(static_cast<const V*>(pc)));
+    lo = uni(gp(static_cast<const V*>(pl)));
+    hi = uni(gp(static_cast<const V*>(pu)));
+    T = uni(gp(static_cast<V*>(pT)));
+    Hp = uni(gp(static_cast<V*>(pH)));
+    Gp = uni(gp(static_cast<V*>(pG)));
+    x = uni(gp(static_cast<const V*>(cur ? px1 : px0)));
+    xs = uni(gp(static_cast<const V*>(cur ? ps1 : ps0)));
+    xn = uni(gp(static_cast<V*>(cur ? px0 : px1)));
+    xsn = uni(gp(static_cast<V*>(cur ? ps0 : ps1)));
+    vecs[0] = uni(gp(static_cast<const V*>(cur ? py1 : py0)));
     Hsrc = upd ? Hp : x;
     Gsrc = upd ? Gp : x;
-    vecs[0] = gp(static_cast<const V*>(lp->y[cur]));
-    rp = gp(lp->rp_t);
-    ci = gp(lp->ci_t);
-    va = gp(static_cast<const V*>(lp->va_t));
-    cc = uni(cc), lo = uni(lo), hi = uni(hi), x = uni(x), xs = uni(xs);
-    T = uni(T), Hp = uni(Hp), xn = uni(xn), xsn = uni(xsn), Gp = uni(Gp);
-    Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
-    rp = uni(rp), ci = uni(ci), va = uni(va);
+    rp = uni(gp(prp));
+    ci = uni(gp(pci));
+    va = uni(gp(static_cast<const V*>(pva)));
+    part_ = uni(ppart);
+    stride_ = uni(pstride);
     tau = uni(tau), etav = uni(etav);
     return true;
   }
@@ -995,7 +1076,7 @@ struct PrimalStep {
     V Tj = q.T;
     if (upd) {
       V h = q.H;
-      Tj = learn_elem<V>(Tj, h, q.G, lscale, lp->prm, hnorm);
+      Tj = learn_elem<V>(Tj, h, q.G, lscale, prm, hnorm);
       stg(T, (uint32_t)j, Tj);
       stg(Hp, (uint32_t)j, h);
     }
@@ -1018,8 +1099,8 @@ struct PrimalStep {
     }
   }
 
-  __device__ __forceinline__ double* part() const { return lp->part_t; }
-  __device__ __forceinline__ int stride() const { return lp->ntiles_t; }
+  __device__ __forceinline__ double* part() const { return part_; }
+  __device__ __forceinline__ int stride() const { return stride_; }
 };
 
 template <typename V>
@@ -1034,6 +1115,7 @@ struct DualPre {
 template <typename V>
 struct DualStep {
   const LpDev* lp = nullptr;
+  const DevParams* prm = nullptr;
   const Ctl* c = nullptr;
   gptr<const V> b = nullptr, y = nullptr, ys = nullptr, Ax = nullptr;
   gptr<V> S = nullptr, Hd = nullptr, yn = nullptr, ysn = nullptr, Axn = nullptr, Gd = nullptr;
@@ -1042,6 +1124,8 @@ struct DualStep {
   gptr<const int32_t> rp = nullptr, ci = nullptr;
   gptr<const V> va = nullptr;
   gptr<const V> vecs[1] = {nullptr};  // the gathered vector, x'
+  double* part_ = nullptr;
+  int stride_ = 0;
   V sig = V(0), etav = V(0);
   bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
@@ -1049,40 +1133,63 @@ struct DualStep {
   __device__ __forceinline__ bool begin(const LaunchCfg& cfg, const Ctl* ctl, int lpi, int,
                                         int force) {
     c = ctl;
-    // as in PrimalStep: uniform values in scalar registers
-    if (!uni((int)(force || attempt_guard(c)))) return false;
     lp = &cfg.lps[lpi];
-    const int cur = uni(c->cur), nxt = cur ^ 1;
-    const double eta = uni(c->eta), om = uni(c->omega);
+    // as in PrimalStep: the LP's record and its control block are read
+    // together, and uniform values live in scalar registers
+    const CtlView v = ctl_view(ctl);
+    const gptr<const LpDev> L = gp(lp);
+    const void* const pb = uni(L->b);
+    void* const pS = uni(L->S);
+    void* const pH = uni(L->Hd);
+    void* const pG = uni(L->Gd);
+    void* const py0 = uni(L->y[0]);
+    void* const py1 = uni(L->y[1]);
+    void* const ps0 = uni(L->ys[0]);
+    void* const ps1 = uni(L->ys[1]);
+    void* const pa0 = uni(L->Ax[0]);
+    void* const pa1 = uni(L->Ax[1]);
+    const void* const px0 = uni(L->x[0]);
+    const void* const px1 = uni(L->x[1]);
+    const int8_t* const psense = uni(L->sense);
+    const int32_t* const prp = uni(L->rp_a);
+    const int32_t* const pci = uni(L->ci_a);
+    const void* const pva = uni(L->va_a);
+    const DevParams* const pprm = uni(L->prm);
+    double* const ppart = uni(L->part_a);
+    const int pstride = uni(L->ntiles_a);
+    if (!uni((int)(force || v.attempt()))) return false;
+    const int cur = uni(v.cur);
+    const double eta = uni(v.eta), om = uni(v.omega);
     sig = (V)(eta * om);
     etav = (V)eta;
-    learn = uni((int)(!force && c->learn_now != 0)) != 0;
-    wstep = uni(c->weighted_step) != 0;
+    prm = uni(pprm);
+    learn = uni((int)(!force && v.learn_now != 0)) != 0;
+    wstep = uni(v.weighted_step) != 0;
     lscale = 1.0;
-    upd = uni((int)(!force && c->learn_pending && learn_side(c, lp->prm, false, &lscale))) != 0;
+    upd = uni((int)(!force && v.learn_pending &&
+                    learn_side(v.learn_pending, v.r2, prm, &lscale))) != 0;
     lscale = uni(lscale);
-    hnorm = uni(c->hd_norm);
-    b = gp(static_cast<const V*>(lp->b));
-    S = gp(static_cast<V*>(lp->S));
-    Hd = gp(static_cast<V*>(lp->Hd));
-    y = gp(static_cast<const V*>(lp->y[cur]));
-    ys = gp(static_cast<const V*>(lp->ys[cur]));
-    Ax = gp(static_cast<const V*>(lp->Ax[cur]));
-    yn = gp(static_cast<V*>(lp->y[nxt]));
-    ysn = gp(static_cast<V*>(lp->ys[nxt]));
-    Axn = gp(static_cast<V*>(lp->Ax[nxt]));
-    Gd = gp(static_cast<V*>(lp->Gd));
-    sense = gp(lp->sense);
+    hnorm = uni(v.hd_norm);
+    b = uni(gp(static_cast<const V*>(pb)));
+    S = uni(gp(static_cast<V*>(pS)));
+    Hd = uni(gp(static_cast<V*>(pH)));
+    Gd = uni(gp(static_cast<V*>(pG)));
+    y = uni(gp(static_cast<const V*>(cur ? py1 : py0)));
+    ys = uni(gp(static_cast<const V*>(cur ? ps1 : ps0)));
+    Ax = uni(gp(static_cast<const V*>(cur ? pa1 : pa0)));
+    yn = uni(gp(static_cast<V*>(cur ? py0 : py1)));
+    ysn = uni(gp(static_cast<V*>(cur ? ps0 : ps1)));
+    Axn = uni(gp(static_cast<V*>(cur ? pa0 : pa1)));
+    // x' was written by this attempt's primal step into the other buffer
+    vecs[0] = uni(gp(static_cast<const V*>(cur ? px0 : px1)));
+    sense = uni(gp(psense));
     Hsrc = upd ? Hd : y;
     Gsrc = upd ? Gd : y;
-    vecs[0] = gp(static_cast<const V*>(lp->x[nxt]));
-    rp = gp(lp->rp_a);
-    ci = gp(lp->ci_a);
-    va = gp(static_cast<const V*>(lp->va_a));
-    b = uni(b), S = uni(S), Hd = uni(Hd), y = uni(y), ys = uni(ys), Ax = uni(Ax);
-    yn = uni(yn), ysn = uni(ysn), Axn = uni(Axn), Gd = uni(Gd), sense = uni(sense);
-    Hsrc = uni(Hsrc), Gsrc = uni(Gsrc), vecs[0] = uni(vecs[0]);
-    rp = uni(rp), ci = uni(ci), va = uni(va);
+    rp = uni(gp(prp));
+    ci = uni(gp(pci));
+    va = uni(gp(static_cast<const V*>(pva)));
+    part_ = uni(ppart);
+    stride_ = uni(pstride);
     sig = uni(sig), etav = uni(etav);
     return true;
   }
@@ -1106,7 +1213,7 @@ struct DualStep {
     V Si = q.S;
     if (upd) {
       V h = q.H;
-      Si = learn_elem<V>(Si, h, q.G, lscale, lp->prm, hnorm);
+      Si = learn_elem<V>(Si, h, q.G, lscale, prm, hnorm);
       stg(S, (uint32_t)i, Si);
       stg(Hd, (uint32_t)i, h);
     }
@@ -1133,16 +1240,29 @@ struct DualStep {
     }
   }
 
-  __device__ __forceinline__ double* part() const { return lp->part_a; }
-  __device__ __forceinline__ int stride() const { return lp->ntiles_a; }
+  __device__ __forceinline__ double* part() const { return part_; }
+  __device__ __forceinline__ int stride() const { return stride_; }
 };
 
 // Chunking of a step kernel's tile list: fixed sets carry it in the launch
 // arguments (no dependent load before the work items); the server's
 // changing set reads the device-side counts.
+// Makes each value live in a scalar register at this point. Kernel
+// arguments read later behind branches would otherwise be loaded one
+// cache line at a time, each load waiting for the branch before it.
+template <typename T>
+__device__ __forceinline__ void sgpr_ready1(const T& v) {
+  asm volatile("" ::"s"(v));
+}
+template <typename... T>
+__device__ __forceinline__ void sgpr_ready(const T&... v) {
+  (sgpr_ready1(v), ...);
+}
+
 __device__ __forceinline__ SideChunks step_chunks(const LaunchCfg& cfg, bool tside) {
-  if (cfg.step_fixed)
-    return SideChunks{tside ? cfg.sgrid_t : cfg.sgrid_a, tside ? cfg.schunk_t : cfg.schunk_a};
+  const int fixed = cfg.step_fixed;
+  const int g = tside ? cfg.sgrid_t : cfg.sgrid_a, ch = tside ? cfg.schunk_t : cfg.schunk_a;
+  if (fixed) return SideChunks{g, ch};
   return side_chunks(cfg.counts, tside);
 }
 
@@ -1155,8 +1275,9 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
   dd_reset(p);
   PrimalStep<V> st;
   __shared__ WorkItem s_items[kItemWin];
+  sgpr_ready(cfg.lps, cfg.step_t, cfg.counts, cfg.step_fixed, cfg.sgrid_t, cfg.schunk_t, force);
   run_chunk_spmv<V, 1>(
-      cfg.step_fixed ? cfg.step_t : cfg.work_t, step_chunks(cfg, true), s_items, st.rp, st.ci,
+      cfg.step_t, step_chunks(cfg, true), s_items, st.rp, st.ci,
       st.va, st.vecs, nodiv,
       [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.slot, force); },
       [&](int j) { return st.load(j); },
@@ -1177,8 +1298,9 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
   dd_reset(p);
   DualStep<V> st;
   __shared__ WorkItem s_items[kItemWin];
+  sgpr_ready(cfg.lps, cfg.step_a, cfg.counts, cfg.step_fixed, cfg.sgrid_a, cfg.schunk_a, force);
   run_chunk_spmv<V, 1>(
-      cfg.step_fixed ? cfg.step_a : cfg.work_a, step_chunks(cfg, false), s_items, st.rp, st.ci,
+      cfg.step_a, step_chunks(cfg, false), s_items, st.rp, st.ci,
       st.va, st.vecs, nodiv,
       [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.slot, force); },
       [&](int i) { return st.load(i); },
@@ -1215,14 +1337,22 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   if (chi < 0) return;
   const WinItem it = list[chi];
   if (it.lp < 0) return;  // padding of the list to a multiple of 8
+  // the window arrays' pointers are read with the step's context (one
+  // round trip for both)
+  const gptr<const LpDev> L = gp(&cfg.lps[it.lp]);
+  const uint16_t* const pwc = tside ? L->wcol_t : L->wcol_a;
+  const uint16_t* const pwr = tside ? L->wrow_t : L->wrow_a;
+  const void* const pwv = tside ? L->wval_t : L->wval_a;
+  const WinPass* const ppass = tside ? L->wpass_t : L->wpass_a;
+  const WinRange* const prange = tside ? L->wrange_t : L->wrange_a;
   Step st;
   if (!st.begin(cfg, it.ctl, it.lp, it.slot, force)) return;
   const LpDev* lp = st.lp;
-  const gptr<const uint16_t> wc = uni(gp(tside ? lp->wcol_t : lp->wcol_a));
-  const gptr<const uint16_t> wr = uni(gp(tside ? lp->wrow_t : lp->wrow_a));
-  const gptr<const float> wv = uni(gp(static_cast<const float*>(tside ? lp->wval_t : lp->wval_a)));
-  const gptr<const WinPass> passes = uni(gp(tside ? lp->wpass_t : lp->wpass_a));
-  const gptr<const WinRange> ranges = uni(gp(tside ? lp->wrange_t : lp->wrange_a));
+  const gptr<const uint16_t> wc = uni(gp(pwc));
+  const gptr<const uint16_t> wr = uni(gp(pwr));
+  const gptr<const float> wv = uni(gp(static_cast<const float*>(pwv)));
+  const gptr<const WinPass> passes = uni(gp(ppass));
+  const gptr<const WinRange> ranges = uni(gp(prange));
   const gptr<const float> vec = st.vecs[0];
   const int t = threadIdx.x;
   const int r0 = uni(it.r0), nrow = uni(it.r1 - it.r0), nseg = uni(it.nseg);
@@ -1391,27 +1521,119 @@ __global__ __launch_bounds__(kWinBlock) void k_dual_win(LaunchCfg cfg, int force
 // first (the LP table holds at least one record per workgroup of this
 // launch, so it is read before the LP count arrives), then the control
 // block and both partial arrays together.
-__global__ __launch_bounds__(kBlock) void k_decide(LaunchCfg cfg) {
+// What the step decision needs from an LP's record, in scalar registers:
+// pointers, partial-slot counts and the copies of the parameters it reads.
+struct DecideLp {
+  Ctl* ctl;
+  const double* ring;
+  const double* part_t;
+  const double* part_a;
+  int ntiles_t, ntiles_a, ns_t, ns_a;
+  double lr;
+  int64_t max_iter;
+  int32_t phi, schedule, normalize, eval_every, max_retries, flags;
+};
+
+__device__ __forceinline__ DecideLp decide_lp(const LpDev* rec, int step_fixed) {
+  const gptr<const LpDev> L = gp(rec);
+  DecideLp d;
+  d.ctl = uni(L->ctl);
+  d.ring = uni((const double*)L->pow_ring);
+  d.part_t = uni((const double*)L->part_t);
+  d.part_a = uni((const double*)L->part_a);
+  d.ntiles_t = uni(L->ntiles_t);
+  d.ntiles_a = uni(L->ntiles_a);
+  // slots of the step kernels: their own lists in fixed sets, else the
+  // evaluation lists
+  d.ns_t = uni(step_fixed ? L->nslot_st : L->nslot_t);
+  d.ns_a = uni(step_fixed ? L->nslot_sa : L->nslot_a);
+  d.lr = uni(L->s_lr);
+  d.max_iter = uni(L->s_max_iter);
+  d.phi = uni(L->s_phi);
+  d.schedule = uni(L->s_schedule);
+  d.normalize = uni(L->s_normalize);
+  d.eval_every = uni(L->s_eval_every);
+  d.max_retries = uni(L->s_max_retries);
+  d.flags = uni(L->s_flags);
+  return d;
+}
+
+// One workgroup per LP: the step decision of the attempt the step kernels
+// just ran. The loads come in three rounds: the launch arguments; the LP
+// count beside the first LP record (the launch grid never exceeds the LP
+// table, and nothing the record points to is read before the count shows
+// that the LP exists); then the factor ring, the partial sums and the
+// control block together. The factor of the attempt is picked from the
+// ring through LDS once the attempt count is known.
+// One wave per SIMD: a single workgroup per LP runs this kernel, so the
+// registers go to keeping the partial loads in flight at once.
+static_assert(2 * kPowRing <= kBlock && (kPowRing & (kPowRing - 1)) == 0,
+              "one thread per ring entry, a power of two");
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_decide(
+    LaunchCfg cfg) {
   __shared__ DD s_red[4 * 7];
+  __shared__ double s_ring[kBlock];
+  sgpr_ready(cfg.lps, cfg.counts, cfg.step_fixed);
   int li = blockIdx.x;
-  LpDev lp = cfg.lps[li];
+  DecideLp d = decide_lp(&cfg.lps[li], cfg.step_fixed);
   const int nlps = uni(gp(cfg.counts)->nlps);
   while (li < nlps) {
-    Ctl* cp = lp.ctl;
-    const int status = uni(cp->status), need = uni(cp->need_eval);
-    const int64_t k = uni(cp->k), k_limit = uni(cp->k_limit);
+    const gptr<const Ctl> g = gp(d.ctl);
+    StepIn in;
+    in.lr = d.lr;
+    in.max_iter = d.max_iter;
+    in.phi = d.phi;
+    in.schedule = d.schedule;
+    in.normalize = d.normalize;
+    in.eval_every = d.eval_every;
+    in.max_retries = d.max_retries;
+    in.flags = d.flags;
+    // every thread reads one ring entry (the two halves twice over); the
+    // value stays in a vector register until after the partial sums
+    const double rv = gp(d.ring)[threadIdx.x & (2 * kPowRing - 1)];
+    int status = 0, need = 0;
+    int64_t k_limit = 0, ring_base = 0;
     double sv[7];
-    // slots of the step kernels: their own lists in fixed sets, else the
-    // evaluation lists
-    const int ns_t = cfg.step_fixed ? lp.nslot_st : lp.nslot_t;
-    const int ns_a = cfg.step_fixed ? lp.nslot_sa : lp.nslot_a;
-    sum_partials2<3, 4>(lp.part_t, lp.ntiles_t, ns_t, lp.part_a, lp.ntiles_a, ns_a,
-                        sv, s_red);
-    if (status == kRunning && need == 0 && k < k_limit && threadIdx.x == 0)
-      decide_step(*cp, *lp.prm, lp, sv);
+    // the control block is read after the first round of partial loads is
+    // issued, in the same round trip
+    sum_partials2<3, 4>(d.part_t, d.ntiles_t, d.ns_t, d.part_a, d.ntiles_a, d.ns_a, sv, s_red,
+                        [&]() {
+                          // every load first, then the moves to scalar
+                          // registers (each of which waits for its load)
+                          const int st0 = g->status, ne0 = g->need_eval, cu0 = g->cur;
+                          const int64_t kl0 = g->k_limit, rb0 = g->ring_base, k0 = g->k;
+                          const int64_t t0 = g->t, at0 = g->attempts, re0 = g->retries;
+                          const double et0 = g->eta, om0 = g->omega, w0 = g->w;
+                          const double hp0 = g->hp_norm, hd0 = g->hd_norm;
+                          status = uni(st0);
+                          need = uni(ne0);
+                          k_limit = uni(kl0);
+                          ring_base = uni(rb0);
+                          in.eta = uni(et0);
+                          in.omega = uni(om0);
+                          in.w = uni(w0);
+                          in.hp_norm = uni(hp0);
+                          in.hd_norm = uni(hd0);
+                          in.k = uni(k0);
+                          in.t = uni(t0);
+                          in.attempts = uni(at0);
+                          in.retries = uni(re0);
+                          in.cur = uni(cu0);
+                        });
+    s_ring[threadIdx.x] = rv;
+    __syncthreads();  // s_ring is written
+    if (status == kRunning && need == 0 && in.k < k_limit && threadIdx.x == 0) {
+      // the attempt decided here is j = attempts + 1, in the ring at
+      // j - ring_base - 1 (the ring covers every attempt of the sequence)
+      int64_t r = in.attempts - ring_base;
+      r = r < 0 ? 0 : (r >= kPowRing ? kPowRing - 1 : r);
+      in.f_red = s_ring[r];
+      in.f_gro = s_ring[kPowRing + r];
+      decide_step(*d.ctl, in, sv);
+    }
     __syncthreads();
     li += gridDim.x;
-    if (li < nlps) lp = cfg.lps[li];
+    if (li < nlps) d = decide_lp(&cfg.lps[li], cfg.step_fixed);
   }
 }
 
@@ -1423,7 +1645,7 @@ __global__ __launch_bounds__(kBlock) void k_learn_flush(LaunchCfg cfg) {
     const LpDev& lp = cfg.lps[it.lp];
     const Ctl* c = it.ctl;
     double scale = 1.0;
-    if (!learn_side(c, lp.prm, tside, &scale)) return;
+    if (!learn_side(c->learn_pending, tside ? c->g2 : c->r2, lp.prm, &scale)) return;
     V* P = static_cast<V*>(tside ? lp.T : lp.S);
     V* H = static_cast<V*>(tside ? lp.Hp : lp.Hd);
     const V* G = static_cast<const V*>(tside ? lp.Gp : lp.Gd);
@@ -1583,19 +1805,24 @@ __global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg) {
     const LpDev& lp = cfg.lps[li];
     Ctl* c = lp.ctl;
     if (c->status != kRunning) continue;
-    // step-rule factors for the attempts of this launch sequence that the
-    // host table does not cover (the step decision, fused into the dual
-    // kernel, reads them instead of computing powers there)
+    // step-rule factors for the attempts j = a0 + 1 .. a0 + kPowRing of this
+    // launch sequence (which holds at most kPowRing attempts): the host
+    // table's values while it covers j, else powers computed here. The step
+    // decision reads the whole ring beside its partial sums.
     const int64_t a0 = c->attempts;
-    if (a0 + kPowRing > kPowTab) {
-      const DevParams* p = lp.prm;
-      for (int t = threadIdx.x; t < kPowRing; t += kBlock) {
-        const double j1 = (double)(a0 + 1 + t) + 1.0;
+    const DevParams* p = lp.prm;
+    for (int t = threadIdx.x; t < kPowRing; t += kBlock) {
+      const int64_t j = a0 + 1 + t;
+      if (j <= kPowTab) {
+        lp.pow_ring[t] = lp.pow_tab[j - 1];
+        lp.pow_ring[kPowRing + t] = lp.pow_tab[kPowTab + j - 1];
+      } else {
+        const double j1 = (double)j + 1.0;
         lp.pow_ring[t] = pow(j1, -p->step_reduction);
         lp.pow_ring[kPowRing + t] = pow(j1, -p->step_growth);
       }
-      if (threadIdx.x == 0) c->ring_base = a0;
     }
+    if (threadIdx.x == 0) c->ring_base = a0;
     if (!eval_guard(c)) continue;
     double st[2 * kEvT], sa[2 * kEvA];
     sum_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, lp.nslot_t, st, s_red);

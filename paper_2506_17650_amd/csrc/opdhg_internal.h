@@ -19,7 +19,8 @@ namespace opdhg {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kPartStride = 32;    // doubles of reduction partials per tile (16 double-doubles)
 constexpr int kPowTab = 8192;      // host-computed step-rule factors for the first attempts
-constexpr int kPowRing = 64;       // factors for the attempts of one launch sequence beyond
+constexpr int kPowRing = 64;       // factors for the attempts of one launch sequence (at most
+                                   // kPowRing attempts each)
 constexpr int kGridCap = 2048;     // default workgroups of a launch (chunks of the work list)
 constexpr int kMaxGrid = 65536;    // largest workgroup count a caller may ask for
 constexpr int kTileCap = 1024;     // nonzeros of a stream tile (staged in LDS)
@@ -191,9 +192,14 @@ struct LpDev {
   double* part_t;       // ntiles_t * kPartStride
   double* part_a;       // ntiles_a * kPartStride
   const double* pow_tab;  // 2 * kPowTab: (j+1)^-reduction, then (j+1)^-growth, j = 1..kPowTab
-  double* pow_ring;       // 2 * kPowRing: the same factors for j = ring_base+1 .. +kPowRing
+  double* pow_ring;       // 2 * kPowRing: the factors for j = ring_base+1 .. +kPowRing
   Ctl* ctl;
   const DevParams* prm;
+  // copies of the parameters the step decision reads, so that they arrive
+  // with the record instead of one dependent load later
+  double s_lr;
+  int64_t s_max_iter;
+  int32_t s_phi, s_schedule, s_normalize, s_eval_every, s_max_retries, s_flags;
   // windowed rows of each side (FP32; empty when the side has none)
   const uint16_t* wcol_t;  // window-local column of each entry
   const uint16_t* wrow_t;  // chunk-local row of each entry
@@ -261,8 +267,8 @@ struct LaunchCfg {
   int grid_t, chunk_t, grid_a, chunk_a;
   // the step kernels' work: tile lists (rows not taken by windowed chunks)
   // and windowed chunks. With step_fixed the tile lists' chunking is the
-  // one below (a fixed set of LPs); else the step kernels run the
-  // evaluation lists with the device-side chunking.
+  // one below (a fixed set of LPs); else step_t / step_a point at the
+  // evaluation lists, which run with the device-side chunking.
   const WorkItem* step_t;
   const WorkItem* step_a;
   const WinItem* win_t;

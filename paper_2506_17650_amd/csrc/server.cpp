@@ -563,6 +563,7 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
     return nullptr;
   }
   if (cfg->max_active < 1 || cfg->max_active > 65535 || cfg->attempts_per_replay < 1 ||
+      cfg->attempts_per_replay > kPowRing ||
       (cfg->precision != OPDHG_FP32 && cfg->precision != OPDHG_FP64) || cfg->workgroups < 0 ||
       cfg->prep_threads < 0 || cfg->prep_threads > 64 ||
       cfg->workgroups > kMaxGrid || !(cfg->poll_interval_s >= 0.0)) {

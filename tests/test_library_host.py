@@ -9,6 +9,7 @@
 No test here launches a kernel.
 """
 
+import ctypes
 import os
 import re
 import subprocess
@@ -204,3 +205,15 @@ def test_constant_step_needs_host_preparation():
     with pytest.raises(P.OpdhgError) as e:
         P.opdhg_workspace_bytes(lp, p)
     assert e.value.code == capi.OPDHG_ERR_INVALID_ARGUMENT
+
+
+def test_server_sequences_hold_at_most_64_attempts():
+    # the step-rule factor ring covers 64 attempts per launch sequence; the
+    # configuration is checked before the arena or any stream is used
+    lib = capi.load()
+    for bad in (0, 65, 1000):
+        cfg = P.opdhg_server_default_cfg(attempts_per_replay=bad)
+        h = lib.opdhg_server_create(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 20,
+                                    None, None, None)
+        assert not h, bad
+        assert "configuration" in capi.opdhg_last_error()
