@@ -134,12 +134,19 @@ __device__ __forceinline__ void stg(gptr<T> base, uint32_t idx, T v) {
 }
 
 // Barrier for data exchanged through LDS only: waits for this wave's LDS
-// accesses, not for its global loads and stores, which stay in flight
-// across the barrier. (__syncthreads also drains every global access.)
+// accesses (lgkmcnt), not for its global loads and stores, which stay in
+// flight across the barrier. A workgroup-scope fence, even one limited to
+// LDS, makes the compiler drain every global store first (vmcnt(0)), which
+// puts a store round trip in front of every reduction that follows a row
+// epilogue. The compiler-only fences keep memory accesses on their side.
+// No kernel here exchanges global data between the waves of a workgroup.
 __device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  // s_waitcnt lgkmcnt(0), with the vmcnt and expcnt fields at their maxima
+  // (no wait on them)
+  __builtin_amdgcn_s_waitcnt(0xC07F);
   __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Chunk of the work list taken by this workgroup. Workgroups are handed to
@@ -160,18 +167,41 @@ __device__ __forceinline__ DD dd_shfl_xor(const DD& a, int off) {
   return DD{__shfl_xor(a.hi, off, 64), __shfl_xor(a.lo, off, 64)};
 }
 
-// Merge NV double-doubles over the workgroup (NW waves) in a fixed tree;
-// thread 0 gets the totals. s_red holds NW * NV DD.
+// The value of another lane moved by DPP (a VALU operand modifier, no LDS
+// traffic): CTRL selects the pattern, ROWS the rows of 16 lanes written;
+// lanes without a source, and rows not written, get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <int CTRL, int ROWS, int NV>
+__device__ __forceinline__ void dd_dpp_step(DD (&v)[NV]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    v[q] = dd_merge(v[q], DD{dpp_f64<CTRL, ROWS>(v[q].hi), dpp_f64<CTRL, ROWS>(v[q].lo)});
+}
+
+// Merge NV double-doubles over the workgroup (NW waves) in a fixed order;
+// thread 0 gets the totals. s_red holds NW * NV DD. Within a wave a scan of
+// DPP moves brings the wave's total to lane 63: row_shr by 1, 2, 4 and 8
+// (lane 15 of each row of 16 holds the row's sum), row_bcast:15 into rows
+// 1 and 3, then row_bcast:31 into rows 2 and 3. Every level runs in the
+// VALU, so the reductions of all workgroups on a CU do not queue on LDS.
 template <int NV, int NW = kBlock / 64>
 __device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = dd_merge(v[q], dd_shfl_xor(v[q], off));
-  }
-  if (lane == 0) {
+  dd_dpp_step<0x111, 0xF>(v);  // row_shr:1
+  dd_dpp_step<0x112, 0xF>(v);  // row_shr:2
+  dd_dpp_step<0x114, 0xF>(v);  // row_shr:4
+  dd_dpp_step<0x118, 0xF>(v);  // row_shr:8
+  dd_dpp_step<0x142, 0xA>(v);  // row_bcast:15
+  dd_dpp_step<0x143, 0xC>(v);  // row_bcast:31
+  if (lane == 63) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) s_red[wave * NV + q] = v[q];
   }
@@ -1070,33 +1100,57 @@ struct PrimalStep {
     return q;
   }
 
-  // Row j with (A^T y)_j = aty: partials |x'-x|^2 (or its T^-1 norm),
-  // |g|^2, |G^p|^2 into p.
-  __device__ __forceinline__ void finish(int j, V aty, PrimalPre<V>& q, DD (&p)[3]) const {
-    V Tj = q.T;
+  // The row epilogue's stores wait in registers until commit(), which runs
+  // at the next row's epilogue or after the workgroup's partial sums are
+  // stored: a store's data registers cannot be reused before the store
+  // completes, so stores issued ahead of the reduction would make it wait
+  // for them.
+  mutable bool w_on = false;
+  mutable int w_j = 0;
+  mutable V w_x = V(0), w_xs = V(0), w_T = V(0), w_H = V(0), w_G = V(0);
+
+  __device__ __forceinline__ void commit() const {
+    if (!w_on) return;
+    const uint32_t j = (uint32_t)w_j;
     if (upd) {
-      V h = q.H;
-      Tj = learn_elem<V>(Tj, h, q.G, lscale, prm, hnorm);
-      stg(T, (uint32_t)j, Tj);
-      stg(Hp, (uint32_t)j, h);
+      stg(T, j, w_T);
+      stg(Hp, j, w_H);
     }
+    stg(xn, j, w_x);
+    stg(xsn, j, w_xs);
+    if (learn) stg(Gp, j, w_G);
+    w_on = false;
+  }
+
+  // Row j with (A^T y)_j = aty: partials |x'-x|^2 (or its T^-1 norm),
+  // |g|^2, |G^p|^2 into p; the row's new values go out at commit().
+  __device__ __forceinline__ void finish(int j, V aty, PrimalPre<V>& q, DD (&p)[3]) const {
+    commit();
+    V Tj = q.T;
+    V h = q.H;
+    if (upd) Tj = learn_elem<V>(Tj, h, q.G, lscale, prm, hnorm);
     const V g = q.c - aty;
     const V xh = q.x - (tau * Tj) * g;
     const V xv = clampv(xh, q.l, q.u);
-    stg(xn, (uint32_t)j, xv);
-    stg(xsn, (uint32_t)j, q.xs + etav * xv);
     const double dx = (double)xv - (double)q.x;
     // the movement of the step rule, optionally in the T^-1 norm
     const double tj = (double)Tj;
     const double wdx = !wstep ? dx : (tj > 0.0 ? dx / tj : 0.0);
     dd_add_prod(p[0], dx, wdx);
     dd_add_prod(p[1], (double)g, (double)g);
+    V gp_ = V(0);
     if (learn) {
       const bool ind = (xh >= q.l) && (xh <= q.u);
-      const V gp_ = ind ? -((tau * g) * g) : V(0);
-      stg(Gp, (uint32_t)j, gp_);
+      gp_ = ind ? -((tau * g) * g) : V(0);
       dd_add_prod(p[2], (double)gp_, (double)gp_);
     }
+    w_on = true;
+    w_j = j;
+    w_x = xv;
+    w_xs = q.xs + etav * xv;
+    w_T = Tj;
+    w_H = h;
+    w_G = gp_;
   }
 
   __device__ __forceinline__ double* part() const { return part_; }
@@ -1207,24 +1261,38 @@ struct DualStep {
     return q;
   }
 
-  // Row i with (A x')_i = axn: partials |y'-y|^2 (or its Sigma^-1 norm),
-  // (y'-y).(Ax'-Ax), |b-Ax|^2, |G^d|^2 into p.
-  __device__ __forceinline__ void finish(int i, V axn, DualPre<V>& q, DD (&p)[4]) const {
-    V Si = q.S;
+  // as in PrimalStep: the row's stores wait in registers until commit()
+  mutable bool w_on = false;
+  mutable int w_i = 0;
+  mutable V w_y = V(0), w_ax = V(0), w_ys = V(0), w_S = V(0), w_H = V(0), w_G = V(0);
+
+  __device__ __forceinline__ void commit() const {
+    if (!w_on) return;
+    const uint32_t i = (uint32_t)w_i;
     if (upd) {
-      V h = q.H;
-      Si = learn_elem<V>(Si, h, q.G, lscale, prm, hnorm);
-      stg(S, (uint32_t)i, Si);
-      stg(Hd, (uint32_t)i, h);
+      stg(S, i, w_S);
+      stg(Hd, i, w_H);
     }
+    stg(yn, i, w_y);
+    stg(Axn, i, w_ax);
+    stg(ysn, i, w_ys);
+    if (learn) stg(Gd, i, w_G);
+    w_on = false;
+  }
+
+  // Row i with (A x')_i = axn: partials |y'-y|^2 (or its Sigma^-1 norm),
+  // (y'-y).(Ax'-Ax), |b-Ax|^2, |G^d|^2 into p; the row's new values go out
+  // at commit().
+  __device__ __forceinline__ void finish(int i, V axn, DualPre<V>& q, DD (&p)[4]) const {
+    commit();
+    V Si = q.S;
+    V h = q.H;
+    if (upd) Si = learn_elem<V>(Si, h, q.G, lscale, prm, hnorm);
     const V axbar = V(2) * axn - q.ax;
     const V rt = q.b - axbar;
     const V yh = q.y + (sig * Si) * rt;
     const bool ineq = q.ineq != 0;
     const V yv = (ineq && yh < V(0)) ? V(0) : yh;
-    stg(yn, (uint32_t)i, yv);
-    stg(Axn, (uint32_t)i, axn);
-    stg(ysn, (uint32_t)i, q.ys + etav * yv);
     const double dy = (double)yv - (double)q.y;
     const double si = (double)Si;
     const double wdy = !wstep ? dy : (si > 0.0 ? dy / si : 0.0);
@@ -1232,12 +1300,20 @@ struct DualStep {
     dd_add_prod(p[1], dy, (double)axn - (double)q.ax);
     const V r = q.b - q.ax;
     dd_add_prod(p[2], (double)r, (double)r);
+    V gd = V(0);
     if (learn) {
       const bool ind = !ineq || yh >= V(0);
-      const V gd = ind ? -((sig * r) * rt) : V(0);
-      stg(Gd, (uint32_t)i, gd);
+      gd = ind ? -((sig * r) * rt) : V(0);
       dd_add_prod(p[3], (double)gd, (double)gd);
     }
+    w_on = true;
+    w_i = i;
+    w_y = yv;
+    w_ax = axn;
+    w_ys = q.ys + etav * yv;
+    w_S = Si;
+    w_H = h;
+    w_G = gd;
   }
 
   __device__ __forceinline__ double* part() const { return part_; }
@@ -1285,8 +1361,10 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
       [&](const WorkItem& it, bool run) {
         if (run) flush_partials<3>(p, s_red, st.part(), st.stride(), it.slot);
         else dd_reset(p);
+        st.commit();
       },
       sh);
+  st.commit();
 }
 
 template <typename V>
@@ -1308,8 +1386,10 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
       [&](const WorkItem& it, bool run) {
         if (run) flush_partials<4>(p, s_red, st.part(), st.stride(), it.slot);
         else dd_reset(p);
+        st.commit();
       },
       sh);
+  st.commit();
 }
 
 // Windowed step kernel (FP32): one workgroup of kWinBlock threads per
@@ -1462,6 +1542,7 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   }
   block_sum<NV, kWinWaves>(p, s_red);
   store_partials<NV>(st.part(), st.stride(), it.slot, p);
+  st.commit();
 }
 
 // Segmented long rows (FP32): kSegLanes lanes per row. Lane l adds the
@@ -1498,6 +1579,7 @@ __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* li
   if (on && lane == 0) st.finish(row, acc, pre, p);
   block_sum<NV>(p, s_red);
   store_partials<NV>(st.part(), st.stride(), it.slot, p);
+  st.commit();
 }
 
 __global__ __launch_bounds__(kBlock) void k_primal_seg(LaunchCfg cfg, int force) {
@@ -1516,11 +1598,6 @@ __global__ __launch_bounds__(kWinBlock) void k_dual_win(LaunchCfg cfg, int force
   win_chunk<DualStep<float>, DualPre<float>, 4>(cfg, cfg.win_a, cfg.nwin_a, false, force);
 }
 
-// One workgroup per LP: the step decision of the attempt that just ran.
-// The loads are arranged so that few wait for another: the LP's record
-// first (the LP table holds at least one record per workgroup of this
-// launch, so it is read before the LP count arrives), then the control
-// block and both partial arrays together.
 // What the step decision needs from an LP's record, in scalar registers:
 // pointers, partial-slot counts and the copies of the parameters it reads.
 struct DecideLp {
