@@ -97,6 +97,17 @@ __device__ __forceinline__ DD dd_merge(DD a, const DD& b) {
 
 __device__ __forceinline__ double dd_value(const DD& a) { return a.hi + a.lo; }
 
+// a += x * y as a double-double, or (PLAIN) in FP64 alone with lo kept at
+// 0. The FP32 step kernels use the plain form: their results move with the
+// tiling by rounding anyway, and a fixed order keeps them run-to-run
+// identical. FP64 runs keep the double-double, on which their independence
+// of the tiling rests.
+template <bool PLAIN>
+__device__ __forceinline__ void acc_prod(DD& a, double x, double y) {
+  if constexpr (PLAIN) a.hi = fma(x, y, a.hi);
+  else dd_add_prod(a, x, y);
+}
+
 // ---- memory access ----
 // Pointers into the workspace reach the kernels through tables, so the
 // compiler sees generic pointers and emits flat accesses, which count
@@ -178,11 +189,13 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-template <int CTRL, int ROWS, int NV>
+template <int CTRL, int ROWS, bool PLAIN, int NV>
 __device__ __forceinline__ void dd_dpp_step(DD (&v)[NV]) {
 #pragma unroll
-  for (int q = 0; q < NV; ++q)
-    v[q] = dd_merge(v[q], DD{dpp_f64<CTRL, ROWS>(v[q].hi), dpp_f64<CTRL, ROWS>(v[q].lo)});
+  for (int q = 0; q < NV; ++q) {
+    if constexpr (PLAIN) v[q].hi += dpp_f64<CTRL, ROWS>(v[q].hi);
+    else v[q] = dd_merge(v[q], DD{dpp_f64<CTRL, ROWS>(v[q].hi), dpp_f64<CTRL, ROWS>(v[q].lo)});
+  }
 }
 
 // Merge NV double-doubles over the workgroup (NW waves) in a fixed order;
@@ -191,16 +204,17 @@ __device__ __forceinline__ void dd_dpp_step(DD (&v)[NV]) {
 // (lane 15 of each row of 16 holds the row's sum), row_bcast:15 into rows
 // 1 and 3, then row_bcast:31 into rows 2 and 3. Every level runs in the
 // VALU, so the reductions of all workgroups on a CU do not queue on LDS.
-template <int NV, int NW = kBlock / 64>
+// PLAIN: FP64 sums of the high parts only (see acc_prod).
+template <int NV, int NW = kBlock / 64, bool PLAIN = false>
 __device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  dd_dpp_step<0x111, 0xF>(v);  // row_shr:1
-  dd_dpp_step<0x112, 0xF>(v);  // row_shr:2
-  dd_dpp_step<0x114, 0xF>(v);  // row_shr:4
-  dd_dpp_step<0x118, 0xF>(v);  // row_shr:8
-  dd_dpp_step<0x142, 0xA>(v);  // row_bcast:15
-  dd_dpp_step<0x143, 0xC>(v);  // row_bcast:31
+  dd_dpp_step<0x111, 0xF, PLAIN>(v);  // row_shr:1
+  dd_dpp_step<0x112, 0xF, PLAIN>(v);  // row_shr:2
+  dd_dpp_step<0x114, 0xF, PLAIN>(v);  // row_shr:4
+  dd_dpp_step<0x118, 0xF, PLAIN>(v);  // row_shr:8
+  dd_dpp_step<0x142, 0xA, PLAIN>(v);  // row_bcast:15
+  dd_dpp_step<0x143, 0xC, PLAIN>(v);  // row_bcast:31
   if (lane == 63) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) s_red[wave * NV + q] = v[q];
@@ -211,7 +225,10 @@ __device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
     for (int q = 0; q < NV; ++q) {
       DD t = s_red[q];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) t = dd_merge(t, s_red[w * NV + q]);
+      for (int w = 1; w < NW; ++w) {
+        if constexpr (PLAIN) t.hi += s_red[w * NV + q].hi;
+        else t = dd_merge(t, s_red[w * NV + q]);
+      }
       v[q] = t;
     }
   }
@@ -621,10 +638,10 @@ __device__ __forceinline__ void dd_reset(DD (&v)[NV]) {
 
 // End of an LP's part of this workgroup's chunk: reduce the thread sums and
 // store them in the LP's partial slot.
-template <int NV>
+template <int NV, bool PLAIN = false>
 __device__ __forceinline__ void flush_partials(DD (&p)[NV], DD* s_red, double* part, int stride,
                                                int slot) {
-  block_sum<NV>(p, s_red);
+  block_sum<NV, kBlock / 64, PLAIN>(p, s_red);
   store_partials<NV>(part, stride, slot, p);
   dd_reset(p);
 }
@@ -1001,6 +1018,8 @@ struct PrimalPre {
 // out of vector registers.
 template <typename V>
 struct PrimalStep {
+  // FP32 runs accumulate the partial sums in plain FP64 (see acc_prod)
+  static constexpr bool kPlain = sizeof(V) == 4;
   const LpDev* lp = nullptr;
   const DevParams* prm = nullptr;
   Ctl* c = nullptr;
@@ -1136,13 +1155,13 @@ struct PrimalStep {
     // the movement of the step rule, optionally in the T^-1 norm
     const double tj = (double)Tj;
     const double wdx = !wstep ? dx : (tj > 0.0 ? dx / tj : 0.0);
-    dd_add_prod(p[0], dx, wdx);
-    dd_add_prod(p[1], (double)g, (double)g);
+    acc_prod<kPlain>(p[0], dx, wdx);
+    acc_prod<kPlain>(p[1], (double)g, (double)g);
     V gp_ = V(0);
     if (learn) {
       const bool ind = (xh >= q.l) && (xh <= q.u);
       gp_ = ind ? -((tau * g) * g) : V(0);
-      dd_add_prod(p[2], (double)gp_, (double)gp_);
+      acc_prod<kPlain>(p[2], (double)gp_, (double)gp_);
     }
     w_on = true;
     w_j = j;
@@ -1168,6 +1187,7 @@ struct DualPre {
 // gradient of eq. (7) and the deferred learner update of Sigma).
 template <typename V>
 struct DualStep {
+  static constexpr bool kPlain = sizeof(V) == 4;  // as in PrimalStep
   const LpDev* lp = nullptr;
   const DevParams* prm = nullptr;
   const Ctl* c = nullptr;
@@ -1296,15 +1316,15 @@ struct DualStep {
     const double dy = (double)yv - (double)q.y;
     const double si = (double)Si;
     const double wdy = !wstep ? dy : (si > 0.0 ? dy / si : 0.0);
-    dd_add_prod(p[0], dy, wdy);
-    dd_add_prod(p[1], dy, (double)axn - (double)q.ax);
+    acc_prod<kPlain>(p[0], dy, wdy);
+    acc_prod<kPlain>(p[1], dy, (double)axn - (double)q.ax);
     const V r = q.b - q.ax;
-    dd_add_prod(p[2], (double)r, (double)r);
+    acc_prod<kPlain>(p[2], (double)r, (double)r);
     V gd = V(0);
     if (learn) {
       const bool ind = !ineq || yh >= V(0);
       gd = ind ? -((sig * r) * rt) : V(0);
-      dd_add_prod(p[3], (double)gd, (double)gd);
+      acc_prod<kPlain>(p[3], (double)gd, (double)gd);
     }
     w_on = true;
     w_i = i;
@@ -1359,7 +1379,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
       [&](int j) { return st.load(j); },
       [&](int j, V (&acc)[1], PrimalPre<V>& q) { st.finish(j, acc[0], q, p); },
       [&](const WorkItem& it, bool run) {
-        if (run) flush_partials<3>(p, s_red, st.part(), st.stride(), it.slot);
+        if (run) flush_partials<3, sizeof(V) == 4>(p, s_red, st.part(), st.stride(), it.slot);
         else dd_reset(p);
         st.commit();
       },
@@ -1384,7 +1404,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
       [&](int i) { return st.load(i); },
       [&](int i, V (&acc)[1], DualPre<V>& q) { st.finish(i, acc[0], q, p); },
       [&](const WorkItem& it, bool run) {
-        if (run) flush_partials<4>(p, s_red, st.part(), st.stride(), it.slot);
+        if (run) flush_partials<4, sizeof(V) == 4>(p, s_red, st.part(), st.stride(), it.slot);
         else dd_reset(p);
         st.commit();
       },
@@ -1540,7 +1560,7 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
     st.finish(r0 + r, part[r], q0, p);
     if (two) st.finish(r0 + r2, part[r2], q1, p);
   }
-  block_sum<NV, kWinWaves>(p, s_red);
+  block_sum<NV, kWinWaves, true>(p, s_red);
   store_partials<NV>(st.part(), st.stride(), it.slot, p);
   st.commit();
 }
@@ -1577,7 +1597,7 @@ __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* li
 #pragma unroll
   for (int off = kSegLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSegLanes);
   if (on && lane == 0) st.finish(row, acc, pre, p);
-  block_sum<NV>(p, s_red);
+  block_sum<NV, kBlock / 64, true>(p, s_red);
   store_partials<NV>(st.part(), st.stride(), it.slot, p);
   st.commit();
 }
