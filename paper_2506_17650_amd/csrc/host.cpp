@@ -1531,15 +1531,18 @@ void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& pre
   }
   const int64_t n = (int64_t)out.size();
   chunking(n, cap, grid, chunk);
-  const int64_t C = *chunk;
+  // every tile stores its own partial sums, in the slot of its index within
+  // the LP's list: an LP's partials, and the order the decision adds them
+  // in, do not depend on how the set's items are chunked over workgroups,
+  // so a packed or served LP adds exactly what its solo solve adds
   for (size_t i = 0; i < lps.size(); ++i) {
     const int64_t s = range[i].first, e = range[i].second;
-    const int64_t first_wg = s / C;
     for (int64_t q = s; q < e; ++q) {
-      out[q].slot = (int32_t)(q / C - first_wg);
-      out[q].last = (q == e - 1 || (q + 1) % C == 0) ? 1 : 0;
+      out[q].slot = out[q].tile;
+      out[q].last = 1;
+      out[q].first = q == s ? 1 : 0;
     }
-    const int32_t nslot = e > s ? (int32_t)((e - 1) / C - first_wg + 1) : 0;
+    const int32_t nslot = (int32_t)(e - s);
     if (step) (tside ? lps[i].nslot_st : lps[i].nslot_sa) = nslot;
     else (tside ? lps[i].nslot_t : lps[i].nslot_a) = nslot;
   }

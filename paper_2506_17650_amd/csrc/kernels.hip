@@ -205,16 +205,21 @@ __device__ __forceinline__ void dd_dpp_step(DD (&v)[NV]) {
 // 1 and 3, then row_bcast:31 into rows 2 and 3. Every level runs in the
 // VALU, so the reductions of all workgroups on a CU do not queue on LDS.
 // PLAIN: FP64 sums of the high parts only (see acc_prod).
-template <int NV, int NW = kBlock / 64, bool PLAIN = false>
-__device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+template <int NV, bool PLAIN>
+__device__ __forceinline__ void wave_scan(DD (&v)[NV]) {
   dd_dpp_step<0x111, 0xF, PLAIN>(v);  // row_shr:1
   dd_dpp_step<0x112, 0xF, PLAIN>(v);  // row_shr:2
   dd_dpp_step<0x114, 0xF, PLAIN>(v);  // row_shr:4
   dd_dpp_step<0x118, 0xF, PLAIN>(v);  // row_shr:8
   dd_dpp_step<0x142, 0xA, PLAIN>(v);  // row_bcast:15
   dd_dpp_step<0x143, 0xC, PLAIN>(v);  // row_bcast:31
+}
+
+template <int NV, int NW = kBlock / 64, bool PLAIN = false>
+__device__ __forceinline__ void block_sum(DD (&v)[NV], DD* s_red) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  wave_scan<NV, PLAIN>(v);
   if (lane == 63) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) s_red[wave * NV + q] = v[q];
@@ -892,7 +897,7 @@ __device__ __forceinline__ WorkItem uniform_item(const WorkItem& w) {
   u.lanes = __builtin_amdgcn_readfirstlane(w.lanes);
   u.slot = __builtin_amdgcn_readfirstlane(w.slot);
   u.last = __builtin_amdgcn_readfirstlane(w.last);
-  u.pad = 0;
+  u.first = __builtin_amdgcn_readfirstlane(w.first);
   return u;
 }
 
@@ -906,23 +911,45 @@ __device__ __forceinline__ SideChunks side_chunks(const Counts* counts, bool tsi
   return SideChunks{uni(tside ? c->grid_t : c->grid_a), uni(tside ? c->chunk_t : c->chunk_a)};
 }
 
+// Partial sums of the tiles of one window of work items: the four waves'
+// totals of each tile (lane 63 after wave_scan) and where the tile's sums
+// go (null: the tile's LP did not run).
+template <int NV>
+struct TilePartials {
+  DD w[kItemWin][kBlock / 64][NV];
+  double* dst[kItemWin];
+  int stride[kItemWin];
+  int slot[kItemWin];
+};
+
 // Drives a workgroup over its chunk of a side's work list, running the
-// sparse product of each tile with the row epilogues load / finish. When
-// the LP changes, begin(item) loads the LP's context (the pointers rp, ci,
-// va, vec refer to variables it sets) and returns whether the LP takes
-// part; end(item, run) closes the LP's part of the chunk.
-template <typename V, int NA, typename Begin, typename Load, typename Finish, typename End>
+// sparse product of each tile with the row epilogues load / finish, which
+// accumulate the tile's partial sums in p. When the LP changes,
+// begin(item) loads the LP's context (the pointers rp, ci, va, vec refer
+// to variables it sets) and returns whether the LP takes part; dest()
+// gives the LP's partial array and stride; commit() issues the row stores
+// the epilogues held back, after the tile's wave totals are in LDS and
+// before the next item can change the LP. Every tile stores its own
+// partial sums in its item's slot: each wave's totals go to LDS after the
+// tile (no barrier), and once per window of items the four waves' totals
+// of each tile are added in a fixed order and stored, after the barrier
+// the window needs anyway.
+template <typename V, int NA, int NV, bool PLAIN, typename Begin, typename Load, typename Finish,
+          typename Dest, typename Commit>
 __device__ __forceinline__ void run_chunk_spmv(const WorkItem* __restrict__ work, SideChunks sc,
                                                WorkItem* s_items, const gptr<const int32_t>& rp,
                                                const gptr<const int32_t>& ci,
                                                const gptr<const V>& va, const gptr<const V>* vec,
                                                const double* div, Begin&& begin, Load&& load,
-                                               Finish&& finish, End&& end,
+                                               Finish&& finish, Dest&& dest, Commit&& commit,
+                                               DD (&p)[NV], TilePartials<NV>& tp,
                                                SpmvShared<V, NA>& sh) {
   const int chi = chunk_index(sc.grid);
   if (chi < 0) return;
   const int chunk = sc.chunk;
   const int w0 = chi * chunk;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   int lp = -1;
   bool run = false;
   for (int k0 = 0; k0 < chunk; k0 += kItemWin) {
@@ -935,15 +962,50 @@ __device__ __forceinline__ void run_chunk_spmv(const WorkItem* __restrict__ work
     __syncthreads();
     for (int k = 0; k < cnt; ++k) {
       const WorkItem it = uniform_item(s_items[k]);
-      if (it.lp < 0) continue;
-      if (it.lp != lp) {
-        lp = it.lp;
-        run = begin(it);
+      bool on = false;
+      if (it.lp >= 0) {
+        if (it.lp != lp) {
+          lp = it.lp;
+          run = begin(it);
+        }
+        if (run) {
+          spmv_tile<V, NA>(it, rp, ci, va, vec, div, load, finish, sh);
+          wave_scan<NV, PLAIN>(p);
+          if (lane == 63) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) tp.w[k][wave][q] = p[q];
+          }
+          dd_reset(p);
+          commit();
+          on = true;
+        }
       }
-      if (run) spmv_tile<V, NA>(it, rp, ci, va, vec, div, load, finish, sh);
-      if (it.last) end(it, run);
+      if (threadIdx.x == 0) {
+        double* d;
+        int sd;
+        dest(d, sd);
+        tp.dst[k] = on ? d : nullptr;
+        tp.stride[k] = sd;
+        tp.slot[k] = it.slot;
+      }
     }
-    lds_barrier();  // the window is rewritten next
+    lds_barrier();  // the window's partials are in LDS; its items are rewritten next
+    for (int x = threadIdx.x; x < cnt * NV; x += kBlock) {
+      const int k = x / NV, q = x - k * NV;
+      double* d = tp.dst[k];
+      if (d) {
+        DD t = tp.w[k][0][q];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) {
+          if constexpr (PLAIN) t.hi += tp.w[k][w][q].hi;
+          else t = dd_merge(t, tp.w[k][w][q]);
+        }
+        const gptr<double> g = gp(d);
+        const size_t sd = (size_t)tp.stride[k], sl = (size_t)tp.slot[k];
+        g[(2 * q) * sd + sl] = t.hi;
+        g[(2 * q + 1) * sd + sl] = t.lo;
+      }
+    }
   }
 }
 
@@ -1038,7 +1100,9 @@ struct PrimalStep {
   bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
 
-  __device__ __forceinline__ bool begin(const LaunchCfg& cfg, Ctl* ctl, int lpi, int slot,
+  // first: this workgroup takes the LP's first item (it clears the flags
+  // below)
+  __device__ __forceinline__ bool begin(const LaunchCfg& cfg, Ctl* ctl, int lpi, int first,
                                         int force) {
     c = ctl;
     lp = &cfg.lps[lpi];
@@ -1065,8 +1129,8 @@ struct PrimalStep {
     double* const ppart = uni(L->part_t);
     const int pstride = uni(L->ntiles_t);
     // the restart / final copy of the evaluation step ran before this
-    // launch; the LP's first chunk (partial slot 0) clears the flags
-    if (slot == 0 && threadIdx.x == 0 && (v.restart_pending | v.finalize_avg)) {
+    // launch; the workgroup with the LP's first item clears the flags
+    if (first && threadIdx.x == 0 && (v.restart_pending | v.finalize_avg)) {
       c->restart_pending = 0;
       c->finalize_avg = 0;
     }
@@ -1365,50 +1429,48 @@ __device__ __forceinline__ SideChunks step_chunks(const LaunchCfg& cfg, bool tsi
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
   __shared__ SpmvShared<V, 1> sh;
-  __shared__ DD s_red[4 * 3];
+  __shared__ TilePartials<3> tp;
   const double nodiv[1] = {0.0};
   DD p[3];
   dd_reset(p);
   PrimalStep<V> st;
   __shared__ WorkItem s_items[kItemWin];
   sgpr_ready(cfg.lps, cfg.step_t, cfg.counts, cfg.step_fixed, cfg.sgrid_t, cfg.schunk_t, force);
-  run_chunk_spmv<V, 1>(
+  run_chunk_spmv<V, 1, 3, PrimalStep<V>::kPlain>(
       cfg.step_t, step_chunks(cfg, true), s_items, st.rp, st.ci,
       st.va, st.vecs, nodiv,
-      [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.slot, force); },
+      [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.first, force); },
       [&](int j) { return st.load(j); },
       [&](int j, V (&acc)[1], PrimalPre<V>& q) { st.finish(j, acc[0], q, p); },
-      [&](const WorkItem& it, bool run) {
-        if (run) flush_partials<3, sizeof(V) == 4>(p, s_red, st.part(), st.stride(), it.slot);
-        else dd_reset(p);
-        st.commit();
+      [&](double*& d, int& sd) {
+        d = st.part();
+        sd = st.stride();
       },
-      sh);
+      [&]() { st.commit(); }, p, tp, sh);
   st.commit();
 }
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
   __shared__ SpmvShared<V, 1> sh;
-  __shared__ DD s_red[4 * 4];
+  __shared__ TilePartials<4> tp;
   const double nodiv[1] = {0.0};
   DD p[4];
   dd_reset(p);
   DualStep<V> st;
   __shared__ WorkItem s_items[kItemWin];
   sgpr_ready(cfg.lps, cfg.step_a, cfg.counts, cfg.step_fixed, cfg.sgrid_a, cfg.schunk_a, force);
-  run_chunk_spmv<V, 1>(
+  run_chunk_spmv<V, 1, 4, DualStep<V>::kPlain>(
       cfg.step_a, step_chunks(cfg, false), s_items, st.rp, st.ci,
       st.va, st.vecs, nodiv,
-      [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.slot, force); },
+      [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.first, force); },
       [&](int i) { return st.load(i); },
       [&](int i, V (&acc)[1], DualPre<V>& q) { st.finish(i, acc[0], q, p); },
-      [&](const WorkItem& it, bool run) {
-        if (run) flush_partials<4, sizeof(V) == 4>(p, s_red, st.part(), st.stride(), it.slot);
-        else dd_reset(p);
-        st.commit();
+      [&](double*& d, int& sd) {
+        d = st.part();
+        sd = st.stride();
       },
-      sh);
+      [&]() { st.commit(); }, p, tp, sh);
   st.commit();
 }
 
@@ -1446,7 +1508,7 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   const WinPass* const ppass = tside ? L->wpass_t : L->wpass_a;
   const WinRange* const prange = tside ? L->wrange_t : L->wrange_a;
   Step st;
-  if (!st.begin(cfg, it.ctl, it.lp, it.slot, force)) return;
+  if (!st.begin(cfg, it.ctl, it.lp, it.slot == 0, force)) return;
   const LpDev* lp = st.lp;
   const gptr<const uint16_t> wc = uni(gp(pwc));
   const gptr<const uint16_t> wr = uni(gp(pwr));
@@ -1577,7 +1639,7 @@ __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* li
   const SegItem it = list[chi];
   if (it.lp < 0) return;
   Step st;
-  if (!st.begin(cfg, it.ctl, it.lp, it.slot, force)) return;
+  if (!st.begin(cfg, it.ctl, it.lp, it.slot == 0, force)) return;
   const LpDev* lp = st.lp;
   const gptr<const float> sp = uni(gp(static_cast<const float*>(tside ? lp->segp_t : lp->segp_a)));
   const gptr<const int32_t> srow = uni(gp(tside ? lp->srow_t : lp->srow_a));

@@ -154,8 +154,9 @@ struct SegItem {
 struct LpDev {
   int32_t m, n;
   int32_t ntiles_t, ntiles_a;  // tiles over A^T rows (n) and A rows (m); partial stride
-  int32_t nslot_t, nslot_a;    // partial slots of the evaluation kernels (workgroups touching the LP)
-  int32_t nslot_st, nslot_sa;  // partial slots of the step kernels (tile chunks, then windowed chunks)
+  int32_t nslot_t, nslot_a;    // partial slots of the evaluation kernels (one per tile)
+  int32_t nslot_st, nslot_sa;  // partial slots of the step kernels (one per step tile, then
+                               // one per windowed chunk and segment workgroup)
   const int32_t* rp_a;
   const int32_t* ci_a;
   const void* va_a;
@@ -235,9 +236,9 @@ struct WorkItem {
   int32_t rb, re; // rows [rb, re)
   int32_t s, e;   // nonzeros [s, e)
   int32_t lanes;  // see Tile
-  int32_t slot;   // partial slot of this item's workgroup for its LP
-  int32_t last;   // last item of its LP in this workgroup's chunk
-  int32_t pad;
+  int32_t slot;   // partial slot of this item: its tile's index in the LP's list
+  int32_t last;   // 1: the item stores its partial sums (every item does)
+  int32_t first;  // 1 on the LP's first item of the list
 };
 
 // Item counts and chunking of a set, in device memory. Chunk c of a side

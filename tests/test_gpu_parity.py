@@ -194,6 +194,36 @@ def test_batch_equals_solo(P):
         assert np.array_equal(x, xs) and np.array_equal(y, ys)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_results_independent_of_workgroup_count(P, prec):
+    # each tile stores its own partial sums, so packing several tiles of an
+    # LP into one workgroup (16 workgroups) gives the same numbers as one
+    # tile per workgroup; FP32 sums them in plain FP64 and relies on this
+    lp = config_lp("cfg1", scale=0.05, seed=2)
+    pr = P.OPDHG_FP32 if prec == "fp32" else P.OPDHG_FP64
+    _say(f"[workgroups] {prec} m={lp.m} n={lp.n} nnz={lp.nnz}")
+    a = P.opdhg_solve(lp, P.opdhg_default_params(precision=pr, max_iter=4000, lr=1e-2,
+                                                 tile_nnz=256, windows=P.OPDHG_WINDOWS_OFF))
+    b = P.opdhg_solve(lp, P.opdhg_default_params(precision=pr, max_iter=4000, lr=1e-2,
+                                                 tile_nnz=256, workgroups=16,
+                                                 windows=P.OPDHG_WINDOWS_OFF))
+    assert a[2].iterations == b[2].iterations and a[2].attempts == b[2].attempts
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_fp32_batch_packs_tiles_equal_solo(P):
+    # a batch whose chunks hold several tiles of one LP, in FP32
+    lps = [config_lp("cfg3", index=i, scale=0.2) for i in range(6)]
+    _say(f"[batch fp32] {len(lps)} LPs")
+    p = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=4000, lr=1e-2, tile_nnz=256,
+                               workgroups=32)
+    out = P.opdhg_solve_batch(lps, p)
+    for lp, (x, y, r) in zip(lps, out):
+        xs, ys, rs = P.opdhg_solve(lp, p)
+        assert r.status == rs.status and r.iterations == rs.iterations
+        assert np.array_equal(x, xs) and np.array_equal(y, ys)
+
+
 def test_fp32_mode_error_reported(P):
     lp = config_lp("cfg0", seed=3)
     _say("[fp32]")
