@@ -237,8 +237,10 @@ int opdhg_spectral_norm(const opdhg_lp* lp, const opdhg_params* p, double* norm_
  * (unscaled); res receives status and statistics. In FP64 the result does
  * not depend on the tiling, the windows or the preparation side (exact
  * sums); in FP32 the row sums of windowed chunks and of tiles are formed in
- * different orders, so the FP32 result moves with those choices by
- * rounding only, and is the same on every run. */
+ * different orders and the partial sums of each tile are plain FP64, so the
+ * FP32 result moves with the tile sizes and the windows by rounding only. In
+ * both precisions it does not depend on the workgroup count and is the
+ * same on every run. */
 int opdhg_solve(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
                 size_t workspace_bytes, void* hip_stream, double* x_out, double* y_out,
                 opdhg_result* res);
