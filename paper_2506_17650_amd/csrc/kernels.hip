@@ -651,6 +651,24 @@ __device__ __forceinline__ void flush_partials(DD (&p)[NV], DD* s_red, double* p
   dd_reset(p);
 }
 
+// Zeros in partial slot `slot` (thread 0): a slot that a workgroup's
+// reduction does not fill, so that every slot the decision adds is defined.
+template <int NV>
+__device__ __forceinline__ void zero_partials(double* part, int stride, int slot) {
+  if (threadIdx.x == 0) {
+    gptr<double> g = gp(part);
+#pragma unroll
+    for (int q = 0; q < 2 * NV; ++q) g[(size_t)q * stride + slot] = 0.0;
+  }
+}
+
+// Whether work item wi is the last of its LP in the chunk [i0, i0 + chunk)
+// (an LP's items are consecutive in the list).
+__device__ __forceinline__ bool last_of_lp(const WorkItem* work, int wi, int i0, int chunk,
+                                           int lp) {
+  return wi + 1 == i0 + chunk || work[wi + 1].lp != lp;
+}
+
 // ---------------------------------------------------------------------------
 // scalar decisions (one workgroup per LP)
 // ---------------------------------------------------------------------------
@@ -1849,9 +1867,13 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
   for (int wi = i0; wi < i0 + sc.chunk; ++wi) {
     const WorkItem it = cfg.work_t[wi];
     if (it.lp < 0) continue;
+    // the evaluation's double-double sums do not depend on their order, so
+    // the workgroup reduces an LP's part of the chunk once, into the slot of
+    // its last item here, and zeros the slots of its other items
+    const bool endc = last_of_lp(cfg.work_t, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
     if (!eval_guard(c)) {
-      if (it.last) dd_reset(p);
+      if (endc) dd_reset(p);
       continue;
     }
     const LpDev& lp = cfg.lps[it.lp];
@@ -1893,7 +1915,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
           }
         },
         sh);
-    if (it.last) flush_partials<2 * kEvT>(p, s_red, lp.part_t, lp.ntiles_t, it.slot);
+    if (endc) flush_partials<2 * kEvT>(p, s_red, lp.part_t, lp.ntiles_t, it.slot);
+    else zero_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, it.slot);
   }
 }
 
@@ -1910,9 +1933,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
   for (int wi = i0; wi < i0 + sc.chunk; ++wi) {
     const WorkItem it = cfg.work_a[wi];
     if (it.lp < 0) continue;
+    // as in k_eval_t: one reduction per LP and chunk, zeros in the other slots
+    const bool endc = last_of_lp(cfg.work_a, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
     if (!eval_guard(c)) {
-      if (it.last) dd_reset(p);
+      if (endc) dd_reset(p);
       continue;
     }
     const LpDev& lp = cfg.lps[it.lp];
@@ -1952,7 +1977,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
           }
         },
         sh);
-    if (it.last) flush_partials<2 * kEvA>(p, s_red, lp.part_a, lp.ntiles_a, it.slot);
+    if (endc) flush_partials<2 * kEvA>(p, s_red, lp.part_a, lp.ntiles_a, it.slot);
+    else zero_partials<2 * kEvA>(lp.part_a, lp.ntiles_a, it.slot);
   }
 }
 

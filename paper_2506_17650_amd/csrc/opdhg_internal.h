@@ -237,7 +237,7 @@ struct WorkItem {
   int32_t s, e;   // nonzeros [s, e)
   int32_t lanes;  // see Tile
   int32_t slot;   // partial slot of this item: its tile's index in the LP's list
-  int32_t last;   // 1: the item stores its partial sums (every item does)
+  int32_t last;   // 1 (every tile has a partial slot of its own; no kernel reads it)
   int32_t first;  // 1 on the LP's first item of the list
 };
 
