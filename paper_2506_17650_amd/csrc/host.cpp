@@ -1531,10 +1531,14 @@ void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& pre
   }
   const int64_t n = (int64_t)out.size();
   chunking(n, cap, grid, chunk);
-  // every tile stores its own partial sums, in the slot of its index within
-  // the LP's list: an LP's partials, and the order the decision adds them
-  // in, do not depend on how the set's items are chunked over workgroups,
-  // so a packed or served LP adds exactly what its solo solve adds
+  const int64_t C = *chunk;
+  // The step kernels store every tile's partial sums in the slot of its
+  // index within the LP's list: an LP's step partials, and the order the
+  // decision adds them in, do not depend on how the set's items are chunked
+  // over workgroups, so a packed or served LP adds exactly what its solo
+  // solve adds. The evaluation kernels, whose double-double sums do not
+  // depend on the order, store one partial per chunk touching the LP, in
+  // the slot of the chunk's ordinal among those chunks.
   for (size_t i = 0; i < lps.size(); ++i) {
     const int64_t s = range[i].first, e = range[i].second;
     for (int64_t q = s; q < e; ++q) {
@@ -1542,9 +1546,13 @@ void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& pre
       out[q].last = 1;
       out[q].first = q == s ? 1 : 0;
     }
-    const int32_t nslot = (int32_t)(e - s);
-    if (step) (tside ? lps[i].nslot_st : lps[i].nslot_sa) = nslot;
-    else (tside ? lps[i].nslot_t : lps[i].nslot_a) = nslot;
+    if (step) {
+      (tside ? lps[i].nslot_st : lps[i].nslot_sa) = (int32_t)(e - s);
+    } else {
+      (tside ? lps[i].nslot_t : lps[i].nslot_a) =
+          e > s ? (int32_t)((e - 1) / C - s / C + 1) : 0;
+      (tside ? lps[i].item0_t : lps[i].item0_a) = (int32_t)s;
+    }
   }
   const WorkItem pad{nullptr, -1, 0, 0, 0, 0, 0, 1, 0, 0, 0};
   out.resize((size_t)(*grid) * (*chunk), pad);
@@ -1568,8 +1576,8 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
     for (size_t i = 0; i < lps.size(); ++i) {
       if (preps[i]->win_t.chunks() || preps[i]->win_a.chunks())
         return fail(OPDHG_ERR_INVALID_ARGUMENT, "windowed chunks in a shared launch set");
-      lps[i].nslot_st = lps[i].nslot_t;
-      lps[i].nslot_sa = lps[i].nslot_a;
+      lps[i].nslot_st = (int32_t)preps[i]->tiles_t.size();
+      lps[i].nslot_sa = (int32_t)preps[i]->tiles_a.size();
     }
     cfg->sgrid_t = cfg->schunk_t = cfg->sgrid_a = cfg->schunk_a = 0;
     cfg->step_fixed = 0;

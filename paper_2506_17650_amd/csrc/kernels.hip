@@ -651,17 +651,6 @@ __device__ __forceinline__ void flush_partials(DD (&p)[NV], DD* s_red, double* p
   dd_reset(p);
 }
 
-// Zeros in partial slot `slot` (thread 0): a slot that a workgroup's
-// reduction does not fill, so that every slot the decision adds is defined.
-template <int NV>
-__device__ __forceinline__ void zero_partials(double* part, int stride, int slot) {
-  if (threadIdx.x == 0) {
-    gptr<double> g = gp(part);
-#pragma unroll
-    for (int q = 0; q < 2 * NV; ++q) g[(size_t)q * stride + slot] = 0.0;
-  }
-}
-
 // Whether work item wi is the last of its LP in the chunk [i0, i0 + chunk)
 // (an LP's items are consecutive in the list).
 __device__ __forceinline__ bool last_of_lp(const WorkItem* work, int wi, int i0, int chunk,
@@ -1711,7 +1700,7 @@ struct DecideLp {
   int32_t phi, schedule, normalize, eval_every, max_retries, flags;
 };
 
-__device__ __forceinline__ DecideLp decide_lp(const LpDev* rec, int step_fixed) {
+__device__ __forceinline__ DecideLp decide_lp(const LpDev* rec) {
   const gptr<const LpDev> L = gp(rec);
   DecideLp d;
   d.ctl = uni(L->ctl);
@@ -1720,10 +1709,9 @@ __device__ __forceinline__ DecideLp decide_lp(const LpDev* rec, int step_fixed) 
   d.part_a = uni((const double*)L->part_a);
   d.ntiles_t = uni(L->ntiles_t);
   d.ntiles_a = uni(L->ntiles_a);
-  // slots of the step kernels: their own lists in fixed sets, else the
-  // evaluation lists
-  d.ns_t = uni(step_fixed ? L->nslot_st : L->nslot_t);
-  d.ns_a = uni(step_fixed ? L->nslot_sa : L->nslot_a);
+  // slots of the step kernels (one per tile, then the windowed chunks)
+  d.ns_t = uni(L->nslot_st);
+  d.ns_a = uni(L->nslot_sa);
   d.lr = uni(L->s_lr);
   d.max_iter = uni(L->s_max_iter);
   d.phi = uni(L->s_phi);
@@ -1750,9 +1738,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     LaunchCfg cfg) {
   __shared__ DD s_red[4 * 7];
   __shared__ double s_ring[kBlock];
-  sgpr_ready(cfg.lps, cfg.counts, cfg.step_fixed);
+  sgpr_ready(cfg.lps, cfg.counts);
   int li = blockIdx.x;
-  DecideLp d = decide_lp(&cfg.lps[li], cfg.step_fixed);
+  DecideLp d = decide_lp(&cfg.lps[li]);
   const int nlps = uni(gp(cfg.counts)->nlps);
   while (li < nlps) {
     const gptr<const Ctl> g = gp(d.ctl);
@@ -1810,7 +1798,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     }
     __syncthreads();
     li += gridDim.x;
-    if (li < nlps) d = decide_lp(&cfg.lps[li], cfg.step_fixed);
+    if (li < nlps) d = decide_lp(&cfg.lps[li]);
   }
 }
 
@@ -1869,7 +1857,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
     if (it.lp < 0) continue;
     // the evaluation's double-double sums do not depend on their order, so
     // the workgroup reduces an LP's part of the chunk once, into the slot of
-    // its last item here, and zeros the slots of its other items
+    // the chunk's ordinal among those touching the LP
     const bool endc = last_of_lp(cfg.work_t, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
     if (!eval_guard(c)) {
@@ -1915,8 +1903,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
           }
         },
         sh);
-    if (endc) flush_partials<2 * kEvT>(p, s_red, lp.part_t, lp.ntiles_t, it.slot);
-    else zero_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, it.slot);
+    if (endc)
+      flush_partials<2 * kEvT>(p, s_red, lp.part_t, lp.ntiles_t, ch - lp.item0_t / sc.chunk);
   }
 }
 
@@ -1933,7 +1921,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
   for (int wi = i0; wi < i0 + sc.chunk; ++wi) {
     const WorkItem it = cfg.work_a[wi];
     if (it.lp < 0) continue;
-    // as in k_eval_t: one reduction per LP and chunk, zeros in the other slots
+    // as in k_eval_t: one reduction per LP and chunk
     const bool endc = last_of_lp(cfg.work_a, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
     if (!eval_guard(c)) {
@@ -1977,8 +1965,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
           }
         },
         sh);
-    if (endc) flush_partials<2 * kEvA>(p, s_red, lp.part_a, lp.ntiles_a, it.slot);
-    else zero_partials<2 * kEvA>(lp.part_a, lp.ntiles_a, it.slot);
+    if (endc)
+      flush_partials<2 * kEvA>(p, s_red, lp.part_a, lp.ntiles_a, ch - lp.item0_a / sc.chunk);
   }
 }
 

@@ -154,9 +154,11 @@ struct SegItem {
 struct LpDev {
   int32_t m, n;
   int32_t ntiles_t, ntiles_a;  // tiles over A^T rows (n) and A rows (m); partial stride
-  int32_t nslot_t, nslot_a;    // partial slots of the evaluation kernels (one per tile)
+  int32_t nslot_t, nslot_a;    // partial slots of the evaluation kernels (one per chunk of
+                               // the evaluation list touching the LP)
   int32_t nslot_st, nslot_sa;  // partial slots of the step kernels (one per step tile, then
                                // one per windowed chunk and segment workgroup)
+  int32_t item0_t, item0_a;    // position of the LP's first item in each evaluation list
   const int32_t* rp_a;
   const int32_t* ci_a;
   const void* va_a;

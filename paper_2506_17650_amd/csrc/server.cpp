@@ -344,9 +344,10 @@ int ServerImpl::write_shared() {
   int gt = 1, ct = 1, ga = 1, ca = 1;
   side_items(lps, preps, true, wg_cap, &gt, &ct, wt);
   side_items(lps, preps, false, wg_cap, &ga, &ca, wa);
-  for (LpDev& l : lps) {  // the step kernels write the same slots as the evaluation kernels
-    l.nslot_st = l.nslot_t;
-    l.nslot_sa = l.nslot_a;
+  // the step kernels run the evaluation lists, one partial slot per tile
+  for (size_t i = 0; i < lps.size(); ++i) {
+    lps[i].nslot_st = (int32_t)preps[i]->tiles_t.size();
+    lps[i].nslot_sa = (int32_t)preps[i]->tiles_a.size();
   }
   if ((int64_t)wt.size() > tab.cap_wt || (int64_t)wa.size() > tab.cap_wa ||
       (int64_t)lps.size() > tab.cap_lps)
