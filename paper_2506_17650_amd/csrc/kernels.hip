@@ -14,9 +14,10 @@
 // kTileCap is a tile of its own, reduced by the whole workgroup.
 //
 // The epilogues fuse the method's vector work into the sparse products and
-// accumulate FP64 partial sums per thread; at the end of an LP's part of a
-// chunk the workgroup reduces them and stores one partial per (workgroup,
-// LP). A one-workgroup-per-LP decision kernel sums an LP's partials in a
+// accumulate FP64 partial sums per thread. The step kernels store one
+// partial per tile (a DPP scan per wave, then the waves' totals added once
+// per window of work items); the evaluation kernels store one per chunk and
+// LP. A one-workgroup-per-LP decision kernel sums an LP's partials in a
 // fixed order and takes its scalar decision. Workgroups never wait for or
 // signal each other inside a launch; kernel boundaries carry every result
 // to the next step.
@@ -43,14 +44,17 @@
 //   k_apply   moves the iterate to the restart point, resets the sums and the
 //             anchor (preconditioners kept), or copies a returned average out
 //
-// Summation. Every FP64 reduction (and, in FP64 mode, every SpMV row sum)
-// is accumulated in double-double: each product is split exactly with an
-// FMA into p + e, p is added with an error-free two-sum and all round-off
-// is gathered in a second double, which is folded in once at the end. The
+// Summation. In FP64 mode every FP64 reduction and every SpMV row sum is
+// accumulated in double-double: each product is split exactly with an FMA
+// into p + e, p is added with an error-free two-sum and all round-off is
+// gathered in a second double, which is folded in once at the end. The
 // result is the correctly rounded sum except when the exact value lies
 // within about n * 2^-106 (relative) of a rounding boundary, so it does not
 // depend on the tiling, the lane count, the grid, or what else shares the
-// launch. In FP32 mode the SpMV products and row sums are FP32.
+// launch. In FP32 mode the SpMV products and row sums are FP32 and the step
+// kernels' partial sums plain FP64 in a fixed order, one partial per tile,
+// so their values depend on the tile sizes but not on the grid or on what
+// else shares the launch; the evaluation's sums stay double-double.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
