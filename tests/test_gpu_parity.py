@@ -194,6 +194,25 @@ def test_batch_equals_solo(P):
         assert np.array_equal(x, xs) and np.array_equal(y, ys)
 
 
+def test_long_run_past_the_factor_table(P):
+    # 11000 attempts with evaluations every 100 iterations: a launch sequence
+    # holds at most 64 attempts, so every attempt past the host table's 8192
+    # finds its own step-rule factor in the ring (a longer sequence would
+    # have read clamped entries and moved the steps by ~1e-4 relative)
+    lp = config_lp("cfg0", seed=1)
+    op = default_params(tol=1e-9, max_iter=12000, eval_every=100, lr=1e-2)
+    _say("[long run] cfg0 seed 1, eval_every 100, tol 1e-9")
+    ref = oracle.solve(lp, op)
+    assert ref.attempts > 8192 + 1000
+    x, y, r = P.opdhg_solve(lp, lib_params(P, op))
+    assert r.status == ref.status
+    assert r.iterations == ref.iterations and r.attempts == ref.attempts
+    assert r.restarts == ref.restarts
+    # past the table the device computes the powers (not bit for bit the
+    # host's), so the iterates agree to rounding, not exactly
+    assert rel(x, ref.x) <= 1e-9 and rel(y, ref.y) <= 1e-9
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_results_independent_of_workgroup_count(P, prec):
     # each tile stores its own partial sums, so packing several tiles of an
