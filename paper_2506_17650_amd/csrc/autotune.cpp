@@ -86,7 +86,8 @@ int time_candidate(std::vector<Prepared>& P, int prec, const Candidate& cand, ui
   if (rc) return rc;
   std::vector<LpDev> lpd(count);
   std::vector<const Prepared*> preps(count);
-  std::vector<uint8_t> img, staging;
+  SlotImage img;
+  std::vector<uint8_t> staging;
   size_t off = 0;
   for (int i = 0; i < count; ++i) {
     const SlotLayout L = slot_layout(P[i], prec);

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <memory>
 #include <string>
@@ -199,6 +200,30 @@ static void parallel_rows(const int64_t* ptr, int64_t rows, F&& f) {
   for (auto& th : pool) th.join();
 }
 
+// Runs the tasks on their own threads (the calling thread takes the first).
+static void run_tasks(std::vector<std::function<void()>> tasks) {
+  std::vector<std::thread> pool;
+  for (size_t t = 1; t < tasks.size(); ++t) pool.emplace_back(tasks[t]);
+  if (!tasks.empty()) tasks[0]();
+  for (auto& th : pool) th.join();
+}
+
+// Calls f(a, b) on consecutive pieces [a, b) of [0, n) on up to 16 host
+// threads, in pieces of at least `min_piece`.
+template <typename F>
+static void parallel_pieces(size_t n, size_t min_piece, F&& f) {
+  const size_t nth = std::max<size_t>(
+      1, std::min<size_t>({(size_t)std::min(host_threads(), 16), n / std::max<size_t>(min_piece, 1)}));
+  if (nth == 1) {
+    f((size_t)0, n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (size_t t = 1; t < nth; ++t) pool.emplace_back([&, t] { f(n * t / nth, n * (t + 1) / nth); });
+  f((size_t)0, n / nth);
+  for (auto& th : pool) th.join();
+}
+
 // Column-major index of a CSR matrix: for column j, entries
 // cstart[j] .. cstart[j+1]-1 of cpos hold the CSR positions of its
 // nonzeros in ascending row order, and crow their rows.
@@ -238,7 +263,8 @@ static void build_col_index(const opdhg_lp* lp, ColIndex& C, bool with_abs = tru
     cut[t] = std::max(cut[t - 1],
                       (int64_t)(std::lower_bound(lp->row_ptr, lp->row_ptr + m + 1, nnz * t / nth) -
                                 lp->row_ptr));
-  std::vector<std::vector<int32_t>> cnt(nth, std::vector<int32_t>(n, 0));
+  // each thread zeroes (and first touches) its own counts
+  std::vector<std::vector<int32_t>> cnt(nth);
   auto run = [&](auto&& f) {
     std::vector<std::thread> pool;
     for (int t = 1; t < nth; ++t) pool.emplace_back([&, t] { f(t); });
@@ -246,6 +272,7 @@ static void build_col_index(const opdhg_lp* lp, ColIndex& C, bool with_abs = tru
     for (auto& th : pool) th.join();
   };
   run([&](int t) {
+    cnt[t].assign(n, 0);
     for (int64_t k = lp->row_ptr[cut[t]]; k < lp->row_ptr[cut[t + 1]]; ++k) cnt[t][lp->col_idx[k]]++;
   });
   // column starts, then each thread's first position in every column
@@ -276,6 +303,28 @@ static void build_col_index(const opdhg_lp* lp, ColIndex& C, bool with_abs = tru
         if (with_abs) C.cabs[q] = std::fabs(lp->val[k]);
       }
   });
+}
+
+// Entries per column (= row lengths of A^T), counted by row ranges in
+// parallel and added per column.
+static void column_counts(const opdhg_lp* lp, std::vector<int64_t>& len) {
+  const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
+  int nth = (int)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)std::min(host_threads(), 16), m, nnz / 262144 + 1}));
+  nth = (int)std::max<int64_t>(1, std::min<int64_t>(nth, (int64_t)(1ll << 29) / (4 * (n + 1))));
+  std::vector<std::vector<int32_t>> cnt(nth);
+  std::vector<std::thread> pool;
+  auto count = [&](int t) {
+    cnt[t].assign(n, 0);
+    const int64_t k0 = lp->row_ptr[m * t / nth], k1 = lp->row_ptr[m * (t + 1) / nth];
+    for (int64_t k = k0; k < k1; ++k) cnt[t][lp->col_idx[k]]++;
+  };
+  for (int t = 1; t < nth; ++t) pool.emplace_back(count, t);
+  count(0);
+  for (auto& th : pool) th.join();
+  len.assign(n, 0);
+  for (int t = 0; t < nth; ++t)
+    for (int64_t j = 0; j < n; ++j) len[j] += cnt[t][j];
 }
 
 // Ruiz passes then one Pock-Chambolle pass (Section 2); see the oracle's
@@ -507,7 +556,7 @@ static int64_t window_chunk_rows(const opdhg_params* p, int64_t rows) {
   return std::min<int64_t>(kWinRows, std::max<int64_t>(1024, per));
 }
 
-static void plan_windows(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t>& ci,
                          int64_t ncols, int64_t lo, int64_t hi, int64_t long_end,
                          int64_t chunk_rows, int per_pass, WinPlan& W) {
   if (hi <= lo || ncols <= 0) return;
@@ -821,10 +870,25 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.n = lp->n;
   out.nnz = lp->nnz;
   const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
+  // device-side preparation: the rescaling and the scaled data on the GPU
+  out.dprep = p->step_rule != OPDHG_STEP_CONSTANT &&
+              (p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz));
+  // A full preparation needs the column index anyway: it is built first
+  // and gives the column counts; sizing alone counts the columns.
+  ColIndex C;
+  bool have_index = false;
+  if (!structure_only) {
+    build_col_index(lp, C, !out.dprep);
+    have_index = true;
+  }
   // row lengths of A and of A^T (= column counts), device order by class
   std::vector<int64_t> len_a(m), len_t(n, 0);
   for (int64_t i = 0; i < m; ++i) len_a[i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
-  for (int64_t k = 0; k < nnz; ++k) len_t[lp->col_idx[k]]++;
+  if (have_index) {
+    for (int64_t j = 0; j < n; ++j) len_t[j] = C.cstart[j + 1] - C.cstart[j];
+  } else {
+    column_counts(lp, len_t);
+  }
   class_order(len_a, out.perm_a, out.cend_a);
   class_order(len_t, out.perm_t, out.cend_t);
   out.rp_a.assign(m + 1, 0);
@@ -844,9 +908,6 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
     windows = windows_worth_planning(lp, out, inv, window_chunk_rows(p, m - out.cend_a[0]),
                                      per_pass);
   }
-  // device-side preparation: the rescaling and the scaled data on the GPU
-  out.dprep = p->step_rule != OPDHG_STEP_CONSTANT &&
-              (p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz));
   out.prep_ruiz = p->ruiz_iters;
   out.prep_l2 = p->l2_rescale != 0;
   out.prep_beta = p->pc_beta;
@@ -860,8 +921,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   for (int64_t i = 0; i < m; ++i) inv_a[out.perm_a[i]] = (int32_t)i;
   for (int64_t j = 0; j < n; ++j) inv_t[out.perm_t[j]] = (int32_t)j;
   std::vector<double> sval;
-  ColIndex C;
-  build_col_index(lp, C, !out.dprep);
+  if (!have_index) build_col_index(lp, C, !out.dprep);
   double spec = -1.0;
   if (!structure_only && !out.dprep) {
     rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, out.dr, out.dc);
@@ -874,8 +934,8 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   const double* vsrc = out.dprep ? lp->val : sval.data();
   // A in device order: row i' is original row perm_a[i'], columns relabelled
   out.ci_a.resize(nnz);
-  std::vector<double>& dst_a = out.dprep ? out.raw_a : out.va_a;
-  std::vector<double>& dst_t = out.dprep ? out.raw_t : out.va_t;
+  HostArray<double>& dst_a = out.dprep ? out.raw_a : out.va_a;
+  HostArray<double>& dst_t = out.dprep ? out.raw_t : out.va_t;
   if (vals) dst_a.resize(nnz);
   {
     std::vector<int64_t> dptr(m + 1);  // nonzero offsets in device order, for balancing
@@ -1181,14 +1241,14 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
   return d;
 }
 
-template <typename V>
-static void put_vec(std::vector<uint8_t>& img, size_t off, const std::vector<double>& v) {
+template <typename V, typename Vec>
+static void put_vec(SlotImage& img, size_t off, const Vec& v) {
   V* dst = reinterpret_cast<V*>(img.data() + off);
   for (size_t i = 0; i < v.size(); ++i) dst[i] = (V)v[i];
 }
 
 template <typename V>
-static void put_const(std::vector<uint8_t>& img, size_t off, size_t count, double value) {
+static void put_const(SlotImage& img, size_t off, size_t count, double value) {
   V* dst = reinterpret_cast<V*>(img.data() + off);
   for (size_t i = 0; i < count; ++i) dst[i] = (V)value;
 }
@@ -1209,8 +1269,11 @@ Ctl initial_ctl(const Prepared& P) {
 
 // Host image of a slot: every byte the device needs at the start.
 template <typename V>
-void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& img) {
-  img.assign(L.total, 0);
+void slot_image(const SlotLayout& L, const Prepared& P, SlotImage& img) {
+  // every byte starts at zero; the threads that zero the pages touch them
+  img.resize(L.total);
+  parallel_pieces(L.total, size_t(1) << 22,
+                  [&](size_t a, size_t b) { std::memset(img.data() + a, 0, b - a); });
   const Ctl c = initial_ctl(P);
   std::memcpy(img.data() + L.ctl, &c, sizeof(c));
   std::memcpy(img.data() + L.prm, &P.prm, sizeof(DevParams));
@@ -1218,12 +1281,21 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
   std::memcpy(img.data() + L.tiles_t, P.tiles_t.data(), sizeof(Tile) * P.tiles_t.size());
   std::memcpy(img.data() + L.pow_tab, P.pow_tab.data(), sizeof(double) * P.pow_tab.size());
   std::memcpy(img.data() + L.rp_a, P.rp_a.data(), 4 * P.rp_a.size());
-  std::memcpy(img.data() + L.ci_a, P.ci_a.data(), 4 * P.ci_a.size());
-  put_vec<V>(img, L.va_a, P.va_a);
   std::memcpy(img.data() + L.rp_t, P.rp_t.data(), 4 * P.rp_t.size());
-  std::memcpy(img.data() + L.ci_t, P.ci_t.data(), 4 * P.ci_t.size());
-  put_vec<V>(img, L.va_t, P.va_t);
-  auto put_win = [&](const WinPlan& W, const std::vector<double>& va, size_t oc, size_t orow,
+  // the nonzero-sized arrays, one thread each
+  run_tasks({[&] { std::memcpy(img.data() + L.ci_a, P.ci_a.data(), 4 * P.ci_a.size()); },
+             [&] { std::memcpy(img.data() + L.ci_t, P.ci_t.data(), 4 * P.ci_t.size()); },
+             [&] { put_vec<V>(img, L.va_a, P.va_a); },
+             [&] { put_vec<V>(img, L.va_t, P.va_t); },
+             [&] {
+               if (P.dprep && !P.raw_a.empty())
+                 std::memcpy(img.data() + L.raw_a, P.raw_a.data(), 8 * P.raw_a.size());
+             },
+             [&] {
+               if (P.dprep && !P.raw_t.empty())
+                 std::memcpy(img.data() + L.raw_t, P.raw_t.data(), 8 * P.raw_t.size());
+             }});
+  auto put_win = [&](const WinPlan& W, const auto& va, size_t oc, size_t orow,
                      size_t ov, size_t opass, size_t orange, size_t osrow, size_t osptr,
                      size_t osids, size_t owsrc) {
     if (!W.chunks()) return;
@@ -1249,11 +1321,9 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
   put_win(P.win_a, P.va_a, L.wcol_a, L.wrow_a, L.wval_a, L.wpass_a, L.wrange_a, L.srow_a,
           L.sptr_a, L.sids_a, L.wsrc_a);
   if (P.dprep) {
-    auto put64 = [&](size_t o, const std::vector<double>& v) {
+    auto put64 = [&](size_t o, const auto& v) {
       if (!v.empty()) std::memcpy(img.data() + o, v.data(), 8 * v.size());
     };
-    put64(L.raw_a, P.raw_a);
-    put64(L.raw_t, P.raw_t);
     put64(L.raw_b, P.raw_b);
     put64(L.raw_c, P.raw_c);
     put64(L.raw_l, P.raw_l);
@@ -1280,8 +1350,8 @@ void slot_image(const SlotLayout& L, const Prepared& P, std::vector<uint8_t>& im
   if (P.m) std::memcpy(img.data() + L.sense, P.sense.data(), P.sense.size());
 }
 
-template void slot_image<double>(const SlotLayout&, const Prepared&, std::vector<uint8_t>&);
-template void slot_image<float>(const SlotLayout&, const Prepared&, std::vector<uint8_t>&);
+template void slot_image<double>(const SlotLayout&, const Prepared&, SlotImage&);
+template void slot_image<float>(const SlotLayout&, const Prepared&, SlotImage&);
 
 // ---------------------------------------------------------------------------
 // a group of LPs launched together (one LP, a batch, or the server's mix)
@@ -1753,7 +1823,7 @@ static int device_prepare(uint8_t* base, const SlotLayout& L, Prepared& P, int p
 }
 
 int upload_slot(uint8_t* base, const SlotLayout& L, Prepared& P, int prec, hipStream_t stream,
-                std::vector<uint8_t>& img) {
+                SlotImage& img) {
   if (prec == OPDHG_FP32) slot_image<float>(L, P, img);
   else slot_image<double>(L, P, img);
   HIP_TRY(hipMemcpyAsync(base, img.data(), L.total, hipMemcpyHostToDevice, stream));
@@ -1978,7 +2048,7 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
   S.ws = static_cast<uint8_t*>(d_workspace);
   S.time_limit = p->time_limit_s;
   if ((rc = S.grp.init(hip_stream, p->precision))) return rc;
-  std::vector<uint8_t> img;
+  SlotImage img;
   if ((rc = upload_slot(S.ws, S.L, S.P, p->precision, S.grp.stream, img))) return rc;
   S.lpd = slot_pointers(S.ws, S.L, S.P);
   S.d_tables = S.ws + S.L.total;
@@ -2207,7 +2277,7 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, voi
   Group grp;
   if ((rc = grp.init(hip_stream, p->precision))) return rc;
   std::vector<LpDev> lpd(count);
-  std::vector<uint8_t> img;
+  SlotImage img;
   for (int i = 0; i < count; ++i) {
     if ((rc = upload_slot(ws + offs[i], L[i], P[i], p->precision, grp.stream, img))) {
       grp.release();

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -24,6 +26,34 @@ int host_threads();  // hardware threads of the host (at least 1)
   } while (0)
 int validate_lp(const opdhg_lp* lp);
 int validate_params(const opdhg_params* p);
+
+// Allocator whose default construction leaves trivially constructible
+// elements uninitialised: resize() then writes nothing, and the threads
+// that fill an array touch its pages themselves, in parallel, instead of
+// one thread zero-filling (and faulting in) every page first.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+// The nonzero-sized host arrays of a prepared LP.
+template <typename T>
+using HostArray = std::vector<T, NoInitAlloc<T>>;
+// Host image of an LP slot (filled in parallel, then copied to the device).
+using SlotImage = HostArray<uint8_t>;
 
 // Windowed chunks of one CSR side (see WinItem): rows and passes of each
 // chunk, the passes' entry ranges and LDS ranges, and the entries in
@@ -56,8 +86,9 @@ constexpr int64_t kDevicePrepNnz = int64_t(1) << 20;
 struct Prepared {
   int64_t m = 0, n = 0, nnz = 0;
   std::vector<int32_t> perm_a, perm_t;
-  std::vector<int32_t> rp_a, ci_a, rp_t, ci_t;  // device order
-  std::vector<double> va_a, va_t;               // device order
+  std::vector<int32_t> rp_a, rp_t;  // device order
+  HostArray<int32_t> ci_a, ci_t;    // device order
+  HostArray<double> va_a, va_t;     // device order
   std::vector<double> b, c, l, u, x0;           // device order
   std::vector<double> dr_dev, dc_dev;           // device order
   std::vector<double> dr, dc;                   // original order (unscaling)
@@ -76,7 +107,8 @@ struct Prepared {
   int prep_ruiz = 0;
   bool prep_l2 = false;
   double prep_beta = -1.0;
-  std::vector<double> raw_a, raw_t, raw_b, raw_c, raw_l, raw_u;
+  HostArray<double> raw_a, raw_t;
+  std::vector<double> raw_b, raw_c, raw_l, raw_u;
   // partial slots per side: evaluation tiles, or step tiles plus windowed chunks
   int64_t part_stride_t() const {
     return (int64_t)std::max(tiles_t.size(),
@@ -116,7 +148,7 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P);
 // preparation kernels and fills P.dr, P.dc, P.eta0 and P.omega0 from the
 // device (synchronizes the stream then).
 int upload_slot(uint8_t* base, const SlotLayout& L, Prepared& P, int prec, hipStream_t stream,
-                std::vector<uint8_t>& img);
+                SlotImage& img);
 // Launch tables of a set of LPs at dst: LP table, both work lists (chunked
 // over at most cap workgroups), counts and the Ctl board. With capacity > 0,
 // OPDHG_ERR_OVER_BUDGET when they need more bytes. With fixed_launch the

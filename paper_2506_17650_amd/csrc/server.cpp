@@ -309,7 +309,7 @@ void ServerImpl::prep_loop() {
 // point on the upload stream; records j.ready.
 int ServerImpl::admit(Job& j) {
   uint8_t* base = arena_base + table_bytes + j.off;
-  std::vector<uint8_t> img;
+  SlotImage img;
   int rc = upload_slot(base, j.L, j.P, cfg.precision, s_h2d, img);
   if (rc) return rc;
   j.lpd = slot_pointers(base, j.L, j.P);
