@@ -93,7 +93,10 @@ extern "C" {
 #define OPDHG_WINDOWS_ALWAYS 2 /* every windowable chunk, however few (small LPs, checks) */
 
 /* ---- where the rescaling and the scaled data are computed ---- */
-#define OPDHG_PREP_AUTO 0   /* on the device for LPs of 2^20 nonzeros or more, else on the host */
+#define OPDHG_PREP_AUTO 0   /* on the device for LPs of 2^20 nonzeros or more, else on the host;
+                               a packed set whose nonzeros reach 2^20 in total is prepared on
+                               the device when that matches the host bit for bit (pc_beta 1 or
+                               < 0, adaptive step) */
 #define OPDHG_PREP_HOST 1   /* host threads (FP64) */
 #define OPDHG_PREP_DEVICE 2 /* device kernels (FP64), same results; not with OPDHG_STEP_CONSTANT,
                                whose power iteration runs on the host */

@@ -2212,12 +2212,30 @@ int opdhg_solve(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
   return rc;
 }
 
-int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_params* p,
+// Parameters a packed set is prepared with. Under OPDHG_PREP_AUTO a set
+// whose nonzeros reach the device-preparation threshold in total is
+// prepared on the device, where that gives the host's numbers bit for bit
+// (Pock-Chambolle exponent 1 or none; not the constant step, whose power
+// iteration runs on the host), so every LP of the set still equals its
+// solo solve. The workspace sizing takes the same decision.
+static opdhg_params batch_params(int count, const opdhg_lp* lps, const opdhg_params* p) {
+  opdhg_params q = *p;
+  if (p->prep != OPDHG_PREP_AUTO || p->step_rule == OPDHG_STEP_CONSTANT) return q;
+  if (!(p->pc_beta == 1.0 || p->pc_beta < 0.0)) return q;
+  int64_t total = 0;
+  for (int i = 0; i < count; ++i) total += lps[i].nnz;
+  if (total >= kDevicePrepNnz) q.prep = OPDHG_PREP_DEVICE;
+  return q;
+}
+
+int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_params* p_in,
                                 size_t* bytes) {
   if (count < 0 || (count > 0 && !lps) || !bytes)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
-  int rc = validate_params(p);
+  int rc = validate_params(p_in);
   if (rc) return rc;
+  const opdhg_params pb = batch_params(count, lps, p_in);
+  const opdhg_params* p = &pb;
   size_t total = 0;
   ListSizes z;
   for (int i = 0; i < count; ++i) {
@@ -2231,13 +2249,15 @@ int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_para
   return OPDHG_OK;
 }
 
-int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, void* d_workspace,
-                      size_t workspace_bytes, void* hip_stream, double* const* x_out,
-                      double* const* y_out, opdhg_result* res) {
+int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p_in,
+                      void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                      double* const* x_out, double* const* y_out, opdhg_result* res) {
   if (count < 0 || (count > 0 && (!lps || !res)) || !d_workspace)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
-  int rc = validate_params(p);
+  int rc = validate_params(p_in);
   if (rc) return rc;
+  const opdhg_params pb = batch_params(count, lps, p_in);
+  const opdhg_params* p = &pb;
   if (count == 0) return OPDHG_OK;
   std::vector<Prepared> P(count);
   std::vector<SlotLayout> L(count);
@@ -2277,15 +2297,45 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p, voi
   Group grp;
   if ((rc = grp.init(hip_stream, p->precision))) return rc;
   std::vector<LpDev> lpd(count);
-  SlotImage img;
-  for (int i = 0; i < count; ++i) {
-    if ((rc = upload_slot(ws + offs[i], L[i], P[i], p->precision, grp.stream, img))) {
-      grp.release();
-      return rc;
+  {
+    // The slots are filled and copied by several threads, each with its own
+    // image and stream (default priority): one thread's copy overlaps the
+    // others' fills. Each waits for its copy before it reuses its image, and
+    // all have finished before the set's launches are enqueued.
+    std::atomic<int> nx{0};
+    std::vector<int> urc(count, OPDHG_OK);
+    auto up = [&] {
+      hipStream_t s = nullptr;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        for (int i = nx++; i < count; i = nx++) {
+          urc[i] = OPDHG_ERR_DEVICE;
+          msgs[i] = "hipStreamCreateWithFlags failed";
+        }
+        return;
+      }
+      SlotImage im;
+      for (int i = nx++; i < count; i = nx++) {
+        int r = upload_slot(ws + offs[i], L[i], P[i], p->precision, s, im);
+        if (!r && hipStreamSynchronize(s) != hipSuccess) r = fail(OPDHG_ERR_DEVICE, "upload failed");
+        if (r) {
+          urc[i] = r;
+          msgs[i] = opdhg_last_error();
+        }
+      }
+      (void)hipStreamDestroy(s);
+    };
+    const int nup = std::max(1, std::min({count, host_threads(), 8}));
+    std::vector<std::thread> ups;
+    for (int t = 1; t < nup; ++t) ups.emplace_back(up);
+    up();
+    for (auto& t : ups) t.join();
+    for (int i = 0; i < count; ++i) {
+      if (urc[i]) {
+        grp.release();
+        return fail(urc[i], "LP " + std::to_string(i) + ": " + msgs[i]);
+      }
+      lpd[i] = slot_pointers(ws + offs[i], L[i], P[i]);
     }
-    lpd[i] = slot_pointers(ws + offs[i], L[i], P[i]);
-    // the staging image is reused: wait for the copy before the next fill
-    (void)hipStreamSynchronize(grp.stream);
   }
   std::vector<uint8_t> staging;
   int64_t wt = 0, wa = 0;

@@ -230,6 +230,21 @@ def test_results_independent_of_workgroup_count(P, prec):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_batch_prepared_on_device_equals_solo(P):
+    # together these LPs reach the device-preparation threshold (2^20
+    # nonzeros), so the automatic choice prepares the set on the device;
+    # each alone is prepared on the host; the results agree bit for bit
+    lps = [config_lp("cfg3", index=i) for i in (4, 9, 14, 16)]
+    assert sum(lp.nnz for lp in lps) >= 1 << 20 and all(lp.nnz < 1 << 20 for lp in lps)
+    _say(f"[batch, device preparation] {[lp.nnz for lp in lps]}")
+    p = P.opdhg_default_params(max_iter=3000, lr=1e-2)
+    out = P.opdhg_solve_batch(lps, p)
+    for lp, (x, y, r) in zip(lps, out):
+        xs, ys, rs = P.opdhg_solve(lp, p)
+        assert r.status == rs.status and r.iterations == rs.iterations
+        assert np.array_equal(x, xs) and np.array_equal(y, ys)
+
+
 def test_fp32_batch_packs_tiles_equal_solo(P):
     # a batch whose chunks hold several tiles of one LP, in FP32
     lps = [config_lp("cfg3", index=i, scale=0.2) for i in range(6)]
