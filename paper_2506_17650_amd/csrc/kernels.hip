@@ -970,7 +970,7 @@ __device__ __forceinline__ void run_chunk_spmv(const WorkItem* __restrict__ work
       int32_t* dst = reinterpret_cast<int32_t*>(s_items);
       for (int q = threadIdx.x; q < cnt * kItemWords; q += kBlock) dst[q] = src[q];
     }
-    __syncthreads();
+    lds_barrier();
     for (int k = 0; k < cnt; ++k) {
       const WorkItem it = uniform_item(s_items[k]);
       bool on = false;
@@ -1497,6 +1497,42 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
 // of kWinBlock * kWinNpt entries owns its first run: the earlier pieces
 // were added at the previous step. After the passes each thread runs the
 // row epilogue for rows r0 + t, r0 + t + kWinBlock, ...
+// One step's entries of one thread of a windowed chunk: kWinNpt
+// consecutive entries from p0 (16-byte loads) and the rows of the entries
+// just before and just after them (-1 outside the thread's neighbours).
+struct WinBatch {
+  uint16_t cs[kWinNpt], rs[kWinNpt];
+  float vs[kWinNpt];
+  int prev_row, next_row;
+  bool active;
+};
+
+__device__ __forceinline__ void win_load(WinBatch& b, int p0, int pe1, int t,
+                                         gptr<const uint16_t> wc, gptr<const uint16_t> wr,
+                                         gptr<const float> wv) {
+  b.active = p0 < pe1;
+  b.prev_row = -1;
+  b.next_row = -1;
+  if (b.active) {
+    using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+    using f32x4 = float __attribute__((ext_vector_type(4)));
+    const u32x4 c0 = *reinterpret_cast<gptr<const u32x4>>(wc + p0);
+    const u32x4 c1 = *reinterpret_cast<gptr<const u32x4>>(wc + p0 + 8);
+    const u32x4 q0 = *reinterpret_cast<gptr<const u32x4>>(wr + p0);
+    const u32x4 q1 = *reinterpret_cast<gptr<const u32x4>>(wr + p0 + 8);
+    f32x4 v4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v4[u] = *reinterpret_cast<gptr<const f32x4>>(wv + p0 + 4 * u);
+    __builtin_memcpy(b.cs, &c0, 16);
+    __builtin_memcpy(b.cs + 8, &c1, 16);
+    __builtin_memcpy(b.rs, &q0, 16);
+    __builtin_memcpy(b.rs + 8, &q1, 16);
+    __builtin_memcpy(b.vs, v4, 64);
+    b.prev_row = t > 0 ? (int)wr[p0 - 1] : -1;
+    b.next_row = p0 + kWinNpt < pe1 ? (int)wr[p0 + kWinNpt] : -1;
+  }
+}
+
 template <typename Step, typename Pre, int NV>
 __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* list, int nwin,
                                           bool tside, int force) {
@@ -1529,94 +1565,104 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   const gptr<const float> vec = st.vecs[0];
   const int t = threadIdx.x;
   const int r0 = uni(it.r0), nrow = uni(it.r1 - it.r0), nseg = uni(it.nseg);
-  for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;
-  for (int ps = it.pass0; ps < it.pass0 + it.npass; ++ps) {
-    const int pe0 = passes[ps].e0, pe1 = passes[ps].e1;
-    const int pr0 = passes[ps].range0, prn = passes[ps].nrange;
-    __syncthreads();  // the previous pass is done with the window (and part is zeroed)
-    // ranges start on bucket boundaries (multiples of 4 entries, here and
-    // in the window), so they are copied 16 bytes at a time; only the
-    // vector's last bucket can end on a partial group
-    int off = 0;
-    for (int g = pr0; g < pr0 + prn; ++g) {
-      const int src = ranges[g].src, len = ranges[g].len;
-      using f32x4 = float __attribute__((ext_vector_type(4)));
-      const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src);
-      f32x4* w4 = reinterpret_cast<f32x4*>(win + off);
-      for (int q = t; q < (len >> 2); q += kWinBlock) w4[q] = v4[q];
-      for (int q = (len & ~3) + t; q < len; q += kWinBlock) win[off + q] = ldg(vec, (uint32_t)(src + q));
-      off += len;
-    }
-    __syncthreads();
-    for (int base = pe0; base < pe1; base += kWinBlock * kWinNpt) {
-      const int p0 = base + t * kWinNpt;
-      const bool active = p0 < pe1;
-      float s_run = 0.f, head_sum = 0.f;
-      int cur_row = -1;
-      bool in_head = false, spans = false, owner = false;
-      if (active) {
-        uint16_t cs[kWinNpt], rs[kWinNpt];
-        float vs[kWinNpt];
-        {
-          using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
-          using f32x4 = float __attribute__((ext_vector_type(4)));
-          const u32x4 c0 = *reinterpret_cast<gptr<const u32x4>>(wc + p0);
-          const u32x4 c1 = *reinterpret_cast<gptr<const u32x4>>(wc + p0 + 8);
-          const u32x4 q0 = *reinterpret_cast<gptr<const u32x4>>(wr + p0);
-          const u32x4 q1 = *reinterpret_cast<gptr<const u32x4>>(wr + p0 + 8);
-          f32x4 v4[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) v4[u] = *reinterpret_cast<gptr<const f32x4>>(wv + p0 + 4 * u);
-          __builtin_memcpy(cs, &c0, 16);
-          __builtin_memcpy(cs + 8, &c1, 16);
-          __builtin_memcpy(rs, &q0, 16);
-          __builtin_memcpy(rs + 8, &q1, 16);
-          __builtin_memcpy(vs, v4, 64);
-        }
-        const int prev_row = t > 0 ? (int)wr[p0 - 1] : -1;
-        const int next_row = p0 + kWinNpt < pe1 ? (int)wr[p0 + kWinNpt] : -1;
-        cur_row = rs[0];
-        in_head = (int)rs[0] == prev_row;
-#pragma unroll
-        for (int i = 0; i < kWinNpt; ++i) {
-          const int r = rs[i];
-          if (r != cur_row) {
-            if (in_head) {
-              head_sum = s_run;
-              in_head = false;
-            } else {
-              part[cur_row] += s_run;
-            }
-            s_run = 0.f;
-            cur_row = r;
-          }
-          s_run += vs[i] * win[cs[i]];
-        }
-        const bool tail_cont = cur_row == next_row;
-        if (in_head) {
-          head_sum = s_run;
-          spans = tail_cont;
-        } else if (tail_cont) {
-          owner = true;
-        } else {
-          part[cur_row] += s_run;
-        }
-      }
-      hs[t] = head_sum;
-      hspan[t] = spans ? 1 : 0;
-      __syncthreads();
-      if (owner) {
-        float tot = s_run;
-        for (int u = t + 1; u < kWinBlock; ++u) {
-          tot += hs[u];
-          if (!hspan[u]) break;
-        }
-        part[cur_row] += tot;
-      }
-      __syncthreads();
-    }
+  // the chunk's pass records in LDS: reading them waits on LDS only, not
+  // on the entry loads in flight (global loads complete in order)
+  __shared__ WinPass s_pass[kWinMaxPass];
+  const int npass = min(uni(it.npass), kWinMaxPass);  // plans hold at most kWinMaxPass
+  if (t < npass) {
+    const gptr<const WinPass> src = passes + (it.pass0 + t);
+    s_pass[t] = WinPass{src->e0, src->e1, src->range0, src->nrange};
   }
-  __syncthreads();
+  for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;
+  lds_barrier();
+  // The steps of all passes in order, kWinBlock * kWinNpt entries each: the
+  // entries of the next step are loaded into registers while the current
+  // one is processed, so their latency overlaps its work and its barriers
+  // (which wait on LDS only). Passes without entries are skipped. Pass
+  // indices here count from the chunk's first pass.
+  constexpr int kStep = kWinBlock * kWinNpt;
+  auto settle = [&](int& ps, int& base) {  // first step at or after (ps, base)
+    while (ps < npass && base >= s_pass[ps].e1) {
+      ++ps;
+      if (ps < npass) base = s_pass[ps].e0;
+    }
+  };
+  int cps = 0, cbase = s_pass[0].e0;
+  settle(cps, cbase);
+  WinBatch nb;
+  if (cps < npass) win_load(nb, cbase + t * kWinNpt, s_pass[cps].e1, t, wc, wr, wv);
+  int staged = -1;
+  while (cps < npass) {
+    if (cps != staged) {
+      const int pr0 = s_pass[cps].range0, prn = s_pass[cps].nrange;
+      lds_barrier();  // the previous pass is done with the window (and part is zeroed)
+      // ranges start on bucket boundaries (multiples of 4 entries, here and
+      // in the window), so they are copied 16 bytes at a time; only the
+      // vector's last bucket can end on a partial group
+      int off = 0;
+      for (int g = pr0; g < pr0 + prn; ++g) {
+        const int src = ranges[g].src, len = ranges[g].len;
+        using f32x4 = float __attribute__((ext_vector_type(4)));
+        const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src);
+        f32x4* w4 = reinterpret_cast<f32x4*>(win + off);
+        for (int q = t; q < (len >> 2); q += kWinBlock) w4[q] = v4[q];
+        for (int q = (len & ~3) + t; q < len; q += kWinBlock) win[off + q] = ldg(vec, (uint32_t)(src + q));
+        off += len;
+      }
+      lds_barrier();
+      staged = cps;
+    }
+    const WinBatch cb = nb;
+    int nps = cps, nbase = cbase + kStep;
+    settle(nps, nbase);
+    if (nps < npass) win_load(nb, nbase + t * kWinNpt, s_pass[nps].e1, t, wc, wr, wv);
+    float s_run = 0.f, head_sum = 0.f;
+    int cur_row = -1;
+    bool in_head = false, spans = false, owner = false;
+    if (cb.active) {
+      cur_row = cb.rs[0];
+      in_head = (int)cb.rs[0] == cb.prev_row;
+#pragma unroll
+      for (int i = 0; i < kWinNpt; ++i) {
+        const int r = cb.rs[i];
+        if (r != cur_row) {
+          if (in_head) {
+            head_sum = s_run;
+            in_head = false;
+          } else {
+            part[cur_row] += s_run;
+          }
+          s_run = 0.f;
+          cur_row = r;
+        }
+        s_run += cb.vs[i] * win[cb.cs[i]];
+      }
+      const bool tail_cont = cur_row == cb.next_row;
+      if (in_head) {
+        head_sum = s_run;
+        spans = tail_cont;
+      } else if (tail_cont) {
+        owner = true;
+      } else {
+        part[cur_row] += s_run;
+      }
+    }
+    hs[t] = head_sum;
+    hspan[t] = spans ? 1 : 0;
+    lds_barrier();
+    if (owner) {
+      float tot = s_run;
+      for (int u = t + 1; u < kWinBlock; ++u) {
+        tot += hs[u];
+        if (!hspan[u]) break;
+      }
+      part[cur_row] += tot;
+    }
+    lds_barrier();
+    cps = nps;
+    cbase = nbase;
+  }
+  lds_barrier();
   DD p[NV];
   dd_reset(p);
   // the segments' partial row sums go out for the finishing kernel
