@@ -1795,6 +1795,8 @@ static int device_prepare(uint8_t* base, const SlotLayout& L, Prepared& P, int p
   c.ctl = d.ctl;
   c.m = (int32_t)P.m;
   c.n = (int32_t)P.n;
+  c.nlong_a = (int32_t)P.cend_a[0];
+  c.nlong_t = (int32_t)P.cend_t[0];
   int rc = 0;
   // Ruiz passes, the L2 pass, the Pock-Chambolle pass (Section 2), as on the host
   for (int it = 0; it < P.prep_ruiz && !rc; ++it)

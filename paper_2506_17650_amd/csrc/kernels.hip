@@ -2192,12 +2192,36 @@ __global__ __launch_bounds__(kBlock) void k_prep_stats(PrepCfg a, int tside, int
   const int32_t* ci = tside ? a.ci_t : a.ci_a;
   const double* raw = tside ? a.raw_t : a.raw_a;
   double* out = tside ? a.sc : a.sr;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < rows; r += gridDim.x * kBlock) {
+  auto scaled = [&](int r, int k) {
+    const double v = fabs(raw[k]);
+    return tside ? (v * a.dr[ci[k]]) * a.dc[r] : (v * a.dr[r]) * a.dc[ci[k]];
+  };
+  int r_first = 0;
+  if (kind == 0) {
+    // maxima do not depend on the order: a wave per long row (the first
+    // rows in device order), then a thread per row for the rest
+    const int nlong = tside ? a.nlong_t : a.nlong_a;
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * (kBlock / 64);
+    for (int r = (blockIdx.x * kBlock + threadIdx.x) >> 6; r < nlong; r += nw) {
+      double mx = 0.0;
+      for (int k = rp[r] + lane; k < rp[r + 1]; k += 64) {
+        const double x = scaled(r, k);
+        mx = mx < x ? x : mx;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(mx, off, 64);
+        mx = mx < o ? o : mx;
+      }
+      if (lane == 0) out[r] = mx;
+    }
+    r_first = nlong;
+  }
+  for (int r = r_first + blockIdx.x * kBlock + threadIdx.x; r < rows; r += gridDim.x * kBlock) {
     double mx = 0.0;
     SeqDD acc;
     for (int k = rp[r]; k < rp[r + 1]; ++k) {
-      const double v = fabs(raw[k]);
-      const double x = tside ? (v * a.dr[ci[k]]) * a.dc[r] : (v * a.dr[r]) * a.dc[ci[k]];
+      const double x = scaled(r, k);
       if (kind == 0) mx = mx < x ? x : mx;
       else if (kind == 1) acc.add(e == 1.0 ? x : pow(x, e));
       else acc.add(x * x);
@@ -2228,16 +2252,27 @@ __global__ __launch_bounds__(kBlock) void k_prep_values(PrepCfg a) {
   __syncthreads();
   unsigned long long mx = 0ull;
   V* va = static_cast<V*>(a.va_a);
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.m; r += gridDim.x * kBlock)
-    for (int k = a.rp_a[r]; k < a.rp_a[r + 1]; ++k) {
-      const double v = (a.raw_a[k] * a.dr[r]) * a.dc[a.ci_a[k]];
-      va[k] = (V)v;
-      const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
-      mx = mx < bits ? bits : mx;
-    }
   V* vt = static_cast<V*>(a.va_t);
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.n; r += gridDim.x * kBlock)
-    for (int k = a.rp_t[r]; k < a.rp_t[r + 1]; ++k) vt[k] = (V)((a.raw_t[k] * a.dr[a.ci_t[k]]) * a.dc[r]);
+  auto put_a = [&](int r, int k) {
+    const double v = (a.raw_a[k] * a.dr[r]) * a.dc[a.ci_a[k]];
+    va[k] = (V)v;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
+    mx = mx < bits ? bits : mx;
+  };
+  auto put_t = [&](int r, int k) { vt[k] = (V)((a.raw_t[k] * a.dr[a.ci_t[k]]) * a.dc[r]); };
+  // a wave per long row (the first rows in device order), a thread per row
+  // for the rest; every entry is computed on its own
+  const int lane = threadIdx.x & 63;
+  const int w0 = (blockIdx.x * kBlock + threadIdx.x) >> 6, nw = gridDim.x * (kBlock / 64);
+  const int t0 = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
+  for (int r = w0; r < a.nlong_a; r += nw)
+    for (int k = a.rp_a[r] + lane; k < a.rp_a[r + 1]; k += 64) put_a(r, k);
+  for (int r = a.nlong_a + t0; r < a.m; r += nt)
+    for (int k = a.rp_a[r]; k < a.rp_a[r + 1]; ++k) put_a(r, k);
+  for (int r = w0; r < a.nlong_t; r += nw)
+    for (int k = a.rp_t[r] + lane; k < a.rp_t[r + 1]; k += 64) put_t(r, k);
+  for (int r = a.nlong_t + t0; r < a.n; r += nt)
+    for (int k = a.rp_t[r]; k < a.rp_t[r + 1]; ++k) put_t(r, k);
   atomicMax(&s_max, mx);
   __syncthreads();
   if (threadIdx.x == 0)

@@ -344,6 +344,7 @@ struct PrepCfg {
   int64_t went_t, went_a;
   Ctl* ctl;
   int32_t m, n;
+  int32_t nlong_a, nlong_t;  // rows of more than 256 nonzeros (the first in device order)
 };
 // kind 0: maxima of |a~|, 1: sums of |a~|^e, 2: L2 norms
 int prep_stats(const PrepCfg& c, void* stream, bool tside, int kind, double e);
