@@ -302,8 +302,9 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 
 // The same for two partial arrays at once (NA quantities over ca slots of
 // pa, then NB over cb slots of pb): one pass, so the loads of both arrays
-// are in flight together.
-template <int NA, int NB, typename Mid>
+// are in flight together. PLAIN: the partials are plain FP64 sums (their
+// low words are zero), read and added as plain doubles.
+template <int NA, int NB, bool PLAIN, typename Mid>
 __device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, const double* pb,
                                               int sb, int cb, double (&out)[NA + NB],
                                               DD* s_red, Mid&& mid) {
@@ -331,14 +332,14 @@ __device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, 
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
           h[k][q] = ga[(size_t)(2 * q) * sa + ta];
-          l[k][q] = ga[(size_t)(2 * q + 1) * sa + ta];
+          if constexpr (!PLAIN) l[k][q] = ga[(size_t)(2 * q + 1) * sa + ta];
         }
       }
       if (r0 + k * kBlock < cb) {
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
           h[k][NA + q] = gb[(size_t)(2 * q) * sb + tb];
-          l[k][NA + q] = gb[(size_t)(2 * q + 1) * sb + tb];
+          if constexpr (!PLAIN) l[k][NA + q] = gb[(size_t)(2 * q + 1) * sb + tb];
         }
       }
     }
@@ -351,14 +352,15 @@ __device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, 
 #pragma unroll
         for (int q = 0; q < NA + NB; ++q) {
           const bool ok = q < NA ? oka : okb;
-          v[q] = dd_merge(v[q], DD{ok ? h[k][q] : 0.0, ok ? l[k][q] : 0.0});
+          if constexpr (PLAIN) v[q].hi += ok ? h[k][q] : 0.0;
+          else v[q] = dd_merge(v[q], DD{ok ? h[k][q] : 0.0, ok ? l[k][q] : 0.0});
         }
       }
     }
   };
   round(0, true);
   for (int r0 = kBlock * B; r0 < count; r0 += kBlock * B) round(r0, false);
-  block_sum<NA + NB>(v, s_red);
+  block_sum<NA + NB, kBlock / 64, PLAIN>(v, s_red);
 #pragma unroll
   for (int q = 0; q < NA + NB; ++q) out[q] = dd_value(v[q]);
 }
@@ -1782,8 +1784,10 @@ __device__ __forceinline__ DecideLp decide_lp(const LpDev* rec) {
 // ring through LDS once the attempt count is known.
 // One wave per SIMD: a single workgroup per LP runs this kernel, so the
 // registers go to keeping the partial loads in flight at once.
+// PLAIN: the step kernels' partials are plain FP64 sums (FP32 runs).
 static_assert(2 * kPowRing <= kBlock && (kPowRing & (kPowRing - 1)) == 0,
               "one thread per ring entry, a power of two");
+template <bool PLAIN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_decide(
     LaunchCfg cfg) {
   __shared__ DD s_red[4 * 7];
@@ -1811,7 +1815,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     double sv[7];
     // the control block is read after the first round of partial loads is
     // issued, in the same round trip
-    sum_partials2<3, 4>(d.part_t, d.ntiles_t, d.ns_t, d.part_a, d.ntiles_a, d.ns_a, sv, s_red,
+    sum_partials2<3, 4, PLAIN>(d.part_t, d.ntiles_t, d.ns_t, d.part_a, d.ntiles_a, d.ns_a, sv, s_red,
                         [&]() {
                           // every load first, then the moves to scalar
                           // registers (each of which waits for its load)
@@ -2418,7 +2422,8 @@ int Kernels<V>::dual_seg(const LaunchCfg& c, void* stream, int force) {
 }
 template <typename V>
 int Kernels<V>::decide(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_decide, c.launch_lp, c);
+  constexpr bool kPlainSums = sizeof(V) == 4;  // FP32 step kernels store plain sums
+  OPDHG_LAUNCH(k_decide<kPlainSums>, c.launch_lp, c);
 }
 template <typename V>
 int Kernels<V>::learn_flush(const LaunchCfg& c, void* stream) {
