@@ -310,8 +310,10 @@ __device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, 
                                               DD* s_red, Mid&& mid) {
   constexpr int B = 8;  // 2048 slots per round: one round of loads for most launch sets
   DD v[NA + NB];
+  if constexpr (!PLAIN) {  // plain sums are set to zero by the first round
 #pragma unroll
-  for (int q = 0; q < NA + NB; ++q) v[q] = dd_zero();
+    for (int q = 0; q < NA + NB; ++q) v[q] = dd_zero();
+  }
   const gptr<const double> ga = gp(pa), gb = gp(pb);
   const int count = ca > cb ? ca : cb;
   // Every thread runs the first round; mid() runs between its loads and
@@ -343,7 +345,18 @@ __device__ __forceinline__ void sum_partials2(const double* pa, int sa, int ca, 
         }
       }
     }
-    if (first) mid();
+    if (first) {
+      mid();
+      // plain sums start from a zero the compiler cannot see: with a known
+      // zero it moves the first additions into the load branches above,
+      // each then waiting there for its loads
+      if constexpr (PLAIN) {
+        double z = 0.0;
+        asm volatile("" : "+v"(z));
+#pragma unroll
+        for (int q = 0; q < NA + NB; ++q) v[q] = DD{z, 0.0};
+      }
+    }
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       if (r0 + k * kBlock < count) {
@@ -687,6 +700,12 @@ struct StepIn {
 // c is the LP's control block (written here), in its fields as read before
 // the decision; s holds the attempt's sums
 // |x'-x|^2, |g|^2, |G^p|^2, |y'-y|^2, (y'-y).(A x'-A x), |b-Ax|^2, |G^d|^2.
+// k mod d for k >= 0 and d >= 1: a 32-bit division while k fits in 32 bits
+// (the 64-bit one is a long instruction sequence on the decision's serial path)
+__device__ __forceinline__ int64_t mod_count(int64_t k, int32_t d) {
+  return k <= (int64_t)INT32_MAX ? (int64_t)((uint32_t)k % (uint32_t)d) : k % d;
+}
+
 __device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
   const double dx2 = s[0], g2 = s[1], gp2 = s[2];
   const double dy2 = s[3], inter = fabs(s[4]), r2 = s[5], gd2 = s[6];
@@ -710,7 +729,7 @@ __device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
   // a pending learner update was applied by this attempt's kernels
   c.learn_pending = 0;
   if (constant || eta <= eta_bar) {
-    const bool learn = in.lr > 0.0 && (in.k % in.phi) == 0;
+    const bool learn = in.lr > 0.0 && mod_count(in.k, in.phi) == 0;
     const int64_t k1 = in.k + 1;
     c.eta_acc = eta;
     c.w = in.w + eta;
@@ -734,8 +753,8 @@ __device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
         if (!nd) c.hd_norm = in.hd_norm + gd2 / (sd * sd);
       }
     }
-    c.learn_now = (in.lr > 0.0 && (k1 % in.phi) == 0) ? 1 : 0;
-    if (k1 % in.eval_every == 0 || k1 >= in.max_iter) c.need_eval = 1;
+    c.learn_now = (in.lr > 0.0 && mod_count(k1, in.phi) == 0) ? 1 : 0;
+    if (mod_count(k1, in.eval_every) == 0 || k1 >= in.max_iter) c.need_eval = 1;
   } else {
     const int64_t r1 = in.retries + 1;
     c.eta = eta_next;
