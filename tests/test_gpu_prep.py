@@ -107,3 +107,27 @@ def test_device_prep_batch_and_server(P):
         got = [srv.wait(srv.submit(lp, dev), 120.0) for lp in lps]
     for g, ref in zip(got, solo):
         _same(g, ref)
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_device_prep_long_rows_and_columns(P, prec_name):
+    """Rows and columns of more than 256 nonzeros take a wave each in the
+    maximum passes and the value pass (lengths that are not multiples of 64
+    included); maxima and values are exact, so the result stays bitwise the
+    host's."""
+    from lpgen import random_lp
+    prec = P.OPDHG_FP64 if prec_name == "fp64" else P.OPDHG_FP32
+    lps = {
+        "long rows": random_lp(11, 200, 3000, degree=("uniform", 20, 40)),
+        "long columns": random_lp(12, 2000, 600, degree=("powerlaw", 1.1, 3, 1500)),
+    }
+    for name, lp in lps.items():
+        rl = np.diff(lp.csr().indptr)
+        cl = np.bincount(lp.csr().indices, minlength=lp.n)
+        _say(f"[prep long] {name} {prec_name}: rows > 256: {int((rl > 256).sum())}, "
+             f"columns > 256: {int((cl > 256).sum())}")
+        assert (rl > 256).any() or (cl > 256).any()
+        kw = dict(precision=prec, max_iter=1500, lr=1e-3, tol=1e-4)
+        host = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw))
+        dev = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw))
+        _same(dev, host)
