@@ -1751,6 +1751,16 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
     cfg->launch_ta = std::max(cfg->grid_t, cfg->grid_a);
     cfg->launch_lp = (int)std::max<size_t>(1, std::min<size_t>(lps.size(), kGridCap));
   }
+  // one LP in a set that never changes: the decision record as uploaded
+  cfg->solo = !fixed_launch && lps.size() == 1 ? 1 : 0;
+  cfg->solo_rec = DecideRec{};
+  if (cfg->solo) {
+    const LpDev& d = lps[0];
+    cfg->solo_rec = DecideRec{d.ctl, d.pow_ring, d.part_t, d.part_a,
+                              d.ntiles_t, d.ntiles_a, d.nslot_st, d.nslot_sa,
+                              d.s_lr, d.s_max_iter, d.s_phi, d.s_schedule,
+                              d.s_normalize, d.s_eval_every, d.s_max_retries, d.s_flags};
+  }
   *nwt = n_t;
   *nwa = n_a;
   return OPDHG_OK;

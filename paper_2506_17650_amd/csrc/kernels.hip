@@ -1760,16 +1760,7 @@ __global__ __launch_bounds__(kWinBlock) void k_dual_win(LaunchCfg cfg, int force
 
 // What the step decision needs from an LP's record, in scalar registers:
 // pointers, partial-slot counts and the copies of the parameters it reads.
-struct DecideLp {
-  Ctl* ctl;
-  const double* ring;
-  const double* part_t;
-  const double* part_a;
-  int ntiles_t, ntiles_a, ns_t, ns_a;
-  double lr;
-  int64_t max_iter;
-  int32_t phi, schedule, normalize, eval_every, max_retries, flags;
-};
+using DecideLp = DecideRec;
 
 __device__ __forceinline__ DecideLp decide_lp(const LpDev* rec) {
   const gptr<const LpDev> L = gp(rec);
@@ -1811,10 +1802,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     LaunchCfg cfg) {
   __shared__ DD s_red[4 * 7];
   __shared__ double s_ring[kBlock];
-  sgpr_ready(cfg.lps, cfg.counts);
+  // all launch arguments in one round, the solo record's fields included
+  const DecideRec& sr = cfg.solo_rec;
+  sgpr_ready(cfg.lps, cfg.counts, cfg.solo, sr.ctl, sr.ring, sr.part_t, sr.part_a, sr.ntiles_t,
+             sr.ntiles_a, sr.ns_t, sr.ns_a, sr.lr, sr.max_iter, sr.phi, sr.schedule,
+             sr.normalize, sr.eval_every, sr.max_retries, sr.flags);
   int li = blockIdx.x;
-  DecideLp d = decide_lp(&cfg.lps[li]);
-  const int nlps = uni(gp(cfg.counts)->nlps);
+  DecideLp d;
+  int nlps;
+  if (cfg.solo) {  // the record came with the launch arguments
+    d = cfg.solo_rec;
+    nlps = 1;
+  } else {
+    d = decide_lp(&cfg.lps[li]);
+    nlps = uni(gp(cfg.counts)->nlps);
+  }
   while (li < nlps) {
     const gptr<const Ctl> g = gp(d.ctl);
     StepIn in;

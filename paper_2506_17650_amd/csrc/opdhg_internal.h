@@ -255,6 +255,20 @@ struct Counts {
 };
 
 // Host-side launch wrappers (kernels.hip). V is float or double.
+// What the step decision reads from an LP's record: its control block,
+// factor ring, the step kernels' partials (stride and slot count per side)
+// and the parameters it uses.
+struct DecideRec {
+  Ctl* ctl;
+  const double* ring;
+  const double* part_t;
+  const double* part_a;
+  int32_t ntiles_t, ntiles_a, ns_t, ns_a;
+  double lr;
+  int64_t max_iter;
+  int32_t phi, schedule, normalize, eval_every, max_retries, flags;
+};
+
 struct LaunchCfg {
   const LpDev* lps;        // device pointers
   const WorkItem* work_t;  // A^T-side tiles of all LPs
@@ -283,6 +297,10 @@ struct LaunchCfg {
   const SegItem* seg_t;  // segmented long rows, finished after the windowed chunks
   const SegItem* seg_a;
   int nseg_t, nseg_a;
+  // a fixed set of one LP: its decision record comes with the launch
+  // arguments, so the decision kernel skips reading the LP table
+  int solo, pad2_;
+  DecideRec solo_rec;
 };
 
 template <typename V>
