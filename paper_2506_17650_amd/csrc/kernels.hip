@@ -1762,6 +1762,14 @@ __global__ __launch_bounds__(kWinBlock) void k_dual_win(LaunchCfg cfg, int force
 // pointers, partial-slot counts and the copies of the parameters it reads.
 using DecideLp = DecideRec;
 
+// Lane l's value of v (l uniform over the wave).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 __device__ __forceinline__ DecideLp decide_lp(const LpDev* rec) {
   const gptr<const LpDev> L = gp(rec);
   DecideLp d;
@@ -1789,19 +1797,18 @@ __device__ __forceinline__ DecideLp decide_lp(const LpDev* rec) {
 // just ran. The loads come in three rounds: the launch arguments; the LP
 // count beside the first LP record (the launch grid never exceeds the LP
 // table, and nothing the record points to is read before the count shows
-// that the LP exists); then the factor ring, the partial sums and the
-// control block together. The factor of the attempt is picked from the
-// ring through LDS once the attempt count is known.
+// that the LP exists; a fixed set of one LP has its record in the launch
+// arguments and skips this round); then the factor ring, the partial sums
+// and the control block together. The factor of the attempt is read from
+// the lane that holds it once the attempt count is known.
 // One wave per SIMD: a single workgroup per LP runs this kernel, so the
 // registers go to keeping the partial loads in flight at once.
 // PLAIN: the step kernels' partials are plain FP64 sums (FP32 runs).
-static_assert(2 * kPowRing <= kBlock && (kPowRing & (kPowRing - 1)) == 0,
-              "one thread per ring entry, a power of two");
+static_assert(kPowRing == 64, "lane l of a wave holds ring entries l and kPowRing + l");
 template <bool PLAIN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_decide(
     LaunchCfg cfg) {
   __shared__ DD s_red[4 * 7];
-  __shared__ double s_ring[kBlock];
   // all launch arguments in one round, the solo record's fields included
   const DecideRec& sr = cfg.solo_rec;
   sgpr_ready(cfg.lps, cfg.counts, cfg.solo, sr.ctl, sr.ring, sr.part_t, sr.part_a, sr.ntiles_t,
@@ -1828,9 +1835,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     in.eval_every = d.eval_every;
     in.max_retries = d.max_retries;
     in.flags = d.flags;
-    // every thread reads one ring entry (the two halves twice over); the
-    // value stays in a vector register until after the partial sums
-    const double rv = gp(d.ring)[threadIdx.x & (2 * kPowRing - 1)];
+    // lane l of every wave reads ring entries l and kPowRing + l; they stay
+    // in vector registers until after the partial sums
+    const int lane = (int)threadIdx.x & 63;
+    const double rv_red = gp(d.ring)[lane];
+    const double rv_gro = gp(d.ring)[kPowRing + lane];
     int status = 0, need = 0;
     int64_t k_limit = 0, ring_base = 0;
     double sv[7];
@@ -1860,20 +1869,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                           in.retries = uni(re0);
                           in.cur = uni(cu0);
                         });
-    s_ring[threadIdx.x] = rv;
-    __syncthreads();  // s_ring is written
-    if (status == kRunning && need == 0 && in.k < k_limit && threadIdx.x == 0) {
-      // the attempt decided here is j = attempts + 1, in the ring at
-      // j - ring_base - 1 (the ring covers every attempt of the sequence)
-      int64_t r = in.attempts - ring_base;
-      r = r < 0 ? 0 : (r >= kPowRing ? kPowRing - 1 : r);
-      in.f_red = s_ring[r];
-      in.f_gro = s_ring[kPowRing + r];
+    // the attempt decided here is j = attempts + 1, in the ring at
+    // j - ring_base - 1 (the ring covers every attempt of the sequence);
+    // the index is uniform, so its lane's values are read across the wave
+    int64_t r = in.attempts - ring_base;
+    r = r < 0 ? 0 : (r >= kPowRing ? kPowRing - 1 : r);
+    in.f_red = lane_value(rv_red, (int)r);
+    in.f_gro = lane_value(rv_gro, (int)r);
+    if (status == kRunning && need == 0 && in.k < k_limit && threadIdx.x == 0)
       decide_step(*d.ctl, in, sv);
-    }
-    __syncthreads();
     li += gridDim.x;
-    if (li < nlps) d = decide_lp(&cfg.lps[li]);
+    if (li < nlps) {
+      __syncthreads();  // s_red is reused by the next LP
+      d = decide_lp(&cfg.lps[li]);
+    }
   }
 }
 
