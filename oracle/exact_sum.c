@@ -6,9 +6,12 @@
  * Precision Floating-Point Arithmetic and Fast Robust Geometric
  * Predicates", 1997: each new term is added to every partial with an
  * error-free two-sum, and the nonzero round-off parts are kept). The final
- * value is the FP64 number nearest the exact sum: the partials are added
- * from the largest down until a nonzero round-off appears, and a
- * half-way case is settled by the sign of the next partial.
+ * rounding is not in Shewchuk's paper: it is the step of R. Hettinger's
+ * "msum" recipe (Python Cookbook recipe 393090, the method behind Python's
+ * math.fsum), restated here. The partials are added from the largest down
+ * until a nonzero round-off appears, and a result that lies exactly half
+ * way between two FP64 numbers is moved to the correct one by the sign of
+ * the next partial, which gives the FP64 number nearest the exact sum.
  *
  * A dot product adds the exact products: fma(a, b, -p) recovers the
  * round-off e of p = a * b exactly, so p + e == a * b.

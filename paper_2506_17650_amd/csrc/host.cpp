@@ -327,9 +327,13 @@ static void column_counts(const opdhg_lp* lp, std::vector<int64_t>& len) {
     for (int64_t j = 0; j < n; ++j) len[j] += cnt[t][j];
 }
 
-// Ruiz passes then one Pock-Chambolle pass (Section 2); see the oracle's
-// rescaling for the definition. Maxima do not depend on order and the sums
-// are double-double, so the threads change no bit of the result.
+// Ruiz passes then one Pock-Chambolle pass (Section 2): per pass, each row
+// and column statistic of |A~| (the infinity norm for Ruiz; for
+// Pock-Chambolle the sum of |a|^beta over a row and of |a|^(2 - beta) over
+// a column; the L2 norm for the optional L2 pass) divides
+// its diagonal by its square root, a zero statistic read as 1. Maxima do not
+// depend on order and the sums are double-double, so the threads change no
+// bit of the result.
 static void rescale_with(const opdhg_lp* lp, const ColIndex& C, int ruiz_iters, bool l2,
                          double beta, std::vector<double>& sval, std::vector<double>& dr,
                          std::vector<double>& dc) {

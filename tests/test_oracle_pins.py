@@ -208,6 +208,35 @@ def test_kkt_hand_example():
     assert math.isclose(p2["dobj"], -7.5, rel_tol=1e-14)
 
 
+def test_weighted_kkt_hand_example():
+    """KKT error in the primal-weight norm of the restart test (Section 3.2
+    adopts PDLP's restart scheme), on the two hand-worked points of
+    test_kkt_hand_example; every expected value is worked out by hand.
+
+    Point 1: |r_p|^2 = 0.26, |r_d|^2 = 0, gap = 0.8 - 0.5 = 0.3.
+      w = 2:   4 * 0.26 + 0 / 4 + 0.09 = 1.13
+      w = 1/2: 0.26 / 4 + 0 * 4 + 0.09 = 0.155
+    Point 2: |r_p|^2 = 0, |r_d|^2 = 2.25, p = 1 + 2 - 1 = 2, d = -7.5, gap = 9.5.
+      w = 2:   0 + 2.25 / 4 + 90.25 = 90.8125
+      w = 1/2: 0 + 2.25 * 4 + 90.25 = 99.25
+    Swapping w and 1/w exchanges the two rows of each point, dropping the
+    square on w gives 0.52 + 0.09 at point 1, and dropping the gap removes
+    the 0.09 / 90.25: each such slip fails one of the four values.
+    """
+    lp = _lp_from_dense([[1, 1], [1, -1]], [1, 0], [1, 0], [1, 2], [0, 0], [5, np.inf])
+    s = rescale(lp, ruiz_iters=0, pc_beta=-1)
+    x, y = np.array([0.2, 0.3]), np.array([0.5, 0.25])
+    p1 = oracle.kkt_parts(s, x, y, s.A @ x, s.AT @ y)
+    lp2 = _lp_from_dense([[1, 1, 1]], [-3], [1], [1, 2, -1], [0, -np.inf, -np.inf],
+                         [np.inf, np.inf, 4])
+    s2 = rescale(lp2, ruiz_iters=0, pc_beta=-1)
+    x2, y2 = np.array([1.0, 1.0, 1.0]), np.array([0.5])
+    p2 = oracle.kkt_parts(s2, x2, y2, s2.A @ x2, s2.AT @ y2)
+    cases = [(p1, 2.0, 1.13), (p1, 0.5, 0.155), (p2, 2.0, 90.8125), (p2, 0.5, 99.25)]
+    for parts, om, sq in cases:
+        assert math.isclose(oracle.weighted_kkt(parts, om), math.sqrt(sq), rel_tol=1e-15), (om, sq)
+
+
 def test_weak_duality_sign():
     # For primal-feasible x and y with zero dual residual, gap >= 0.
     lp = config_lp("cfg0", seed=2)
