@@ -40,6 +40,7 @@ from typing import Iterable, Optional, Union
 
 import numpy as np
 
+from .crmath import cr_exp, cr_log, cr_pow
 from .exact import exact_dot, exact_norm, exact_spmv
 from .kkt import kkt_parts, rel_kkt, weighted_kkt
 from .params import (Params, RESTART_NONE, SCHEDULE_ADAGRAD_DIAG, SCHEDULE_ADAGRAD_NORM,
@@ -225,13 +226,13 @@ def step_size_rule(eta: float, omega: float, dx2: float, dy2: float, interaction
     interaction is zero; eta_next = min((1 - (j+1)^-0.3) eta_bar,
     (1 + (j+1)^-0.6) eta) where j counts every attempt so far, this one
     included (j >= 1, so the first factor is never 0); accepted iff
-    eta <= eta_bar.
+    eta <= eta_bar. The powers are correctly rounded (module crmath).
     """
     movement = 0.5 * omega * dx2 + 0.5 * dy2 / omega
     eta_bar = movement / interaction if interaction > 0.0 else math.inf
     kk = float(attempts + 1)
-    first = (1.0 - kk ** (-p.step_reduction)) * eta_bar
-    second = (1.0 + kk ** (-p.step_growth)) * eta
+    first = (1.0 - cr_pow(kk, -p.step_reduction)) * eta_bar
+    second = (1.0 + cr_pow(kk, -p.step_growth)) * eta
     return eta_bar, min(first, second), eta <= eta_bar
 
 
@@ -360,8 +361,9 @@ def _evaluate(slp: ScaledLP, st: State, p: Params):
             dxn = exact_norm(xc - st.x_anchor)
             dyn = exact_norm(yc - st.y_anchor)
             if dxn > 1e-10 and dyn > 1e-10:
+                # primal-weight smoothing; exp and log correctly rounded (crmath)
                 th = p.pw_smoothing
-                st.omega = math.exp(th * math.log(dyn / dxn) + (1.0 - th) * math.log(st.omega))
+                st.omega = cr_exp(th * cr_log(dyn / dxn) + (1.0 - th) * cr_log(st.omega))
             st.x, st.y, st.Ax = xc.copy(), yc.copy(), Axc.copy()
             st.x_anchor, st.y_anchor = xc.copy(), yc.copy()
             st.anchor_parts = pc
