@@ -65,7 +65,8 @@ extern "C" {
 #define OPDHG_STATUS_OPTIMAL 0          /* relative KKT error <= tol */
 #define OPDHG_STATUS_ITERATION_LIMIT 1  /* max_iter accepted iterations */
 #define OPDHG_STATUS_TIME_LIMIT 2       /* time_limit_s of wall time */
-#define OPDHG_STATUS_NUMERICAL_ERROR 3  /* non-finite reductions or too many step rejections */
+#define OPDHG_STATUS_NUMERICAL_ERROR 3  /* non-finite reductions or too many step rejections;
+                                           the current iterate is returned with its KKT error */
 #define OPDHG_STATUS_RUNNING 4          /* sessions only: paused before finishing */
 
 /* ---- precision ---- */
@@ -278,6 +279,8 @@ typedef struct opdhg_tuning {
   int32_t candidates;     /* candidates timed */
   double attempts_per_s;  /* measured for the chosen tiling */
   double default_attempts_per_s; /* measured for the automatic tiling */
+  double executed_fraction; /* chosen tiling: attempts run / step-attempt slots launched (the
+                               slots an LP leaves idle while an evaluation is due) */
 } opdhg_tuning;
 
 /* Workspace bytes opdhg_autotune needs for these LPs (the largest

@@ -122,6 +122,7 @@ class opdhg_tuning(ctypes.Structure):
     _fields_ = [
         ("tile_nnz", c_i32), ("lanes", c_i32), ("workgroups", c_i32), ("candidates", c_i32),
         ("attempts_per_s", c_dbl), ("default_attempts_per_s", c_dbl),
+        ("executed_fraction", c_dbl),
     ]
 
 

@@ -27,6 +27,8 @@ struct Candidate {
   int tile_nnz, lanes, workgroups;
 };
 
+constexpr int kSlots = 64;  // step-attempt slots per timed launch sequence
+
 // tile sizes x workgroup counts; lanes per row are picked per tile
 constexpr Candidate kCandidates[] = {
     {256, 0, 256},  {256, 0, 512},  {256, 0, 1024},  {256, 0, 2048},
@@ -78,7 +80,7 @@ size_t max_bytes(std::vector<Prepared>& P, int prec) {
 // Attempts per second of the set under one candidate: upload, capture,
 // one warm-up replay, then `replays` timed replays.
 int time_candidate(std::vector<Prepared>& P, int prec, const Candidate& cand, uint8_t* ws,
-                   void* stream, int replays, double* rate) {
+                   void* stream, int replays, double* rate, double* executed) {
   const int count = (int)P.size();
   for (Prepared& q : P) retile(q, cand.tile_nnz, cand.lanes);
   Group grp;
@@ -103,7 +105,7 @@ int time_candidate(std::vector<Prepared>& P, int prec, const Candidate& cand, ui
                             &nwt, &nwa);
   if (!rc && grp.launch_init()) rc = fail(OPDHG_ERR_DEVICE, device_error_string());
   if (!rc && hipStreamSynchronize(grp.stream) != hipSuccess) rc = fail(OPDHG_ERR_DEVICE, "init");
-  if (!rc) rc = grp.capture(64);
+  if (!rc) rc = grp.capture(kSlots);
   std::vector<Ctl> b0(count), b1(count);
   auto board = [&](std::vector<Ctl>& out) {
     if (hipMemcpyAsync(out.data(), grp.cfg.board, sizeof(Ctl) * count, hipMemcpyDeviceToHost,
@@ -123,6 +125,8 @@ int time_candidate(std::vector<Prepared>& P, int prec, const Candidate& cand, ui
   int64_t att = 0;
   for (int i = 0; i < count; ++i) att += b1[i].attempts - b0[i].attempts;
   *rate = dt > 0.0 ? (double)att / dt : 0.0;
+  // the LPs never stop here, so every slot of every replay could hold an attempt
+  *executed = (double)att / ((double)replays * kSlots * count);
   return OPDHG_OK;
 }
 
@@ -161,9 +165,9 @@ int opdhg_autotune(int count, const opdhg_lp* lps, const opdhg_params* p, void* 
   std::memset(out, 0, sizeof(*out));
   double best = -1.0;
   for (const Candidate& c : kCandidates) {
-    double rate = 0.0;
+    double rate = 0.0, executed = 0.0;
     if ((rc = time_candidate(P, p->precision, c, static_cast<uint8_t*>(d_workspace), hip_stream,
-                             replays, &rate)))
+                             replays, &rate, &executed)))
       return rc;
     if (c.tile_nnz == kTileCap && c.lanes == 0 && c.workgroups == kGridCap)
       out->default_attempts_per_s = rate;
@@ -173,6 +177,7 @@ int opdhg_autotune(int count, const opdhg_lp* lps, const opdhg_params* p, void* 
       out->lanes = c.lanes;
       out->workgroups = c.workgroups;
       out->attempts_per_s = rate;
+      out->executed_fraction = executed;
     }
     ++out->candidates;
   }

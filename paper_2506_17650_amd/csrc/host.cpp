@@ -10,11 +10,14 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
 
+#include "crmath.h"
 #include "opdhg.h"
 #include "opdhg_host.h"
 #include "opdhg_internal.h"
@@ -869,6 +872,28 @@ void step_tiles(Prepared& P, int64_t cap, int lanes) {
 // preparation: everything the device needs, computed on the host in FP64
 // ---------------------------------------------------------------------------
 
+// The step rule's factors (j+1)^-reduction and (j+1)^-growth for
+// j = 1..kPowTab, correctly rounded (crmath.h; about 25 ms per table), kept
+// per pair of exponents for the life of the process: every LP with the same
+// exponents shares one table.
+static std::vector<double> step_factor_table(double reduction, double growth) {
+  static std::mutex mu;
+  static std::map<std::pair<uint64_t, uint64_t>, std::vector<double>> cache;
+  uint64_t kr = 0, kg = 0;
+  std::memcpy(&kr, &reduction, 8);
+  std::memcpy(&kg, &growth, 8);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kr, kg});
+  if (it != cache.end()) return it->second;
+  std::vector<double> t(2 * kPowTab);
+  for (int j = 1; j <= kPowTab; ++j) {
+    t[j - 1] = crm::cr_pow((double)(j + 1), -reduction);
+    t[kPowTab + j - 1] = crm::cr_pow((double)(j + 1), -growth);
+  }
+  if (cache.size() >= 64) cache.clear();  // a bound on what odd exponent sweeps keep
+  return cache.emplace(std::make_pair(kr, kg), std::move(t)).first->second;
+}
+
 int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool structure_only) {
   out.m = lp->m;
   out.n = lp->n;
@@ -1064,11 +1089,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   d.step_reduction = p->step_reduction;
   d.b_norm = dd_norm(lp->b, m);
   d.c_norm = dd_norm(lp->c, n);
-  out.pow_tab.resize(2 * kPowTab);
-  for (int j = 1; j <= kPowTab; ++j) {
-    out.pow_tab[j - 1] = std::pow((double)(j + 1), -p->step_reduction);
-    out.pow_tab[kPowTab + j - 1] = std::pow((double)(j + 1), -p->step_growth);
-  }
+  out.pow_tab = step_factor_table(p->step_reduction, p->step_growth);
   d.c0 = lp->obj_offset;
   d.max_iter = p->max_iter;
   d.phi = p->phi;
@@ -1361,31 +1382,44 @@ template void slot_image<float>(const SlotLayout&, const Prepared&, SlotImage&);
 // a group of LPs launched together (one LP, a batch, or the server's mix)
 // ---------------------------------------------------------------------------
 
+int Group::enqueue(hipStream_t s, int attempts) {
+  int rc = 0;
+  auto K = [&](auto tag) {
+    using V = decltype(tag);
+    auto evaluation = [&](int mid) {
+      rc |= Kernels<V>::eval_t(cfg, s, mid);
+      rc |= Kernels<V>::eval_a(cfg, s, mid);
+      rc |= Kernels<V>::eval_decide(cfg, s, mid);
+      rc |= Kernels<V>::apply(cfg, s);
+    };
+    evaluation(0);
+    for (int a = 0; a < attempts; ++a) {
+      if (a > 0 && a % kMidEvalEvery == 0) evaluation(1);
+      rc |= launch_side(true, 0, s);
+      rc |= launch_side(false, 0, s);
+      rc |= Kernels<V>::decide(cfg, s);
+    }
+    rc |= launch_board(cfg, s);
+  };
+  if (prec == OPDHG_FP32) K(float{});
+  else K(double{});
+  return rc;
+}
+
 int Group::capture(int attempts_per_replay) {
   // the step-rule factor ring covers kPowRing attempts per launch sequence
   attempts_per_replay = std::min(std::max(1, attempts_per_replay), kPowRing);
+  if (direct) {
+    seq_attempts = attempts_per_replay;
+    return OPDHG_OK;
+  }
   if (exec) {
     (void)hipGraphExecDestroy(exec);
     exec = nullptr;
   }
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-  int rc = 0;
-  auto K = [&](auto tag) {
-    using V = decltype(tag);
-    rc |= Kernels<V>::eval_t(cfg, cap_stream);
-    rc |= Kernels<V>::eval_a(cfg, cap_stream);
-    rc |= Kernels<V>::eval_decide(cfg, cap_stream);
-    rc |= Kernels<V>::apply(cfg, cap_stream);
-    for (int a = 0; a < attempts_per_replay; ++a) {
-      rc |= launch_side(true, 0, cap_stream);
-      rc |= launch_side(false, 0, cap_stream);
-      rc |= Kernels<V>::decide(cfg, cap_stream);
-    }
-    rc |= launch_board(cfg, cap_stream);
-  };
-  if (prec == OPDHG_FP32) K(float{});
-  else K(double{});
+  const int rc = enqueue(cap_stream, attempts_per_replay);
   hipError_t e = hipStreamEndCapture(cap_stream, &graph);
   if (rc != 0) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -1427,7 +1461,8 @@ int Group::launch_side(bool primal, int force, hipStream_t s) {
     return primal ? Kernels<double>::primal_seg(cfg, q, force)
                   : Kernels<double>::dual_seg(cfg, q, force);
   };
-  if (!(tiles && wins)) return (tiles ? tile(s) : 0) | (wins ? win(s) | seg(s) : 0);
+  if (!(tiles && wins) || !side_stream)
+    return (tiles ? tile(s) : 0) | (wins ? win(s) | seg(s) : 0);
   if (hipEventRecord(ev_fork, s) != hipSuccess ||
       hipStreamWaitEvent(side_stream, ev_fork, 0) != hipSuccess)
     return -1;
@@ -1439,9 +1474,16 @@ int Group::launch_side(bool primal, int force, hipStream_t s) {
   return rc;
 }
 
-int Group::init(void* stream_, int prec_) {
+int Group::init(void* stream_, int prec_, bool direct_) {
   stream = (hipStream_t)stream_;
   prec = prec_;
+  direct = direct_;
+  if (direct) {
+    // outside any capture: the windowed kernels' LDS attribute (no allocation)
+    if (prec == OPDHG_FP32 && window_kernels_ready())
+      return fail(OPDHG_ERR_DEVICE, device_error_string());
+    return OPDHG_OK;
+  }
   HIP_TRY(hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
@@ -1480,6 +1522,11 @@ int Group::launch_primal_forced() { return launch_side(true, 1, stream); }
 int Group::launch_dual_forced() { return launch_side(false, 1, stream); }
 
 int Group::replay() {
+  if (direct) {
+    if (enqueue(stream, seq_attempts))
+      return fail(OPDHG_ERR_DEVICE, std::string("kernel launch failed: ") + device_error_string());
+    return OPDHG_OK;
+  }
   HIP_TRY(hipGraphLaunch(exec, stream));
   return OPDHG_OK;
 }
@@ -1495,7 +1542,9 @@ struct SessionImpl {
   LpDev lpd;
   Group grp;
   uint8_t* d_tables = nullptr;  // LpDev, WorkItems and BatchDev live after the slot
-  Ctl* h_ctl = nullptr;         // pinned readback
+  Ctl* h_ctl = nullptr;         // pinned readback (direct mode: h_ctl_local)
+  Ctl h_ctl_local{};
+  bool direct = false;          // no graph, streams, events or pinned memory of its own
   double time_limit = 600.0;
   double elapsed = 0.0;
   int replays = 0;
@@ -1872,7 +1921,9 @@ void fill_result(const Ctl& c, double seconds, opdhg_result* r) {
   r->iterations = c.k;
   r->attempts = c.attempts;
   r->restarts = c.restarts;
-  const bool evaluated = c.status == kOptimal || c.status == kIterLimit || c.status == kTimeLimit;
+  // every final status comes from an evaluation (a numerical failure's too,
+  // on the current iterate); a paused session has none yet
+  const bool evaluated = c.status != kRunning;
   const double nan = std::numeric_limits<double>::quiet_NaN();
   r->primal_obj = evaluated ? c.out_pobj : nan;
   r->dual_obj = evaluated ? c.out_dobj : nan;
@@ -2044,8 +2095,17 @@ int opdhg_spectral_norm(const opdhg_lp* lp, const opdhg_params* p, double* norm_
   return OPDHG_OK;
 }
 
-int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
-                         size_t workspace_bytes, void* hip_stream, opdhg_session** out) {
+}  // extern "C"
+
+namespace opdhg {
+
+// Session set-up shared by opdhg_session_create and the allocation-free
+// solve: validation, preparation, upload, launch tables, the first
+// products and the launch sequence. need_out (if set) receives the device
+// bytes the LP needs, also when the workspace is too small.
+int session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                   size_t workspace_bytes, void* hip_stream, bool direct, opdhg_session** out,
+                   size_t* need_out) {
   if (!out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
   int rc = validate_lp(lp);
@@ -2058,12 +2118,14 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
   S.L = slot_layout(S.P, p->precision);
   const size_t need =
       S.L.total + tables_bytes({&S.P}, grid_cap(p));
+  if (need_out) *need_out = need;
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL,
                 "workspace needs " + std::to_string(need) + " bytes");
   S.ws = static_cast<uint8_t*>(d_workspace);
   S.time_limit = p->time_limit_s;
-  if ((rc = S.grp.init(hip_stream, p->precision))) return rc;
+  S.direct = direct;
+  if ((rc = S.grp.init(hip_stream, p->precision, direct))) return rc;
   SlotImage img;
   if ((rc = upload_slot(S.ws, S.L, S.P, p->precision, S.grp.stream, img))) return rc;
   S.lpd = slot_pointers(S.ws, S.L, S.P);
@@ -2076,9 +2138,19 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
   if ((rc = S.grp.launch_init())) return fail(OPDHG_ERR_DEVICE, device_error_string());
   HIP_TRY(hipStreamSynchronize(S.grp.stream));
   if ((rc = S.grp.capture(std::max(1, p->eval_every)))) return rc;
-  HIP_TRY(hipHostMalloc((void**)&S.h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  if (direct) S.h_ctl = &S.h_ctl_local;
+  else HIP_TRY(hipHostMalloc((void**)&S.h_ctl, sizeof(Ctl), hipHostMallocDefault));
   *out = s.release();
   return OPDHG_OK;
+}
+
+}  // namespace opdhg
+
+extern "C" {
+
+int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                         size_t workspace_bytes, void* hip_stream, opdhg_session** out) {
+  return session_create(lp, p, d_workspace, workspace_bytes, hip_stream, false, out, nullptr);
 }
 
 int opdhg_session_run(opdhg_session* s, int64_t k_target) {
@@ -2212,7 +2284,7 @@ void opdhg_session_destroy(opdhg_session* s) {
   SessionImpl& S = s->impl;
   if (S.grp.stream || S.grp.cap_stream) (void)hipStreamSynchronize(S.grp.stream);
   S.grp.release();
-  if (S.h_ctl) (void)hipHostFree(S.h_ctl);
+  if (S.h_ctl && !S.direct) (void)hipHostFree(S.h_ctl);
   delete s;
 }
 

@@ -34,7 +34,8 @@
 // (the learner of Algorithm 1) after an accepted update iteration is applied by
 // the next attempt's k_primal (T) and k_dual (Sigma) to the rows they
 // visit, before those rows use the preconditioner.
-// Every eval_every accepted iterations:
+// Every eval_every accepted iterations (at the start of a launch sequence,
+// or at one of the guarded evaluation steps inside it):
 //   k_eval_t  CSR(A^T) SpMV of y and of the average of y: reduced costs,
 //             dual residuals, bound terms of the dual objective, c^T x, and
 //             distances to the restart anchor, for current and average
@@ -63,6 +64,7 @@
 #include <mutex>
 #include <type_traits>
 
+#include "crmath.h"
 #include "opdhg_internal.h"
 
 namespace opdhg {
@@ -650,8 +652,12 @@ __device__ __forceinline__ V clampv(V v, V lo, V hi) {
   return t > hi ? hi : t;
 }
 
-__device__ __forceinline__ bool eval_guard(const Ctl* c) {
-  return c->status == kRunning && c->need_eval != 0;
+// Whether an LP takes part in an evaluation step. The evaluation that opens
+// a launch sequence serves every due LP; the guarded evaluations inside the
+// sequence (mid) serve only LPs below their pause point, so a session paused
+// at k_limit keeps the evaluation due there for its next run.
+__device__ __forceinline__ bool eval_guard(const Ctl* c, int mid) {
+  return c->status == kRunning && c->need_eval != 0 && (!mid || c->k < c->k_limit);
 }
 
 template <int NV>
@@ -710,8 +716,14 @@ __device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
   const double dx2 = s[0], g2 = s[1], gp2 = s[2];
   const double dy2 = s[3], inter = fabs(s[4]), r2 = s[5], gd2 = s[6];
   c.attempts = in.attempts + 1;
+  // a numerical failure is reported by the next evaluation, on the current
+  // iterate (the failed attempt is not committed)
+  auto fail = [&]() {
+    c.fail_pending = 1;
+    c.need_eval = 1;
+  };
   if (!(isfinite(dx2) && isfinite(dy2) && isfinite(inter))) {
-    c.status = kNumError;
+    fail();
     return;
   }
   const double eta = in.eta, om = in.omega;
@@ -759,7 +771,7 @@ __device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
     const int64_t r1 = in.retries + 1;
     c.eta = eta_next;
     c.retries = r1;
-    if (r1 > in.max_retries || !(eta_next > 0.0 && isfinite(eta_next))) c.status = kNumError;
+    if (r1 > in.max_retries || !(eta_next > 0.0 && isfinite(eta_next))) fail();
   }
 }
 
@@ -795,6 +807,19 @@ __device__ void decide_eval(Ctl* c, const DevParams* p, const double* st, const 
     rel[z][2] = fabs(pobj[z] - dobj[z]) / (1.0 + fabs(pobj[z]) + fabs(dobj[z]));
     const double m01 = rel[z][0] > rel[z][1] ? rel[z][0] : rel[z][1];
     rel[z][3] = m01 > rel[z][2] ? m01 : rel[z][2];
+  }
+  if (c->fail_pending) {
+    // numerical failure: the current iterate with its KKT, as it stands
+    c->out_pobj = pobj[0];
+    c->out_dobj = dobj[0];
+    c->out_relp = rel[0][0];
+    c->out_reld = rel[0][1];
+    c->out_relg = rel[0][2];
+    c->out_rel = rel[0][3];
+    c->which = 0;
+    c->need_eval = 0;
+    c->status = kNumError;
+    return;
   }
   if (!c->anchor_set) {
     c->anc_rp2 = rp2[0];
@@ -832,8 +857,9 @@ __device__ void decide_eval(Ctl* c, const DevParams* p, const double* st, const 
       const double dxn = sqrt(dxa2[z]);
       const double dyn = sqrt(dya2[z]);
       if (dxn > 1e-10 && dyn > 1e-10) {
+        // correctly rounded exp and log: the same bits on every platform
         const double th = p->pw_smoothing;
-        c->omega = exp(th * log(dyn / dxn) + (1.0 - th) * log(om));
+        c->omega = crm::cr_exp(th * crm::cr_log(dyn / dxn) + (1.0 - th) * crm::cr_log(om));
       }
       c->anc_rp2 = rp2[z];
       c->anc_rd2 = rd2[z];
@@ -1927,7 +1953,7 @@ __device__ __forceinline__ void reduced_cost(double q, int8_t bf, double& lam, d
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
+__global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg, int mid) {
   __shared__ SpmvShared<V, 2> sh;
   __shared__ DD s_red[4 * 2 * kEvT];
   DD p[2 * kEvT];
@@ -1944,7 +1970,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
     // the chunk's ordinal among those touching the LP
     const bool endc = last_of_lp(cfg.work_t, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
-    if (!eval_guard(c)) {
+    if (!eval_guard(c, mid)) {
       if (endc) dd_reset(p);
       continue;
     }
@@ -1993,7 +2019,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg) {
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
+__global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg, int mid) {
   __shared__ SpmvShared<V, 1> sh;
   __shared__ DD s_red[4 * 2 * kEvA];
   DD p[2 * kEvA];
@@ -2008,7 +2034,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
     // as in k_eval_t: one reduction per LP and chunk
     const bool endc = last_of_lp(cfg.work_a, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
-    if (!eval_guard(c)) {
+    if (!eval_guard(c, mid)) {
       if (endc) dd_reset(p);
       continue;
     }
@@ -2055,17 +2081,30 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg) {
 }
 
 // One workgroup per LP: termination and restart decision of an evaluation.
-__global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg) {
+// The evaluation that opens a launch sequence (mid == 0) also fills the
+// step-rule factor ring for the sequence; the guarded ones inside it leave
+// the ring alone (it already covers every attempt of the sequence).
+__global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg, int mid) {
   __shared__ DD s_red[4 * 2 * kEvT];
   const int nlps = cfg.counts->nlps;
   for (int li = blockIdx.x; li < nlps; li += gridDim.x) {
     const LpDev& lp = cfg.lps[li];
     Ctl* c = lp.ctl;
     if (c->status != kRunning) continue;
+    if (mid) {
+      if (!eval_guard(c, 1)) continue;
+      double st[2 * kEvT], sa[2 * kEvA];
+      sum_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, lp.nslot_t, st, s_red);
+      sum_partials<2 * kEvA>(lp.part_a, lp.ntiles_a, lp.nslot_a, sa, s_red);
+      if (threadIdx.x == 0) decide_eval(c, lp.prm, st, sa);
+      __syncthreads();
+      continue;
+    }
     // step-rule factors for the attempts j = a0 + 1 .. a0 + kPowRing of this
     // launch sequence (which holds at most kPowRing attempts): the host
-    // table's values while it covers j, else powers computed here. The step
-    // decision reads the whole ring beside its partial sums.
+    // table's values while it covers j, else the same correctly rounded
+    // powers computed here. The step decision reads the whole ring beside
+    // its partial sums.
     const int64_t a0 = c->attempts;
     const DevParams* p = lp.prm;
     for (int t = threadIdx.x; t < kPowRing; t += kBlock) {
@@ -2075,12 +2114,12 @@ __global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg) {
         lp.pow_ring[kPowRing + t] = lp.pow_tab[kPowTab + j - 1];
       } else {
         const double j1 = (double)j + 1.0;
-        lp.pow_ring[t] = pow(j1, -p->step_reduction);
-        lp.pow_ring[kPowRing + t] = pow(j1, -p->step_growth);
+        lp.pow_ring[t] = crm::cr_pow(j1, -p->step_reduction);
+        lp.pow_ring[kPowRing + t] = crm::cr_pow(j1, -p->step_growth);
       }
     }
     if (threadIdx.x == 0) c->ring_base = a0;
-    if (!eval_guard(c)) continue;
+    if (!eval_guard(c, 0)) continue;
     double st[2 * kEvT], sa[2 * kEvA];
     sum_partials<2 * kEvT>(lp.part_t, lp.ntiles_t, lp.nslot_t, st, s_red);
     sum_partials<2 * kEvA>(lp.part_a, lp.ntiles_a, lp.nslot_a, sa, s_red);
@@ -2092,7 +2131,9 @@ __global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg) {
 // Restart application or the final copy of the returned average. The
 // flags stay set until the next k_primal clears them, and restarting to the
 // average reads the sums it then clears, so this kernel runs exactly once
-// per evaluation step, right before the attempts.
+// per evaluation step, right before attempt slots (every evaluation step of
+// a launch sequence, the guarded ones included, is followed by at least one
+// attempt slot before the next).
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_apply(LaunchCfg cfg) {
   auto body = [&](const WorkItem& it, bool tside) {
@@ -2460,16 +2501,16 @@ int Kernels<V>::learn_flush(const LaunchCfg& c, void* stream) {
   OPDHG_LAUNCH(k_learn_flush<V>, c.launch_ta, c);
 }
 template <typename V>
-int Kernels<V>::eval_t(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_eval_t<V>, c.launch_t, c);
+int Kernels<V>::eval_t(const LaunchCfg& c, void* stream, int mid) {
+  OPDHG_LAUNCH(k_eval_t<V>, c.launch_t, c, mid);
 }
 template <typename V>
-int Kernels<V>::eval_a(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_eval_a<V>, c.launch_a, c);
+int Kernels<V>::eval_a(const LaunchCfg& c, void* stream, int mid) {
+  OPDHG_LAUNCH(k_eval_a<V>, c.launch_a, c, mid);
 }
 template <typename V>
-int Kernels<V>::eval_decide(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_eval_decide, c.launch_lp, c);
+int Kernels<V>::eval_decide(const LaunchCfg& c, void* stream, int mid) {
+  OPDHG_LAUNCH(k_eval_decide, c.launch_lp, c, mid);
 }
 template <typename V>
 int Kernels<V>::apply(const LaunchCfg& c, void* stream) {

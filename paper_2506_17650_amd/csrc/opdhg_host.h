@@ -182,8 +182,20 @@ void unpermute(const double* dev, const std::vector<int32_t>& perm, const double
                double* out);
 Ctl initial_ctl(const Prepared& P);
 
-// A set of LPs launched together, with its captured launch sequence:
-// one evaluation step then `attempts` step attempts.
+// Attempt slots between the guarded evaluations inside a launch sequence.
+constexpr int kMidEvalEvery = 16;
+
+// A set of LPs launched together, with its captured launch sequence: one
+// evaluation step, then `attempts` step attempts with a guarded evaluation
+// step after every kMidEvalEvery of them. An LP whose iteration count
+// reaches an evaluation point inside the sequence (after a rejected attempt,
+// say) is evaluated there and goes on within kMidEvalEvery slots, instead of
+// waiting for the next sequence.
+//
+// Direct mode (for callers that cannot let the library create HIP objects):
+// no captured graph, no streams or events of the library's own; each replay
+// launches the same sequence on the caller's stream, and a side's tile and
+// windowed kernels run one after the other.
 struct Group {
   hipStream_t stream = nullptr;      // caller's stream (replays, copies)
   hipStream_t cap_stream = nullptr;  // private stream used only for capture
@@ -193,8 +205,12 @@ struct Group {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   LaunchCfg cfg{};
   int prec = 0;
-  int init(void* stream, int prec);
+  bool direct = false;
+  int seq_attempts = 0;  // attempts per sequence (direct mode)
+  int init(void* stream, int prec, bool direct = false);
   int launch_side(bool primal, int force, hipStream_t s);
+  // enqueue one launch sequence (evaluation, attempts, board) on s
+  int enqueue(hipStream_t s, int attempts);
   int capture(int attempts_per_replay);
   int launch_init();
   int launch_primal_forced();
@@ -206,5 +222,12 @@ struct Group {
 
 int run_group(Group& grp, const std::vector<Ctl*>& d_ctls, std::vector<Ctl>& h_ctls,
               Ctl* pinned, int64_t k_target, double time_limit, double* elapsed);
+
+// Session set-up behind opdhg_session_create; direct: a launch group in
+// direct mode and pageable readback (nothing allocated on the device or
+// pinned). need_out (optional) receives the device bytes the LP needs.
+int session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                   size_t workspace_bytes, void* hip_stream, bool direct, opdhg_session** out,
+                   size_t* need_out);
 
 }  // namespace opdhg

@@ -93,7 +93,9 @@ struct Ctl {
   int32_t stop_request;  // host asks for a final evaluation (time limit)
   int32_t learn_now;     // the next attempt is an update iteration (k mod phi == 0)
   int32_t weighted_step; // movement partials divided by T and Sigma (read with the other fields)
-  int32_t pad2, pad3, pad4, pad5;
+  int32_t fail_pending;  // a numerical failure ends the solve at the next evaluation, which
+                         // reports the current iterate with NUMERICAL_ERROR
+  int32_t pad3, pad4, pad5;
 };
 
 // Tile: rows [rb, re) of one CSR side with nonzeros [s, e).
@@ -316,9 +318,10 @@ struct Kernels {
   static int dual_seg(const LaunchCfg& c, void* stream, int force = 0);
   static int decide(const LaunchCfg& c, void* stream);
   static int learn_flush(const LaunchCfg& c, void* stream);
-  static int eval_t(const LaunchCfg& c, void* stream);
-  static int eval_a(const LaunchCfg& c, void* stream);
-  static int eval_decide(const LaunchCfg& c, void* stream);
+  // mid: a guarded evaluation inside a launch sequence (see k_eval_decide)
+  static int eval_t(const LaunchCfg& c, void* stream, int mid);
+  static int eval_a(const LaunchCfg& c, void* stream, int mid);
+  static int eval_decide(const LaunchCfg& c, void* stream, int mid);
   static int apply(const LaunchCfg& c, void* stream);
 };
 
