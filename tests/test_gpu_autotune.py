@@ -8,7 +8,10 @@ chosen tiling must give the same results as the automatic one bit for bit
 import numpy as np
 import pytest
 
+import oracle
+from oracle.params import default_params
 from lpgen import config_lp
+from gpu_common import check_final_fp32, check_final_fp64, lib_params
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +30,8 @@ def P():
 
 def test_autotune_fp64_results_unchanged(P):
     lps = [config_lp("cfg3", index=i, scale=0.05) for i in range(6)] + [config_lp("cfg0", seed=4)]
-    p = P.opdhg_default_params(max_iter=5000, lr=1e-2)
+    op = default_params(max_iter=5000, lr=1e-2)
+    p = lib_params(P, op)
     tun, tuned = P.opdhg_autotune(lps, p, replays=2)
     print(f"tuned tile {tun.tile_nnz} workgroups {tun.workgroups}: "
           f"{tun.attempts_per_s:.0f} vs {tun.default_attempts_per_s:.0f} attempts/s", flush=True)
@@ -37,18 +41,21 @@ def test_autotune_fp64_results_unchanged(P):
     assert tun.attempts_per_s >= tun.default_attempts_per_s
     a = P.opdhg_solve_batch(lps, p)
     b = P.opdhg_solve_batch(lps, tuned)
-    for (xa, ya, ra), (xb, yb, rb) in zip(a, b):
+    for i, (lp, (xa, ya, ra), (xb, yb, rb)) in enumerate(zip(lps, a, b)):
         assert ra.status == rb.status and ra.iterations == rb.iterations
         assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+        check_final_fp64((xb, yb, rb), oracle.solve(lp, op), label=f"tuned LP {i}")
 
 
 def test_autotune_fp32_results_close(P):
     lps = [config_lp("cfg3", index=i, scale=0.05) for i in range(4)]
-    p = P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=20000, lr=1e-3)
+    op = default_params(max_iter=20000, lr=1e-3)
+    p = lib_params(P, op, precision=P.OPDHG_FP32)
     tun, tuned = P.opdhg_autotune(lps, p, replays=2)
     a = P.opdhg_solve_batch(lps, p)
     b = P.opdhg_solve_batch(lps, tuned)
-    for (_, _, ra), (_, _, rb) in zip(a, b):
+    for i, (lp, (_, _, ra), (_, _, rb)) in enumerate(zip(lps, a, b)):
         assert ra.status == rb.status == P.capi.OPDHG_STATUS_OPTIMAL
         # both are 1e-4-optimal: objectives agree to the tolerance scale
         assert abs(ra.primal_obj - rb.primal_obj) <= 1e-3 * (1.0 + abs(rb.primal_obj))
+        check_final_fp32(rb, oracle.solve(lp, op), label=f"tuned FP32 LP {i}")

@@ -9,12 +9,13 @@ equal to the oracle's (test_library_host.py), so these solves are tied to
 the oracle's rescaling.
 """
 
-import sys
-
 import numpy as np
 import pytest
 
+import oracle
+from oracle.params import default_params
 from lpgen import block_angular_lp, config_lp
+from gpu_common import check_final_fp32, check_final_fp64, lib_params, say as _say
 
 pytestmark = pytest.mark.gpu
 
@@ -29,11 +30,6 @@ def P():
     return P
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
 def _lps():
     return {
         "cfg0": config_lp("cfg0", seed=3),
@@ -41,6 +37,17 @@ def _lps():
         "cfg4-2x0.01": config_lp("cfg4", index=2, scale=0.01),
         "cfg3-1x0.2": config_lp("cfg3", index=1, scale=0.2),
     }
+
+
+_ORACLE = {}
+
+
+def _oracle(name, lp, op, key):
+    """The oracle's solve of one test LP, computed once per parameter set
+    (both precisions compare with it)."""
+    if (name, key) not in _ORACLE:
+        _ORACLE[(name, key)] = oracle.solve(lp, op)
+    return _ORACLE[(name, key)]
 
 
 def _same(a, b):
@@ -57,10 +64,17 @@ def test_device_prep_equals_host_prep(P, prec_name, extra):
     prec = P.OPDHG_FP64 if prec_name == "fp64" else P.OPDHG_FP32
     for name, lp in _lps().items():
         _say(f"[prep] {name} {prec_name} {extra}")
-        kw = dict(precision=prec, max_iter=3000, lr=1e-3, tol=1e-4, **extra)
-        host = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw))
-        dev = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw))
+        op = default_params(max_iter=3000, lr=1e-3, tol=1e-4, **extra)
+        host = P.opdhg_solve(lp, lib_params(P, op, precision=prec, prep=P.OPDHG_PREP_HOST))
+        dev = P.opdhg_solve(lp, lib_params(P, op, precision=prec, prep=P.OPDHG_PREP_DEVICE))
         _same(dev, host)
+        ref = _oracle(name, lp, op, tuple(sorted(extra.items())))
+        if prec == P.OPDHG_FP64:
+            check_final_fp64(dev, ref, label=name)
+        elif ref.status == oracle.pdhg.OPTIMAL:
+            check_final_fp32(dev[2], ref, label=name)
+        else:  # both stop at the iteration limit
+            assert dev[2].status == ref.status and dev[2].iterations == ref.iterations, name
 
 
 def test_device_prep_other_exponent_to_rounding(P):
@@ -98,15 +112,21 @@ def test_device_prep_windows_and_segments(P):
 
 def test_device_prep_batch_and_server(P):
     lps = list(_lps().values())
-    kw = dict(precision=P.OPDHG_FP32, max_iter=3000, lr=1e-3, windows=P.OPDHG_WINDOWS_OFF)
-    dev = P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw)
-    solo = [P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw)) for lp in lps]
+    op = default_params(max_iter=3000, lr=1e-3)
+    kw = dict(precision=P.OPDHG_FP32, windows=P.OPDHG_WINDOWS_OFF)
+    dev = lib_params(P, op, prep=P.OPDHG_PREP_DEVICE, **kw)
+    solo = [P.opdhg_solve(lp, lib_params(P, op, prep=P.OPDHG_PREP_HOST, **kw)) for lp in lps]
     for got, ref in zip(P.opdhg_solve_batch(lps, dev), solo):
         _same(got, ref)
     with P.Server(64 << 20, precision=P.OPDHG_FP32) as srv:
         got = [srv.wait(srv.submit(lp, dev), 120.0) for lp in lps]
-    for g, ref in zip(got, solo):
+    for (name, lp), g, ref in zip(_lps().items(), got, solo):
         _same(g, ref)
+        want = _oracle(name, lp, op, ())
+        if want.status == oracle.pdhg.OPTIMAL:
+            check_final_fp32(g[2], want, label=f"device-prepared served {name}")
+        else:
+            assert g[2].status == want.status and g[2].iterations == want.iterations, name
 
 
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])

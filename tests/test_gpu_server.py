@@ -5,7 +5,10 @@ tile, exact cross-tile sums), so each result from the server must equal the
 solo opdhg_solve of the same LP with the same parameters bit for bit, in
 whatever mix it ran (the server runs tiles only, so the solo solves turn
 windows off): submitted together, under a budget that admits only a
-few at a time, or arriving while others iterate.
+few at a time, or arriving while others iterate. Every served result is
+also checked against the FP64 oracle's solve of the same LP: in FP64 the
+same counts and the same iterate to 1e-6 per coordinate, in FP32 the same
+status and the objective at the FP32 bound.
 """
 
 import time
@@ -13,7 +16,10 @@ import time
 import numpy as np
 import pytest
 
+import oracle
+from oracle.params import default_params, vanilla_params
 from lpgen import config_lp
+from gpu_common import check_final_fp32, check_final_fp64, lib_params
 
 pytestmark = pytest.mark.gpu
 
@@ -31,13 +37,24 @@ def _mix():
     return lps
 
 
+def _oparams(**kw):
+    base = dict(tol=1e-4, max_iter=20000, lr=1e-3, phi=20)
+    base.update(kw)
+    return default_params(**base)
+
+
 def _params(P, prec, **kw):
     # the server runs every request in tiles (one captured sequence serves
     # every mix), so the solo solves it is compared with use tiles too
-    base = dict(precision=prec, tol=1e-4, max_iter=20000, lr=1e-3, phi=20,
-                windows=P.OPDHG_WINDOWS_OFF)
-    base.update(kw)
-    return P.opdhg_default_params(**base)
+    lib_kw = {k: kw.pop(k) for k in list(kw) if k in ("time_limit_s",)}
+    return lib_params(P, _oparams(**kw), precision=prec, windows=P.OPDHG_WINDOWS_OFF, **lib_kw)
+
+
+def _vs_oracle(P, prec, lp, res, op, label):
+    if prec == P.OPDHG_FP64:
+        check_final_fp64(res, oracle.solve(lp, op), label=label)
+    else:
+        check_final_fp32(res[2], oracle.solve(lp, op), label=label)
 
 
 def _same(a, b):
@@ -62,8 +79,9 @@ def test_mix_equals_solo(prec_name):
         st = srv.stats()
         assert st.completed == len(lps) and st.failed == 0 and st.active == 0
         lat = [srv.latency(t) for t in tickets]
-    for a, b in zip(got, solo):
+    for i, (lp, a, b) in enumerate(zip(lps, got, solo)):
         _same(a, b)
+        _vs_oracle(P, prec, lp, a, _oparams(), f"served LP {i} ({prec_name})")
     assert all(r.status == P.capi.OPDHG_STATUS_OPTIMAL for _, _, r in got)
     assert all(v > 0 for v in lat)
 
@@ -82,8 +100,9 @@ def test_tight_budget_admits_in_turn():
         st = srv.stats()
     assert st.peak_bytes <= budget
     assert st.completed == len(lps)
-    for a, b in zip(got, solo):
+    for i, (lp, a, b) in enumerate(zip(lps, got, solo)):
         _same(a, b)
+        _vs_oracle(P, prec, lp, a, _oparams(), f"budgeted LP {i}")
 
 
 def test_over_budget_request_fails_alone():
@@ -138,8 +157,9 @@ def test_arrivals_while_others_iterate():
             time.sleep(0.02)
         got = [srv.wait(t, 120.0) for t in tickets]
         assert srv.stats().replays > 0
-    for a, b in zip(got, solo):
+    for i, (lp, a, b) in enumerate(zip(lps, got, solo)):
         _same(a, b)
+        _vs_oracle(P, prec, lp, a, _oparams(), f"arriving LP {i}")
 
 
 def test_vanilla_and_adaptive_requests_mixed():
@@ -148,13 +168,14 @@ def test_vanilla_and_adaptive_requests_mixed():
     P = _P()
     prec = P.OPDHG_FP32
     lps = [config_lp("cfg0", seed=s) for s in range(4)]
-    plist = [P.opdhg_vanilla_params(lr, precision=prec, max_iter=20000,
-                                    windows=P.OPDHG_WINDOWS_OFF) for lr in (0.0, 1e-1)]
-    plist += [_params(P, prec), _params(P, prec, lr=0.0)]
+    olist = [vanilla_params(lr, max_iter=20000) for lr in (0.0, 1e-1)]
+    olist += [_oparams(), _oparams(lr=0.0)]
+    plist = [lib_params(P, op, precision=prec, windows=P.OPDHG_WINDOWS_OFF) for op in olist]
     solo = [P.opdhg_solve(lp, q) for lp, q in zip(lps, plist)]
     with P.Server(64 << 20, precision=prec) as srv:
         tickets = [srv.submit(lp, q) for lp, q in zip(lps, plist)]
         got = [srv.wait(t, 120.0) for t in tickets]
-    for a, b in zip(got, solo):
+    for i, (lp, a, b, op) in enumerate(zip(lps, got, solo, olist)):
         _same(a, b)
+        _vs_oracle(P, prec, lp, a, op, f"mixed-scheme LP {i}")
     assert got[0][2].restarts == 0 and got[1][2].restarts == 0

@@ -10,9 +10,6 @@ At the full block-angular size one step from the GPU's own iterate is
 checked against one oracle step from the same point.
 """
 
-import math
-import sys
-
 import numpy as np
 import pytest
 
@@ -20,10 +17,14 @@ import oracle
 from oracle import pdhg as OP
 from oracle.params import default_params
 from lpgen import config_lp
+from gpu_common import (adagrad_flip_slack, check_final_fp32, ew_mixed, ew_mixed_slack,
+                        say as _say, scal_rel)
 
 pytestmark = pytest.mark.gpu
 
-# as in test_gpu_parity: FP32 rounding of O(1) row sums over 30 steps, 5x margin
+# as in test_gpu_parity: FP32 rounding of row sums over 30 steps, per
+# coordinate against its size plus the vector's scale, 5x margin; T and
+# Sigma after the learner's sign-flip allowance (adagrad_flip_slack)
 FP32_TRACE_TOL = 2e-4
 FP32_ETA_TOL = 2e-3
 
@@ -36,19 +37,6 @@ def P():
     import paper_2506_17650_amd as P
     P.load()
     return P
-
-
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def rel(a, b):
-    a = np.asarray(a, dtype=float)
-    b = np.asarray(b, dtype=float)
-    nb = np.linalg.norm(b)
-    d = np.linalg.norm(a - b)
-    return 0.0 if (nb == 0.0 and d == 0.0) else d / nb
 
 
 def _lib(P, op, **kw):
@@ -109,12 +97,14 @@ def _trace_case(P, lp, kw, label):
             x, y, T, S, st = s.state()
             e = tr[k]
             assert st.k == k and st.attempts == e.attempts, (k, st.attempts, e.attempts)
-            errs = {"x": rel(x, e.x), "y": rel(y, e.y), "T": rel(T, e.T), "S": rel(S, e.S),
-                    "eta": abs(st.eta - e.eta) / abs(e.eta)}
+            slack = adagrad_flip_slack(op.lr, op.phi, k)
+            errs = {"x": ew_mixed(x, e.x), "y": ew_mixed(y, e.y),
+                    "T": ew_mixed_slack(T, e.T, slack), "S": ew_mixed_slack(S, e.S, slack),
+                    "eta": scal_rel(st.eta, e.eta)}
             worst = max(worst, max(v for nm, v in errs.items() if nm != "eta"))
             for nm, v in errs.items():
                 assert v <= (FP32_ETA_TOL if nm == "eta" else FP32_TRACE_TOL), (k, nm, v)
-    _say(f"  worst FP32 relative deviation {worst:.2e}")
+    _say(f"  worst FP32 per-coordinate deviation {worst:.2e}")
 
 
 def test_windowed_solve_matches_tiles_and_oracle(P):
@@ -126,10 +116,8 @@ def test_windowed_solve_matches_tiles_and_oracle(P):
     xw, yw, rw = P.opdhg_solve(lp, p)
     xt, yt, rt = P.opdhg_solve(lp, P.opdhg_default_params(precision=P.OPDHG_FP32, max_iter=40000,
                                                          windows=P.OPDHG_WINDOWS_OFF))
-    assert rw.status == 0 and rt.status == 0 and ref.status == 0
     for r in (rw, rt):
-        assert abs(r.primal_obj - ref.primal_obj) <= 1e-3 * abs(ref.primal_obj)
-        assert r.rel_kkt <= 1e-4
+        check_final_fp32(r, ref)
     _say(f"  iterations windows {rw.iterations}, tiles {rt.iterations}, oracle {ref.iterations}")
 
 
@@ -165,21 +153,25 @@ def test_server_ignores_windows(P):
 
 
 def _one_step_check(P, lp, params, k):
-    """Run k iterations on the GPU, then compare the GPU's next accepted
-    attempt with one oracle attempt from the GPU's own iterate (FP64)."""
+    """Run the GPU to the first k' >= k whose next attempt is accepted, then
+    compare that accepted attempt with one oracle attempt (FP64) from the
+    GPU's own iterate, preconditioners and step, coordinate by coordinate."""
     slp = oracle.rescale(lp, params.ruiz_iters, params.pc_beta)
     with P.Session(lp, params) as s:
-        s.run(k)
-        x, y, T, S, st = s.state()
-        s.run(k + 1)
-        x1, y1, T1, S1, st1 = s.state()
-    if st1.attempts != st.attempts + 1:
-        pytest.skip("the next attempt was rejected; nothing to compare")
+        for kk in range(k, k + 16):
+            s.run(kk)
+            x, y, T, S, st = s.state()
+            s.run(kk + 1)
+            x1, y1, T1, S1, st1 = s.state()
+            if st1.attempts == st.attempts + 1 and st1.k == kk + 1:
+                break
+        else:
+            raise AssertionError("no accepted first attempt in 16 iterations")
     g = slp.c - OP.AT_mul(slp, y)
     Ax = OP.A_mul(slp, x)
     a = OP.pdhg_attempt(slp, x, y, Ax, g, T, S, st.eta, st.omega)
-    ex, ey = rel(x1, a["x_new"]), rel(y1, a["y_new"])
-    _say(f"  one step from k={k}: x rel {ex:.2e}, y rel {ey:.2e}")
+    ex, ey = ew_mixed(x1, a["x_new"]), ew_mixed(y1, a["y_new"])
+    _say(f"  one step from k={kk}: x per-coordinate {ex:.2e}, y {ey:.2e}")
     assert ex <= FP32_TRACE_TOL and ey <= FP32_TRACE_TOL
 
 

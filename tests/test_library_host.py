@@ -170,7 +170,8 @@ def test_new_parameters_validated():
 
 
 def test_binding_structs_match_the_header_layout(tmp_path):
-    """Every ctypes mirror has the C compiler's size and field offsets."""
+    """Every ctypes mirror has the C compiler's size and field offsets, and
+    every numeric constant of the binding the header's value."""
     import ctypes
     import shutil
     cc = shutil.which("gcc") or shutil.which("cc")
@@ -187,6 +188,14 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         for f, _ in st._fields_:
             lines.append(f'  printf("%zu\\n", offsetof({st.__name__}, {f}));')
             want.append(getattr(st, f).offset)
+    # every numeric constant of the binding that the header defines
+    import re
+    with open(os.path.join(ROOT, "include", "opdhg.h")) as f:
+        defined = set(re.findall(r"^#define (OPDHG_\w+) ", f.read(), re.M))
+    consts = sorted(n for n in dir(capi) if n in defined and isinstance(getattr(capi, n), int))
+    for n in consts:
+        lines.append(f'  printf("%lld\\n", (long long)({n}));')
+        want.append(getattr(capi, n))
     lines += ["  return 0;", "}"]
     src = tmp_path / "abi.c"
     src.write_text("\n".join(lines))
@@ -194,7 +203,7 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
-    assert len(structs) >= 6
+    assert len(structs) >= 6 and len(consts) >= 30
     assert got == want
 
 
