@@ -1,37 +1,42 @@
 """Benchmark of restarted PDHG with online preconditioning on one MI355X.
 
 One step is one launch sequence of the hot path on the resident LP: the KKT
-evaluation with its restart / termination decision, then 64 step attempts,
-each the CSR(A^T) SpMV fused with the primal step, the CSR(A) SpMV fused
-with the dual step, and the adaptive step decision, with the AdaGrad
-learner on update iterations (every 20th). The LP never terminates during
-timing (tol 0), so every step does the full work.
+evaluation with its restart / termination decision, then 64 step-attempt
+slots, each the CSR(A^T) SpMV fused with the primal step, the CSR(A) SpMV
+fused with the dual step, and the adaptive step decision, with a guarded
+evaluation after every 16 slots and the AdaGrad learner on update
+iterations (every 20th). The LP never terminates during timing (tol 0), so
+every step does the full work.
 
-Headline: accepted PDHG iterations per second on the badly scaled LP
-(m = 50k rows, 40% equality, n = 100k columns, power-law column degree on
-2..2000 with exponent 2.2, ~0.7M nonzeros, row scales log-uniform in
-[1e-3, 1e3]; synthetic, seeded), FP32 storage and SpMV with FP64
+Headline: accepted PDHG iterations per second on the block-angular LP
+(64 blocks of 30k rows x 80k columns with 6 +-1 entries per column, plus
+2,000 linking >= rows of ~2,140 N(0,1) entries; m = 1.922M, n = 5.12M,
+35M nonzeros; synthetic, seeded), FP32 storage and SpMV with FP64
 reductions, data resident in HBM. The same JSON line carries:
-  roofline      the dominant sparse-product kernel: algorithmic bytes per
-                launch / average launch time (HIP events on the solver's
-                stream) against 8 TB/s; HBM traffic from rocprofv3 counters
-                when a counter summary for the current kernel source exists
+  roofline      the dominant kernel (the windowed primal step, k_primal_win):
+                algorithmic bytes per launch / average launch time (HIP
+                events on the solver's stream) against 8 TB/s, HBM traffic
+                from rocprofv3 counters when a counter summary for the
+                current kernel source exists; beside it the dual side and
+                the whole iteration
   cpu_baseline  the FP64 oracle on a bounded sample of the same LP
-  fp64          the same LP in FP64
-  hbm           the block-angular LP (1.92M x 5.12M, 35M nonzeros), FP32
+  cfg1          the badly scaled power-law LP (50k x 100k, ~0.7M nonzeros)
+                in FP32 and in FP64
   batch         256 LPs solved to relative KKT 1e-4 in one packed launch
                 set (FP32), against plain FP64 PDHG (lr 0) one at a time,
-                with the FP32 error against FP64 per result
+                with the FP32 error against FP64 per result and the batch's
+                bytes per batch-attempt against the HBM roofline
   serving       a Poisson stream of serving requests through the
                 continuous-batching server (FP32), against plain FP64 PDHG
-                served first-in first-out one at a time; p50 / p99 latency
+                served first-in first-out one at a time through the same
+                server machinery (one LP at a time); p50 / p99 latency
   variants      (on request: --sections ...,variants) the paper's variant
                 matrix with #Opt, SGM10 / mean iterations, GM / mean time
                 and #Imp / #Wors on a mixed synthetic set, for restarted
                 adaptive PDHG and for vanilla PDHG
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--sections main,fp64,hbm,batch,serving[,variants]]
+                       [--sections cfg1,batch,serving[,variants]]
 """
 
 from __future__ import annotations
@@ -50,7 +55,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "PDHG iters/s + SpMV HBM GB/s; LP solves/s and p99 latency at rel KKT 1e-4"
-SECTIONS = ("main", "fp64", "hbm", "batch", "serving")
+SECTIONS = ("cfg1", "batch", "serving")
+SLOTS_PER_STEP = 64  # step-attempt slots per launch sequence
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_17650_amd", "csrc", "kernels.hip")
 
 
@@ -170,39 +176,21 @@ def iterate_section(P, lp, prec, args, steps, warmup, reps):
     }
 
 
-def section_main(P, args):
+def section_headline(P, args):
+    """The block-angular LP in FP32 (windowed products): the headline."""
     from lpgen import config_lp
     from lpgen.generators import summary
     t = time.perf_counter()
-    lp = config_lp("cfg1")
-    log(f"[bench] main: cfg1 m={lp.m} n={lp.n} nnz={lp.nnz} "
+    lp = config_lp("cfg2")
+    log(f"[bench] headline: cfg2 m={lp.m} n={lp.n} nnz={lp.nnz} "
         f"(generated in {time.perf_counter() - t:.1f}s)")
     r = iterate_section(P, lp, P.OPDHG_FP32, args, args.steps, args.warmup, args.kernel_reps)
-    log(f"[bench] main: {r['iters'] / r['seconds']:.0f} iters/s")
-    return lp, summary(lp), r
-
-
-def section_fp64(P, args, lp):
-    log("[bench] fp64: cfg1 in FP64")
-    r = iterate_section(P, lp, P.OPDHG_FP64, args, args.steps, args.warmup, args.kernel_reps)
-    log(f"[bench] fp64: {r['iters'] / r['seconds']:.0f} iters/s")
-    return {"workload": "cfg1", "dtype": "f64", "value": r["iters"] / r["seconds"],
-            "unit": "PDHG iters/s", "attempts_per_s": r["attempts"] / r["seconds"],
-            "kernels": r["kernels"]}
-
-
-def section_hbm(P, args):
-    from lpgen import config_lp
-    t = time.perf_counter()
-    lp = config_lp("cfg2")
-    log(f"[bench] hbm: cfg2 m={lp.m} n={lp.n} nnz={lp.nnz} "
-        f"(generated in {time.perf_counter() - t:.1f}s)")
-    r = iterate_section(P, lp, P.OPDHG_FP32, args, args.hbm_steps, 1, 10)
-    log(f"[bench] hbm: {r['iters'] / r['seconds']:.0f} iters/s, primal "
+    log(f"[bench] headline: {r['iters'] / r['seconds']:.0f} iters/s, "
+        f"{r['attempts'] / args.steps:.2f} attempts per step of {SLOTS_PER_STEP} slots, primal "
         f"{r['kernels']['primal']['achieved_GBs']:.0f} GB/s, dual "
         f"{r['kernels']['dual']['achieved_GBs']:.0f} GB/s")
-    # HBM traffic of each step from the committed counter summaries: the
-    # primal step is the windowed kernel; the dual step is the windowed
+    # HBM traffic of each side from the committed counter summaries: the
+    # primal side is the windowed kernel alone; the dual side is the windowed
     # kernel, the tile kernel of the rows left in tiles (beside it) and the
     # segmented linking rows' finish
     parts = {"primal": ["k_primal_win"], "dual": ["k_dual_win", "k_dual", "k_dual_seg"]}
@@ -213,11 +201,34 @@ def section_hbm(P, args):
         k["traffic"] = None if any(v is None for v in vals) else sum(vals)
         if k["traffic"] is not None:
             k["traffic_GBs"] = k["traffic"] / (k["avg_launch_ms"] * 1e-3) / 1e9
-    return {"workload": "cfg2: block-angular LP, 64 blocks of 30k x 80k + 2k linking rows",
-            "m": lp.m, "n": lp.n, "nnz": lp.nnz, "dtype": "f32",
-            "value": r["iters"] / r["seconds"], "unit": "PDHG iters/s",
-            "attempts_per_s": r["attempts"] / r["seconds"], "steps": args.hbm_steps,
-            "kernels": r["kernels"]}
+    return lp, summary(lp), r
+
+
+def section_cfg1(P, args):
+    """The badly scaled power-law LP (MALL-resident) in FP32 and FP64."""
+    from lpgen import config_lp
+    from lpgen.generators import summary
+    t = time.perf_counter()
+    lp = config_lp("cfg1")
+    shape = summary(lp)
+    log(f"[bench] cfg1: m={lp.m} n={lp.n} nnz={lp.nnz} "
+        f"(generated in {time.perf_counter() - t:.1f}s)")
+    out = {"workload": "cfg1: badly scaled random LP, power-law column degree",
+           "m": lp.m, "n": lp.n, "nnz": lp.nnz,
+           "row_len_mean": round(shape["row_len_mean"], 2), "col_len_max": shape["col_len_max"],
+           "note": "the matrix (5.6 MB in FP32) stays in the 256 MB MALL: GB/s here are "
+                   "algorithmic bytes over kernel time, not HBM traffic"}
+    for name, prec in (("f32", P.OPDHG_FP32), ("f64", P.OPDHG_FP64)):
+        r = iterate_section(P, lp, prec, args, args.cfg1_steps, args.warmup, args.kernel_reps)
+        log(f"[bench] cfg1 {name}: {r['iters'] / r['seconds']:.0f} iters/s, "
+            f"{r['attempts'] / args.cfg1_steps:.2f} attempts per step")
+        out[name] = {"value": r["iters"] / r["seconds"], "unit": "PDHG iters/s",
+                     "attempts_per_s": r["attempts"] / r["seconds"],
+                     "attempts_per_step": r["attempts"] / args.cfg1_steps,
+                     "slots_per_step": SLOTS_PER_STEP,
+                     "executed_fraction": r["attempts"] / (args.cfg1_steps * SLOTS_PER_STEP),
+                     "steps": args.cfg1_steps, "kernels": r["kernels"]}
+    return out
 
 
 def section_batch(P, args):
@@ -234,10 +245,17 @@ def section_batch(P, args):
                                  time_limit_s=600)
     import torch
     t0 = time.perf_counter()
-    tun, p32 = P.opdhg_autotune(lps, p32, replays=2)
+    tun, p32 = P.opdhg_autotune(lps, p32, replays=args.tune_replays)
     log(f"[bench] batch: autotuned tile {tun.tile_nnz}, workgroups {tun.workgroups}: "
-        f"{tun.attempts_per_s:.0f} attempts/s (automatic tiling {tun.default_attempts_per_s:.0f}); "
+        f"{tun.attempts_per_s:.0f} attempts/s (automatic tiling {tun.default_attempts_per_s:.0f}), "
+        f"{100 * tun.executed_fraction:.1f}% of slots executed; "
         f"{time.perf_counter() - t0:.1f}s")
+    # the batch against the HBM roofline: one batch-attempt moves every LP's
+    # primal- and dual-kernel bytes once (V = 4); the tuner's replays keep
+    # all LPs running, so batch-attempts/s is the attempts/s over the count
+    b_att = sum(primal_kernel_bytes(lp, 4) + dual_kernel_bytes(lp, 4) for lp in lps)
+    ba_per_s = tun.attempts_per_s / len(lps)
+    batch_gbs = b_att * ba_per_s / 1e9
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res32 = P.opdhg_solve_batch(lps, p32)
@@ -265,8 +283,17 @@ def section_batch(P, args):
         "solves_per_s": opt32 / wall32, "solves_per_s_loop": opt32 / loop32,
         "optimal": opt32, "wall_s": wall32, "loop_s": loop32,
         "autotune": {"tile_nnz": tun.tile_nnz, "lanes": tun.lanes, "workgroups": tun.workgroups,
-                     "candidates": tun.candidates, "attempts_per_s": tun.attempts_per_s,
-                     "automatic_tiling_attempts_per_s": tun.default_attempts_per_s},
+                     "candidates": tun.candidates, "replays": args.tune_replays,
+                     "attempts_per_s": tun.attempts_per_s,
+                     "automatic_tiling_attempts_per_s": tun.default_attempts_per_s,
+                     "executed_fraction": tun.executed_fraction},
+        "roofline": {"bound": "hbm", "achieved": batch_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": batch_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_batch_attempt": b_att, "batch_attempts_per_s": ba_per_s,
+                     "note": "whole step (primal, dual and decision kernels of every LP) "
+                             "over the tuner's timed replays; bytes from the per-kernel "
+                             "algorithmic model (primal_kernel_bytes + dual_kernel_bytes), "
+                             "V = 4"},
         "fp32_rel_kkt_max": max(kkt32),
         "baseline": {
             "kind": "plain FP64 PDHG (lr 0), one LP at a time, same GPU",
@@ -281,72 +308,90 @@ def section_batch(P, args):
 
 
 def section_serving(P, args):
+    """Open-loop Poisson arrivals through the continuous-batching server.
+
+    The first `serve_warmup` requests measure plain FP64 one-at-a-time
+    throughput (mu_plain) and warm the server up; then `serve_requests`
+    further requests arrive at rate 0.7 mu_plain and are served twice with
+    the same arrival times: by the FP32 server (continuous batching, up to
+    256 resident LPs) and by plain FP64 PDHG (lr 0) one LP at a time through
+    the same server machinery (max_active 1, first in first out). Latency
+    runs from submit to the result on the host.
+    """
     import numpy as np
     from lpgen import config_lp
     from lpgen.generators import serving_requests
-    n = args.serve_requests
+    nw, n = args.serve_warmup, args.serve_requests
     t = time.perf_counter()
-    reqs = [config_lp("cfg4", index=i) for i in range(n)]
-    log(f"[bench] serving: {n} cfg4 requests, nnz "
+    reqs = [config_lp("cfg4", index=i) for i in range(nw + n)]
+    warm, meas = reqs[:nw], reqs[nw:]
+    log(f"[bench] serving: {nw} warm-up + {n} measured cfg4 requests, nnz "
         f"{min(r.nnz for r in reqs)}..{max(r.nnz for r in reqs)} "
         f"(generated in {time.perf_counter() - t:.1f}s)")
     p32 = P.opdhg_default_params(precision=P.OPDHG_FP32, tol=1e-4, max_iter=200000,
                                  lr=args.lr, phi=args.phi, time_limit_s=600)
     p64 = P.opdhg_default_params(precision=P.OPDHG_FP64, tol=1e-4, max_iter=200000, lr=0.0,
                                  time_limit_s=600)
-    # plain FP64 one at a time: measured service time of each request
-    service, ok64 = [], 0
-    for i, lp in enumerate(reqs):
-        t0 = time.perf_counter()
-        _, _, r = P.opdhg_solve(lp, p64)
-        service.append(time.perf_counter() - t0)
-        ok64 += r.status == P.capi.OPDHG_STATUS_OPTIMAL
-    mu_plain = n / sum(service)
-    log(f"[bench] serving: FP64 one at a time: {ok64}/{n} optimal, mu {mu_plain:.2f}/s")
+    # plain FP64 one at a time on the warm-up requests: mu_plain
+    t0 = time.perf_counter()
+    for lp in warm:
+        P.opdhg_solve(lp, p64)
+    mu_plain = nw / (time.perf_counter() - t0)
     rate = 0.7 * mu_plain
     arrivals, _ = serving_requests(n, rate)
     arrivals = np.asarray(arrivals) - arrivals[0]
-    # first-in first-out single server with the measured service times
-    fin, lat64 = 0.0, []
-    for a, s in zip(arrivals, service):
-        fin = max(fin, a) + s
-        lat64.append(fin - a)
-    span64 = fin - arrivals[0]
-    # the continuous-batching server, open loop at the same arrival times
+    log(f"[bench] serving: FP64 one at a time: mu {mu_plain:.2f}/s; arrivals at {rate:.2f}/s")
     import torch
     free, _ = torch.cuda.mem_get_info()
     arena = int(min(args.serve_budget_gb * 1e9, 0.8 * free))
-    lat32, ok32 = [], 0
-    with P.Server(arena, precision=P.OPDHG_FP32, max_active=256) as srv:
-        # closed loop: everything at once
-        t0 = time.perf_counter()
-        tk = [srv.submit(lp, p32) for lp in reqs]
-        for x in tk:
-            srv.wait(x)
-        mu_srv = n / (time.perf_counter() - t0)
-        log(f"[bench] serving: server closed loop mu {mu_srv:.2f}/s")
-        # open loop
+
+    def open_loop(srv, params):
         tickets = [None] * n
         t0 = time.perf_counter()
 
         def feed():
-            for i, lp in enumerate(reqs):
+            for i, lp in enumerate(meas):
                 d = arrivals[i] - (time.perf_counter() - t0)
                 if d > 0:
                     time.sleep(d)
-                tickets[i] = srv.submit(lp, p32)
+                tickets[i] = srv.submit(lp, params)
 
         th = threading.Thread(target=feed)
         th.start()
         th.join()
+        res, lat = [], []
         for x in tickets:
-            _, _, r = srv.wait(x)
-            ok32 += r.status == P.capi.OPDHG_STATUS_OPTIMAL
-            lat32.append(srv.latency(x))
-        span32 = time.perf_counter() - t0
+            res.append(srv.wait(x)[2])
+            lat.append(srv.latency(x))
+        return res, lat, time.perf_counter() - t0
+
+    with P.Server(arena, precision=P.OPDHG_FP32, max_active=256) as srv:
+        # warm-up, closed loop: every warm-up request at once
+        t0 = time.perf_counter()
+        for x in [srv.submit(lp, p32) for lp in warm]:
+            srv.wait(x)
+        mu_srv = nw / (time.perf_counter() - t0)
+        log(f"[bench] serving: server closed loop (warm-up set) mu {mu_srv:.2f}/s")
+        res32, lat32, span32 = open_loop(srv, p32)
         st = srv.stats()
-    log(f"[bench] serving: server open loop p50 {pct(lat32, 50):.3f}s p99 {pct(lat32, 99):.3f}s; "
-        f"FIFO FP64 p50 {pct(lat64, 50):.3f}s p99 {pct(lat64, 99):.3f}s")
+    del srv
+    torch.cuda.empty_cache()  # the FP32 server's arena goes back to the device
+    ok32 = sum(r.status == P.capi.OPDHG_STATUS_OPTIMAL for r in res32)
+    log(f"[bench] serving: FP32 server: {ok32}/{n} optimal, p50 {pct(lat32, 50):.3f}s "
+        f"p99 {pct(lat32, 99):.3f}s")
+    # one LP at a time needs room for the largest request only (plus tables)
+    one = max(P.opdhg_workspace_bytes(lp, p64) for lp in meas)
+    with P.Server(min(arena, 4 * one + (256 << 20)), precision=P.OPDHG_FP64,
+                  max_active=1) as srv:
+        res64, lat64, span64 = open_loop(srv, p64)
+    del srv
+    torch.cuda.empty_cache()
+    ok64 = sum(r.status == P.capi.OPDHG_STATUS_OPTIMAL for r in res64)
+    log(f"[bench] serving: FP64 one at a time: {ok64}/{n} optimal, p50 {pct(lat64, 50):.3f}s "
+        f"p99 {pct(lat64, 99):.3f}s")
+    errs = [abs(a.primal_obj - b.primal_obj) / (1.0 + abs(b.primal_obj))
+            for a, b in zip(res32, res64)
+            if a.status == b.status == P.capi.OPDHG_STATUS_OPTIMAL]
     # preparation of the largest request, on the host and on the device
     # (session creation: validation, structure, rescaling, upload, initial products)
     big = max(reqs, key=lambda lp: lp.nnz)
@@ -355,27 +400,35 @@ def section_serving(P, args):
         q = P.opdhg_default_params(precision=P.OPDHG_FP32, prep=mode, lr=args.lr, phi=args.phi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s = P.Session(big, q)
+        sess = P.Session(big, q)
         torch.cuda.synchronize()
         prep[name] = time.perf_counter() - t0
-        s.close()
+        sess.close()
     log(f"[bench] serving: preparing the largest request ({big.nnz} nonzeros): host "
         f"{prep['host']:.3f}s, device {prep['device']:.3f}s")
     return {
-        "workload": f"cfg4: {n} requests, m log-uniform in [500, 500k], n=2.5m, "
-                    "power-law degree 4..10, Poisson arrivals",
-        "requests": n, "rate_per_s": rate, "rate_rule": "0.7 x plain FP64 throughput",
+        "workload": f"cfg4: {n} measured requests after {nw} warm-up, m log-uniform in "
+                    "[500, 500k], n=2.5m, power-law degree 4..10, Poisson arrivals",
+        "requests": n, "warmup_requests": nw, "rate_per_s": rate,
+        "rate_rule": "0.7 x plain FP64 one-at-a-time throughput on the warm-up requests",
         "arena_bytes": arena, "peak_bytes": st.peak_bytes, "dtype": "f32",
-        "optimal": ok32, "solves_per_s": ok32 / span32, "closed_loop_solves_per_s": mu_srv,
+        "optimal": ok32, "solves_per_s": ok32 / span32,
+        "closed_loop_solves_per_s_warmup": mu_srv,
         "latency_p50_s": pct(lat32, 50), "latency_p99_s": pct(lat32, 99),
+        "latency_max_s": max(lat32),
+        "fp32_vs_fp64_rel_objective_error": {
+            "compared": len(errs), "max": max(errs) if errs else None,
+            "median": pct(errs, 50), "p99": pct(errs, 99),
+            "note": "|p32 - p64| / (1 + |p64|) per request, both at rel KKT <= 1e-4"},
         "largest_request_prep_s": {"nnz": big.nnz, "host": prep["host"], "device": prep["device"],
                                    "note": "session creation; requests of 2^20 nonzeros or more "
                                            "are prepared on the device in the server runs"},
         "baseline": {
-            "kind": "plain FP64 PDHG (lr 0) served first-in first-out one at a time, same GPU "
-                    "and arrivals; latencies from the measured per-request solve times",
+            "kind": "plain FP64 PDHG (lr 0) served one LP at a time, first in first out, by the "
+                    "same server (max_active 1) at the same arrival times on the same GPU",
             "optimal": ok64, "solves_per_s": ok64 / span64, "closed_loop_solves_per_s": mu_plain,
-            "latency_p50_s": pct(lat64, 50), "latency_p99_s": pct(lat64, 99)},
+            "latency_p50_s": pct(lat64, 50), "latency_p99_s": pct(lat64, 99),
+            "latency_max_s": max(lat64)},
     }
 
 
@@ -472,32 +525,38 @@ def section_variants(P, args):
 
 
 def oracle_baseline(lp, lr: float, phi: int, seconds: float) -> dict:
-    """The FP64 oracle as it stands, single-threaded, on a bounded sample:
-    as many accepted iterations of the same LP as fit in ~`seconds`."""
+    """The FP64 oracle as it stands, single-threaded, on a bounded sample of
+    the same LP: its rescaling and start, the evaluation and first iteration
+    at k = 0, then as many further iterations as fit in ~`seconds` (no
+    evaluation falls among them), which give the rate."""
     import oracle
+    from oracle import pdhg as OP
     from oracle.params import default_params
-    # per-iteration cost from the difference of two short runs, so that the
-    # setup (rescaling, transposition) does not shorten the sample
-    runs = []
-    for k in (4, 16):
-        t0 = time.perf_counter()
-        r = oracle.solve(lp, default_params(tol=0.0, max_iter=k, lr=lr, phi=phi))
-        runs.append((r.iterations, time.perf_counter() - t0))
-    (k0, t0_), (k1, t1_) = runs
-    per_it = max((t1_ - t0_) / max(k1 - k0, 1), 1e-4)
-    setup = max(t0_ - k0 * per_it, 0.0)
-    iters = int(max(8, min(5000, (seconds - setup) / per_it)))
+    p = default_params(tol=0.0, max_iter=10**9, lr=lr, phi=phi)
     t0 = time.perf_counter()
-    r = oracle.solve(lp, default_params(tol=0.0, max_iter=iters, lr=lr, phi=phi))
+    slp = oracle.rescale(lp, p.ruiz_iters, p.pc_beta, p.l2_rescale)
+    st = OP.initial_state(slp, p)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    OP.solve_from_state(slp, st, p, stop_k=1)
+    first = time.perf_counter() - t0
+    # sized from the first iteration, which also carried the k = 0 evaluation
+    # (about three more sparse products): a plain iteration costs less
+    iters = int(max(2, min(p.eval_every - 2, seconds / max(first / 2.5, 1e-4))))
+    t0 = time.perf_counter()
+    r = OP.solve_from_state(slp, st, p, stop_k=1 + iters)
     dt = time.perf_counter() - t0
+    done = r.iterations - 1
     return {
-        "value": r.iterations / dt,
+        "value": done / dt,
         "unit": "PDHG iters/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"first {r.iterations} iterations of the same LP (FP64, single thread, "
-                  f"includes rescaling and setup), {dt:.1f} s on {cpu_model()} "
-                  f"({os.cpu_count()} logical CPUs on the host)",
+        "sample": f"iterations 2..{r.iterations} of the same LP (FP64, single thread): "
+                  f"{done} iterations in {dt:.1f} s on {cpu_model()} ({os.cpu_count()} logical "
+                  f"CPUs on the host); its rescaling and start ({setup:.1f} s) and the first "
+                  f"iteration with the k = 0 evaluation ({first:.1f} s) ran before and are not "
+                  f"in the rate",
     }
 
 
@@ -519,10 +578,15 @@ def run(args) -> dict:
         del src, dst
         log(f"[bench] copy probe: {nb} bytes device to device")
     sections = [s for s in args.sections.split(",") if s]
-    lp, shape, main = section_main(P, args)
+    lp, shape, main = section_headline(P, args)
     ker = main["kernels"]
-    dom = max(ker, key=lambda k: ker[k]["avg_launch_ms"])
-    kname = {"primal": "k_primal", "dual": "k_dual"}[dom]
+    prim = ker["primal"]
+    # one attempt moves the primal and the dual kernel's bytes once (the
+    # decision kernel reads partial sums only); the whole-step rate counts
+    # every attempt, evaluations and decisions included in the time
+    b_att = prim["bytes_per_launch"] + ker["dual"]["bytes_per_launch"]
+    att_s = main["attempts"] / main["seconds"]
+    whole = b_att * att_s / 1e9
     out = {
         "metric": METRIC,
         "value": main["iters"] / main["seconds"],
@@ -537,31 +601,38 @@ def run(args) -> dict:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "cfg1: badly scaled random LP, power-law column degree",
+            "workload": "cfg2: block-angular LP, 64 blocks of 30k x 80k (6 +-1 per column) "
+                        "+ 2k linking rows of ~2,140 N(0,1) entries",
             "m": lp.m, "n": lp.n, "nnz": lp.nnz,
             "row_len_mean": round(shape["row_len_mean"], 2), "col_len_max": shape["col_len_max"],
             "precision": "f32 A, vectors and SpMV; f64 reductions, steps and KKT",
-            "attempts_per_step": 64, "attempts_per_s": main["attempts"] / main["seconds"],
-            "tile_nnz": args.tile_nnz, "lanes": args.lanes, "workgroups": args.workgroups,
+            "slots_per_step": SLOTS_PER_STEP,
+            "attempts_per_step": main["attempts"] / args.steps,
+            "executed_fraction": main["attempts"] / (args.steps * SLOTS_PER_STEP),
+            "attempts_per_s": att_s,
+            "windows": "automatic (every A^T row and every block row of A windowed)",
             "lr": args.lr, "phi": args.phi, "normalize": True,
         },
         "roofline": {
             "bound": "hbm",
-            "achieved": ker[dom]["achieved_GBs"],
+            "achieved": prim["achieved_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": ker[dom]["frac"],
-            "traffic": counter_traffic(kname, "cfg1", "fp32"),
-            "kernel": kname,
-            "bytes_per_launch": ker[dom]["bytes_per_launch"],
-            "avg_launch_ms": ker[dom]["avg_launch_ms"],
-            "kernels": ker,
+            "frac": prim["frac"],
+            "traffic": prim.get("traffic"),
+            "kernel": "k_primal_win",
+            "bytes_per_launch": prim["bytes_per_launch"],
+            "avg_launch_ms": prim["avg_launch_ms"],
+            "sides": ker,
+            "iteration": {"bytes_per_attempt": b_att, "attempts_per_s": att_s,
+                          "achieved_GBs": whole, "frac": whole / HBM_PEAK_GBS,
+                          "note": "both sparse-product sides' algorithmic bytes per attempt x "
+                                  "attempts/s over the timed replays (decisions, evaluations "
+                                  "and launch gaps in the time)"},
         },
     }
-    if "fp64" in sections:
-        out["fp64"] = section_fp64(P, args, lp)
-    if "hbm" in sections:
-        out["hbm"] = section_hbm(P, args)
+    if "cfg1" in sections:
+        out["cfg1"] = section_cfg1(P, args)
     if "batch" in sections:
         out["batch"] = section_batch(P, args)
     if "serving" in sections:
@@ -586,10 +657,12 @@ def main():
     ap.add_argument("--tile-nnz", type=int, default=0, help="SpMV tile target (0: automatic)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per row (0: per tile)")
     ap.add_argument("--workgroups", type=int, default=0, help="workgroups per launch (0: auto)")
-    ap.add_argument("--hbm-steps", type=int, default=5)
+    ap.add_argument("--cfg1-steps", type=int, default=20)
     ap.add_argument("--batch-size", type=int, default=256)
     ap.add_argument("--batch-baseline", type=int, default=16)
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--tune-replays", type=int, default=4)
+    ap.add_argument("--serve-warmup", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--study-size", type=int, default=24)
     ap.add_argument("--study-max-iter", type=int, default=100000)
