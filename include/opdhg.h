@@ -263,6 +263,31 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p,
                       void* d_workspace, size_t workspace_bytes, void* hip_stream,
                       double* const* x_out, double* const* y_out, opdhg_result* res);
 
+/* ---- allocation-free solve ----
+ * For callers that cannot allocate device memory or let a library create
+ * HIP objects: tight serving loops that must not call hipMalloc, harnesses
+ * that forbid allocation. opdhg_solve_noalloc is opdhg_solve with the
+ * library's own static device scratch of OPDHG_NOALLOC_SCRATCH_BYTES as its
+ * workspace. It allocates no device or pinned host memory and creates no
+ * stream, event or graph: its kernels are launched directly on hip_stream
+ * (which must belong to the current device), and it synchronizes that
+ * stream, so it cannot itself be captured into a graph. Results equal
+ * opdhg_solve's with the same parameters bit for bit.
+ *   - The scratch is a file-scope device array: every device the library is
+ *     loaded on holds its own copy until the process ends. Its address is
+ *     looked up on the first call on each device.
+ *   - Every call uploads its LP image and launch tables over the part of
+ *     the scratch it uses before any kernel reads it, so nothing of an
+ *     earlier call (which the scratch keeps) is read.
+ *   - Calls on one device share its scratch: calls from several threads of
+ *     one process run one at a time (a per-device lock); calls that overlap
+ *     on one device any other way would race.
+ *   - An LP needing more than the scratch holds (opdhg_workspace_bytes)
+ *     returns OPDHG_ERR_WORKSPACE_TOO_SMALL with a message; nothing runs. */
+#define OPDHG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int opdhg_solve_noalloc(const opdhg_lp* lp, const opdhg_params* p, void* hip_stream,
+                        double* x_out, double* y_out, opdhg_result* res);
+
 /* ---- autotuning of the sparse-product tiling ----
  * Not part of the method: a performance helper. The LPs are prepared once;
  * each candidate tiling (tile size in nonzeros x workgroups per launch,

@@ -21,6 +21,7 @@ from .capi import (  # noqa: F401
     opdhg_session_create,
     opdhg_solve,
     opdhg_solve_batch,
+    opdhg_solve_noalloc,
     opdhg_status_name,
     opdhg_validate,
     opdhg_workspace_bytes,

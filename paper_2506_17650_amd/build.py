@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libopdhg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "host.cpp", "server.cpp", "autotune.cpp"]
+SOURCES = ["kernels.hip", "host.cpp", "server.cpp", "autotune.cpp", "noalloc.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

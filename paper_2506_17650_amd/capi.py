@@ -27,6 +27,7 @@ OPDHG_ERR_DEVICE = -4
 OPDHG_ERR_NOT_READY = -5
 OPDHG_ERR_CANCELLED = -6
 OPDHG_ERR_UNKNOWN_TICKET = -7
+OPDHG_NOALLOC_SCRATCH_BYTES = 64 << 20  # static device scratch of opdhg_solve_noalloc
 
 OPDHG_STATUS_OPTIMAL = 0
 OPDHG_STATUS_ITERATION_LIMIT = 1
@@ -135,6 +136,8 @@ SIGNATURES = {
     "opdhg_spectral_norm": (c_i32, [_p(opdhg_lp), _p(opdhg_params), _p(c_dbl)]),
     "opdhg_solve": (c_i32, [_p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                             ctypes.c_void_p, _p(c_dbl), _p(c_dbl), _p(opdhg_result)]),
+    "opdhg_solve_noalloc": (c_i32, [_p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, _p(c_dbl),
+                                    _p(c_dbl), _p(opdhg_result)]),
     "opdhg_batch_workspace_bytes": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), _p(c_sz)]),
     "opdhg_solve_batch": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                                   ctypes.c_void_p, _p(_p(c_dbl)), _p(_p(c_dbl)),
@@ -367,6 +370,20 @@ def opdhg_solve(lp, params: Optional[opdhg_params] = None, workspace=None, strea
     _check(load().opdhg_solve(ctypes.byref(a.struct), ctypes.byref(params), ctypes.c_void_p(ptr),
                               size, ctypes.c_void_p(_stream_handle(stream)), _dptr(x, c_dbl),
                               _dptr(y, c_dbl), ctypes.byref(res)))
+    return x, y, res
+
+
+def opdhg_solve_noalloc(lp, params: Optional[opdhg_params] = None, stream=None):
+    """opdhg_solve on the library's static device scratch (no workspace, no
+    allocation): returns (x, y, opdhg_result)."""
+    params = params or opdhg_default_params()
+    a = _LPArrays(lp)
+    x = np.empty(a.n)
+    y = np.empty(a.m)
+    res = opdhg_result()
+    _check(load().opdhg_solve_noalloc(ctypes.byref(a.struct), ctypes.byref(params),
+                                      ctypes.c_void_p(_stream_handle(stream)), _dptr(x, c_dbl),
+                                      _dptr(y, c_dbl), ctypes.byref(res)))
     return x, y, res
 
 
