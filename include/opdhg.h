@@ -158,6 +158,10 @@ typedef struct opdhg_params {
   int32_t window_buckets; /* LDS window per pass in buckets of 1024 entries, 1..26; 0: 26 */
   int32_t window_rows;   /* rows per windowed chunk, 1..10240; 0: picked from the side's size */
   int32_t prep;          /* OPDHG_PREP_*: rescaling passes and scaled data on the host or device */
+  int32_t eval_slots;    /* attempt slots between the guarded evaluation steps inside a launch
+                            sequence (an LP that becomes due mid-sequence waits at most this
+                            many slots); 0: automatic; < 0: none (only the evaluation that opens
+                            each sequence). Results do not depend on it. */
 } opdhg_params;
 
 typedef struct opdhg_result {
@@ -293,10 +297,16 @@ int opdhg_solve_noalloc(const opdhg_lp* lp, const opdhg_params* p, void* hip_str
  * each candidate tiling (tile size in nonzeros x workgroups per launch,
  * lanes per row picked per tile) is uploaded, captured and timed over
  * `replays` launch sequences (64 step attempts each) with the LPs kept
- * running. The fastest candidate by step attempts per second, summed over
- * the set, is returned; pass its fields as tile_nnz, lanes and workgroups
- * of opdhg_params. In FP64 every tiling gives identical results; in FP32
- * results move only by rounding. The workspace is overwritten. */
+ * running. In FP32 with automatic windows, the best tiling is timed once
+ * more with windowed chunks of up to 10240 rows wherever they stage at
+ * most half of their matrix bytes (OPDHG_WINDOWS_ALWAYS): LDS-staged
+ * gathers instead of one gather per nonzero from global memory. The
+ * fastest candidate by step attempts per second, summed over the set, is
+ * returned; pass its fields as tile_nnz, lanes, workgroups, windows and
+ * window_rows of opdhg_params (each LP then equals its solo solve with the
+ * same parameters bit for bit). In FP64 every tiling gives identical
+ * results; in FP32 results move only by rounding. The workspace is
+ * overwritten. */
 typedef struct opdhg_tuning {
   int32_t tile_nnz;       /* chosen tile size (nonzeros) */
   int32_t lanes;          /* chosen lanes per row (0: per tile) */
@@ -306,6 +316,8 @@ typedef struct opdhg_tuning {
   double default_attempts_per_s; /* measured for the automatic tiling */
   double executed_fraction; /* chosen tiling: attempts run / step-attempt slots launched (the
                                slots an LP leaves idle while an evaluation is due) */
+  int32_t windows;        /* chosen OPDHG_WINDOWS_* (the parameters' own unless windows won) */
+  int32_t window_rows;    /* chosen window_rows */
 } opdhg_tuning;
 
 /* Workspace bytes opdhg_autotune needs for these LPs (the largest

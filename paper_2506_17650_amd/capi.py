@@ -79,7 +79,7 @@ class opdhg_params(ctypes.Structure):
         ("step_rule", c_i32), ("restart_scheme", c_i32), ("l2_rescale", c_i32),
         ("power_iters", c_i32), ("step_scale", c_dbl), ("power_tol", c_dbl),
         ("step_norm", c_i32), ("windows", c_i32), ("window_buckets", c_i32),
-        ("window_rows", c_i32), ("prep", c_i32),
+        ("window_rows", c_i32), ("prep", c_i32), ("eval_slots", c_i32),
     ]
 
 
@@ -123,7 +123,7 @@ class opdhg_tuning(ctypes.Structure):
     _fields_ = [
         ("tile_nnz", c_i32), ("lanes", c_i32), ("workgroups", c_i32), ("candidates", c_i32),
         ("attempts_per_s", c_dbl), ("default_attempts_per_s", c_dbl),
-        ("executed_fraction", c_dbl),
+        ("executed_fraction", c_dbl), ("windows", c_i32), ("window_rows", c_i32),
     ]
 
 
@@ -426,6 +426,7 @@ def opdhg_autotune(lps: Sequence, params: Optional[opdhg_params] = None, replays
                                  ctypes.byref(out)))
     tuned = copy.copy(params)
     tuned.tile_nnz, tuned.lanes, tuned.workgroups = out.tile_nnz, out.lanes, out.workgroups
+    tuned.windows, tuned.window_rows = out.windows, out.window_rows
     return out, tuned
 
 

@@ -10,10 +10,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <limits>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "opdhg.h"
@@ -53,6 +55,19 @@ size_t set_bytes(const std::vector<Prepared>& P, int prec, int64_t wg_cap) {
   return total + tables_bytes(preps, wg_cap);
 }
 
+// Whether the windowed candidate is tried: FP32 with automatic windows.
+bool try_windows(const opdhg_params* p) {
+  return p->precision == OPDHG_FP32 && p->windows == OPDHG_WINDOWS_AUTO;
+}
+
+// The parameters of the windowed candidate.
+opdhg_params windowed(const opdhg_params* p) {
+  opdhg_params q = *p;
+  q.windows = OPDHG_WINDOWS_ALWAYS;
+  q.window_rows = kWinRows;
+  return q;
+}
+
 // Prepares every LP with parameters that keep it running while timed.
 int prepare_set(int count, const opdhg_lp* lps, const opdhg_params* p, std::vector<Prepared>& P) {
   opdhg_params q = *p;
@@ -60,11 +75,27 @@ int prepare_set(int count, const opdhg_lp* lps, const opdhg_params* p, std::vect
   q.max_iter = std::numeric_limits<int64_t>::max() / 4;
   q.time_limit_s = 1e30;
   P.assign(count, Prepared());
-  for (int i = 0; i < count; ++i) {
-    int rc = validate_lp(&lps[i]);
-    if (!rc) rc = prepare(&lps[i], &q, P[i], false);
-    if (rc) return rc;
-  }
+  // the LPs are independent: up to 16 host threads take them in turn
+  std::vector<int> rcs(count, OPDHG_OK);
+  std::vector<std::string> msgs(count);
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (int i = next++; i < count; i = next++) {
+      int rc = validate_lp(&lps[i]);
+      if (!rc) rc = prepare(&lps[i], &q, P[i], false);
+      if (rc) {
+        rcs[i] = rc;
+        msgs[i] = opdhg_last_error();
+      }
+    }
+  };
+  const int nth = std::max(1, std::min({count, host_threads(), 16}));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < count; ++i)
+    if (rcs[i]) return fail(rcs[i], "LP " + std::to_string(i) + ": " + msgs[i]);
   return OPDHG_OK;
 }
 
@@ -79,13 +110,14 @@ size_t max_bytes(std::vector<Prepared>& P, int prec) {
 
 // Attempts per second of the set under one candidate: upload, capture,
 // one warm-up replay, then `replays` timed replays.
-int time_candidate(std::vector<Prepared>& P, int prec, const Candidate& cand, uint8_t* ws,
-                   void* stream, int replays, double* rate, double* executed) {
+int time_candidate(std::vector<Prepared>& P, int prec, int mid_every, const Candidate& cand,
+                   uint8_t* ws, void* stream, int replays, double* rate, double* executed) {
   const int count = (int)P.size();
   for (Prepared& q : P) retile(q, cand.tile_nnz, cand.lanes);
   Group grp;
   int rc = grp.init(stream, prec);
   if (rc) return rc;
+  grp.mid_every = mid_every;
   std::vector<LpDev> lpd(count);
   std::vector<const Prepared*> preps(count);
   SlotImage img;
@@ -148,6 +180,11 @@ int opdhg_autotune_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_p
     prepare(&lps[i], p, P[i], true);
   }
   *bytes = max_bytes(P, p->precision);
+  if (try_windows(p)) {
+    const opdhg_params q = windowed(p);
+    for (int i = 0; i < count; ++i) prepare(&lps[i], &q, P[i], true);
+    *bytes = std::max(*bytes, max_bytes(P, p->precision));
+  }
   return OPDHG_OK;
 }
 
@@ -157,17 +194,25 @@ int opdhg_autotune(int count, const opdhg_lp* lps, const opdhg_params* p, void* 
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
   int rc = validate_params(p);
   if (rc) return rc;
-  std::vector<Prepared> P;
+  std::vector<Prepared> P, PW;
   if ((rc = prepare_set(count, lps, p, P))) return rc;
-  const size_t need = max_bytes(P, p->precision);
+  size_t need = max_bytes(P, p->precision);
+  const opdhg_params pw = windowed(p);
+  if (try_windows(p)) {
+    if ((rc = prepare_set(count, lps, &pw, PW))) return rc;
+    need = std::max(need, max_bytes(PW, p->precision));
+  }
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(need) + " bytes");
   std::memset(out, 0, sizeof(*out));
+  out->windows = p->windows;
+  out->window_rows = p->window_rows;
   double best = -1.0;
   for (const Candidate& c : kCandidates) {
     double rate = 0.0, executed = 0.0;
-    if ((rc = time_candidate(P, p->precision, c, static_cast<uint8_t*>(d_workspace), hip_stream,
-                             replays, &rate, &executed)))
+    if ((rc = time_candidate(P, p->precision, mid_eval_every(p, count), c,
+                             static_cast<uint8_t*>(d_workspace), hip_stream, replays, &rate,
+                             &executed)))
       return rc;
     if (c.tile_nnz == kTileCap && c.lanes == 0 && c.workgroups == kGridCap)
       out->default_attempts_per_s = rate;
@@ -178,6 +223,22 @@ int opdhg_autotune(int count, const opdhg_lp* lps, const opdhg_params* p, void* 
       out->workgroups = c.workgroups;
       out->attempts_per_s = rate;
       out->executed_fraction = executed;
+    }
+    ++out->candidates;
+  }
+  if (try_windows(p)) {
+    // the best tiling once more, with windowed chunks wherever they pay
+    const Candidate c{out->tile_nnz, out->lanes, out->workgroups};
+    double rate = 0.0, executed = 0.0;
+    if ((rc = time_candidate(PW, p->precision, mid_eval_every(&pw, count), c,
+                             static_cast<uint8_t*>(d_workspace), hip_stream, replays, &rate,
+                             &executed)))
+      return rc;
+    if (rate > best) {
+      out->attempts_per_s = rate;
+      out->executed_fraction = executed;
+      out->windows = pw.windows;
+      out->window_rows = pw.window_rows;
     }
     ++out->candidates;
   }

@@ -45,6 +45,10 @@ int fail_hip(hipError_t e, const char* what) {
 // validation
 // ---------------------------------------------------------------------------
 
+// f(r0, r1) on row ranges of about equal nonzeros, on up to 16 host threads
+template <typename F>
+static void parallel_rows(const int64_t* ptr, int64_t rows, F&& f);
+
 int validate_lp(const opdhg_lp* lp) {
   if (!lp) return fail(OPDHG_ERR_INVALID_ARGUMENT, "lp is NULL");
   const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
@@ -65,20 +69,46 @@ int validate_lp(const opdhg_lp* lp) {
     if (lp->row_ptr[i + 1] < lp->row_ptr[i])
       return fail(OPDHG_ERR_INVALID_ARGUMENT, "row_ptr must be nondecreasing");
   if (lp->row_ptr[m] != nnz) return fail(OPDHG_ERR_INVALID_ARGUMENT, "row_ptr[m] must equal nnz");
-  std::vector<int64_t> seen(static_cast<size_t>(n), -1);
-  for (int64_t i = 0; i < m; ++i) {
-    for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
-      const int32_t j = lp->col_idx[k];
-      if (j < 0 || j >= n) return fail(OPDHG_ERR_INVALID_ARGUMENT, "column index out of range");
-      if (seen[j] == i) return fail(OPDHG_ERR_INVALID_ARGUMENT, "duplicate (row, column) entry");
-      seen[j] = i;
-      if (!std::isfinite(lp->val[k]))
-        return fail(OPDHG_ERR_INVALID_ARGUMENT, "A has a non-finite entry");
+  // The entries, by row ranges on up to 16 threads. A row whose columns
+  // ascend has no duplicate; another row's columns are sorted in a copy.
+  // Each range reports its first bad row; the first over all ranges wins,
+  // so the message is the one a serial pass would give.
+  static const char* const kWhy[] = {"", "column index out of range",
+                                     "duplicate (row, column) entry",
+                                     "A has a non-finite entry", "b must be finite",
+                                     "row sense must be 0 or 1"};
+  std::mutex mu;
+  int64_t bad_row = m;
+  int bad_why = 0;
+  parallel_rows(lp->row_ptr, m, [&](int64_t r0, int64_t r1) {
+    std::vector<int32_t> cols;
+    for (int64_t i = r0; i < r1; ++i) {
+      int why = 0;
+      bool ascending = true;
+      for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1] && !why; ++k) {
+        const int32_t j = lp->col_idx[k];
+        if (j < 0 || j >= n) why = 1;
+        else if (!std::isfinite(lp->val[k])) why = 3;
+        else if (k > lp->row_ptr[i] && j <= lp->col_idx[k - 1]) ascending = false;
+      }
+      if (!why && !ascending) {
+        cols.assign(lp->col_idx + lp->row_ptr[i], lp->col_idx + lp->row_ptr[i + 1]);
+        std::sort(cols.begin(), cols.end());
+        if (std::adjacent_find(cols.begin(), cols.end()) != cols.end()) why = 2;
+      }
+      if (!why && !std::isfinite(lp->b[i])) why = 4;
+      if (!why && lp->row_sense[i] != 0 && lp->row_sense[i] != 1) why = 5;
+      if (why) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (i < bad_row) {
+          bad_row = i;
+          bad_why = why;
+        }
+        return;
+      }
     }
-    if (!std::isfinite(lp->b[i])) return fail(OPDHG_ERR_INVALID_ARGUMENT, "b must be finite");
-    if (lp->row_sense[i] != 0 && lp->row_sense[i] != 1)
-      return fail(OPDHG_ERR_INVALID_ARGUMENT, "row sense must be 0 or 1");
-  }
+  });
+  if (bad_why) return fail(OPDHG_ERR_INVALID_ARGUMENT, kWhy[bad_why]);
   for (int64_t j = 0; j < n; ++j) {
     if (!std::isfinite(lp->c[j])) return fail(OPDHG_ERR_INVALID_ARGUMENT, "c must be finite");
     const double l = lp->l[j], u = lp->u[j];
@@ -725,45 +755,84 @@ static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t
       }
   }
   // entries of each pass of each chunk: its own rows in order, then its
-  // segments in order; padded to whole kWinNpt groups
-  std::vector<int32_t> bpass(nb, -1), boff(nb, 0);
-  for (int64_t c = 0; c < nch; ++c) {
-    for (const Slot& x : slots[c]) {
-      bpass[x.bucket] = x.pass;
-      boff[x.bucket] = x.off;
-    }
-    const int64_t a = W.r0[c], b = W.r1[c];
-    for (int q = 0; q < W.npass[c]; ++q) {
-      WinPass& ps = W.passes[W.pass0[c] + q];
-      ps.e0 = (int32_t)W.col.size();
-      uint16_t last_col = 0, last_row = 0;
-      auto emit = [&](int64_t k, int64_t local) {
-        const int64_t bk = ci[k] / kWinBucket;
-        last_col = (uint16_t)(boff[bk] + (ci[k] - bk * kWinBucket));
-        last_row = (uint16_t)local;
-        W.col.push_back(last_col);
-        W.row.push_back(last_row);
-        W.src.push_back(k);
-      };
-      for (int64_t r = a; r < b; ++r)
-        for (int64_t k = rp[r]; k < rp[r + 1]; ++k)
-          if (bpass[ci[k] / kWinBucket] == q) emit(k, r - a);
-      for (const auto& e : seg_entries[c])
-        if (bpass[ci[e.first] / kWinBucket] == q) emit(e.first, e.second);
-      if (W.col.size() == (size_t)ps.e0) {  // a pass with no entry keeps one zero entry
-        W.col.push_back(0);
-        W.row.push_back(0);
-        W.src.push_back(-1);
+  // segments in order; padded to whole kWinNpt groups. The chunks are
+  // independent, so they are spread over up to 16 host threads: each chunk
+  // first counts its entries per pass, the passes' ranges follow in chunk
+  // order, and then every chunk writes its own ranges, entry for entry as
+  // one serial pass over the chunks would.
+  auto for_chunks = [&](auto&& f) {
+    std::atomic<int64_t> next{0};
+    auto work = [&] {
+      std::vector<int32_t> bpass(nb, -1), boff(nb, 0);
+      for (int64_t c = next++; c < nch; c = next++) {
+        for (const Slot& x : slots[c]) {
+          bpass[x.bucket] = x.pass;
+          boff[x.bucket] = x.off;
+        }
+        f(c, bpass, boff);
+        for (const Slot& x : slots[c]) bpass[x.bucket] = -1;
       }
-      while ((W.col.size() - ps.e0) % kWinNpt) {
-        W.col.push_back(last_col);
-        W.row.push_back(last_row);
-        W.src.push_back(-1);
-      }
-      ps.e1 = (int32_t)W.col.size();
-    }
-    for (const Slot& x : slots[c]) bpass[x.bucket] = -1;
+    };
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(host_threads(), 16), nch));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+  };
+  std::vector<int64_t> pass_cnt(W.passes.size(), 0);
+  for_chunks([&](int64_t c, const std::vector<int32_t>& bpass, const std::vector<int32_t>&) {
+    int64_t* cnt = pass_cnt.data() + W.pass0[c];
+    for (int64_t r = W.r0[c]; r < W.r1[c]; ++r)
+      for (int64_t k = rp[r]; k < rp[r + 1]; ++k) ++cnt[bpass[ci[k] / kWinBucket]];
+    for (const auto& e : seg_entries[c]) ++cnt[bpass[ci[e.first] / kWinBucket]];
+  });
+  int64_t total = 0;
+  for (size_t q = 0; q < W.passes.size(); ++q) {
+    // a pass with no entry keeps one zero entry
+    const int64_t len = std::max<int64_t>(pass_cnt[q], 1);
+    W.passes[q].e0 = (int32_t)total;
+    total += (len + kWinNpt - 1) / kWinNpt * kWinNpt;
+    W.passes[q].e1 = (int32_t)total;
   }
+  W.col.resize(total);
+  W.row.resize(total);
+  W.src.resize(total);
+  for_chunks([&](int64_t c, const std::vector<int32_t>& bpass, const std::vector<int32_t>& boff) {
+    // one scan of the chunk's entries, each to the cursor of its pass: own
+    // rows in order, then segments in order, within every pass
+    const int64_t a = W.r0[c], b = W.r1[c];
+    int64_t pos[kWinMaxPass];
+    uint16_t last_col[kWinMaxPass] = {}, last_row[kWinMaxPass] = {};
+    for (int q = 0; q < W.npass[c]; ++q) pos[q] = W.passes[W.pass0[c] + q].e0;
+    auto emit = [&](int64_t k, int64_t local) {
+      const int64_t bk = ci[k] / kWinBucket;
+      const int q = bpass[bk];
+      last_col[q] = (uint16_t)(boff[bk] + (ci[k] - bk * kWinBucket));
+      last_row[q] = (uint16_t)local;
+      W.col[pos[q]] = last_col[q];
+      W.row[pos[q]] = last_row[q];
+      W.src[pos[q]] = k;
+      ++pos[q];
+    };
+    for (int64_t r = a; r < b; ++r)
+      for (int64_t k = rp[r]; k < rp[r + 1]; ++k) emit(k, r - a);
+    for (const auto& e : seg_entries[c]) emit(e.first, e.second);
+    for (int q = 0; q < W.npass[c]; ++q) {
+      const WinPass& ps = W.passes[W.pass0[c] + q];
+      int64_t p = pos[q];
+      if (p == ps.e0) {  // the zero entry of an empty pass
+        W.col[p] = 0;
+        W.row[p] = 0;
+        W.src[p] = -1;
+        ++p;
+      }
+      for (; p < ps.e1; ++p) {
+        W.col[p] = last_col[q];
+        W.row[p] = last_row[q];
+        W.src[p] = -1;
+      }
+    }
+  });
 }
 
 // Every index a windowed kernel derives from the plan stays in its
@@ -894,128 +963,16 @@ static std::vector<double> step_factor_table(double reduction, double growth) {
   return cache.emplace(std::make_pair(kr, kg), std::move(t)).first->second;
 }
 
-int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool structure_only) {
-  out.m = lp->m;
-  out.n = lp->n;
-  out.nnz = lp->nnz;
-  const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
-  // device-side preparation: the rescaling and the scaled data on the GPU
-  out.dprep = p->step_rule != OPDHG_STEP_CONSTANT &&
-              (p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz));
-  // A full preparation needs the column index anyway: it is built first
-  // and gives the column counts; sizing alone counts the columns.
-  ColIndex C;
-  bool have_index = false;
-  if (!structure_only) {
-    build_col_index(lp, C, !out.dprep);
-    have_index = true;
-  }
-  // row lengths of A and of A^T (= column counts), device order by class
-  std::vector<int64_t> len_a(m), len_t(n, 0);
-  for (int64_t i = 0; i < m; ++i) len_a[i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
-  if (have_index) {
-    for (int64_t j = 0; j < n; ++j) len_t[j] = C.cstart[j + 1] - C.cstart[j];
-  } else {
-    column_counts(lp, len_t);
-  }
-  class_order(len_a, out.perm_a, out.cend_a);
-  class_order(len_t, out.perm_t, out.cend_t);
-  out.rp_a.assign(m + 1, 0);
-  for (int64_t i = 0; i < m; ++i) out.rp_a[i + 1] = out.rp_a[i] + (int32_t)len_a[out.perm_a[i]];
-  out.rp_t.assign(n + 1, 0);
-  for (int64_t j = 0; j < n; ++j) out.rp_t[j + 1] = out.rp_t[j] + (int32_t)len_t[out.perm_t[j]];
-  const int64_t cap = p->tile_nnz > 0 ? std::min<int64_t>(p->tile_nnz, kTileCap) : kTileCap;
-  out.tiles_a = build_tiles(out.rp_a.data(), m, cap, p->lanes);
-  out.tiles_t = build_tiles(out.rp_t.data(), n, cap, p->lanes);
-  // windowed chunks need the device-order column indices, also for sizing;
-  // automatic windows only where a sample of chunks shows column locality
-  bool windows = p->precision == OPDHG_FP32 && p->windows != OPDHG_WINDOWS_OFF;
-  const int per_pass = p->window_buckets > 0 ? p->window_buckets : kWinBuckets;
-  if (windows && p->windows == OPDHG_WINDOWS_AUTO) {
-    std::vector<int32_t> inv(n);
-    for (int64_t j = 0; j < n; ++j) inv[out.perm_t[j]] = (int32_t)j;
-    windows = windows_worth_planning(lp, out, inv, window_chunk_rows(p, m - out.cend_a[0]),
-                                     per_pass);
-  }
-  out.prep_ruiz = p->ruiz_iters;
-  out.prep_l2 = p->l2_rescale != 0;
-  out.prep_beta = p->pc_beta;
-  if (structure_only && !windows) {
-    out.stiles_a = out.tiles_a;
-    out.stiles_t = out.tiles_t;
-    return OPDHG_OK;
-  }
-
-  std::vector<int32_t> inv_a(m), inv_t(n);
-  for (int64_t i = 0; i < m; ++i) inv_a[out.perm_a[i]] = (int32_t)i;
-  for (int64_t j = 0; j < n; ++j) inv_t[out.perm_t[j]] = (int32_t)j;
-  std::vector<double> sval;
-  if (!have_index) build_col_index(lp, C, !out.dprep);
-  double spec = -1.0;
-  if (!structure_only && !out.dprep) {
-    rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, out.dr, out.dc);
-    if (p->step_rule == OPDHG_STEP_CONSTANT)
-      spec = spectral_norm_with(lp, C, sval, p->power_iters, p->power_tol);
-  }
-  // values go to the device order: scaled on the host, or unscaled (raw)
-  // for the device-side preparation
-  const bool vals = !structure_only;
-  const double* vsrc = out.dprep ? lp->val : sval.data();
-  // A in device order: row i' is original row perm_a[i'], columns relabelled
-  out.ci_a.resize(nnz);
-  HostArray<double>& dst_a = out.dprep ? out.raw_a : out.va_a;
-  HostArray<double>& dst_t = out.dprep ? out.raw_t : out.va_t;
-  if (vals) dst_a.resize(nnz);
-  {
-    std::vector<int64_t> dptr(m + 1);  // nonzero offsets in device order, for balancing
-    for (int64_t i2 = 0; i2 <= m; ++i2) dptr[i2] = out.rp_a[i2];
-    parallel_rows(dptr.data(), m, [&](int64_t r0, int64_t r1) {
-      for (int64_t i2 = r0; i2 < r1; ++i2) {
-        const int64_t i = out.perm_a[i2];
-        int64_t pos = out.rp_a[i2];
-        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k, ++pos) {
-          out.ci_a[pos] = inv_t[lp->col_idx[k]];
-          if (vals) dst_a[pos] = vsrc[k];
-        }
-      }
-    });
-  }
-  // A^T in device order: row j' is original column perm_t[j']; entries in
-  // ascending original row, labelled with device row indices
-  out.ci_t.resize(nnz);
-  if (vals) dst_t.resize(nnz);
-  {
-    std::vector<int64_t> dptr(n + 1);
-    for (int64_t j2 = 0; j2 <= n; ++j2) dptr[j2] = out.rp_t[j2];
-    parallel_rows(dptr.data(), n, [&](int64_t r0, int64_t r1) {
-      for (int64_t j2 = r0; j2 < r1; ++j2) {
-        const int64_t j = out.perm_t[j2];
-        int64_t pos = out.rp_t[j2];
-        for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q, ++pos) {
-          out.ci_t[pos] = inv_a[C.crow[q]];
-          if (vals) dst_t[pos] = vsrc[C.cpos[q]];
-        }
-      }
-    });
-  }
-  // windowed chunks of both sides (rows of the long class stay in tiles):
-  // A^T rows gather y (m entries), A rows gather x' (n entries)
-  out.win_t = WinPlan();
-  out.win_a = WinPlan();
-  if (windows) {
-    plan_windows(out.rp_t, out.ci_t, m, out.cend_t[0], n, out.cend_t[0],
-                 window_chunk_rows(p, n - out.cend_t[0]), per_pass, out.win_t);
-    plan_windows(out.rp_a, out.ci_a, n, out.cend_a[0], m, out.cend_a[0],
-                 window_chunk_rows(p, m - out.cend_a[0]), per_pass, out.win_a);
-    if (!plan_ok(out.win_t, n, m) || !plan_ok(out.win_a, m, n))
-      return fail(OPDHG_ERR_DEVICE, "internal error: inconsistent window plan");
-    if (p->windows == OPDHG_WINDOWS_AUTO) {
-      if ((int64_t)out.win_t.chunks() < kWinMinChunks) out.win_t = WinPlan();
-      if ((int64_t)out.win_a.chunks() < kWinMinChunks) out.win_a = WinPlan();
-    }
-  }
-  step_tiles(out, cap, p->lanes);
-  if (structure_only) return OPDHG_OK;
+// The rest of a full preparation, after the structure: the vectors in
+// device order (unscaled for the device-side preparation, scaled here
+// otherwise), the first step size and primal weight (host side), and the
+// per-LP constants. sval: the scaled values (host side); spec: the
+// estimate of |A~|_2 for the constant step (host side).
+static int prepare_finish(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, double spec,
+                          const std::vector<double>* sval_p) {
+  const int64_t m = out.m, n = out.n, nnz = out.nnz;
+  static const std::vector<double> kNone;
+  const std::vector<double>& sval = sval_p ? *sval_p : kNone;
   if (out.dprep) {
     // unscaled vectors in device order; the device scales them
     out.raw_b.resize(m);
@@ -1101,6 +1058,152 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
             (p->restart_scheme == OPDHG_RESTART_NONE ? kNoRestart : 0) |
             (p->step_norm == OPDHG_STEP_NORM_PRECOND ? kWeightedStep : 0);
   return OPDHG_OK;
+}
+
+int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool structure_only) {
+  out.m = lp->m;
+  out.n = lp->n;
+  out.nnz = lp->nnz;
+  const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
+  // device-side preparation: the rescaling and the scaled data on the GPU
+  out.dprep = p->step_rule != OPDHG_STEP_CONSTANT &&
+              (p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz));
+  // A full host preparation needs the column index anyway: it is built
+  // first and gives the column counts; sizing alone, and the device-side
+  // preparation (which may build the structure on the device), count the
+  // columns.
+  ColIndex C;
+  bool have_index = false;
+  if (!structure_only && !out.dprep) {
+    build_col_index(lp, C, true);
+    have_index = true;
+  }
+  // row lengths of A and of A^T (= column counts), device order by class
+  std::vector<int64_t> len_a(m), len_t(n, 0);
+  for (int64_t i = 0; i < m; ++i) len_a[i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
+  if (have_index) {
+    for (int64_t j = 0; j < n; ++j) len_t[j] = C.cstart[j + 1] - C.cstart[j];
+  } else {
+    column_counts(lp, len_t);
+  }
+  class_order(len_a, out.perm_a, out.cend_a);
+  class_order(len_t, out.perm_t, out.cend_t);
+  out.rp_a.assign(m + 1, 0);
+  for (int64_t i = 0; i < m; ++i) out.rp_a[i + 1] = out.rp_a[i] + (int32_t)len_a[out.perm_a[i]];
+  out.rp_t.assign(n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) out.rp_t[j + 1] = out.rp_t[j] + (int32_t)len_t[out.perm_t[j]];
+  const int64_t cap = p->tile_nnz > 0 ? std::min<int64_t>(p->tile_nnz, kTileCap) : kTileCap;
+  out.tiles_a = build_tiles(out.rp_a.data(), m, cap, p->lanes);
+  out.tiles_t = build_tiles(out.rp_t.data(), n, cap, p->lanes);
+  // windowed chunks need the device-order column indices, also for sizing;
+  // automatic windows only where a sample of chunks shows column locality
+  bool windows = p->precision == OPDHG_FP32 && p->windows != OPDHG_WINDOWS_OFF;
+  const int per_pass = p->window_buckets > 0 ? p->window_buckets : kWinBuckets;
+  if (windows && p->windows == OPDHG_WINDOWS_AUTO) {
+    std::vector<int32_t> inv(n);
+    for (int64_t j = 0; j < n; ++j) inv[out.perm_t[j]] = (int32_t)j;
+    windows = windows_worth_planning(lp, out, inv, window_chunk_rows(p, m - out.cend_a[0]),
+                                     per_pass);
+  }
+  out.prep_ruiz = p->ruiz_iters;
+  out.prep_l2 = p->l2_rescale != 0;
+  out.prep_beta = p->pc_beta;
+  // device-side structure: with the device preparation and no windowed
+  // chunks (whose planning needs the structure on the host), when every
+  // column fits the device's per-column ordering
+  int64_t max_col = 0;
+  for (int64_t j = 0; j < n; ++j) max_col = std::max(max_col, len_t[j]);
+  out.dstruct = out.dprep && !windows && nnz > 0 && max_col <= kStructMaxCol;
+  if (structure_only && !windows) {
+    out.stiles_a = out.tiles_a;
+    out.stiles_t = out.tiles_t;
+    return OPDHG_OK;
+  }
+
+  std::vector<int32_t> inv_a(m), inv_t(n);
+  for (int64_t i = 0; i < m; ++i) inv_a[out.perm_a[i]] = (int32_t)i;
+  for (int64_t j = 0; j < n; ++j) inv_t[out.perm_t[j]] = (int32_t)j;
+  if (out.dstruct) {
+    // the device builds both CSR copies from the caller's arrays
+    out.h_rp = lp->row_ptr;
+    out.h_ci = lp->col_idx;
+    out.h_val = lp->val;
+    out.inv_a = std::move(inv_a);
+    out.inv_t = std::move(inv_t);
+    out.win_t = WinPlan();
+    out.win_a = WinPlan();
+    step_tiles(out, cap, p->lanes);
+    if (structure_only) return OPDHG_OK;
+    return prepare_finish(lp, p, out, 0.0, nullptr);
+  }
+  std::vector<double> sval;
+  if (!have_index) build_col_index(lp, C, !out.dprep);
+  double spec = -1.0;
+  if (!structure_only && !out.dprep) {
+    rescale_with(lp, C, p->ruiz_iters, p->l2_rescale != 0, p->pc_beta, sval, out.dr, out.dc);
+    if (p->step_rule == OPDHG_STEP_CONSTANT)
+      spec = spectral_norm_with(lp, C, sval, p->power_iters, p->power_tol);
+  }
+  // values go to the device order: scaled on the host, or unscaled (raw)
+  // for the device-side preparation
+  const bool vals = !structure_only;
+  const double* vsrc = out.dprep ? lp->val : sval.data();
+  // A in device order: row i' is original row perm_a[i'], columns relabelled
+  out.ci_a.resize(nnz);
+  HostArray<double>& dst_a = out.dprep ? out.raw_a : out.va_a;
+  HostArray<double>& dst_t = out.dprep ? out.raw_t : out.va_t;
+  if (vals) dst_a.resize(nnz);
+  {
+    std::vector<int64_t> dptr(m + 1);  // nonzero offsets in device order, for balancing
+    for (int64_t i2 = 0; i2 <= m; ++i2) dptr[i2] = out.rp_a[i2];
+    parallel_rows(dptr.data(), m, [&](int64_t r0, int64_t r1) {
+      for (int64_t i2 = r0; i2 < r1; ++i2) {
+        const int64_t i = out.perm_a[i2];
+        int64_t pos = out.rp_a[i2];
+        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k, ++pos) {
+          out.ci_a[pos] = inv_t[lp->col_idx[k]];
+          if (vals) dst_a[pos] = vsrc[k];
+        }
+      }
+    });
+  }
+  // A^T in device order: row j' is original column perm_t[j']; entries in
+  // ascending original row, labelled with device row indices
+  out.ci_t.resize(nnz);
+  if (vals) dst_t.resize(nnz);
+  {
+    std::vector<int64_t> dptr(n + 1);
+    for (int64_t j2 = 0; j2 <= n; ++j2) dptr[j2] = out.rp_t[j2];
+    parallel_rows(dptr.data(), n, [&](int64_t r0, int64_t r1) {
+      for (int64_t j2 = r0; j2 < r1; ++j2) {
+        const int64_t j = out.perm_t[j2];
+        int64_t pos = out.rp_t[j2];
+        for (int64_t q = C.cstart[j]; q < C.cstart[j + 1]; ++q, ++pos) {
+          out.ci_t[pos] = inv_a[C.crow[q]];
+          if (vals) dst_t[pos] = vsrc[C.cpos[q]];
+        }
+      }
+    });
+  }
+  // windowed chunks of both sides (rows of the long class stay in tiles):
+  // A^T rows gather y (m entries), A rows gather x' (n entries)
+  out.win_t = WinPlan();
+  out.win_a = WinPlan();
+  if (windows) {
+    plan_windows(out.rp_t, out.ci_t, m, out.cend_t[0], n, out.cend_t[0],
+                 window_chunk_rows(p, n - out.cend_t[0]), per_pass, out.win_t);
+    plan_windows(out.rp_a, out.ci_a, n, out.cend_a[0], m, out.cend_a[0],
+                 window_chunk_rows(p, m - out.cend_a[0]), per_pass, out.win_a);
+    if (!plan_ok(out.win_t, n, m) || !plan_ok(out.win_a, m, n))
+      return fail(OPDHG_ERR_DEVICE, "internal error: inconsistent window plan");
+    if (p->windows == OPDHG_WINDOWS_AUTO) {
+      if ((int64_t)out.win_t.chunks() < kWinMinChunks) out.win_t = WinPlan();
+      if ((int64_t)out.win_a.chunks() < kWinMinChunks) out.win_a = WinPlan();
+    }
+  }
+  step_tiles(out, cap, p->lanes);
+  if (structure_only) return OPDHG_OK;
+  return prepare_finish(lp, p, out, spec, &sval);
 }
 
 // Device-order vector back to the caller's order, scaled by `scale`
@@ -1191,6 +1294,19 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
     L.pscr = take(8 * (4 * kPrepGrid + 3));
     if (P.win_t.chunks()) L.wsrc_t = take(4 * P.win_t.src.size());
     if (P.win_a.chunks()) L.wsrc_a = take(4 * P.win_a.src.size());
+  }
+  if (P.dstruct) {
+    L.st_perm_a = take(4 * m);
+    L.st_inv_a = take(4 * m);
+    L.st_inv_t = take(4 * n);
+    L.st_cur = take(4 * n);
+    // the caller's arrays and the entries' places last: the host image
+    // skips them (and the CSR copies the device builds)
+    L.st_rp = take(8 * (m + 1));
+    L.st_ci = take(4 * nnz);
+    L.st_val = take(8 * nnz);
+    L.st_ti = take(4 * nnz);
+    L.st_tk = take(4 * nnz);
   }
   L.total = off;
   return L;
@@ -1292,13 +1408,25 @@ Ctl initial_ctl(const Prepared& P) {
   return c;
 }
 
+// Byte ranges of a slot that the host image fills and uploads: the whole
+// slot, or with the device-side structure everything but the CSR copies
+// and their values (built on the device) and the staging of the caller's
+// arrays (uploaded from them directly).
+static std::vector<std::pair<size_t, size_t>> image_ranges(const SlotLayout& L, const Prepared& P) {
+  if (!P.dstruct) return {{0, L.total}};
+  return {{0, L.ci_a}, {L.rp_t, L.ci_t}, {L.vn[0], L.raw_a}, {L.raw_b, L.st_rp}};
+}
+
 // Host image of a slot: every byte the device needs at the start.
 template <typename V>
 void slot_image(const SlotLayout& L, const Prepared& P, SlotImage& img) {
-  // every byte starts at zero; the threads that zero the pages touch them
+  // every byte that goes up starts at zero; the threads that zero the pages
+  // touch them (with the device-side structure only the ranges that go up)
   img.resize(L.total);
-  parallel_pieces(L.total, size_t(1) << 22,
-                  [&](size_t a, size_t b) { std::memset(img.data() + a, 0, b - a); });
+  for (const auto& r : image_ranges(L, P))
+    parallel_pieces(r.second - r.first, size_t(1) << 22, [&](size_t a, size_t b) {
+      std::memset(img.data() + r.first + a, 0, b - a);
+    });
   const Ctl c = initial_ctl(P);
   std::memcpy(img.data() + L.ctl, &c, sizeof(c));
   std::memcpy(img.data() + L.prm, &P.prm, sizeof(DevParams));
@@ -1307,7 +1435,15 @@ void slot_image(const SlotLayout& L, const Prepared& P, SlotImage& img) {
   std::memcpy(img.data() + L.pow_tab, P.pow_tab.data(), sizeof(double) * P.pow_tab.size());
   std::memcpy(img.data() + L.rp_a, P.rp_a.data(), 4 * P.rp_a.size());
   std::memcpy(img.data() + L.rp_t, P.rp_t.data(), 4 * P.rp_t.size());
-  // the nonzero-sized arrays, one thread each
+  if (P.dstruct) {
+    std::memcpy(img.data() + L.st_perm_a, P.perm_a.data(), 4 * P.perm_a.size());
+    std::memcpy(img.data() + L.st_inv_a, P.inv_a.data(), 4 * P.inv_a.size());
+    std::memcpy(img.data() + L.st_inv_t, P.inv_t.data(), 4 * P.inv_t.size());
+    std::memcpy(img.data() + L.st_cur, P.rp_t.data(), 4 * P.n);  // A^T rows fill from their starts
+  }
+  // the nonzero-sized arrays, one thread each (the device builds them from
+  // the caller's arrays with the device-side structure)
+  if (!P.dstruct)
   run_tasks({[&] { std::memcpy(img.data() + L.ci_a, P.ci_a.data(), 4 * P.ci_a.size()); },
              [&] { std::memcpy(img.data() + L.ci_t, P.ci_t.data(), 4 * P.ci_t.size()); },
              [&] { put_vec<V>(img, L.va_a, P.va_a); },
@@ -1382,6 +1518,11 @@ template void slot_image<float>(const SlotLayout&, const Prepared&, SlotImage&);
 // a group of LPs launched together (one LP, a batch, or the server's mix)
 // ---------------------------------------------------------------------------
 
+int mid_eval_every(const opdhg_params* p, int64_t nlps) {
+  if (p->eval_slots != 0) return p->eval_slots > 0 ? p->eval_slots : 0;
+  return nlps > 1 ? kMidEvalEveryShared : kMidEvalEvery;
+}
+
 int Group::enqueue(hipStream_t s, int attempts) {
   int rc = 0;
   auto K = [&](auto tag) {
@@ -1390,11 +1531,11 @@ int Group::enqueue(hipStream_t s, int attempts) {
       rc |= Kernels<V>::eval_t(cfg, s, mid);
       rc |= Kernels<V>::eval_a(cfg, s, mid);
       rc |= Kernels<V>::eval_decide(cfg, s, mid);
-      rc |= Kernels<V>::apply(cfg, s);
+      rc |= Kernels<V>::apply(cfg, s, mid);
     };
     evaluation(0);
-    for (int a = 0; a < attempts; ++a) {
-      if (a > 0 && a % kMidEvalEvery == 0) evaluation(1);
+    for (int a = 0, b = 0; a < attempts; ++a) {
+      if (a > 0 && mid_every > 0 && a % mid_every == 0) evaluation(++b);
       rc |= launch_side(true, 0, s);
       rc |= launch_side(false, 0, s);
       rc |= Kernels<V>::decide(cfg, s);
@@ -1784,7 +1925,7 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
   if (!gt.empty()) std::memcpy(staging.data() + o_gt, gt.data(), sizeof(SegItem) * gt.size());
   if (!ga.empty()) std::memcpy(staging.data() + o_ga, ga.data(), sizeof(SegItem) * ga.size());
   Counts cn{(int32_t)n_t, (int32_t)n_a, (int32_t)lps.size(), 0,
-            cfg->grid_t, cfg->chunk_t, cfg->grid_a, cfg->chunk_a};
+            cfg->grid_t, cfg->chunk_t, cfg->grid_a, cfg->chunk_a, {0, 0}, {0, 0}};
   std::memcpy(staging.data() + o_cn, &cn, sizeof(cn));
   HIP_TRY(hipMemcpyAsync(dst, staging.data(), upload, hipMemcpyHostToDevice, stream));
   cfg->lps = reinterpret_cast<const LpDev*>(dst + o_lps);
@@ -1887,11 +2028,49 @@ static int device_prepare(uint8_t* base, const SlotLayout& L, Prepared& P, int p
   return OPDHG_OK;
 }
 
+// Both CSR copies in device order, built on the device from the caller's
+// arrays (already uploaded to the slot's staging).
+static int device_structure(uint8_t* base, const SlotLayout& L, const Prepared& P,
+                            hipStream_t stream) {
+  StructCfg c{};
+  c.src_rp = reinterpret_cast<const int64_t*>(base + L.st_rp);
+  c.src_ci = reinterpret_cast<const int32_t*>(base + L.st_ci);
+  c.src_val = reinterpret_cast<const double*>(base + L.st_val);
+  c.perm_a = reinterpret_cast<const int32_t*>(base + L.st_perm_a);
+  c.inv_a = reinterpret_cast<const int32_t*>(base + L.st_inv_a);
+  c.inv_t = reinterpret_cast<const int32_t*>(base + L.st_inv_t);
+  c.rp_a = reinterpret_cast<const int32_t*>(base + L.rp_a);
+  c.rp_t = reinterpret_cast<const int32_t*>(base + L.rp_t);
+  c.cur = reinterpret_cast<int32_t*>(base + L.st_cur);
+  c.tmp_i = reinterpret_cast<int32_t*>(base + L.st_ti);
+  c.tmp_k = reinterpret_cast<int32_t*>(base + L.st_tk);
+  c.ci_a = reinterpret_cast<int32_t*>(base + L.ci_a);
+  c.raw_a = reinterpret_cast<double*>(base + L.raw_a);
+  c.ci_t = reinterpret_cast<int32_t*>(base + L.ci_t);
+  c.raw_t = reinterpret_cast<double*>(base + L.raw_t);
+  c.m = (int32_t)P.m;
+  c.n = (int32_t)P.n;
+  c.nlong_a = (int32_t)P.cend_a[0];
+  c.nmed_t = (int32_t)P.cend_t[1];
+  if (struct_build(c, stream))
+    return fail(OPDHG_ERR_DEVICE, std::string("structure kernels: ") + device_error_string());
+  return OPDHG_OK;
+}
+
 int upload_slot(uint8_t* base, const SlotLayout& L, Prepared& P, int prec, hipStream_t stream,
                 SlotImage& img) {
   if (prec == OPDHG_FP32) slot_image<float>(L, P, img);
   else slot_image<double>(L, P, img);
-  HIP_TRY(hipMemcpyAsync(base, img.data(), L.total, hipMemcpyHostToDevice, stream));
+  for (const auto& r : image_ranges(L, P))
+    HIP_TRY(hipMemcpyAsync(base + r.first, img.data() + r.first, r.second - r.first,
+                           hipMemcpyHostToDevice, stream));
+  if (P.dstruct) {
+    HIP_TRY(hipMemcpyAsync(base + L.st_rp, P.h_rp, 8 * (P.m + 1), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(base + L.st_ci, P.h_ci, 4 * P.nnz, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(base + L.st_val, P.h_val, 8 * P.nnz, hipMemcpyHostToDevice, stream));
+    int rc = device_structure(base, L, P, stream);
+    if (rc) return rc;
+  }
   if (P.dprep) return device_prepare(base, L, P, prec, stream);
   return OPDHG_OK;
 }
@@ -2053,6 +2232,7 @@ void opdhg_default_params(opdhg_params* p) {
   p->window_buckets = 0;
   p->window_rows = 0;
   p->prep = OPDHG_PREP_AUTO;
+  p->eval_slots = 0;
 }
 
 int opdhg_validate(const opdhg_lp* lp) { return validate_lp(lp); }
@@ -2126,6 +2306,7 @@ int session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
   S.time_limit = p->time_limit_s;
   S.direct = direct;
   if ((rc = S.grp.init(hip_stream, p->precision, direct))) return rc;
+  S.grp.mid_every = mid_eval_every(p, 1);
   SlotImage img;
   if ((rc = upload_slot(S.ws, S.L, S.P, p->precision, S.grp.stream, img))) return rc;
   S.lpd = slot_pointers(S.ws, S.L, S.P);
@@ -2324,14 +2505,32 @@ int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_para
   if (rc) return rc;
   const opdhg_params pb = batch_params(count, lps, p_in);
   const opdhg_params* p = &pb;
+  // the LPs' structures are sized on up to 16 host threads
+  std::vector<Prepared> P(count);
+  std::vector<int> rcs(count, OPDHG_OK);
+  std::vector<std::string> msgs(count);
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (int i = next++; i < count; i = next++) {
+      int r = validate_lp(&lps[i]);
+      if (!r) r = prepare(&lps[i], p, P[i], true);
+      if (r) {
+        rcs[i] = r;
+        msgs[i] = opdhg_last_error();
+      }
+    }
+  };
+  const int nth = std::max(1, std::min({count, host_threads(), 16}));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
   size_t total = 0;
   ListSizes z;
   for (int i = 0; i < count; ++i) {
-    if ((rc = validate_lp(&lps[i]))) return rc;
-    Prepared P;
-    prepare(&lps[i], p, P, true);
-    total += slot_layout(P, p->precision).total;
-    z.add(P);
+    if (rcs[i]) return fail(rcs[i], "LP " + std::to_string(i) + ": " + msgs[i]);
+    total += slot_layout(P[i], p->precision).total;
+    z.add(P[i]);
   }
   *bytes = total + tables_bytes(z, grid_cap(p));
   return OPDHG_OK;
@@ -2384,6 +2583,7 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p_in,
   uint8_t* ws = static_cast<uint8_t*>(d_workspace);
   Group grp;
   if ((rc = grp.init(hip_stream, p->precision))) return rc;
+  grp.mid_every = mid_eval_every(p, count);
   std::vector<LpDev> lpd(count);
   {
     // The slots are filled and copied by several threads, each with its own

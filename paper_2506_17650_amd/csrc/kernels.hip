@@ -712,7 +712,8 @@ __device__ __forceinline__ int64_t mod_count(int64_t k, int32_t d) {
   return k <= (int64_t)INT32_MAX ? (int64_t)((uint32_t)k % (uint32_t)d) : k % d;
 }
 
-__device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
+// Returns whether the decision made an evaluation due.
+__device__ bool decide_step(Ctl& c, const StepIn& in, const double* s) {
   const double dx2 = s[0], g2 = s[1], gp2 = s[2];
   const double dy2 = s[3], inter = fabs(s[4]), r2 = s[5], gd2 = s[6];
   c.attempts = in.attempts + 1;
@@ -721,11 +722,9 @@ __device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
   auto fail = [&]() {
     c.fail_pending = 1;
     c.need_eval = 1;
+    return true;
   };
-  if (!(isfinite(dx2) && isfinite(dy2) && isfinite(inter))) {
-    fail();
-    return;
-  }
+  if (!(isfinite(dx2) && isfinite(dy2) && isfinite(inter))) return fail();
   const double eta = in.eta, om = in.omega;
   const double movement = 0.5 * om * dx2 + 0.5 * dy2 / om;
   const double eta_bar = inter > 0.0 ? movement / inter : INFINITY;
@@ -766,13 +765,17 @@ __device__ void decide_step(Ctl& c, const StepIn& in, const double* s) {
       }
     }
     c.learn_now = (in.lr > 0.0 && mod_count(k1, in.phi) == 0) ? 1 : 0;
-    if (mod_count(k1, in.eval_every) == 0 || k1 >= in.max_iter) c.need_eval = 1;
-  } else {
-    const int64_t r1 = in.retries + 1;
-    c.eta = eta_next;
-    c.retries = r1;
-    if (r1 > in.max_retries || !(eta_next > 0.0 && isfinite(eta_next))) fail();
+    if (mod_count(k1, in.eval_every) == 0 || k1 >= in.max_iter) {
+      c.need_eval = 1;
+      return true;
+    }
+    return false;
   }
+  const int64_t r1 = in.retries + 1;
+  c.eta = eta_next;
+  c.retries = r1;
+  if (r1 > in.max_retries || !(eta_next > 0.0 && isfinite(eta_next))) return fail();
+  return false;
 }
 
 __device__ __forceinline__ double wkkt(double rp2, double rd2, double gap, double om) {
@@ -1902,8 +1905,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     r = r < 0 ? 0 : (r >= kPowRing ? kPowRing - 1 : r);
     in.f_red = lane_value(rv_red, (int)r);
     in.f_gro = lane_value(rv_gro, (int)r);
-    if (status == kRunning && need == 0 && in.k < k_limit && threadIdx.x == 0)
-      decide_step(*d.ctl, in, sv);
+    if (status == kRunning && need == 0 && in.k < k_limit && threadIdx.x == 0) {
+      if (decide_step(*d.ctl, in, sv)) {
+        // the guarded evaluation steps ahead look for due LPs again
+        const gptr<Counts> cn = gp(const_cast<Counts*>(cfg.counts));
+        cn->hint[0] = 1;
+        cn->hint[1] = 1;
+      }
+    }
     li += gridDim.x;
     if (li < nlps) {
       __syncthreads();  // s_red is reused by the next LP
@@ -1952,10 +1961,21 @@ __device__ __forceinline__ void reduced_cost(double q, int8_t bf, double& lam, d
   rd = q - lam;
 }
 
+// Entry of an evaluation kernel. Step `mid` of a launch sequence (0: the
+// evaluation opening it, which always looks at every LP; b > 0: the b-th
+// guarded step inside it) returns at once when its hint word is clear; the
+// first kernel of each step (clear_next) clears the next step's word.
+__device__ __forceinline__ bool eval_step_skips(const LaunchCfg& cfg, int mid, bool clear_next) {
+  const gptr<Counts> cn = gp(const_cast<Counts*>(cfg.counts));
+  if (clear_next && blockIdx.x == 0 && threadIdx.x == 0) cn->hint[(mid + 1) & 1] = 0;
+  return mid != 0 && uni(cn->hint[mid & 1]) == 0;
+}
+
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg, int mid) {
   __shared__ SpmvShared<V, 2> sh;
   __shared__ DD s_red[4 * 2 * kEvT];
+  if (eval_step_skips(cfg, mid, true)) return;
   DD p[2 * kEvT];
   dd_reset(p);
   const SideChunks sc = side_chunks(cfg.counts, true);
@@ -2022,6 +2042,7 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg, int mid) {
   __shared__ SpmvShared<V, 1> sh;
   __shared__ DD s_red[4 * 2 * kEvA];
+  if (eval_step_skips(cfg, mid, false)) return;
   DD p[2 * kEvA];
   dd_reset(p);
   const SideChunks sc = side_chunks(cfg.counts, false);
@@ -2082,10 +2103,12 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg, int mid) {
 
 // One workgroup per LP: termination and restart decision of an evaluation.
 // The evaluation that opens a launch sequence (mid == 0) also fills the
-// step-rule factor ring for the sequence; the guarded ones inside it leave
-// the ring alone (it already covers every attempt of the sequence).
+// step-rule factor ring for the sequence; the guarded ones inside it
+// (mid = 1, 2, ...) leave the ring alone (it already covers every attempt
+// of the sequence).
 __global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg, int mid) {
   __shared__ DD s_red[4 * 2 * kEvT];
+  if (eval_step_skips(cfg, mid, false)) return;
   const int nlps = cfg.counts->nlps;
   for (int li = blockIdx.x; li < nlps; li += gridDim.x) {
     const LpDev& lp = cfg.lps[li];
@@ -2135,7 +2158,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_decide(LaunchCfg cfg, int mid) 
 // a launch sequence, the guarded ones included, is followed by at least one
 // attempt slot before the next).
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_apply(LaunchCfg cfg) {
+__global__ __launch_bounds__(kBlock) void k_apply(LaunchCfg cfg, int mid) {
+  if (eval_step_skips(cfg, mid, false)) return;
   auto body = [&](const WorkItem& it, bool tside) {
     const Ctl* c = it.ctl;
     const bool restart = c->restart_pending != 0;
@@ -2313,6 +2337,82 @@ __global__ __launch_bounds__(kBlock) void k_prep_apply(PrepCfg a) {
     else {
       const int j = q - a.m;
       a.dc[j] = a.dc[j] / sqrt(a.sc[j] == 0.0 ? 1.0 : a.sc[j]);
+    }
+  }
+}
+
+// ---- device-side structure ----
+
+// Rows of A to device order; each entry also to its A^T row's cursor. A
+// wave per row of more than 256 entries (the first rows in device order),
+// a thread per row for the rest.
+__global__ __launch_bounds__(kBlock) void k_struct_rows(StructCfg a) {
+  auto entry = [&](int i, int64_t k, int d) {
+    const int j2 = a.inv_t[a.src_ci[k]];
+    a.ci_a[d] = j2;
+    a.raw_a[d] = a.src_val[k];
+    const int q = atomicAdd(&a.cur[j2], 1);
+    a.tmp_i[q] = i;
+    a.tmp_k[q] = (int)k;
+  };
+  const int lane = threadIdx.x & 63;
+  const int w0 = (blockIdx.x * kBlock + threadIdx.x) >> 6, nw = gridDim.x * (kBlock / 64);
+  for (int i2 = w0; i2 < a.nlong_a; i2 += nw) {
+    const int i = a.perm_a[i2];
+    const int64_t s = a.src_rp[i], e = a.src_rp[i + 1];
+    for (int64_t k = s + lane; k < e; k += 64) entry(i, k, a.rp_a[i2] + (int)(k - s));
+  }
+  const int t0 = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
+  for (int i2 = a.nlong_a + t0; i2 < a.m; i2 += nt) {
+    const int i = a.perm_a[i2];
+    const int64_t s = a.src_rp[i], e = a.src_rp[i + 1];
+    const int d0 = a.rp_a[i2];
+    for (int64_t k = s; k < e; ++k) entry(i, k, d0 + (int)(k - s));
+  }
+}
+
+// Each A^T row in ascending original row: an entry's place is its rank
+// among the row's original rows (distinct: A has no duplicate entry). A
+// wave per row of more than 32 entries (first in device order), with the
+// row's original rows in LDS; a thread per row for the rest.
+__global__ __launch_bounds__(kBlock) void k_struct_cols(StructCfg a) {
+  __shared__ int32_t s_rows[kBlock / 64][kStructMaxCol];
+  auto place = [&](int s, int p, int ip, int rank) {
+    const int d = s + rank;
+    a.ci_t[d] = a.inv_a[ip];
+    a.raw_t[d] = a.src_val[a.tmp_k[p]];
+  };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w0 = blockIdx.x * (kBlock / 64) + wave, nw = gridDim.x * (kBlock / 64);
+  int32_t* rows = s_rows[wave];
+  for (int j2 = w0; j2 < a.nmed_t; j2 += nw) {
+    const int s = a.rp_t[j2];
+    const int L = min(a.rp_t[j2 + 1] - s, kStructMaxCol);  // the host checked L <= kStructMaxCol
+    for (int p = lane; p < L; p += 64) rows[p] = a.tmp_i[s + p];
+    // the wave's LDS writes before its reads (DS instructions of one wave
+    // complete in order; the fences keep the compiler from moving them)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    for (int p = lane; p < L; p += 64) {
+      const int ip = rows[p];
+      int rank = 0;
+      for (int q = 0; q < L; ++q) rank += rows[q] < ip ? 1 : 0;
+      place(s, s + p, ip, rank);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
+  for (int j2 = a.nmed_t + blockIdx.x * kBlock + threadIdx.x; j2 < a.n; j2 += gridDim.x * kBlock) {
+    const int s = a.rp_t[j2], e = a.rp_t[j2 + 1];
+    for (int p = s; p < e; ++p) {
+      const int ip = a.tmp_i[p];
+      int rank = 0;
+      for (int q = s; q < e; ++q) rank += a.tmp_i[q] < ip ? 1 : 0;
+      place(s, p, ip, rank);
     }
   }
 }
@@ -2513,8 +2613,8 @@ int Kernels<V>::eval_decide(const LaunchCfg& c, void* stream, int mid) {
   OPDHG_LAUNCH(k_eval_decide, c.launch_lp, c, mid);
 }
 template <typename V>
-int Kernels<V>::apply(const LaunchCfg& c, void* stream) {
-  OPDHG_LAUNCH(k_apply<V>, c.launch_ta, c);
+int Kernels<V>::apply(const LaunchCfg& c, void* stream, int mid) {
+  OPDHG_LAUNCH(k_apply<V>, c.launch_ta, c, mid);
 }
 
 int launch_board(const LaunchCfg& c, void* stream) { OPDHG_LAUNCH(k_board, c.launch_lp, c); }
@@ -2524,6 +2624,15 @@ int prep_stats(const PrepCfg& c, void* stream, bool tside, int kind, double e) {
   const int grid = std::max(1, std::min(4096, (rows + kBlock - 1) / kBlock));
   hipLaunchKernelGGL(k_prep_stats, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, c,
                      tside ? 1 : 0, kind, e);
+  return launched();
+}
+
+int struct_build(const StructCfg& c, void* stream) {
+  const int g1 = std::max(1, std::min(4096, (c.m + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_struct_rows, dim3(g1), dim3(kBlock), 0, (hipStream_t)stream, c);
+  if (launched()) return -1;
+  const int g2 = std::max(1, std::min(4096, (c.n + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_struct_cols, dim3(g2), dim3(kBlock), 0, (hipStream_t)stream, c);
   return launched();
 }
 

@@ -64,8 +64,8 @@ struct WinPlan {
   std::vector<int32_t> nseg, seg0;  // per chunk: segments after its rows, first segment id
   std::vector<WinPass> passes;
   std::vector<WinRange> ranges;
-  std::vector<uint16_t> col, row;
-  std::vector<int64_t> src;
+  HostArray<uint16_t> col, row;  // filled by the planning threads (not zeroed first)
+  HostArray<int64_t> src;
   // long rows split into segments: the rows (device order), and per row the
   // ids of its segments' partials in chunk order (CSR over srow)
   std::vector<int32_t> srow, sptr, sids;
@@ -109,6 +109,14 @@ struct Prepared {
   double prep_beta = -1.0;
   HostArray<double> raw_a, raw_t;
   std::vector<double> raw_b, raw_c, raw_l, raw_u;
+  // device-side structure (with dprep, no windows): both CSR copies are
+  // built on the device from the caller's arrays, which must stay valid
+  // until the slot is uploaded; the host keeps lengths, orders and tiles
+  bool dstruct = false;
+  const int64_t* h_rp = nullptr;
+  const int32_t* h_ci = nullptr;
+  const double* h_val = nullptr;
+  std::vector<int32_t> inv_a, inv_t;
   // partial slots per side: evaluation tiles, or step tiles plus windowed chunks
   int64_t part_stride_t() const {
     return (int64_t)std::max(tiles_t.size(),
@@ -138,6 +146,10 @@ struct SlotLayout {
   // device-side preparation (0 when the host prepares)
   size_t raw_a = 0, raw_t = 0, raw_b = 0, raw_c = 0, raw_l = 0, raw_u = 0, sr = 0, sc = 0;
   size_t pscr = 0, wsrc_t = 0, wsrc_a = 0;
+  // device-side structure (0 when the host builds it): the caller's CSR,
+  // the orders, the fill cursors and the entries' places
+  size_t st_rp = 0, st_perm_a = 0, st_inv_a = 0, st_inv_t = 0, st_cur = 0, st_ci = 0,
+         st_val = 0, st_ti = 0, st_tk = 0;
   size_t total = 0;
 };
 
@@ -182,15 +194,21 @@ void unpermute(const double* dev, const std::vector<int32_t>& perm, const double
                double* out);
 Ctl initial_ctl(const Prepared& P);
 
-// Attempt slots between the guarded evaluations inside a launch sequence.
-constexpr int kMidEvalEvery = 16;
+// Attempt slots between the guarded evaluation steps inside a launch
+// sequence, by default: every 8 slots for one LP, every 4 for a set of
+// several (each LP of a set reaches its evaluation points at its own
+// times). mid_eval_every() resolves opdhg_params::eval_slots.
+constexpr int kMidEvalEvery = 8;
+constexpr int kMidEvalEveryShared = 4;
+int mid_eval_every(const opdhg_params* p, int64_t nlps);
 
 // A set of LPs launched together, with its captured launch sequence: one
 // evaluation step, then `attempts` step attempts with a guarded evaluation
-// step after every kMidEvalEvery of them. An LP whose iteration count
-// reaches an evaluation point inside the sequence (after a rejected attempt,
-// say) is evaluated there and goes on within kMidEvalEvery slots, instead of
-// waiting for the next sequence.
+// step after every mid_every of them (none when mid_every <= 0). An LP
+// whose iteration count reaches an evaluation point inside the sequence
+// (after a rejected attempt, say) is evaluated there and goes on within
+// mid_every slots, instead of waiting for the next sequence. A guarded step
+// in which no LP is due returns after one load per kernel (Counts::hint).
 //
 // Direct mode (for callers that cannot let the library create HIP objects):
 // no captured graph, no streams or events of the library's own; each replay
@@ -207,6 +225,7 @@ struct Group {
   int prec = 0;
   bool direct = false;
   int seq_attempts = 0;  // attempts per sequence (direct mode)
+  int mid_every = kMidEvalEvery;
   int init(void* stream, int prec, bool direct = false);
   int launch_side(bool primal, int force, hipStream_t s);
   // enqueue one launch sequence (evaluation, attempts, board) on s

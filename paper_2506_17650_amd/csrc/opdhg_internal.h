@@ -254,6 +254,13 @@ struct Counts {
   int32_t nwork_t, nwork_a, nlps, pad;
   int32_t grid_t, chunk_t;  // chunks (a multiple of 8 when above 8) and items per chunk
   int32_t grid_a, chunk_a;
+  // Hints for the guarded evaluation steps inside a launch sequence (a
+  // performance hint only: the evaluation that opens each sequence ignores
+  // them). The step decision sets both words when it makes an evaluation
+  // due; guarded step b reads word b & 1 and returns at once when it is 0;
+  // step b clears word (b + 1) & 1, the next step's, at its start.
+  int32_t hint[2];
+  int32_t pad2[2];
 };
 
 // Host-side launch wrappers (kernels.hip). V is float or double.
@@ -318,11 +325,12 @@ struct Kernels {
   static int dual_seg(const LaunchCfg& c, void* stream, int force = 0);
   static int decide(const LaunchCfg& c, void* stream);
   static int learn_flush(const LaunchCfg& c, void* stream);
-  // mid: a guarded evaluation inside a launch sequence (see k_eval_decide)
+  // mid: 0 for the evaluation opening a launch sequence, b > 0 for the b-th
+  // guarded evaluation step inside it (see Counts::hint)
   static int eval_t(const LaunchCfg& c, void* stream, int mid);
   static int eval_a(const LaunchCfg& c, void* stream, int mid);
   static int eval_decide(const LaunchCfg& c, void* stream, int mid);
-  static int apply(const LaunchCfg& c, void* stream);
+  static int apply(const LaunchCfg& c, void* stream, int mid);
 };
 
 // Copies every LP's Ctl into c.board (precision independent).
@@ -367,6 +375,38 @@ struct PrepCfg {
   int32_t m, n;
   int32_t nlong_a, nlong_t;  // rows of more than 256 nonzeros (the first in device order)
 };
+// Device-side structure of one slot (the host keeps only the row and
+// column lengths, the row-class orders and the tiles): the caller's CSR
+// goes up as given, and two kernels build both copies in device order.
+// k_struct_rows copies each row of A to device order (columns relabelled)
+// and drops every entry into its A^T row at a fill cursor; k_struct_cols
+// then puts each A^T row in ascending original row order by rank, the
+// order of the host's column index, so both copies equal the host's bit
+// for bit. Columns are at most kStructMaxCol long (else the host builds the
+// structure).
+constexpr int kStructMaxCol = 4096;
+struct StructCfg {
+  const int64_t* src_rp;   // m + 1, the caller's row pointers
+  const int32_t* src_ci;   // nnz, the caller's column indices
+  const double* src_val;   // nnz, the caller's values
+  const int32_t* perm_a;   // device row -> original row (m)
+  const int32_t* inv_a;    // original row -> device row (m)
+  const int32_t* inv_t;    // original column -> device column (n)
+  const int32_t* rp_a;     // device order row pointers of A (m + 1)
+  const int32_t* rp_t;     // and of A^T (n + 1)
+  int32_t* cur;            // n fill cursors, starting at rp_t[j]
+  int32_t* tmp_i;          // nnz: original row of each entry at its cursor position
+  int32_t* tmp_k;          // nnz: its position in the caller's arrays
+  int32_t* ci_a;
+  double* raw_a;
+  int32_t* ci_t;
+  double* raw_t;
+  int32_t m, n;
+  int32_t nlong_a;  // rows of A longer than 256 (first in device order)
+  int32_t nmed_t;   // rows of A^T longer than 32 (first in device order)
+};
+int struct_build(const StructCfg& c, void* stream);
+
 // kind 0: maxima of |a~|, 1: sums of |a~|^e, 2: L2 norms
 int prep_stats(const PrepCfg& c, void* stream, bool tside, int kind, double e);
 int prep_apply(const PrepCfg& c, void* stream);  // dr /= sqrt(sr), dc /= sqrt(sc)

@@ -284,9 +284,11 @@ void ServerImpl::prep_loop() {
         msg = "LP has more tiles than the launch tables hold";
       }
     }
-    release_vec(j->rp);
-    release_vec(j->ci);
-    release_vec(j->va);
+    if (!j->P.dstruct) {  // else the device builds the structure from them at admission
+      release_vec(j->rp);
+      release_vec(j->ci);
+      release_vec(j->va);
+    }
     release_vec(j->b);
     release_vec(j->c);
     release_vec(j->l);
@@ -313,8 +315,16 @@ int ServerImpl::admit(Job& j) {
   int rc = upload_slot(base, j.L, j.P, cfg.precision, s_h2d, img);
   if (rc) return rc;
   j.lpd = slot_pointers(base, j.L, j.P);
-  // the staging image must outlive the copy
+  // the staging image (and the LP's own arrays) must outlive the copy
   HIP_TRY(hipStreamSynchronize(s_h2d));
+  if (j.P.dstruct) {
+    release_vec(j.rp);
+    release_vec(j.ci);
+    release_vec(j.va);
+    j.P.h_rp = nullptr;
+    j.P.h_ci = nullptr;
+    j.P.h_val = nullptr;
+  }
   LaunchCfg own{};
   std::vector<uint8_t> staging;
   int64_t nwt = 0, nwa = 0;
@@ -352,7 +362,8 @@ int ServerImpl::write_shared() {
   if ((int64_t)wt.size() > tab.cap_wt || (int64_t)wa.size() > tab.cap_wa ||
       (int64_t)lps.size() > tab.cap_lps)
     return fail(OPDHG_ERR_OVER_BUDGET, "launch tables overflow");
-  Counts cn{(int32_t)items_t, (int32_t)items_a, (int32_t)lps.size(), 0, gt, ct, ga, ca};
+  Counts cn{(int32_t)items_t, (int32_t)items_a, (int32_t)lps.size(), 0, gt, ct, ga, ca,
+            {1, 1}, {0, 0}};  // a changed set: let the next guarded evaluations look
   if (!lps.empty())
     HIP_TRY(hipMemcpyAsync(tab.base + tab.o_lps, lps.data(), sizeof(LpDev) * lps.size(),
                            hipMemcpyHostToDevice, s_comp));
@@ -616,7 +627,7 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
   L.launch_t = L.launch_a = L.launch_ta = g8;
   L.launch_lp = std::min(cfg->max_active, kGridCap);
   // an empty set until the first admission
-  const Counts cn{0, 0, 0, 0, 0, 1, 0, 1};
+  const Counts cn{0, 0, 0, 0, 0, 1, 0, 1, {0, 0}, {0, 0}};
   if (hipMemcpyAsync((void*)L.counts, &cn, sizeof(cn), hipMemcpyHostToDevice, S.s_comp) !=
           hipSuccess ||
       hipStreamSynchronize(S.s_comp) != hipSuccess) {
@@ -624,6 +635,8 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
     S.grp.release();
     return nullptr;
   }
+  // the server's mix holds several LPs at once (or will)
+  S.grp.mid_every = cfg->max_active > 1 ? kMidEvalEveryShared : kMidEvalEvery;
   if (S.grp.capture(cfg->attempts_per_replay)) {
     S.grp.release();
     return nullptr;

@@ -52,6 +52,10 @@ def test_autotune_fp32_results_close(P):
     op = default_params(max_iter=20000, lr=1e-3)
     p = lib_params(P, op, precision=P.OPDHG_FP32)
     tun, tuned = P.opdhg_autotune(lps, p, replays=2)
+    # the twelve tilings, then the best one with windowed chunks
+    assert tun.candidates == len(CANDIDATES) + 1
+    assert tun.windows in (P.OPDHG_WINDOWS_AUTO, P.OPDHG_WINDOWS_ALWAYS)
+    assert tuned.windows == tun.windows and tuned.window_rows == tun.window_rows
     a = P.opdhg_solve_batch(lps, p)
     b = P.opdhg_solve_batch(lps, tuned)
     for i, (lp, (_, _, ra), (_, _, rb)) in enumerate(zip(lps, a, b)):
@@ -59,3 +63,7 @@ def test_autotune_fp32_results_close(P):
         # both are 1e-4-optimal: objectives agree to the tolerance scale
         assert abs(ra.primal_obj - rb.primal_obj) <= 1e-3 * (1.0 + abs(rb.primal_obj))
         check_final_fp32(rb, oracle.solve(lp, op), label=f"tuned FP32 LP {i}")
+    # a tuned batch equals its LPs' solo solves with the tuned parameters
+    for lp, (xb, yb, rb) in zip(lps, b):
+        xs, ys, rs = P.opdhg_solve(lp, tuned)
+        assert np.array_equal(xb, xs) and np.array_equal(yb, ys) and rb.iterations == rs.iterations

@@ -169,6 +169,28 @@ def test_batch_equals_solo_and_oracle(P):
         check_final_fp64((x, y, r), oracle.solve(lp, op), label=f"batch LP {i}")
 
 
+@pytest.mark.parametrize("slots", [-1, 1, 3])
+def test_guarded_evaluations_change_nothing(P, slots):
+    """The guarded evaluation steps inside a launch sequence (every `slots`
+    attempt slots; -1: none) change when an LP that became due mid-sequence
+    is evaluated, never what it computes: solo and batch results equal the
+    automatic setting's and the oracle's. The LPs reject attempts, so
+    evaluations fall due mid-sequence."""
+    lps = [config_lp("cfg1", scale=0.02), config_lp("cfg0", seed=1)]
+    op = default_params(max_iter=20000, lr=1e-3)
+    _say(f"[guarded evaluations] eval_slots={slots}")
+    for i, lp in enumerate(lps):
+        auto = P.opdhg_solve(lp, lib_params(P, op))
+        got = P.opdhg_solve(lp, lib_params(P, op, eval_slots=slots))
+        assert np.array_equal(got[0], auto[0]) and np.array_equal(got[1], auto[1])
+        assert got[2].attempts == auto[2].attempts and got[2].restarts == auto[2].restarts
+        check_final_fp64(got, oracle.solve(lp, op), label=f"LP {i}")
+    out = P.opdhg_solve_batch(lps, lib_params(P, op, eval_slots=slots))
+    for lp, (x, y, r) in zip(lps, out):
+        xs, ys, rs = P.opdhg_solve(lp, lib_params(P, op))
+        assert np.array_equal(x, xs) and np.array_equal(y, ys) and r.attempts == rs.attempts
+
+
 def test_long_run_past_the_factor_table(P):
     # 11000 attempts with evaluations every 100 iterations: a launch sequence
     # holds at most 64 attempts, so every attempt past the host table's 8192

@@ -2,11 +2,14 @@
 
 With OPDHG_PREP_DEVICE the Ruiz, L2 and Pock-Chambolle passes, the scaled
 values and vectors, and the first step size and primal weight are computed
-by device kernels in the device order of the rows. Each row statistic
-follows the host's expression and order, so the whole solve must equal the
-host-prepared solve bit for bit; the host's rescaling is in turn bitwise
-equal to the oracle's (test_library_host.py), so these solves are tied to
-the oracle's rescaling.
+by device kernels in the device order of the rows. Without windowed chunks
+the device also builds both CSR copies (A in device order and its
+transpose) from the caller's arrays, unless a column is longer than the
+device's per-column ordering takes. Each row statistic follows the host's
+expression and order, and each CSR copy the host's entry order, so the
+whole solve must equal the host-prepared solve bit for bit; the host's
+rescaling is in turn bitwise equal to the oracle's (test_library_host.py),
+and every solve here is also checked against the oracle's.
 """
 
 import numpy as np
@@ -127,6 +130,37 @@ def test_device_prep_batch_and_server(P):
             check_final_fp32(g[2], want, label=f"device-prepared served {name}")
         else:
             assert g[2].status == want.status and g[2].iterations == want.iterations, name
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_device_structure_falls_back_for_very_long_columns(P, prec_name):
+    """A column of more than 4096 entries: the host builds the structure and
+    the device rescales; a column of 4096 exactly: the device builds it.
+    Both equal the host-prepared solve bit for bit and the oracle's."""
+    from lpgen import random_lp
+    prec = P.OPDHG_FP64 if prec_name == "fp64" else P.OPDHG_FP32
+    for longest in (4096, 4097):
+        lp = random_lp(21, 5000, 300, degree=("uniform", 3, 6))
+        # one dense column: rows 0..longest-1 of column 0, values 1
+        A = lp.csr().tolil()
+        A[:, 0] = 0.0
+        A[:longest, 0] = 1.0
+        A = A.tocsr()
+        A.sort_indices()
+        lp.row_ptr = A.indptr.astype(np.int64)
+        lp.col_idx = A.indices.astype(np.int32)
+        lp.val = A.data.astype(float)
+        assert np.bincount(lp.col_idx, minlength=lp.n)[0] == longest
+        _say(f"[prep] longest column {longest}, {prec_name}, nnz {lp.nnz}")
+        op = default_params(max_iter=1500, lr=1e-3, tol=1e-4)
+        host = P.opdhg_solve(lp, lib_params(P, op, precision=prec, prep=P.OPDHG_PREP_HOST))
+        dev = P.opdhg_solve(lp, lib_params(P, op, precision=prec, prep=P.OPDHG_PREP_DEVICE))
+        _same(dev, host)
+        ref = oracle.solve(lp, op)
+        if prec == P.OPDHG_FP64:
+            check_final_fp64(dev, ref, label=f"longest column {longest}")
+        else:
+            assert dev[2].status == ref.status or ref.status != oracle.pdhg.OPTIMAL
 
 
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
