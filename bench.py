@@ -392,6 +392,16 @@ def section_serving(P, args):
     errs = [abs(a.primal_obj - b.primal_obj) / (1.0 + abs(b.primal_obj))
             for a, b in zip(res32, res64)
             if a.status == b.status == P.capi.OPDHG_STATUS_OPTIMAL]
+
+    def statuses(res):
+        out = {}
+        for r in res:
+            k = P.opdhg_status_name(r.status)
+            out[k] = out.get(k, 0) + 1
+        return out
+    not_opt = [{"request": i, "status": P.opdhg_status_name(r.status), "nnz": meas[i].nnz,
+                "iterations": r.iterations, "rel_kkt": r.rel_kkt}
+               for i, r in enumerate(res32) if r.status != P.capi.OPDHG_STATUS_OPTIMAL]
     # preparation of the largest request, on the host and on the device
     # (session creation: validation, structure, rescaling, upload, initial products)
     big = max(reqs, key=lambda lp: lp.nnz)
@@ -412,7 +422,8 @@ def section_serving(P, args):
         "requests": n, "warmup_requests": nw, "rate_per_s": rate,
         "rate_rule": "0.7 x plain FP64 one-at-a-time throughput on the warm-up requests",
         "arena_bytes": arena, "peak_bytes": st.peak_bytes, "dtype": "f32",
-        "optimal": ok32, "solves_per_s": ok32 / span32,
+        "optimal": ok32, "statuses": statuses(res32), "not_optimal": not_opt,
+        "solves_per_s": ok32 / span32,
         "closed_loop_solves_per_s_warmup": mu_srv,
         "latency_p50_s": pct(lat32, 50), "latency_p99_s": pct(lat32, 99),
         "latency_max_s": max(lat32),
@@ -426,7 +437,8 @@ def section_serving(P, args):
         "baseline": {
             "kind": "plain FP64 PDHG (lr 0) served one LP at a time, first in first out, by the "
                     "same server (max_active 1) at the same arrival times on the same GPU",
-            "optimal": ok64, "solves_per_s": ok64 / span64, "closed_loop_solves_per_s": mu_plain,
+            "optimal": ok64, "statuses": statuses(res64), "solves_per_s": ok64 / span64,
+            "closed_loop_solves_per_s": mu_plain,
             "latency_p50_s": pct(lat64, 50), "latency_p99_s": pct(lat64, 99),
             "latency_max_s": max(lat64)},
     }
@@ -542,7 +554,7 @@ def oracle_baseline(lp, lr: float, phi: int, seconds: float) -> dict:
     first = time.perf_counter() - t0
     # sized from the first iteration, which also carried the k = 0 evaluation
     # (about three more sparse products): a plain iteration costs less
-    iters = int(max(2, min(p.eval_every - 2, seconds / max(first / 2.5, 1e-4))))
+    iters = int(max(2, min(p.eval_every - 2, seconds / max(first / 1.5, 1e-4))))
     t0 = time.perf_counter()
     r = OP.solve_from_state(slp, st, p, stop_k=1 + iters)
     dt = time.perf_counter() - t0
