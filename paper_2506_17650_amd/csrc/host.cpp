@@ -587,7 +587,12 @@ constexpr int64_t kWinRound = 256;
 constexpr int64_t kWinMinChunks = 128;  // fewer chunks than this leave most CUs idle
 
 static int64_t window_chunk_rows(const opdhg_params* p, int64_t rows) {
-  if (p->window_rows > 0) return p->window_rows;
+  if (p->window_rows > 0) {
+    // as few chunks as the cap allows, of equal size: a short last chunk
+    // would stage the whole window for few rows and fall back to tiles
+    const int64_t nch = std::max<int64_t>(1, (rows + p->window_rows - 1) / p->window_rows);
+    return std::max<int64_t>(1, (rows + nch - 1) / nch);
+  }
   const int64_t rounds = std::max<int64_t>(1, (rows + kWinRound * kWinRows - 1) / (kWinRound * kWinRows));
   const int64_t per = (rows + rounds * kWinRound - 1) / (rounds * kWinRound);
   return std::min<int64_t>(kWinRows, std::max<int64_t>(1024, per));
@@ -675,13 +680,15 @@ static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t
   W.seg0.assign(nch, 0);
   if (nch == 0) return;
 
-  // Row segments. A long row (rows [0, long_end)) whose every entry falls
-  // in some chunk's window is split by chunk: the entries of a bucket go to
-  // one of the chunks that stage it (chosen by the row, so that the long
-  // rows spread over those chunks), and each (row, chunk) pair becomes an
-  // extra row of that chunk, after its own rows. Its pass sums go to a
-  // partial of its own; a finishing kernel adds a row's partials in chunk
-  // order. The row then leaves the tiles.
+  // Row segments. A long row (rows [0, long_end)), or a row of [lo, hi)
+  // that no chunk took, whose every entry falls in some chunk's window is
+  // split by chunk: the entries of a bucket go to one of the chunks that
+  // stage it (chosen by the row, so that the long rows spread over those
+  // chunks), and each (row, chunk) pair becomes an extra row of that chunk,
+  // after its own rows. Its pass sums go to a partial of its own; a
+  // finishing kernel adds a row's partials in chunk order. The row then
+  // leaves the tiles (a side whose rows all leave them needs no tile launch
+  // beside its windowed one).
   std::vector<std::vector<int32_t>> cover(nb);  // chunks staging each bucket
   for (int64_t c = 0; c < nch; ++c)
     for (const Slot& x : slots[c]) cover[x.bucket].push_back((int32_t)c);
@@ -692,7 +699,19 @@ static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t
   std::vector<std::vector<int64_t>> seg_rows(nch);  // per chunk: its segment rows, in order
   std::vector<int32_t> used;
   std::vector<int32_t> cstamp(nch, -1);
-  for (int64_t r = 0; r < std::min(long_end, hi); ++r) {
+  // candidate rows in ascending order: the long rows, then the rows of
+  // [lo, hi) outside every chunk (the chunks are in row order)
+  std::vector<int64_t> cand;
+  for (int64_t r = 0; r < std::min(long_end, hi); ++r) cand.push_back(r);
+  {
+    int64_t r = std::max(lo, std::min(long_end, hi));
+    for (int64_t c = 0; c <= nch; ++c) {
+      const int64_t stop = c < nch ? (int64_t)W.r0[c] : hi;
+      for (; r < stop; ++r) cand.push_back(r);
+      if (c < nch) r = std::max<int64_t>(r, W.r1[c]);
+    }
+  }
+  for (int64_t r : cand) {
     if (rp[r + 1] == rp[r]) continue;
     used.clear();
     bool ok = true;
@@ -726,7 +745,7 @@ static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t
   {
     std::vector<int32_t> next(nch, 0);
     std::vector<std::vector<std::pair<int32_t, int32_t>>> per_row(W.srow.size());
-    std::vector<int32_t> row_index((size_t)std::min(long_end, hi), -1);
+    std::vector<int32_t> row_index((size_t)hi, -1);
     for (size_t q = 0; q < W.srow.size(); ++q) row_index[W.srow[q]] = (int32_t)q;
     for (int64_t c = 0; c < nch; ++c)
       for (int64_t r : seg_rows[c]) per_row[row_index[r]].push_back({(int32_t)c, W.seg0[c] + next[c]++});
