@@ -950,9 +950,38 @@ static std::vector<Tile> tiles_outside(const std::vector<int32_t>& rp, int64_t r
   return out;
 }
 
+// Long-row tiles of a step list longer than kSplitNnz become pieces of
+// kPieceNnz nonzeros (see Tile); their rows join the side's segments after
+// the windowed plan's, which are kept as planned.
+static void split_long_tiles(std::vector<Tile>& tiles, WinPlan& W) {
+  W.srow.resize(W.nsrow_win);
+  W.sids.resize(W.nsrow_win ? (size_t)W.sptr[W.nsrow_win] : 0);
+  W.sptr.resize(W.nsrow_win ? W.nsrow_win + 1 : 0);
+  W.nsegs = W.nsegs_win;
+  std::vector<Tile> out;
+  out.reserve(tiles.size());
+  for (const Tile& t : tiles) {
+    if (t.lanes != 0 || t.e - t.s <= kSplitNnz) {
+      out.push_back(t);
+      continue;
+    }
+    if (W.sptr.empty()) W.sptr.push_back(0);
+    W.srow.push_back(t.rb);
+    for (int32_t a = t.s; a < t.e; a += kPieceNnz) {
+      const int32_t id = W.nsegs++;
+      out.push_back(Tile{t.rb, t.re, a, std::min(t.e, a + kPieceNnz), -1, id});
+      W.sids.push_back(id);
+    }
+    W.sptr.push_back((int32_t)W.sids.size());
+  }
+  tiles.swap(out);
+}
+
 void step_tiles(Prepared& P, int64_t cap, int lanes) {
   P.stiles_t = P.win_t.chunks() ? tiles_outside(P.rp_t, P.n, P.win_t, cap, lanes) : P.tiles_t;
   P.stiles_a = P.win_a.chunks() ? tiles_outside(P.rp_a, P.m, P.win_a, cap, lanes) : P.tiles_a;
+  split_long_tiles(P.stiles_t, P.win_t);
+  split_long_tiles(P.stiles_a, P.win_a);
 }
 
 
@@ -1134,8 +1163,7 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   for (int64_t j = 0; j < n; ++j) max_col = std::max(max_col, len_t[j]);
   out.dstruct = out.dprep && !windows && nnz > 0 && max_col <= kStructMaxCol;
   if (structure_only && !windows) {
-    out.stiles_a = out.tiles_a;
-    out.stiles_t = out.tiles_t;
+    step_tiles(out, cap, p->lanes);
     return OPDHG_OK;
   }
 
@@ -1220,6 +1248,10 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
       if ((int64_t)out.win_a.chunks() < kWinMinChunks) out.win_a = WinPlan();
     }
   }
+  for (WinPlan* W : {&out.win_t, &out.win_a}) {
+    W->nsrow_win = W->srow.size();
+    W->nsegs_win = W->nsegs;
+  }
   step_tiles(out, cap, p->lanes);
   if (structure_only) return OPDHG_OK;
   return prepare_finish(lp, p, out, spec, &sval);
@@ -1280,12 +1312,12 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
     L.wval_t = take(V * e);
     L.wpass_t = take(sizeof(WinPass) * P.win_t.passes.size());
     L.wrange_t = take(sizeof(WinRange) * P.win_t.ranges.size());
-    if (!P.win_t.srow.empty()) {
-      L.segp_t = take(V * P.win_t.nsegs);
-      L.srow_t = take(4 * P.win_t.srow.size());
-      L.sptr_t = take(4 * P.win_t.sptr.size());
-      L.sids_t = take(4 * P.win_t.sids.size());
-    }
+  }
+  if (!P.win_t.srow.empty()) {  // segmented rows (windowed chunks or split tiles)
+    L.segp_t = take((V == 8 ? 16 : 4) * (size_t)P.win_t.nsegs);
+    L.srow_t = take(4 * P.win_t.srow.size());
+    L.sptr_t = take(4 * P.win_t.sptr.size());
+    L.sids_t = take(4 * P.win_t.sids.size());
   }
   if (P.win_a.chunks()) {
     const size_t e = P.win_a.col.size();
@@ -1294,12 +1326,12 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
     L.wval_a = take(V * e);
     L.wpass_a = take(sizeof(WinPass) * P.win_a.passes.size());
     L.wrange_a = take(sizeof(WinRange) * P.win_a.ranges.size());
-    if (!P.win_a.srow.empty()) {
-      L.segp_a = take(V * P.win_a.nsegs);
-      L.srow_a = take(4 * P.win_a.srow.size());
-      L.sptr_a = take(4 * P.win_a.sptr.size());
-      L.sids_a = take(4 * P.win_a.sids.size());
-    }
+  }
+  if (!P.win_a.srow.empty()) {  // segmented rows (windowed chunks or split tiles)
+    L.segp_a = take((V == 8 ? 16 : 4) * (size_t)P.win_a.nsegs);
+    L.srow_a = take(4 * P.win_a.srow.size());
+    L.sptr_a = take(4 * P.win_a.sptr.size());
+    L.sids_a = take(4 * P.win_a.sids.size());
   }
   if (P.dprep) {
     L.raw_a = take(8 * nnz);
@@ -1378,12 +1410,12 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
     d.wval_t = base + L.wval_t;
     d.wpass_t = reinterpret_cast<const WinPass*>(base + L.wpass_t);
     d.wrange_t = reinterpret_cast<const WinRange*>(base + L.wrange_t);
-    if (!P.win_t.srow.empty()) {
-      d.segp_t = base + L.segp_t;
-      d.srow_t = reinterpret_cast<const int32_t*>(base + L.srow_t);
-      d.sptr_t = reinterpret_cast<const int32_t*>(base + L.sptr_t);
-      d.sids_t = reinterpret_cast<const int32_t*>(base + L.sids_t);
-    }
+  }
+  if (!P.win_t.srow.empty()) {
+    d.segp_t = base + L.segp_t;
+    d.srow_t = reinterpret_cast<const int32_t*>(base + L.srow_t);
+    d.sptr_t = reinterpret_cast<const int32_t*>(base + L.sptr_t);
+    d.sids_t = reinterpret_cast<const int32_t*>(base + L.sids_t);
   }
   if (P.win_a.chunks()) {
     d.wcol_a = reinterpret_cast<const uint16_t*>(base + L.wcol_a);
@@ -1391,12 +1423,12 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
     d.wval_a = base + L.wval_a;
     d.wpass_a = reinterpret_cast<const WinPass*>(base + L.wpass_a);
     d.wrange_a = reinterpret_cast<const WinRange*>(base + L.wrange_a);
-    if (!P.win_a.srow.empty()) {
-      d.segp_a = base + L.segp_a;
-      d.srow_a = reinterpret_cast<const int32_t*>(base + L.srow_a);
-      d.sptr_a = reinterpret_cast<const int32_t*>(base + L.sptr_a);
-      d.sids_a = reinterpret_cast<const int32_t*>(base + L.sids_a);
-    }
+  }
+  if (!P.win_a.srow.empty()) {
+    d.segp_a = base + L.segp_a;
+    d.srow_a = reinterpret_cast<const int32_t*>(base + L.srow_a);
+    d.sptr_a = reinterpret_cast<const int32_t*>(base + L.sptr_a);
+    d.sids_a = reinterpret_cast<const int32_t*>(base + L.sids_a);
   }
   return d;
 }
@@ -1478,15 +1510,15 @@ void slot_image(const SlotLayout& L, const Prepared& P, SlotImage& img) {
   auto put_win = [&](const WinPlan& W, const auto& va, size_t oc, size_t orow,
                      size_t ov, size_t opass, size_t orange, size_t osrow, size_t osptr,
                      size_t osids, size_t owsrc) {
-    if (!W.chunks()) return;
-    if (P.dprep) {  // the device fills the values from the scaled entries they stand for
-      int32_t* ws = reinterpret_cast<int32_t*>(img.data() + owsrc);
-      for (size_t e = 0; e < W.src.size(); ++e) ws[e] = (int32_t)W.src[e];
-    }
     if (!W.srow.empty()) {
       std::memcpy(img.data() + osrow, W.srow.data(), 4 * W.srow.size());
       std::memcpy(img.data() + osptr, W.sptr.data(), 4 * W.sptr.size());
       std::memcpy(img.data() + osids, W.sids.data(), 4 * W.sids.size());
+    }
+    if (!W.chunks()) return;
+    if (P.dprep) {  // the device fills the values from the scaled entries they stand for
+      int32_t* ws = reinterpret_cast<int32_t*>(img.data() + owsrc);
+      for (size_t e = 0; e < W.src.size(); ++e) ws[e] = (int32_t)W.src[e];
     }
     std::memcpy(img.data() + oc, W.col.data(), 2 * W.col.size());
     std::memcpy(img.data() + orow, W.row.data(), 2 * W.row.size());
@@ -1621,16 +1653,18 @@ int Group::launch_side(bool primal, int force, hipStream_t s) {
     return primal ? Kernels<double>::primal_seg(cfg, q, force)
                   : Kernels<double>::dual_seg(cfg, q, force);
   };
+  // the finishing kernel reads partials of windowed chunks and of split
+  // tiles, so it runs after both
   if (!(tiles && wins) || !side_stream)
-    return (tiles ? tile(s) : 0) | (wins ? win(s) | seg(s) : 0);
+    return (tiles ? tile(s) : 0) | (wins ? win(s) : 0) | seg(s);
   if (hipEventRecord(ev_fork, s) != hipSuccess ||
       hipStreamWaitEvent(side_stream, ev_fork, 0) != hipSuccess)
     return -1;
   int rc = tile(side_stream);
   if (hipEventRecord(ev_join, side_stream) != hipSuccess) return -1;
   rc |= win(s);
-  rc |= seg(s);
   if (hipStreamWaitEvent(s, ev_join, 0) != hipSuccess) return -1;
+  rc |= seg(s);
   return rc;
 }
 
@@ -1781,7 +1815,7 @@ size_t tables_bytes(int64_t nlps, int64_t nwork_t, int64_t nwork_a, int64_t cap)
 // reductions are exact, so the order does not change any result.
 static std::vector<int64_t> spread_long_tiles(const std::vector<Tile>& tiles) {
   std::vector<int64_t> longs, stream, order;
-  for (size_t t = 0; t < tiles.size(); ++t) (tiles[t].lanes == 0 ? longs : stream).push_back(t);
+  for (size_t t = 0; t < tiles.size(); ++t) (tiles[t].lanes <= 0 ? longs : stream).push_back(t);
   order.reserve(tiles.size());
   const int64_t nl = (int64_t)longs.size(), ns = (int64_t)stream.size();
   int64_t il = 0;
@@ -1794,7 +1828,7 @@ static std::vector<int64_t> spread_long_tiles(const std::vector<Tile>& tiles) {
   return order;
 }
 
-// Items of one side for all LPs, chunked: fills slot / last and each LP's
+// Items of one side for all LPs, chunked: fills slot / first and each LP's
 // slot count.
 void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& preps, bool tside,
                 int64_t cap, int* grid, int* chunk, std::vector<WorkItem>& out, bool step) {
@@ -1808,7 +1842,7 @@ void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& pre
     for (int64_t t : spread_long_tiles(tiles)) {
       const Tile& tl = tiles[t];
       out.push_back(WorkItem{lps[i].ctl, (int32_t)i, (int32_t)t, tl.rb, tl.re, tl.s, tl.e,
-                             tl.lanes, 0, 0, 0});
+                             tl.lanes, 0, tl.lanes < 0 ? tl.seg : -1, 0});
     }
     range[i].second = (int64_t)out.size();
   }
@@ -1826,7 +1860,6 @@ void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& pre
     const int64_t s = range[i].first, e = range[i].second;
     for (int64_t q = s; q < e; ++q) {
       out[q].slot = out[q].tile;
-      out[q].last = 1;
       out[q].first = q == s ? 1 : 0;
     }
     if (step) {
@@ -1837,7 +1870,7 @@ void side_items(std::vector<LpDev>& lps, const std::vector<const Prepared*>& pre
       (tside ? lps[i].item0_t : lps[i].item0_a) = (int32_t)s;
     }
   }
-  const WorkItem pad{nullptr, -1, 0, 0, 0, 0, 0, 1, 0, 0, 0};
+  const WorkItem pad{nullptr, -1, 0, 0, 0, 0, 0, 1, 0, -1, 0};
   out.resize((size_t)(*grid) * (*chunk), pad);
 }
 

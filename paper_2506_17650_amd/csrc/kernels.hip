@@ -436,6 +436,25 @@ using Prod = typename Num<V>::Prod;
 template <typename V>
 using Acc = typename Num<V>::Acc;
 
+// Segment partials of split rows: FP32 runs keep a float per segment; FP64
+// runs keep the double-double sum (hi, lo), so that a split row's value is
+// rounded once, after its pieces are merged, as an unsplit row's is.
+__device__ __forceinline__ void seg_store(void* base, int sid, const Acc<float>& a) {
+  stg(gp(static_cast<float*>(base)), (uint32_t)sid, a.v);
+}
+__device__ __forceinline__ void seg_store(void* base, int sid, const Acc<double>& a) {
+  const gptr<double> g = gp(static_cast<double*>(base));
+  stg(g, (uint32_t)(2 * sid), a.v.hi);
+  stg(g, (uint32_t)(2 * sid + 1), a.v.lo);
+}
+__device__ __forceinline__ void seg_load(const void* base, int sid, Acc<float>& a) {
+  a.v = ldg(gp(static_cast<const float*>(base)), (uint32_t)sid);
+}
+__device__ __forceinline__ void seg_load(const void* base, int sid, Acc<double>& a) {
+  const gptr<const double> g = gp(static_cast<const double*>(base));
+  a.v = DD{ldg(g, (uint32_t)(2 * sid)), ldg(g, (uint32_t)(2 * sid + 1))};
+}
+
 // Vector q at column c: vec[q][c], or vec[q][c] / div[q] for the average.
 template <typename V>
 __device__ __forceinline__ V vec_at(const gptr<const V>* vec, const double* div, int q, int c) {
@@ -620,6 +639,49 @@ __device__ __forceinline__ void long_row_tile(const WorkItem& it, gptr<const int
       out[q] = t.value();
     }
     finish(r, out, pre);
+  }
+  lds_barrier();
+}
+
+// A piece of a split long row (lanes < 0): the workgroup sums the piece's
+// products with vector 0 as long_row_tile does and hands the sum to
+// store(seg, acc) instead of running the row epilogue; the finishing kernel
+// merges the row's pieces in order.
+template <typename V, int NA, typename Store>
+__device__ __forceinline__ void piece_tile(const WorkItem& it, gptr<const int32_t> ci,
+                                           gptr<const V> va, const gptr<const V>* vec,
+                                           const double* div, Store&& store,
+                                           SpmvShared<V, NA>& sh) {
+  const int tid = threadIdx.x;
+  const int last = it.e - 1;
+  Acc<V> acc;
+  acc.zero();
+  constexpr int U = 4;
+  for (int k = it.s + tid; k < it.e; k += U * kBlock) {
+    V a[U], x[U];
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t kk = (uint32_t)min(k + u * kBlock, last);
+      a[u] = ldg(va, kk);
+      c[u] = ldg(ci, kk);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = vec_at(vec, div, 0, c[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      acc.add(Num<V>::mask(k + u * kBlock < it.e, Num<V>::mul(a[u], x[u])));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc.merge_xor(off);
+  if ((tid & 63) == 0) sh.wave[tid >> 6][0] = acc;
+  lds_barrier();
+  if (tid == 0) {
+    Acc<V> t = sh.wave[0][0];
+    t.merge(sh.wave[1][0]);
+    t.merge(sh.wave[2][0]);
+    t.merge(sh.wave[3][0]);
+    store(it.seg, t);
   }
   lds_barrier();
 }
@@ -957,7 +1019,7 @@ __device__ __forceinline__ WorkItem uniform_item(const WorkItem& w) {
   u.e = __builtin_amdgcn_readfirstlane(w.e);
   u.lanes = __builtin_amdgcn_readfirstlane(w.lanes);
   u.slot = __builtin_amdgcn_readfirstlane(w.slot);
-  u.last = __builtin_amdgcn_readfirstlane(w.last);
+  u.seg = __builtin_amdgcn_readfirstlane(w.seg);
   u.first = __builtin_amdgcn_readfirstlane(w.first);
   return u;
 }
@@ -996,14 +1058,14 @@ struct TilePartials {
 // of each tile are added in a fixed order and stored, after the barrier
 // the window needs anyway.
 template <typename V, int NA, int NV, bool PLAIN, typename Begin, typename Load, typename Finish,
-          typename Dest, typename Commit>
+          typename Dest, typename Commit, typename Piece>
 __device__ __forceinline__ void run_chunk_spmv(const WorkItem* __restrict__ work, SideChunks sc,
                                                WorkItem* s_items, const gptr<const int32_t>& rp,
                                                const gptr<const int32_t>& ci,
                                                const gptr<const V>& va, const gptr<const V>* vec,
                                                const double* div, Begin&& begin, Load&& load,
                                                Finish&& finish, Dest&& dest, Commit&& commit,
-                                               DD (&p)[NV], TilePartials<NV>& tp,
+                                               Piece&& piece, DD (&p)[NV], TilePartials<NV>& tp,
                                                SpmvShared<V, NA>& sh) {
   const int chi = chunk_index(sc.grid);
   if (chi < 0) return;
@@ -1030,7 +1092,11 @@ __device__ __forceinline__ void run_chunk_spmv(const WorkItem* __restrict__ work
           run = begin(it);
         }
         if (run) {
-          spmv_tile<V, NA>(it, rp, ci, va, vec, div, load, finish, sh);
+          // a piece of a split row stores its sum (its partial slot gets zeros)
+          if (it.lanes < 0)
+            piece_tile<V, NA>(it, ci, va, vec, div, piece, sh);
+          else
+            spmv_tile<V, NA>(it, rp, ci, va, vec, div, load, finish, sh);
           wave_scan<NV, PLAIN>(p);
           if (lane == 63) {
 #pragma unroll
@@ -1157,6 +1223,7 @@ struct PrimalStep {
   gptr<const V> va = nullptr;
   double* part_ = nullptr;
   int stride_ = 0;
+  void* segp_ = nullptr;  // segment partials of split rows
   V tau = V(0), etav = V(0);
   bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
@@ -1189,6 +1256,7 @@ struct PrimalStep {
     const DevParams* const pprm = uni(L->prm);
     double* const ppart = uni(L->part_t);
     const int pstride = uni(L->ntiles_t);
+    void* const pseg = uni(L->segp_t);
     // the restart / final copy of the evaluation step ran before this
     // launch; the workgroup with the LP's first item clears the flags
     if (first && threadIdx.x == 0 && (v.restart_pending | v.finalize_avg)) {
@@ -1227,6 +1295,7 @@ struct PrimalStep {
     va = uni(gp(static_cast<const V*>(pva)));
     part_ = uni(ppart);
     stride_ = uni(pstride);
+    segp_ = uni(pseg);
     tau = uni(tau), etav = uni(etav);
     return true;
   }
@@ -1299,6 +1368,7 @@ struct PrimalStep {
 
   __device__ __forceinline__ double* part() const { return part_; }
   __device__ __forceinline__ int stride() const { return stride_; }
+  __device__ __forceinline__ void piece(int sid, const Acc<V>& a) const { seg_store(segp_, sid, a); }
 };
 
 template <typename V>
@@ -1325,6 +1395,7 @@ struct DualStep {
   gptr<const V> vecs[1] = {nullptr};  // the gathered vector, x'
   double* part_ = nullptr;
   int stride_ = 0;
+  void* segp_ = nullptr;  // segment partials of split rows
   V sig = V(0), etav = V(0);
   bool learn = false, upd = false, wstep = false;
   double lscale = 1.0, hnorm = 0.0;
@@ -1356,6 +1427,7 @@ struct DualStep {
     const DevParams* const pprm = uni(L->prm);
     double* const ppart = uni(L->part_a);
     const int pstride = uni(L->ntiles_a);
+    void* const pseg = uni(L->segp_a);
     if (!uni((int)(force || v.attempt()))) return false;
     const int cur = uni(v.cur);
     const double eta = uni(v.eta), om = uni(v.omega);
@@ -1389,6 +1461,7 @@ struct DualStep {
     va = uni(gp(static_cast<const V*>(pva)));
     part_ = uni(ppart);
     stride_ = uni(pstride);
+    segp_ = uni(pseg);
     sig = uni(sig), etav = uni(etav);
     return true;
   }
@@ -1463,6 +1536,7 @@ struct DualStep {
 
   __device__ __forceinline__ double* part() const { return part_; }
   __device__ __forceinline__ int stride() const { return stride_; }
+  __device__ __forceinline__ void piece(int sid, const Acc<V>& a) const { seg_store(segp_, sid, a); }
 };
 
 // Chunking of a step kernel's tile list: fixed sets carry it in the launch
@@ -1507,7 +1581,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(LaunchCfg cfg, int force) {
         d = st.part();
         sd = st.stride();
       },
-      [&]() { st.commit(); }, p, tp, sh);
+      [&]() { st.commit(); }, [&](int sid, const Acc<V>& a) { st.piece(sid, a); }, p, tp, sh);
   st.commit();
 }
 
@@ -1531,7 +1605,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
         d = st.part();
         sd = st.stride();
       },
-      [&]() { st.commit(); }, p, tp, sh);
+      [&]() { st.commit(); }, [&](int sid, const Acc<V>& a) { st.piece(sid, a); }, p, tp, sh);
   st.commit();
 }
 
@@ -1734,10 +1808,12 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   st.commit();
 }
 
-// Segmented long rows (FP32): kSegLanes lanes per row. Lane l adds the
-// row's partials l, l + kSegLanes, ... in order, the lanes combine in a
-// fixed shuffle tree, and the row's first lane runs the row epilogue.
-template <typename Step, typename Pre, int NV>
+// Segmented long rows: kSegLanes lanes per row. Lane l merges the row's
+// partials l, l + kSegLanes, ... in order, the lanes combine in a fixed
+// shuffle tree, and the row's first lane runs the row epilogue. The
+// partials come from windowed chunks (FP32) and from the pieces of rows
+// split in tiles (float in FP32 runs, double-double in FP64 runs).
+template <typename V, typename Step, typename Pre, int NV>
 __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* list, int nitems,
                                          bool tside, int force) {
   __shared__ DD s_red[4 * NV];
@@ -1748,7 +1824,7 @@ __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* li
   Step st;
   if (!st.begin(cfg, it.ctl, it.lp, it.slot == 0, force)) return;
   const LpDev* lp = st.lp;
-  const gptr<const float> sp = uni(gp(static_cast<const float*>(tside ? lp->segp_t : lp->segp_a)));
+  const void* const sp = uni(tside ? lp->segp_t : lp->segp_a);
   const gptr<const int32_t> srow = uni(gp(tside ? lp->srow_t : lp->srow_a));
   const gptr<const int32_t> sptr = uni(gp(tside ? lp->sptr_t : lp->sptr_a));
   const gptr<const int32_t> sids = uni(gp(tside ? lp->sids_t : lp->sids_a));
@@ -1761,22 +1837,30 @@ __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* li
   const int row = ldg(srow, (uint32_t)qq);
   Pre pre = st.load(row);
   const int k0 = ldg(sptr, (uint32_t)qq), k1 = ldg(sptr, (uint32_t)(qq + 1));
-  float acc = 0.f;
-  for (int k = k0 + lane; k < k1; k += kSegLanes) acc += ldg(sp, (uint32_t)ldg(sids, (uint32_t)k));
+  Acc<V> acc;
+  acc.zero();
+  for (int k = k0 + lane; k < k1; k += kSegLanes) {
+    Acc<V> a;
+    seg_load(sp, ldg(sids, (uint32_t)k), a);
+    acc.merge(a);
+  }
+  // xor offsets below kSegLanes stay inside the row's aligned lane group
 #pragma unroll
-  for (int off = kSegLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSegLanes);
-  if (on && lane == 0) st.finish(row, acc, pre, p);
-  block_sum<NV, kBlock / 64, true>(p, s_red);
+  for (int off = kSegLanes / 2; off > 0; off >>= 1) acc.merge_xor(off);
+  if (on && lane == 0) st.finish(row, (V)acc.value(), pre, p);
+  block_sum<NV, kBlock / 64, Step::kPlain>(p, s_red);
   store_partials<NV>(st.part(), st.stride(), it.slot, p);
   st.commit();
 }
 
+template <typename V>
 __global__ __launch_bounds__(kBlock) void k_primal_seg(LaunchCfg cfg, int force) {
-  seg_rows<PrimalStep<float>, PrimalPre<float>, 3>(cfg, cfg.seg_t, cfg.nseg_t, true, force);
+  seg_rows<V, PrimalStep<V>, PrimalPre<V>, 3>(cfg, cfg.seg_t, cfg.nseg_t, true, force);
 }
 
+template <typename V>
 __global__ __launch_bounds__(kBlock) void k_dual_seg(LaunchCfg cfg, int force) {
-  seg_rows<DualStep<float>, DualPre<float>, 4>(cfg, cfg.seg_a, cfg.nseg_a, false, force);
+  seg_rows<V, DualStep<V>, DualPre<V>, 4>(cfg, cfg.seg_a, cfg.nseg_a, false, force);
 }
 
 __global__ __launch_bounds__(kWinBlock) void k_primal_win(LaunchCfg cfg, int force) {
@@ -2576,20 +2660,12 @@ int Kernels<V>::dual_win(const LaunchCfg& c, void* stream, int force) {
 template <typename V>
 int Kernels<V>::primal_seg(const LaunchCfg& c, void* stream, int force) {
   if (c.nseg_t <= 0) return 0;
-  if constexpr (!std::is_same<V, float>::value) {
-    return -1;
-  } else {
-    OPDHG_LAUNCH(k_primal_seg, c.nseg_t, c, force);
-  }
+  OPDHG_LAUNCH(k_primal_seg<V>, c.nseg_t, c, force);
 }
 template <typename V>
 int Kernels<V>::dual_seg(const LaunchCfg& c, void* stream, int force) {
   if (c.nseg_a <= 0) return 0;
-  if constexpr (!std::is_same<V, float>::value) {
-    return -1;
-  } else {
-    OPDHG_LAUNCH(k_dual_seg, c.nseg_a, c, force);
-  }
+  OPDHG_LAUNCH(k_dual_seg<V>, c.nseg_a, c, force);
 }
 template <typename V>
 int Kernels<V>::decide(const LaunchCfg& c, void* stream) {

@@ -67,9 +67,14 @@ struct WinPlan {
   HostArray<uint16_t> col, row;  // filled by the planning threads (not zeroed first)
   HostArray<int64_t> src;
   // long rows split into segments: the rows (device order), and per row the
-  // ids of its segments' partials in chunk order (CSR over srow)
+  // ids of its segments' partials in order (CSR over srow). The windowed
+  // plan's segments come first (nsrow_win rows, nsegs_win partials); rows
+  // that stay in tiles and are longer than kSplitNnz follow, as pieces of
+  // kPieceNnz nonzeros (step_tiles rebuilds that part for each tiling).
   std::vector<int32_t> srow, sptr, sids;
   int32_t nsegs = 0;
+  size_t nsrow_win = 0;
+  int32_t nsegs_win = 0;
   size_t chunks() const { return r0.size(); }
   // workgroups of the finishing kernel (kSegRows segmented rows each)
   size_t seg_items() const { return (srow.size() + kSegRows - 1) / kSegRows; }

@@ -101,10 +101,18 @@ struct Ctl {
 // Tile: rows [rb, re) of one CSR side with nonzeros [s, e).
 // lanes > 0: stream tile (e - s <= kTileCap, re - rb <= kBlock / lanes),
 // each row reduced from LDS by `lanes` threads; lanes == 0: one row longer
-// than kTileCap, reduced by the whole workgroup.
+// than kTileCap, reduced by the whole workgroup; lanes < 0 (step lists
+// only): a piece of a row longer than kSplitNnz, whose sum the workgroup
+// stores as segment partial `seg` for the finishing kernel.
 struct Tile {
-  int32_t rb, re, s, e, lanes, pad;
+  int32_t rb, re, s, e, lanes, seg;
 };
+
+// Rows longer than kSplitNnz that the step kernels take in tiles are split
+// into pieces of kPieceNnz nonzeros, one workgroup each, so that one long
+// row does not hold a single workgroup for the whole launch.
+constexpr int kSplitNnz = 16384;
+constexpr int kPieceNnz = 4096;
 
 // Windowed sparse products (FP32). Rows of one side whose gathered vector
 // entries fall into a few column ranges are taken in chunks of up to
@@ -241,7 +249,7 @@ struct WorkItem {
   int32_t s, e;   // nonzeros [s, e)
   int32_t lanes;  // see Tile
   int32_t slot;   // partial slot of this item: its tile's index in the LP's list
-  int32_t last;   // 1 (every tile has a partial slot of its own; no kernel reads it)
+  int32_t seg;    // lanes < 0 (a piece of a split long row): its segment partial; else -1
   int32_t first;  // 1 on the LP's first item of the list
 };
 
