@@ -97,10 +97,10 @@ extern "C" {
 #define OPDHG_PREP_AUTO 0   /* on the device for LPs of 2^20 nonzeros or more, else on the host;
                                a packed set whose nonzeros reach 2^20 in total is prepared on
                                the device when that matches the host bit for bit (pc_beta 1 or
-                               < 0, adaptive step) */
+                               < 0) */
 #define OPDHG_PREP_HOST 1   /* host threads (FP64) */
-#define OPDHG_PREP_DEVICE 2 /* device kernels (FP64), same results; not with OPDHG_STEP_CONSTANT,
-                               whose power iteration runs on the host */
+#define OPDHG_PREP_DEVICE 2 /* device kernels (FP64), same results (with OPDHG_STEP_CONSTANT the
+                               power iteration runs on the device too) */
 
 /* ---- restart scheme ---- */
 #define OPDHG_RESTART_ADAPTIVE 0 /* PDLP's KKT-based restarts, preconditioners kept (Section 3.2) */

@@ -168,9 +168,6 @@ int validate_params(const opdhg_params* p) {
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_rows must be in [0, 10240]");
   if (p->prep < OPDHG_PREP_AUTO || p->prep > OPDHG_PREP_DEVICE)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "prep must be OPDHG_PREP_AUTO, _HOST or _DEVICE");
-  if (p->prep == OPDHG_PREP_DEVICE && p->step_rule == OPDHG_STEP_CONSTANT)
-    return fail(OPDHG_ERR_INVALID_ARGUMENT,
-                "the constant step's power iteration needs host preparation");
   return OPDHG_OK;
 }
 
@@ -1114,8 +1111,8 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.nnz = lp->nnz;
   const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
   // device-side preparation: the rescaling and the scaled data on the GPU
-  out.dprep = p->step_rule != OPDHG_STEP_CONSTANT &&
-              (p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz));
+  out.dprep =
+      p->prep == OPDHG_PREP_DEVICE || (p->prep == OPDHG_PREP_AUTO && nnz >= kDevicePrepNnz);
   // A full host preparation needs the column index anyway: it is built
   // first and gives the column counts; sizing alone, and the device-side
   // preparation (which may build the structure on the device), count the
@@ -1156,6 +1153,10 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.prep_ruiz = p->ruiz_iters;
   out.prep_l2 = p->l2_rescale != 0;
   out.prep_beta = p->pc_beta;
+  out.prep_power = p->step_rule == OPDHG_STEP_CONSTANT;
+  out.prep_power_iters = p->power_iters;
+  out.prep_power_tol = p->power_tol;
+  out.prep_step_scale = p->step_scale;
   // device-side structure: with the device preparation and no windowed
   // chunks (whose planning needs the structure on the host), when every
   // column fits the device's per-column ordering
@@ -1342,7 +1343,7 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
     L.raw_u = take(8 * n);
     L.sr = take(8 * m);
     L.sc = take(8 * n);
-    L.pscr = take(8 * (4 * kPrepGrid + 3));
+    L.pscr = take(8 * kPrepScr);
     if (P.win_t.chunks()) L.wsrc_t = take(4 * P.win_t.src.size());
     if (P.win_a.chunks()) L.wsrc_a = take(4 * P.win_a.src.size());
   }
@@ -2053,6 +2054,9 @@ static int device_prepare(uint8_t* base, const SlotLayout& L, Prepared& P, int p
   c.n = (int32_t)P.n;
   c.nlong_a = (int32_t)P.cend_a[0];
   c.nlong_t = (int32_t)P.cend_t[0];
+  c.step_scale = P.prep_step_scale;
+  c.power_tol = P.prep_power_tol;
+  c.power_iters = P.prep_power_iters;
   int rc = 0;
   // Ruiz passes, the L2 pass, the Pock-Chambolle pass (Section 2), as on the host
   for (int it = 0; it < P.prep_ruiz && !rc; ++it)
@@ -2065,6 +2069,9 @@ static int device_prepare(uint8_t* base, const SlotLayout& L, Prepared& P, int p
     rc = prep_stats(c, stream, false, 1, P.prep_beta) |
          prep_stats(c, stream, true, 1, 2.0 - P.prep_beta) | prep_apply(c, stream);
   if (!rc) rc = prec == OPDHG_FP32 ? prep_finish<float>(c, stream) : prep_finish<double>(c, stream);
+  // the constant step's eta0 from the power iteration (after the scalars,
+  // whose eta0 it replaces)
+  if (!rc && P.prep_power) rc = power_norm(c, stream);
   if (rc) return fail(OPDHG_ERR_DEVICE, std::string("preparation kernels: ") + device_error_string());
   std::vector<double> dr(P.m), dc(P.n), sc(2);
   if (P.m) HIP_TRY(hipMemcpyAsync(dr.data(), c.dr, 8 * P.m, hipMemcpyDeviceToHost, stream));
@@ -2536,12 +2543,11 @@ int opdhg_solve(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
 // Parameters a packed set is prepared with. Under OPDHG_PREP_AUTO a set
 // whose nonzeros reach the device-preparation threshold in total is
 // prepared on the device, where that gives the host's numbers bit for bit
-// (Pock-Chambolle exponent 1 or none; not the constant step, whose power
-// iteration runs on the host), so every LP of the set still equals its
-// solo solve. The workspace sizing takes the same decision.
+// (Pock-Chambolle exponent 1 or none), so every LP of the set still equals
+// its solo solve. The workspace sizing takes the same decision.
 static opdhg_params batch_params(int count, const opdhg_lp* lps, const opdhg_params* p) {
   opdhg_params q = *p;
-  if (p->prep != OPDHG_PREP_AUTO || p->step_rule == OPDHG_STEP_CONSTANT) return q;
+  if (p->prep != OPDHG_PREP_AUTO) return q;
   if (!(p->pc_beta == 1.0 || p->pc_beta < 0.0)) return q;
   int64_t total = 0;
   for (int i = 0; i < count; ++i) total += lps[i].nnz;

@@ -2413,6 +2413,92 @@ __global__ __launch_bounds__(kBlock) void k_prep_stats(PrepCfg a, int tside, int
   }
 }
 
+// Power iteration on A~^T A~ for |A~|_2 (vanilla PDHG's constant step
+// needs tau sigma |A~|_2^2 < 1, Section 2), round by round as on the host:
+// v_0 = 1 / sqrt(n); each round forms av = A~ v and w = A~^T av, each row's
+// products added one at a time in stored order in double-double and
+// rounded once, with the entries formed from the raw values and the
+// diagonals by the host's expression; then lam = |w| and v = w / lam. It
+// stops after power_iters rounds, when lam moves by at most
+// power_tol * lam, or when w = 0. av lives in sr, w in sc, and v = w / lam
+// is formed where it is read. The rounds after the stop return at once.
+constexpr int kPwLam = 4 * kPrepGrid + 3, kPwDone = kPwLam + 1, kPwZero = kPwLam + 2;
+
+__global__ __launch_bounds__(kBlock) void k_power_av(PrepCfg a, int round) {
+  if (round == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.scr[kPwLam] = 0.0;
+      a.scr[kPwDone] = 0.0;
+      a.scr[kPwZero] = 0.0;
+    }
+  } else if (a.scr[kPwDone] != 0.0) {
+    return;
+  }
+  const double lam = round ? a.scr[kPwLam] : 1.0;
+  const double v0 = 1.0 / sqrt((double)a.n);
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.m; r += gridDim.x * kBlock) {
+    SeqDD acc;
+    for (int k = a.rp_a[r]; k < a.rp_a[r + 1]; ++k) {
+      const int c = a.ci_a[k];
+      const double sv = (a.raw_a[k] * a.dr[r]) * a.dc[c];
+      acc.add_prod(sv, round ? a.sc[c] / lam : v0);
+    }
+    a.sr[r] = acc.value();
+  }
+}
+
+// w = A~^T av (sc), and per-workgroup double-double partials of |w|^2 in
+// scr (kPrepGrid workgroups).
+__global__ __launch_bounds__(kBlock) void k_power_w(PrepCfg a, int round) {
+  __shared__ DD s_red[4];
+  if (round > 0 && a.scr[kPwDone] != 0.0) return;
+  DD p[1];
+  p[0] = dd_zero();
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+    SeqDD acc;
+    for (int k = a.rp_t[j]; k < a.rp_t[j + 1]; ++k) {
+      const int i = a.ci_t[k];
+      const double sv = (a.raw_t[k] * a.dr[i]) * a.dc[j];
+      acc.add_prod(sv, a.sr[i]);
+    }
+    const double w = acc.value();
+    a.sc[j] = w;
+    dd_add_prod(p[0], w, w);
+  }
+  block_sum<1>(p, s_red);
+  if (threadIdx.x == 0) {
+    a.scr[2 * blockIdx.x + 0] = p[0].hi;
+    a.scr[2 * blockIdx.x + 1] = p[0].lo;
+  }
+}
+
+// lam = |w| and the stopping test of the round (one thread).
+__global__ void k_power_step(PrepCfg a, int round) {
+  if (threadIdx.x != 0 || (round > 0 && a.scr[kPwDone] != 0.0)) return;
+  DD t = dd_zero();
+  for (int g = 0; g < kPrepGrid; ++g) t = dd_merge(t, DD{a.scr[2 * g], a.scr[2 * g + 1]});
+  const double lam_new = sqrt(dd_value(t));
+  if (lam_new == 0.0) {
+    a.scr[kPwZero] = 1.0;
+    a.scr[kPwDone] = 1.0;
+    return;
+  }
+  const double lam = a.scr[kPwLam];
+  const bool done = fabs(lam_new - lam) <= a.power_tol * lam_new;
+  a.scr[kPwLam] = lam_new;
+  if (done) a.scr[kPwDone] = 1.0;
+}
+
+// eta0 = step_scale / |A~|_2 (step_scale when the norm is 0) into the
+// control block and the scalars read back by the host.
+__global__ void k_power_final(PrepCfg a) {
+  if (threadIdx.x != 0) return;
+  const double nu = a.scr[kPwZero] != 0.0 ? 0.0 : sqrt(a.scr[kPwLam]);
+  const double eta0 = nu > 0.0 ? a.step_scale / nu : a.step_scale;
+  a.ctl->eta = eta0;
+  a.scr[4 * kPrepGrid + 1] = eta0;
+}
+
 // d_r /= sqrt(s_r), d_c /= sqrt(s_c), a zero statistic read as 1.
 __global__ __launch_bounds__(kBlock) void k_prep_apply(PrepCfg a) {
   const int tot = a.m + a.n;
@@ -2709,6 +2795,20 @@ int struct_build(const StructCfg& c, void* stream) {
   if (launched()) return -1;
   const int g2 = std::max(1, std::min(4096, (c.n + kBlock - 1) / kBlock));
   hipLaunchKernelGGL(k_struct_cols, dim3(g2), dim3(kBlock), 0, (hipStream_t)stream, c);
+  return launched();
+}
+
+int power_norm(const PrepCfg& c, void* stream) {
+  const int ga = std::max(1, std::min(4096, (c.m + kBlock - 1) / kBlock));
+  for (int r = 0; r < c.power_iters; ++r) {
+    hipLaunchKernelGGL(k_power_av, dim3(ga), dim3(kBlock), 0, (hipStream_t)stream, c, r);
+    if (launched()) return -1;
+    hipLaunchKernelGGL(k_power_w, dim3(kPrepGrid), dim3(kBlock), 0, (hipStream_t)stream, c, r);
+    if (launched()) return -1;
+    hipLaunchKernelGGL(k_power_step, dim3(1), dim3(64), 0, (hipStream_t)stream, c, r);
+    if (launched()) return -1;
+  }
+  hipLaunchKernelGGL(k_power_final, dim3(1), dim3(64), 0, (hipStream_t)stream, c);
   return launched();
 }
 

@@ -112,6 +112,10 @@ struct Prepared {
   int prep_ruiz = 0;
   bool prep_l2 = false;
   double prep_beta = -1.0;
+  // the constant step: the power iteration's limits and eta0's scale
+  bool prep_power = false;
+  int prep_power_iters = 0;
+  double prep_power_tol = 0.0, prep_step_scale = 1.0;
   HostArray<double> raw_a, raw_t;
   std::vector<double> raw_b, raw_c, raw_l, raw_u;
   // device-side structure (with dprep, no windows): both CSR copies are

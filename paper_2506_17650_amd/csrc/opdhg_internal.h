@@ -365,7 +365,8 @@ struct PrepCfg {
   double* dc;
   double* sr;  // row / column statistics of a pass
   double* sc;
-  double* scr;  // 4 * kPrepGrid norm partials, then amax bits, then eta0, omega0
+  double* scr;  // 4 * kPrepGrid norm partials, then amax bits, eta0, omega0, then the
+                // power iteration's lam, done and zero flags (kPrepScr doubles)
   void* va_a;
   void* va_t;
   void* b;
@@ -382,7 +383,12 @@ struct PrepCfg {
   Ctl* ctl;
   int32_t m, n;
   int32_t nlong_a, nlong_t;  // rows of more than 256 nonzeros (the first in device order)
+  // the constant step (vanilla PDHG): eta0 = step_scale / |A~|_2, the norm
+  // from power_iters rounds of power iteration stopped at power_tol
+  double step_scale, power_tol;
+  int32_t power_iters, pad;
 };
+constexpr int kPrepScr = 4 * kPrepGrid + 6;
 // Device-side structure of one slot (the host keeps only the row and
 // column lengths, the row-class orders and the tiles): the caller's CSR
 // goes up as given, and two kernels build both copies in device order.
@@ -418,6 +424,7 @@ int struct_build(const StructCfg& c, void* stream);
 // kind 0: maxima of |a~|, 1: sums of |a~|^e, 2: L2 norms
 int prep_stats(const PrepCfg& c, void* stream, bool tside, int kind, double e);
 int prep_apply(const PrepCfg& c, void* stream);  // dr /= sqrt(sr), dc /= sqrt(sc)
+int power_norm(const PrepCfg& c, void* stream);  // the constant step's eta0 (power iteration)
 template <typename V>
 int prep_finish(const PrepCfg& c, void* stream);
 // Sets the windowed kernels' LDS attribute (once per process); 0 on success.

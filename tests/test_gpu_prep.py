@@ -16,7 +16,8 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.params import default_params
+from oracle.params import default_params, vanilla_params
+from oracle.pdhg import spectral_norm_estimate
 from lpgen import block_angular_lp, config_lp
 from gpu_common import check_final_fp32, check_final_fp64, lib_params, say as _say
 
@@ -185,3 +186,23 @@ def test_device_prep_long_rows_and_columns(P, prec_name):
         host = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_HOST, **kw))
         dev = P.opdhg_solve(lp, P.opdhg_default_params(prep=P.OPDHG_PREP_DEVICE, **kw))
         _same(dev, host)
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_device_power_iteration_equals_host(P, prec_name):
+    """Vanilla PDHG (constant step): the power iteration for |A~|_2 runs on
+    the device after the device's rescaling. The solve equals the
+    host-prepared one bit for bit, and its step size is step_scale over the
+    oracle's estimate of the norm."""
+    prec = P.OPDHG_FP64 if prec_name == "fp64" else P.OPDHG_FP32
+    for name, lp in _lps().items():
+        _say(f"[prep power] {name} {prec_name}")
+        op = vanilla_params(1e-2, max_iter=1500)
+        host = P.opdhg_solve(lp, lib_params(P, op, precision=prec, prep=P.OPDHG_PREP_HOST))
+        dev = P.opdhg_solve(lp, lib_params(P, op, precision=prec, prep=P.OPDHG_PREP_DEVICE))
+        _same(dev, host)
+        slp = oracle.problem.rescale(lp, op.ruiz_iters, op.pc_beta, op.l2_rescale)
+        nu = spectral_norm_estimate(slp, op.power_iters, op.power_tol)
+        assert dev[2].eta == op.step_scale / nu, (name, dev[2].eta, op.step_scale / nu)
+        if prec == P.OPDHG_FP64:
+            check_final_fp64(dev, oracle.solve(lp, op), label=name)

@@ -207,13 +207,14 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     assert got == want
 
 
-def test_constant_step_needs_host_preparation():
-    # the power iteration behind the constant step runs on the host
+def test_constant_step_takes_device_preparation():
+    # the power iteration behind the constant step runs on the device too:
+    # the parameters are accepted and the slot is sized for the device's
+    # raw data, larger than a host-prepared slot
     lp = tiny_lp(seed=3)
-    p = P.opdhg_vanilla_params(0.0, prep=capi.OPDHG_PREP_DEVICE)
-    with pytest.raises(P.OpdhgError) as e:
-        P.opdhg_workspace_bytes(lp, p)
-    assert e.value.code == capi.OPDHG_ERR_INVALID_ARGUMENT
+    dev = P.opdhg_workspace_bytes(lp, P.opdhg_vanilla_params(0.0, prep=capi.OPDHG_PREP_DEVICE))
+    host = P.opdhg_workspace_bytes(lp, P.opdhg_vanilla_params(0.0, prep=capi.OPDHG_PREP_HOST))
+    assert dev > host
 
 
 def test_server_sequences_hold_at_most_64_attempts():
