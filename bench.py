@@ -191,9 +191,9 @@ def section_headline(P, args):
         f"{r['kernels']['dual']['achieved_GBs']:.0f} GB/s")
     # HBM traffic of each side from the committed counter summaries: the
     # primal side is the windowed kernel alone; the dual side is the windowed
-    # kernel, the tile kernel of the rows left in tiles (beside it) and the
-    # segmented linking rows' finish
-    parts = {"primal": ["k_primal_win"], "dual": ["k_dual_win", "k_dual", "k_dual_seg"]}
+    # kernel and the finish of the segmented rows (the linking rows, and the
+    # few block rows that no chunk takes); no A row is left in tiles
+    parts = {"primal": ["k_primal_win"], "dual": ["k_dual_win", "k_dual_seg"]}
     for side, names in parts.items():
         vals = [counter_traffic(nm, "cfg2", "fp32") for nm in names]
         k = r["kernels"][side]
@@ -218,7 +218,9 @@ def section_cfg1(P, args):
            "row_len_mean": round(shape["row_len_mean"], 2), "col_len_max": shape["col_len_max"],
            "note": "the matrix (5.6 MB in FP32) stays in the 256 MB MALL: GB/s here are "
                    "algorithmic bytes over kernel time, not HBM traffic"}
-    for name, prec in (("f32", P.OPDHG_FP32), ("f64", P.OPDHG_FP64)):
+    precs = {"f32": P.OPDHG_FP32, "f64": P.OPDHG_FP64}
+    for name in [q for q in args.cfg1_precisions.split(",") if q in precs]:
+        prec = precs[name]
         r = iterate_section(P, lp, prec, args, args.cfg1_steps, args.warmup, args.kernel_reps)
         log(f"[bench] cfg1 {name}: {r['iters'] / r['seconds']:.0f} iters/s, "
             f"{r['attempts'] / args.cfg1_steps:.2f} attempts per step")
@@ -622,7 +624,8 @@ def run(args) -> dict:
             "attempts_per_step": main["attempts"] / args.steps,
             "executed_fraction": main["attempts"] / (args.steps * SLOTS_PER_STEP),
             "attempts_per_s": att_s,
-            "windows": "automatic (every A^T row and every block row of A windowed)",
+            "windows": "automatic (every A^T row windowed; every A row in a windowed chunk or a "
+                       "segment of one)",
             "lr": args.lr, "phi": args.phi, "normalize": True,
         },
         "roofline": {
@@ -670,6 +673,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per row (0: per tile)")
     ap.add_argument("--workgroups", type=int, default=0, help="workgroups per launch (0: auto)")
     ap.add_argument("--cfg1-steps", type=int, default=20)
+    ap.add_argument("--cfg1-precisions", default="f32,f64",
+                    help="precisions of the power-law LP section (f32, f64 or both)")
     ap.add_argument("--batch-size", type=int, default=256)
     ap.add_argument("--batch-baseline", type=int, default=16)
     ap.add_argument("--tune-replays", type=int, default=4)
