@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -34,6 +35,27 @@ int fail(int code, const std::string& msg) {
 int host_threads() {
   const unsigned hw = std::thread::hardware_concurrency();
   return hw ? (int)hw : 1;
+}
+
+// f(b, lo, hi) for blocks b = 0..nb-1 of [0, items) (equal sizes), on up
+// to 16 host threads. The blocks depend only on items and nb, never on the
+// thread count, so work split this way gives the same result on any host.
+template <typename F>
+static void for_blocks(int64_t items, int nb, F&& f) {
+  const int nth = std::max(1, std::min({host_threads(), 16, nb}));
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (int b = next++; b < nb; b = next++) f(b, items * b / nb, items * (b + 1) / nb);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+}
+
+// Blocks for for_blocks: about 64k items each, at most 64.
+static int item_blocks(int64_t items) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, items / 65536));
 }
 
 int fail_hip(hipError_t e, const char* what) {
@@ -338,23 +360,20 @@ static void build_col_index(const opdhg_lp* lp, ColIndex& C, bool with_abs = tru
 // Entries per column (= row lengths of A^T), counted by row ranges in
 // parallel and added per column.
 static void column_counts(const opdhg_lp* lp, std::vector<int64_t>& len) {
-  const int64_t m = lp->m, n = lp->n, nnz = lp->nnz;
-  int nth = (int)std::max<int64_t>(
-      1, std::min<int64_t>({(int64_t)std::min(host_threads(), 16), m, nnz / 262144 + 1}));
-  nth = (int)std::max<int64_t>(1, std::min<int64_t>(nth, (int64_t)(1ll << 29) / (4 * (n + 1))));
-  std::vector<std::vector<int32_t>> cnt(nth);
-  std::vector<std::thread> pool;
-  auto count = [&](int t) {
-    cnt[t].assign(n, 0);
-    const int64_t k0 = lp->row_ptr[m * t / nth], k1 = lp->row_ptr[m * (t + 1) / nth];
-    for (int64_t k = k0; k < k1; ++k) cnt[t][lp->col_idx[k]]++;
-  };
-  for (int t = 1; t < nth; ++t) pool.emplace_back(count, t);
-  count(0);
-  for (auto& th : pool) th.join();
-  len.assign(n, 0);
-  for (int t = 0; t < nth; ++t)
-    for (int64_t j = 0; j < n; ++j) len[j] += cnt[t][j];
+  const int64_t m = lp->m, n = lp->n;
+  // one shared count per column, incremented atomically by blocks of rows
+  // (integer counts: the order of the increments does not matter)
+  std::vector<int32_t> cnt(n, 0);
+  int32_t* c = cnt.data();
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(64, lp->nnz / 131072));
+  for_blocks(m, nb, [&](int, int64_t i0, int64_t i1) {
+    for (int64_t k = lp->row_ptr[i0]; k < lp->row_ptr[i1]; ++k)
+      __atomic_fetch_add(c + lp->col_idx[k], 1, __ATOMIC_RELAXED);
+  });
+  len.resize(n);
+  for_blocks(n, item_blocks(n), [&](int, int64_t j0, int64_t j1) {
+    for (int64_t j = j0; j < j1; ++j) len[j] = cnt[j];
+  });
 }
 
 // Ruiz passes then one Pock-Chambolle pass (Section 2): per pass, each row
@@ -509,17 +528,57 @@ static double spectral_norm_with(const opdhg_lp* lp, const ColIndex& C,
 static int row_class(int64_t len) { return len > 256 ? 0 : (len > 32 ? 1 : 2); }
 
 // perm[new] = old, stable within each class; class_end[c] = end of class c.
+// Blocks of rows count their classes, then each block writes its rows of
+// each class at that class's offset for the block (a stable partition).
 static void class_order(const std::vector<int64_t>& len, std::vector<int32_t>& perm,
                         int64_t class_end[3]) {
   const int64_t rows = (int64_t)len.size();
-  int64_t cnt[3] = {0, 0, 0};
-  for (int64_t i = 0; i < rows; ++i) cnt[row_class(len[i])]++;
-  int64_t start[3] = {0, cnt[0], cnt[0] + cnt[1]};
-  class_end[0] = cnt[0];
-  class_end[1] = cnt[0] + cnt[1];
+  const int nb = item_blocks(rows);
+  std::vector<std::array<int64_t, 3>> cnt(nb, {0, 0, 0});
+  for_blocks(rows, nb, [&](int b, int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) cnt[b][row_class(len[i])]++;
+  });
+  int64_t tot[3] = {0, 0, 0};
+  for (int b = 0; b < nb; ++b)
+    for (int c = 0; c < 3; ++c) tot[c] += cnt[b][c];
+  class_end[0] = tot[0];
+  class_end[1] = tot[0] + tot[1];
   class_end[2] = rows;
+  std::vector<std::array<int64_t, 3>> at(nb);
+  int64_t run[3] = {0, tot[0], tot[0] + tot[1]};
+  for (int b = 0; b < nb; ++b)
+    for (int c = 0; c < 3; ++c) {
+      at[b][c] = run[c];
+      run[c] += cnt[b][c];
+    }
   perm.resize(rows);
-  for (int64_t i = 0; i < rows; ++i) perm[start[row_class(len[i])]++] = (int32_t)i;
+  for_blocks(rows, nb, [&](int b, int64_t i0, int64_t i1) {
+    std::array<int64_t, 3> w = at[b];
+    for (int64_t i = i0; i < i1; ++i) perm[w[row_class(len[i])]++] = (int32_t)i;
+  });
+}
+
+// rp[0] = 0, rp[i + 1] = rp[i] + len[perm[i]] (row pointers in device
+// order), as a two-pass blocked scan.
+static void device_row_ptr(const std::vector<int64_t>& len, const std::vector<int32_t>& perm,
+                           std::vector<int32_t>& rp) {
+  const int64_t rows = (int64_t)perm.size();
+  rp.assign(rows + 1, 0);
+  const int nb = item_blocks(rows);
+  std::vector<int64_t> sum(nb + 1, 0);
+  for_blocks(rows, nb, [&](int b, int64_t i0, int64_t i1) {
+    int64_t t = 0;
+    for (int64_t i = i0; i < i1; ++i) t += len[perm[i]];
+    sum[b + 1] = t;
+  });
+  for (int b = 0; b < nb; ++b) sum[b + 1] += sum[b];
+  for_blocks(rows, nb, [&](int b, int64_t i0, int64_t i1) {
+    int64_t t = sum[b];
+    for (int64_t i = i0; i < i1; ++i) {
+      t += len[perm[i]];
+      rp[i + 1] = (int32_t)t;
+    }
+  });
 }
 
 // Lanes per row for a stream tile whose longest row has max_len nonzeros:
@@ -1125,7 +1184,9 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   }
   // row lengths of A and of A^T (= column counts), device order by class
   std::vector<int64_t> len_a(m), len_t(n, 0);
-  for (int64_t i = 0; i < m; ++i) len_a[i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
+  for_blocks(m, item_blocks(m), [&](int, int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) len_a[i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
+  });
   if (have_index) {
     for (int64_t j = 0; j < n; ++j) len_t[j] = C.cstart[j + 1] - C.cstart[j];
   } else {
@@ -1133,10 +1194,8 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   }
   class_order(len_a, out.perm_a, out.cend_a);
   class_order(len_t, out.perm_t, out.cend_t);
-  out.rp_a.assign(m + 1, 0);
-  for (int64_t i = 0; i < m; ++i) out.rp_a[i + 1] = out.rp_a[i] + (int32_t)len_a[out.perm_a[i]];
-  out.rp_t.assign(n + 1, 0);
-  for (int64_t j = 0; j < n; ++j) out.rp_t[j + 1] = out.rp_t[j] + (int32_t)len_t[out.perm_t[j]];
+  device_row_ptr(len_a, out.perm_a, out.rp_a);
+  device_row_ptr(len_t, out.perm_t, out.rp_t);
   const int64_t cap = p->tile_nnz > 0 ? std::min<int64_t>(p->tile_nnz, kTileCap) : kTileCap;
   out.tiles_a = build_tiles(out.rp_a.data(), m, cap, p->lanes);
   out.tiles_t = build_tiles(out.rp_t.data(), n, cap, p->lanes);
