@@ -1393,6 +1393,12 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
     L.sptr_a = take(4 * P.win_a.sptr.size());
     L.sids_a = take(4 * P.win_a.sids.size());
   }
+  if (prec == OPDHG_FP32 && (P.win_t.chunks() || P.win_a.chunks())) {
+    L.has_evp = true;
+    L.evp_t0 = take(4 * n);
+    L.evp_t1 = take(4 * n);
+    L.evp_a = take(4 * m);
+  }
   if (P.dprep) {
     L.raw_a = take(8 * nnz);
     L.raw_t = take(8 * nnz);
@@ -1483,6 +1489,11 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
     d.wval_a = base + L.wval_a;
     d.wpass_a = reinterpret_cast<const WinPass*>(base + L.wpass_a);
     d.wrange_a = reinterpret_cast<const WinRange*>(base + L.wrange_a);
+  }
+  if (L.has_evp) {
+    d.evp_t0 = reinterpret_cast<float*>(base + L.evp_t0);
+    d.evp_t1 = reinterpret_cast<float*>(base + L.evp_t1);
+    d.evp_a = reinterpret_cast<float*>(base + L.evp_a);
   }
   if (!P.win_a.srow.empty()) {
     d.segp_a = base + L.segp_a;
@@ -1639,6 +1650,9 @@ int Group::enqueue(hipStream_t s, int attempts) {
   auto K = [&](auto tag) {
     using V = decltype(tag);
     auto evaluation = [&](int mid) {
+      // the opening evaluation of LPs with windowed chunks takes its sparse
+      // products from the windowed machinery; the guarded ones gather
+      if (mid == 0) rc |= Kernels<V>::eval_products(cfg, s);
       rc |= Kernels<V>::eval_t(cfg, s, mid);
       rc |= Kernels<V>::eval_a(cfg, s, mid);
       rc |= Kernels<V>::eval_decide(cfg, s, mid);
@@ -1957,6 +1971,7 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
     }
     cfg->sgrid_t = cfg->schunk_t = cfg->sgrid_a = cfg->schunk_a = 0;
     cfg->step_fixed = 0;
+    cfg->evprod = 0;
   } else {
     side_items(lps, preps, true, cap, &cfg->sgrid_t, &cfg->schunk_t, st, true);
     side_items(lps, preps, false, cap, &cfg->sgrid_a, &cfg->schunk_a, sa, true);
@@ -1968,6 +1983,10 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
     }
     if (nst == 0) cfg->sgrid_t = 0;  // every row windowed: no tile launch
     if (nsa == 0) cfg->sgrid_a = 0;
+    // 1: some LP has evaluation products; 2: every LP has them
+    int with = 0;
+    for (const LpDev& d : lps) with += d.evp_t0 != nullptr ? 1 : 0;
+    cfg->evprod = with == 0 ? 0 : (with == (int)lps.size() ? 2 : 1);
     // windowed chunks take the partial slots after the LP's step tiles
     auto wins = [&](bool tside, std::vector<WinItem>& out) {
       for (size_t i = 0; i < lps.size(); ++i) {

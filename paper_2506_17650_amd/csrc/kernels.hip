@@ -1803,8 +1803,10 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
     st.finish(r0 + r, part[r], q0, p);
     if (two) st.finish(r0 + r2, part[r2], q1, p);
   }
-  block_sum<NV, kWinWaves, true>(p, s_red);
-  store_partials<NV>(st.part(), st.stride(), it.slot, p);
+  if (st.part() != nullptr) {  // (a product run stores rows only)
+    block_sum<NV, kWinWaves, true>(p, s_red);
+    store_partials<NV>(st.part(), st.stride(), it.slot, p);
+  }
   st.commit();
 }
 
@@ -1848,8 +1850,10 @@ __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* li
 #pragma unroll
   for (int off = kSegLanes / 2; off > 0; off >>= 1) acc.merge_xor(off);
   if (on && lane == 0) st.finish(row, (V)acc.value(), pre, p);
-  block_sum<NV, kBlock / 64, Step::kPlain>(p, s_red);
-  store_partials<NV>(st.part(), st.stride(), it.slot, p);
+  if (st.part() != nullptr) {
+    block_sum<NV, kBlock / 64, Step::kPlain>(p, s_red);
+    store_partials<NV>(st.part(), st.stride(), it.slot, p);
+  }
   st.commit();
 }
 
@@ -1861,6 +1865,99 @@ __global__ __launch_bounds__(kBlock) void k_primal_seg(LaunchCfg cfg, int force)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_dual_seg(LaunchCfg cfg, int force) {
   seg_rows<V, DualStep<V>, DualPre<V>, 4>(cfg, cfg.seg_a, cfg.nseg_a, false, force);
+}
+
+// The opening evaluation's sparse products of an FP32 LP with windowed
+// chunks, one vector at a time, through the step machinery (tiles, windowed
+// chunks, segments): A^T y (WHICH 0) and A^T y_s / w (WHICH 1) over the rows
+// of A^T, A x_s / w over the rows of A. A row's sum goes to the LP's
+// product vector; no partial sums. The evaluation kernels then read the
+// products instead of gathering per nonzero. Only LPs whose evaluation is
+// due take part; a sum of the running sums is divided by w once per row
+// (the tile evaluation divides each gathered entry: the two differ by
+// FP32 rounding).
+struct ProdPre {};
+
+template <bool TSIDE, int WHICH>
+struct ProdStep {
+  static constexpr bool kPlain = true;
+  const LpDev* lp = nullptr;
+  gptr<const float> vecs[1] = {nullptr};
+  gptr<const int32_t> rp = nullptr, ci = nullptr;
+  gptr<const float> va = nullptr;
+  gptr<float> out = nullptr;
+  void* segp_ = nullptr;
+  double w = 0.0;
+  bool divide = false;
+
+  __device__ __forceinline__ bool begin(const LaunchCfg& cfg, const Ctl* ctl, int lpi, int, int) {
+    lp = &cfg.lps[lpi];
+    const gptr<const LpDev> L = gp(lp);
+    const gptr<const Ctl> g = gp(ctl);
+    float* const po = uni(TSIDE ? (WHICH ? L->evp_t1 : L->evp_t0) : L->evp_a);
+    const void* const pv0 = uni(TSIDE ? (WHICH ? L->ys[0] : L->y[0]) : L->xs[0]);
+    const void* const pv1 = uni(TSIDE ? (WHICH ? L->ys[1] : L->y[1]) : L->xs[1]);
+    const int32_t* const prp = uni(TSIDE ? L->rp_t : L->rp_a);
+    const int32_t* const pci = uni(TSIDE ? L->ci_t : L->ci_a);
+    const void* const pva = uni(TSIDE ? L->va_t : L->va_a);
+    void* const pseg = uni(TSIDE ? L->segp_t : L->segp_a);
+    const int status = uni(g->status), need = uni(g->need_eval), cur = uni(g->cur);
+    const double wv = uni(g->w);
+    if (!uni((int)(po != nullptr && status == kRunning && need != 0))) return false;
+    out = uni(gp(po));
+    vecs[0] = uni(gp(static_cast<const float*>(cur ? pv1 : pv0)));
+    rp = uni(gp(prp));
+    ci = uni(gp(pci));
+    va = uni(gp(static_cast<const float*>(pva)));
+    segp_ = uni(pseg);
+    w = wv;
+    divide = uni((int)((TSIDE ? WHICH == 1 : true) && wv > 0.0)) != 0;
+    return true;
+  }
+  __device__ __forceinline__ ProdPre load(int) const { return ProdPre{}; }
+  __device__ __forceinline__ void finish(int j, float sum, ProdPre&, DD (&)[1]) const {
+    stg(out, (uint32_t)j, divide ? (float)((double)sum / w) : sum);
+  }
+  __device__ __forceinline__ void commit() const {}
+  __device__ __forceinline__ double* part() const { return nullptr; }
+  __device__ __forceinline__ int stride() const { return 0; }
+  __device__ __forceinline__ void piece(int sid, const Acc<float>& a) const {
+    seg_store(segp_, sid, a);
+  }
+};
+
+template <bool TSIDE, int WHICH>
+__global__ __launch_bounds__(kBlock) void k_prod_tiles(LaunchCfg cfg) {
+  __shared__ SpmvShared<float, 1> sh;
+  __shared__ TilePartials<1> tp;
+  const double nodiv[1] = {0.0};
+  DD p[1];
+  dd_reset(p);
+  ProdStep<TSIDE, WHICH> st;
+  __shared__ WorkItem s_items[kItemWin];
+  run_chunk_spmv<float, 1, 1, true>(
+      TSIDE ? cfg.step_t : cfg.step_a, step_chunks(cfg, TSIDE), s_items, st.rp, st.ci, st.va,
+      st.vecs, nodiv,
+      [&](const WorkItem& it) { return st.begin(cfg, it.ctl, it.lp, it.first, 0); },
+      [&](int j) { return st.load(j); },
+      [&](int j, float (&acc)[1], ProdPre& q) { st.finish(j, acc[0], q, p); },
+      [&](double*& d, int& sd) {
+        d = st.part();
+        sd = st.stride();
+      },
+      [&]() {}, [&](int sid, const Acc<float>& a) { st.piece(sid, a); }, p, tp, sh);
+}
+
+template <bool TSIDE, int WHICH>
+__global__ __launch_bounds__(kWinBlock) void k_prod_win(LaunchCfg cfg) {
+  win_chunk<ProdStep<TSIDE, WHICH>, ProdPre, 1>(cfg, TSIDE ? cfg.win_t : cfg.win_a,
+                                               TSIDE ? cfg.nwin_t : cfg.nwin_a, TSIDE, 0);
+}
+
+template <bool TSIDE, int WHICH>
+__global__ __launch_bounds__(kBlock) void k_prod_seg(LaunchCfg cfg) {
+  seg_rows<float, ProdStep<TSIDE, WHICH>, ProdPre, 1>(cfg, TSIDE ? cfg.seg_t : cfg.seg_a,
+                                                      TSIDE ? cfg.nseg_t : cfg.nseg_a, TSIDE, 0);
 }
 
 __global__ __launch_bounds__(kWinBlock) void k_primal_win(LaunchCfg cfg, int force) {
@@ -2055,6 +2152,107 @@ __device__ __forceinline__ bool eval_step_skips(const LaunchCfg& cfg, int mid, b
   return mid != 0 && uni(cn->hint[mid & 1]) == 0;
 }
 
+// The evaluation's row terms (residuals, reduced costs, objectives,
+// distances to the anchor) for the current iterate (z = 0) and the average
+// (z = 1, when w > 0), added to double-double partials: over the rows of
+// A^T (EvalT, given (A^T y)_j and (A^T y_avg)_j) and of A (EvalA, given
+// (A x_avg)_i; A x of the current iterate is cached).
+template <typename V>
+struct EvalT {
+  gptr<const V> cc, lo, hi, x, xs, xa;
+  gptr<const double> dc;
+  gptr<const int8_t> bfin;
+  double w;
+  bool has_avg;
+  __device__ __forceinline__ EvalT(const LpDev& lp, const Ctl* c) {
+    const int cur = c->cur;
+    w = c->w;
+    has_avg = w > 0.0;
+    cc = gp(static_cast<const V*>(lp.c));
+    lo = gp(static_cast<const V*>(lp.l));
+    hi = gp(static_cast<const V*>(lp.u));
+    x = gp(static_cast<const V*>(lp.x[cur]));
+    xs = gp(static_cast<const V*>(lp.xs[cur]));
+    xa = gp(static_cast<const V*>(lp.xa));
+    dc = gp(lp.dc);
+    bfin = gp(lp.bfin);
+  }
+  __device__ __forceinline__ void row(int j, const V (&acc)[2], DD* p) const {
+    const double cj = (double)cc[j];
+    const int8_t bf = bfin[j];
+    const double lj = (double)lo[j], uj = (double)hi[j];
+    const double xaj = (double)xa[j];
+    // unrolled, so that the partials' indices are constants (a runtime
+    // index would put them in scratch memory)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      if (z == 1 && !has_avg) break;
+      const double xz = z == 0 ? (double)x[j] : (double)xs[j] / w;
+      double lam, rd;
+      reduced_cost(cj - (double)acc[z], bf, lam, rd);
+      const double rdu = rd / dc[j];
+      const double d = xz - xaj;
+      DD* q = p + kEvT * z;
+      dd_add_prod(q[0], rd, rd);
+      dd_add_prod(q[1], rdu, rdu);
+      if (bf & 1) dd_add_prod(q[2], lj, lam > 0.0 ? lam : 0.0);
+      if (bf & 2) dd_add_prod(q[3], uj, lam < 0.0 ? -lam : 0.0);
+      dd_add_prod(q[4], cj, xz);
+      dd_add_prod(q[5], d, d);
+    }
+  }
+};
+
+template <typename V>
+struct EvalA {
+  gptr<const V> b, y, ys, ya, Ax;
+  gptr<V> Axa;
+  gptr<const double> dr;
+  gptr<const int8_t> sense;
+  double w;
+  bool has_avg;
+  __device__ __forceinline__ EvalA(const LpDev& lp, const Ctl* c) {
+    const int cur = c->cur;
+    w = c->w;
+    has_avg = w > 0.0;
+    b = gp(static_cast<const V*>(lp.b));
+    y = gp(static_cast<const V*>(lp.y[cur]));
+    ys = gp(static_cast<const V*>(lp.ys[cur]));
+    ya = gp(static_cast<const V*>(lp.ya));
+    Ax = gp(static_cast<const V*>(lp.Ax[cur]));
+    Axa = gp(static_cast<V*>(lp.Axa));
+    dr = gp(lp.dr);
+    sense = gp(lp.sense);
+  }
+  __device__ __forceinline__ void row(int i, const V (&acc)[1], DD* p) const {
+    const double bi = (double)b[i];
+    const bool ineq = sense[i] != 0;
+    const double yai = (double)ya[i];
+    if (has_avg) Axa[i] = acc[0];
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {  // unrolled: constant partial indices
+      if (z == 1 && !has_avg) break;
+      const double ax = z == 0 ? (double)Ax[i] : (double)acc[0];
+      const double yz = z == 0 ? (double)y[i] : (double)ys[i] / w;
+      double rp = bi - ax;
+      if (ineq && rp < 0.0) rp = 0.0;
+      const double rpu = rp / dr[i];
+      const double d = yz - yai;
+      DD* q = p + kEvA * z;
+      dd_add_prod(q[0], rp, rp);
+      dd_add_prod(q[1], rpu, rpu);
+      dd_add_prod(q[2], bi, yz);
+      dd_add_prod(q[3], d, d);
+    }
+  }
+};
+
+// Whether an LP's opening evaluation takes precomputed products (then
+// k_eval_pre serves it and the tile kernels below skip it).
+__device__ __forceinline__ bool eval_pre(const LpDev& lp, int mid, bool tside) {
+  return mid == 0 && (tside ? lp.evp_t0 : lp.evp_a) != nullptr;
+}
+
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg, int mid) {
   __shared__ SpmvShared<V, 2> sh;
@@ -2074,49 +2272,18 @@ __global__ __launch_bounds__(kBlock) void k_eval_t(LaunchCfg cfg, int mid) {
     // the chunk's ordinal among those touching the LP
     const bool endc = last_of_lp(cfg.work_t, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
-    if (!eval_guard(c, mid)) {
+    const LpDev& lp = cfg.lps[it.lp];
+    if (!eval_guard(c, mid) || eval_pre(lp, mid, true)) {
       if (endc) dd_reset(p);
       continue;
     }
-    const LpDev& lp = cfg.lps[it.lp];
-    const int cur = c->cur;
-    const double w = c->w;
-    const bool has_avg = w > 0.0;
-    const gptr<const V> cc = gp(static_cast<const V*>(lp.c));
-    const gptr<const V> lo = gp(static_cast<const V*>(lp.l));
-    const gptr<const V> hi = gp(static_cast<const V*>(lp.u));
-    const gptr<const V> x = gp(static_cast<const V*>(lp.x[cur]));
-    const gptr<const V> xs = gp(static_cast<const V*>(lp.xs[cur]));
-    const gptr<const V> xa = gp(static_cast<const V*>(lp.xa));
-    const gptr<const double> dc = gp(lp.dc);
-    const gptr<const int8_t> bfin = gp(lp.bfin);
-    const gptr<const V> vecs[2] = {gp(static_cast<const V*>(lp.y[cur])),
-                                   gp(static_cast<const V*>(lp.ys[cur]))};
-    const double divs[2] = {0.0, has_avg ? w : -1.0};
-    spmv_tile<V, 2>(
-        it, gp(lp.rp_t), gp(lp.ci_t), gp(static_cast<const V*>(lp.va_t)), vecs, divs,
-        [&](int) { return 0; },
-        [&](int j, V (&acc)[2], int) {
-          const double cj = (double)cc[j];
-          const int8_t bf = bfin[j];
-          const double lj = (double)lo[j], uj = (double)hi[j];
-          const double xaj = (double)xa[j];
-          for (int z = 0; z < (has_avg ? 2 : 1); ++z) {
-            const double xz = z == 0 ? (double)x[j] : (double)xs[j] / w;
-            double lam, rd;
-            reduced_cost(cj - (double)acc[z], bf, lam, rd);
-            const double rdu = rd / dc[j];
-            const double d = xz - xaj;
-            DD* q = p + kEvT * z;
-            dd_add_prod(q[0], rd, rd);
-            dd_add_prod(q[1], rdu, rdu);
-            if (bf & 1) dd_add_prod(q[2], lj, lam > 0.0 ? lam : 0.0);
-            if (bf & 2) dd_add_prod(q[3], uj, lam < 0.0 ? -lam : 0.0);
-            dd_add_prod(q[4], cj, xz);
-            dd_add_prod(q[5], d, d);
-          }
-        },
-        sh);
+    const EvalT<V> E(lp, c);
+    const gptr<const V> vecs[2] = {gp(static_cast<const V*>(lp.y[c->cur])),
+                                   gp(static_cast<const V*>(lp.ys[c->cur]))};
+    const double divs[2] = {0.0, E.has_avg ? E.w : -1.0};
+    spmv_tile<V, 2>(it, gp(lp.rp_t), gp(lp.ci_t), gp(static_cast<const V*>(lp.va_t)), vecs,
+                    divs, [&](int) { return 0; },
+                    [&](int j, V (&acc)[2], int) { E.row(j, acc, p); }, sh);
     if (endc)
       flush_partials<2 * kEvT>(p, s_red, lp.part_t, lp.ntiles_t, ch - lp.item0_t / sc.chunk);
   }
@@ -2139,49 +2306,72 @@ __global__ __launch_bounds__(kBlock) void k_eval_a(LaunchCfg cfg, int mid) {
     // as in k_eval_t: one reduction per LP and chunk
     const bool endc = last_of_lp(cfg.work_a, wi, i0, sc.chunk, it.lp);
     const Ctl* c = it.ctl;
-    if (!eval_guard(c, mid)) {
+    const LpDev& lp = cfg.lps[it.lp];
+    if (!eval_guard(c, mid) || eval_pre(lp, mid, false)) {
       if (endc) dd_reset(p);
       continue;
     }
-    const LpDev& lp = cfg.lps[it.lp];
-    const int cur = c->cur;
-    const double w = c->w;
-    const bool has_avg = w > 0.0;
-    const gptr<const V> b = gp(static_cast<const V*>(lp.b));
-    const gptr<const V> y = gp(static_cast<const V*>(lp.y[cur]));
-    const gptr<const V> ys = gp(static_cast<const V*>(lp.ys[cur]));
-    const gptr<const V> ya = gp(static_cast<const V*>(lp.ya));
-    const gptr<const V> Ax = gp(static_cast<const V*>(lp.Ax[cur]));
-    const gptr<V> Axa = gp(static_cast<V*>(lp.Axa));
-    const gptr<const double> dr = gp(lp.dr);
-    const gptr<const int8_t> sense = gp(lp.sense);
-    const gptr<const V> vecs[1] = {gp(static_cast<const V*>(lp.xs[cur]))};
-    const double divs[1] = {has_avg ? w : -1.0};
-    spmv_tile<V, 1>(
-        it, gp(lp.rp_a), gp(lp.ci_a), gp(static_cast<const V*>(lp.va_a)), vecs, divs,
-        [&](int) { return 0; },
-        [&](int i, V (&acc)[1], int) {
-          const double bi = (double)b[i];
-          const bool ineq = sense[i] != 0;
-          const double yai = (double)ya[i];
-          if (has_avg) Axa[i] = acc[0];
-          for (int z = 0; z < (has_avg ? 2 : 1); ++z) {
-            const double ax = z == 0 ? (double)Ax[i] : (double)acc[0];
-            const double yz = z == 0 ? (double)y[i] : (double)ys[i] / w;
-            double rp = bi - ax;
-            if (ineq && rp < 0.0) rp = 0.0;
-            const double rpu = rp / dr[i];
-            const double d = yz - yai;
-            DD* q = p + kEvA * z;
-            dd_add_prod(q[0], rp, rp);
-            dd_add_prod(q[1], rpu, rpu);
-            dd_add_prod(q[2], bi, yz);
-            dd_add_prod(q[3], d, d);
-          }
-        },
-        sh);
+    const EvalA<V> E(lp, c);
+    const gptr<const V> vecs[1] = {gp(static_cast<const V*>(lp.xs[c->cur]))};
+    const double divs[1] = {E.has_avg ? E.w : -1.0};
+    spmv_tile<V, 1>(it, gp(lp.rp_a), gp(lp.ci_a), gp(static_cast<const V*>(lp.va_a)), vecs,
+                    divs, [&](int) { return 0; },
+                    [&](int i, V (&acc)[1], int) { E.row(i, acc, p); }, sh);
     if (endc)
       flush_partials<2 * kEvA>(p, s_red, lp.part_a, lp.ntiles_a, ch - lp.item0_a / sc.chunk);
+  }
+}
+
+// The opening evaluation of LPs with precomputed products (FP32 windowed
+// LPs), streaming: the workgroups keep the evaluation lists' chunking, and
+// a workgroup whose chunk is the s-th of the nslot touching an LP takes the
+// s-th of nslot equal row ranges of that LP, a thread per row, and stores
+// slot s (the slots the tile kernels would fill, the same total).
+template <bool TSIDE>
+__global__ __launch_bounds__(kBlock) void k_eval_pre(LaunchCfg cfg) {
+  constexpr int NV = TSIDE ? 2 * kEvT : 2 * kEvA;
+  __shared__ DD s_red[4 * NV];
+  // the tile kernel of this side may not run (every LP of the set served
+  // here): the A^T one clears the next guarded step's hint as it would
+  (void)eval_step_skips(cfg, 0, TSIDE);
+  const SideChunks sc = side_chunks(cfg.counts, TSIDE);
+  const int ch = chunk_index(sc.grid);
+  if (ch < 0) return;
+  const WorkItem* work = TSIDE ? cfg.work_t : cfg.work_a;
+  const int i0 = ch * sc.chunk;
+  int prev = -1;
+  for (int wi = i0; wi < i0 + sc.chunk; ++wi) {
+    const int lpi = uni(work[wi].lp);
+    if (lpi < 0 || lpi == prev) continue;  // an LP's items are consecutive
+    prev = lpi;
+    const LpDev& lp = cfg.lps[lpi];
+    const Ctl* c = lp.ctl;
+    if (!uni((int)(eval_guard(c, 0) && eval_pre(lp, 0, TSIDE)))) continue;
+    const int c0 = (TSIDE ? lp.item0_t : lp.item0_a) / sc.chunk;
+    const int ns = TSIDE ? lp.nslot_t : lp.nslot_a;
+    const int slot = ch - c0;
+    const int64_t rows = TSIDE ? lp.n : lp.m;
+    const int r0 = (int)(rows * slot / ns), r1 = (int)(rows * (slot + 1) / ns);
+    DD p[NV];
+    dd_reset(p);
+    if constexpr (TSIDE) {
+      const EvalT<float> E(lp, c);
+      const gptr<const float> e0 = gp(static_cast<const float*>(lp.evp_t0));
+      const gptr<const float> e1 = gp(static_cast<const float*>(lp.evp_t1));
+      for (int j = r0 + (int)threadIdx.x; j < r1; j += kBlock) {
+        const float acc[2] = {ldg(e0, (uint32_t)j), ldg(e1, (uint32_t)j)};
+        E.row(j, acc, p);
+      }
+      flush_partials<NV>(p, s_red, lp.part_t, lp.ntiles_t, slot);
+    } else {
+      const EvalA<float> E(lp, c);
+      const gptr<const float> e = gp(static_cast<const float*>(lp.evp_a));
+      for (int i = r0 + (int)threadIdx.x; i < r1; i += kBlock) {
+        const float acc[1] = {ldg(e, (uint32_t)i)};
+        E.row(i, acc, p);
+      }
+      flush_partials<NV>(p, s_red, lp.part_a, lp.ntiles_a, slot);
+    }
   }
 }
 
@@ -2709,9 +2899,11 @@ static int win_attributes() {
   std::call_once(once, [] {
     err = hipFuncSetAttribute((const void*)k_primal_win,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLds);
-    if (err == hipSuccess)
-      err = hipFuncSetAttribute((const void*)k_dual_win,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLds);
+    const void* more[] = {(const void*)k_dual_win, (const void*)k_prod_win<true, 0>,
+                          (const void*)k_prod_win<true, 1>, (const void*)k_prod_win<false, 0>};
+    for (const void* f : more)
+      if (err == hipSuccess)
+        err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLds);
   });
   if (err != hipSuccess) g_last_device_error = err;
   return err == hipSuccess ? 0 : -1;
@@ -2763,11 +2955,67 @@ int Kernels<V>::learn_flush(const LaunchCfg& c, void* stream) {
   OPDHG_LAUNCH(k_learn_flush<V>, c.launch_ta, c);
 }
 template <typename V>
+int Kernels<V>::eval_products(const LaunchCfg& c, void* stream) {
+  if (!c.evprod) return 0;
+  if constexpr (!std::is_same<V, float>::value) {
+    return -1;
+  } else {
+    if (win_attributes()) return -1;
+    hipStream_t q = (hipStream_t)stream;
+    // one vector at a time: its tiles and windowed chunks, then the
+    // segments, whose partials both write
+    auto side = [&](auto tside, auto which) -> int {
+      constexpr bool T = decltype(tside)::value;
+      constexpr int W = decltype(which)::value;
+      const int sg = T ? c.sgrid_t : c.sgrid_a, nw = T ? c.nwin_t : c.nwin_a;
+      const int ns = T ? c.nseg_t : c.nseg_a;
+      if (sg > 0) {
+        hipLaunchKernelGGL((k_prod_tiles<T, W>), dim3(sg), dim3(kBlock), 0, q, c);
+        if (launched()) return -1;
+      }
+      if (nw > 0) {
+        hipLaunchKernelGGL((k_prod_win<T, W>), dim3(nw), dim3(kWinBlock), kWinLds, q, c);
+        if (launched()) return -1;
+      }
+      if (ns > 0) {
+        hipLaunchKernelGGL((k_prod_seg<T, W>), dim3(ns), dim3(kBlock), 0, q, c);
+        if (launched()) return -1;
+      }
+      return 0;
+    };
+    using t_ = std::true_type;
+    using f_ = std::false_type;
+    if (side(t_{}, std::integral_constant<int, 0>{})) return -1;
+    if (side(t_{}, std::integral_constant<int, 1>{})) return -1;
+    return side(f_{}, std::integral_constant<int, 0>{});
+  }
+}
+
+// The opening evaluation of a set with evaluation products: the streaming
+// kernel for the LPs that have them, the tile kernel for the others (not
+// launched when every LP has them).
+template <typename V>
 int Kernels<V>::eval_t(const LaunchCfg& c, void* stream, int mid) {
+  if constexpr (std::is_same<V, float>::value) {
+    if (mid == 0 && c.evprod) {
+      hipLaunchKernelGGL(k_eval_pre<true>, dim3(c.launch_t), dim3(kBlock), 0,
+                         (hipStream_t)stream, c);
+      if (launched()) return -1;
+      if (c.evprod == 2) return 0;
+    }
+  }
   OPDHG_LAUNCH(k_eval_t<V>, c.launch_t, c, mid);
 }
 template <typename V>
 int Kernels<V>::eval_a(const LaunchCfg& c, void* stream, int mid) {
+  if constexpr (std::is_same<V, float>::value) {
+    if (mid == 0 && c.evprod) {
+      hipLaunchKernelGGL(k_eval_pre<false>, dim3(c.launch_a), dim3(kBlock), 0,
+                         (hipStream_t)stream, c);
+      if (launched()) return -1;
+      if (c.evprod == 2) return 0;
+    }
+  }
   OPDHG_LAUNCH(k_eval_a<V>, c.launch_a, c, mid);
 }
 template <typename V>

@@ -152,6 +152,9 @@ struct SlotLayout {
   size_t wcol_a = 0, wrow_a = 0, wval_a = 0, wpass_a = 0, wrange_a = 0;
   size_t segp_t = 0, srow_t = 0, sptr_t = 0, sids_t = 0;  // segmented rows (0 when none)
   size_t segp_a = 0, srow_a = 0, sptr_a = 0, sids_a = 0;
+  // the opening evaluation's sparse products (FP32 with windowed chunks)
+  bool has_evp = false;
+  size_t evp_t0 = 0, evp_t1 = 0, evp_a = 0;
   // device-side preparation (0 when the host prepares)
   size_t raw_a = 0, raw_t = 0, raw_b = 0, raw_c = 0, raw_l = 0, raw_u = 0, sr = 0, sc = 0;
   size_t pscr = 0, wsrc_t = 0, wsrc_a = 0;

@@ -234,6 +234,13 @@ struct LpDev {
   const int32_t* srow_a;
   const int32_t* sptr_a;
   const int32_t* sids_a;
+  // FP32 LPs with windowed chunks: the opening evaluation's sparse
+  // products, computed by the windowed machinery before the evaluation
+  // kernels read them (A^T y, A^T y_avg over n; A x_avg over m); null
+  // otherwise (the evaluation kernels then gather per nonzero)
+  float* evp_t0;
+  float* evp_t1;
+  float* evp_a;
 };
 
 // A set of LPs launched together. A work item is one tile of one LP, with
@@ -310,7 +317,7 @@ struct LaunchCfg {
   int sgrid_t, schunk_t, sgrid_a, schunk_a;
   int nwin_t, nwin_a;  // windowed chunks per side (launch grid rounded up to 8)
   int step_fixed;
-  int pad_;
+  int evprod;  // LPs of the set with evaluation products (evp_*): 0 none, 1 some, 2 all
   const SegItem* seg_t;  // segmented long rows, finished after the windowed chunks
   const SegItem* seg_a;
   int nseg_t, nseg_a;
@@ -335,6 +342,10 @@ struct Kernels {
   static int learn_flush(const LaunchCfg& c, void* stream);
   // mid: 0 for the evaluation opening a launch sequence, b > 0 for the b-th
   // guarded evaluation step inside it (see Counts::hint)
+  // the opening evaluation's sparse products of LPs with windowed chunks
+  // (FP32; nothing to launch otherwise): tiles, windowed chunks and
+  // segments of each side, one vector at a time
+  static int eval_products(const LaunchCfg& c, void* stream);
   static int eval_t(const LaunchCfg& c, void* stream, int mid);
   static int eval_a(const LaunchCfg& c, void* stream, int mid);
   static int eval_decide(const LaunchCfg& c, void* stream, int mid);
