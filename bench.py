@@ -30,13 +30,16 @@ reductions, data resident in HBM. The same JSON line carries:
                 continuous-batching server (FP32), against plain FP64 PDHG
                 served first-in first-out one at a time through the same
                 server machinery (one LP at a time); p50 / p99 latency
+  cfg2lit       (on request: --sections ...,cfg2lit) the block-angular LP
+                with linking rows of the literal 2% density (102,400
+                nonzeros each, nnz ~235M; minutes to generate)
   variants      (on request: --sections ...,variants) the paper's variant
                 matrix with #Opt, SGM10 / mean iterations, GM / mean time
                 and #Imp / #Wors on a mixed synthetic set, for restarted
                 adaptive PDHG and for vanilla PDHG
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--sections cfg1,batch,serving[,variants]]
+                       [--sections cfg1,batch,serving[,cfg2lit][,variants]]
 """
 
 from __future__ import annotations
@@ -155,9 +158,17 @@ def iterate_section(P, lp, prec, args, steps, warmup, reps):
     sess.replay(warmup)
     _, _, _, _, st0 = sess.state()
     torch.cuda.synchronize()
+    # the K timed replays in up to 5 runs of consecutive replays, each
+    # bracketed by a synchronization, for the spread of the rate
+    nrun = max(1, min(5, steps))
+    sizes = [steps // nrun + (1 if r < steps % nrun else 0) for r in range(nrun)]
+    run_ms = []
     t0 = time.perf_counter()
-    sess.replay(steps)
-    torch.cuda.synchronize()
+    for sz in sizes:
+        ta = time.perf_counter()
+        sess.replay(sz)
+        torch.cuda.synchronize()
+        run_ms.append((time.perf_counter() - ta) * 1e3 / sz)
     dt = time.perf_counter() - t0
     _, _, _, _, st1 = sess.state()
     if st1.status != P.capi.OPDHG_STATUS_RUNNING:
@@ -167,8 +178,12 @@ def iterate_section(P, lp, prec, args, steps, warmup, reps):
     vb = 4 if prec == P.OPDHG_FP32 else 8
     kb = {"primal": primal_kernel_bytes(lp, vb), "dual": dual_kernel_bytes(lp, vb)}
     km = {"primal": primal_ms, "dual": dual_ms}
+    import numpy as np
+    runs = {"runs": len(run_ms), "ms_per_step_median": float(np.median(run_ms)),
+            "ms_per_step_min": min(run_ms), "ms_per_step_max": max(run_ms)}
     return {
         "iters": st1.k - st0.k, "attempts": st1.attempts - st0.attempts, "seconds": dt,
+        "runs": runs,
         "kernels": {k: {"avg_launch_ms": km[k], "bytes_per_launch": kb[k],
                         "achieved_GBs": kb[k] / (km[k] * 1e-3) / 1e9,
                         "frac": kb[k] / (km[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
@@ -229,8 +244,36 @@ def section_cfg1(P, args):
                      "attempts_per_step": r["attempts"] / args.cfg1_steps,
                      "slots_per_step": SLOTS_PER_STEP,
                      "executed_fraction": r["attempts"] / (args.cfg1_steps * SLOTS_PER_STEP),
-                     "steps": args.cfg1_steps, "kernels": r["kernels"]}
+                     "steps": args.cfg1_steps, "timing_runs": r["runs"], "kernels": r["kernels"]}
     return out
+
+
+def section_cfg2lit(P, args):
+    """cfg2 with linking rows of the literal 2% density (102,400 nonzeros
+    each, nnz ~235M): the long rows run as segments of the windowed chunks.
+    Opt-in (--sections ...,cfg2lit): generating it takes minutes."""
+    from lpgen import config_lp
+    from lpgen.generators import summary
+    t = time.perf_counter()
+    lp = config_lp("cfg2lit", log=lambda msg: log(f"[bench] cfg2lit: {msg} "
+                                                  f"({time.perf_counter() - t:.0f}s)"))
+    log(f"[bench] cfg2lit: m={lp.m} n={lp.n} nnz={lp.nnz} "
+        f"(generated in {time.perf_counter() - t:.1f}s)")
+    steps = max(2, args.steps // 4)
+    r = iterate_section(P, lp, P.OPDHG_FP32, args, steps, 1, max(3, args.kernel_reps // 10))
+    b_att = r["kernels"]["primal"]["bytes_per_launch"] + r["kernels"]["dual"]["bytes_per_launch"]
+    att_s = r["attempts"] / r["seconds"]
+    log(f"[bench] cfg2lit: {r['iters'] / r['seconds']:.0f} iters/s, primal "
+        f"{r['kernels']['primal']['achieved_GBs']:.0f} GB/s, dual "
+        f"{r['kernels']['dual']['achieved_GBs']:.0f} GB/s")
+    shape = summary(lp)
+    return {"workload": "cfg2 with 2% dense linking rows (102,400 nonzeros each)",
+            "m": lp.m, "n": lp.n, "nnz": lp.nnz, "row_len_max": shape.get("row_len_max"),
+            "value": r["iters"] / r["seconds"], "unit": "PDHG iters/s", "dtype": "f32",
+            "steps": steps, "attempts_per_s": att_s, "timing_runs": r["runs"],
+            "kernels": r["kernels"],
+            "iteration": {"bytes_per_attempt": b_att, "achieved_GBs": b_att * att_s / 1e9,
+                          "frac": b_att * att_s / 1e9 / HBM_PEAK_GBS}}
 
 
 def section_batch(P, args):
@@ -624,6 +667,7 @@ def run(args) -> dict:
             "attempts_per_step": main["attempts"] / args.steps,
             "executed_fraction": main["attempts"] / (args.steps * SLOTS_PER_STEP),
             "attempts_per_s": att_s,
+            "timing_runs": main["runs"],
             "windows": "automatic (every A^T row windowed; every A row in a windowed chunk or a "
                        "segment of one)",
             "lr": args.lr, "phi": args.phi, "normalize": True,
@@ -648,6 +692,8 @@ def run(args) -> dict:
     }
     if "cfg1" in sections:
         out["cfg1"] = section_cfg1(P, args)
+    if "cfg2lit" in sections:
+        out["cfg2lit"] = section_cfg2lit(P, args)
     if "batch" in sections:
         out["batch"] = section_batch(P, args)
     if "serving" in sections:

@@ -285,7 +285,7 @@ def random_lp(seed, m: int, n: int, *, degree=("fixed", 5), eq_frac: float = 0.5
 def block_angular_lp(seed, *, blocks: int = 64, block_rows: int = 30000,
                      block_cols: int = 80000, col_degree: int = 6, link_rows: int = 2000,
                      link_nnz_per_row: int = 2140, bounds=("box_uniform", 1.0, 100.0),
-                     name: str = "") -> LP:
+                     name: str = "", log=None) -> LP:
     """Block-angular, flow-like LP.
 
     Each diagonal block is block_rows x block_cols with col_degree distinct
@@ -293,8 +293,10 @@ def block_angular_lp(seed, *, blocks: int = 64, block_rows: int = 30000,
     equalities. link_rows dense-ish linking >= rows follow, each with
     link_nnz_per_row distinct random columns holding N(0, 1).
     Draw order: block (column, row) pairs, signs, linking (row, column)
-    pairs, linking values, bounds, planted optimum.
+    pairs, linking values, bounds, planted optimum. ``log`` (optional)
+    receives a line after each stage.
     """
+    say = log if log is not None else (lambda msg: None)
     rng = _rng(seed)
     m = blocks * block_rows + link_rows
     n = blocks * block_cols
@@ -304,15 +306,18 @@ def block_angular_lp(seed, *, blocks: int = 64, block_rows: int = 30000,
     blk = cols_b // block_cols
     rows_b = rows_local + blk * block_rows
     signs = np.where(rng.random(cols_b.size) < 0.5, -1.0, 1.0)
+    say(f"block entries drawn ({cols_b.size})")
     k = min(link_nnz_per_row, n)
     lrows, lcols = _distinct_draws(rng, link_rows, np.full(link_rows, k, dtype=np.int64), n)
     lvals = rng.standard_normal(lrows.size)
+    say(f"linking entries drawn ({lrows.size})")
     rows = np.concatenate([rows_b, lrows + blocks * block_rows])
     cols = np.concatenate([cols_b, lcols])
     vals = np.concatenate([signs, lvals])
     del rows_b, cols_b, lrows, lcols, signs, lvals, blk, rows_local
     row_ptr, col_idx, val = _to_csr(m, n, rows, cols, vals)
     del rows, cols, vals
+    say("CSR built")
     sense = np.zeros(m, dtype=np.int8)
     sense[blocks * block_rows:] = 1
     l, u = _bounds(rng, n, bounds)
@@ -357,7 +362,7 @@ def tiny_lp(seed, m: int = 3, n: int = 4, *, m_eq: int = 1, density: float = 0.8
 # the five workload families
 # ---------------------------------------------------------------------------
 
-_CONFIGS = ("cfg0", "cfg1", "cfg2", "cfg3", "cfg4")
+_CONFIGS = ("cfg0", "cfg1", "cfg2", "cfg2lit", "cfg3", "cfg4")
 
 
 def config_names() -> tuple[str, ...]:
@@ -368,7 +373,7 @@ def _scaled(v: int, scale: float, lo: int = 1) -> int:
     return max(lo, int(round(v * scale)))
 
 
-def config_lp(name: str, seed=None, scale: float = 1.0, index: int = 0) -> LP:
+def config_lp(name: str, seed=None, scale: float = 1.0, index: int = 0, log=None) -> LP:
     """One LP of a workload family, optionally shrunk by ``scale``.
 
     cfg0  random sparse LP, m=200 (100 '=', 100 '>='), n=500, 5 nonzeros
@@ -378,6 +383,8 @@ def config_lp(name: str, seed=None, scale: float = 1.0, index: int = 0) -> LP:
           [1e-3, 1e3]; bounds 50% [0, inf), 30% [0, U(1,100)], 20% free.
     cfg2  block-angular LP: 64 blocks of 30k x 80k, 6 nonzeros per column,
           +-1 entries, plus 2k linking rows of ~2140 N(0,1) entries.
+    cfg2lit  cfg2 with linking rows of the literal 2% density: 102,400
+          entries each (nnz ~235M; the same blocks as cfg2).
     cfg3  one LP of the 256-LP batch (``index`` picks it): m log-uniform in
           [1k, 50k], n=2m, 3..8 nonzeros per column, 50% '=', bounds
           [0, U(1,100)].
@@ -409,6 +416,9 @@ def config_lp(name: str, seed=None, scale: float = 1.0, index: int = 0) -> LP:
         return block_angular_lp(seed, blocks=blocks, block_rows=br, block_cols=bc,
                                 col_degree=6, link_rows=link_rows, link_nnz_per_row=link_nnz,
                                 name=f"cfg2-s{seed}-x{scale:g}")
+    if name == "cfg2lit":
+        seed = 2 if seed is None else seed
+        return block_angular_lp(seed, link_nnz_per_row=102400, name=f"cfg2lit-s{seed}", log=log)
     if name == "cfg3":
         rng = _rng((3, index) if seed is None else seed)
         m = int(round(math.exp(rng.uniform(math.log(1000), math.log(50000)))))
