@@ -14,6 +14,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1989,18 +1990,52 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
     cfg->evprod = with == 0 ? 0 : (with == (int)lps.size() ? 2 : 1);
     // windowed chunks take the partial slots after the LP's step tiles
     auto wins = [&](bool tside, std::vector<WinItem>& out) {
+      std::vector<double> work;  // per chunk: entries, staged buckets and rows, in entry units
       for (size_t i = 0; i < lps.size(); ++i) {
         const WinPlan& W = tside ? preps[i]->win_t : preps[i]->win_a;
         int32_t& ns = tside ? lps[i].nslot_st : lps[i].nslot_sa;
-        for (size_t c = 0; c < W.chunks(); ++c)
+        for (size_t c = 0; c < W.chunks(); ++c) {
           out.push_back(WinItem{lps[i].ctl, (int32_t)i, ns + (int32_t)c, W.r0[c], W.r1[c],
                                 W.pass0[c], W.npass[c], W.nseg[c], W.seg0[c]});
+          double w = 4.0 * (W.r1[c] - W.r0[c] + W.nseg[c]);  // a row's vectors: ~4 entries
+          for (int32_t q = W.pass0[c]; q < W.pass0[c] + W.npass[c]; ++q) {
+            w += W.passes[q].e1 - W.passes[q].e0;
+            for (int32_t g = W.passes[q].range0; g < W.passes[q].range0 + W.passes[q].nrange; ++g)
+              w += 0.5 * W.ranges[g].len;  // a staged float: half an entry's bytes
+          }
+          work.push_back(w);
+        }
         ns += (int32_t)W.chunks();
       }
-      // a multiple of 8 workgroups (above 8) spreads consecutive chunks of
-      // one LP over one XCD at a time
-      if (out.size() > 8)
-        while (out.size() % 8) out.push_back(WinItem{nullptr, -1, 0, 0, 0, 0, 0, 0, 0});
+      if (out.size() <= 8) return;
+      // The kernels give chunk c of a grid of 8L to XCD floor(c / L) (see
+      // chunk_index), each XCD taking its L chunks in order. The list is
+      // cut into 8 contiguous runs of about equal work (a packed set's LPs
+      // differ in size; contiguity keeps an LP's chunks, which stage the
+      // same vector, on one XCD's L2), each run ordered by decreasing work
+      // so that the small chunks fill the end of the launch, and padded to
+      // the longest run.
+      const double total = std::accumulate(work.begin(), work.end(), 0.0);
+      std::vector<std::vector<size_t>> run(8);
+      double acc = 0.0;
+      for (size_t c = 0; c < out.size(); ++c) {
+        const int x = std::min(7, (int)((acc + 0.5 * work[c]) * 8.0 / total));
+        run[x].push_back(c);
+        acc += work[c];
+      }
+      size_t L = 0;
+      for (auto& r : run) {
+        std::stable_sort(r.begin(), r.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+        L = std::max(L, r.size());
+      }
+      std::vector<WinItem> lay;
+      lay.reserve(8 * L);
+      const WinItem pad{nullptr, -1, 0, 0, 0, 0, 0, 0, 0};
+      for (auto& r : run) {
+        for (size_t c : r) lay.push_back(out[c]);
+        for (size_t k = r.size(); k < L; ++k) lay.push_back(pad);
+      }
+      out.swap(lay);
     };
     wins(true, vt);
     wins(false, va);
