@@ -830,12 +830,14 @@ static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t
         seg_entries[c].push_back({k, local[c]});
       }
   }
-  // entries of each pass of each chunk: its own rows in order, then its
-  // segments in order; padded to whole kWinNpt groups. The chunks are
-  // independent, so they are spread over up to 16 host threads: each chunk
-  // first counts its entries per pass, the passes' ranges follow in chunk
-  // order, and then every chunk writes its own ranges, entry for entry as
-  // one serial pass over the chunks would.
+  // Each pass of each chunk: the rows with entries in it (own rows, then
+  // segments), longest first (equal counts in row order), cut into slices of
+  // kWinSlice rows. A slice's entries go k-major, each row's in CSR order,
+  // padded to the slice's longest row with zero entries of window column 0.
+  // The chunks are independent, so they are spread over up to 16 host
+  // threads: each chunk first counts its slices and entries per pass, the
+  // passes' ranges follow in chunk order, and then every chunk writes its
+  // own ranges.
   auto for_chunks = [&](auto&& f) {
     std::atomic<int64_t> next{0};
     auto work = [&] {
@@ -855,65 +857,123 @@ static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t
     work();
     for (auto& th : pool) th.join();
   };
-  std::vector<int64_t> pass_cnt(W.passes.size(), 0);
+  // a chunk's rows per pass: entry counts (pass-major) and the order
+  struct PassRows {
+    int32_t nrows = 0;
+    std::vector<int32_t> cnt, order;
+    int32_t nact[kWinMaxPass] = {};
+  };
+  auto pass_rows = [&](int64_t c, const std::vector<int32_t>& bpass, PassRows& R) {
+    const int64_t a = W.r0[c], b = W.r1[c];
+    const int np = W.npass[c];
+    const int32_t nr = (int32_t)(b - a + W.nseg[c]);
+    R.nrows = nr;
+    R.cnt.assign((size_t)np * nr, 0);
+    for (int64_t r = a; r < b; ++r)
+      for (int64_t k = rp[r]; k < rp[r + 1]; ++k)
+        ++R.cnt[(size_t)bpass[ci[k] / kWinBucket] * nr + (r - a)];
+    for (const auto& e : seg_entries[c])
+      ++R.cnt[(size_t)bpass[ci[e.first] / kWinBucket] * nr + e.second];
+    R.order.resize((size_t)np * nr);
+    std::vector<int32_t> at;
+    for (int q = 0; q < np; ++q) {
+      // counting sort by count, descending; rows ascending within a count
+      const int32_t* cq = R.cnt.data() + (size_t)q * nr;
+      int32_t* oq = R.order.data() + (size_t)q * nr;
+      int32_t mx = 0;
+      for (int32_t r = 0; r < nr; ++r) mx = std::max(mx, cq[r]);
+      at.assign((size_t)mx + 1, 0);
+      for (int32_t r = 0; r < nr; ++r)
+        if (cq[r] > 0) ++at[mx - cq[r]];
+      int32_t s = 0;
+      for (int32_t v = 0; v <= mx; ++v) {
+        const int32_t k = at[v];
+        at[v] = s;
+        s += k;
+      }
+      for (int32_t r = 0; r < nr; ++r)
+        if (cq[r] > 0) oq[at[mx - cq[r]]++] = r;
+      R.nact[q] = s;
+    }
+  };
+  std::vector<int64_t> pass_slices(W.passes.size(), 0), pass_entries(W.passes.size(), 0);
   for_chunks([&](int64_t c, const std::vector<int32_t>& bpass, const std::vector<int32_t>&) {
-    int64_t* cnt = pass_cnt.data() + W.pass0[c];
-    for (int64_t r = W.r0[c]; r < W.r1[c]; ++r)
-      for (int64_t k = rp[r]; k < rp[r + 1]; ++k) ++cnt[bpass[ci[k] / kWinBucket]];
-    for (const auto& e : seg_entries[c]) ++cnt[bpass[ci[e.first] / kWinBucket]];
+    PassRows R;
+    pass_rows(c, bpass, R);
+    for (int q = 0; q < W.npass[c]; ++q) {
+      const int32_t* cq = R.cnt.data() + (size_t)q * R.nrows;
+      const int32_t* oq = R.order.data() + (size_t)q * R.nrows;
+      int64_t ns = 0, ne = 0;
+      for (int32_t i = 0; i < R.nact[q]; i += kWinSlice, ++ns) ne += (int64_t)kWinSlice * cq[oq[i]];
+      pass_slices[W.pass0[c] + q] = ns;
+      pass_entries[W.pass0[c] + q] = ne;
+    }
   });
-  int64_t total = 0;
+  std::vector<int64_t> pass_e0(W.passes.size(), 0);
+  int64_t nslice = 0, total = 0;
   for (size_t q = 0; q < W.passes.size(); ++q) {
-    // a pass with no entry keeps one zero entry
-    const int64_t len = std::max<int64_t>(pass_cnt[q], 1);
-    W.passes[q].e0 = (int32_t)total;
-    total += (len + kWinNpt - 1) / kWinNpt * kWinNpt;
-    W.passes[q].e1 = (int32_t)total;
+    W.passes[q].s0 = (int32_t)nslice;
+    nslice += pass_slices[q];
+    W.passes[q].s1 = (int32_t)nslice;
+    pass_e0[q] = total;
+    total += pass_entries[q];
   }
+  if (total > (int64_t)INT32_MAX || nslice * kWinSlice > (int64_t)INT32_MAX) {
+    W = WinPlan();  // beyond 32-bit entry offsets: no windows
+    return;
+  }
+  W.slices.resize(nslice);
+  W.lane.resize(nslice * kWinSlice);
   W.col.resize(total);
-  W.row.resize(total);
   W.src.resize(total);
   for_chunks([&](int64_t c, const std::vector<int32_t>& bpass, const std::vector<int32_t>& boff) {
-    // one scan of the chunk's entries, each to the cursor of its pass: own
-    // rows in order, then segments in order, within every pass
-    const int64_t a = W.r0[c], b = W.r1[c];
-    int64_t pos[kWinMaxPass];
-    uint16_t last_col[kWinMaxPass] = {}, last_row[kWinMaxPass] = {};
-    for (int q = 0; q < W.npass[c]; ++q) pos[q] = W.passes[W.pass0[c] + q].e0;
-    auto emit = [&](int64_t k, int64_t local) {
-      const int64_t bk = ci[k] / kWinBucket;
-      const int q = bpass[bk];
-      last_col[q] = (uint16_t)(boff[bk] + (ci[k] - bk * kWinBucket));
-      last_row[q] = (uint16_t)local;
-      W.col[pos[q]] = last_col[q];
-      W.row[pos[q]] = last_row[q];
-      W.src[pos[q]] = k;
-      ++pos[q];
-    };
-    for (int64_t r = a; r < b; ++r)
-      for (int64_t k = rp[r]; k < rp[r + 1]; ++k) emit(k, r - a);
-    for (const auto& e : seg_entries[c]) emit(e.first, e.second);
-    for (int q = 0; q < W.npass[c]; ++q) {
-      const WinPass& ps = W.passes[W.pass0[c] + q];
-      int64_t p = pos[q];
-      if (p == ps.e0) {  // the zero entry of an empty pass
-        W.col[p] = 0;
-        W.row[p] = 0;
-        W.src[p] = -1;
-        ++p;
-      }
-      for (; p < ps.e1; ++p) {
-        W.col[p] = last_col[q];
-        W.row[p] = last_row[q];
-        W.src[p] = -1;
+    PassRows R;
+    pass_rows(c, bpass, R);
+    const int np = W.npass[c];
+    const int32_t nr = R.nrows;
+    // each row's slice and lane in every pass, and its next entry there
+    std::vector<int32_t> place((size_t)np * nr, -1), fill((size_t)np * nr, 0);
+    for (int q = 0; q < np; ++q) {
+      const int64_t gq = W.pass0[c] + q;
+      const int32_t* cq = R.cnt.data() + (size_t)q * nr;
+      const int32_t* oq = R.order.data() + (size_t)q * nr;
+      int64_t e = pass_e0[gq];
+      for (int32_t i = 0, j = 0; i < R.nact[q]; i += kWinSlice, ++j) {
+        const int32_t S = W.passes[gq].s0 + j;
+        const int32_t len = cq[oq[i]];
+        W.slices[S] = WinSlice{(int32_t)e, len};
+        for (int l = 0; l < kWinSlice; ++l) {
+          const bool on = i + l < R.nact[q];
+          W.lane[(size_t)S * kWinSlice + l] = on ? (uint16_t)oq[i + l] : kWinNoRow;
+          if (on) place[(size_t)q * nr + oq[i + l]] = S * kWinSlice + l;
+        }
+        for (int64_t p = e; p < e + (int64_t)kWinSlice * len; ++p) {  // padding first
+          W.col[p] = 0;
+          W.src[p] = -1;
+        }
+        e += (int64_t)kWinSlice * len;
       }
     }
+    auto emit = [&](int64_t k, int32_t local) {
+      const int64_t bk = ci[k] / kWinBucket;
+      const int q = bpass[bk];
+      const int32_t pl = place[(size_t)q * nr + local];
+      const WinSlice& sl = W.slices[pl / kWinSlice];
+      const int64_t p = sl.e0 + (int64_t)fill[(size_t)q * nr + local]++ * kWinSlice + pl % kWinSlice;
+      W.col[p] = (uint16_t)(boff[bk] + (ci[k] - bk * kWinBucket));
+      W.src[p] = k;
+    };
+    const int64_t a = W.r0[c], b = W.r1[c];
+    for (int64_t r = a; r < b; ++r)
+      for (int64_t k = rp[r]; k < rp[r + 1]; ++k) emit(k, (int32_t)(r - a));
+    for (const auto& e : seg_entries[c]) emit(e.first, e.second);
   });
 }
 
 // Every index a windowed kernel derives from the plan stays in its
-// buffers: LDS columns inside their pass's staged length, chunk rows below
-// kWinRows, entry groups whole, staged ranges inside the vector.
+// buffers: LDS columns inside their pass's staged length, lane rows below
+// the chunk's rows, slice entries inside the entry arrays, staged ranges
+// inside the vector.
 static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
   for (size_t c = 0; c < W.chunks(); ++c) {
     const int64_t nrow = (int64_t)W.r1[c] - W.r0[c] + W.nseg[c];
@@ -923,9 +983,10 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
     for (int32_t q = W.pass0[c]; q < W.pass0[c] + W.npass[c]; ++q) {
       if (q < 0 || (size_t)q >= W.passes.size()) return false;
       const WinPass& ps = W.passes[q];
-      if (ps.e0 % kWinNpt || ps.e1 % kWinNpt || ps.e1 <= ps.e0) return false;
-      if ((size_t)ps.e1 > W.col.size() || ps.range0 < 0 || ps.nrange < 1 ||
-          (size_t)(ps.range0 + ps.nrange) > W.ranges.size())
+      if (ps.s0 < 0 || ps.s1 < ps.s0 || (size_t)ps.s1 > W.slices.size() ||
+          ps.s1 - ps.s0 > kWinRows / kWinSlice)
+        return false;
+      if (ps.range0 < 0 || ps.nrange < 1 || (size_t)(ps.range0 + ps.nrange) > W.ranges.size())
         return false;
       int64_t len = 0;
       for (int32_t g = ps.range0; g < ps.range0 + ps.nrange; ++g) {
@@ -934,8 +995,18 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
         len += rg.len;
       }
       if (len > kWinCap) return false;
-      for (int32_t e = ps.e0; e < ps.e1; ++e)
-        if (W.col[e] >= len || W.row[e] >= nrow) return false;
+      for (int32_t sj = ps.s0; sj < ps.s1; ++sj) {
+        const WinSlice& sl = W.slices[sj];
+        if (sl.e0 < 0 || sl.e0 % kWinSlice || sl.len < 1 ||
+            (int64_t)sl.e0 + (int64_t)kWinSlice * sl.len > (int64_t)W.col.size())
+          return false;
+        for (int l = 0; l < kWinSlice; ++l) {
+          const uint16_t r = W.lane[(size_t)sj * kWinSlice + l];
+          if (r != kWinNoRow && r >= nrow) return false;
+        }
+        for (int64_t e = sl.e0; e < sl.e0 + (int64_t)kWinSlice * sl.len; ++e)
+          if (W.col[e] >= len) return false;
+      }
     }
   }
   if (!W.srow.empty() &&
@@ -945,7 +1016,7 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
     if (r < 0 || r >= rows) return false;
   for (int32_t q : W.sids)
     if (q < 0 || q >= W.nsegs) return false;
-  return W.col.size() == W.row.size() && W.col.size() == W.src.size();
+  return W.col.size() == W.src.size() && W.lane.size() == W.slices.size() * kWinSlice;
 }
 
 // Whether automatic windows are worth planning: enough nonzeros for
@@ -1369,7 +1440,8 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
   if (P.win_t.chunks()) {
     const size_t e = P.win_t.col.size();
     L.wcol_t = take(2 * e);
-    L.wrow_t = take(2 * e);
+    L.wlane_t = take(2 * P.win_t.lane.size());
+    L.wslice_t = take(sizeof(WinSlice) * P.win_t.slices.size());
     L.wval_t = take(V * e);
     L.wpass_t = take(sizeof(WinPass) * P.win_t.passes.size());
     L.wrange_t = take(sizeof(WinRange) * P.win_t.ranges.size());
@@ -1383,7 +1455,8 @@ SlotLayout slot_layout(const Prepared& P, int prec) {
   if (P.win_a.chunks()) {
     const size_t e = P.win_a.col.size();
     L.wcol_a = take(2 * e);
-    L.wrow_a = take(2 * e);
+    L.wlane_a = take(2 * P.win_a.lane.size());
+    L.wslice_a = take(sizeof(WinSlice) * P.win_a.slices.size());
     L.wval_a = take(V * e);
     L.wpass_a = take(sizeof(WinPass) * P.win_a.passes.size());
     L.wrange_a = take(sizeof(WinRange) * P.win_a.ranges.size());
@@ -1473,7 +1546,8 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
   d.s_flags = P.prm.flags;
   if (P.win_t.chunks()) {
     d.wcol_t = reinterpret_cast<const uint16_t*>(base + L.wcol_t);
-    d.wrow_t = reinterpret_cast<const uint16_t*>(base + L.wrow_t);
+    d.wlane_t = reinterpret_cast<const uint16_t*>(base + L.wlane_t);
+    d.wslice_t = reinterpret_cast<const WinSlice*>(base + L.wslice_t);
     d.wval_t = base + L.wval_t;
     d.wpass_t = reinterpret_cast<const WinPass*>(base + L.wpass_t);
     d.wrange_t = reinterpret_cast<const WinRange*>(base + L.wrange_t);
@@ -1486,7 +1560,8 @@ LpDev slot_pointers(uint8_t* base, const SlotLayout& L, const Prepared& P) {
   }
   if (P.win_a.chunks()) {
     d.wcol_a = reinterpret_cast<const uint16_t*>(base + L.wcol_a);
-    d.wrow_a = reinterpret_cast<const uint16_t*>(base + L.wrow_a);
+    d.wlane_a = reinterpret_cast<const uint16_t*>(base + L.wlane_a);
+    d.wslice_a = reinterpret_cast<const WinSlice*>(base + L.wslice_a);
     d.wval_a = base + L.wval_a;
     d.wpass_a = reinterpret_cast<const WinPass*>(base + L.wpass_a);
     d.wrange_a = reinterpret_cast<const WinRange*>(base + L.wrange_a);
@@ -1579,7 +1654,7 @@ void slot_image(const SlotLayout& L, const Prepared& P, SlotImage& img) {
                if (P.dprep && !P.raw_t.empty())
                  std::memcpy(img.data() + L.raw_t, P.raw_t.data(), 8 * P.raw_t.size());
              }});
-  auto put_win = [&](const WinPlan& W, const auto& va, size_t oc, size_t orow,
+  auto put_win = [&](const WinPlan& W, const auto& va, size_t oc, size_t olane, size_t oslice,
                      size_t ov, size_t opass, size_t orange, size_t osrow, size_t osptr,
                      size_t osids, size_t owsrc) {
     if (!W.srow.empty()) {
@@ -1593,17 +1668,18 @@ void slot_image(const SlotLayout& L, const Prepared& P, SlotImage& img) {
       for (size_t e = 0; e < W.src.size(); ++e) ws[e] = (int32_t)W.src[e];
     }
     std::memcpy(img.data() + oc, W.col.data(), 2 * W.col.size());
-    std::memcpy(img.data() + orow, W.row.data(), 2 * W.row.size());
+    std::memcpy(img.data() + olane, W.lane.data(), 2 * W.lane.size());
+    std::memcpy(img.data() + oslice, W.slices.data(), sizeof(WinSlice) * W.slices.size());
     V* dst = reinterpret_cast<V*>(img.data() + ov);
     if (!P.dprep)
       for (size_t e = 0; e < W.src.size(); ++e) dst[e] = W.src[e] < 0 ? V(0) : (V)va[W.src[e]];
     std::memcpy(img.data() + opass, W.passes.data(), sizeof(WinPass) * W.passes.size());
     std::memcpy(img.data() + orange, W.ranges.data(), sizeof(WinRange) * W.ranges.size());
   };
-  put_win(P.win_t, P.va_t, L.wcol_t, L.wrow_t, L.wval_t, L.wpass_t, L.wrange_t, L.srow_t,
-          L.sptr_t, L.sids_t, L.wsrc_t);
-  put_win(P.win_a, P.va_a, L.wcol_a, L.wrow_a, L.wval_a, L.wpass_a, L.wrange_a, L.srow_a,
-          L.sptr_a, L.sids_a, L.wsrc_a);
+  put_win(P.win_t, P.va_t, L.wcol_t, L.wlane_t, L.wslice_t, L.wval_t, L.wpass_t, L.wrange_t,
+          L.srow_t, L.sptr_t, L.sids_t, L.wsrc_t);
+  put_win(P.win_a, P.va_a, L.wcol_a, L.wlane_a, L.wslice_a, L.wval_a, L.wpass_a, L.wrange_a,
+          L.srow_a, L.sptr_a, L.sids_a, L.wsrc_a);
   if (P.dprep) {
     auto put64 = [&](size_t o, const auto& v) {
       if (!v.empty()) std::memcpy(img.data() + o, v.data(), 8 * v.size());
@@ -1999,7 +2075,8 @@ int write_tables(uint8_t* dst, const std::vector<LpDev>& lps_in,
                                 W.pass0[c], W.npass[c], W.nseg[c], W.seg0[c]});
           double w = 4.0 * (W.r1[c] - W.r0[c] + W.nseg[c]);  // a row's vectors: ~4 entries
           for (int32_t q = W.pass0[c]; q < W.pass0[c] + W.npass[c]; ++q) {
-            w += W.passes[q].e1 - W.passes[q].e0;
+            for (int32_t sj = W.passes[q].s0; sj < W.passes[q].s1; ++sj)
+              w += (double)kWinSlice * W.slices[sj].len;
             for (int32_t g = W.passes[q].range0; g < W.passes[q].range0 + W.passes[q].nrange; ++g)
               w += 0.5 * W.ranges[g].len;  // a staged float: half an entry's bytes
           }

@@ -1610,62 +1610,20 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
 }
 
 // Windowed step kernel (FP32): one workgroup of kWinBlock threads per
-// windowed chunk. Each pass stages its vector ranges in LDS, then every
-// thread takes kWinNpt consecutive entries at a time (16-byte loads of
-// columns, rows and values) and adds up its runs of equal rows, gathering
-// from LDS. A run that lies inside one thread's entries is added to the
-// row's sum at once; a run that crosses threads is added by the thread
-// where it starts, which collects the pieces of the threads after it in
-// thread order, so every row sum is formed in one fixed order (the same
-// for every grid and every co-resident LP). The first thread of each step
-// of kWinBlock * kWinNpt entries owns its first run: the earlier pieces
-// were added at the previous step. After the passes each thread runs the
-// row epilogue for rows r0 + t, r0 + t + kWinBlock, ...
-// One step's entries of one thread of a windowed chunk: kWinNpt
-// consecutive entries from p0 (16-byte loads) and the rows of the entries
-// just before and just after them (-1 outside the thread's neighbours).
-struct WinBatch {
-  uint16_t cs[kWinNpt], rs[kWinNpt];
-  float vs[kWinNpt];
-  int prev_row, next_row;
-  bool active;
-};
-
-__device__ __forceinline__ void win_load(WinBatch& b, int p0, int pe1, int t,
-                                         gptr<const uint16_t> wc, gptr<const uint16_t> wr,
-                                         gptr<const float> wv) {
-  b.active = p0 < pe1;
-  b.prev_row = -1;
-  b.next_row = -1;
-  if (b.active) {
-    using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
-    using f32x4 = float __attribute__((ext_vector_type(4)));
-    const u32x4 c0 = *reinterpret_cast<gptr<const u32x4>>(wc + p0);
-    const u32x4 c1 = *reinterpret_cast<gptr<const u32x4>>(wc + p0 + 8);
-    const u32x4 q0 = *reinterpret_cast<gptr<const u32x4>>(wr + p0);
-    const u32x4 q1 = *reinterpret_cast<gptr<const u32x4>>(wr + p0 + 8);
-    f32x4 v4[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v4[u] = *reinterpret_cast<gptr<const f32x4>>(wv + p0 + 4 * u);
-    __builtin_memcpy(b.cs, &c0, 16);
-    __builtin_memcpy(b.cs + 8, &c1, 16);
-    __builtin_memcpy(b.rs, &q0, 16);
-    __builtin_memcpy(b.rs + 8, &q1, 16);
-    __builtin_memcpy(b.vs, v4, 64);
-    b.prev_row = t > 0 ? (int)wr[p0 - 1] : -1;
-    b.next_row = p0 + kWinNpt < pe1 ? (int)wr[p0 + kWinNpt] : -1;
-  }
-}
-
+// windowed chunk. Each pass stages its vector ranges in LDS; then the
+// pass's slices go to the waves in turn (slice j to wave j mod kWinWaves),
+// each lane adding up its row's entries in order, gathering from LDS, and
+// adding that sum to the row's total in LDS. A row has one lane in a pass,
+// so every row sum is formed in one fixed order (the same for every grid
+// and every co-resident LP). After the passes each thread runs the row
+// epilogue for rows r0 + t, r0 + t + kWinBlock, ...
 template <typename Step, typename Pre, int NV>
 __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* list, int nwin,
                                           bool tside, int force) {
   extern __shared__ float wlds[];
   float* win = wlds;
   float* part = win + kWinCap;
-  float* hs = part + kWinRows;
-  int* hspan = reinterpret_cast<int*>(hs + kWinBlock);
-  DD* s_red = reinterpret_cast<DD*>(hspan + kWinBlock);
+  DD* s_red = reinterpret_cast<DD*>(part + kWinRows);
   const int chi = chunk_index(nwin);
   if (chi < 0) return;
   const WinItem it = list[chi];
@@ -1674,7 +1632,8 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   // round trip for both)
   const gptr<const LpDev> L = gp(&cfg.lps[it.lp]);
   const uint16_t* const pwc = tside ? L->wcol_t : L->wcol_a;
-  const uint16_t* const pwr = tside ? L->wrow_t : L->wrow_a;
+  const uint16_t* const pwl = tside ? L->wlane_t : L->wlane_a;
+  const WinSlice* const pws = tside ? L->wslice_t : L->wslice_a;
   const void* const pwv = tside ? L->wval_t : L->wval_a;
   const WinPass* const ppass = tside ? L->wpass_t : L->wpass_a;
   const WinRange* const prange = tside ? L->wrange_t : L->wrange_a;
@@ -1682,109 +1641,108 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   if (!st.begin(cfg, it.ctl, it.lp, it.slot == 0, force)) return;
   const LpDev* lp = st.lp;
   const gptr<const uint16_t> wc = uni(gp(pwc));
-  const gptr<const uint16_t> wr = uni(gp(pwr));
+  const gptr<const uint16_t> wl = uni(gp(pwl));
+  const gptr<const WinSlice> slices = uni(gp(pws));
   const gptr<const float> wv = uni(gp(static_cast<const float*>(pwv)));
   const gptr<const WinPass> passes = uni(gp(ppass));
   const gptr<const WinRange> ranges = uni(gp(prange));
   const gptr<const float> vec = st.vecs[0];
   const int t = threadIdx.x;
+  const int lane = t & (kWinSlice - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(t / kWinSlice);
   const int r0 = uni(it.r0), nrow = uni(it.r1 - it.r0), nseg = uni(it.nseg);
-  // the chunk's pass records in LDS: reading them waits on LDS only, not
-  // on the entry loads in flight (global loads complete in order)
   __shared__ WinPass s_pass[kWinMaxPass];
   const int npass = min(uni(it.npass), kWinMaxPass);  // plans hold at most kWinMaxPass
   if (t < npass) {
     const gptr<const WinPass> src = passes + (it.pass0 + t);
-    s_pass[t] = WinPass{src->e0, src->e1, src->range0, src->nrange};
+    s_pass[t] = WinPass{src->s0, src->s1, src->range0, src->nrange};
   }
   for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;
   lds_barrier();
-  // The steps of all passes in order, kWinBlock * kWinNpt entries each: the
-  // entries of the next step are loaded into registers while the current
-  // one is processed, so their latency overlaps its work and its barriers
-  // (which wait on LDS only). Passes without entries are skipped. Pass
-  // indices here count from the chunk's first pass.
-  constexpr int kStep = kWinBlock * kWinNpt;
-  auto settle = [&](int& ps, int& base) {  // first step at or after (ps, base)
-    while (ps < npass && base >= s_pass[ps].e1) {
-      ++ps;
-      if (ps < npass) base = s_pass[ps].e0;
+  constexpr int kU = 8;  // entries of a lane loaded together
+  // A wave takes a pass's slices in turn. Each slice's first kU entries are
+  // loaded while the previous slice is summed, or, for the pass's first
+  // slice, while the window is staged (a lane's entries past kU load with
+  // their own slice).
+  // (the pass's slice records are copied to LDS at its start; the first
+  // slice of each wave reads its record from memory, before that copy)
+  __shared__ WinSlice s_sl[kWinRows / kWinSlice];
+  auto head = [&](int sj, const WinSlice& rec, int& e0, int& len, int& row, float (&vv)[kU],
+                  int (&cc)[kU]) {
+    e0 = __builtin_amdgcn_readfirstlane(rec.e0);
+    len = __builtin_amdgcn_readfirstlane(rec.len);
+    row = ldg(wl, (uint32_t)(sj * kWinSlice + lane));
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const bool on = u < len;
+      vv[u] = on ? ldg(wv, (uint32_t)(e0 + u * kWinSlice + lane)) : 0.f;
+      cc[u] = on ? (int)ldg(wc, (uint32_t)(e0 + u * kWinSlice + lane)) : 0;
     }
   };
-  int cps = 0, cbase = s_pass[0].e0;
-  settle(cps, cbase);
-  WinBatch nb;
-  if (cps < npass) win_load(nb, cbase + t * kWinNpt, s_pass[cps].e1, t, wc, wr, wv);
-  int staged = -1;
-  while (cps < npass) {
-    if (cps != staged) {
-      const int pr0 = s_pass[cps].range0, prn = s_pass[cps].nrange;
-      lds_barrier();  // the previous pass is done with the window (and part is zeroed)
-      // ranges start on bucket boundaries (multiples of 4 entries, here and
-      // in the window), so they are copied 16 bytes at a time; only the
-      // vector's last bucket can end on a partial group
-      int off = 0;
-      for (int g = pr0; g < pr0 + prn; ++g) {
-        const int src = ranges[g].src, len = ranges[g].len;
-        using f32x4 = float __attribute__((ext_vector_type(4)));
-        const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src);
-        f32x4* w4 = reinterpret_cast<f32x4*>(win + off);
-        for (int q = t; q < (len >> 2); q += kWinBlock) w4[q] = v4[q];
-        for (int q = (len & ~3) + t; q < len; q += kWinBlock) win[off + q] = ldg(vec, (uint32_t)(src + q));
-        off += len;
-      }
-      lds_barrier();
-      staged = cps;
+  for (int ps = 0; ps < npass; ++ps) {
+    const int pr0 = s_pass[ps].range0, prn = s_pass[ps].nrange;
+    const int sl0 = s_pass[ps].s0, sl1 = s_pass[ps].s1;
+    int sj = sl0 + wave;
+    int e0 = 0, len = 0, row = kWinNoRow;
+    float vv[kU];
+    int cc[kU];
+    if (sj < sl1) {
+      const gptr<const WinSlice> slp = slices + sj;
+      head(sj, WinSlice{uni(slp->e0), uni(slp->len)}, e0, len, row, vv, cc);
     }
-    const WinBatch cb = nb;
-    int nps = cps, nbase = cbase + kStep;
-    settle(nps, nbase);
-    if (nps < npass) win_load(nb, nbase + t * kWinNpt, s_pass[nps].e1, t, wc, wr, wv);
-    float s_run = 0.f, head_sum = 0.f;
-    int cur_row = -1;
-    bool in_head = false, spans = false, owner = false;
-    if (cb.active) {
-      cur_row = cb.rs[0];
-      in_head = (int)cb.rs[0] == cb.prev_row;
+    if (ps > 0) lds_barrier();  // the previous pass is done with the window and records
+    for (int q = t; q < sl1 - sl0; q += kWinBlock) {
+      const gptr<const WinSlice> slp = slices + (sl0 + q);
+      s_sl[q] = WinSlice{slp->e0, slp->len};
+    }
+    // ranges start on bucket boundaries (multiples of 4 entries, here and
+    // in the window), so they are copied 16 bytes at a time; only the
+    // vector's last bucket can end on a partial group
+    int off = 0;
+    for (int g = pr0; g < pr0 + prn; ++g) {
+      const int src = ranges[g].src, glen = ranges[g].len;
+      using f32x4 = float __attribute__((ext_vector_type(4)));
+      const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src);
+      f32x4* w4 = reinterpret_cast<f32x4*>(win + off);
+      for (int q = t; q < (glen >> 2); q += kWinBlock) w4[q] = v4[q];
+      for (int q = (glen & ~3) + t; q < glen; q += kWinBlock) win[off + q] = ldg(vec, (uint32_t)(src + q));
+      off += glen;
+    }
+    lds_barrier();
+    while (sj < sl1) {
+      const int nsj = sj + kWinWaves;
+      int ne0 = 0, nlen = 0, nrow_ = kWinNoRow;
+      float nvv[kU];
+      int ncc[kU];
+      if (nsj < sl1) head(nsj, s_sl[nsj - sl0], ne0, nlen, nrow_, nvv, ncc);
+      float acc = 0.f;
 #pragma unroll
-      for (int i = 0; i < kWinNpt; ++i) {
-        const int r = cb.rs[i];
-        if (r != cur_row) {
-          if (in_head) {
-            head_sum = s_run;
-            in_head = false;
-          } else {
-            part[cur_row] += s_run;
-          }
-          s_run = 0.f;
-          cur_row = r;
+      for (int u = 0; u < kU; ++u)
+        if (u < len) acc += vv[u] * win[cc[u]];
+      for (int k = kU; k < len; k += kU) {
+        float tv[kU];
+        int tc[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const bool on = k + u < len;
+          tv[u] = on ? ldg(wv, (uint32_t)(e0 + (k + u) * kWinSlice + lane)) : 0.f;
+          tc[u] = on ? (int)ldg(wc, (uint32_t)(e0 + (k + u) * kWinSlice + lane)) : 0;
         }
-        s_run += cb.vs[i] * win[cb.cs[i]];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (k + u < len) acc += tv[u] * win[tc[u]];
       }
-      const bool tail_cont = cur_row == cb.next_row;
-      if (in_head) {
-        head_sum = s_run;
-        spans = tail_cont;
-      } else if (tail_cont) {
-        owner = true;
-      } else {
-        part[cur_row] += s_run;
+      if (row != kWinNoRow) part[row] += acc;
+      sj = nsj;
+      e0 = ne0;
+      len = nlen;
+      row = nrow_;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        vv[u] = nvv[u];
+        cc[u] = ncc[u];
       }
     }
-    hs[t] = head_sum;
-    hspan[t] = spans ? 1 : 0;
-    lds_barrier();
-    if (owner) {
-      float tot = s_run;
-      for (int u = t + 1; u < kWinBlock; ++u) {
-        tot += hs[u];
-        if (!hspan[u]) break;
-      }
-      part[cur_row] += tot;
-    }
-    lds_barrier();
-    cps = nps;
-    cbase = nbase;
   }
   lds_barrier();
   DD p[NV];

@@ -56,15 +56,18 @@ using HostArray = std::vector<T, NoInitAlloc<T>>;
 using SlotImage = HostArray<uint8_t>;
 
 // Windowed chunks of one CSR side (see WinItem): rows and passes of each
-// chunk, the passes' entry ranges and LDS ranges, and the entries in
-// window-major order (window-local column, chunk-local row) with the
-// device-order CSR position of each (-1 for padding).
+// chunk, the passes' slices and LDS ranges, the slices (entry offset and
+// length, and the chunk-local row of each lane), and the entries in slice
+// order (window-local column) with the device-order CSR position of each
+// (-1 for padding).
 struct WinPlan {
   std::vector<int32_t> r0, r1, pass0, npass;
   std::vector<int32_t> nseg, seg0;  // per chunk: segments after its rows, first segment id
   std::vector<WinPass> passes;
   std::vector<WinRange> ranges;
-  HostArray<uint16_t> col, row;  // filled by the planning threads (not zeroed first)
+  std::vector<WinSlice> slices;
+  HostArray<uint16_t> lane;  // kWinSlice per slice
+  HostArray<uint16_t> col;   // filled by the planning threads (not zeroed first)
   HostArray<int64_t> src;
   // long rows split into segments: the rows (device order), and per row the
   // ids of its segments' partials in order (CSR over srow). The windowed
@@ -148,8 +151,8 @@ struct SlotLayout {
   size_t vm[kNVecM] = {};
   size_t dc = 0, bfin = 0, dr = 0, sense = 0;
   // windowed entries of each side (0 when none)
-  size_t wcol_t = 0, wrow_t = 0, wval_t = 0, wpass_t = 0, wrange_t = 0;
-  size_t wcol_a = 0, wrow_a = 0, wval_a = 0, wpass_a = 0, wrange_a = 0;
+  size_t wcol_t = 0, wlane_t = 0, wslice_t = 0, wval_t = 0, wpass_t = 0, wrange_t = 0;
+  size_t wcol_a = 0, wlane_a = 0, wslice_a = 0, wval_a = 0, wpass_a = 0, wrange_a = 0;
   size_t segp_t = 0, srow_t = 0, sptr_t = 0, sids_t = 0;  // segmented rows (0 when none)
   size_t segp_a = 0, srow_a = 0, sptr_a = 0, sids_a = 0;
   // the opening evaluation's sparse products (FP32 with windowed chunks)

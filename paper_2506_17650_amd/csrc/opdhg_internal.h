@@ -118,25 +118,33 @@ constexpr int kPieceNnz = 4096;
 // entries fall into a few column ranges are taken in chunks of up to
 // kWinRows consecutive rows by workgroups of kWinBlock threads. For each
 // pass the workgroup copies up to kWinCap vector entries (whole buckets of
-// kWinBucket columns) into LDS, then streams the pass's entries
-// (window-local column, chunk-local row, value; padded to kWinNpt) and
+// kWinBucket columns) into LDS, then streams the pass's entries and
 // gathers from LDS; row sums of the passes add up in LDS and feed the same
-// row epilogues as the tile kernels.
+// row epilogues as the tile kernels. A pass's rows, ordered by their entry
+// count in the pass, form slices of kWinSlice rows, one row per lane of a
+// wavefront; a slice stores its entries (window-local column, value) k-major,
+// entry k of lane l at e0 + k * kWinSlice + l, padded to its longest row.
 constexpr int kWinBlock = 1024;
-constexpr int kWinNpt = 16;
+constexpr int kWinSlice = 64;
+constexpr uint16_t kWinNoRow = 0xFFFF;  // an empty lane of a slice
 constexpr int kWinBucket = 1024;
 constexpr int kWinBuckets = 26;
 constexpr int kWinCap = kWinBuckets * kWinBucket;
 constexpr int kWinRows = 10240;
 constexpr int kWinMaxPass = 4;
 constexpr int kWinWaves = kWinBlock / 64;
-// LDS of a windowed workgroup: window, row sums, per-thread carries, reduction
-constexpr size_t kWinLds = (size_t)(kWinCap + kWinRows + 2 * kWinBlock) * 4 + kWinWaves * 4 * 16;
+// LDS of a windowed workgroup: window, row sums, reduction
+constexpr size_t kWinLds = (size_t)(kWinCap + kWinRows) * 4 + kWinWaves * 4 * 16;
 
-// Entries [e0, e1) of a pass (both multiples of kWinNpt) and the vector
-// ranges [range0, range0 + nrange) it stages, in window order.
+// Slices [s0, s1) of a pass and the vector ranges [range0, range0 + nrange)
+// it stages, in window order.
 struct WinPass {
-  int32_t e0, e1, range0, nrange;
+  int32_t s0, s1, range0, nrange;
+};
+// A slice: entries e0 + k * kWinSlice + lane for k < len (e0 a multiple of
+// kWinSlice); the chunk-local row of each lane is in a parallel array.
+struct WinSlice {
+  int32_t e0, len;
 };
 struct WinRange {
   int32_t src, len;  // vector entries [src, src + len), device order
@@ -214,13 +222,15 @@ struct LpDev {
   int64_t s_max_iter;
   int32_t s_phi, s_schedule, s_normalize, s_eval_every, s_max_retries, s_flags;
   // windowed rows of each side (FP32; empty when the side has none)
-  const uint16_t* wcol_t;  // window-local column of each entry
-  const uint16_t* wrow_t;  // chunk-local row of each entry
-  const void* wval_t;      // value of each entry (type V)
+  const uint16_t* wcol_t;   // window-local column of each entry
+  const uint16_t* wlane_t;  // chunk-local row of each slice lane (kWinNoRow: none)
+  const WinSlice* wslice_t;
+  const void* wval_t;       // value of each entry (type V)
   const WinPass* wpass_t;
   const WinRange* wrange_t;
   const uint16_t* wcol_a;
-  const uint16_t* wrow_a;
+  const uint16_t* wlane_a;
+  const WinSlice* wslice_a;
   const void* wval_a;
   const WinPass* wpass_a;
   const WinRange* wrange_a;
