@@ -186,7 +186,7 @@ int validate_params(const opdhg_params* p) {
   if (p->windows < OPDHG_WINDOWS_AUTO || p->windows > OPDHG_WINDOWS_ALWAYS)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "windows must be OPDHG_WINDOWS_AUTO, _OFF or _ALWAYS");
   if (p->window_buckets < 0 || p->window_buckets > kWinBuckets)
-    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_buckets must be in [0, 26]");
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_buckets must be in [0, 28]");
   if (p->window_rows < 0 || p->window_rows > kWinRows)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_rows must be in [0, 10240]");
   if (p->prep < OPDHG_PREP_AUTO || p->prep > OPDHG_PREP_DEVICE)

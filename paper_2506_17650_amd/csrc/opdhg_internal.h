@@ -128,7 +128,7 @@ constexpr int kWinBlock = 1024;
 constexpr int kWinSlice = 64;
 constexpr uint16_t kWinNoRow = 0xFFFF;  // an empty lane of a slice
 constexpr int kWinBucket = 1024;
-constexpr int kWinBuckets = 26;
+constexpr int kWinBuckets = 28;
 constexpr int kWinCap = kWinBuckets * kWinBucket;
 constexpr int kWinRows = 10240;
 constexpr int kWinMaxPass = 4;
