@@ -1704,8 +1704,17 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
       using f32x4 = float __attribute__((ext_vector_type(4)));
       const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src);
       f32x4* w4 = reinterpret_cast<f32x4*>(win + off);
-      for (int q = t; q < (glen >> 2); q += kWinBlock) w4[q] = v4[q];
-      for (int q = (glen & ~3) + t; q < glen; q += kWinBlock) win[off + q] = ldg(vec, (uint32_t)(src + q));
+      const int n4 = glen >> 2;
+      int q = t;
+      for (; q + 3 * kWinBlock < n4; q += 4 * kWinBlock) {  // four loads in flight
+        f32x4 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = v4[q + u * kWinBlock];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w4[q + u * kWinBlock] = a[u];
+      }
+      for (; q < n4; q += kWinBlock) w4[q] = v4[q];
+      for (q = (glen & ~3) + t; q < glen; q += kWinBlock) win[off + q] = ldg(vec, (uint32_t)(src + q));
       off += glen;
     }
     lds_barrier();
