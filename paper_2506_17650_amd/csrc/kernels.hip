@@ -1808,7 +1808,19 @@ __device__ __forceinline__ void seg_rows(const LaunchCfg& cfg, const SegItem* li
   const int k0 = ldg(sptr, (uint32_t)qq), k1 = ldg(sptr, (uint32_t)(qq + 1));
   Acc<V> acc;
   acc.zero();
-  for (int k = k0 + lane; k < k1; k += kSegLanes) {
+  // four partials of the lane in flight at a time, merged in order
+  int k = k0 + lane;
+  for (; k + 3 * kSegLanes < k1; k += 4 * kSegLanes) {
+    int id[4];
+    Acc<V> a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) id[u] = ldg(sids, (uint32_t)(k + u * kSegLanes));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) seg_load(sp, id[u], a[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc.merge(a[u]);
+  }
+  for (; k < k1; k += kSegLanes) {
     Acc<V> a;
     seg_load(sp, ldg(sids, (uint32_t)k), a);
     acc.merge(a);
