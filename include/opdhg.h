@@ -155,8 +155,10 @@ typedef struct opdhg_params {
   double power_tol;      /* power iteration stops when |A~|_2^2 moves less than this, relatively */
   int32_t step_norm;     /* OPDHG_STEP_NORM_*: norms of the adaptive rule's movement term */
   int32_t windows;       /* OPDHG_WINDOWS_*: FP32 only; FP64 and the server never use windows */
-  int32_t window_buckets; /* LDS window per pass in buckets of 1024 entries, 1..28; 0: 28 */
-  int32_t window_rows;   /* rows per windowed chunk, 1..10240; 0: picked from the side's size */
+  int32_t window_buckets; /* LDS window per pass in buckets of 1024 entries, 1..32, at most 32 on
+                             the A^T side and 28 on the A side; 0: those */
+  int32_t window_rows;   /* rows per windowed chunk, 1..10240 (at most 7168 on the A^T side);
+                            0: picked from the side's size */
   int32_t prep;          /* OPDHG_PREP_*: rescaling passes and scaled data on the host or device */
   int32_t eval_slots;    /* attempt slots between the guarded evaluation steps inside a launch
                             sequence (an LP that becomes due mid-sequence waits at most this
@@ -298,8 +300,9 @@ int opdhg_solve_noalloc(const opdhg_lp* lp, const opdhg_params* p, void* hip_str
  * lanes per row picked per tile) is uploaded, captured and timed over
  * `replays` launch sequences (64 step attempts each) with the LPs kept
  * running. In FP32 with automatic windows, the best tiling is timed once
- * more with windowed chunks of up to 10240 rows wherever they stage at
- * most half of their matrix bytes (OPDHG_WINDOWS_ALWAYS): LDS-staged
+ * more with windowed chunks of up to 10240 rows (7168 on the A^T side)
+ * wherever they stage at most half of their matrix bytes
+ * (OPDHG_WINDOWS_ALWAYS): LDS-staged
  * gathers instead of one gather per nonzero from global memory. The
  * fastest candidate by step attempts per second, summed over the set, is
  * returned; pass its fields as tile_nnz, lanes, workgroups, windows and

@@ -185,10 +185,13 @@ int validate_params(const opdhg_params* p) {
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "unknown step norm");
   if (p->windows < OPDHG_WINDOWS_AUTO || p->windows > OPDHG_WINDOWS_ALWAYS)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "windows must be OPDHG_WINDOWS_AUTO, _OFF or _ALWAYS");
-  if (p->window_buckets < 0 || p->window_buckets > kWinBuckets)
-    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_buckets must be in [0, 28]");
+  constexpr int kMaxParam = kWinCap / kWinParamBucket;
+  if (p->window_buckets < 0 || p->window_buckets > kMaxParam)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT,
+                "window_buckets must be in [0, " + std::to_string(kMaxParam) + "]");
   if (p->window_rows < 0 || p->window_rows > kWinRows)
-    return fail(OPDHG_ERR_INVALID_ARGUMENT, "window_rows must be in [0, 10240]");
+    return fail(OPDHG_ERR_INVALID_ARGUMENT,
+                "window_rows must be in [0, " + std::to_string(kWinRows) + "]");
   if (p->prep < OPDHG_PREP_AUTO || p->prep > OPDHG_PREP_DEVICE)
     return fail(OPDHG_ERR_INVALID_ARGUMENT, "prep must be OPDHG_PREP_AUTO, _HOST or _DEVICE");
   return OPDHG_OK;
@@ -628,7 +631,7 @@ std::vector<Tile> build_tiles(const int32_t* rp, int64_t rows, int64_t cap, int 
 //
 // Rows [lo, hi) of one side are cut into chunks of `chunk_rows` rows. A
 // chunk is windowed when the vector entries its nonzeros gather lie in a few
-// runs of 1024-entry buckets: the runs are packed into at most kWinMaxPass
+// runs of kWinBucket-entry buckets: the runs are packed into at most kWinMaxPass
 // passes of `per_pass` buckets, and the staged entries (4 bytes each) must
 // cost at most half the chunk's matrix bytes (8 per nonzero), so the window
 // copies stay small against the stream of the matrix. Other chunks stay
@@ -655,9 +658,19 @@ static int64_t window_chunk_rows(const opdhg_params* p, int64_t rows) {
   return std::min<int64_t>(kWinRows, std::max<int64_t>(1024, per));
 }
 
+// Buckets per pass of a chunk of several passes, and the most buckets a
+// chunk of one pass stages (the parameter sets both, in units of
+// kWinParamBucket entries).
+static int window_per_pass(const opdhg_params* p) {
+  return p->window_buckets > 0 ? p->window_buckets * (kWinParamBucket / kWinBucket) : kWinBuckets;
+}
+static int window_one_pass(const opdhg_params* p) {
+  return p->window_buckets > 0 ? window_per_pass(p) : kWinOneBuckets;
+}
+
 static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t>& ci,
                          int64_t ncols, int64_t lo, int64_t hi, int64_t long_end,
-                         int64_t chunk_rows, int per_pass, WinPlan& W) {
+                         int64_t chunk_rows, int per_pass, int one_cap, WinPlan& W) {
   if (hi <= lo || ncols <= 0) return;
   const int64_t nb = (ncols + kWinBucket - 1) / kWinBucket;
   const int64_t max_buckets = (int64_t)per_pass * kWinMaxPass;
@@ -700,17 +713,19 @@ static void plan_windows(const std::vector<int32_t>& rp, const HostArray<int32_t
     const int64_t nz = (int64_t)rp[b] - rp[a];
     if (nz < kWinMinNnz) continue;
     const int64_t nbk = (int64_t)touched.size();
-    if ((nbk + per_pass - 1) / per_pass > kWinMaxPass) continue;
+    // a chunk whose buckets fit one_cap takes one pass over them all
+    const int64_t step = nbk <= one_cap ? std::max<int64_t>(nbk, 1) : per_pass;
+    if ((nbk + step - 1) / step > kWinMaxPass) continue;
     if (nbk * kWinBucket * 4 > nz * 4) continue;  // staged bytes <= half the matrix bytes
     std::sort(touched.begin(), touched.end());
     // buckets to passes in order; runs of consecutive buckets become one range
     const int32_t pass0 = (int32_t)W.passes.size();
     int npass = 0;
     std::vector<Slot> sl;
-    for (int64_t q = 0; q < nbk; q += per_pass) {
+    for (int64_t q = 0; q < nbk; q += step) {
       WinPass ps{0, 0, (int32_t)W.ranges.size(), 0};
       int32_t off = 0;
-      for (int64_t u = q; u < std::min(nbk, q + per_pass); ++u) {
+      for (int64_t u = q; u < std::min(nbk, q + step); ++u) {
         const int64_t bk = touched[u];
         const int32_t src = (int32_t)(bk * kWinBucket);
         const int32_t len = (int32_t)std::min<int64_t>(kWinBucket, ncols - src);
@@ -978,6 +993,8 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
   for (size_t c = 0; c < W.chunks(); ++c) {
     const int64_t nrow = (int64_t)W.r1[c] - W.r0[c] + W.nseg[c];
     if (W.r0[c] < 0 || W.r1[c] > rows || W.r1[c] <= W.r0[c] || nrow > kWinRows) return false;
+    // one pass: the window may take the row sums' LDS too
+    const int64_t cap = W.npass[c] == 1 ? kWinOneCap : kWinCap;
     if (W.seg0[c] < 0 || W.seg0[c] + W.nseg[c] > W.nsegs) return false;
     if (W.npass[c] < 1 || W.npass[c] > kWinMaxPass) return false;
     for (int32_t q = W.pass0[c]; q < W.pass0[c] + W.npass[c]; ++q) {
@@ -994,7 +1011,7 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
         if (rg.src < 0 || rg.len <= 0 || (int64_t)rg.src + rg.len > ncols) return false;
         len += rg.len;
       }
-      if (len > kWinCap) return false;
+      if (len > cap) return false;
       for (int32_t sj = ps.s0; sj < ps.s1; ++sj) {
         const WinSlice& sl = W.slices[sj];
         if (sl.e0 < 0 || sl.e0 % kWinSlice || sl.len < 1 ||
@@ -1026,7 +1043,7 @@ static bool plan_ok(const WinPlan& W, int64_t rows, int64_t ncols) {
 // column locality skip the device-order indices and the planning.
 static bool windows_worth_planning(const opdhg_lp* lp, const Prepared& out,
                                    const std::vector<int32_t>& inv_t, int64_t chunk_rows,
-                                   int per_pass) {
+                                   int per_pass, int one_cap) {
   if (lp->nnz < kWinMinChunks * kWinMinNnz) return false;
   const int64_t lo = out.cend_a[0], hi = lp->m;
   if (hi - lo < 8 * chunk_rows) return false;
@@ -1047,7 +1064,8 @@ static bool windows_worth_planning(const opdhg_lp* lp, const Prepared& out,
         }
       }
     }
-    if ((nbk + per_pass - 1) / per_pass <= kWinMaxPass && nbk * kWinBucket <= nz) ++ok;
+    const bool passes_ok = nbk <= one_cap || (nbk + per_pass - 1) / per_pass <= kWinMaxPass;
+    if (passes_ok && nbk * kWinBucket <= nz) ++ok;
   }
   return ok >= 4;
 }
@@ -1274,12 +1292,12 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   // windowed chunks need the device-order column indices, also for sizing;
   // automatic windows only where a sample of chunks shows column locality
   bool windows = p->precision == OPDHG_FP32 && p->windows != OPDHG_WINDOWS_OFF;
-  const int per_pass = p->window_buckets > 0 ? p->window_buckets : kWinBuckets;
+  const int per_pass = window_per_pass(p), one_cap = window_one_pass(p);
   if (windows && p->windows == OPDHG_WINDOWS_AUTO) {
     std::vector<int32_t> inv(n);
     for (int64_t j = 0; j < n; ++j) inv[out.perm_t[j]] = (int32_t)j;
     windows = windows_worth_planning(lp, out, inv, window_chunk_rows(p, m - out.cend_a[0]),
-                                     per_pass);
+                                     per_pass, one_cap);
   }
   out.prep_ruiz = p->ruiz_iters;
   out.prep_l2 = p->l2_rescale != 0;
@@ -1370,9 +1388,9 @@ int prepare(const opdhg_lp* lp, const opdhg_params* p, Prepared& out, bool struc
   out.win_a = WinPlan();
   if (windows) {
     plan_windows(out.rp_t, out.ci_t, m, out.cend_t[0], n, out.cend_t[0],
-                 window_chunk_rows(p, n - out.cend_t[0]), per_pass, out.win_t);
+                 window_chunk_rows(p, n - out.cend_t[0]), per_pass, one_cap, out.win_t);
     plan_windows(out.rp_a, out.ci_a, n, out.cend_a[0], m, out.cend_a[0],
-                 window_chunk_rows(p, m - out.cend_a[0]), per_pass, out.win_a);
+                 window_chunk_rows(p, m - out.cend_a[0]), per_pass, one_cap, out.win_a);
     if (!plan_ok(out.win_t, n, m) || !plan_ok(out.win_a, m, n))
       return fail(OPDHG_ERR_DEVICE, "internal error: inconsistent window plan");
     if (p->windows == OPDHG_WINDOWS_AUTO) {

@@ -1617,13 +1617,12 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
 // so every row sum is formed in one fixed order (the same for every grid
 // and every co-resident LP). After the passes each thread runs the row
 // epilogue for rows r0 + t, r0 + t + kWinBlock, ...
-template <typename Step, typename Pre, int NV>
+template <bool tside, typename Step, typename Pre, int NV>
 __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* list, int nwin,
-                                          bool tside, int force) {
+                                          int force) {
   extern __shared__ float wlds[];
   float* win = wlds;
-  float* part = win + kWinCap;
-  DD* s_red = reinterpret_cast<DD*>(part + kWinRows);
+  DD* s_red = reinterpret_cast<DD*>(wlds + kWinOneCap);
   const int chi = chunk_index(nwin);
   if (chi < 0) return;
   const WinItem it = list[chi];
@@ -1653,12 +1652,22 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   const int r0 = uni(it.r0), nrow = uni(it.r1 - it.r0), nseg = uni(it.nseg);
   __shared__ WinPass s_pass[kWinMaxPass];
   const int npass = min(uni(it.npass), kWinMaxPass);  // plans hold at most kWinMaxPass
+  // A chunk of one pass keeps each slice's sums in registers until the
+  // window is no longer needed and then writes them into its LDS; the row
+  // sums of a chunk of several passes sit beside the window and add up.
+  const bool one = npass == 1;
+  float* const part = one ? wlds : wlds + kWinCap;
   if (t < npass) {
     const gptr<const WinPass> src = passes + (it.pass0 + t);
     s_pass[t] = WinPass{src->s0, src->s1, src->range0, src->nrange};
   }
-  for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;
+  if (!one)
+    for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;
   lds_barrier();
+  float racc[kWinWaveSlices];
+  int rrow[kWinWaveSlices];
+#pragma unroll
+  for (int j = 0; j < kWinWaveSlices; ++j) rrow[j] = kWinNoRow;
   constexpr int kU = 8;  // entries of a lane loaded together
   // A wave takes a pass's slices in turn. Each slice's first kU entries are
   // loaded while the previous slice is summed, or, for the pass's first
@@ -1718,7 +1727,11 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
       off += glen;
     }
     lds_barrier();
-    while (sj < sl1) {
+    // the wave's slices of the pass (at most kWinWaveSlices), unrolled so
+    // that a chunk of one pass can keep each slice's sums in registers
+#pragma unroll
+    for (int j = 0; j < kWinWaveSlices; ++j) {
+      if (sj >= sl1) break;
       const int nsj = sj + kWinWaves;
       int ne0 = 0, nlen = 0, nrow_ = kWinNoRow;
       float nvv[kU];
@@ -1741,7 +1754,12 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
         for (int u = 0; u < kU; ++u)
           if (k + u < len) acc += tv[u] * win[tc[u]];
       }
-      if (row != kWinNoRow) part[row] += acc;
+      if (one) {
+        racc[j] = acc;
+        rrow[j] = row;
+      } else if (row != kWinNoRow) {
+        part[row] += acc;
+      }
       sj = nsj;
       e0 = ne0;
       len = nlen;
@@ -1754,6 +1772,14 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
     }
   }
   lds_barrier();
+  if (one) {  // the window is done with: its LDS takes the row sums
+    for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;  // rows without entries
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < kWinWaveSlices; ++j)
+      if (rrow[j] != kWinNoRow) part[rrow[j]] = racc[j];
+    lds_barrier();
+  }
   DD p[NV];
   dd_reset(p);
   // the segments' partial row sums go out for the finishing kernel
@@ -1929,8 +1955,8 @@ __global__ __launch_bounds__(kBlock) void k_prod_tiles(LaunchCfg cfg) {
 
 template <bool TSIDE, int WHICH>
 __global__ __launch_bounds__(kWinBlock) void k_prod_win(LaunchCfg cfg) {
-  win_chunk<ProdStep<TSIDE, WHICH>, ProdPre, 1>(cfg, TSIDE ? cfg.win_t : cfg.win_a,
-                                               TSIDE ? cfg.nwin_t : cfg.nwin_a, TSIDE, 0);
+  win_chunk<TSIDE, ProdStep<TSIDE, WHICH>, ProdPre, 1>(cfg, TSIDE ? cfg.win_t : cfg.win_a,
+                                                       TSIDE ? cfg.nwin_t : cfg.nwin_a, 0);
 }
 
 template <bool TSIDE, int WHICH>
@@ -1940,11 +1966,11 @@ __global__ __launch_bounds__(kBlock) void k_prod_seg(LaunchCfg cfg) {
 }
 
 __global__ __launch_bounds__(kWinBlock) void k_primal_win(LaunchCfg cfg, int force) {
-  win_chunk<PrimalStep<float>, PrimalPre<float>, 3>(cfg, cfg.win_t, cfg.nwin_t, true, force);
+  win_chunk<true, PrimalStep<float>, PrimalPre<float>, 3>(cfg, cfg.win_t, cfg.nwin_t, force);
 }
 
 __global__ __launch_bounds__(kWinBlock) void k_dual_win(LaunchCfg cfg, int force) {
-  win_chunk<DualStep<float>, DualPre<float>, 4>(cfg, cfg.win_a, cfg.nwin_a, false, force);
+  win_chunk<false, DualStep<float>, DualPre<float>, 4>(cfg, cfg.win_a, cfg.nwin_a, force);
 }
 
 // What the step decision needs from an LP's record, in scalar registers:
@@ -2876,11 +2902,10 @@ static int win_attributes() {
   static std::once_flag once;
   static hipError_t err = hipSuccess;
   std::call_once(once, [] {
-    err = hipFuncSetAttribute((const void*)k_primal_win,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLds);
-    const void* more[] = {(const void*)k_dual_win, (const void*)k_prod_win<true, 0>,
-                          (const void*)k_prod_win<true, 1>, (const void*)k_prod_win<false, 0>};
-    for (const void* f : more)
+    const void* ks[] = {(const void*)k_primal_win, (const void*)k_dual_win,
+                        (const void*)k_prod_win<true, 0>, (const void*)k_prod_win<true, 1>,
+                        (const void*)k_prod_win<false, 0>};
+    for (const void* f : ks)
       if (err == hipSuccess)
         err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLds);
   });

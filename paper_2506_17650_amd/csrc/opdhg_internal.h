@@ -115,10 +115,10 @@ constexpr int kSplitNnz = 16384;
 constexpr int kPieceNnz = 4096;
 
 // Windowed sparse products (FP32). Rows of one side whose gathered vector
-// entries fall into a few column ranges are taken in chunks of up to
-// kWinRows consecutive rows by workgroups of kWinBlock threads. For each
-// pass the workgroup copies up to kWinCap vector entries (whole buckets of
-// kWinBucket columns) into LDS, then streams the pass's entries and
+// entries fall into a few column ranges are taken in chunks of consecutive
+// rows by workgroups of kWinBlock threads. For each pass the workgroup
+// copies a window of vector entries (whole buckets of kWinBucket columns)
+// into LDS, then streams the pass's entries and
 // gathers from LDS; row sums of the passes add up in LDS and feed the same
 // row epilogues as the tile kernels. A pass's rows, ordered by their entry
 // count in the pass, form slices of kWinSlice rows, one row per lane of a
@@ -127,14 +127,25 @@ constexpr int kPieceNnz = 4096;
 constexpr int kWinBlock = 1024;
 constexpr int kWinSlice = 64;
 constexpr uint16_t kWinNoRow = 0xFFFF;  // an empty lane of a slice
-constexpr int kWinBucket = 1024;
-constexpr int kWinBuckets = 28;
-constexpr int kWinCap = kWinBuckets * kWinBucket;
+constexpr int kWinBucket = 512;
+constexpr int kWinParamBucket = 1024;  // the unit of the window_buckets parameter
 constexpr int kWinRows = 10240;
+// The LDS of a windowed workgroup: a chunk of several passes holds one
+// pass's window of up to kWinBuckets buckets beside the chunk's row sums; a
+// chunk of one pass keeps its row sums in registers during the pass, so its
+// window takes up to kWinOneBuckets buckets and the row sums reuse that LDS
+// afterwards.
+constexpr int kWinBuckets = 56;
+constexpr int kWinCap = kWinBuckets * kWinBucket;
+constexpr int kWinOneBuckets = kWinBuckets + kWinRows / kWinBucket;
+constexpr int kWinOneCap = kWinOneBuckets * kWinBucket;
 constexpr int kWinMaxPass = 4;
 constexpr int kWinWaves = kWinBlock / 64;
-// LDS of a windowed workgroup: window, row sums, reduction
-constexpr size_t kWinLds = (size_t)(kWinCap + kWinRows) * 4 + kWinWaves * 4 * 16;
+// slices of one pass per wave (a pass has at most kWinRows rows)
+constexpr int kWinWaveSlices = kWinRows / kWinSlice / kWinWaves;
+// LDS of a windowed workgroup: window (and row sums), reduction
+constexpr size_t kWinLds = (size_t)kWinOneCap * 4 + kWinWaves * 4 * 16;
+static_assert(kWinOneCap == kWinCap + kWinRows, "one layout of LDS for both kinds of chunk");
 
 // Slices [s0, s1) of a pass and the vector ranges [range0, range0 + nrange)
 // it stages, in window order.

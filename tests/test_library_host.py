@@ -162,7 +162,7 @@ def test_new_parameters_validated():
     lp = tiny_lp(seed=3)
     for k, v in [("step_rule", 2), ("restart_scheme", -1), ("l2_rescale", 2),
                  ("power_iters", 0), ("step_scale", 0.0), ("step_scale", float("inf")),
-                 ("power_tol", -1.0), ("windows", 3), ("window_buckets", 27),
+                 ("power_tol", -1.0), ("windows", 3), ("window_buckets", 33),
                  ("window_rows", 10241), ("prep", 3)]:
         with pytest.raises(P.OpdhgError) as e:
             P.opdhg_spectral_norm(lp, P.opdhg_default_params(**{k: v}))
