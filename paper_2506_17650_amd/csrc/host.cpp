@@ -1248,9 +1248,15 @@ static int prepare_finish(const opdhg_lp* lp, const opdhg_params* p, Prepared& o
   d.schedule = p->schedule;
   d.eval_every = p->eval_every;
   d.max_retries = p->max_step_retries;
+  bool lower_zero = true, no_upper = true;
+  for (int64_t j = 0; j < n && (lower_zero || no_upper); ++j) {
+    lower_zero = lower_zero && lp->l[j] == 0.0;
+    no_upper = no_upper && lp->u[j] == std::numeric_limits<double>::infinity();
+  }
   d.flags = (p->step_rule == OPDHG_STEP_CONSTANT ? kConstantStep : 0) |
             (p->restart_scheme == OPDHG_RESTART_NONE ? kNoRestart : 0) |
-            (p->step_norm == OPDHG_STEP_NORM_PRECOND ? kWeightedStep : 0);
+            (p->step_norm == OPDHG_STEP_NORM_PRECOND ? kWeightedStep : 0) |
+            (lower_zero ? kLowerZero : 0) | (no_upper ? kNoUpper : 0);
   return OPDHG_OK;
 }
 

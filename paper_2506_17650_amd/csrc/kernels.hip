@@ -1225,7 +1225,7 @@ struct PrimalStep {
   int stride_ = 0;
   void* segp_ = nullptr;  // segment partials of split rows
   V tau = V(0), etav = V(0);
-  bool learn = false, upd = false, wstep = false;
+  bool learn = false, upd = false, wstep = false, lzero = false, noup = false;
   double lscale = 1.0, hnorm = 0.0;
 
   // first: this workgroup takes the LP's first item (it clears the flags
@@ -1257,6 +1257,7 @@ struct PrimalStep {
     double* const ppart = uni(L->part_t);
     const int pstride = uni(L->ntiles_t);
     void* const pseg = uni(L->segp_t);
+    const int32_t pflags = uni(L->s_flags);
     // the restart / final copy of the evaluation step ran before this
     // launch; the workgroup with the LP's first item clears the flags
     if (first && threadIdx.x == 0 && (v.restart_pending | v.finalize_avg)) {
@@ -1296,6 +1297,8 @@ struct PrimalStep {
     part_ = uni(ppart);
     stride_ = uni(pstride);
     segp_ = uni(pseg);
+    lzero = (pflags & kLowerZero) != 0;
+    noup = (pflags & kNoUpper) != 0;
     tau = uni(tau), etav = uni(etav);
     return true;
   }
@@ -1305,8 +1308,8 @@ struct PrimalStep {
     q.c = ldg(cc, (uint32_t)j);
     q.x = ldg(x, (uint32_t)j);
     q.T = ldg(T, (uint32_t)j);
-    q.l = ldg(lo, (uint32_t)j);
-    q.u = ldg(hi, (uint32_t)j);
+    q.l = lzero ? V(0) : ldg(lo, (uint32_t)j);
+    q.u = noup ? V(INFINITY) : ldg(hi, (uint32_t)j);
     q.xs = ldg(xs, (uint32_t)j);
     q.H = ldg(Hsrc, (uint32_t)j);
     q.G = ldg(Gsrc, (uint32_t)j);

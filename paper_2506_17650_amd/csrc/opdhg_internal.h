@@ -48,12 +48,16 @@ struct DevParams {
   int32_t schedule;
   int32_t eval_every;
   int32_t max_retries;
-  int32_t flags;  // kConstantStep | kNoRestart | kWeightedStep
+  int32_t flags;  // kConstantStep | kNoRestart | kWeightedStep | kLowerZero | kNoUpper
 };
 
 constexpr int32_t kConstantStep = 1;  // every attempt accepted, eta unchanged (vanilla PDHG)
 constexpr int32_t kNoRestart = 2;     // evaluations test termination only
 constexpr int32_t kWeightedStep = 4;  // step-rule movement in the T^-1 and Sigma^-1 norms
+// every lower bound is 0 / every upper bound is +inf: the primal step knows
+// those bounds without reading them
+constexpr int32_t kLowerZero = 8;
+constexpr int32_t kNoUpper = 16;
 
 // Per-LP control block: the scalar state of the iteration. Written by the
 // decision kernels (step, termination / restart), the first tile of the
