@@ -2516,7 +2516,7 @@ int opdhg_workspace_bytes(const opdhg_lp* lp, const opdhg_params* p, size_t* byt
   if ((rc = validate_params(p))) return rc;
   if (!bytes) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bytes is NULL");
   Prepared P;
-  prepare(lp, p, P, true);
+  if ((rc = prepare(lp, p, P, true))) return rc;
   SlotLayout L = slot_layout(P, p->precision);
   *bytes = L.total + tables_bytes({&P}, grid_cap(p));
   return OPDHG_OK;

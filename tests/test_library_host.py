@@ -227,3 +227,29 @@ def test_server_sequences_hold_at_most_64_attempts():
                                     None, None, None)
         assert not h, bad
         assert "configuration" in capi.opdhg_last_error()
+
+
+def test_window_plans_pass_their_checks():
+    """Windowed chunks (FP32) are planned for every shape and window setting
+    the GPU tests use: each plan passes the library's index checks (slice
+    entries inside the entry arrays, lane rows below the chunk's rows,
+    window columns inside the staged window), or workspace sizing reports
+    an internal error. Windows take workspace: at the default window size
+    the block-angular LPs need more than in tiles (small windows may plan
+    no chunk at all)."""
+    from lpgen.generators import block_angular_lp
+    lps = [block_angular_lp(5, blocks=4, block_rows=3000, block_cols=8000, col_degree=6,
+                            link_rows=40, link_nnz_per_row=300),
+           block_angular_lp(6, blocks=3, block_rows=2500, block_cols=9000, col_degree=4,
+                            link_rows=3, link_nnz_per_row=6000),
+           config_lp("cfg3", index=7, scale=0.2), config_lp("cfg1", scale=0.1)]
+    for i, lp in enumerate(lps):
+        base = P.opdhg_default_params(precision=P.OPDHG_FP32, windows=P.OPDHG_WINDOWS_OFF)
+        tiles = P.opdhg_workspace_bytes(lp, base)
+        for wb, wr in [(0, 0), (1, 0), (2, 1500), (3, 2500), (8, 3000), (28, 10240)]:
+            p = P.opdhg_default_params(precision=P.OPDHG_FP32, windows=P.OPDHG_WINDOWS_ALWAYS,
+                                       window_buckets=wb, window_rows=wr)
+            ws = P.opdhg_workspace_bytes(lp, p)
+            assert ws >= tiles, (i, wb, wr)
+            if i < 2 and wb == 0:
+                assert ws > tiles, (i, wb, wr)
