@@ -359,9 +359,10 @@ def section_serving(P, args):
     throughput (mu_plain) and warm the server up; then `serve_requests`
     further requests arrive at rate 0.7 mu_plain and are served twice with
     the same arrival times: by the FP32 server (continuous batching, up to
-    256 resident LPs) and by plain FP64 PDHG (lr 0) one LP at a time through
-    the same server machinery (max_active 1, first in first out). Latency
-    runs from submit to the result on the host.
+    256 resident LPs, with the FP64 fallback for requests whose FP32 solve
+    ends short of the tolerance) and by plain FP64 PDHG (lr 0) one LP at a
+    time through the same server machinery (max_active 1, first in first
+    out). Latency runs from submit to the result on the host.
     """
     import numpy as np
     from lpgen import config_lp
@@ -404,39 +405,42 @@ def section_serving(P, args):
         th = threading.Thread(target=feed)
         th.start()
         th.join()
-        res, lat = [], []
+        res, lat, prec = [], [], []
         for x in tickets:
             res.append(srv.wait(x)[2])
             lat.append(srv.latency(x))
-        return res, lat, time.perf_counter() - t0
+            prec.append(srv.precision(x))
+        return res, lat, prec, time.perf_counter() - t0
 
-    with P.Server(arena, precision=P.OPDHG_FP32, max_active=256) as srv:
+    with P.Server(arena, precision=P.OPDHG_FP32, max_active=256,
+                  fallback=P.OPDHG_FALLBACK_FP64) as srv:
         # warm-up, closed loop: every warm-up request at once
         t0 = time.perf_counter()
         for x in [srv.submit(lp, p32) for lp in warm]:
             srv.wait(x)
         mu_srv = nw / (time.perf_counter() - t0)
         log(f"[bench] serving: server closed loop (warm-up set) mu {mu_srv:.2f}/s")
-        res32, lat32, span32 = open_loop(srv, p32)
+        res32, lat32, prec32, span32 = open_loop(srv, p32)
         st = srv.stats()
     del srv
     torch.cuda.empty_cache()  # the FP32 server's arena goes back to the device
     ok32 = sum(r.status == P.capi.OPDHG_STATUS_OPTIMAL for r in res32)
-    log(f"[bench] serving: FP32 server: {ok32}/{n} optimal, p50 {pct(lat32, 50):.3f}s "
-        f"p99 {pct(lat32, 99):.3f}s")
+    fell = [i for i in range(n) if prec32[i] == P.OPDHG_FP64]
+    log(f"[bench] serving: FP32 server: {ok32}/{n} optimal ({len(fell)} solved again in FP64), "
+        f"p50 {pct(lat32, 50):.3f}s p99 {pct(lat32, 99):.3f}s")
     # one LP at a time needs room for the largest request only (plus tables)
     one = max(P.opdhg_workspace_bytes(lp, p64) for lp in meas)
     with P.Server(min(arena, 4 * one + (256 << 20)), precision=P.OPDHG_FP64,
                   max_active=1) as srv:
-        res64, lat64, span64 = open_loop(srv, p64)
+        res64, lat64, _, span64 = open_loop(srv, p64)
     del srv
     torch.cuda.empty_cache()
     ok64 = sum(r.status == P.capi.OPDHG_STATUS_OPTIMAL for r in res64)
     log(f"[bench] serving: FP64 one at a time: {ok64}/{n} optimal, p50 {pct(lat64, 50):.3f}s "
         f"p99 {pct(lat64, 99):.3f}s")
     errs = [abs(a.primal_obj - b.primal_obj) / (1.0 + abs(b.primal_obj))
-            for a, b in zip(res32, res64)
-            if a.status == b.status == P.capi.OPDHG_STATUS_OPTIMAL]
+            for a, b, q in zip(res32, res64, prec32)
+            if a.status == b.status == P.capi.OPDHG_STATUS_OPTIMAL and q == P.OPDHG_FP32]
 
     def statuses(res):
         out = {}
@@ -468,6 +472,11 @@ def section_serving(P, args):
         "rate_rule": "0.7 x plain FP64 one-at-a-time throughput on the warm-up requests",
         "arena_bytes": arena, "peak_bytes": st.peak_bytes, "dtype": "f32",
         "optimal": ok32, "statuses": statuses(res32), "not_optimal": not_opt,
+        "fallback": "OPDHG_FALLBACK_FP64: a request whose FP32 solve ends short of its "
+                    "tolerance is solved again in FP64 by the server",
+        "fell_back": [{"request": i, "nnz": meas[i].nnz, "status": P.opdhg_status_name(res32[i].status),
+                       "fp64_iterations": res32[i].iterations, "latency_s": lat32[i]}
+                      for i in fell],
         "solves_per_s": ok32 / span32,
         "closed_loop_solves_per_s_warmup": mu_srv,
         "latency_p50_s": pct(lat32, 50), "latency_p99_s": pct(lat32, 99),
@@ -475,7 +484,8 @@ def section_serving(P, args):
         "fp32_vs_fp64_rel_objective_error": {
             "compared": len(errs), "max": max(errs) if errs else None,
             "median": pct(errs, 50), "p99": pct(errs, 99),
-            "note": "|p32 - p64| / (1 + |p64|) per request, both at rel KKT <= 1e-4"},
+            "note": "|p32 - p64| / (1 + |p64|) per request solved in FP32, both at rel KKT "
+                    "<= 1e-4"},
         "largest_request_prep_s": {"nnz": big.nnz, "host": prep["host"], "device": prep["device"],
                                    "note": "session creation; requests of 2^20 nonzeros or more "
                                            "are prepared on the device in the server runs"},

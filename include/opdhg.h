@@ -376,11 +376,30 @@ typedef struct opdhg_server_cfg {
   int32_t precision;     /* OPDHG_FP64 or OPDHG_FP32; every request must use it */
   int32_t workgroups;    /* workgroups of the sparse-product launches; 0: automatic */
   int32_t prep_threads;  /* host threads preparing submitted LPs; 0: automatic */
+  int32_t fallback;      /* OPDHG_FALLBACK_*: what happens to an FP32 request that ends
+                            without reaching its tolerance */
   double poll_interval_s; /* idle wait of the scheduler thread */
 } opdhg_server_cfg;
 
+/* Server fallback. FP32 stores A, the iterates and the gathered vectors in
+ * single precision; on an LP that needs a tiny primal weight, the rounding
+ * of the gathered y, multiplied by the primal step eta / omega, can stop
+ * progress (the iterate moves by noise and the restarts keep lowering
+ * omega). With OPDHG_FALLBACK_FP64 a request whose FP32 solve ends with
+ * OPDHG_STATUS_ITERATION_LIMIT or OPDHG_STATUS_NUMERICAL_ERROR is solved
+ * again from the start in FP64, with the same parameters, by a host thread
+ * of the server on a stream of its own (default priority), in arena memory
+ * taken like an admission; its result replaces the FP32 one, and
+ * opdhg_server_precision reports it. The server keeps each request's copy of
+ * the LP until the request is done. No fallback for a request that hit its
+ * time limit, was cancelled, or whose FP64 workspace exceeds the budget
+ * (the FP32 result is delivered). Ignored when the server runs FP64. */
+#define OPDHG_FALLBACK_NONE 0
+#define OPDHG_FALLBACK_FP64 1
+
 /* Defaults: budget = whole arena, 256 active LPs, 64 attempts per sequence,
- * FP32, automatic workgroups and preparation threads, 1 ms idle wait. */
+ * FP32, automatic workgroups and preparation threads, no fallback, 1 ms
+ * idle wait. */
 void opdhg_server_default_cfg(opdhg_server_cfg* cfg);
 
 typedef struct opdhg_server_stats {
@@ -393,6 +412,7 @@ typedef struct opdhg_server_stats {
   int64_t replays;       /* launch sequences issued */
   size_t bytes_in_use;   /* arena bytes held by resident LPs */
   size_t peak_bytes;
+  int64_t fallbacks;     /* requests solved again in FP64 (OPDHG_FALLBACK_FP64) */
 } opdhg_server_stats;
 
 /* Create a server over a caller-owned device arena (the launch tables take
@@ -427,6 +447,9 @@ int opdhg_server_get_stats(opdhg_server* s, opdhg_server_stats* out);
 /* Latency of the ticket: submit time to result-on-host, in seconds (valid
  * after poll returned the result). */
 int opdhg_server_latency(opdhg_server* s, uint64_t ticket, double* seconds);
+/* Precision of the solve that produced the ticket's result: the server's,
+ * or OPDHG_FP64 after a fallback (valid after poll returned the result). */
+int opdhg_server_precision(opdhg_server* s, uint64_t ticket, int32_t* precision);
 void opdhg_server_destroy(opdhg_server* s);
 
 const char* opdhg_last_error(void);

@@ -39,4 +39,6 @@ from .capi import (  # noqa: F401
     OPDHG_PREP_AUTO,
     OPDHG_PREP_HOST,
     OPDHG_PREP_DEVICE,
+    OPDHG_FALLBACK_NONE,
+    OPDHG_FALLBACK_FP64,
 )

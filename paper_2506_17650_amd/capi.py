@@ -53,6 +53,8 @@ OPDHG_WINDOWS_ALWAYS = 2
 OPDHG_PREP_AUTO = 0
 OPDHG_PREP_HOST = 1
 OPDHG_PREP_DEVICE = 2
+OPDHG_FALLBACK_NONE = 0
+OPDHG_FALLBACK_FP64 = 1
 
 _p = ctypes.POINTER
 c_i64, c_i32, c_dbl, c_sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
@@ -107,7 +109,7 @@ class opdhg_server_cfg(ctypes.Structure):
     _fields_ = [
         ("budget_bytes", c_sz), ("max_active", c_i32), ("attempts_per_replay", c_i32),
         ("precision", c_i32), ("workgroups", c_i32), ("prep_threads", c_i32),
-        ("poll_interval_s", c_dbl),
+        ("fallback", c_i32), ("poll_interval_s", c_dbl),
     ]
 
 
@@ -115,7 +117,7 @@ class opdhg_server_stats(ctypes.Structure):
     _fields_ = [
         ("submitted", c_i64), ("completed", c_i64), ("cancelled", c_i64), ("failed", c_i64),
         ("active", c_i64), ("queued", c_i64), ("replays", c_i64), ("bytes_in_use", c_sz),
-        ("peak_bytes", c_sz),
+        ("peak_bytes", c_sz), ("fallbacks", c_i64),
     ]
 
 
@@ -169,6 +171,7 @@ SIGNATURES = {
     "opdhg_server_cancel": (c_i32, [ctypes.c_void_p, ctypes.c_uint64]),
     "opdhg_server_get_stats": (c_i32, [ctypes.c_void_p, _p(opdhg_server_stats)]),
     "opdhg_server_latency": (c_i32, [ctypes.c_void_p, ctypes.c_uint64, _p(c_dbl)]),
+    "opdhg_server_precision": (c_i32, [ctypes.c_void_p, ctypes.c_uint64, _p(c_i32)]),
     "opdhg_server_destroy": (None, [ctypes.c_void_p]),
     "opdhg_last_error": (ctypes.c_char_p, []),
     "opdhg_status_name": (ctypes.c_char_p, [c_i32]),
@@ -578,6 +581,13 @@ class Server:
         out = c_dbl(0.0)
         _check(load().opdhg_server_latency(self._h, ctypes.c_uint64(ticket), ctypes.byref(out)))
         return float(out.value)
+
+    def precision(self, ticket: int) -> int:
+        """Precision of the solve that produced the ticket's result (the
+        server's, or OPDHG_FP64 after a fallback)."""
+        out = c_i32(0)
+        _check(load().opdhg_server_precision(self._h, ctypes.c_uint64(ticket), ctypes.byref(out)))
+        return int(out.value)
 
     def close(self) -> None:
         if self._h:

@@ -30,6 +30,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "opdhg.h"
@@ -184,8 +185,20 @@ struct ServerImpl {
   std::vector<std::thread> th_prep;
   std::thread th_sched;
 
+  // FP64 fallback of FP32 requests that end short of their tolerance
+  bool fallback_on = false;
+  int device = 0;
+  hipStream_t s_fb = nullptr;
+  std::deque<std::shared_ptr<Job>> to_fallback;
+  std::condition_variable cv_fb;
+  std::thread th_fb;
+  size_t fb_wait = 0;  // arena bytes a fallback waits for (admissions pause meanwhile)
+  int64_t n_fallback = 0;
+  std::unordered_set<uint64_t> fell_back;  // tickets whose result is the FP64 solve's
+
   void prep_loop();
   void sched_loop();
+  void fallback_loop();
   bool fits_tables(int64_t nlps, int64_t it, int64_t ia) const;
   int admit(Job& j);
   int write_shared();
@@ -233,6 +246,16 @@ bool ServerImpl::fits_tables(int64_t nlps, int64_t it, int64_t ia) const {
 }
 
 void ServerImpl::finish_job(Job& j, int err, const std::string& msg) {
+  if (fallback_on) {  // the copy of the LP kept for a fallback
+    release_vec(j.rp);
+    release_vec(j.ci);
+    release_vec(j.va);
+    release_vec(j.b);
+    release_vec(j.c);
+    release_vec(j.l);
+    release_vec(j.u);
+    release_vec(j.sense);
+  }
   j.err = err;
   j.errmsg = msg;
   j.state = JobState::kDone;
@@ -284,16 +307,18 @@ void ServerImpl::prep_loop() {
         msg = "LP has more tiles than the launch tables hold";
       }
     }
-    if (!j->P.dstruct) {  // else the device builds the structure from them at admission
-      release_vec(j->rp);
-      release_vec(j->ci);
-      release_vec(j->va);
+    if (!fallback_on) {  // else a fallback solves the LP again from its copy
+      if (!j->P.dstruct) {  // else the device builds the structure from them at admission
+        release_vec(j->rp);
+        release_vec(j->ci);
+        release_vec(j->va);
+      }
+      release_vec(j->b);
+      release_vec(j->c);
+      release_vec(j->l);
+      release_vec(j->u);
+      release_vec(j->sense);
     }
-    release_vec(j->b);
-    release_vec(j->c);
-    release_vec(j->l);
-    release_vec(j->u);
-    release_vec(j->sense);
     std::lock_guard<std::mutex> lk(mu);
     if (j->state != JobState::kQueued) continue;  // cancelled meanwhile
     if (rc) {
@@ -318,9 +343,11 @@ int ServerImpl::admit(Job& j) {
   // the staging image (and the LP's own arrays) must outlive the copy
   HIP_TRY(hipStreamSynchronize(s_h2d));
   if (j.P.dstruct) {
-    release_vec(j.rp);
-    release_vec(j.ci);
-    release_vec(j.va);
+    if (!fallback_on) {
+      release_vec(j.rp);
+      release_vec(j.ci);
+      release_vec(j.va);
+    }
     j.P.h_rp = nullptr;
     j.P.h_ci = nullptr;
     j.P.h_val = nullptr;
@@ -404,8 +431,84 @@ int ServerImpl::retire(Job& j, bool cancelled) {
   if (j.placed) arena.release(j.off, j.need);
   j.placed = false;
   --n_active;
+  cv_fb.notify_all();  // a fallback may be waiting for the memory
+  const bool short_of_tol = j.res.status == OPDHG_STATUS_ITERATION_LIMIT ||
+                            j.res.status == OPDHG_STATUS_NUMERICAL_ERROR;
+  if (fallback_on && !cancelled && rc == OPDHG_OK && !stopping && short_of_tol) {
+    auto it = jobs.find(j.ticket);
+    if (it != jobs.end()) {
+      to_fallback.push_back(it->second);
+      return rc;
+    }
+  }
   finish_job(j, cancelled ? OPDHG_ERR_CANCELLED : rc, cancelled ? "cancelled" : msg);
   return rc;
+}
+
+// Fallback worker: solves the handed-over FP32 requests again in FP64, one
+// at a time, on its own stream, in arena memory taken like an admission. The
+// FP32 result stands where the fallback cannot run.
+void ServerImpl::fallback_loop() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    std::shared_ptr<Job> j;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_fb.wait(lk, [&] { return stopping || !to_fallback.empty(); });
+      if (to_fallback.empty()) return;
+      j = to_fallback.front();
+      to_fallback.pop_front();
+      if (j->cancel || stopping) {
+        finish_job(*j, j->cancel ? OPDHG_ERR_CANCELLED : OPDHG_OK, j->cancel ? "cancelled" : "");
+        continue;
+      }
+    }
+    opdhg_params p64 = j->p;
+    p64.precision = OPDHG_FP64;
+    const opdhg_lp v = lp_view(*j);
+    size_t need = 0;
+    int rc = opdhg_workspace_bytes(&v, &p64, &need);
+    need = align256(need);
+    size_t off = 0;
+    bool got = false;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (rc || need > budget) {
+        finish_job(*j, OPDHG_OK, "");
+        continue;
+      }
+      fb_wait = need;
+      while (!stopping && !j->cancel && !(got = arena.alloc(need, &off)))
+        cv_fb.wait_for(lk, std::chrono::duration<double>(std::max(cfg.poll_interval_s, 1e-4)));
+      fb_wait = 0;
+      cv_sched.notify_all();
+      if (!got) {
+        finish_job(*j, j->cancel ? OPDHG_ERR_CANCELLED : OPDHG_OK, j->cancel ? "cancelled" : "");
+        continue;
+      }
+      peak = std::max(peak, arena.used());
+    }
+    std::vector<double> x((size_t)j->n), y((size_t)std::max<int64_t>(j->m, 1));
+    opdhg_result res{};
+    rc = opdhg_solve(&v, &p64, arena_base + table_bytes + off, need, s_fb, x.data(), y.data(),
+                     &res);
+    const std::string msg = rc ? std::string(opdhg_last_error()) : std::string();
+    std::lock_guard<std::mutex> lk(mu);
+    arena.release(off, need);
+    cv_sched.notify_all();
+    if (rc == OPDHG_OK) {
+      y.resize((size_t)j->m);
+      j->x.swap(x);
+      j->y.swap(y);
+      j->res = res;
+      ++n_fallback;
+      fell_back.insert(j->ticket);
+      finish_job(*j, OPDHG_OK, "");
+    } else {
+      // a device error is the request's; otherwise the FP32 result stands
+      finish_job(*j, rc == OPDHG_ERR_DEVICE ? rc : OPDHG_OK, rc == OPDHG_ERR_DEVICE ? msg : "");
+    }
+  }
 }
 
 void ServerImpl::sched_loop() {
@@ -455,6 +558,7 @@ void ServerImpl::sched_loop() {
         it += j->P.tiles_t.size();
         ia += j->P.tiles_a.size();
         if (nl > cfg.max_active || !fits_tables(nl, it, ia)) break;
+        if (fb_wait > 0) break;  // a fallback takes freed memory first
         size_t off = 0;
         if (!arena.alloc(j->need, &off)) break;
         j->off = off;
@@ -565,6 +669,7 @@ void opdhg_server_default_cfg(opdhg_server_cfg* cfg) {
   cfg->precision = OPDHG_FP32;
   cfg->workgroups = 0;
   cfg->prep_threads = 0;
+  cfg->fallback = OPDHG_FALLBACK_NONE;
   cfg->poll_interval_s = 1e-3;
 }
 
@@ -578,6 +683,7 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
       cfg->attempts_per_replay > kPowRing ||
       (cfg->precision != OPDHG_FP32 && cfg->precision != OPDHG_FP64) || cfg->workgroups < 0 ||
       cfg->prep_threads < 0 || cfg->prep_threads > 64 ||
+      (cfg->fallback != OPDHG_FALLBACK_NONE && cfg->fallback != OPDHG_FALLBACK_FP64) ||
       cfg->workgroups > kMaxGrid || !(cfg->poll_interval_s >= 0.0)) {
     fail(OPDHG_ERR_INVALID_ARGUMENT, "bad server configuration");
     return nullptr;
@@ -647,10 +753,20 @@ opdhg_server* opdhg_server_create(const opdhg_server_cfg* cfg, void* d_arena, si
     S.grp.release();
     return nullptr;
   }
+  S.fallback_on = cfg->fallback == OPDHG_FALLBACK_FP64 && cfg->precision == OPDHG_FP32;
+  if (S.fallback_on &&
+      (hipGetDevice(&S.device) != hipSuccess ||
+       hipStreamCreateWithFlags(&S.s_fb, hipStreamNonBlocking) != hipSuccess)) {
+    fail(OPDHG_ERR_DEVICE, "creating the fallback stream failed");
+    (void)hipHostFree(S.pinned_board);
+    S.grp.release();
+    return nullptr;
+  }
   const int nprep = cfg->prep_threads > 0 ? cfg->prep_threads
                                           : std::max(1, std::min(host_threads() / 2, 8));
   for (int t = 0; t < nprep; ++t) S.th_prep.emplace_back([&S] { S.prep_loop(); });
   S.th_sched = std::thread([&S] { S.sched_loop(); });
+  if (S.fallback_on) S.th_fb = std::thread([&S] { S.fallback_loop(); });
   return s.release();
 }
 
@@ -762,6 +878,7 @@ int opdhg_server_get_stats(opdhg_server* s, opdhg_server_stats* out) {
   out->replays = S.n_replays;
   out->bytes_in_use = S.arena.used();
   out->peak_bytes = S.peak;
+  out->fallbacks = S.n_fallback;
   return OPDHG_OK;
 }
 
@@ -775,6 +892,16 @@ int opdhg_server_latency(opdhg_server* s, uint64_t ticket, double* seconds) {
   return OPDHG_OK;
 }
 
+int opdhg_server_precision(opdhg_server* s, uint64_t ticket, int32_t* precision) {
+  if (!s || !precision) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  ServerImpl& S = s->impl;
+  std::lock_guard<std::mutex> lk(S.mu);
+  if (S.latency.find(ticket) == S.latency.end())
+    return fail(OPDHG_ERR_NOT_READY, "no result for this ticket yet");
+  *precision = S.fell_back.count(ticket) ? OPDHG_FP64 : S.cfg.precision;
+  return OPDHG_OK;
+}
+
 void opdhg_server_destroy(opdhg_server* s) {
   if (!s) return;
   ServerImpl& S = s->impl;
@@ -784,9 +911,12 @@ void opdhg_server_destroy(opdhg_server* s) {
   }
   S.cv_prep.notify_all();
   S.cv_sched.notify_all();
+  S.cv_fb.notify_all();
   for (auto& t : S.th_prep)
     if (t.joinable()) t.join();
   if (S.th_sched.joinable()) S.th_sched.join();
+  if (S.th_fb.joinable()) S.th_fb.join();  // a solve in progress finishes first
+  if (S.s_fb) (void)hipStreamDestroy(S.s_fb);
   if (S.pinned_board) (void)hipHostFree(S.pinned_board);
   S.grp.release();
   delete s;

@@ -179,3 +179,35 @@ def test_vanilla_and_adaptive_requests_mixed():
         _same(a, b)
         _vs_oracle(P, prec, lp, a, op, f"mixed-scheme LP {i}")
     assert got[0][2].restarts == 0 and got[1][2].restarts == 0
+
+
+def test_fp64_fallback_of_requests_short_of_tolerance():
+    # With OPDHG_FALLBACK_FP64 an FP32 request that ends at its iteration
+    # limit is solved again in FP64 with the same parameters: its result is
+    # the plain FP64 solve's (and the oracle's), the server reports FP64 for
+    # its ticket, and a request that reaches its tolerance keeps its FP32
+    # result. Without the fallback the FP32 result comes back.
+    P = _P()
+    lps = [config_lp("cfg0", seed=s) for s in range(2)]
+    short = _params(P, P.OPDHG_FP32, max_iter=30)  # stops at the iteration limit
+    full = _params(P, P.OPDHG_FP32)
+    with P.Server(256 << 20, precision=P.OPDHG_FP32, fallback=P.OPDHG_FALLBACK_FP64) as srv:
+        t_short = srv.submit(lps[0], short)
+        t_full = srv.submit(lps[1], full)
+        got_short = srv.wait(t_short, 120.0)
+        got_full = srv.wait(t_full, 120.0)
+        st = srv.stats()
+        prec_short, prec_full = srv.precision(t_short), srv.precision(t_full)
+    assert st.fallbacks == 1 and st.completed == 2 and st.failed == 0
+    assert prec_short == P.OPDHG_FP64 and prec_full == P.OPDHG_FP32
+    assert got_short[2].status == P.capi.OPDHG_STATUS_ITERATION_LIMIT
+    _same(got_short, P.opdhg_solve(lps[0], _params(P, P.OPDHG_FP64, max_iter=30)))
+    _vs_oracle(P, P.OPDHG_FP64, lps[0], got_short, _oparams(max_iter=30), "fallback")
+    assert got_full[2].status == P.capi.OPDHG_STATUS_OPTIMAL
+    _same(got_full, P.opdhg_solve(lps[1], full))
+    with P.Server(256 << 20, precision=P.OPDHG_FP32) as srv:
+        t = srv.submit(lps[0], short)
+        got = srv.wait(t, 120.0)
+        assert srv.precision(t) == P.OPDHG_FP32 and srv.stats().fallbacks == 0
+    assert got[2].status == P.capi.OPDHG_STATUS_ITERATION_LIMIT
+    _same(got, P.opdhg_solve(lps[0], short))
