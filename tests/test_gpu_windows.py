@@ -48,15 +48,16 @@ def _lib(P, op, **kw):
         windows=P.OPDHG_WINDOWS_ALWAYS, **kw)
 
 
-# block-angular LPs small enough for the oracle: 6 blocks of 3000 x 8000,
-# 6 nonzeros per column, plus linking rows; the A side (block rows, 16 per
-# row) is windowed. window_buckets / window_rows force more passes and other
-# chunkings.
+# block-angular LPs small enough for the oracle (cfg2 at a tenth: 18.2k x
+# 48k), plus linking rows; the A side (block rows) is windowed, the A^T side
+# too where the chunkings allow. window_buckets / window_rows force more
+# passes and other chunkings. A chunk of one pass keeps its row sums in
+# registers, a chunk of several in LDS: both kinds run in these cases.
 CASES = [
-    dict(window_buckets=0, window_rows=0),     # automatic: 2 passes per chunk
-    dict(window_buckets=2, window_rows=0),     # 4 passes of 2048 entries
-    dict(window_buckets=3, window_rows=2500),  # 3 passes, chunks ending mid-block
-    dict(window_buckets=8, window_rows=3000),  # 1 pass, one chunk per block
+    dict(window_buckets=0, window_rows=0),     # A: one pass per chunk but one (two)
+    dict(window_buckets=2, window_rows=0),     # A: 4 passes of 2048 entries
+    dict(window_buckets=3, window_rows=2500),  # A^T 2 passes, A 3; chunks ending mid-block
+    dict(window_buckets=8, window_rows=3000),  # A^T one pass; A one or two
 ]
 
 
@@ -69,8 +70,8 @@ def _block_long():
 
 
 CASES_LONG = [
-    dict(window_buckets=0, window_rows=0),     # A rows windowed, linking rows as segments
-    dict(window_buckets=2, window_rows=1500),  # A^T rows windowed in up to 3 passes
+    dict(window_buckets=0, window_rows=0),     # A rows in one pass, linking rows as segments
+    dict(window_buckets=2, window_rows=1500),  # A^T rows in 2 passes, A rows in 4
 ]
 
 
