@@ -269,6 +269,25 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p,
                       void* d_workspace, size_t workspace_bytes, void* hip_stream,
                       double* const* x_out, double* const* y_out, opdhg_result* res);
 
+/* The same packed solve in two calls, so that the set is prepared once:
+ * opdhg_batch_prepare validates and prepares the LPs (structure, tiling,
+ * windows, and their scaled data when the host prepares them) and sizes
+ * the workspace exactly (opdhg_batch_bytes), where
+ * opdhg_batch_workspace_bytes followed by opdhg_solve_batch prepares each
+ * LP twice. The LPs' arrays are borrowed: they must stay valid and
+ * unchanged until opdhg_batch_solve returns. opdhg_batch_solve runs once
+ * per handle (OPDHG_ERR_INVALID_ARGUMENT after that); its results equal
+ * opdhg_solve_batch's bit for bit. opdhg_batch_destroy frees the handle
+ * (NULL is ignored). */
+typedef struct opdhg_batch opdhg_batch;
+int opdhg_batch_prepare(int count, const opdhg_lp* lps, const opdhg_params* p,
+                        opdhg_batch** out);
+int opdhg_batch_bytes(const opdhg_batch* b, size_t* bytes);
+int opdhg_batch_solve(opdhg_batch* b, void* d_workspace, size_t workspace_bytes,
+                      void* hip_stream, double* const* x_out, double* const* y_out,
+                      opdhg_result* res);
+void opdhg_batch_destroy(opdhg_batch* b);
+
 /* ---- allocation-free solve ----
  * For callers that cannot allocate device memory or let a library create
  * HIP objects: tight serving loops that must not call hipMalloc, harnesses

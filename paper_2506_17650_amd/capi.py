@@ -144,6 +144,12 @@ SIGNATURES = {
     "opdhg_solve_batch": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                                   ctypes.c_void_p, _p(_p(c_dbl)), _p(_p(c_dbl)),
                                   _p(opdhg_result)]),
+    "opdhg_batch_prepare": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params),
+                                    _p(ctypes.c_void_p)]),
+    "opdhg_batch_bytes": (c_i32, [ctypes.c_void_p, _p(c_sz)]),
+    "opdhg_batch_solve": (c_i32, [ctypes.c_void_p, ctypes.c_void_p, c_sz, ctypes.c_void_p,
+                                  _p(_p(c_dbl)), _p(_p(c_dbl)), _p(opdhg_result)]),
+    "opdhg_batch_destroy": (None, [ctypes.c_void_p]),
     "opdhg_autotune_workspace_bytes": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), _p(c_sz)]),
     "opdhg_autotune": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                                ctypes.c_void_p, c_i32, _p(opdhg_tuning)]),
@@ -392,21 +398,31 @@ def opdhg_solve_noalloc(lp, params: Optional[opdhg_params] = None, stream=None):
 
 def opdhg_solve_batch(lps: Sequence, params: Optional[opdhg_params] = None, workspace=None,
                       stream=None):
-    """Solve LPs packed into one set of launches: list of (x, y, result)."""
+    """Solve LPs packed into one set of launches: list of (x, y, result).
+
+    The set is prepared once (opdhg_batch_prepare), the workspace sized
+    from it (a device tensor when none is given), then solved."""
     params = params or opdhg_default_params()
-    arrs = [_LPArrays(lp) for lp in lps]
+    arrs = [_LPArrays(lp) for lp in lps]  # borrowed by the handle until the solve
     count = len(arrs)
     structs = (opdhg_lp * count)(*[a.struct for a in arrs])
-    need = opdhg_batch_workspace_bytes(lps, params)
-    ws = workspace if workspace is not None else device_workspace(need)
-    ptr, size = _ws_ptr(ws)
-    xs = [np.empty(a.n) for a in arrs]
-    ys = [np.empty(max(a.m, 1)) for a in arrs]
-    xp = (_p(c_dbl) * count)(*[_dptr(v, c_dbl) for v in xs])
-    yp = (_p(c_dbl) * count)(*[_dptr(v, c_dbl) for v in ys])
-    res = (opdhg_result * count)()
-    _check(load().opdhg_solve_batch(count, structs, ctypes.byref(params), ctypes.c_void_p(ptr),
-                                    size, ctypes.c_void_p(_stream_handle(stream)), xp, yp, res))
+    lib = load()
+    h = ctypes.c_void_p()
+    _check(lib.opdhg_batch_prepare(count, structs, ctypes.byref(params), ctypes.byref(h)))
+    try:
+        need = c_sz(0)
+        _check(lib.opdhg_batch_bytes(h, ctypes.byref(need)))
+        ws = workspace if workspace is not None else device_workspace(int(need.value))
+        ptr, size = _ws_ptr(ws)
+        xs = [np.empty(a.n) for a in arrs]
+        ys = [np.empty(max(a.m, 1)) for a in arrs]
+        xp = (_p(c_dbl) * count)(*[_dptr(v, c_dbl) for v in xs])
+        yp = (_p(c_dbl) * count)(*[_dptr(v, c_dbl) for v in ys])
+        res = (opdhg_result * count)()
+        _check(lib.opdhg_batch_solve(h, ctypes.c_void_p(ptr), size,
+                                     ctypes.c_void_p(_stream_handle(stream)), xp, yp, res))
+    finally:
+        lib.opdhg_batch_destroy(h)
     return [(xs[i], ys[i][: arrs[i].m], res[i]) for i in range(count)]
 
 

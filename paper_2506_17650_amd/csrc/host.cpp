@@ -2808,20 +2808,35 @@ int opdhg_batch_workspace_bytes(int count, const opdhg_lp* lps, const opdhg_para
   return OPDHG_OK;
 }
 
-int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p_in,
-                      void* d_workspace, size_t workspace_bytes, void* hip_stream,
-                      double* const* x_out, double* const* y_out, opdhg_result* res) {
-  if (count < 0 || (count > 0 && (!lps || !res)) || !d_workspace)
-    return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+}  // extern "C"
+
+// A packed set prepared once: the LPs' validation, structure, tiling and
+// windows (and, with host preparation, their scaled data), the slot layouts
+// and the exact workspace bytes.
+struct opdhg_batch {
+  int count = 0;
+  std::vector<opdhg_lp> lps;  // the caller's arrays, borrowed until the solve
+  opdhg_params p{};
+  std::vector<Prepared> P;
+  std::vector<SlotLayout> L;
+  std::vector<size_t> offs;
+  size_t off = 0, need = 0;
+};
+
+static int batch_prepare(int count, const opdhg_lp* lps, const opdhg_params* p_in,
+                         opdhg_batch& B) {
+  if (count < 0 || (count > 0 && !lps)) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
   int rc = validate_params(p_in);
   if (rc) return rc;
-  const opdhg_params pb = batch_params(count, lps, p_in);
-  const opdhg_params* p = &pb;
-  if (count == 0) return OPDHG_OK;
-  std::vector<Prepared> P(count);
-  std::vector<SlotLayout> L(count);
-  size_t off = 0;
-  std::vector<size_t> offs(count);
+  B.count = count;
+  B.lps.assign(lps, lps + count);
+  B.p = batch_params(count, lps, p_in);
+  const opdhg_params* p = &B.p;
+  std::vector<Prepared>& P = B.P;
+  std::vector<SlotLayout>& L = B.L;
+  P.assign(count, Prepared());
+  L.assign(count, SlotLayout());
+  B.offs.assign(count, 0);
   // validation, rescaling, transposes and tiling of each LP are independent
   std::vector<int> rcs(count, OPDHG_OK);
   std::vector<std::string> msgs(count);
@@ -2841,15 +2856,34 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p_in,
   for (int t = 1; t < nth; ++t) pool.emplace_back(work);
   work();
   for (auto& t : pool) t.join();
+  size_t off = 0;
   for (int i = 0; i < count; ++i) {
     if (rcs[i]) return fail(rcs[i], "LP " + std::to_string(i) + ": " + msgs[i]);
     L[i] = slot_layout(P[i], p->precision);
-    offs[i] = off;
+    B.offs[i] = off;
     off += L[i].total;
   }
   ListSizes z;
   for (int i = 0; i < count; ++i) z.add(P[i]);
-  const size_t need = off + tables_bytes(z, grid_cap(p));
+  B.off = off;
+  B.need = off + tables_bytes(z, grid_cap(p));
+  return OPDHG_OK;
+}
+
+static int batch_solve(opdhg_batch& B, void* d_workspace, size_t workspace_bytes,
+                       void* hip_stream, double* const* x_out, double* const* y_out,
+                       opdhg_result* res) {
+  const int count = B.count;
+  if (count == 0) return OPDHG_OK;
+  if (!d_workspace || !res) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  int rc = OPDHG_OK;
+  const opdhg_params* p = &B.p;
+  std::vector<Prepared>& P = B.P;
+  std::vector<SlotLayout>& L = B.L;
+  std::vector<size_t>& offs = B.offs;
+  const size_t off = B.off;
+  std::vector<std::string> msgs(count);
+  const size_t need = B.need;
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(need) + " bytes");
   uint8_t* ws = static_cast<uint8_t*>(d_workspace);
@@ -2945,6 +2979,49 @@ int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p_in,
   grp.release();
   return rc;
 }
+
+extern "C" {
+
+int opdhg_solve_batch(int count, const opdhg_lp* lps, const opdhg_params* p_in,
+                      void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                      double* const* x_out, double* const* y_out, opdhg_result* res) {
+  if (count < 0 || (count > 0 && (!lps || !res)) || !d_workspace)
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  opdhg_batch B;
+  int rc = batch_prepare(count, lps, p_in, B);
+  if (rc) return rc;
+  return batch_solve(B, d_workspace, workspace_bytes, hip_stream, x_out, y_out, res);
+}
+
+int opdhg_batch_prepare(int count, const opdhg_lp* lps, const opdhg_params* p,
+                        opdhg_batch** out) {
+  if (!out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  auto B = std::make_unique<opdhg_batch>();
+  int rc = batch_prepare(count, lps, p, *B);
+  if (rc) return rc;
+  *out = B.release();
+  return OPDHG_OK;
+}
+
+int opdhg_batch_bytes(const opdhg_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  *bytes = b->need;
+  return OPDHG_OK;
+}
+
+int opdhg_batch_solve(opdhg_batch* b, void* d_workspace, size_t workspace_bytes,
+                      void* hip_stream, double* const* x_out, double* const* y_out,
+                      opdhg_result* res) {
+  if (!b) return fail(OPDHG_ERR_INVALID_ARGUMENT, "batch is NULL");
+  if (b->count > 0 && b->P.empty())
+    return fail(OPDHG_ERR_INVALID_ARGUMENT, "batch was solved already");
+  const int rc = batch_solve(*b, d_workspace, workspace_bytes, hip_stream, x_out, y_out, res);
+  b->P.clear();  // the prepared data went into the workspace
+  return rc;
+}
+
+void opdhg_batch_destroy(opdhg_batch* b) { delete b; }
 
 const char* opdhg_last_error(void) { return g_err.c_str(); }
 

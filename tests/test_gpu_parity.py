@@ -402,3 +402,49 @@ def test_weighted_step_vanilla_trace_parity(P):
     # the constant step ignores the movement: weighting must change nothing there
     _say("[weighted step + vanilla]")
     check_trace(P, config_lp("cfg0", seed=5), vanilla_params(1e-1, step_norm=1), K=120)
+
+
+def test_prepared_batch_handle_equals_one_call(P):
+    # opdhg_batch_prepare / _bytes / _solve (what the binding's
+    # opdhg_solve_batch uses) against the one-call opdhg_solve_batch through
+    # the C-ABI, bit for bit; the handle sizes the workspace as
+    # opdhg_batch_workspace_bytes does, and solves once only
+    import ctypes
+    from paper_2506_17650_amd import capi
+    lps = [config_lp("cfg0", seed=s) for s in range(3)] + [config_lp("cfg3", index=2, scale=0.1)]
+    _say(f"[batch handle] {len(lps)} LPs")
+    for prec in (P.OPDHG_FP64, P.OPDHG_FP32):
+        p = lib_params(P, default_params(max_iter=3000, lr=1e-2), precision=prec)
+        via_handle = P.opdhg_solve_batch(lps, p)
+        lib = capi.load()
+        arrs = [capi._LPArrays(lp) for lp in lps]
+        structs = (capi.opdhg_lp * len(lps))(*[a.struct for a in arrs])
+        need = P.opdhg_batch_workspace_bytes(lps, p)
+        h = ctypes.c_void_p()
+        capi._check(lib.opdhg_batch_prepare(len(lps), structs, ctypes.byref(p), ctypes.byref(h)))
+        got = ctypes.c_size_t(0)
+        capi._check(lib.opdhg_batch_bytes(h, ctypes.byref(got)))
+        assert got.value == need
+        ws = capi.device_workspace(need)
+        ptr, size = capi._ws_ptr(ws)
+        xs = [np.empty(a.n) for a in arrs]
+        ys = [np.empty(max(a.m, 1)) for a in arrs]
+        xp = (ctypes.POINTER(ctypes.c_double) * len(lps))(*[capi._dptr(v, ctypes.c_double) for v in xs])
+        yp = (ctypes.POINTER(ctypes.c_double) * len(lps))(*[capi._dptr(v, ctypes.c_double) for v in ys])
+        res = (capi.opdhg_result * len(lps))()
+        capi._check(lib.opdhg_batch_solve(h, ctypes.c_void_p(ptr), size, None, xp, yp, res))
+        again = lib.opdhg_batch_solve(h, ctypes.c_void_p(ptr), size, None, xp, yp, res)
+        lib.opdhg_batch_destroy(h)
+        assert again == capi.OPDHG_ERR_INVALID_ARGUMENT
+        one_call = (capi.opdhg_result * len(lps))()
+        xo = [np.empty(a.n) for a in arrs]
+        yo = [np.empty(max(a.m, 1)) for a in arrs]
+        xop = (ctypes.POINTER(ctypes.c_double) * len(lps))(*[capi._dptr(v, ctypes.c_double) for v in xo])
+        yop = (ctypes.POINTER(ctypes.c_double) * len(lps))(*[capi._dptr(v, ctypes.c_double) for v in yo])
+        capi._check(lib.opdhg_solve_batch(len(lps), structs, ctypes.byref(p), ctypes.c_void_p(ptr),
+                                          size, None, xop, yop, one_call))
+        for i, (x, y, r) in enumerate(via_handle):
+            m = lps[i].m
+            assert np.array_equal(x, xo[i]) and np.array_equal(y, yo[i][:m]), i
+            assert r.iterations == one_call[i].iterations and r.status == one_call[i].status
+            assert np.array_equal(xs[i], xo[i]) and np.array_equal(ys[i][:m], yo[i][:m]), i
