@@ -1615,11 +1615,13 @@ __global__ __launch_bounds__(kBlock) void k_dual(LaunchCfg cfg, int force) {
 // Windowed step kernel (FP32): one workgroup of kWinBlock threads per
 // windowed chunk. Each pass stages its vector ranges in LDS; then the
 // pass's slices go to the waves in turn (slice j to wave j mod kWinWaves),
-// each lane adding up its row's entries in order, gathering from LDS, and
-// adding that sum to the row's total in LDS. A row has one lane in a pass,
-// so every row sum is formed in one fixed order (the same for every grid
-// and every co-resident LP). After the passes each thread runs the row
-// epilogue for rows r0 + t, r0 + t + kWinBlock, ...
+// each lane adding up its row's entries in order, gathering from LDS. A
+// chunk of several passes adds each such sum to the row's total in LDS; a
+// chunk of one pass keeps the sums in registers and writes them to LDS once
+// the window is done with. A row has one lane in a pass, so every row sum is
+// formed in one fixed order (the same for every grid and every co-resident
+// LP). After the passes each thread runs the row epilogue for rows r0 + t,
+// r0 + t + kWinBlock, ...
 template <bool tside, typename Step, typename Pre, int NV>
 __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* list, int nwin,
                                           int force) {
