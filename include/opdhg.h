@@ -353,6 +353,24 @@ int opdhg_autotune(int count, const opdhg_lp* lps, const opdhg_params* p, void* 
 
 int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
                          size_t workspace_bytes, void* hip_stream, opdhg_session** out);
+
+/* A session in two calls, so that the LP is prepared once: opdhg_prepare
+ * validates and prepares it (structure, tiling, windows, and its scaled
+ * data when the host prepares it) and sizes the workspace exactly
+ * (opdhg_prepared_bytes), where opdhg_workspace_bytes followed by
+ * opdhg_session_create prepares the LP twice. opdhg_session_create_prepared
+ * then creates the session as opdhg_session_create does (same results bit
+ * for bit); it takes the prepared data, so it runs once per handle
+ * (OPDHG_ERR_INVALID_ARGUMENT after that). The LP's arrays are borrowed:
+ * they must stay valid and unchanged until the session is created.
+ * opdhg_prepared_destroy frees the handle (NULL is ignored). */
+typedef struct opdhg_prepared opdhg_prepared;
+int opdhg_prepare(const opdhg_lp* lp, const opdhg_params* p, opdhg_prepared** out);
+int opdhg_prepared_bytes(const opdhg_prepared* pr, size_t* bytes);
+int opdhg_session_create_prepared(opdhg_prepared* pr, void* d_workspace, size_t workspace_bytes,
+                                  void* hip_stream, opdhg_session** out);
+void opdhg_prepared_destroy(opdhg_prepared* pr);
+
 /* Run until k >= k_target accepted iterations or the solve finishes
  * (k_target < 0: until it finishes). An evaluation due at k_target is left
  * for the next call, so a paused state is the state after k_target

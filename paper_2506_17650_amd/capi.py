@@ -150,6 +150,11 @@ SIGNATURES = {
     "opdhg_batch_solve": (c_i32, [ctypes.c_void_p, ctypes.c_void_p, c_sz, ctypes.c_void_p,
                                   _p(_p(c_dbl)), _p(_p(c_dbl)), _p(opdhg_result)]),
     "opdhg_batch_destroy": (None, [ctypes.c_void_p]),
+    "opdhg_prepare": (c_i32, [_p(opdhg_lp), _p(opdhg_params), _p(ctypes.c_void_p)]),
+    "opdhg_prepared_bytes": (c_i32, [ctypes.c_void_p, _p(c_sz)]),
+    "opdhg_session_create_prepared": (c_i32, [ctypes.c_void_p, ctypes.c_void_p, c_sz,
+                                              ctypes.c_void_p, _p(ctypes.c_void_p)]),
+    "opdhg_prepared_destroy": (None, [ctypes.c_void_p]),
     "opdhg_autotune_workspace_bytes": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), _p(c_sz)]),
     "opdhg_autotune": (c_i32, [c_i32, _p(opdhg_lp), _p(opdhg_params), ctypes.c_void_p, c_sz,
                                ctypes.c_void_p, c_i32, _p(opdhg_tuning)]),
@@ -366,20 +371,53 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def _prepared_session(a, params, workspace, stream):
+    """A session over the LP arrays a, prepared once (opdhg_prepare): its
+    handle and workspace (a device tensor when none is given)."""
+    lib = load()
+    pr = ctypes.c_void_p()
+    _check(lib.opdhg_prepare(ctypes.byref(a.struct), ctypes.byref(params), ctypes.byref(pr)))
+    try:
+        need = c_sz(0)
+        _check(lib.opdhg_prepared_bytes(pr, ctypes.byref(need)))
+        ws = workspace if workspace is not None else device_workspace(int(need.value))
+        ptr, size = _ws_ptr(ws)
+        h = ctypes.c_void_p()
+        _check(lib.opdhg_session_create_prepared(pr, ctypes.c_void_p(ptr), size,
+                                                 ctypes.c_void_p(_stream_handle(stream)),
+                                                 ctypes.byref(h)))
+    finally:
+        lib.opdhg_prepared_destroy(pr)
+    return h, ws
+
+
 def opdhg_solve(lp, params: Optional[opdhg_params] = None, workspace=None, stream=None):
-    """Solve one LP on the GPU: returns (x, y, opdhg_result)."""
+    """Solve one LP on the GPU: returns (x, y, opdhg_result).
+
+    With a caller's workspace this is the C opdhg_solve. Without one the
+    workspace has to be sized first; opdhg_workspace_bytes followed by
+    opdhg_solve would prepare the LP twice, so the LP is prepared once
+    (opdhg_prepare) and solved through the session calls, which give the
+    same result bit for bit."""
     params = params or opdhg_default_params()
     a = _LPArrays(lp)
-    need = opdhg_workspace_bytes(lp, params)
-    ws = workspace if workspace is not None else device_workspace(need)
-    ptr, size = _ws_ptr(ws)
+    lib = load()
     x = np.empty(a.n)
-    y = np.empty(a.m)
+    y = np.empty(max(a.m, 1))
     res = opdhg_result()
-    _check(load().opdhg_solve(ctypes.byref(a.struct), ctypes.byref(params), ctypes.c_void_p(ptr),
-                              size, ctypes.c_void_p(_stream_handle(stream)), _dptr(x, c_dbl),
-                              _dptr(y, c_dbl), ctypes.byref(res)))
-    return x, y, res
+    if workspace is not None:
+        ptr, size = _ws_ptr(workspace)
+        _check(lib.opdhg_solve(ctypes.byref(a.struct), ctypes.byref(params), ctypes.c_void_p(ptr),
+                               size, ctypes.c_void_p(_stream_handle(stream)), _dptr(x, c_dbl),
+                               _dptr(y, c_dbl), ctypes.byref(res)))
+        return x, y[: a.m], res
+    h, ws = _prepared_session(a, params, None, stream)
+    try:
+        _check(lib.opdhg_session_run(h, -1))
+        _check(lib.opdhg_session_result(h, _dptr(x, c_dbl), _dptr(y, c_dbl), ctypes.byref(res)))
+    finally:
+        lib.opdhg_session_destroy(h)
+    return x, y[: a.m], res
 
 
 def opdhg_solve_noalloc(lp, params: Optional[opdhg_params] = None, stream=None):
@@ -455,15 +493,7 @@ class Session:
     def __init__(self, lp, params: Optional[opdhg_params] = None, stream=None):
         self.params = params or opdhg_default_params()
         self._a = _LPArrays(lp)
-        need = opdhg_workspace_bytes(lp, self.params)
-        self._ws = device_workspace(need)
-        ptr, size = _ws_ptr(self._ws)
-        h = ctypes.c_void_p()
-        _check(load().opdhg_session_create(ctypes.byref(self._a.struct), ctypes.byref(self.params),
-                                           ctypes.c_void_p(ptr), size,
-                                           ctypes.c_void_p(_stream_handle(stream)),
-                                           ctypes.byref(h)))
-        self._h = h
+        self._h, self._ws = _prepared_session(self._a, self.params, None, stream)
 
     def run(self, k_target: int = -1) -> None:
         _check(load().opdhg_session_run(self._h, int(k_target)))

@@ -219,9 +219,22 @@ struct HostDD {
   double value() const { return hi + lo; }
 };
 
+// Euclidean norm, the squares summed in double-double: per block of
+// for_blocks (one block below 2^17 entries), then the blocks in order, so the
+// result depends on n only, not on the host's threads.
 static double dd_norm(const double* v, int64_t n) {
-  HostDD acc;
-  for (int64_t i = 0; i < n; ++i) acc.add_prod(v[i], v[i]);
+  const int nb = item_blocks(n);
+  std::vector<HostDD> part(nb);
+  for_blocks(n, nb, [&](int b, int64_t i0, int64_t i1) {
+    HostDD a;
+    for (int64_t i = i0; i < i1; ++i) a.add_prod(v[i], v[i]);
+    part[b] = a;
+  });
+  HostDD acc = part[0];
+  for (int b = 1; b < nb; ++b) {
+    acc.add(part[b].hi);
+    acc.lo += part[b].lo;
+  }
   return std::sqrt(acc.value());
 }
 
@@ -1171,23 +1184,27 @@ static int prepare_finish(const opdhg_lp* lp, const opdhg_params* p, Prepared& o
     // unscaled vectors in device order; the device scales them
     out.raw_b.resize(m);
     out.sense.resize(m);
-    for (int64_t i2 = 0; i2 < m; ++i2) {
-      const int64_t i = out.perm_a[i2];
-      out.raw_b[i2] = lp->b[i];
-      out.sense[i2] = lp->row_sense[i];
-    }
+    for_blocks(m, item_blocks(m), [&](int, int64_t i0, int64_t i1) {
+      for (int64_t i2 = i0; i2 < i1; ++i2) {
+        const int64_t i = out.perm_a[i2];
+        out.raw_b[i2] = lp->b[i];
+        out.sense[i2] = lp->row_sense[i];
+      }
+    });
     out.raw_c.resize(n);
     out.raw_l.resize(n);
     out.raw_u.resize(n);
     out.bfin.resize(n);
-    for (int64_t j2 = 0; j2 < n; ++j2) {
-      const int64_t j = out.perm_t[j2];
-      out.raw_c[j2] = lp->c[j];
-      out.raw_l[j2] = lp->l[j];
-      out.raw_u[j2] = lp->u[j];
-      out.bfin[j2] =
-          (int8_t)((std::isfinite(lp->l[j]) ? 1 : 0) | (std::isfinite(lp->u[j]) ? 2 : 0));
-    }
+    for_blocks(n, item_blocks(n), [&](int, int64_t j0, int64_t j1) {
+      for (int64_t j2 = j0; j2 < j1; ++j2) {
+        const int64_t j = out.perm_t[j2];
+        out.raw_c[j2] = lp->c[j];
+        out.raw_l[j2] = lp->l[j];
+        out.raw_u[j2] = lp->u[j];
+        out.bfin[j2] =
+            (int8_t)((std::isfinite(lp->l[j]) ? 1 : 0) | (std::isfinite(lp->u[j]) ? 2 : 0));
+      }
+    });
   }
   out.b.resize(out.dprep ? 0 : m);
   out.sense.resize(m);
@@ -2556,25 +2573,49 @@ namespace opdhg {
 // solve: validation, preparation, upload, launch tables, the first
 // products and the launch sequence. need_out (if set) receives the device
 // bytes the LP needs, also when the workspace is too small.
-int session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
-                   size_t workspace_bytes, void* hip_stream, bool direct, opdhg_session** out,
-                   size_t* need_out) {
-  if (!out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "out is NULL");
-  *out = nullptr;
+}  // namespace opdhg
+
+// One LP prepared for a session: validation, structure, tiling, windows
+// (and the scaled data when the host prepares it), its slot layout and the
+// exact workspace bytes.
+struct opdhg_prepared {
+  opdhg_params p{};
+  Prepared P;
+  SlotLayout L;
+  size_t need = 0;
+  bool used = false;
+};
+
+namespace opdhg {
+
+static int prepared_make(const opdhg_lp* lp, const opdhg_params* p, opdhg_prepared& pr) {
   int rc = validate_lp(lp);
   if (rc) return rc;
   if ((rc = validate_params(p))) return rc;
+  pr.p = *p;
+  if ((rc = prepare(lp, p, pr.P, false))) return rc;
+  pr.L = slot_layout(pr.P, p->precision);
+  pr.need = pr.L.total + tables_bytes({&pr.P}, grid_cap(p));
+  return OPDHG_OK;
+}
+
+static int session_from_prepared(opdhg_prepared& pr, void* d_workspace, size_t workspace_bytes,
+                                 void* hip_stream, bool direct, opdhg_session** out) {
+  if (!out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (pr.used) return fail(OPDHG_ERR_INVALID_ARGUMENT, "prepared LP was used already");
   if (!d_workspace) return fail(OPDHG_ERR_INVALID_ARGUMENT, "workspace is NULL");
-  auto s = std::make_unique<opdhg_session>();
-  SessionImpl& S = s->impl;
-  if ((rc = prepare(lp, p, S.P, false))) return rc;
-  S.L = slot_layout(S.P, p->precision);
-  const size_t need =
-      S.L.total + tables_bytes({&S.P}, grid_cap(p));
-  if (need_out) *need_out = need;
+  const opdhg_params* p = &pr.p;
+  const size_t need = pr.need;
   if (workspace_bytes < need)
     return fail(OPDHG_ERR_WORKSPACE_TOO_SMALL,
                 "workspace needs " + std::to_string(need) + " bytes");
+  int rc = OPDHG_OK;
+  auto s = std::make_unique<opdhg_session>();
+  SessionImpl& S = s->impl;
+  pr.used = true;  // the prepared data moves into the session
+  S.P = std::move(pr.P);
+  S.L = pr.L;
   S.ws = static_cast<uint8_t*>(d_workspace);
   S.time_limit = p->time_limit_s;
   S.direct = direct;
@@ -2598,6 +2639,23 @@ int session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
   return OPDHG_OK;
 }
 
+int session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_workspace,
+                   size_t workspace_bytes, void* hip_stream, bool direct, opdhg_session** out,
+                   size_t* need_out) {
+  if (!out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!d_workspace) {
+    int rc = validate_lp(lp);
+    if (!rc) rc = validate_params(p);
+    return rc ? rc : fail(OPDHG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  }
+  opdhg_prepared pr;
+  int rc = prepared_make(lp, p, pr);
+  if (rc) return rc;
+  if (need_out) *need_out = pr.need;
+  return session_from_prepared(pr, d_workspace, workspace_bytes, hip_stream, direct, out);
+}
+
 }  // namespace opdhg
 
 extern "C" {
@@ -2606,6 +2664,30 @@ int opdhg_session_create(const opdhg_lp* lp, const opdhg_params* p, void* d_work
                          size_t workspace_bytes, void* hip_stream, opdhg_session** out) {
   return session_create(lp, p, d_workspace, workspace_bytes, hip_stream, false, out, nullptr);
 }
+
+int opdhg_prepare(const opdhg_lp* lp, const opdhg_params* p, opdhg_prepared** out) {
+  if (!out) return fail(OPDHG_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  auto pr = std::make_unique<opdhg_prepared>();
+  int rc = prepared_make(lp, p, *pr);
+  if (rc) return rc;
+  *out = pr.release();
+  return OPDHG_OK;
+}
+
+int opdhg_prepared_bytes(const opdhg_prepared* pr, size_t* bytes) {
+  if (!pr || !bytes) return fail(OPDHG_ERR_INVALID_ARGUMENT, "bad arguments");
+  *bytes = pr->need;
+  return OPDHG_OK;
+}
+
+int opdhg_session_create_prepared(opdhg_prepared* pr, void* d_workspace, size_t workspace_bytes,
+                                  void* hip_stream, opdhg_session** out) {
+  if (!pr) return fail(OPDHG_ERR_INVALID_ARGUMENT, "prepared LP is NULL");
+  return session_from_prepared(*pr, d_workspace, workspace_bytes, hip_stream, false, out);
+}
+
+void opdhg_prepared_destroy(opdhg_prepared* pr) { delete pr; }
 
 int opdhg_session_run(opdhg_session* s, int64_t k_target) {
   if (!s) return fail(OPDHG_ERR_INVALID_ARGUMENT, "session is NULL");

@@ -448,3 +448,50 @@ def test_prepared_batch_handle_equals_one_call(P):
             assert np.array_equal(x, xo[i]) and np.array_equal(y, yo[i][:m]), i
             assert r.iterations == one_call[i].iterations and r.status == one_call[i].status
             assert np.array_equal(xs[i], xo[i]) and np.array_equal(ys[i][:m], yo[i][:m]), i
+
+
+def test_prepared_session_equals_one_call_solve(P):
+    # the binding's opdhg_solve without a workspace, and Session, prepare the
+    # LP once (opdhg_prepare / _prepared_bytes / opdhg_session_create_prepared):
+    # against the one-call C opdhg_solve bit for bit, FP64 and FP32 (windows
+    # forced, so the windowed plan goes through the handle too); the handle
+    # sizes the workspace as opdhg_workspace_bytes does and creates once only
+    import ctypes
+    from paper_2506_17650_amd import capi
+    lib = capi.load()
+    cases = [(config_lp("cfg0", seed=2), {}),
+             (config_lp("cfg2", scale=0.1), dict(precision=P.OPDHG_FP32,
+                                                 windows=P.OPDHG_WINDOWS_ALWAYS))]
+    for lp, kw in cases:
+        p = lib_params(P, default_params(max_iter=4000, lr=1e-2), **kw)
+        x, y, r = P.opdhg_solve(lp, p)
+        a = capi._LPArrays(lp)
+        need = P.opdhg_workspace_bytes(lp, p)
+        pr = ctypes.c_void_p()
+        capi._check(lib.opdhg_prepare(ctypes.byref(a.struct), ctypes.byref(p), ctypes.byref(pr)))
+        got = ctypes.c_size_t(0)
+        capi._check(lib.opdhg_prepared_bytes(pr, ctypes.byref(got)))
+        assert got.value == need
+        ws = capi.device_workspace(need)
+        ptr, size = capi._ws_ptr(ws)
+        h = ctypes.c_void_p()
+        capi._check(lib.opdhg_session_create_prepared(pr, ctypes.c_void_p(ptr), size, None,
+                                                      ctypes.byref(h)))
+        h2 = ctypes.c_void_p()
+        again = lib.opdhg_session_create_prepared(pr, ctypes.c_void_p(ptr), size, None,
+                                                  ctypes.byref(h2))
+        lib.opdhg_session_destroy(h)
+        lib.opdhg_prepared_destroy(pr)
+        assert again == capi.OPDHG_ERR_INVALID_ARGUMENT
+        xo, yo = np.empty(lp.n), np.empty(max(lp.m, 1))
+        ro = capi.opdhg_result()
+        capi._check(lib.opdhg_solve(ctypes.byref(a.struct), ctypes.byref(p), ctypes.c_void_p(ptr),
+                                    size, None, capi._dptr(xo, ctypes.c_double),
+                                    capi._dptr(yo, ctypes.c_double), ctypes.byref(ro)))
+        assert np.array_equal(x, xo) and np.array_equal(y, yo[:lp.m])
+        assert r.status == ro.status and r.iterations == ro.iterations
+        assert r.primal_obj == ro.primal_obj and r.rel_kkt == ro.rel_kkt
+        # with the caller's workspace the binding is the C opdhg_solve
+        xw, yw, rw = P.opdhg_solve(lp, p, workspace=ws)
+        assert np.array_equal(xw, xo) and np.array_equal(yw, yo[:lp.m])
+        assert rw.iterations == ro.iterations and rw.rel_kkt == ro.rel_kkt
