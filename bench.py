@@ -452,17 +452,20 @@ def section_serving(P, args):
                 "iterations": r.iterations, "rel_kkt": r.rel_kkt}
                for i, r in enumerate(res32) if r.status != P.capi.OPDHG_STATUS_OPTIMAL]
     # preparation of the largest request, on the host and on the device
-    # (session creation: validation, structure, rescaling, upload, initial products)
+    # (session creation: validation, structure, rescaling, upload, initial
+    # products), the best of three creations of each
     big = max(reqs, key=lambda lp: lp.nnz)
     prep = {}
     for name, mode in (("host", P.OPDHG_PREP_HOST), ("device", P.OPDHG_PREP_DEVICE)):
         q = P.opdhg_default_params(precision=P.OPDHG_FP32, prep=mode, lr=args.lr, phi=args.phi)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sess = P.Session(big, q)
-        torch.cuda.synchronize()
-        prep[name] = time.perf_counter() - t0
-        sess.close()
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sess = P.Session(big, q)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sess.close()
+            prep[name] = min(prep.get(name, dt), dt)
     log(f"[bench] serving: preparing the largest request ({big.nnz} nonzeros): host "
         f"{prep['host']:.3f}s, device {prep['device']:.3f}s")
     return {
@@ -487,7 +490,7 @@ def section_serving(P, args):
             "note": "|p32 - p64| / (1 + |p64|) per request solved in FP32, both at rel KKT "
                     "<= 1e-4"},
         "largest_request_prep_s": {"nnz": big.nnz, "host": prep["host"], "device": prep["device"],
-                                   "note": "session creation; requests of 2^20 nonzeros or more "
+                                   "note": "session creation, best of three; requests of 2^20 nonzeros or more "
                                            "are prepared on the device in the server runs"},
         "baseline": {
             "kind": "plain FP64 PDHG (lr 0) served one LP at a time, first in first out, by the "
