@@ -155,10 +155,10 @@ typedef struct opdhg_params {
   double power_tol;      /* power iteration stops when |A~|_2^2 moves less than this, relatively */
   int32_t step_norm;     /* OPDHG_STEP_NORM_*: norms of the adaptive rule's movement term */
   int32_t windows;       /* OPDHG_WINDOWS_*: FP32 only; FP64 and the server never use windows */
-  int32_t window_buckets; /* LDS window per pass in buckets of 1024 entries, 1..32, at most 32 on
-                             the A^T side and 28 on the A side; 0: those */
-  int32_t window_rows;   /* rows per windowed chunk, 1..10240 (at most 7168 on the A^T side);
-                            0: picked from the side's size */
+  int32_t window_buckets; /* LDS window per pass in buckets of 1024 entries, 1..28, for chunks
+                             of one pass and of several alike; 0: 28 per pass, and up to 38 for a
+                             chunk of one pass (its row sums then reuse the window's LDS) */
+  int32_t window_rows;   /* rows per windowed chunk, 1..10240; 0: picked from the side's size */
   int32_t prep;          /* OPDHG_PREP_*: rescaling passes and scaled data on the host or device */
   int32_t eval_slots;    /* attempt slots between the guarded evaluation steps inside a launch
                             sequence (an LP that becomes due mid-sequence waits at most this
