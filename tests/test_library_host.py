@@ -253,3 +253,53 @@ def test_window_plans_pass_their_checks():
             assert ws >= tiles, (i, wb, wr)
             if i < 2 and wb == 0:
                 assert ws > tiles, (i, wb, wr)
+
+
+def test_prepared_handle_sizes_as_workspace_bytes():
+    """opdhg_prepare runs on the host only (validation, structure, tiling,
+    windows, and the scaled data when the host prepares): the handle's
+    workspace size equals opdhg_workspace_bytes for every precision, window
+    setting and preparation mode, and the handle's error paths report
+    without touching a device."""
+    lib = capi.load()
+    lps = [config_lp("cfg0", seed=1), config_lp("cfg2", scale=0.05),
+           config_lp("cfg3", index=7, scale=0.2)]
+    settings = [dict(), dict(precision=P.OPDHG_FP32),
+                dict(precision=P.OPDHG_FP32, windows=P.OPDHG_WINDOWS_ALWAYS),
+                dict(precision=P.OPDHG_FP32, prep=P.OPDHG_PREP_DEVICE),
+                dict(prep=P.OPDHG_PREP_HOST)]
+    for i, lp in enumerate(lps):
+        a = capi._LPArrays(lp)
+        for kw in settings:
+            p = P.opdhg_default_params(**kw)
+            pr = ctypes.c_void_p()
+            capi._check(lib.opdhg_prepare(ctypes.byref(a.struct), ctypes.byref(p),
+                                          ctypes.byref(pr)))
+            try:
+                got = ctypes.c_size_t(0)
+                capi._check(lib.opdhg_prepared_bytes(pr, ctypes.byref(got)))
+                assert got.value == P.opdhg_workspace_bytes(lp, p), (i, kw)
+                # no workspace: refused before any device work, handle still unused
+                h = ctypes.c_void_p()
+                rc = lib.opdhg_session_create_prepared(pr, None, got.value, None, ctypes.byref(h))
+                assert rc == capi.OPDHG_ERR_INVALID_ARGUMENT and not h.value
+            finally:
+                lib.opdhg_prepared_destroy(pr)
+    # invalid LP and parameters are refused by opdhg_prepare, with no handle
+    bad = tiny_lp(1)
+    a = capi._LPArrays(bad)
+    a.struct.m = -1
+    pr = ctypes.c_void_p()
+    p = P.opdhg_default_params()
+    assert lib.opdhg_prepare(ctypes.byref(a.struct), ctypes.byref(p), ctypes.byref(pr)) != 0
+    assert not pr.value
+    a = capi._LPArrays(tiny_lp(2))
+    p = P.opdhg_default_params(tol=-1.0)
+    assert lib.opdhg_prepare(ctypes.byref(a.struct), ctypes.byref(p), ctypes.byref(pr)) \
+        == capi.OPDHG_ERR_INVALID_ARGUMENT
+    assert not pr.value
+    assert lib.opdhg_prepared_bytes(None, ctypes.byref(ctypes.c_size_t(0))) \
+        == capi.OPDHG_ERR_INVALID_ARGUMENT
+    assert lib.opdhg_session_create_prepared(None, None, 0, None, ctypes.byref(ctypes.c_void_p())) \
+        == capi.OPDHG_ERR_INVALID_ARGUMENT
+    lib.opdhg_prepared_destroy(None)
