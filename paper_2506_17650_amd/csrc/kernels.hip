@@ -1668,6 +1668,11 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   }
   if (!one)
     for (int r = t; r < nrow + nseg; r += kWinBlock) part[r] = 0.f;
+  // the first two rows' epilogue loads go out before the passes, so they
+  // are in flight while the entries stream
+  const int ra = min(t, nrow - 1), rb0 = min(t + kWinBlock, nrow - 1);
+  Pre pa = st.load(r0 + ra);
+  Pre pb = st.load(r0 + rb0);
   lds_barrier();
   float racc[kWinWaveSlices];
   int rrow[kWinWaveSlices];
@@ -1796,8 +1801,9 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
   for (int r = t; r < nrow; r += 2 * kWinBlock) {
     const int r2 = r + kWinBlock;
     const bool two = r2 < nrow;
-    Pre q0 = st.load(r0 + r);
-    Pre q1 = st.load(r0 + (two ? r2 : r));
+    const bool first = r == t;
+    Pre q0 = first ? pa : st.load(r0 + r);
+    Pre q1 = first ? pb : st.load(r0 + (two ? r2 : r));
     st.finish(r0 + r, part[r], q0, p);
     if (two) st.finish(r0 + r2, part[r2], q1, p);
   }
