@@ -1709,22 +1709,37 @@ __device__ __forceinline__ void win_chunk(const LaunchCfg& cfg, const WinItem* l
       const gptr<const WinSlice> slp = slices + sj;
       head(sj, WinSlice{uni(slp->e0), uni(slp->len)}, e0, len, row, vv, cc);
     }
+    // ranges start on bucket boundaries (multiples of 4 entries, here and
+    // in the window), so they are copied 16 bytes at a time; only the
+    // vector's last bucket can end on a partial group. The first two
+    // groups of each thread in the pass's first range are loaded before the
+    // barrier that ends the previous pass, so they arrive while it ends.
+    using f32x4 = float __attribute__((ext_vector_type(4)));
+    const int src0 = uni(ranges[pr0].src), len0 = uni(ranges[pr0].len);
+    const bool early = (len0 >> 2) >= 2 * kWinBlock;
+    f32x4 pf[2];
+    if (early) {
+      const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src0);
+      pf[0] = v4[t];
+      pf[1] = v4[t + kWinBlock];
+    }
     if (ps > 0) lds_barrier();  // the previous pass is done with the window and records
     for (int q = t; q < sl1 - sl0; q += kWinBlock) {
       const gptr<const WinSlice> slp = slices + (sl0 + q);
       s_sl[q] = WinSlice{slp->e0, slp->len};
     }
-    // ranges start on bucket boundaries (multiples of 4 entries, here and
-    // in the window), so they are copied 16 bytes at a time; only the
-    // vector's last bucket can end on a partial group
     int off = 0;
     for (int g = pr0; g < pr0 + prn; ++g) {
       const int src = ranges[g].src, glen = ranges[g].len;
-      using f32x4 = float __attribute__((ext_vector_type(4)));
       const gptr<const f32x4> v4 = reinterpret_cast<gptr<const f32x4>>(vec + src);
       f32x4* w4 = reinterpret_cast<f32x4*>(win + off);
       const int n4 = glen >> 2;
       int q = t;
+      if (g == pr0 && early) {
+        w4[t] = pf[0];
+        w4[t + kWinBlock] = pf[1];
+        q = t + 2 * kWinBlock;
+      }
       for (; q + 3 * kWinBlock < n4; q += 4 * kWinBlock) {  // four loads in flight
         f32x4 a[4];
 #pragma unroll
